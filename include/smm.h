@@ -1,0 +1,211 @@
+/*
+ * smm.h -- C ABI of libsmm: the high-order DG S_N transport sweep inside the
+ * Second Moment Method (Olivier & Haut, "High-Order Finite Element Second
+ * Moment Methods for Linear Transport"), on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. 2, eq. transport / eq. inflow): mono-energetic fixed-source
+ * transport with isotropic scattering,
+ *     Omega.grad psi + sigma_t psi = sigma_s/(4 pi) int psi dOmega + q,
+ *     psi = psibar on inflow boundary points,
+ * on a 2D domain meshed by nx * ny quadrilaterals mapped by Q_m polynomials
+ * (Sec. 3.1).  The angular flux is discretised by upwind DG in Y_p and S_N
+ * collocation (Sec. 4); the SMM moment system is the interior-penalty
+ * discretisation eq. ipsmm (Sec. 5.1), solved by FP64 preconditioned CG; the
+ * two are coupled by the fixed point X = G(X) (eq. moment:smm_fp).
+ *
+ * Conventions
+ *  - Every call returns int: SMM_OK (0) or a negative SMM_E* code.  No C++
+ *    exception crosses the ABI.  smm_strerror() names a code; smm_last_error()
+ *    gives the message of the last failure on a context.
+ *  - DOF layout: element-major, element index K = j*nx + i (i along x);
+ *    inside an element the (p+1)^2 Gauss-Lobatto nodal values are
+ *    lexicographic with the x index fastest.
+ *  - Directions: level-symmetric S_N, 2D half-sphere set of N(N+2)/2
+ *    directions (weights sum to 4 pi), ordered by quadrant (+,+), (-,+),
+ *    (-,-), (+,-) and inside a quadrant by octant point order;
+ *    smm_get_quadrature() returns them.
+ *  - Boundary faces are enumerated by element K, then local face
+ *    (0 bottom, 1 right, 2 top, 3 left); each carries nq = p+m+1 Gauss points
+ *    ordered by increasing x (faces 0, 2) or increasing y (faces 1, 3).
+ *  - Ownership: the caller owns every array passed in or out.  Inputs given to
+ *    smm_set_* are copied before the call returns.  Arguments documented as
+ *    "device" must be device pointers on the context's device; they are read
+ *    or written on the context's stream, and the call returns once that work
+ *    is queued (smm_apply_* and smm_get_outputs with on_device = 1) or done
+ *    (everything else synchronises the stream before returning).
+ *  - A context is bound to one device and one HIP stream and must not be used
+ *    from two threads at once.
+ */
+#ifndef SMM_H
+#define SMM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SMM_OK 0
+#define SMM_EINVAL -1        /* bad argument (sizes, ranges, null pointers, det J <= 0) */
+#define SMM_ENOMEM -2        /* device or host allocation failed */
+#define SMM_EHIP -3          /* a HIP runtime call failed */
+#define SMM_ENOCONV -4       /* outer iteration hit max_outer; outputs hold the last iterate */
+#define SMM_ENAN -5          /* NaN or Inf in the outer residual */
+#define SMM_EBREAKDOWN -6    /* CG breakdown: p.Ap <= 0 (moment operator not positive definite) */
+#define SMM_EUNSUPPORTED -7  /* valid input the library does not handle (e.g. slanted boundary) */
+#define SMM_ESTATE -8        /* call order violated (e.g. solve before set_materials) */
+
+/* precision of the sweep and the angular-moment contraction */
+#define SMM_FP64 0
+#define SMM_FP32_SWEEP 1
+
+/* source layouts for smm_set_source */
+#define SMM_SRC_ISO 0        /* q[n_elem][n_node], per steradian, same for all directions */
+#define SMM_SRC_ANISO 1      /* q[n_dir][n_elem][n_node] */
+
+/* inflow layouts for smm_set_inflow */
+#define SMM_INFLOW_VACUUM 0  /* psibar = 0 (pointer ignored) */
+#define SMM_INFLOW_ISO_FACE 1/* psibar[n_bface]: isotropic, constant per boundary face */
+#define SMM_INFLOW_FULL 2    /* psibar[n_bface][nq][n_dir] at the boundary face points */
+
+/* initial guess for smm_solve */
+#define SMM_START_ZERO 0
+#define SMM_START_DIFFUSION 1 /* moment system with zero transport corrections */
+#define SMM_START_GIVEN 2     /* varphi0 argument (host) */
+
+typedef struct smm_ctx smm_ctx;
+typedef struct smm_problem smm_problem;
+
+/* Mesh: structured nx * ny quadrilaterals with a continuous Q_m map whose
+ * control points sit at the Gauss-Lobatto positions of each element
+ * (Sec. 3.1).  ctrl is host memory, shape [ny*m+1][nx*m+1][2] (x fastest),
+ * shared between neighbouring elements. */
+typedef struct {
+    int nx, ny;
+    int m;
+    const double* ctrl;
+} smm_mesh_desc;
+
+typedef struct {
+    int n_elem;      /* nx * ny */
+    int n_node;      /* (p+1)^2 DOF per element */
+    int n_dir;       /* S_N directions */
+    int n_bface;     /* boundary faces */
+    int nq;          /* Gauss points per face (p+m+1) */
+    int cartesian;   /* 1: uniform axis-aligned rectangles (operator tables per material and direction) */
+    int n_material;  /* distinct sigma_t values (cartesian path) */
+    int n_levels;    /* max sweep wavefront levels over directions */
+} smm_problem_dims;
+
+typedef struct {
+    int precision;       /* SMM_FP64 or SMM_FP32_SWEEP */
+    double outer_tol;    /* stop when max|X^{k+1}-X^k| / max|X^{k+1}| < outer_tol */
+    int max_outer;
+    double inner_tol;    /* CG relative residual ||r||_2/||b||_2 */
+    int max_inner;       /* CG iterations per outer iteration */
+    int start;           /* SMM_START_* */
+    int delta_sweeps;    /* 1: sweep only the change of the scattering source and
+                            accumulate the moments in FP64 (default for FP32_SWEEP) */
+    int use_graph;       /* 1: replay each outer iteration from a captured hipGraph */
+} smm_solve_opts;
+
+typedef struct {
+    int iterations;          /* outer iterations done */
+    double residual;         /* last relative outer residual */
+    double residual_abs;     /* last absolute max-norm change */
+    int cg_iterations_total;
+    int cg_iterations_max;
+    double t_total_ms;       /* wall time of the solve (host clock) */
+    double t_setup_ms;       /* one-time setup at the first solve (device tables) */
+} smm_solve_info;
+
+const char* smm_strerror(int code);
+
+/* Context bound to HIP device `device` and stream `hip_stream` (a hipStream_t,
+ * NULL = the null stream).  device < 0 creates a host-only context: problems
+ * may be created and their setup tables inspected, but nothing runs. */
+int smm_ctx_create(int device, void* hip_stream, smm_ctx** out);
+int smm_ctx_destroy(smm_ctx* ctx);
+const char* smm_last_error(smm_ctx* ctx);
+
+/* Geometry, quadrature and basis setup (Sec. 3, Sec. 4).  p in 1..4;
+ * sn_order in {4, 6, 8, 10, 12}.  SMM_EINVAL if det J <= 0 at a volume
+ * quadrature point or if the boundary is not axis-aligned. */
+int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_order,
+                       smm_problem** out);
+int smm_problem_destroy(smm_problem* prob);
+int smm_get_dims(const smm_problem* prob, smm_problem_dims* out);
+
+/* host outputs: omega[n_dir][3], w[n_dir] */
+int smm_get_quadrature(const smm_problem* prob, double* omega, double* w);
+/* host output: physical coordinates of the DOF nodes [n_elem][n_node][2] */
+int smm_get_nodes(const smm_problem* prob, double* xy);
+/* host output: physical coordinates of the boundary face points [n_bface][nq][2] */
+int smm_get_bface_points(const smm_problem* prob, double* xy);
+
+/* Per-element cross sections (host, length n_elem); requires sigma_t > 0 and
+ * 0 <= sigma_s <= sigma_t.  Fixes the IP operator (eq. ipsmm, penalty
+ * kappa = {(p+1)^2/(sigma_t h)}, h = |K|^(1/2)). */
+int smm_set_materials(smm_problem* prob, const double* sigma_t, const double* sigma_s);
+/* Fixed source q per steradian (host), layout SMM_SRC_*. */
+int smm_set_source(smm_problem* prob, const double* q, int layout);
+/* Inflow psibar (host), layout SMM_INFLOW_*. */
+int smm_set_inflow(smm_problem* prob, const double* psibar, int layout);
+
+void smm_default_opts(smm_solve_opts* opts);
+
+/* Fixed-point solve X^{k+1} = G(X^k) (eq. fixed-point).  varphi0 (host,
+ * [n_elem*n_node]) is read when opts->start == SMM_START_GIVEN.  Returns
+ * SMM_ENOCONV with valid outputs when max_outer is reached. */
+int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varphi0,
+              smm_solve_info* info);
+
+/* Results of the last smm_solve or smm_apply_G.  Any pointer may be NULL.
+ * varphi, phi [n_elem*n_node]; J [2][n_elem*n_node]; T [3][n_elem*n_node]
+ * (xx, xy, yy); beta [n_bface][nq].  on_device selects device or host
+ * destination buffers. */
+int smm_get_outputs(smm_problem* prob, double* varphi, double* phi, double* J, double* T,
+                    double* beta, int on_device);
+
+/* One application of L^{-1} (Sec. 4), for testing and benchmarking.
+ * S: device, [n_elem][n_node] (s_layout SMM_SRC_ISO) or [n_dir][n_elem][n_node]
+ * (SMM_SRC_ANISO), of type double (precision SMM_FP64) or float
+ * (SMM_FP32_SWEEP).  psi_lag: device, previous sweep [n_dir][n_elem][n_node]
+ * read at curved-face points whose upwind neighbour is downstream in the
+ * sweep graph (NULL = zero).  psi_out: device [n_dir][n_elem][n_node], same
+ * type.  Boundary inflow is the one set by smm_set_inflow (if with_inflow). */
+int smm_apply_sweep(smm_problem* prob, int precision, const void* S, int s_layout,
+                    const void* psi_lag, void* psi_out, int with_inflow);
+
+/* Angular moments (Sec. 4) of psi (device [n_dir][n_elem][n_node], type per
+ * precision) on the matrix cores: mom (device, double [8][n_elem*n_node]) rows
+ * phi, J_x, J_y, P_xx, P_xy, P_yy, sum w|Omega_x| psi, sum w|Omega_y| psi. */
+int smm_apply_moments(smm_problem* prob, int precision, const void* psi, double* mom);
+
+/* One evaluation of G (eq. moment:smm_fp) in FP64 (or with an FP32 sweep):
+ * varphi_in, varphi_out device [n_elem*n_node]; lagged curved-face couplings
+ * read zero.  CG runs to inner_tol from varphi_in.  smm_get_outputs then
+ * returns this evaluation's moments and closures. */
+int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, double* varphi_out,
+                double inner_tol, int max_inner);
+
+/* Host-only inspection of the setup tables (for tests): the IP matrix as
+ * dense row-major [N][N] with N = n_elem*n_node (small problems only), and
+ * the fixed right-hand side [N]. */
+int smm_debug_ip_dense(const smm_problem* prob, double* A, double* b_fixed);
+
+/* Sweep kernel selection: 0 = automatic (tabulated operators on uniform
+ * Cartesian meshes, otherwise per-element assembly and elimination);
+ * 1 = always the per-element kernel (for cross-checking the two). */
+int smm_set_sweep_path(smm_problem* prob, int force_general);
+
+/* Time one sweep configuration on device (average ms over `reps` launches
+ * measured with HIP events on the context stream); used by the benchmark. */
+int smm_time_sweep(smm_problem* prob, int precision, int reps, double* ms_avg);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMM_H */

@@ -1,0 +1,765 @@
+// C ABI of libsmm: contexts, problems, device tables and the SMM outer loop.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "smm_internal.hpp"
+
+struct smm_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+};
+
+namespace smm {
+
+// Device-resident state of one problem.
+struct Dev {
+    bool built = false;
+    bool tables_dirty = true;   // materials changed
+    bool src_dirty = true;      // source / inflow changed
+    std::vector<void*> allocs;
+    // quadrature
+    double* omega = nullptr;
+    void* W32 = nullptr;
+    void* W64 = nullptr;
+    int ldw = 0;
+    // cartesian operator tables
+    void *Pm32 = nullptr, *Px32 = nullptr, *Py32 = nullptr;
+    void *Pm64 = nullptr, *Px64 = nullptr, *Py64 = nullptr;
+    uint8_t* mat = nullptr;
+    void *bx32 = nullptr, *by32 = nullptr, *bx64 = nullptr, *by64 = nullptr;
+    // general sweep data
+    void *Mk32 = nullptr, *Gx32 = nullptr, *Gy32 = nullptr, *nds32 = nullptr, *Lf32 = nullptr, *st32 = nullptr;
+    void *Mk64 = nullptr, *Gx64 = nullptr, *Gy64 = nullptr, *nds64 = nullptr, *Lf64 = nullptr, *st64 = nullptr;
+    int *nbr = nullptr, *bface_of = nullptr, *lev_ptr = nullptr, *lev_elem = nullptr;
+    uint8_t* upflag = nullptr;
+    void *pbar32 = nullptr, *pbar64 = nullptr;
+    // materials, source
+    double* sigma_s = nullptr;
+    double* q = nullptr;
+    // moment system
+    int* bsr_col = nullptr;
+    double *bsr_val = nullptr, *bjac = nullptr, *corr = nullptr, *beta_op = nullptr, *bfix = nullptr;
+    int *bface_K = nullptr, *bface_f = nullptr;
+    // work vectors
+    double *varphi = nullptr, *varphi_prev = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr,
+           *p = nullptr, *qv = nullptr, *part = nullptr, *scal = nullptr, *rpart = nullptr, *rout = nullptr;
+    void* S = nullptr;          // sweep source (sized for fp64, [nd_q][ne][n])
+    void* psi[2] = {nullptr, nullptr};  // sweep outputs (sized for fp64)
+    double *mom = nullptr, *mom_acc = nullptr, *T = nullptr, *beta = nullptr;
+    int cg_blocks = 0, r_blocks = 0;
+    bool have_outputs = false;
+    int force_general = 0;
+    const double* last_mom = nullptr;   // moments of the last G evaluation
+    const double* last_varphi = nullptr;
+};
+
+}  // namespace smm
+
+struct smm_problem {
+    smm::Problem P;
+    smm::Dev D;
+};
+
+using namespace smm;
+
+static int fail(smm_ctx* c, int code, const std::string& msg) {
+    if (c) c->last_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(ctx, SMM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" {
+
+const char* smm_strerror(int code) {
+    switch (code) {
+        case SMM_OK: return "ok";
+        case SMM_EINVAL: return "invalid argument";
+        case SMM_ENOMEM: return "out of memory";
+        case SMM_EHIP: return "HIP runtime error";
+        case SMM_ENOCONV: return "outer iteration did not converge";
+        case SMM_ENAN: return "NaN or Inf in the outer residual";
+        case SMM_EBREAKDOWN: return "CG breakdown (operator not positive definite)";
+        case SMM_EUNSUPPORTED: return "unsupported input";
+        case SMM_ESTATE: return "call order violated";
+        default: return "unknown status";
+    }
+}
+
+int smm_ctx_create(int device, void* hip_stream, smm_ctx** out) {
+    if (!out) return SMM_EINVAL;
+    smm_ctx* c = new (std::nothrow) smm_ctx();
+    if (!c) return SMM_ENOMEM;
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (device >= 0) {
+        int cnt = 0;
+        if (hipGetDeviceCount(&cnt) != hipSuccess || device >= cnt) {
+            delete c;
+            return SMM_EHIP;
+        }
+        if (hipSetDevice(device) != hipSuccess) {
+            delete c;
+            return SMM_EHIP;
+        }
+    }
+    *out = c;
+    return SMM_OK;
+}
+
+int smm_ctx_destroy(smm_ctx* ctx) {
+    delete ctx;
+    return SMM_OK;
+}
+
+const char* smm_last_error(smm_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_order, smm_problem** out) {
+    if (!ctx || !mesh || !out || !mesh->ctrl) return fail(ctx, SMM_EINVAL, "null argument");
+    if (p < 1 || p > 4) return fail(ctx, SMM_EINVAL, "p must be in 1..4");
+    if (mesh->nx < 1 || mesh->ny < 1 || mesh->m < 1 || mesh->m > 6)
+        return fail(ctx, SMM_EINVAL, "bad mesh sizes");
+    smm_problem* pr = new (std::nothrow) smm_problem();
+    if (!pr) return SMM_ENOMEM;
+    Problem& P = pr->P;
+    P.ctx = ctx;
+    P.nx = mesh->nx;
+    P.ny = mesh->ny;
+    P.m = mesh->m;
+    P.p = p;
+    P.nb = p + 1;
+    P.n = P.nb * P.nb;
+    P.nq = p + mesh->m + 1;
+    P.ne = P.nx * P.ny;
+    P.sn = sn_order;
+    if (level_symmetric(sn_order, P.omega, P.w) != 0) {
+        delete pr;
+        return fail(ctx, SMM_EINVAL, "S_N order must be 4, 6, 8, 10 or 12");
+    }
+    P.nd = (int)P.w.size();
+    const size_t nctrl = (size_t)(P.ny * P.m + 1) * (P.nx * P.m + 1) * 2;
+    P.ctrl.assign(mesh->ctrl, mesh->ctrl + nctrl);
+    std::string err;
+    int rc = setup_geometry(P, err);
+    if (rc != SMM_OK) {
+        delete pr;
+        return fail(ctx, rc, err);
+    }
+    setup_sweep_graph(P);
+    P.q.assign((size_t)P.ne * P.n, 0.0);
+    *out = pr;
+    return SMM_OK;
+}
+
+static void dev_free(Dev& D) {
+    for (void* ptr : D.allocs) hipFree(ptr);
+    D.allocs.clear();
+    D = Dev();
+}
+
+int smm_problem_destroy(smm_problem* prob) {
+    if (!prob) return SMM_OK;
+    dev_free(prob->D);
+    delete prob;
+    return SMM_OK;
+}
+
+int smm_get_dims(const smm_problem* prob, smm_problem_dims* out) {
+    if (!prob || !out) return SMM_EINVAL;
+    const Problem& P = prob->P;
+    out->n_elem = P.ne;
+    out->n_node = P.n;
+    out->n_dir = P.nd;
+    out->n_bface = P.nbf;
+    out->nq = P.nq;
+    out->cartesian = P.cartesian ? 1 : 0;
+    out->n_material = P.nmat;
+    out->n_levels = P.cartesian ? P.nx + P.ny - 1 : P.nlev_max;
+    return SMM_OK;
+}
+
+int smm_get_quadrature(const smm_problem* prob, double* omega, double* w) {
+    if (!prob) return SMM_EINVAL;
+    if (omega) std::memcpy(omega, prob->P.omega.data(), sizeof(double) * prob->P.omega.size());
+    if (w) std::memcpy(w, prob->P.w.data(), sizeof(double) * prob->P.w.size());
+    return SMM_OK;
+}
+
+int smm_get_nodes(const smm_problem* prob, double* xy) {
+    if (!prob || !xy) return SMM_EINVAL;
+    std::memcpy(xy, prob->P.xnode.data(), sizeof(double) * prob->P.xnode.size());
+    return SMM_OK;
+}
+
+int smm_get_bface_points(const smm_problem* prob, double* xy) {
+    if (!prob || !xy) return SMM_EINVAL;
+    const Problem& P = prob->P;
+    for (int bf = 0; bf < P.nbf; ++bf)
+        for (int q = 0; q < P.nq; ++q)
+            for (int c = 0; c < 2; ++c)
+                xy[((size_t)bf * P.nq + q) * 2 + c] =
+                    P.xf[(((size_t)P.bface_K[bf] * 4 + P.bface_f[bf]) * P.nq + q) * 2 + c];
+    return SMM_OK;
+}
+
+int smm_set_materials(smm_problem* prob, const double* sigma_t, const double* sigma_s) {
+    if (!prob || !sigma_t || !sigma_s) return SMM_EINVAL;
+    Problem& P = prob->P;
+    for (int K = 0; K < P.ne; ++K) {
+        if (!(sigma_t[K] > 0.0) || !(sigma_s[K] >= 0.0) || !(sigma_s[K] <= sigma_t[K]) ||
+            !std::isfinite(sigma_t[K]))
+            return fail(P.ctx, SMM_EINVAL, "need sigma_t > 0 and 0 <= sigma_s <= sigma_t");
+    }
+    P.sigma_t.assign(sigma_t, sigma_t + P.ne);
+    P.sigma_s.assign(sigma_s, sigma_s + P.ne);
+    P.have_mat = true;
+    P.lhs_ready = false;
+    P.rhs_fixed_ready = false;
+    prob->D.tables_dirty = true;
+    prob->D.src_dirty = true;
+    return SMM_OK;
+}
+
+int smm_set_source(smm_problem* prob, const double* q, int layout) {
+    if (!prob || !q) return SMM_EINVAL;
+    Problem& P = prob->P;
+    size_t cnt;
+    if (layout == SMM_SRC_ISO) cnt = (size_t)P.ne * P.n;
+    else if (layout == SMM_SRC_ANISO) cnt = (size_t)P.nd * P.ne * P.n;
+    else return fail(P.ctx, SMM_EINVAL, "bad source layout");
+    for (size_t k = 0; k < cnt; ++k)
+        if (!std::isfinite(q[k])) return fail(P.ctx, SMM_EINVAL, "non-finite source");
+    P.q.assign(q, q + cnt);
+    P.src_layout = layout;
+    P.rhs_fixed_ready = false;
+    prob->D.src_dirty = true;
+    return SMM_OK;
+}
+
+int smm_set_inflow(smm_problem* prob, const double* psibar, int layout) {
+    if (!prob) return SMM_EINVAL;
+    Problem& P = prob->P;
+    const size_t full = (size_t)P.nbf * P.nq * P.nd;
+    if (layout == SMM_INFLOW_VACUUM) {
+        P.psibar.assign(full, 0.0);
+    } else if (layout == SMM_INFLOW_ISO_FACE) {
+        if (!psibar) return SMM_EINVAL;
+        P.psibar.assign(full, 0.0);
+        for (int bf = 0; bf < P.nbf; ++bf)
+            for (int q = 0; q < P.nq; ++q)
+                for (int d = 0; d < P.nd; ++d) P.psibar[((size_t)bf * P.nq + q) * P.nd + d] = psibar[bf];
+    } else if (layout == SMM_INFLOW_FULL) {
+        if (!psibar) return SMM_EINVAL;
+        P.psibar.assign(psibar, psibar + full);
+    } else {
+        return fail(P.ctx, SMM_EINVAL, "bad inflow layout");
+    }
+    for (double v : P.psibar)
+        if (!std::isfinite(v)) return fail(P.ctx, SMM_EINVAL, "non-finite inflow");
+    P.inflow_layout = layout;
+    P.rhs_fixed_ready = false;
+    prob->D.src_dirty = true;
+    return SMM_OK;
+}
+
+int smm_set_sweep_path(smm_problem* prob, int force_general) {
+    if (!prob) return SMM_EINVAL;
+    prob->D.force_general = force_general ? 1 : 0;
+    return SMM_OK;
+}
+
+void smm_default_opts(smm_solve_opts* o) {
+    if (!o) return;
+    o->precision = SMM_FP64;
+    o->outer_tol = 1e-10;
+    o->max_outer = 200;
+    o->inner_tol = 1e-12;
+    o->max_inner = 20000;
+    o->start = SMM_START_ZERO;
+    o->delta_sweeps = 0;
+    o->use_graph = 0;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// host tables and device upload
+// ---------------------------------------------------------------------------
+static int ensure_host(smm_problem* pr) {
+    Problem& P = pr->P;
+    if (!P.have_mat) return fail(P.ctx, SMM_ESTATE, "materials not set");
+    if (!P.lhs_ready) {
+        assemble_ip(P);
+        assemble_correction_operator(P);
+        setup_cartesian_operators(P);
+    }
+    if (!P.rhs_fixed_ready) {
+        if (P.psibar.empty()) P.psibar.assign((size_t)P.nbf * P.nq * P.nd, 0.0);
+        assemble_rhs_fixed(P);
+    }
+    return SMM_OK;
+}
+
+template <typename T>
+static int upload(smm_ctx* c, Dev& D, T** dst, const void* src, size_t bytes) {
+    if (!*dst) {
+        void* ptr = nullptr;
+        if (hipMalloc(&ptr, bytes ? bytes : 16) != hipSuccess) return fail(c, SMM_ENOMEM, "hipMalloc failed");
+        D.allocs.push_back(ptr);
+        *dst = reinterpret_cast<T*>(ptr);
+    }
+    if (src && bytes)
+        if (hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(c, SMM_EHIP, "hipMemcpy failed");
+    return SMM_OK;
+}
+
+template <typename T>
+static int alloc(smm_ctx* c, Dev& D, T** dst, size_t bytes) {
+    return upload(c, D, dst, nullptr, bytes);
+}
+
+static std::vector<float> to_f32(const std::vector<double>& v) {
+    std::vector<float> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+    return o;
+}
+
+#define UP(dst, vec)                                                              \
+    do {                                                                          \
+        int rc_ = upload(c, D, &(dst), (vec).data(), sizeof((vec)[0]) * (vec).size()); \
+        if (rc_) return rc_;                                                      \
+    } while (0)
+
+static int ensure_device(smm_problem* pr) {
+    Problem& P = pr->P;
+    Dev& D = pr->D;
+    smm_ctx* c = P.ctx;
+    if (c->device < 0) return fail(c, SMM_ESTATE, "host-only context");
+    int rc = ensure_host(pr);
+    if (rc) return rc;
+    const long L = (long)P.ne * P.n;
+    if (!D.built) {
+        UP(D.omega, P.omega);
+        D.ldw = (P.nd + 3) / 4 * 4;
+        std::vector<double> W(16 * (size_t)D.ldw, 0.0);
+        for (int d = 0; d < P.nd; ++d) {
+            const double w = P.w[d], ox = P.omega[d * 3], oy = P.omega[d * 3 + 1];
+            const double rows[8] = {w, w * ox, w * oy, w * ox * ox, w * ox * oy, w * oy * oy, w * std::fabs(ox),
+                                    w * std::fabs(oy)};
+            for (int r = 0; r < 8; ++r) W[(size_t)r * D.ldw + d] = rows[r];
+        }
+        std::vector<float> W32 = to_f32(W);
+        UP(D.W64, W);
+        UP(D.W32, W32);
+        // general sweep geometry
+        std::vector<float> f;
+        UP(D.Mk64, P.Mk); f = to_f32(P.Mk); UP(D.Mk32, f);
+        UP(D.Gx64, P.Gxk); f = to_f32(P.Gxk); UP(D.Gx32, f);
+        UP(D.Gy64, P.Gyk); f = to_f32(P.Gyk); UP(D.Gy32, f);
+        UP(D.nds64, P.nds); f = to_f32(P.nds); UP(D.nds32, f);
+        UP(D.Lf64, P.Lf); f = to_f32(P.Lf); UP(D.Lf32, f);
+        UP(D.nbr, P.nbr);
+        UP(D.bface_of, P.bface_of);
+        UP(D.upflag, P.upflag);
+        UP(D.lev_ptr, P.lev_ptr);
+        UP(D.lev_elem, P.lev_elem);
+        UP(D.bface_K, P.bface_K);
+        UP(D.bface_f, P.bface_f);
+        // work vectors
+        const int nd_q = P.nd;  // room for an anisotropic source
+        if ((rc = alloc(c, D, &D.S, sizeof(double) * (size_t)nd_q * L))) return rc;
+        for (int k = 0; k < 2; ++k)
+            if ((rc = alloc(c, D, &D.psi[k], sizeof(double) * (size_t)P.nd * L))) return rc;
+        if ((rc = alloc(c, D, &D.mom, sizeof(double) * 8 * L))) return rc;
+        if ((rc = alloc(c, D, &D.mom_acc, sizeof(double) * 8 * L))) return rc;
+        if ((rc = alloc(c, D, &D.T, sizeof(double) * 3 * L))) return rc;
+        if ((rc = alloc(c, D, &D.beta, sizeof(double) * (size_t)std::max(1, P.nbf * P.nq)))) return rc;
+        double** vecs[] = {&D.varphi, &D.varphi_prev, &D.x, &D.b, &D.r, &D.z, &D.p, &D.qv};
+        for (double** v : vecs)
+            if ((rc = alloc(c, D, v, sizeof(double) * L))) return rc;
+        const int epb = 256 / P.n;
+        D.cg_blocks = (P.ne + epb - 1) / epb;
+        if ((rc = alloc(c, D, &D.part, sizeof(double) * 3 * D.cg_blocks))) return rc;
+        if ((rc = alloc(c, D, &D.scal, sizeof(double) * 16))) return rc;
+        D.r_blocks = (int)std::min<long>(1024, (L + 255) / 256);
+        if ((rc = alloc(c, D, &D.rpart, sizeof(double) * 2 * D.r_blocks))) return rc;
+        if ((rc = alloc(c, D, &D.rout, sizeof(double) * 2))) return rc;
+        D.built = true;
+    }
+    if (D.tables_dirty) {
+        std::vector<float> f;
+        UP(D.st64, P.sigma_t); f = to_f32(P.sigma_t); UP(D.st32, f);
+        UP(D.sigma_s, P.sigma_s);
+        UP(D.bsr_col, P.bsr_col);
+        UP(D.bsr_val, P.bsr_val);
+        UP(D.bjac, P.bjac_inv);
+        UP(D.corr, P.corr_val);
+        if (P.nbf > 0) UP(D.beta_op, P.beta_op);
+        if (P.cartesian) {
+            UP(D.mat, P.mat_of);
+            // tables may grow when the material count changes: reallocate
+            auto reup = [&](void** dst64, void** dst32, const std::vector<double>& v) -> int {
+                if (*dst64) { hipFree(*dst64); D.allocs.erase(std::find(D.allocs.begin(), D.allocs.end(), *dst64)); *dst64 = nullptr; }
+                if (*dst32) { hipFree(*dst32); D.allocs.erase(std::find(D.allocs.begin(), D.allocs.end(), *dst32)); *dst32 = nullptr; }
+                int r1 = upload(c, D, dst64, v.data(), sizeof(double) * v.size());
+                if (r1) return r1;
+                std::vector<float> g = to_f32(v);
+                return upload(c, D, dst32, g.data(), sizeof(float) * g.size());
+            };
+            if ((rc = reup(&D.Pm64, &D.Pm32, P.Pm))) return rc;
+            if ((rc = reup(&D.Px64, &D.Px32, P.Px))) return rc;
+            if ((rc = reup(&D.Py64, &D.Py32, P.Py))) return rc;
+        }
+        D.tables_dirty = false;
+    }
+    if (D.src_dirty) {
+        UP(D.q, P.q);
+        UP(D.bfix, P.b_fixed);
+        // inflow: [nd][nbf][nq] for the general kernel, traces for the cartesian kernel
+        std::vector<double> pb((size_t)P.nd * P.nbf * P.nq);
+        for (int bf = 0; bf < P.nbf; ++bf)
+            for (int q = 0; q < P.nq; ++q)
+                for (int d = 0; d < P.nd; ++d)
+                    pb[((size_t)d * P.nbf + bf) * P.nq + q] = P.psibar[((size_t)bf * P.nq + q) * P.nd + d];
+        std::vector<float> f = to_f32(pb);
+        UP(D.pbar64, pb);
+        UP(D.pbar32, f);
+        if (P.cartesian) {
+            std::vector<double> bx, by;
+            cartesian_boundary_traces(P, bx, by);
+            UP(D.bx64, bx); f = to_f32(bx); UP(D.bx32, f);
+            UP(D.by64, by); f = to_f32(by); UP(D.by32, f);
+        }
+        D.src_dirty = false;
+    }
+    return SMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernels of one outer iteration
+// ---------------------------------------------------------------------------
+static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, const void* psi_lag, void* psi_out,
+                     bool with_inflow) {
+    Problem& P = pr->P;
+    Dev& D = pr->D;
+    smm_ctx* c = P.ctx;
+    hipError_t e;
+    if (P.cartesian && !D.force_general) {
+        CartSweepArgs a{};
+        a.nx = P.nx; a.ny = P.ny; a.nd = P.nd; a.nb = P.nb; a.nmat = P.nmat;
+        a.s_aniso = s_aniso;
+        a.S = S;
+        a.Pm = fp64 ? D.Pm64 : D.Pm32;
+        a.Px = fp64 ? D.Px64 : D.Px32;
+        a.Py = fp64 ? D.Py64 : D.Py32;
+        a.mat = D.mat;
+        a.omega = D.omega;
+        a.bx = with_inflow && P.inflow_layout != SMM_INFLOW_VACUUM ? (fp64 ? D.bx64 : D.bx32) : nullptr;
+        a.by = with_inflow && P.inflow_layout != SMM_INFLOW_VACUUM ? (fp64 ? D.by64 : D.by32) : nullptr;
+        a.psi = psi_out;
+        e = launch_sweep_cart(fp64, a, c->stream);
+    } else {
+        GenSweepArgs a{};
+        a.ne = P.ne; a.nd = P.nd; a.nb = P.nb; a.nq = P.nq; a.nbf = P.nbf; a.nlev = P.nlev_max;
+        a.s_aniso = s_aniso;
+        a.S = S;
+        a.Mk = fp64 ? D.Mk64 : D.Mk32;
+        a.Gx = fp64 ? D.Gx64 : D.Gx32;
+        a.Gy = fp64 ? D.Gy64 : D.Gy32;
+        a.nds = fp64 ? D.nds64 : D.nds32;
+        a.Lf = fp64 ? D.Lf64 : D.Lf32;
+        a.sigma_t = fp64 ? D.st64 : D.st32;
+        a.nbr = D.nbr;
+        a.bface_of = D.bface_of;
+        a.upflag = D.upflag;
+        a.lev_ptr = D.lev_ptr;
+        a.lev_elem = D.lev_elem;
+        a.omega = D.omega;
+        a.psibar = with_inflow && P.inflow_layout != SMM_INFLOW_VACUUM ? (fp64 ? D.pbar64 : D.pbar32) : nullptr;
+        a.psi_lag = psi_lag;
+        a.psi = psi_out;
+        e = launch_sweep_general(fp64, a, c->stream);
+    }
+    if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
+    return SMM_OK;
+}
+
+static CgState cg_state(smm_problem* pr) {
+    Problem& P = pr->P;
+    Dev& D = pr->D;
+    CgState s{};
+    s.ne = P.ne; s.n = P.n;
+    s.col = D.bsr_col; s.A = D.bsr_val; s.Dinv = D.bjac; s.b = D.b;
+    s.x = D.x; s.r = D.r; s.z = D.z; s.p = D.p; s.q = D.qv;
+    s.part = D.part; s.scal = D.scal; s.nblocks = D.cg_blocks;
+    return s;
+}
+
+// Solve the IP system for b (already in D.b) starting from D.x.  Returns the
+// CG iteration count in *its.
+static int moment_solve(smm_problem* pr, double tol, int max_inner, int* its) {
+    Problem& P = pr->P;
+    Dev& D = pr->D;
+    smm_ctx* c = P.ctx;
+    CgState s = cg_state(pr);
+    HIPCHK(c, cg_start(s, tol, c->stream));
+    int done_its = 0;
+    double sc[8];
+    int chunk = 4;
+    while (true) {
+        HIPCHK(c, hipMemcpyAsync(sc, D.scal, sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        done_its = (int)sc[5];
+        if (sc[6] != 0.0) return fail(c, SMM_EBREAKDOWN, "CG breakdown");
+        if (sc[4] != 0.0) break;
+        if (done_its >= max_inner) break;
+        const int k = std::min(chunk, max_inner - done_its);
+        HIPCHK(c, cg_iterations(s, k, tol, c->stream));
+        chunk = std::min(chunk * 2, 64);
+    }
+    *its = done_its;
+    return SMM_OK;
+}
+
+// One evaluation of G from D.varphi into D.x (b, closures, moments updated).
+// psi_cur / psi_prev are sweep buffers; delta mode sweeps sigma_s/(4pi)(varphi - varphi_prev).
+static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, double inner_tol, int max_inner,
+                  int* cg_its) {
+    Problem& P = pr->P;
+    Dev& D = pr->D;
+    smm_ctx* c = P.ctx;
+    const long L = (long)P.ne * P.n;
+    const bool aniso = P.src_layout == SMM_SRC_ANISO;
+    const int nd_q = aniso ? P.nd : 1;
+    int rc;
+    // scattering source (a1)
+    if (!delta || first) {
+        HIPCHK(c, launch_source(fp64, P.ne, P.n, nd_q, D.sigma_s, D.varphi, nullptr, D.q, D.S, c->stream));
+    } else {
+        HIPCHK(c, launch_source(fp64, P.ne, P.n, 1, D.sigma_s, D.varphi, D.varphi_prev, nullptr, D.S, c->stream));
+    }
+    const bool s_aniso = aniso && (!delta || first);
+    // sweep (a2): the previous sweep serves as the lagged input on curved meshes
+    void* out = D.psi[cur];
+    const void* lag = first ? nullptr : D.psi[cur ^ 1];
+    if ((rc = run_sweep(pr, fp64, D.S, s_aniso ? 1 : 0, lag, out, !delta || first))) return rc;
+    // moments (a3)
+    HIPCHK(c, launch_moments(fp64, out, P.nd, L, fp64 ? D.W64 : D.W32, D.ldw, D.mom, c->stream));
+    const double* mom = D.mom;
+    if (delta) {
+        if (first) HIPCHK(c, hipMemsetAsync(D.mom_acc, 0, sizeof(double) * 8 * L, c->stream));
+        HIPCHK(c, launch_axpy_mom(8 * L, D.mom, D.mom_acc, c->stream));
+        mom = D.mom_acc;
+    }
+    D.last_mom = mom;
+    // closures (a4) and right-hand side (a5)
+    HIPCHK(c, launch_closures(P.ne, P.n, P.nb, P.nq, P.nbf, mom, D.bface_K, D.bface_f, (const double*)D.Lf64,
+                              P.eb0x, P.eb0y, D.T, D.beta, c->stream));
+    HIPCHK(c, launch_rhs(P.ne, P.n, P.nq, D.bfix, D.bsr_col, D.corr, D.T, D.bface_of, D.beta_op, D.beta, D.b,
+                         c->stream));
+    // moment solve (a6), warm-started from the current iterate
+    HIPCHK(c, hipMemcpyAsync(D.x, D.varphi, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
+    return moment_solve(pr, inner_tol, max_inner, cg_its);
+}
+
+extern "C" {
+
+int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varphi0, smm_solve_info* info) {
+    if (!prob) return SMM_EINVAL;
+    smm_solve_opts o;
+    smm_default_opts(&o);
+    if (opts) o = *opts;
+    Problem& P = prob->P;
+    Dev& D = prob->D;
+    smm_ctx* c = P.ctx;
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = ensure_device(prob);
+    if (rc) return rc;
+    auto t1 = std::chrono::steady_clock::now();
+    const long L = (long)P.ne * P.n;
+    const bool fp64 = o.precision == SMM_FP64;
+    const bool delta = o.delta_sweeps != 0;
+    int its = 0;
+    if (o.start == SMM_START_GIVEN) {
+        if (!varphi0) return fail(c, SMM_EINVAL, "varphi0 required");
+        HIPCHK(c, hipMemcpyAsync(D.varphi, varphi0, sizeof(double) * L, hipMemcpyHostToDevice, c->stream));
+    } else if (o.start == SMM_START_DIFFUSION) {
+        HIPCHK(c, hipMemcpyAsync(D.b, D.bfix, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemsetAsync(D.x, 0, sizeof(double) * L, c->stream));
+        if ((rc = moment_solve(prob, o.inner_tol, o.max_inner, &its))) return rc;
+        HIPCHK(c, hipMemcpyAsync(D.varphi, D.x, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        HIPCHK(c, hipMemsetAsync(D.varphi, 0, sizeof(double) * L, c->stream));
+    }
+    HIPCHK(c, hipMemsetAsync(D.varphi_prev, 0, sizeof(double) * L, c->stream));
+    int cg_total = 0, cg_max = 0;
+    double r = 0, rabs = 0;
+    int it = 0;
+    int status = SMM_ENOCONV;
+    for (it = 1; it <= o.max_outer; ++it) {
+        int cgi = 0;
+        if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, o.inner_tol, o.max_inner, &cgi))) return rc;
+        cg_total += cgi;
+        cg_max = std::max(cg_max, cgi);
+        // residual (a7)
+        HIPCHK(c, launch_residual(L, D.x, D.varphi, D.rpart, D.r_blocks, D.rout, c->stream));
+        double ro[2];
+        HIPCHK(c, hipMemcpyAsync(ro, D.rout, sizeof(double) * 2, hipMemcpyDeviceToHost, c->stream));
+        // shift iterates: varphi_prev <- varphi, varphi <- x
+        std::swap(D.varphi_prev, D.varphi);
+        std::swap(D.varphi, D.x);
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        rabs = ro[0];
+        r = ro[1] > 0 ? ro[0] / ro[1] : (ro[0] == 0 ? 0.0 : INFINITY);
+        if (!std::isfinite(r) || !std::isfinite(rabs)) { status = SMM_ENAN; break; }
+        if (r < o.outer_tol) { status = SMM_OK; break; }
+    }
+    D.last_varphi = D.varphi;
+    if (it > o.max_outer) it = o.max_outer;
+    D.have_outputs = true;
+    auto t2 = std::chrono::steady_clock::now();
+    if (info) {
+        info->iterations = it;
+        info->residual = r;
+        info->residual_abs = rabs;
+        info->cg_iterations_total = cg_total;
+        info->cg_iterations_max = cg_max;
+        info->t_total_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+        info->t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (status == SMM_ENAN) return fail(c, SMM_ENAN, "non-finite residual");
+    if (status == SMM_ENOCONV) return fail(c, SMM_ENOCONV, "max_outer reached");
+    return SMM_OK;
+}
+
+int smm_get_outputs(smm_problem* prob, double* varphi, double* phi, double* J, double* T, double* beta,
+                    int on_device) {
+    if (!prob) return SMM_EINVAL;
+    Problem& P = prob->P;
+    Dev& D = prob->D;
+    smm_ctx* c = P.ctx;
+    if (!D.have_outputs || !D.last_mom) return fail(c, SMM_ESTATE, "no solve has run");
+    const long L = (long)P.ne * P.n;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (varphi && D.last_varphi)
+        HIPCHK(c, hipMemcpyAsync(varphi, D.last_varphi, sizeof(double) * L, k, c->stream));
+    if (phi) HIPCHK(c, hipMemcpyAsync(phi, D.last_mom, sizeof(double) * L, k, c->stream));
+    if (J) HIPCHK(c, hipMemcpyAsync(J, D.last_mom + L, sizeof(double) * 2 * L, k, c->stream));
+    if (T) HIPCHK(c, hipMemcpyAsync(T, D.T, sizeof(double) * 3 * L, k, c->stream));
+    if (beta && P.nbf > 0)
+        HIPCHK(c, hipMemcpyAsync(beta, D.beta, sizeof(double) * P.nbf * P.nq, k, c->stream));
+    if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SMM_OK;
+}
+
+int smm_apply_sweep(smm_problem* prob, int precision, const void* S, int s_layout, const void* psi_lag,
+                    void* psi_out, int with_inflow) {
+    if (!prob || !S || !psi_out) return SMM_EINVAL;
+    if (precision != SMM_FP64 && precision != SMM_FP32_SWEEP) return SMM_EINVAL;
+    if (s_layout != SMM_SRC_ISO && s_layout != SMM_SRC_ANISO) return SMM_EINVAL;
+    int rc = ensure_device(prob);
+    if (rc) return rc;
+    return run_sweep(prob, precision == SMM_FP64, S, s_layout == SMM_SRC_ANISO ? 1 : 0, psi_lag, psi_out,
+                     with_inflow != 0);
+}
+
+int smm_apply_moments(smm_problem* prob, int precision, const void* psi, double* mom) {
+    if (!prob || !psi || !mom) return SMM_EINVAL;
+    if (precision != SMM_FP64 && precision != SMM_FP32_SWEEP) return SMM_EINVAL;
+    int rc = ensure_device(prob);
+    if (rc) return rc;
+    Problem& P = prob->P;
+    Dev& D = prob->D;
+    const bool fp64 = precision == SMM_FP64;
+    HIPCHK(P.ctx, launch_moments(fp64, psi, P.nd, (long)P.ne * P.n, fp64 ? D.W64 : D.W32, D.ldw, mom,
+                                 P.ctx->stream));
+    return SMM_OK;
+}
+
+int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, double* varphi_out, double inner_tol,
+                int max_inner) {
+    if (!prob || !varphi_in || !varphi_out) return SMM_EINVAL;
+    int rc = ensure_device(prob);
+    if (rc) return rc;
+    Problem& P = prob->P;
+    Dev& D = prob->D;
+    smm_ctx* c = P.ctx;
+    const long L = (long)P.ne * P.n;
+    HIPCHK(c, hipMemcpyAsync(D.varphi, varphi_in, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
+    int its = 0;
+    if ((rc = eval_G(prob, precision == SMM_FP64, false, true, 0, inner_tol, max_inner, &its))) return rc;
+    HIPCHK(c, hipMemcpyAsync(varphi_out, D.x, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    D.have_outputs = true;
+    D.last_varphi = D.x;
+    return SMM_OK;
+}
+
+int smm_debug_ip_dense(const smm_problem* prob_c, double* A, double* b_fixed) {
+    smm_problem* prob = const_cast<smm_problem*>(prob_c);
+    if (!prob) return SMM_EINVAL;
+    int rc = ensure_host(prob);
+    if (rc) return rc;
+    Problem& P = prob->P;
+    const long N = (long)P.ne * P.n;
+    if (N > 20000) return fail(P.ctx, SMM_EINVAL, "problem too large for a dense copy");
+    if (A) {
+        std::memset(A, 0, sizeof(double) * N * N);
+        for (int K = 0; K < P.ne; ++K)
+            for (int s = 0; s < 5; ++s) {
+                const int Kc = P.bsr_col[K * 5 + s];
+                if (Kc < 0) continue;
+                for (int i = 0; i < P.n; ++i)
+                    for (int j = 0; j < P.n; ++j)
+                        A[((long)K * P.n + i) * N + (long)Kc * P.n + j] +=
+                            P.bsr_val[(((size_t)K * 5 + s) * P.n + i) * P.n + j];
+            }
+    }
+    if (b_fixed) std::memcpy(b_fixed, P.b_fixed.data(), sizeof(double) * N);
+    return SMM_OK;
+}
+
+int smm_time_sweep(smm_problem* prob, int precision, int reps, double* ms_avg) {
+    if (!prob || !ms_avg || reps < 1) return SMM_EINVAL;
+    int rc = ensure_device(prob);
+    if (rc) return rc;
+    Problem& P = prob->P;
+    Dev& D = prob->D;
+    smm_ctx* c = P.ctx;
+    const bool fp64 = precision == SMM_FP64;
+    const long L = (long)P.ne * P.n;
+    HIPCHK(c, launch_source(fp64, P.ne, P.n, 1, D.sigma_s, D.varphi, nullptr, D.q, D.S, c->stream));
+    if ((rc = run_sweep(prob, fp64, D.S, 0, nullptr, D.psi[0], true))) return rc;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int k = 0; k < reps; ++k)
+        if ((rc = run_sweep(prob, fp64, D.S, 0, nullptr, D.psi[k & 1], true))) return rc;
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    (void)L;
+    *ms_avg = ms / reps;
+    return SMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,736 @@
+// Device kernels of libsmm (gfx950 / CDNA4).
+//
+//  * sweep_cart_kernel    Cartesian wavefront sweep: one workgroup per
+//                         direction walks the anti-diagonals of the element
+//                         grid; the upwind face traces live in LDS.
+//  * sweep_general_kernel Curved meshes: per (element, direction) the local
+//                         upwind DG matrix is assembled in LDS and eliminated
+//                         by one wavefront; levels come from the sweep graph.
+//  * moments_kernel       Angular moments mom = W psi on the matrix cores.
+//  * closure / rhs / cg   SMM correction tensor and boundary factor, the IP
+//                         right-hand side, FP64 block-Jacobi PCG.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace smm {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Cartesian sweep.
+// For direction d in quadrant (sx, sy), element (i, j) receives its x-face
+// trace from (i - sx, j) and its y-face trace from (i, j - sy); all elements
+// on one anti-diagonal of the quadrant-oriented grid are independent.  With
+// the tabulated operators of the element's material,
+//     psi_K = Pm S_K + Px t_x + Py t_y.
+// Traces are double-buffered by level parity in LDS so one barrier per level
+// suffices.
+// ---------------------------------------------------------------------------
+template <typename T, int NB>
+__global__ __launch_bounds__(1024) void sweep_cart_kernel(CartSweepArgs a) {
+    constexpr int N = NB * NB;
+    const int d = blockIdx.x;
+    const int nx = a.nx, ny = a.ny, nd = a.nd;
+    const long ne = (long)nx * ny;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* xtr = reinterpret_cast<T*>(smem);  // [2][ny][NB]
+    T* ytr = xtr + 2 * ny * NB;           // [2][nx][NB]
+    const double ox = a.omega[d * 3], oy = a.omega[d * 3 + 1];
+    const bool sx = ox > 0.0, sy = oy > 0.0;
+    const T* bx = reinterpret_cast<const T*>(a.bx);
+    const T* by = reinterpret_cast<const T*>(a.by);
+    for (int t = threadIdx.x; t < ny * NB; t += blockDim.x) {
+        const T v = bx ? bx[(long)d * ny * NB + t] : T(0);
+        xtr[t] = v;
+        xtr[ny * NB + t] = v;
+    }
+    for (int t = threadIdx.x; t < nx * NB; t += blockDim.x) {
+        const T v = by ? by[(long)d * nx * NB + t] : T(0);
+        ytr[t] = v;
+        ytr[nx * NB + t] = v;
+    }
+    __syncthreads();
+    const int aout = sx ? NB - 1 : 0;
+    const int bout = sy ? NB - 1 : 0;
+    const T* S = reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0);
+    T* psi = reinterpret_cast<T*>(a.psi) + (long)d * ne * N;
+    const T* Pm = reinterpret_cast<const T*>(a.Pm);
+    const T* Px = reinterpret_cast<const T*>(a.Px);
+    const T* Py = reinterpret_cast<const T*>(a.Py);
+    const int nlev = nx + ny - 1;
+    for (int l = 0; l < nlev; ++l) {
+        const int i0 = l - (ny - 1) > 0 ? l - (ny - 1) : 0;
+        const int i1 = l < nx - 1 ? l : nx - 1;
+        const int len = i1 - i0 + 1;
+        const int cur = l & 1, nxt = cur ^ 1;
+        for (int t = threadIdx.x; t < len * N; t += blockDim.x) {
+            const int e = t / N, r = t - e * N;
+            const int ip = i0 + e, jp = l - ip;
+            const int i = sx ? ip : nx - 1 - ip;
+            const int j = sy ? jp : ny - 1 - jp;
+            const long K = (long)j * nx + i;
+            const long o = (long)a.mat[K] * nd + d;
+            const T* pm = Pm + (o * N + r) * N;
+            const T* px = Px + (o * N + r) * NB;
+            const T* py = Py + (o * N + r) * NB;
+            const T* sk = S + K * N;
+            T acc = T(0);
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc += pm[c] * sk[c];
+            const T* tx = xtr + (cur * ny + j) * NB;
+            const T* ty = ytr + (cur * nx + i) * NB;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc += px[c] * tx[c] + py[c] * ty[c];
+            psi[K * N + r] = acc;
+            const int ra = r % NB, rb = r / NB;
+            if (ra == aout) xtr[(nxt * ny + j) * NB + rb] = acc;
+            if (rb == bout) ytr[(nxt * nx + i) * NB + ra] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NB>
+static hipError_t launch_cart_t(const CartSweepArgs& a, hipStream_t s) {
+    constexpr int N = NB * NB;
+    const int maxlen = a.nx < a.ny ? a.nx : a.ny;
+    int threads = ((maxlen * N + 63) / 64) * 64;
+    if (threads > 1024) threads = 1024;
+    if (threads < 64) threads = 64;
+    const size_t lds = sizeof(T) * 2 * (size_t)(a.nx + a.ny) * NB;
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_cart_kernel<T, NB>), dim3(a.nd), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_cart(bool fp64, const CartSweepArgs& a, hipStream_t s) {
+    switch (a.nb) {
+        case 2: return fp64 ? launch_cart_t<double, 2>(a, s) : launch_cart_t<float, 2>(a, s);
+        case 3: return fp64 ? launch_cart_t<double, 3>(a, s) : launch_cart_t<float, 3>(a, s);
+        case 4: return fp64 ? launch_cart_t<double, 4>(a, s) : launch_cart_t<float, 4>(a, s);
+        case 5: return fp64 ? launch_cart_t<double, 5>(a, s) : launch_cart_t<float, 5>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// General sweep.  Per element K and direction Omega (upwind DG, integrated by
+// parts once, pointwise upwinding at the face Gauss points):
+//   A_ij = sigma_t M_ij - Omega_x Gx_ij - Omega_y Gy_ij
+//          + sum_f sum_q max(Omega.n_q, 0) u_i(q) u_j(q)
+//   b_i  = sum_j M_ij S_j + sum_f sum_q max(-Omega.n_q, 0) u_i(q) psi_up(q)
+// psi_up is the neighbour's trace (this sweep if the neighbour is upstream in
+// the chord graph, else the previous sweep) or the inflow on the boundary.
+// One wavefront per element: assembly, elimination without pivoting (the
+// symmetric part of A is positive definite) and back substitution in LDS.
+// ---------------------------------------------------------------------------
+constexpr int GEN_WAVES = 4;
+constexpr int GEN_MAXQ = 12;
+
+template <int NB>
+__device__ __forceinline__ int face_pos(int f, int i) {
+    const int a = i % NB, b = i / NB;
+    switch (f) {
+        case 0: return b == 0 ? a : -1;
+        case 1: return a == NB - 1 ? b : -1;
+        case 2: return b == NB - 1 ? a : -1;
+        default: return a == 0 ? b : -1;
+    }
+}
+
+template <int NB>
+__device__ __forceinline__ int face_node(int f, int c) {
+    switch (f) {
+        case 0: return c;
+        case 1: return (NB - 1) + NB * c;
+        case 2: return c + NB * (NB - 1);
+        default: return NB * c;
+    }
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepArgs a) {
+    constexpr int N = NB * NB;
+    const int d = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nq = a.nq, ne = a.ne;
+    __shared__ T Aug[GEN_WAVES][N][N + 1];
+    __shared__ T xs[GEN_WAVES][N];
+    __shared__ T fval[GEN_WAVES][4][GEN_MAXQ];
+    __shared__ T fon[GEN_WAVES][4][GEN_MAXQ];
+    const T ox = (T)a.omega[d * 3], oy = (T)a.omega[d * 3 + 1];
+    const T* S = reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0);
+    const T* Mk = reinterpret_cast<const T*>(a.Mk);
+    const T* Gx = reinterpret_cast<const T*>(a.Gx);
+    const T* Gy = reinterpret_cast<const T*>(a.Gy);
+    const T* nds = reinterpret_cast<const T*>(a.nds);
+    const T* Lf = reinterpret_cast<const T*>(a.Lf);
+    const T* st = reinterpret_cast<const T*>(a.sigma_t);
+    const T* pbar = reinterpret_cast<const T*>(a.psibar);
+    const T* plag = reinterpret_cast<const T*>(a.psi_lag);
+    T* psi = reinterpret_cast<T*>(a.psi);
+    const int* lp = a.lev_ptr + (long)d * (a.nlev + 1);
+    const int* le = a.lev_elem + (long)d * ne;
+    for (int l = 0; l < a.nlev; ++l) {
+        const int beg = lp[l], end = lp[l + 1];
+        for (int base = beg; base < end; base += GEN_WAVES) {
+            const int e = base + wv;
+            const bool active = e < end;
+            const int K = active ? le[e] : le[beg];
+            // face Omega.n and inflow values at the face points
+            if (lane < 4 * nq) {
+                const int f = lane / nq, q = lane - f * nq;
+                const T* nn = nds + (((long)K * 4 + f) * nq + q) * 2;
+                const T on = ox * nn[0] + oy * nn[1];
+                T val = T(0);
+                if (on < T(0)) {
+                    const int Nb = a.nbr[K * 4 + f];
+                    if (Nb < 0) {
+                        if (pbar) val = pbar[((long)d * a.nbf + a.bface_of[K * 4 + f]) * nq + q];
+                    } else {
+                        const bool up = (a.upflag[(long)d * ne + K] >> f) & 1;
+                        const T* src = up ? psi : plag;
+                        if (src) {
+                            const int fN = (f + 2) & 3;
+                            const T* sN = src + ((long)d * ne + Nb) * N;
+                            for (int c = 0; c < NB; ++c) val += Lf[c * nq + q] * sN[face_node<NB>(fN, c)];
+                        }
+                    }
+                }
+                fval[wv][f][q] = val;
+                fon[wv][f][q] = on;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const T sK = st[K];
+            const T* M = Mk + (long)K * N * N;
+            const T* gx = Gx + (long)K * N * N;
+            const T* gy = Gy + (long)K * N * N;
+            for (int idx = lane; idx < N * N; idx += 64) {
+                const int i = idx / N, j = idx - i * N;
+                T v = sK * M[idx] - ox * gx[idx] - oy * gy[idx];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    const int ci = face_pos<NB>(f, i), cj = face_pos<NB>(f, j);
+                    if (ci >= 0 && cj >= 0)
+                        for (int q = 0; q < nq; ++q) {
+                            const T on = fon[wv][f][q];
+                            if (on > T(0)) v += on * Lf[ci * nq + q] * Lf[cj * nq + q];
+                        }
+                }
+                Aug[wv][i][j] = v;
+            }
+            for (int i = lane; i < N; i += 64) {
+                T b = T(0);
+                const T* sk = S + (long)K * N;
+                for (int j = 0; j < N; ++j) b += M[i * N + j] * sk[j];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    const int ci = face_pos<NB>(f, i);
+                    if (ci >= 0)
+                        for (int q = 0; q < nq; ++q) {
+                            const T on = fon[wv][f][q];
+                            if (on < T(0)) b -= on * Lf[ci * nq + q] * fval[wv][f][q];
+                        }
+                }
+                Aug[wv][i][N] = b;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int k = 0; k < N; ++k) {
+                const T piv = Aug[wv][k][k];
+                const int w = N - k;  // columns k+1 .. N
+                for (int idx = lane; idx < (N - 1 - k) * w; idx += 64) {
+                    const int i = k + 1 + idx / w, j = k + 1 + idx % w;
+                    Aug[wv][i][j] -= Aug[wv][i][k] / piv * Aug[wv][k][j];
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            for (int k = N - 1; k >= 0; --k) {
+                if (lane == 0) xs[wv][k] = Aug[wv][k][N] / Aug[wv][k][k];
+                __builtin_amdgcn_wave_barrier();
+                const T xk = xs[wv][k];
+                for (int i = lane; i < k; i += 64) Aug[wv][i][N] -= Aug[wv][i][k] * xk;
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (active)
+                for (int i = lane; i < N; i += 64) psi[((long)d * ne + K) * N + i] = xs[wv][i];
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NB>
+static hipError_t launch_gen_t(const GenSweepArgs& a, hipStream_t s) {
+    if (a.nq > GEN_MAXQ || 4 * a.nq > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_general_kernel<T, NB>), dim3(a.nd), dim3(64 * GEN_WAVES), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_general(bool fp64, const GenSweepArgs& a, hipStream_t s) {
+    switch (a.nb) {
+        case 2: return fp64 ? launch_gen_t<double, 2>(a, s) : launch_gen_t<float, 2>(a, s);
+        case 3: return fp64 ? launch_gen_t<double, 3>(a, s) : launch_gen_t<float, 3>(a, s);
+        case 4: return fp64 ? launch_gen_t<double, 4>(a, s) : launch_gen_t<float, 4>(a, s);
+        case 5: return fp64 ? launch_gen_t<double, 5>(a, s) : launch_gen_t<float, 5>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Angular moments on the matrix cores: mom[row][c] = sum_d W[row][d] psi[d][c]
+// for rows phi, J_x, J_y, P_xx, P_xy, P_yy, sum w|O_x|, sum w|O_y| (rows 8-15
+// of the 16x16 tile are zero).  One wavefront per 16 columns; the 16x16x4
+// MFMA takes A[i][k] from lane i + 16 k and B[k][j] from lane j + 16 k; the
+// FP32 variant returns D[i][j] in lane j + 16 (i / 4), element i % 4.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void moments_f32_kernel(const float* __restrict__ psi, int nd, long L,
+                                                          const float* __restrict__ W, int ldw,
+                                                          double* __restrict__ mom) {
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long col0 = wave * 16;
+    if (col0 >= L) return;
+    const int i = lane & 15, kk = lane >> 4;
+    const bool colok = col0 + i < L;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < nd; k += 4) {
+        const int dk = k + kk;
+        const float av = dk < nd ? W[i * ldw + dk] : 0.f;
+        const float bv = (dk < nd && colok) ? psi[(long)dk * L + col0 + i] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+    }
+    if (kk < 2 && colok) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mom[(long)(4 * kk + r) * L + col0 + i] = (double)acc[r];
+    }
+}
+
+__global__ __launch_bounds__(256) void moments_f64_kernel(const double* __restrict__ psi, int nd, long L,
+                                                          const double* __restrict__ W, int ldw,
+                                                          double* __restrict__ mom) {
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long col0 = wave * 16;
+    if (col0 >= L) return;
+    const int i = lane & 15, kk = lane >> 4;
+    const bool colok = col0 + i < L;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < nd; k += 4) {
+        const int dk = k + kk;
+        const double av = dk < nd ? W[i * ldw + dk] : 0.0;
+        const double bv = (dk < nd && colok) ? psi[(long)dk * L + col0 + i] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    // the FP64 variant returns D[i][j] in lane j + 16 (i % 4), element i / 4
+    if (colok) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) mom[(long)(kk + 4 * r) * L + col0 + i] = acc[r];
+    }
+}
+
+hipError_t launch_moments(bool fp64, const void* psi, int nd, long L, const void* W, int ldw,
+                          double* mom, hipStream_t s) {
+    const long waves = (L + 15) / 16;
+    const long blocks = (waves + 3) / 4;
+    if (fp64)
+        hipLaunchKernelGGL(moments_f64_kernel, dim3(blocks), dim3(256), 0, s, (const double*)psi, nd, L,
+                           (const double*)W, ldw, mom);
+    else
+        hipLaunchKernelGGL(moments_f32_kernel, dim3(blocks), dim3(256), 0, s, (const float*)psi, nd, L,
+                           (const float*)W, ldw, mom);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scattering source S = sigma_s/(4 pi) (x - x_prev) [+ q]  (x_prev may be null).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void source_kernel(int ne, int n, int nd_q, const double* __restrict__ ss,
+                              const double* __restrict__ x, const double* __restrict__ xp,
+                              const double* __restrict__ q, T* __restrict__ S) {
+    const long L = (long)ne * n;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int dq = blockIdx.y;
+    if (t >= L) return;
+    const long K = t / n;
+    double v = x ? ss[K] * (1.0 / (4.0 * 3.14159265358979323846)) * (xp ? x[t] - xp[t] : x[t]) : 0.0;
+    if (q) v += q[(long)dq * L + t];
+    S[(long)dq * L + t] = (T)v;
+}
+
+hipError_t launch_source(bool fp64, int ne, int n, int nd_q, const double* sigma_s, const double* x,
+                         const double* x_prev, const double* q, void* S, hipStream_t s) {
+    const long L = (long)ne * n;
+    dim3 grid((unsigned)((L + 255) / 256), nd_q > 0 ? nd_q : 1);
+    if (fp64)
+        hipLaunchKernelGGL(source_kernel<double>, grid, dim3(256), 0, s, ne, n, nd_q, sigma_s, x, x_prev, q,
+                           (double*)S);
+    else
+        hipLaunchKernelGGL(source_kernel<float>, grid, dim3(256), 0, s, ne, n, nd_q, sigma_s, x, x_prev, q,
+                           (float*)S);
+    return hipGetLastError();
+}
+
+__global__ void axpy_kernel(long L, const double* __restrict__ a, double* __restrict__ acc) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < L) acc[t] += a[t];
+}
+
+hipError_t launch_axpy_mom(long L, const double* a, double* acc, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, s, L, a, acc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Closures: T = P - phi/3 I (xx, xy, yy) at the nodes; beta at boundary face
+// points from the interior trace: beta = sum w |Omega.n| psi - E_b0 phi, with
+// |Omega.n| = |Omega_x| on x-normal faces (1, 3), |Omega_y| on y-normal faces.
+// ---------------------------------------------------------------------------
+__global__ void closures_T_kernel(long L, const double* __restrict__ mom, double* __restrict__ T) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= L) return;
+    const double phi = mom[t];
+    T[t] = mom[3 * L + t] - phi / 3.0;
+    T[L + t] = mom[4 * L + t];
+    T[2 * L + t] = mom[5 * L + t] - phi / 3.0;
+}
+
+__global__ void closures_beta_kernel(int n, int nb, int nq, int nbf, long L, const double* __restrict__ mom,
+                                     const int* __restrict__ bK, const int* __restrict__ bF,
+                                     const double* __restrict__ Lf, double eb0x, double eb0y,
+                                     double* __restrict__ beta) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbf * nq) return;
+    const int bf = t / nq, q = t - bf * nq;
+    const int K = bK[bf], f = bF[bf];
+    const bool xnorm = (f == 1 || f == 3);
+    const double* row = mom + (xnorm ? 6 : 7) * L;
+    const double e = xnorm ? eb0x : eb0y;
+    double v = 0.0;
+    for (int c = 0; c < nb; ++c) {
+        int k;
+        switch (f) {
+            case 0: k = c; break;
+            case 1: k = (nb - 1) + nb * c; break;
+            case 2: k = c + nb * (nb - 1); break;
+            default: k = nb * c; break;
+        }
+        const long idx = (long)K * n + k;
+        v += Lf[c * nq + q] * (row[idx] - e * mom[idx]);
+    }
+    beta[t] = v;
+}
+
+hipError_t launch_closures(int ne, int n, int nb, int nq, int nbf, const double* mom, const int* bface_K,
+                           const int* bface_f, const double* Lf, double eb0x, double eb0y, double* T,
+                           double* beta, hipStream_t s) {
+    const long L = (long)ne * n;
+    hipLaunchKernelGGL(closures_T_kernel, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, s, L, mom, T);
+    if (nbf > 0)
+        hipLaunchKernelGGL(closures_beta_kernel, dim3((nbf * nq + 255) / 256), dim3(256), 0, s, n, nb, nq, nbf,
+                           L, mom, bface_K, bface_f, Lf, eb0x, eb0y, beta);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// IP right-hand side: b = b_fixed + C T - B beta (one thread per row).
+// ---------------------------------------------------------------------------
+__global__ void rhs_kernel(int ne, int n, int nq, const double* __restrict__ bfix, const int* __restrict__ col,
+                           const double* __restrict__ corr, const double* __restrict__ T,
+                           const int* __restrict__ bface_of, const double* __restrict__ bop,
+                           const double* __restrict__ beta, double* __restrict__ b) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long L = (long)ne * n;
+    if (t >= L) return;
+    const int K = (int)(t / n), i = (int)(t - (long)K * n);
+    const int n3 = 3 * n;
+    double v = bfix[t];
+    for (int s = 0; s < 5; ++s) {
+        const int Kc = col[K * 5 + s];
+        if (Kc < 0) continue;
+        const double* row = corr + (((long)K * 5 + s) * n + i) * n3;
+        for (int c = 0; c < 3; ++c) {
+            const double* tv = T + c * L + (long)Kc * n;
+            for (int j = 0; j < n; ++j) v += row[c * n + j] * tv[j];
+        }
+    }
+    for (int f = 0; f < 4; ++f) {
+        const int bf = bface_of[K * 4 + f];
+        if (bf < 0) continue;
+        const double* bo = bop + ((long)bf * n + i) * nq;
+        const double* be = beta + (long)bf * nq;
+        for (int q = 0; q < nq; ++q) v -= bo[q] * be[q];
+    }
+    b[t] = v;
+}
+
+hipError_t launch_rhs(int ne, int n, int nq, const double* bfix, const int* bsr_col, const double* corr,
+                      const double* T, const int* bface_of, const double* beta_op, const double* beta,
+                      double* b, hipStream_t s) {
+    const long L = (long)ne * n;
+    hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, s, ne, n, nq, bfix, bsr_col,
+                       corr, T, bface_of, beta_op, beta, b);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 PCG with element block-Jacobi preconditioner.
+// Blocks cover whole elements (epb = 256 / n elements each) so the
+// preconditioner can be applied from LDS.  Device scalars:
+//   scal[0] rz   scal[1] rz_old   scal[2] bb   scal[3] rr
+//   scal[4] done scal[5] iterations   scal[6] breakdown   scal[7] tol^2 bb
+// Reductions are per-block partials summed by every block in a fixed order,
+// so results are bitwise reproducible.
+// ---------------------------------------------------------------------------
+constexpr int CG_THREADS = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = CG_THREADS / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double sum_partials(const double* part, int nblocks, double* red) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += CG_THREADS) v += part[k];
+    return block_sum(v, red);
+}
+
+__device__ __forceinline__ void bsr_row(const int* col, const double* A, const double* x, int K, int i, int n,
+                                        double& out) {
+    double v = 0.0;
+    for (int s = 0; s < 5; ++s) {
+        const int Kc = col[K * 5 + s];
+        if (Kc < 0) continue;
+        const double* row = A + (((long)K * 5 + s) * n + i) * n;
+        const double* xv = x + (long)Kc * n;
+        for (int j = 0; j < n; ++j) v += row[j] * xv[j];
+    }
+    out = v;
+}
+
+// r = b - A x
+__global__ __launch_bounds__(CG_THREADS) void cg_init1(CgState c) {
+    const int epb = CG_THREADS / c.n;
+    const int K = blockIdx.x * epb + threadIdx.x / c.n;
+    const int i = threadIdx.x % c.n;
+    if (threadIdx.x >= epb * c.n || K >= c.ne) return;
+    double ax;
+    bsr_row(c.col, c.A, c.x, K, i, c.n, ax);
+    const long t = (long)K * c.n + i;
+    c.r[t] = c.b[t] - ax;
+}
+
+// z = Dinv r, p = z; partials of r.z, r.r, b.b
+__global__ __launch_bounds__(CG_THREADS) void cg_init2(CgState c) {
+    __shared__ double red[CG_THREADS];
+    const int n = c.n, epb = CG_THREADS / n;
+    const int K = blockIdx.x * epb + threadIdx.x / n;
+    const int i = threadIdx.x % n;
+    const bool act = threadIdx.x < epb * n && K < c.ne;
+    double rz = 0, rr = 0, bb = 0;
+    if (act) {
+        const long t = (long)K * n + i;
+        const double* D = c.Dinv + ((long)K * n + i) * n;
+        double z = 0;
+        for (int j = 0; j < n; ++j) z += D[j] * c.r[(long)K * n + j];
+        c.z[t] = z;
+        c.p[t] = z;
+        rz = c.r[t] * z;
+        rr = c.r[t] * c.r[t];
+        bb = c.b[t] * c.b[t];
+    }
+    rz = block_sum(rz, red);
+    rr = block_sum(rr, red);
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        c.part[blockIdx.x] = rz;
+        c.part[c.nblocks + blockIdx.x] = rr;
+        c.part[2 * c.nblocks + blockIdx.x] = bb;
+    }
+}
+
+__global__ __launch_bounds__(CG_THREADS) void cg_init3(CgState c, double tol) {
+    __shared__ double red[CG_THREADS];
+    const double rz = sum_partials(c.part, c.nblocks, red);
+    const double rr = sum_partials(c.part + c.nblocks, c.nblocks, red);
+    const double bb = sum_partials(c.part + 2 * c.nblocks, c.nblocks, red);
+    if (threadIdx.x == 0) {
+        c.scal[0] = rz;
+        c.scal[1] = rz;
+        c.scal[2] = bb;
+        c.scal[3] = rr;
+        c.scal[7] = tol * tol * bb;
+        c.scal[4] = (rr <= c.scal[7]) ? 1.0 : 0.0;
+        c.scal[5] = 0.0;
+        c.scal[6] = 0.0;
+    }
+}
+
+// q = A p; partial p.q
+__global__ __launch_bounds__(CG_THREADS) void cg_k1(CgState c) {
+    __shared__ double red[CG_THREADS];
+    if (c.scal[4] != 0.0) return;
+    const int n = c.n, epb = CG_THREADS / n;
+    const int K = blockIdx.x * epb + threadIdx.x / n;
+    const int i = threadIdx.x % n;
+    double pq = 0;
+    if (threadIdx.x < epb * n && K < c.ne) {
+        double v;
+        bsr_row(c.col, c.A, c.p, K, i, n, v);
+        const long t = (long)K * n + i;
+        c.q[t] = v;
+        pq = c.p[t] * v;
+    }
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) c.part[blockIdx.x] = pq;
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q; z = Dinv r; partials r.z, r.r
+__global__ __launch_bounds__(CG_THREADS) void cg_k2(CgState c) {
+    __shared__ double red[CG_THREADS];
+    __shared__ double rl[CG_THREADS];
+    if (c.scal[4] != 0.0) return;
+    const double pq = sum_partials(c.part, c.nblocks, red);
+    const double rz = c.scal[0];
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            c.scal[6] = 1.0;
+            c.scal[4] = 1.0;
+        }
+        return;
+    }
+    const double alpha = rz / pq;
+    const int n = c.n, epb = CG_THREADS / n;
+    const int K = blockIdx.x * epb + threadIdx.x / n;
+    const int i = threadIdx.x % n;
+    const bool act = threadIdx.x < epb * n && K < c.ne;
+    double rnew = 0;
+    if (act) {
+        const long t = (long)K * n + i;
+        c.x[t] += alpha * c.p[t];
+        rnew = c.r[t] - alpha * c.q[t];
+        c.r[t] = rnew;
+    }
+    rl[threadIdx.x] = rnew;
+    __syncthreads();
+    double rz2 = 0, rr = 0;
+    if (act) {
+        const int e0 = (threadIdx.x / n) * n;
+        const double* D = c.Dinv + ((long)K * n + i) * n;
+        double z = 0;
+        for (int j = 0; j < n; ++j) z += D[j] * rl[e0 + j];
+        c.z[(long)K * n + i] = z;
+        rz2 = rnew * z;
+        rr = rnew * rnew;
+    }
+    rz2 = block_sum(rz2, red);
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        c.part[c.nblocks + blockIdx.x] = rz2;
+        c.part[2 * c.nblocks + blockIdx.x] = rr;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.scal[1] = rz;
+}
+
+// beta = rz_new / rz_old; p = z + beta p; convergence test
+__global__ __launch_bounds__(CG_THREADS) void cg_k3(CgState c) {
+    __shared__ double red[CG_THREADS];
+    if (c.scal[4] != 0.0) return;
+    const double rzn = sum_partials(c.part + c.nblocks, c.nblocks, red);
+    const double rr = sum_partials(c.part + 2 * c.nblocks, c.nblocks, red);
+    const bool conv = rr <= c.scal[7];
+    const double beta = rzn / c.scal[1];
+    const int n = c.n, epb = CG_THREADS / n;
+    const int K = blockIdx.x * epb + threadIdx.x / n;
+    const int i = threadIdx.x % n;
+    if (!conv && threadIdx.x < epb * n && K < c.ne) {
+        const long t = (long)K * n + i;
+        c.p[t] = c.z[t] + beta * c.p[t];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c.scal[0] = rzn;
+        c.scal[3] = rr;
+        c.scal[5] += 1.0;
+        if (conv) c.scal[4] = 1.0;
+    }
+}
+
+hipError_t cg_start(const CgState& c, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(cg_init1, dim3(c.nblocks), dim3(CG_THREADS), 0, s, c);
+    hipLaunchKernelGGL(cg_init2, dim3(c.nblocks), dim3(CG_THREADS), 0, s, c);
+    hipLaunchKernelGGL(cg_init3, dim3(1), dim3(CG_THREADS), 0, s, c, tol);
+    return hipGetLastError();
+}
+
+hipError_t cg_iterations(const CgState& c, int iters, double tol, hipStream_t s) {
+    (void)tol;
+    for (int t = 0; t < iters; ++t) {
+        hipLaunchKernelGGL(cg_k1, dim3(c.nblocks), dim3(CG_THREADS), 0, s, c);
+        hipLaunchKernelGGL(cg_k2, dim3(c.nblocks), dim3(CG_THREADS), 0, s, c);
+        hipLaunchKernelGGL(cg_k3, dim3(c.nblocks), dim3(CG_THREADS), 0, s, c);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Outer residual: out[0] = max |xn - xo|, out[1] = max |xn|.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void resid_part(long L, const double* __restrict__ xn,
+                                                  const double* __restrict__ xo, double* __restrict__ part,
+                                                  int nblocks) {
+    __shared__ double r0[256], r1[256];
+    double a = 0, b = 0;
+    for (long t = (long)blockIdx.x * 256 + threadIdx.x; t < L; t += (long)nblocks * 256) {
+        const double v = xn[t];
+        const double dv = fabs(v - xo[t]);
+        a = dv > a || dv != dv ? dv : a;
+        b = fabs(v) > b || v != v ? fabs(v) : b;
+    }
+    r0[threadIdx.x] = a;
+    r1[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double x0 = r0[threadIdx.x + s], x1 = r1[threadIdx.x + s];
+            r0[threadIdx.x] = (x0 > r0[threadIdx.x] || x0 != x0) ? x0 : r0[threadIdx.x];
+            r1[threadIdx.x] = (x1 > r1[threadIdx.x] || x1 != x1) ? x1 : r1[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = r0[0];
+        part[nblocks + blockIdx.x] = r1[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void resid_final(const double* __restrict__ part, int nblocks,
+                                                   double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double a = 0, b = 0;
+    for (int k = 0; k < nblocks; ++k) {
+        const double x0 = part[k], x1 = part[nblocks + k];
+        a = (x0 > a || x0 != x0) ? x0 : a;
+        b = (x1 > b || x1 != x1) ? x1 : b;
+    }
+    out[0] = a;
+    out[1] = b;
+}
+
+hipError_t launch_residual(long L, const double* xn, const double* xo, double* part, int nblocks, double* out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(resid_part, dim3(nblocks), dim3(256), 0, s, L, xn, xo, part, nblocks);
+    hipLaunchKernelGGL(resid_final, dim3(1), dim3(256), 0, s, part, nblocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace smm

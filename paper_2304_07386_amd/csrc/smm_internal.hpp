@@ -1,0 +1,109 @@
+// Internal data structures of libsmm (host side).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "smm.h"
+
+namespace smm {
+
+// ---------------------------------------------------------------------------
+// 1D rules and bases (host_setup.cpp)
+// ---------------------------------------------------------------------------
+void gauss_legendre01(int q, std::vector<double>& x, std::vector<double>& w);
+void gauss_lobatto01(int p, std::vector<double>& x);
+// L[a*npts + k] = l_a(x_k), dL likewise for the derivative
+void lagrange_tables(const std::vector<double>& nodes, const std::vector<double>& pts,
+                     std::vector<double>& L, std::vector<double>& dL);
+// 2D level-symmetric half-sphere set (quadrant-major), weights sum to 4 pi
+int level_symmetric(int N, std::vector<double>& omega, std::vector<double>& w);
+
+// ---------------------------------------------------------------------------
+// Problem
+// ---------------------------------------------------------------------------
+struct DeviceBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct smm_ctx_impl;
+
+struct Problem {
+    smm_ctx* ctx = nullptr;
+    // sizes
+    int nx = 0, ny = 0, m = 0, p = 0, nb = 0, n = 0, nq = 0, ne = 0, nd = 0, nbf = 0, sn = 0;
+    int nlev_max = 0;
+    // quadrature / basis
+    std::vector<double> omega, w;          // [nd][3], [nd]
+    std::vector<double> gl;                // solution nodes (nb)
+    std::vector<double> sq, wq;            // face / 1D volume Gauss rule (nq)
+    std::vector<double> Lf, dLf;           // [nb][nq] 1D basis at Gauss points
+    double eb0x = 0, eb0y = 0;             // E_b0 for x- and y-normal boundary faces
+
+    // geometry (general path data, FP64)
+    std::vector<double> ctrl;              // copy of control points
+    std::vector<double> xnode;             // [ne][n][2]
+    std::vector<double> area;              // [ne]
+    std::vector<double> Mk, Gxk, Gyk;      // [ne][n][n]
+    std::vector<double> nds;               // [ne][4][nq][2] weight * n ds
+    std::vector<double> dsw;               // [ne][4][nq]   weight * ds
+    std::vector<double> nhat;              // [ne][4][nq][2]
+    std::vector<double> xf;                // [ne][4][nq][2]
+    std::vector<double> vol_wJ;            // [ne][nq*nq]
+    std::vector<double> vol_grad;          // [ne][nq*nq][n][2]
+    std::vector<double> face_grad;         // [ne][4][nq][n][2]
+    std::vector<double> vol_U;             // [nq*nq][n]
+    std::vector<int> nbr;                  // [ne][4]
+    std::vector<int> bface_of;             // [ne][4] -> boundary face id or -1
+    std::vector<int> bface_K, bface_f;     // [nbf]
+    std::vector<double> chord;             // [ne][4][2] integral of n ds (from end points)
+
+    // cartesian fast path
+    bool cartesian = false;
+    double hx = 0, hy = 0;
+    int nmat = 0;
+    std::vector<double> mat_sigma;         // [nmat]
+    std::vector<uint8_t> mat_of;           // [ne]
+    std::vector<double> Pm, Px, Py;        // [nmat][nd][n][n], [nmat][nd][n][nb] x2
+
+    // general-path sweep graph
+    std::vector<int> lev_ptr;              // [nd][nlev_max+1]
+    std::vector<int> lev_elem;             // [nd][ne]
+    std::vector<uint8_t> upflag;           // [nd][ne] bit f: neighbour across f is upstream
+
+    // materials, sources, inflow
+    bool have_mat = false;
+    std::vector<double> sigma_t, sigma_s;  // [ne]
+    int src_layout = SMM_SRC_ISO;
+    std::vector<double> q;                 // [ne][n] or [nd][ne][n]
+    int inflow_layout = SMM_INFLOW_VACUUM;
+    std::vector<double> psibar;            // [nbf][nq][nd] (full layout)
+
+    // moment system (FP64)
+    std::vector<int> bsr_col;              // [ne][5] (slot 0 = self, 1+f = neighbour f; -1 none)
+    std::vector<double> bsr_val;           // [ne][5][n][n]
+    std::vector<double> bjac_inv;          // [ne][n][n]
+    std::vector<double> corr_val;          // [ne][5][n][3n] correction-tensor operator
+    std::vector<double> beta_op;           // [nbf][n][nq]: dsw_q u_i(q)
+    std::vector<double> b_fixed;           // [ne*n]
+    bool lhs_ready = false;
+    bool rhs_fixed_ready = false;
+
+    // device state (api.hip)
+    void* dev = nullptr;
+};
+
+int setup_geometry(Problem& P, std::string& err);
+void setup_cartesian_operators(Problem& P);
+void setup_sweep_graph(Problem& P);
+void assemble_ip(Problem& P);
+void assemble_rhs_fixed(Problem& P);
+void assemble_correction_operator(Problem& P);
+void cartesian_boundary_traces(const Problem& P, std::vector<double>& bx, std::vector<double>& by);
+int lu_invert(int n, double* A);  // in-place inverse, partial pivoting; returns 0 on success
+
+}  // namespace smm

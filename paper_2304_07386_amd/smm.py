@@ -1,0 +1,296 @@
+"""Thin Python binding of libsmm (include/smm.h).
+
+Argument marshalling only: every computation runs inside libsmm.so (host
+setup in C++, the solve path in HIP kernels).  Functions keep the C names;
+host arrays are numpy float64, device arrays are torch CUDA tensors (only
+their data pointers are passed).  A non-zero status raises SmmError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmm.so")
+
+SMM_OK, SMM_EINVAL, SMM_ENOMEM, SMM_EHIP, SMM_ENOCONV, SMM_ENAN, SMM_EBREAKDOWN, SMM_EUNSUPPORTED, SMM_ESTATE = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+SMM_FP64, SMM_FP32_SWEEP = 0, 1
+SMM_SRC_ISO, SMM_SRC_ANISO = 0, 1
+SMM_INFLOW_VACUUM, SMM_INFLOW_ISO_FACE, SMM_INFLOW_FULL = 0, 1, 2
+SMM_START_ZERO, SMM_START_DIFFUSION, SMM_START_GIVEN = 0, 1, 2
+
+EXPORTED = [
+    "smm_strerror", "smm_ctx_create", "smm_ctx_destroy", "smm_last_error", "smm_problem_create",
+    "smm_problem_destroy", "smm_get_dims", "smm_get_quadrature", "smm_get_nodes", "smm_get_bface_points",
+    "smm_set_materials", "smm_set_source", "smm_set_inflow", "smm_default_opts", "smm_solve",
+    "smm_get_outputs", "smm_apply_sweep", "smm_apply_moments", "smm_apply_G", "smm_debug_ip_dense",
+    "smm_set_sweep_path", "smm_time_sweep",
+]
+
+
+class SmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libsmm error {code}: {msg}")
+        self.code = code
+
+
+class smm_mesh_desc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("m", C.c_int), ("ctrl", C.POINTER(C.c_double))]
+
+
+class smm_problem_dims(C.Structure):
+    _fields_ = [("n_elem", C.c_int), ("n_node", C.c_int), ("n_dir", C.c_int), ("n_bface", C.c_int),
+                ("nq", C.c_int), ("cartesian", C.c_int), ("n_material", C.c_int), ("n_levels", C.c_int)]
+
+
+class smm_solve_opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("outer_tol", C.c_double), ("max_outer", C.c_int),
+                ("inner_tol", C.c_double), ("max_inner", C.c_int), ("start", C.c_int),
+                ("delta_sweeps", C.c_int), ("use_graph", C.c_int)]
+
+
+class smm_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("residual", C.c_double), ("residual_abs", C.c_double),
+                ("cg_iterations_total", C.c_int), ("cg_iterations_max", C.c_int),
+                ("t_total_ms", C.c_double), ("t_setup_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsmm.so (built in-tree by paper_2304_07386_amd.build).  Raises
+    if it is missing: there is no fallback implementation."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libsmm.so not built at {path}; run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    vp, ip, dp = C.c_void_p, C.c_int, C.POINTER(C.c_double)
+    sig = {
+        "smm_strerror": (C.c_char_p, [ip]),
+        "smm_ctx_create": (ip, [ip, vp, C.POINTER(vp)]),
+        "smm_ctx_destroy": (ip, [vp]),
+        "smm_last_error": (C.c_char_p, [vp]),
+        "smm_problem_create": (ip, [vp, C.POINTER(smm_mesh_desc), ip, ip, C.POINTER(vp)]),
+        "smm_problem_destroy": (ip, [vp]),
+        "smm_get_dims": (ip, [vp, C.POINTER(smm_problem_dims)]),
+        "smm_get_quadrature": (ip, [vp, vp, vp]),
+        "smm_get_nodes": (ip, [vp, vp]),
+        "smm_get_bface_points": (ip, [vp, vp]),
+        "smm_set_materials": (ip, [vp, vp, vp]),
+        "smm_set_source": (ip, [vp, vp, ip]),
+        "smm_set_inflow": (ip, [vp, vp, ip]),
+        "smm_default_opts": (None, [C.POINTER(smm_solve_opts)]),
+        "smm_solve": (ip, [vp, C.POINTER(smm_solve_opts), vp, C.POINTER(smm_solve_info)]),
+        "smm_get_outputs": (ip, [vp, vp, vp, vp, vp, vp, ip]),
+        "smm_apply_sweep": (ip, [vp, ip, vp, ip, vp, vp, ip]),
+        "smm_apply_moments": (ip, [vp, ip, vp, vp]),
+        "smm_apply_G": (ip, [vp, ip, vp, vp, C.c_double, ip]),
+        "smm_debug_ip_dense": (ip, [vp, vp, vp]),
+        "smm_set_sweep_path": (ip, [vp, ip]),
+        "smm_time_sweep": (ip, [vp, ip, ip, dp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    """Data pointer of a numpy array (host) or torch tensor (device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(a.data_ptr())
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Context:
+    def __init__(self, handle):
+        self.handle = handle
+
+
+def _check(rc, ctx=None):
+    if rc != SMM_OK:
+        lib = load_library()
+        msg = lib.smm_strerror(rc).decode()
+        if ctx is not None:
+            detail = lib.smm_last_error(ctx.handle)
+            if detail:
+                msg += f" ({detail.decode()})"
+        raise SmmError(rc, msg)
+
+
+def smm_ctx_create(device: int = 0, stream=None) -> Context:
+    """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+    lib = load_library()
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    h = C.c_void_p()
+    _check(lib.smm_ctx_create(device, C.c_void_p(stream) if stream else None, C.byref(h)))
+    return Context(h)
+
+
+def smm_ctx_destroy(ctx: Context):
+    load_library().smm_ctx_destroy(ctx.handle)
+
+
+class Problem:
+    """Handle of one smm_problem plus the context it belongs to."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+        d = smm_problem_dims()
+        _check(load_library().smm_get_dims(handle, C.byref(d)), ctx)
+        self.dims = d
+
+    @property
+    def n_elem(self):
+        return self.dims.n_elem
+
+    @property
+    def n_node(self):
+        return self.dims.n_node
+
+    @property
+    def n_dir(self):
+        return self.dims.n_dir
+
+
+def smm_problem_create(ctx: Context, nx: int, ny: int, m: int, ctrl: np.ndarray, p: int, sn: int) -> Problem:
+    lib = load_library()
+    ctrl = _f64(ctrl)
+    assert ctrl.size == (ny * m + 1) * (nx * m + 1) * 2
+    desc = smm_mesh_desc(nx, ny, m, ctrl.ctypes.data_as(C.POINTER(C.c_double)))
+    h = C.c_void_p()
+    _check(lib.smm_problem_create(ctx.handle, C.byref(desc), p, sn, C.byref(h)), ctx)
+    return Problem(ctx, h)
+
+
+def smm_problem_destroy(prob: Problem):
+    load_library().smm_problem_destroy(prob.handle)
+
+
+def smm_get_dims(prob: Problem) -> dict:
+    d = smm_problem_dims()
+    _check(load_library().smm_get_dims(prob.handle, C.byref(d)), prob.ctx)
+    prob.dims = d
+    return {k: getattr(d, k) for k, _ in d._fields_}
+
+
+def smm_get_quadrature(prob: Problem):
+    om = np.zeros((prob.n_dir, 3))
+    w = np.zeros(prob.n_dir)
+    _check(load_library().smm_get_quadrature(prob.handle, _ptr(om), _ptr(w)), prob.ctx)
+    return om, w
+
+
+def smm_get_nodes(prob: Problem):
+    xy = np.zeros((prob.n_elem, prob.n_node, 2))
+    _check(load_library().smm_get_nodes(prob.handle, _ptr(xy)), prob.ctx)
+    return xy
+
+
+def smm_get_bface_points(prob: Problem):
+    xy = np.zeros((prob.dims.n_bface, prob.dims.nq, 2))
+    _check(load_library().smm_get_bface_points(prob.handle, _ptr(xy)), prob.ctx)
+    return xy
+
+
+def smm_set_materials(prob: Problem, sigma_t, sigma_s):
+    st, ss = _f64(sigma_t), _f64(sigma_s)
+    _check(load_library().smm_set_materials(prob.handle, _ptr(st), _ptr(ss)), prob.ctx)
+    smm_get_dims(prob)
+
+
+def smm_set_source(prob: Problem, q, layout: int = SMM_SRC_ISO):
+    q = _f64(q)
+    _check(load_library().smm_set_source(prob.handle, _ptr(q), layout), prob.ctx)
+
+
+def smm_set_inflow(prob: Problem, psibar=None, layout: int = SMM_INFLOW_VACUUM):
+    pb = _f64(psibar) if psibar is not None else None
+    _check(load_library().smm_set_inflow(prob.handle, _ptr(pb), layout), prob.ctx)
+
+
+def smm_default_opts(**kw) -> smm_solve_opts:
+    o = smm_solve_opts()
+    load_library().smm_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def smm_solve(prob: Problem, opts: smm_solve_opts | None = None, varphi0=None, raise_on_noconv=True):
+    """Returns (status, info dict).  SMM_ENOCONV raises unless
+    raise_on_noconv is False (outputs stay valid either way)."""
+    info = smm_solve_info()
+    v0 = _f64(varphi0) if varphi0 is not None else None
+    rc = load_library().smm_solve(prob.handle, C.byref(opts) if opts is not None else None, _ptr(v0),
+                                  C.byref(info))
+    if rc == SMM_ENOCONV and not raise_on_noconv:
+        return rc, info.as_dict()
+    _check(rc, prob.ctx)
+    return rc, info.as_dict()
+
+
+def smm_get_outputs(prob: Problem, varphi=None, phi=None, J=None, T=None, beta=None, on_device=False):
+    _check(load_library().smm_get_outputs(prob.handle, _ptr(varphi), _ptr(phi), _ptr(J), _ptr(T), _ptr(beta),
+                                          1 if on_device else 0), prob.ctx)
+
+
+def smm_get_outputs_host(prob: Problem) -> dict:
+    """Convenience: all outputs as fresh numpy arrays."""
+    L = prob.n_elem * prob.n_node
+    out = {"varphi": np.zeros(L), "phi": np.zeros(L), "J": np.zeros((2, L)), "T": np.zeros((3, L)),
+           "beta": np.zeros((max(prob.dims.n_bface, 1), prob.dims.nq))}
+    smm_get_outputs(prob, out["varphi"], out["phi"], out["J"], out["T"], out["beta"], on_device=False)
+    return out
+
+
+def smm_apply_sweep(prob: Problem, precision: int, S, s_layout: int, psi_lag, psi_out, with_inflow: bool = True):
+    _check(load_library().smm_apply_sweep(prob.handle, precision, _ptr(S), s_layout, _ptr(psi_lag), _ptr(psi_out),
+                                          1 if with_inflow else 0), prob.ctx)
+
+
+def smm_apply_moments(prob: Problem, precision: int, psi, mom):
+    _check(load_library().smm_apply_moments(prob.handle, precision, _ptr(psi), _ptr(mom)), prob.ctx)
+
+
+def smm_apply_G(prob: Problem, precision: int, varphi_in, varphi_out, inner_tol: float = 1e-14,
+                max_inner: int = 100000):
+    _check(load_library().smm_apply_G(prob.handle, precision, _ptr(varphi_in), _ptr(varphi_out), inner_tol,
+                                      max_inner), prob.ctx)
+
+
+def smm_debug_ip_dense(prob: Problem):
+    N = prob.n_elem * prob.n_node
+    A = np.zeros((N, N))
+    b = np.zeros(N)
+    _check(load_library().smm_debug_ip_dense(prob.handle, _ptr(A), _ptr(b)), prob.ctx)
+    return A, b
+
+
+def smm_set_sweep_path(prob: Problem, force_general: bool):
+    _check(load_library().smm_set_sweep_path(prob.handle, 1 if force_general else 0), prob.ctx)
+
+
+def smm_time_sweep(prob: Problem, precision: int, reps: int) -> float:
+    ms = C.c_double()
+    _check(load_library().smm_time_sweep(prob.handle, precision, reps, C.byref(ms)), prob.ctx)
+    return ms.value

@@ -1,0 +1,116 @@
+"""C-ABI library checks that need no GPU.
+
+* libsmm.so loads and exports every function declared in include/smm.h.
+* Host-only contexts run the one-time setup; its tables equal the oracle's
+  (IP operator and fixed right-hand side of eq. ipsmm, quadrature, node
+  coordinates) on straight, non-uniform and curved meshes.
+* Argument validation and error codes (forced from the host).
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import smm as osmm
+from workloads import config_channel, config_curved_mms, config_plain, structured_ctrl
+
+L = pytest.importorskip("paper_2304_07386_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_header_symbols():
+    lib = L.load_library()
+    hdr = open(os.path.join(ROOT, "include", "smm.h")).read()
+    names = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(smm_\w+)\s*\(", hdr, re.M))
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(L.EXPORTED) == names
+
+
+@pytest.fixture(scope="module")
+def hctx():
+    return L.smm_ctx_create(-1)
+
+
+def _compare(hctx, wl):
+    pr = osmm.make_problem(wl)
+    p = L.problem_from_workload(hctx, wl, q=pr.q, psibar=pr.psibar)
+    A1, b1 = L.smm_debug_ip_dense(p)
+    A0 = osmm.ip_matrix(pr).toarray()
+    b0 = osmm.rhs_fixed(pr)
+    om, w = L.smm_get_quadrature(p)
+    assert np.abs(A1 - A0).max() <= 1e-13 * np.abs(A0).max()
+    assert np.abs(b1 - b0).max() <= 1e-13 * max(np.abs(b0).max(), 1.0)
+    assert np.abs(om - pr.omega).max() < 1e-15 and np.abs(w - pr.w).max() < 1e-14
+    assert np.abs(L.smm_get_nodes(p) - pr.mesh.xnode).max() < 1e-14
+    xb = L.smm_get_bface_points(p)
+    for b, (K, f) in enumerate(pr.mesh.bfaces):
+        assert np.abs(xb[b] - pr.mesh.xf[K, f]).max() < 1e-14
+    L.smm_get_dims(p)
+    return p
+
+
+def test_setup_matches_oracle_plain(hctx):
+    p = _compare(hctx, config_plain())
+    assert p.dims.cartesian == 1 and p.dims.n_material == 1
+
+
+def test_setup_matches_oracle_curved(hctx):
+    for pp in (2, 3):
+        p = _compare(hctx, config_curved_mms(n=4, p=pp, sn=8))
+        assert p.dims.cartesian == 0
+
+
+def test_setup_matches_oracle_nonuniform_inflow(hctx):
+    from tests.test_oracle_smm import _patch_workload
+    wl, _, _ = _patch_workload(3)
+    p = _compare(hctx, wl)
+    assert p.dims.cartesian == 0
+
+
+def test_channel_layout_materials(hctx):
+    wl = config_channel(n=32, side=2.5)
+    p = L.problem_from_workload(hctx, wl)
+    L.smm_debug_ip_dense(p)
+    L.smm_get_dims(p)
+    assert p.dims.cartesian == 1 and p.dims.n_material == 2
+    assert set(np.unique(wl.sigma_t)) == {0.2, 200.0}
+
+
+def test_validation_errors(hctx):
+    wl = config_plain(n=2)
+    with pytest.raises(L.SmmError) as e:
+        L.smm_problem_create(hctx, 2, 2, 1, wl.ctrl, 5, 4)
+    assert e.value.code == L.SMM_EINVAL
+    with pytest.raises(L.SmmError) as e:
+        L.smm_problem_create(hctx, 2, 2, 1, wl.ctrl, 1, 5)
+    assert e.value.code == L.SMM_EINVAL
+    # inverted element -> det J <= 0
+    bad = wl.ctrl.copy()
+    bad[1, 1] = [1.5, 1.5]
+    with pytest.raises(L.SmmError) as e:
+        L.smm_problem_create(hctx, 2, 2, 1, bad, 1, 4)
+    assert e.value.code == L.SMM_EINVAL
+    # slanted boundary is reported as unsupported
+    sl = wl.ctrl.copy()
+    sl[0, 1] = [0.5, -0.1]
+    with pytest.raises(L.SmmError) as e:
+        L.smm_problem_create(hctx, 2, 2, 1, sl, 1, 4)
+    assert e.value.code == L.SMM_EUNSUPPORTED
+    p = L.smm_problem_create(hctx, 2, 2, 1, wl.ctrl, 1, 4)
+    with pytest.raises(L.SmmError) as e:
+        L.smm_set_materials(p, np.ones(4), np.full(4, 2.0))
+    assert e.value.code == L.SMM_EINVAL
+    with pytest.raises(L.SmmError) as e:
+        L.smm_debug_ip_dense(p)          # materials not set yet
+    assert e.value.code == L.SMM_ESTATE
+    L.smm_set_materials(p, np.ones(4), np.full(4, 0.5))
+    with pytest.raises(L.SmmError) as e:
+        L.smm_set_source(p, np.full((4, 4), np.nan))
+    assert e.value.code == L.SMM_EINVAL
+    # a host-only context refuses to run the solve path
+    with pytest.raises(L.SmmError) as e:
+        L.smm_solve(p)
+    assert e.value.code == L.SMM_ESTATE
