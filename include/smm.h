@@ -197,8 +197,10 @@ int smm_debug_ip_dense(const smm_problem* prob, double* A, double* b_fixed);
 
 /* Sweep kernel selection: 0 = automatic (tabulated operators on uniform
  * Cartesian meshes, otherwise per-element assembly and elimination);
- * 1 = always the per-element kernel (for cross-checking the two). */
-int smm_set_sweep_path(smm_problem* prob, int force_general);
+ * 1 = always the per-element assembly/elimination kernel; 2 = on Cartesian
+ * meshes, the element-row kernel instead of the column-per-thread one (for
+ * cross-checking the kernels against each other). */
+int smm_set_sweep_path(smm_problem* prob, int path);
 
 /* Time one sweep configuration on device (average ms over `reps` launches
  * measured with HIP events on the context stream); used by the benchmark. */

@@ -278,7 +278,8 @@ int smm_set_inflow(smm_problem* prob, const double* psibar, int layout) {
 
 int smm_set_sweep_path(smm_problem* prob, int force_general) {
     if (!prob) return SMM_EINVAL;
-    prob->D.force_general = force_general ? 1 : 0;
+    if (force_general < 0 || force_general > 2) return SMM_EINVAL;
+    prob->D.force_general = force_general;
     return SMM_OK;
 }
 
@@ -459,7 +460,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
     hipError_t e;
-    if (P.cartesian && !D.force_general) {
+    if (P.cartesian && D.force_general != 1) {
         CartSweepArgs a{};
         a.nx = P.nx; a.ny = P.ny; a.nd = P.nd; a.nb = P.nb; a.nmat = P.nmat;
         a.s_aniso = s_aniso;
@@ -472,6 +473,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
         a.bx = with_inflow && P.inflow_layout != SMM_INFLOW_VACUUM ? (fp64 ? D.bx64 : D.bx32) : nullptr;
         a.by = with_inflow && P.inflow_layout != SMM_INFLOW_VACUUM ? (fp64 ? D.by64 : D.by32) : nullptr;
         a.psi = psi_out;
+        a.variant = D.force_general == 2 ? 1 : 0;
         e = launch_sweep_cart(fp64, a, c->stream);
     } else {
         GenSweepArgs a{};

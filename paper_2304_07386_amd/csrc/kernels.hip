@@ -105,12 +105,281 @@ static hipError_t launch_cart_t(const CartSweepArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Column-per-thread Cartesian sweep.  Each element of an anti-diagonal is
+// handled by NB threads; thread `ca` owns the element's node column
+// {ca + NB b}, so its rows of the tabulated operators [Pm | Px | Py] stay in
+// registers for the whole sweep (one or two materials) or are read from LDS
+// (more materials).  The source of the next anti-diagonal is prefetched into
+// registers while the current one is computed and parked in a double-buffered
+// LDS array, so each level costs LDS traffic and one barrier, not a global
+// memory round trip.
+// ---------------------------------------------------------------------------
+// Barrier for LDS-only communication: waits for this wave's LDS operations
+// and synchronises the workgroup, but does not wait for outstanding global
+// stores (the sweep never reads back what it writes to global memory).  The
+// "memory" clobber keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <typename T, int NB, int MREG, int MAXT, int B>
+__global__ __launch_bounds__(MAXT) void sweep_cart2_kernel(CartSweepArgs a) {
+    constexpr int N = NB * NB;
+    constexpr int ROWW = N + 2 * NB;
+    const int d = blockIdx.x;
+    const int nx = a.nx, ny = a.ny, nd = a.nd;
+    const long ne = (long)nx * ny;
+    const int maxlen = nx < ny ? nx : ny;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* xtr = reinterpret_cast<T*>(smem);  // [2][ny][NB]
+    T* ytr = xtr + 2 * ny * NB;           // [2][nx][NB]
+    T* sch = ytr + 2 * nx * NB;           // [2][B][maxlen][N] source of two blocks of B levels
+    T* tab = sch + 2 * B * maxlen * N;    // [nmat][N][ROWW]   (MREG == 0)
+    uint8_t* msh = reinterpret_cast<uint8_t*>(tab + (MREG == 0 ? a.nmat * N * ROWW : 0));  // [ne]
+    const int slot = threadIdx.x / NB;
+    const int ca = threadIdx.x - slot * NB;
+    const double ox = a.omega[d * 3], oy = a.omega[d * 3 + 1];
+    const bool sx = ox > 0.0, sy = oy > 0.0;
+    const T* Pm = reinterpret_cast<const T*>(a.Pm);
+    const T* Px = reinterpret_cast<const T*>(a.Px);
+    const T* Py = reinterpret_cast<const T*>(a.Py);
+    const T* S = reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0);
+    T* psi = reinterpret_cast<T*>(a.psi) + (long)d * ne * N;
+    if constexpr (MREG != 1) {
+        for (long t = threadIdx.x; t < ne; t += blockDim.x) msh[t] = a.mat[t];
+    }
+
+    // operator rows of this thread's node column
+    T reg[MREG > 0 ? MREG : 1][NB][ROWW];
+    if constexpr (MREG > 0) {
+#pragma unroll
+        for (int m = 0; m < MREG; ++m) {
+            const int mm = m < a.nmat ? m : 0;
+            const long o = (long)mm * nd + d;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int r = ca + NB * b;
+#pragma unroll
+                for (int c = 0; c < N; ++c) reg[m][b][c] = Pm[(o * N + r) * N + c];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    reg[m][b][N + c] = Px[(o * N + r) * NB + c];
+                    reg[m][b][N + NB + c] = Py[(o * N + r) * NB + c];
+                }
+            }
+        }
+    } else {
+        for (int t = threadIdx.x; t < a.nmat * N; t += blockDim.x) {
+            const int m = t / N, r = t - m * N;
+            const long o = (long)m * nd + d;
+            T* row = tab + (long)t * ROWW;
+            for (int c = 0; c < N; ++c) row[c] = Pm[(o * N + r) * N + c];
+            for (int c = 0; c < NB; ++c) {
+                row[N + c] = Px[(o * N + r) * NB + c];
+                row[N + NB + c] = Py[(o * N + r) * NB + c];
+            }
+        }
+    }
+    const T* bx = reinterpret_cast<const T*>(a.bx);
+    const T* by = reinterpret_cast<const T*>(a.by);
+    for (int t = threadIdx.x; t < ny * NB; t += blockDim.x) {
+        const T v = bx ? bx[(long)d * ny * NB + t] : T(0);
+        xtr[t] = v;
+        xtr[ny * NB + t] = v;
+    }
+    for (int t = threadIdx.x; t < nx * NB; t += blockDim.x) {
+        const T v = by ? by[(long)d * nx * NB + t] : T(0);
+        ytr[t] = v;
+        ytr[nx * NB + t] = v;
+    }
+    const int aout = sx ? NB - 1 : 0;
+    const int bout = sy ? NB - 1 : 0;
+    const int nlev = nx + ny - 1;
+    // element of this slot at level l: returns K or -1
+    auto elem = [&](int l, int& i, int& j) -> long {
+        if (l >= nlev) return -1;
+        const int i0 = l - (ny - 1) > 0 ? l - (ny - 1) : 0;
+        const int i1 = l < nx - 1 ? l : nx - 1;
+        if (slot > i1 - i0) return -1;
+        const int ip = i0 + slot, jp = l - ip;
+        i = sx ? ip : nx - 1 - ip;
+        j = sy ? jp : ny - 1 - jp;
+        return (long)j * nx + i;
+    };
+    // Source of a block of B levels: loaded into registers at the start of
+    // the previous block and parked in LDS at its end.  Loads are issued
+    // unconditionally (element 0 stands in for an empty slot), so load and
+    // wait sit in one straight-line block with a known number of
+    // intervening memory operations.
+    T pre[B][NB];
+    auto fetch_block = [&](int l0) {
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            int i, j;
+            long K = elem(l0 + u, i, j);
+            K = K < 0 ? 0 : K;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) pre[u][b] = S[K * N + ca + NB * b];
+        }
+    };
+    auto park_block = [&](int buf) {
+        if (slot < maxlen) {
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    sch[((buf * B + u) * maxlen + slot) * N + ca + NB * b] = pre[u][b];
+        }
+    };
+    fetch_block(0);
+    park_block(0);
+    lds_barrier();
+    for (int l0 = 0, blk = 0; l0 < nlev; l0 += B, ++blk) {
+        const int buf = blk & 1;
+        fetch_block(l0 + B);
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int l = l0 + u;
+            if (l >= nlev) break;
+            const int cur = l & 1, nxt = cur ^ 1;
+            int ci, cj;
+            const long K = elem(l, ci, cj);
+            if (K >= 0) {
+                const int cmat = MREG == 1 ? 0 : (int)msh[K];
+                T sv[N], tx[NB], ty[NB];
+                const T* sp = sch + ((buf * B + u) * maxlen + slot) * N;
+#pragma unroll
+                for (int c = 0; c < N; ++c) sv[c] = sp[c];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    tx[c] = xtr[(cur * ny + cj) * NB + c];
+                    ty[c] = ytr[(cur * nx + ci) * NB + c];
+                }
+                T acc[NB];
+                auto apply = [&](const T (&rw)[NB][ROWW]) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        T v = T(0);
+#pragma unroll
+                        for (int c = 0; c < N; ++c) v += rw[b][c] * sv[c];
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) v += rw[b][N + c] * tx[c] + rw[b][N + NB + c] * ty[c];
+                        acc[b] = v;
+                    }
+                };
+                if constexpr (MREG == 1) {
+                    apply(reg[0]);
+                } else if constexpr (MREG == 2) {
+                    // materials are spatially coherent: take a wave-uniform branch
+                    // whenever the wave's elements share one material
+                    // The empty asm statements that consume the results end each
+                    // branch differently, so the branches are not merged into
+                    // per-operand selects.
+                    const unsigned long long m1 = __ballot(cmat != 0);
+                    const unsigned long long act = __ballot(1);
+                    if (m1 == 0ull) {
+                        apply(reg[0]);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) asm volatile("; material 0" : "+v"(acc[b]));
+                    } else if (m1 == act) {
+                        apply(reg[1]);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) asm volatile("; material 1" : "+v"(acc[b]));
+                    } else {
+                        T acc0[NB];
+                        apply(reg[0]);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) acc0[b] = acc[b];
+                        apply(reg[1]);
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) acc[b] = cmat == 0 ? acc0[b] : acc[b];
+                    }
+                } else {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const T* row = tab + ((long)cmat * N + ca + NB * b) * ROWW;
+                        T v = T(0);
+#pragma unroll
+                        for (int c = 0; c < N; ++c) v += row[c] * sv[c];
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) v += row[N + c] * tx[c] + row[N + NB + c] * ty[c];
+                        acc[b] = v;
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < NB; ++b) psi[K * N + ca + NB * b] = acc[b];
+                if (ca == aout) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) xtr[(nxt * ny + cj) * NB + b] = acc[b];
+                }
+                ytr[(nxt * nx + ci) * NB + ca] = acc[bout];
+            }
+            lds_barrier();
+        }
+        park_block(buf ^ 1);
+        lds_barrier();
+    }
+}
+
+constexpr int CART_BLOCK = 6;  // levels whose source is fetched one block ahead
+
+template <typename T, int NB, int MREG, int MAXT>
+static hipError_t launch_cart2_t(const CartSweepArgs& a, hipStream_t s, int threads, size_t lds) {
+    constexpr int B = CART_BLOCK;
+    auto kfn = sweep_cart2_kernel<T, NB, MREG, MAXT, B>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kfn, dim3(a.nd), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+// Returns hipErrorNotSupported when the column-per-thread kernel does not
+// apply (anti-diagonal longer than the workgroup or LDS too small).
+template <typename T, int NB>
+static hipError_t try_cart2(const CartSweepArgs& a, hipStream_t s) {
+    constexpr int N = NB * NB;
+    const int maxlen = a.nx < a.ny ? a.nx : a.ny;
+    int threads = ((maxlen * NB + 63) / 64) * 64;
+    if (threads > 1024) return hipErrorNotSupported;
+    // register-resident operator rows only where they fit without spilling
+    constexpr bool f64 = sizeof(T) == 8;
+    int mreg = 0;
+    if (a.nmat == 1 && NB <= (f64 ? 3 : 4)) mreg = 1;
+    else if (a.nmat == 2 && NB <= (f64 ? 2 : 3)) mreg = 2;
+    size_t lds = sizeof(T) * (2 * (size_t)(a.nx + a.ny) * NB + 2 * (size_t)CART_BLOCK * maxlen * N);
+    if (mreg == 0) lds += sizeof(T) * (size_t)a.nmat * N * (N + 2 * NB);
+    if (mreg != 1) lds += (size_t)a.nx * a.ny;
+    if (lds > 160 * 1024) return hipErrorNotSupported;
+    if (threads <= 512) {
+        if (mreg == 1) return launch_cart2_t<T, NB, 1, 512>(a, s, threads, lds);
+        if constexpr (NB <= 3) {
+            if (mreg == 2) return launch_cart2_t<T, NB, 2, 512>(a, s, threads, lds);
+        }
+        return launch_cart2_t<T, NB, 0, 512>(a, s, threads, lds);
+    }
+    if (f64 && NB >= 4) return hipErrorNotSupported;
+    return launch_cart2_t<T, NB, 0, 1024>(a, s, threads, lds);
+}
+
+template <typename T, int NB>
+static hipError_t launch_cart_any(const CartSweepArgs& a, hipStream_t s) {
+    if (a.variant != 1) {
+        hipError_t e = try_cart2<T, NB>(a, s);
+        if (e != hipErrorNotSupported) return e;
+    }
+    return launch_cart_t<T, NB>(a, s);
+}
+
 hipError_t launch_sweep_cart(bool fp64, const CartSweepArgs& a, hipStream_t s) {
     switch (a.nb) {
-        case 2: return fp64 ? launch_cart_t<double, 2>(a, s) : launch_cart_t<float, 2>(a, s);
-        case 3: return fp64 ? launch_cart_t<double, 3>(a, s) : launch_cart_t<float, 3>(a, s);
-        case 4: return fp64 ? launch_cart_t<double, 4>(a, s) : launch_cart_t<float, 4>(a, s);
-        case 5: return fp64 ? launch_cart_t<double, 5>(a, s) : launch_cart_t<float, 5>(a, s);
+        case 2: return fp64 ? launch_cart_any<double, 2>(a, s) : launch_cart_any<float, 2>(a, s);
+        case 3: return fp64 ? launch_cart_any<double, 3>(a, s) : launch_cart_any<float, 3>(a, s);
+        case 4: return fp64 ? launch_cart_any<double, 4>(a, s) : launch_cart_any<float, 4>(a, s);
+        case 5: return fp64 ? launch_cart_any<double, 5>(a, s) : launch_cart_any<float, 5>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -330,8 +599,88 @@ __global__ __launch_bounds__(256) void moments_f64_kernel(const double* __restri
     }
 }
 
+// Wide variant (L divisible by 4): one wavefront covers 64 columns; lane
+// (j, k) loads psi[d + k][col0 + 4 j .. 4 j + 3] with one 16-byte (FP32) or
+// two 16-byte (FP64) loads and feeds component t to MFMA tile t, so tile t
+// holds columns col0 + 4 j + t and each lane stores 4 adjacent columns.
+__global__ __launch_bounds__(256) void moments_f32_wide_kernel(const float* __restrict__ psi, int nd, long L,
+                                                               const float* __restrict__ W, int ldw,
+                                                               double* __restrict__ mom) {
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long col0 = wave * 64;
+    if (col0 >= L) return;
+    const int j = lane & 15, kk = lane >> 4;
+    const long c4 = col0 + 4 * j;
+    const bool colok = c4 < L;  // L % 4 == 0, so c4 < L implies c4 + 3 < L
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+    for (int k = 0; k < nd; k += 4) {
+        const int dk = k + kk;
+        const float av = dk < nd ? W[j * ldw + dk] : 0.f;
+        v4f bv = {0.f, 0.f, 0.f, 0.f};
+        if (dk < nd && colok) bv = *reinterpret_cast<const v4f*>(psi + (long)dk * L + c4);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[1], acc1, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[2], acc2, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[3], acc3, 0, 0, 0);
+    }
+    if (kk < 2 && colok) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            v4d o = {(double)acc0[r], (double)acc1[r], (double)acc2[r], (double)acc3[r]};
+            *reinterpret_cast<v4d*>(mom + (long)(4 * kk + r) * L + c4) = o;
+        }
+    }
+}
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void moments_f64_wide_kernel(const double* __restrict__ psi, int nd, long L,
+                                                               const double* __restrict__ W, int ldw,
+                                                               double* __restrict__ mom) {
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long col0 = wave * 64;
+    if (col0 >= L) return;
+    const int j = lane & 15, kk = lane >> 4;
+    const long c4 = col0 + 4 * j;
+    const bool colok = c4 < L;
+    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
+    for (int k = 0; k < nd; k += 4) {
+        const int dk = k + kk;
+        const double av = dk < nd ? W[j * ldw + dk] : 0.0;
+        v2d b01 = {0.0, 0.0}, b23 = {0.0, 0.0};
+        if (dk < nd && colok) {
+            const v2d* src = reinterpret_cast<const v2d*>(psi + (long)dk * L + c4);
+            b01 = src[0];
+            b23 = src[1];
+        }
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b01[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b01[1], acc1, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b23[0], acc2, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b23[1], acc3, 0, 0, 0);
+    }
+    if (colok) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            v4d o = {acc0[r], acc1[r], acc2[r], acc3[r]};
+            *reinterpret_cast<v4d*>(mom + (long)(kk + 4 * r) * L + c4) = o;
+        }
+    }
+}
+
 hipError_t launch_moments(bool fp64, const void* psi, int nd, long L, const void* W, int ldw,
                           double* mom, hipStream_t s) {
+    if (L % 4 == 0) {
+        const long blocks = ((L + 63) / 64 + 3) / 4;
+        if (fp64)
+            hipLaunchKernelGGL(moments_f64_wide_kernel, dim3(blocks), dim3(256), 0, s, (const double*)psi, nd, L,
+                               (const double*)W, ldw, mom);
+        else
+            hipLaunchKernelGGL(moments_f32_wide_kernel, dim3(blocks), dim3(256), 0, s, (const float*)psi, nd, L,
+                               (const float*)W, ldw, mom);
+        return hipGetLastError();
+    }
     const long waves = (L + 15) / 16;
     const long blocks = (waves + 3) / 4;
     if (fp64)

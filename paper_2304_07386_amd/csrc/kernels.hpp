@@ -19,6 +19,7 @@ struct CartSweepArgs {
     const void* bx;              // [nd][ny][nb] boundary traces (or null)
     const void* by;              // [nd][nx][nb]
     void* psi;                   // [nd][ne][n]
+    int variant;                 // 0 automatic, 1 element-row kernel only
 };
 hipError_t launch_sweep_cart(bool fp64, const CartSweepArgs& a, hipStream_t s);
 

@@ -286,8 +286,8 @@ def smm_debug_ip_dense(prob: Problem):
     return A, b
 
 
-def smm_set_sweep_path(prob: Problem, force_general: bool):
-    _check(load_library().smm_set_sweep_path(prob.handle, 1 if force_general else 0), prob.ctx)
+def smm_set_sweep_path(prob: Problem, path: int):
+    _check(load_library().smm_set_sweep_path(prob.handle, int(path)), prob.ctx)
 
 
 def smm_time_sweep(prob: Problem, precision: int, reps: int) -> float:

@@ -44,29 +44,34 @@ def _sweep_gpu(p, prec, S, lag=None, inflow=True):
 
 
 SWEEP_CASES = [
-    # (name, workload factory, force_general)
-    ("plain8_p1_s4", lambda: config_plain(8, 1, 4), False),
-    ("plain8_p1_s4_general", lambda: config_plain(8, 1, 4), True),
-    ("ragged7x3_p4_s12", lambda: _rect(7, 3, 4, 12), False),
-    ("ragged7x3_p3_s6_general", lambda: _rect(7, 3, 3, 6), True),
-    ("single_p2_s8", lambda: _rect(1, 1, 2, 8), False),
-    ("curved4_p2_s8", lambda: config_curved_mms(4, 2, 8, amplitude=0.09), False),
-    ("curved3_p4_s4", lambda: config_curved_mms(3, 4, 4), False),
+    # (name, workload factory, sweep path: 0 auto, 1 per-element kernel, 2 element-row kernel)
+    ("plain8_p1_s4", lambda: config_plain(8, 1, 4), 0),
+    ("plain8_p1_s4_general", lambda: config_plain(8, 1, 4), 1),
+    ("plain8_p1_s4_rowkernel", lambda: config_plain(8, 1, 4), 2),
+    ("plain5_p3_s8_onemat", lambda: config_plain(5, 3, 8), 0),
+    ("twomat9x6_p2_s10", lambda: _rect(9, 6, 2, 10, nmat=2), 0),
+    ("twomat6x9_p1_s6", lambda: _rect(6, 9, 1, 6, nmat=2), 0),
+    ("ragged7x3_p4_s12", lambda: _rect(7, 3, 4, 12), 0),
+    ("ragged7x3_p4_s12_rowkernel", lambda: _rect(7, 3, 4, 12), 2),
+    ("ragged7x3_p3_s6_general", lambda: _rect(7, 3, 3, 6), 1),
+    ("single_p2_s8", lambda: _rect(1, 1, 2, 8), 0),
+    ("curved4_p2_s8", lambda: config_curved_mms(4, 2, 8, amplitude=0.09), 0),
+    ("curved3_p4_s4", lambda: config_curved_mms(3, 4, 4), 0),
 ]
 
 
-def _rect(nx, ny, p, sn, inflow=("iso", 0.4)):
+def _rect(nx, ny, p, sn, inflow=("iso", 0.4), nmat=3):
     xv = np.linspace(0.0, 1.4, nx + 1)
     yv = np.linspace(0.0, 0.6, ny + 1)
     ne = nx * ny
     rng = np.random.default_rng(nx * 100 + ny)
-    st = rng.choice([0.5, 2.0, 7.0], size=ne)
+    st = rng.choice([0.5, 2.0, 7.0][:nmat], size=ne)
     return Workload("rect", nx, ny, 1, p, sn, structured_ctrl(xv, yv, 1), st, 0.5 * st,
                     q_elem=rng.uniform(0.2, 1.0, ne), inflow=inflow)
 
 
-@pytest.mark.parametrize("name,factory,general", SWEEP_CASES, ids=[c[0] for c in SWEEP_CASES])
-def test_sweep_fp64(ctx, name, factory, general):
+@pytest.mark.parametrize("name,factory,path", SWEEP_CASES, ids=[c[0] for c in SWEEP_CASES])
+def test_sweep_fp64(ctx, name, factory, path):
     announce(f"sweep fp64 {name}")
     wl = factory()
     if name.startswith("curved"):
@@ -74,7 +79,7 @@ def test_sweep_fp64(ctx, name, factory, general):
         wl.q_fn = None
         wl.q_elem = np.ones(wl.n_elem)
     pr, p = make_pair(L, ctx, wl)
-    L.smm_set_sweep_path(p, general)
+    L.smm_set_sweep_path(p, path)
     rng = np.random.default_rng(7)
     S = rng.uniform(-1.0, 2.0, (pr.ne, pr.n))
     lag = rng.uniform(0.0, 1.0, (len(pr.w), pr.ne, pr.n)) if name.startswith("curved") else None
@@ -92,9 +97,10 @@ def test_sweep_fp64(ctx, name, factory, general):
     assert rel_l2(got32, ref) < 1e-5, rel_l2(got32, ref)
 
 
-def test_moments_and_closures(ctx):
-    announce("moments fp64/fp32 on plain8 p2 s12")
-    wl = config_plain(8, 2, 12)
+@pytest.mark.parametrize("n,p,sn", [(8, 2, 12), (3, 2, 4), (5, 1, 6)])
+def test_moments(ctx, n, p, sn):
+    announce(f"moments fp64/fp32 on plain{n} p{p} s{sn}")
+    wl = config_plain(n, p, sn)
     pr, p = make_pair(L, ctx, wl)
     rng = np.random.default_rng(11)
     psi = rng.uniform(-1, 1, (len(pr.w), pr.ne, pr.n))
