@@ -76,6 +76,7 @@ extern "C" {
 
 typedef struct smm_ctx smm_ctx;
 typedef struct smm_problem smm_problem;
+typedef struct smm_batch smm_batch;
 
 /* Mesh: structured nx * ny quadrilaterals with a continuous Q_m map whose
  * control points sit at the Gauss-Lobatto positions of each element
@@ -96,6 +97,8 @@ typedef struct {
     int cartesian;   /* 1: uniform axis-aligned rectangles (operator tables per material and direction) */
     int n_material;  /* distinct sigma_t values (cartesian path) */
     int n_levels;    /* max sweep wavefront levels over directions */
+    int n_self_types;/* typed Cartesian path: distinct element blocks (0 until built) */
+    int n_nbr_types; /* typed Cartesian path: distinct neighbour blocks */
 } smm_problem_dims;
 
 typedef struct {
@@ -108,6 +111,9 @@ typedef struct {
     int delta_sweeps;    /* 1: sweep only the change of the scattering source and
                             accumulate the moments in FP64 (default for FP32_SWEEP) */
     int use_graph;       /* 1: replay each outer iteration from a captured hipGraph */
+    int moment_path;     /* 0: typed blocks on uniform Cartesian meshes with isotropic
+                            sources (batched kernels), else per-element operators;
+                            1: always per-element operators */
 } smm_solve_opts;
 
 typedef struct {
@@ -205,6 +211,39 @@ int smm_set_sweep_path(smm_problem* prob, int path);
 /* Time one sweep configuration on device (average ms over `reps` launches
  * measured with HIP events on the context stream); used by the benchmark. */
 int smm_time_sweep(smm_problem* prob, int precision, int reps, double* ms_avg);
+
+/* Host-only inspection of the typed Cartesian representation: the IP matrix
+ * [N][N], the correction-source operator [N][3N] (columns: T_xx, T_xy, T_yy
+ * blocks of N) and the fixed right-hand side [N], rebuilt from the typed
+ * blocks (small problems only; SMM_EUNSUPPORTED if the typed path does not
+ * apply). */
+int smm_debug_typed_dense(smm_problem* prob, double* A, double* C, double* b_fixed);
+/* The same correction-source operator [N][3N] from the per-element assembly. */
+int smm_debug_corr_dense(smm_problem* prob, double* C);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent problems (uniform Cartesian meshes, isotropic
+ * sources, vacuum or face-wise isotropic inflow) solved together.  Each
+ * kernel launch of the outer iteration covers every problem that has not yet
+ * converged; the sweep runs as one persistent launch per order p, fed by a
+ * queue of (problem, direction) tasks.  The problems stay owned by the
+ * caller and must outlive the batch; changing their data afterwards requires
+ * a new batch.
+ * ------------------------------------------------------------------------- */
+int smm_batch_create(smm_ctx* ctx, smm_problem* const* probs, int n, smm_batch** out);
+int smm_batch_destroy(smm_batch* batch);
+/* varphi0: NULL, or n pointers (host or device, NULL entries allowed) read
+ * when opts->start == SMM_START_GIVEN.  info: NULL or n entries.  Returns
+ * SMM_ENOCONV if any problem reached max_outer (all outputs stay valid). */
+int smm_batch_solve(smm_batch* batch, const smm_solve_opts* opts, const double* const* varphi0,
+                    smm_solve_info* info);
+/* Outputs of problem k of the last smm_batch_solve (layouts as smm_get_outputs). */
+int smm_batch_get_outputs(smm_batch* batch, int k, double* varphi, double* phi, double* J, double* T,
+                          double* beta, int on_device);
+/* Average time of one batched sweep (all problems, all directions). */
+int smm_batch_time_sweep(smm_batch* batch, int precision, int reps, double* ms_avg);
+/* Elem*angle*DOF units of one batched sweep. */
+int smm_batch_units(const smm_batch* batch, double* units);
 
 #ifdef __cplusplus
 }

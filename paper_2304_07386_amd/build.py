@@ -28,6 +28,8 @@ def build(verbose: bool = True) -> str:
     for src, flags in (
         ("host_setup.cpp", ["-x", "hip", *DEVICE_FLAGS, "-ffp-contract=off"]),
         ("api.cpp", ["-x", "hip", *DEVICE_FLAGS]),
+        ("typed.cpp", ["-x", "hip", *DEVICE_FLAGS, "-ffp-contract=off"]),
+        ("batch.cpp", ["-x", "hip", *DEVICE_FLAGS]),
         ("kernels.hip", DEVICE_FLAGS),
     ):
         obj = os.path.join(objdir, src + ".o")

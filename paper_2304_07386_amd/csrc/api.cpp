@@ -9,79 +9,14 @@
 
 #include <hip/hip_runtime.h>
 
-#include "kernels.hpp"
-#include "smm_internal.hpp"
-
-struct smm_ctx {
-    int device = -1;
-    hipStream_t stream = nullptr;
-    std::string last_error;
-};
-
-namespace smm {
-
-// Device-resident state of one problem.
-struct Dev {
-    bool built = false;
-    bool tables_dirty = true;   // materials changed
-    bool src_dirty = true;      // source / inflow changed
-    std::vector<void*> allocs;
-    // quadrature
-    double* omega = nullptr;
-    void* W32 = nullptr;
-    void* W64 = nullptr;
-    int ldw = 0;
-    // cartesian operator tables
-    void *Pm32 = nullptr, *Px32 = nullptr, *Py32 = nullptr;
-    void *Pm64 = nullptr, *Px64 = nullptr, *Py64 = nullptr;
-    uint8_t* mat = nullptr;
-    void *bx32 = nullptr, *by32 = nullptr, *bx64 = nullptr, *by64 = nullptr;
-    // general sweep data
-    void *Mk32 = nullptr, *Gx32 = nullptr, *Gy32 = nullptr, *nds32 = nullptr, *Lf32 = nullptr, *st32 = nullptr;
-    void *Mk64 = nullptr, *Gx64 = nullptr, *Gy64 = nullptr, *nds64 = nullptr, *Lf64 = nullptr, *st64 = nullptr;
-    int *nbr = nullptr, *bface_of = nullptr, *lev_ptr = nullptr, *lev_elem = nullptr;
-    uint8_t* upflag = nullptr;
-    void *pbar32 = nullptr, *pbar64 = nullptr;
-    // materials, source
-    double* sigma_s = nullptr;
-    double* q = nullptr;
-    // moment system
-    int* bsr_col = nullptr;
-    double *bsr_val = nullptr, *bjac = nullptr, *corr = nullptr, *beta_op = nullptr, *bfix = nullptr;
-    int *bface_K = nullptr, *bface_f = nullptr;
-    // work vectors
-    double *varphi = nullptr, *varphi_prev = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr,
-           *p = nullptr, *qv = nullptr, *part = nullptr, *scal = nullptr, *rpart = nullptr, *rout = nullptr;
-    void* S = nullptr;          // sweep source (sized for fp64, [nd_q][ne][n])
-    void* psi[2] = {nullptr, nullptr};  // sweep outputs (sized for fp64)
-    double *mom = nullptr, *mom_acc = nullptr, *T = nullptr, *beta = nullptr;
-    int cg_blocks = 0, r_blocks = 0;
-    bool have_outputs = false;
-    int force_general = 0;
-    const double* last_mom = nullptr;   // moments of the last G evaluation
-    const double* last_varphi = nullptr;
-};
-
-}  // namespace smm
-
-struct smm_problem {
-    smm::Problem P;
-    smm::Dev D;
-};
+#include "api_internal.hpp"
 
 using namespace smm;
 
-static int fail(smm_ctx* c, int code, const std::string& msg) {
+int smm::fail(smm_ctx* c, int code, const std::string& msg) {
     if (c) c->last_error = msg;
     return code;
 }
-
-#define HIPCHK(ctx, call)                                                              \
-    do {                                                                               \
-        hipError_t e_ = (call);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(ctx, SMM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
 
 extern "C" {
 
@@ -154,12 +89,17 @@ int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_or
     const size_t nctrl = (size_t)(P.ny * P.m + 1) * (P.nx * P.m + 1) * 2;
     P.ctrl.assign(mesh->ctrl, mesh->ctrl + nctrl);
     std::string err;
-    int rc = setup_geometry(P, err);
+    int rc = setup_geometry(P, err, false);
     if (rc != SMM_OK) {
         delete pr;
         return fail(ctx, rc, err);
     }
-    setup_sweep_graph(P);
+    // curved or irregular meshes need the per-element quadrature data and the
+    // sweep graph at once; uniform Cartesian meshes build them only on demand
+    if (!P.cartesian && (rc = ensure_heavy(P)) != SMM_OK) {
+        delete pr;
+        return fail(ctx, rc, "geometry setup failed");
+    }
     P.q.assign((size_t)P.ne * P.n, 0.0);
     *out = pr;
     return SMM_OK;
@@ -173,6 +113,7 @@ static void dev_free(Dev& D) {
 
 int smm_problem_destroy(smm_problem* prob) {
     if (!prob) return SMM_OK;
+    batch_release_single(prob);
     dev_free(prob->D);
     delete prob;
     return SMM_OK;
@@ -189,6 +130,8 @@ int smm_get_dims(const smm_problem* prob, smm_problem_dims* out) {
     out->cartesian = P.cartesian ? 1 : 0;
     out->n_material = P.nmat;
     out->n_levels = P.cartesian ? P.nx + P.ny - 1 : P.nlev_max;
+    out->n_self_types = P.nself;
+    out->n_nbr_types = P.nnbrt;
     return SMM_OK;
 }
 
@@ -229,6 +172,9 @@ int smm_set_materials(smm_problem* prob, const double* sigma_t, const double* si
     P.have_mat = true;
     P.lhs_ready = false;
     P.rhs_fixed_ready = false;
+    P.typed_ready = false;
+    P.Pm.clear();
+    batch_release_single(prob);
     prob->D.tables_dirty = true;
     prob->D.src_dirty = true;
     return SMM_OK;
@@ -246,6 +192,8 @@ int smm_set_source(smm_problem* prob, const double* q, int layout) {
     P.q.assign(q, q + cnt);
     P.src_layout = layout;
     P.rhs_fixed_ready = false;
+    P.typed_ready = false;
+    batch_release_single(prob);
     prob->D.src_dirty = true;
     return SMM_OK;
 }
@@ -272,6 +220,8 @@ int smm_set_inflow(smm_problem* prob, const double* psibar, int layout) {
         if (!std::isfinite(v)) return fail(P.ctx, SMM_EINVAL, "non-finite inflow");
     P.inflow_layout = layout;
     P.rhs_fixed_ready = false;
+    P.typed_ready = false;
+    batch_release_single(prob);
     prob->D.src_dirty = true;
     return SMM_OK;
 }
@@ -293,6 +243,7 @@ void smm_default_opts(smm_solve_opts* o) {
     o->start = SMM_START_ZERO;
     o->delta_sweeps = 0;
     o->use_graph = 0;
+    o->moment_path = 0;
 }
 
 }  // extern "C"
@@ -300,20 +251,42 @@ void smm_default_opts(smm_solve_opts* o) {
 // ---------------------------------------------------------------------------
 // host tables and device upload
 // ---------------------------------------------------------------------------
-static int ensure_host(smm_problem* pr) {
+// Host tables of the general path (per-element operators); `typed` also
+// builds the typed Cartesian blocks instead.
+static int ensure_host(smm_problem* pr, bool general = true) {
     Problem& P = pr->P;
     if (!P.have_mat) return fail(P.ctx, SMM_ESTATE, "materials not set");
-    if (!P.lhs_ready) {
-        assemble_ip(P);
-        assemble_correction_operator(P);
-        setup_cartesian_operators(P);
-    }
-    if (!P.rhs_fixed_ready) {
-        if (P.psibar.empty()) P.psibar.assign((size_t)P.nbf * P.nq * P.nd, 0.0);
-        assemble_rhs_fixed(P);
+    if (P.psibar.empty()) P.psibar.assign((size_t)P.nbf * P.nq * P.nd, 0.0);
+    if (P.cartesian && P.Pm.empty()) setup_cartesian_operators(P);
+    if (general) {
+        int rc = ensure_heavy(P);
+        if (rc) return fail(P.ctx, rc, "geometry setup failed");
+        if (!P.lhs_ready) {
+            assemble_ip(P);
+            assemble_correction_operator(P);
+            P.lhs_ready = true;
+        }
+        if (!P.rhs_fixed_ready) assemble_rhs_fixed(P);
     }
     return SMM_OK;
 }
+
+namespace smm {
+int ensure_typed(smm_problem* pr) {
+    Problem& P = pr->P;
+    if (!P.have_mat) return fail(P.ctx, SMM_ESTATE, "materials not set");
+    if (!typed_applicable(P)) return fail(P.ctx, SMM_EUNSUPPORTED, "typed path needs a uniform Cartesian mesh, "
+                                          "an isotropic source and vacuum or face-wise isotropic inflow");
+    int rc = ensure_host(pr, false);
+    if (rc) return rc;
+    if (!P.typed_ready) {
+        std::string err;
+        rc = build_typed_blocks(P, err);
+        if (rc) return fail(P.ctx, rc, err);
+    }
+    return SMM_OK;
+}
+}  // namespace smm
 
 template <typename T>
 static int upload(smm_ctx* c, Dev& D, T** dst, const void* src, size_t bytes) {
@@ -346,12 +319,16 @@ static std::vector<float> to_f32(const std::vector<double>& v) {
         if (rc_) return rc_;                                                      \
     } while (0)
 
-static int ensure_device(smm_problem* pr) {
+// Device tables.  Base data (quadrature, Cartesian operator tables, sources,
+// work vectors) always; the general sweep's per-element data when
+// `gen_sweep`; the per-element moment system when `gen_moment`.
+static int ensure_device(smm_problem* pr, bool gen_moment, bool gen_sweep) {
     Problem& P = pr->P;
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
     if (c->device < 0) return fail(c, SMM_ESTATE, "host-only context");
-    int rc = ensure_host(pr);
+    if (!P.cartesian) gen_sweep = true;
+    int rc = ensure_host(pr, gen_moment || gen_sweep);
     if (rc) return rc;
     const long L = (long)P.ne * P.n;
     if (!D.built) {
@@ -367,21 +344,12 @@ static int ensure_device(smm_problem* pr) {
         std::vector<float> W32 = to_f32(W);
         UP(D.W64, W);
         UP(D.W32, W32);
-        // general sweep geometry
         std::vector<float> f;
-        UP(D.Mk64, P.Mk); f = to_f32(P.Mk); UP(D.Mk32, f);
-        UP(D.Gx64, P.Gxk); f = to_f32(P.Gxk); UP(D.Gx32, f);
-        UP(D.Gy64, P.Gyk); f = to_f32(P.Gyk); UP(D.Gy32, f);
-        UP(D.nds64, P.nds); f = to_f32(P.nds); UP(D.nds32, f);
         UP(D.Lf64, P.Lf); f = to_f32(P.Lf); UP(D.Lf32, f);
         UP(D.nbr, P.nbr);
         UP(D.bface_of, P.bface_of);
-        UP(D.upflag, P.upflag);
-        UP(D.lev_ptr, P.lev_ptr);
-        UP(D.lev_elem, P.lev_elem);
         UP(D.bface_K, P.bface_K);
         UP(D.bface_f, P.bface_f);
-        // work vectors
         const int nd_q = P.nd;  // room for an anisotropic source
         if ((rc = alloc(c, D, &D.S, sizeof(double) * (size_t)nd_q * L))) return rc;
         for (int k = 0; k < 2; ++k)
@@ -402,21 +370,27 @@ static int ensure_device(smm_problem* pr) {
         if ((rc = alloc(c, D, &D.rout, sizeof(double) * 2))) return rc;
         D.built = true;
     }
+    if (gen_sweep && !D.gen_sweep_built) {
+        std::vector<float> f;
+        UP(D.Mk64, P.Mk); f = to_f32(P.Mk); UP(D.Mk32, f);
+        UP(D.Gx64, P.Gxk); f = to_f32(P.Gxk); UP(D.Gx32, f);
+        UP(D.Gy64, P.Gyk); f = to_f32(P.Gyk); UP(D.Gy32, f);
+        UP(D.nds64, P.nds); f = to_f32(P.nds); UP(D.nds32, f);
+        UP(D.upflag, P.upflag);
+        UP(D.lev_ptr, P.lev_ptr);
+        UP(D.lev_elem, P.lev_elem);
+        D.gen_sweep_built = true;
+    }
     if (D.tables_dirty) {
         std::vector<float> f;
         UP(D.st64, P.sigma_t); f = to_f32(P.sigma_t); UP(D.st32, f);
         UP(D.sigma_s, P.sigma_s);
-        UP(D.bsr_col, P.bsr_col);
-        UP(D.bsr_val, P.bsr_val);
-        UP(D.bjac, P.bjac_inv);
-        UP(D.corr, P.corr_val);
-        if (P.nbf > 0) UP(D.beta_op, P.beta_op);
         if (P.cartesian) {
             UP(D.mat, P.mat_of);
             // tables may grow when the material count changes: reallocate
             auto reup = [&](void** dst64, void** dst32, const std::vector<double>& v) -> int {
-                if (*dst64) { hipFree(*dst64); D.allocs.erase(std::find(D.allocs.begin(), D.allocs.end(), *dst64)); *dst64 = nullptr; }
-                if (*dst32) { hipFree(*dst32); D.allocs.erase(std::find(D.allocs.begin(), D.allocs.end(), *dst32)); *dst32 = nullptr; }
+                if (*dst64) { (void)hipFree(*dst64); D.allocs.erase(std::find(D.allocs.begin(), D.allocs.end(), *dst64)); *dst64 = nullptr; }
+                if (*dst32) { (void)hipFree(*dst32); D.allocs.erase(std::find(D.allocs.begin(), D.allocs.end(), *dst32)); *dst32 = nullptr; }
                 int r1 = upload(c, D, dst64, v.data(), sizeof(double) * v.size());
                 if (r1) return r1;
                 std::vector<float> g = to_f32(v);
@@ -427,10 +401,10 @@ static int ensure_device(smm_problem* pr) {
             if ((rc = reup(&D.Py64, &D.Py32, P.Py))) return rc;
         }
         D.tables_dirty = false;
+        D.gen_dirty = true;
     }
     if (D.src_dirty) {
         UP(D.q, P.q);
-        UP(D.bfix, P.b_fixed);
         // inflow: [nd][nbf][nq] for the general kernel, traces for the cartesian kernel
         std::vector<double> pb((size_t)P.nd * P.nbf * P.nq);
         for (int bf = 0; bf < P.nbf; ++bf)
@@ -447,6 +421,16 @@ static int ensure_device(smm_problem* pr) {
             UP(D.by64, by); f = to_f32(by); UP(D.by32, f);
         }
         D.src_dirty = false;
+        D.gen_dirty = true;
+    }
+    if (gen_moment && D.gen_dirty) {
+        UP(D.bsr_col, P.bsr_col);
+        UP(D.bsr_val, P.bsr_val);
+        UP(D.bjac, P.bjac_inv);
+        UP(D.corr, P.corr_val);
+        if (P.nbf > 0) UP(D.beta_op, P.beta_op);
+        UP(D.bfix, P.b_fixed);
+        D.gen_dirty = false;
     }
     return SMM_OK;
 }
@@ -589,8 +573,16 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     Problem& P = prob->P;
     Dev& D = prob->D;
     smm_ctx* c = P.ctx;
+    if (c->device < 0) return fail(c, SMM_ESTATE, "host-only context");
+    if (!P.have_mat) return fail(c, SMM_ESTATE, "materials not set");
+    if (o.moment_path == 0 && typed_applicable(P) && D.force_general != 1) {
+        const int r = batch_solve_single(prob, o, varphi0, info);
+        D.last_typed = (r == SMM_OK || r == SMM_ENOCONV);
+        return r;
+    }
+    D.last_typed = false;
     auto t0 = std::chrono::steady_clock::now();
-    int rc = ensure_device(prob);
+    int rc = ensure_device(prob, true, D.force_general == 1);
     if (rc) return rc;
     auto t1 = std::chrono::steady_clock::now();
     const long L = (long)P.ne * P.n;
@@ -655,6 +647,7 @@ int smm_get_outputs(smm_problem* prob, double* varphi, double* phi, double* J, d
     Problem& P = prob->P;
     Dev& D = prob->D;
     smm_ctx* c = P.ctx;
+    if (D.last_typed) return batch_outputs_single(prob, varphi, phi, J, T, beta, on_device);
     if (!D.have_outputs || !D.last_mom) return fail(c, SMM_ESTATE, "no solve has run");
     const long L = (long)P.ne * P.n;
     const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -674,7 +667,7 @@ int smm_apply_sweep(smm_problem* prob, int precision, const void* S, int s_layou
     if (!prob || !S || !psi_out) return SMM_EINVAL;
     if (precision != SMM_FP64 && precision != SMM_FP32_SWEEP) return SMM_EINVAL;
     if (s_layout != SMM_SRC_ISO && s_layout != SMM_SRC_ANISO) return SMM_EINVAL;
-    int rc = ensure_device(prob);
+    int rc = ensure_device(prob, false, prob->D.force_general == 1);
     if (rc) return rc;
     return run_sweep(prob, precision == SMM_FP64, S, s_layout == SMM_SRC_ANISO ? 1 : 0, psi_lag, psi_out,
                      with_inflow != 0);
@@ -683,7 +676,7 @@ int smm_apply_sweep(smm_problem* prob, int precision, const void* S, int s_layou
 int smm_apply_moments(smm_problem* prob, int precision, const void* psi, double* mom) {
     if (!prob || !psi || !mom) return SMM_EINVAL;
     if (precision != SMM_FP64 && precision != SMM_FP32_SWEEP) return SMM_EINVAL;
-    int rc = ensure_device(prob);
+    int rc = ensure_device(prob, false, false);
     if (rc) return rc;
     Problem& P = prob->P;
     Dev& D = prob->D;
@@ -696,7 +689,7 @@ int smm_apply_moments(smm_problem* prob, int precision, const void* psi, double*
 int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, double* varphi_out, double inner_tol,
                 int max_inner) {
     if (!prob || !varphi_in || !varphi_out) return SMM_EINVAL;
-    int rc = ensure_device(prob);
+    int rc = ensure_device(prob, true, prob->D.force_general == 1);
     if (rc) return rc;
     Problem& P = prob->P;
     Dev& D = prob->D;
@@ -709,6 +702,7 @@ int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, doubl
     HIPCHK(c, hipStreamSynchronize(c->stream));
     D.have_outputs = true;
     D.last_varphi = D.x;
+    D.last_typed = false;
     return SMM_OK;
 }
 
@@ -736,9 +730,60 @@ int smm_debug_ip_dense(const smm_problem* prob_c, double* A, double* b_fixed) {
     return SMM_OK;
 }
 
+int smm_debug_typed_dense(smm_problem* prob, double* A, double* C, double* b_fixed) {
+    if (!prob) return SMM_EINVAL;
+    int rc = ensure_typed(prob);
+    if (rc) return rc;
+    Problem& P = prob->P;
+    const long n = P.n, N = (long)P.ne * n;
+    if (N > 20000) return fail(P.ctx, SMM_EINVAL, "problem too large for a dense copy");
+    auto nbr_of = [&](int K, int f) { return f == 0 ? K - P.nx : f == 1 ? K + 1 : f == 2 ? K + P.nx : K - 1; };
+    if (A) std::memset(A, 0, sizeof(double) * N * N);
+    if (C) std::memset(C, 0, sizeof(double) * N * 3 * N);
+    for (int K = 0; K < P.ne; ++K)
+        for (int s = 0; s < 5; ++s) {
+            int Kc, t;
+            if (s == 0) { Kc = K; t = P.sid[K]; }
+            else { t = P.nid[(size_t)K * 4 + s - 1]; if (t < 0) continue; Kc = nbr_of(K, s - 1); }
+            const double* ab = (s == 0 ? P.t_ip_self.data() : P.t_ip_nbr.data()) + (size_t)t * n * n;
+            const double* cb = (s == 0 ? P.t_c_self.data() : P.t_c_nbr.data()) + (size_t)t * n * 3 * n;
+            for (int i = 0; i < n; ++i) {
+                if (A)
+                    for (int j = 0; j < n; ++j) A[((long)K * n + i) * N + (long)Kc * n + j] += ab[i * n + j];
+                if (C)
+                    for (int cc = 0; cc < 3; ++cc)
+                        for (int j = 0; j < n; ++j)
+                            C[((long)K * n + i) * 3 * N + cc * N + (long)Kc * n + j] += cb[i * 3 * n + cc * n + j];
+            }
+        }
+    if (b_fixed) std::memcpy(b_fixed, P.t_bfix.data(), sizeof(double) * N);
+    return SMM_OK;
+}
+
+int smm_debug_corr_dense(smm_problem* prob, double* C) {
+    if (!prob || !C) return SMM_EINVAL;
+    int rc = ensure_host(prob);
+    if (rc) return rc;
+    Problem& P = prob->P;
+    const long n = P.n, N = (long)P.ne * n;
+    if (N > 20000) return fail(P.ctx, SMM_EINVAL, "problem too large for a dense copy");
+    std::memset(C, 0, sizeof(double) * N * 3 * N);
+    for (int K = 0; K < P.ne; ++K)
+        for (int s = 0; s < 5; ++s) {
+            const int Kc = P.bsr_col[K * 5 + s];
+            if (Kc < 0) continue;
+            const double* cb = &P.corr_val[((size_t)K * 5 + s) * n * 3 * n];
+            for (int i = 0; i < n; ++i)
+                for (int cc = 0; cc < 3; ++cc)
+                    for (int j = 0; j < n; ++j)
+                        C[((long)K * n + i) * 3 * N + cc * N + (long)Kc * n + j] += cb[i * 3 * n + cc * n + j];
+        }
+    return SMM_OK;
+}
+
 int smm_time_sweep(smm_problem* prob, int precision, int reps, double* ms_avg) {
     if (!prob || !ms_avg || reps < 1) return SMM_EINVAL;
-    int rc = ensure_device(prob);
+    int rc = ensure_device(prob, false, prob->D.force_general == 1);
     if (rc) return rc;
     Problem& P = prob->P;
     Dev& D = prob->D;

@@ -1,0 +1,89 @@
+// Internal definitions shared by the C-ABI translation units.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "smm_internal.hpp"
+
+struct smm_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+};
+
+namespace smm {
+
+// Device-resident state of one problem.
+struct Dev {
+    bool built = false;
+    bool tables_dirty = true;   // materials changed
+    bool src_dirty = true;      // source / inflow changed
+    std::vector<void*> allocs;
+    // quadrature
+    double* omega = nullptr;
+    void* W32 = nullptr;
+    void* W64 = nullptr;
+    int ldw = 0;
+    // cartesian operator tables
+    void *Pm32 = nullptr, *Px32 = nullptr, *Py32 = nullptr;
+    void *Pm64 = nullptr, *Px64 = nullptr, *Py64 = nullptr;
+    uint8_t* mat = nullptr;
+    void *bx32 = nullptr, *by32 = nullptr, *bx64 = nullptr, *by64 = nullptr;
+    // general sweep data
+    void *Mk32 = nullptr, *Gx32 = nullptr, *Gy32 = nullptr, *nds32 = nullptr, *Lf32 = nullptr, *st32 = nullptr;
+    void *Mk64 = nullptr, *Gx64 = nullptr, *Gy64 = nullptr, *nds64 = nullptr, *Lf64 = nullptr, *st64 = nullptr;
+    int *nbr = nullptr, *bface_of = nullptr, *lev_ptr = nullptr, *lev_elem = nullptr;
+    uint8_t* upflag = nullptr;
+    void *pbar32 = nullptr, *pbar64 = nullptr;
+    // materials, source
+    double* sigma_s = nullptr;
+    double* q = nullptr;
+    // moment system
+    int* bsr_col = nullptr;
+    double *bsr_val = nullptr, *bjac = nullptr, *corr = nullptr, *beta_op = nullptr, *bfix = nullptr;
+    int *bface_K = nullptr, *bface_f = nullptr;
+    // work vectors
+    double *varphi = nullptr, *varphi_prev = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr,
+           *p = nullptr, *qv = nullptr, *part = nullptr, *scal = nullptr, *rpart = nullptr, *rout = nullptr;
+    void* S = nullptr;          // sweep source (sized for fp64, [nd_q][ne][n])
+    void* psi[2] = {nullptr, nullptr};  // sweep outputs (sized for fp64)
+    double *mom = nullptr, *mom_acc = nullptr, *T = nullptr, *beta = nullptr;
+    int cg_blocks = 0, r_blocks = 0;
+    bool have_outputs = false;
+    bool last_typed = false;       // last solve ran on the typed (batched) path
+    bool gen_sweep_built = false;  // per-element sweep data uploaded
+    bool gen_dirty = true;         // per-element moment system needs (re)upload
+    int force_general = 0;
+    const double* last_mom = nullptr;   // moments of the last G evaluation
+    const double* last_varphi = nullptr;
+};
+
+}  // namespace smm
+
+struct smm_batch;
+
+struct smm_problem {
+    smm::Problem P;
+    smm::Dev D;
+    smm_batch* own_batch = nullptr;   // batch of one used by smm_solve on the typed path
+};
+
+
+namespace smm {
+int fail(smm_ctx* c, int code, const std::string& msg);
+int batch_solve_single(smm_problem* pr, const smm_solve_opts& o, const double* varphi0, smm_solve_info* info);
+int batch_outputs_single(smm_problem* pr, double* varphi, double* phi, double* J, double* T, double* beta,
+                         int on_device);
+void batch_release_single(smm_problem* pr);
+}  // namespace smm
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return smm::fail(ctx, SMM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)

@@ -1,0 +1,739 @@
+// Batched SMM solves on uniform Cartesian meshes: many problems of different
+// size, order p and S_N set share each kernel launch.
+//
+//  * the sweep runs as one persistent launch per order p, whose workgroups
+//    take (problem, direction) tasks from a queue ordered by decreasing cost;
+//    the launches of the different orders run concurrently on forked
+//    streams;
+//  * moments, closures, right-hand side, block-Jacobi PCG and the outer
+//    residual run as single launches over all problems, with per-problem
+//    reductions and convergence flags (problems that have converged drop out
+//    of every later launch);
+//  * the grid of each persistent sweep launch is chosen by timing the
+//    candidates on the batch itself (cached per launch shape).
+// A single problem on the typed path is a batch of one.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <tuple>
+
+#include "api_internal.hpp"
+
+namespace smm {
+int ensure_typed(smm_problem* pr);
+}
+
+using namespace smm;
+
+namespace {
+
+struct PerProb {
+    double *varphi, *varphi_prev, *x, *b, *r, *z, *p, *q, *bfix, *qsrc, *sigma_s, *mom, *mom_acc, *T, *beta;
+    int *sid, *nid, *bface_of, *bK, *bF;
+    double *ip_self, *ip_nbr, *dinv, *c_self, *c_nbr, *bop, *Lf;
+    void* S;
+    void* psi;
+    double* W64;
+    float* W32;
+    double* omega;
+    double *Pm64, *Px64, *Py64, *bx64, *by64;
+    float *Pm32, *Px32, *Py32, *bx32, *by32;
+    uint8_t* mat;
+};
+
+struct Group {
+    int nb = 0, mreg_any = 1, threads = 0;
+    int mreg[2] = {0, 0};                  // per precision: 1 register-resident rows, 0 LDS tables
+    size_t lds[2] = {0, 0};
+    int grid[2] = {0, 0};
+    std::vector<int2> tasks;
+    int2* d_tasks = nullptr;
+    int* d_counter = nullptr;
+};
+
+struct Pool {
+    struct Req {
+        void** dst;
+        size_t off;
+    };
+    std::vector<Req> reqs;
+    size_t total = 0;
+    template <typename T>
+    void req(T** dst, size_t bytes) {
+        reqs.push_back({reinterpret_cast<void**>(dst), total});
+        total += (bytes + 255) / 256 * 256;
+    }
+};
+
+std::map<std::tuple<int, int, int, size_t, size_t, int>, int>& tune_cache() {
+    static std::map<std::tuple<int, int, int, size_t, size_t, int>, int> m;
+    return m;
+}
+
+}  // namespace
+
+struct smm_batch {
+    smm_ctx* ctx = nullptr;
+    std::vector<smm_problem*> probs;
+    int nprob = 0;
+    void* pool = nullptr;
+    std::vector<PerProb> pp;
+    std::vector<BProb> hP;
+    BProb* dP = nullptr;
+    std::vector<int> blk2p;
+    int* d_blk2p = nullptr;
+    int nblocks = 0;
+    double* part = nullptr;
+    std::vector<long> bq0, mw0;
+    long* d_bq0 = nullptr;
+    long* d_mw0 = nullptr;
+    long nbq = 0, nmw = 0;
+    int* d_active = nullptr;
+    std::vector<int> active;
+    double* d_scal = nullptr;
+    double* d_rout = nullptr;
+    std::vector<Group> groups;
+    CartSweepArgs* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<smm_solve_info> last_info;
+    bool have_outputs = false;
+    int ncu = 256;
+};
+
+namespace {
+
+BatchLaunch launch_desc(smm_batch* B) {
+    BatchLaunch L{};
+    L.P = B->dP;
+    L.nprob = B->nprob;
+    L.blk2p = B->d_blk2p;
+    L.nblocks = B->nblocks;
+    L.active = B->d_active;
+    L.part = B->part;
+    L.nbq = B->nbq;
+    L.nmw = B->nmw;
+    L.bq0 = B->d_bq0;
+    L.mw0 = B->d_mw0;
+    return L;
+}
+
+std::vector<float> f32(const std::vector<double>& v) {
+    std::vector<float> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+    return o;
+}
+
+// Every device pointer of a descriptor must be set before any kernel reads it.
+int check_desc(smm_ctx* c, const BProb& D, int b) {
+    const void* ptrs[] = {D.varphi, D.varphi_prev, D.x, D.b, D.r, D.z, D.p, D.q, D.bfix, D.qsrc, D.sigma_s,
+                          D.mom, D.mom_acc, D.T, D.beta, D.sid, D.nid, D.bface_of, D.bK, D.bF, D.ip_self,
+                          D.ip_nbr, D.dinv, D.c_self, D.c_nbr, D.bop, D.Lf, D.scal, D.S, D.psi, D.W64, D.W32};
+    for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k)
+        if (!ptrs[k])
+            return fail(c, SMM_EHIP, "batch descriptor " + std::to_string(b) + " field " + std::to_string(k) +
+                                         " unset");
+    if (D.ldw < D.nd || D.Lpad < D.L || D.Lpad % 4 != 0 || D.nblk < 1) return fail(c, SMM_EHIP, "bad descriptor");
+    return SMM_OK;
+}
+
+int check_args(smm_ctx* c, const CartSweepArgs& A) {
+    if (!A.S || !A.Pm || !A.Px || !A.Py || !A.mat || !A.omega || !A.psi || A.psi_ld < (long)A.nx * A.ny * A.nb * A.nb)
+        return fail(c, SMM_EHIP, "bad sweep descriptor");
+    return SMM_OK;
+}
+
+int put(smm_ctx* c, void* dst, const void* src, size_t bytes) {
+    if (!bytes) return SMM_OK;
+    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return fail(c, SMM_EHIP, "hipMemcpy");
+    return SMM_OK;
+}
+
+void batch_free(smm_batch* B) {
+    if (!B) return;
+    if (B->pool) (void)hipFree(B->pool);
+    for (auto& s : B->side)
+        if (s) (void)hipStreamDestroy(s);
+    if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+    for (auto& e : B->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    delete B;
+}
+
+int batch_build(smm_batch* B) {
+    smm_ctx* c = B->ctx;
+    const int np = B->nprob;
+    for (smm_problem* pr : B->probs) {
+        int rc = ensure_typed(pr);
+        if (rc) return rc;
+    }
+    (void)hipDeviceGetAttribute(&B->ncu, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (B->ncu <= 0) B->ncu = 256;
+    B->pp.assign(np, PerProb{});
+    B->hP.assign(np, BProb{});
+    Pool pool;
+    B->bq0.assign(np, 0);
+    B->mw0.assign(np, 0);
+    B->blk2p.clear();
+    long bq = 0, mw = 0;
+    for (int b = 0; b < np; ++b) {
+        const Problem& P = B->probs[b]->P;
+        PerProb& q = B->pp[b];
+        const size_t L = (size_t)P.ne * P.n, Lpad = (L + 3) / 4 * 4, n = P.n, ne = P.ne;
+        const int ldw = (P.nd + 3) / 4 * 4;
+        double** v8[] = {&q.varphi, &q.varphi_prev, &q.x, &q.b, &q.r, &q.z, &q.p, &q.q, &q.bfix, &q.qsrc};
+        for (double** v : v8) pool.req(v, sizeof(double) * L);
+        pool.req(&q.sigma_s, sizeof(double) * ne);
+        pool.req(&q.mom, sizeof(double) * 8 * L);
+        pool.req(&q.mom_acc, sizeof(double) * 8 * L);
+        pool.req(&q.T, sizeof(double) * 3 * L);
+        pool.req(&q.beta, sizeof(double) * std::max<size_t>(1, (size_t)P.nbf * P.nq));
+        pool.req(&q.sid, sizeof(int) * ne);
+        pool.req(&q.nid, sizeof(int) * 4 * ne);
+        pool.req(&q.bface_of, sizeof(int) * 4 * ne);
+        pool.req(&q.bK, sizeof(int) * std::max(1, P.nbf));
+        pool.req(&q.bF, sizeof(int) * std::max(1, P.nbf));
+        pool.req(&q.ip_self, sizeof(double) * P.t_ip_self.size());
+        pool.req(&q.ip_nbr, sizeof(double) * std::max<size_t>(1, P.t_ip_nbr.size()));
+        pool.req(&q.dinv, sizeof(double) * P.t_dinv.size());
+        pool.req(&q.c_self, sizeof(double) * P.t_c_self.size());
+        pool.req(&q.c_nbr, sizeof(double) * std::max<size_t>(1, P.t_c_nbr.size()));
+        pool.req(&q.bop, sizeof(double) * P.t_bop.size());
+        pool.req(&q.Lf, sizeof(double) * P.Lf.size());
+        pool.req(&q.S, sizeof(double) * L);
+        pool.req(&q.psi, sizeof(double) * (size_t)P.nd * Lpad);
+        pool.req(&q.W64, sizeof(double) * 16 * ldw);
+        pool.req(&q.W32, sizeof(float) * 16 * ldw);
+        pool.req(&q.omega, sizeof(double) * P.omega.size());
+        pool.req(&q.Pm64, sizeof(double) * P.Pm.size());
+        pool.req(&q.Px64, sizeof(double) * P.Px.size());
+        pool.req(&q.Py64, sizeof(double) * P.Py.size());
+        pool.req(&q.Pm32, sizeof(float) * P.Pm.size());
+        pool.req(&q.Px32, sizeof(float) * P.Px.size());
+        pool.req(&q.Py32, sizeof(float) * P.Py.size());
+        pool.req(&q.bx64, sizeof(double) * (size_t)P.nd * P.ny * P.nb);
+        pool.req(&q.by64, sizeof(double) * (size_t)P.nd * P.nx * P.nb);
+        pool.req(&q.bx32, sizeof(float) * (size_t)P.nd * P.ny * P.nb);
+        pool.req(&q.by32, sizeof(float) * (size_t)P.nd * P.nx * P.nb);
+        pool.req(&q.mat, ne);
+        // element blocks
+        const int epb = 256 / P.n;
+        const int nblk = (P.ne + epb - 1) / epb;
+        B->hP[b].blk0 = (int)B->blk2p.size();
+        B->hP[b].nblk = nblk;
+        for (int k = 0; k < nblk; ++k) B->blk2p.push_back(b);
+        B->bq0[b] = bq;
+        bq += (long)P.nbf * P.nq;
+        B->mw0[b] = mw;
+        mw += (long)((Lpad + 63) / 64);
+    }
+    B->nblocks = (int)B->blk2p.size();
+    B->nbq = bq;
+    B->nmw = mw;
+    pool.req(&B->dP, sizeof(BProb) * np);
+    pool.req(&B->d_blk2p, sizeof(int) * B->nblocks);
+    pool.req(&B->part, sizeof(double) * 3 * std::max(B->nblocks, np));
+    pool.req(&B->d_bq0, sizeof(long) * np);
+    pool.req(&B->d_mw0, sizeof(long) * np);
+    pool.req(&B->d_active, sizeof(int) * np);
+    pool.req(&B->d_scal, sizeof(double) * 16 * np);
+    pool.req(&B->d_rout, sizeof(double) * 2 * np);
+    for (int f = 0; f < 2; ++f)
+        for (int g = 0; g < 2; ++g) pool.req(&B->d_args[f][g], sizeof(CartSweepArgs) * np);
+    // sweep groups by order
+    std::map<int, int> gi;
+    B->groups.clear();
+    for (int b = 0; b < np; ++b) {
+        const Problem& P = B->probs[b]->P;
+        if (!gi.count(P.nb)) {
+            gi[P.nb] = (int)B->groups.size();
+            B->groups.push_back(Group{});
+            B->groups.back().nb = P.nb;
+            B->groups.back().mreg_any = 1;
+        }
+        Group& G = B->groups[gi[P.nb]];
+        const int maxlen = std::min(P.nx, P.ny);
+        G.threads = std::max(G.threads, (maxlen * P.nb + 63) / 64 * 64);
+        if (P.nmat != 1) G.mreg_any = 0;
+        for (int d = 0; d < P.nd; ++d) G.tasks.push_back(make_int2(b, d));
+    }
+    for (Group& G : B->groups) {
+        if (G.threads > 1024) return fail(c, SMM_EUNSUPPORTED, "anti-diagonal too long for one workgroup");
+        for (int f = 0; f < 2; ++f) {
+            // same rule as the launcher: register rows only where they do not spill
+            G.mreg[f] = (G.mreg_any && G.threads <= 512 && G.nb <= (f == 1 ? 3 : 4)) ? 1 : 0;
+            size_t lds = 0;
+            for (const int2& t : G.tasks) {
+                const Problem& P = B->probs[t.x]->P;
+                lds = std::max(lds, b_sweep_lds(f == 1, G.nb, G.mreg[f], P.nx, P.ny, P.nmat));
+            }
+            G.lds[f] = lds;
+        }
+        // longest problems first (levels, then anti-diagonal length)
+        std::stable_sort(G.tasks.begin(), G.tasks.end(), [&](const int2& a, const int2& b) {
+            const Problem& A = B->probs[a.x]->P;
+            const Problem& Bp = B->probs[b.x]->P;
+            const long ca = (long)(A.nx + A.ny) * 4096 + std::min(A.nx, A.ny);
+            const long cb = (long)(Bp.nx + Bp.ny) * 4096 + std::min(Bp.nx, Bp.ny);
+            return ca > cb;
+        });
+        pool.req(&G.d_tasks, sizeof(int2) * G.tasks.size());
+        pool.req(&G.d_counter, sizeof(int) * 4);
+    }
+    if (hipMalloc(&B->pool, pool.total) != hipSuccess) return fail(c, SMM_ENOMEM, "batch pool allocation");
+    for (const auto& r : pool.reqs) *r.dst = static_cast<char*>(B->pool) + r.off;
+    if (hipMemset(B->pool, 0, pool.total) != hipSuccess) return fail(c, SMM_EHIP, "hipMemset");
+    // uploads and descriptors
+    std::vector<CartSweepArgs> args[2][2];
+    for (int f = 0; f < 2; ++f)
+        for (int g = 0; g < 2; ++g) args[f][g].assign(np, CartSweepArgs{});
+    int rc;
+    for (int b = 0; b < np; ++b) {
+        const Problem& P = B->probs[b]->P;
+        PerProb& q = B->pp[b];
+        const size_t L = (size_t)P.ne * P.n, Lpad = (L + 3) / 4 * 4;
+        const int ldw = (P.nd + 3) / 4 * 4;
+        std::vector<double> W(16 * (size_t)ldw, 0.0);
+        for (int d = 0; d < P.nd; ++d) {
+            const double w = P.w[d], ox = P.omega[d * 3], oy = P.omega[d * 3 + 1];
+            const double rows[8] = {w, w * ox, w * oy, w * ox * ox, w * ox * oy, w * oy * oy, w * std::fabs(ox),
+                                    w * std::fabs(oy)};
+            for (int r = 0; r < 8; ++r) W[(size_t)r * ldw + d] = rows[r];
+        }
+        std::vector<double> bx, by;
+        cartesian_boundary_traces(P, bx, by);
+        struct U {
+            void* d;
+            const void* s;
+            size_t n;
+        };
+        const std::vector<float> W32 = f32(W), Pm32 = f32(P.Pm), Px32 = f32(P.Px), Py32 = f32(P.Py), bx32 = f32(bx),
+                                 by32 = f32(by);
+        const U ups[] = {
+            {q.bfix, P.t_bfix.data(), sizeof(double) * L},
+            {q.qsrc, P.q.data(), sizeof(double) * L},
+            {q.sigma_s, P.sigma_s.data(), sizeof(double) * P.ne},
+            {q.sid, P.sid.data(), sizeof(int) * P.ne},
+            {q.nid, P.nid.data(), sizeof(int) * 4 * P.ne},
+            {q.bface_of, P.bface_of.data(), sizeof(int) * 4 * P.ne},
+            {q.bK, P.bface_K.data(), sizeof(int) * P.nbf},
+            {q.bF, P.bface_f.data(), sizeof(int) * P.nbf},
+            {q.ip_self, P.t_ip_self.data(), sizeof(double) * P.t_ip_self.size()},
+            {q.ip_nbr, P.t_ip_nbr.data(), sizeof(double) * P.t_ip_nbr.size()},
+            {q.dinv, P.t_dinv.data(), sizeof(double) * P.t_dinv.size()},
+            {q.c_self, P.t_c_self.data(), sizeof(double) * P.t_c_self.size()},
+            {q.c_nbr, P.t_c_nbr.data(), sizeof(double) * P.t_c_nbr.size()},
+            {q.bop, P.t_bop.data(), sizeof(double) * P.t_bop.size()},
+            {q.Lf, P.Lf.data(), sizeof(double) * P.Lf.size()},
+            {q.W64, W.data(), sizeof(double) * W.size()},
+            {q.W32, W32.data(), sizeof(float) * W32.size()},
+            {q.omega, P.omega.data(), sizeof(double) * P.omega.size()},
+            {q.Pm64, P.Pm.data(), sizeof(double) * P.Pm.size()},
+            {q.Px64, P.Px.data(), sizeof(double) * P.Px.size()},
+            {q.Py64, P.Py.data(), sizeof(double) * P.Py.size()},
+            {q.Pm32, Pm32.data(), sizeof(float) * Pm32.size()},
+            {q.Px32, Px32.data(), sizeof(float) * Px32.size()},
+            {q.Py32, Py32.data(), sizeof(float) * Py32.size()},
+            {q.bx64, bx.data(), sizeof(double) * bx.size()},
+            {q.by64, by.data(), sizeof(double) * by.size()},
+            {q.bx32, bx32.data(), sizeof(float) * bx32.size()},
+            {q.by32, by32.data(), sizeof(float) * by32.size()},
+            {q.mat, P.mat_of.data(), P.mat_of.size()},
+        };
+        for (const U& u : ups)
+            if ((rc = put(c, u.d, u.s, u.n))) return rc;
+        BProb& D = B->hP[b];
+        D.ne = P.ne; D.n = P.n; D.nb = P.nb; D.nq = P.nq; D.nbf = P.nbf; D.nd = P.nd; D.nx = P.nx; D.ldw = ldw;
+        D.L = (long)L; D.Lpad = (long)Lpad; D.eb0x = P.eb0x; D.eb0y = P.eb0y;
+        D.bq0 = B->bq0[b]; D.mw0 = B->mw0[b];
+        D.varphi = q.varphi; D.varphi_prev = q.varphi_prev; D.x = q.x; D.b = q.b; D.r = q.r; D.z = q.z; D.p = q.p;
+        D.q = q.q; D.bfix = q.bfix; D.qsrc = q.qsrc; D.sigma_s = q.sigma_s;
+        D.mom = q.mom; D.mom_acc = q.mom_acc; D.T = q.T; D.beta = q.beta;
+        D.sid = q.sid; D.nid = q.nid; D.bface_of = q.bface_of; D.bK = q.bK; D.bF = q.bF;
+        D.ip_self = q.ip_self; D.ip_nbr = q.ip_nbr; D.dinv = q.dinv; D.c_self = q.c_self; D.c_nbr = q.c_nbr;
+        D.bop = q.bop; D.Lf = q.Lf;
+        D.scal = B->d_scal + 16 * b;
+        D.S = q.S; D.psi = q.psi;
+        D.W64 = q.W64; D.W32 = q.W32;
+        if ((rc = check_desc(c, D, b))) return rc;
+        for (int f = 0; f < 2; ++f)
+            for (int g = 0; g < 2; ++g) {
+                CartSweepArgs& A = args[f][g][b];
+                A.nx = P.nx; A.ny = P.ny; A.nd = P.nd; A.nb = P.nb; A.nmat = P.nmat; A.s_aniso = 0;
+                A.S = q.S;
+                A.Pm = f ? (const void*)q.Pm64 : (const void*)q.Pm32;
+                A.Px = f ? (const void*)q.Px64 : (const void*)q.Px32;
+                A.Py = f ? (const void*)q.Py64 : (const void*)q.Py32;
+                A.mat = q.mat;
+                A.omega = q.omega;
+                const bool inflow = g == 1 && P.inflow_layout != SMM_INFLOW_VACUUM;
+                A.bx = inflow ? (f ? (const void*)q.bx64 : (const void*)q.bx32) : nullptr;
+                A.by = inflow ? (f ? (const void*)q.by64 : (const void*)q.by32) : nullptr;
+                A.psi = q.psi;
+                A.variant = 0;
+                A.psi_ld = (long)Lpad;
+                if ((rc = check_args(c, A))) return rc;
+            }
+    }
+    if ((rc = put(c, B->dP, B->hP.data(), sizeof(BProb) * np))) return rc;
+    if ((rc = put(c, B->d_blk2p, B->blk2p.data(), sizeof(int) * B->nblocks))) return rc;
+    if ((rc = put(c, B->d_bq0, B->bq0.data(), sizeof(long) * np))) return rc;
+    if ((rc = put(c, B->d_mw0, B->mw0.data(), sizeof(long) * np))) return rc;
+    for (int f = 0; f < 2; ++f)
+        for (int g = 0; g < 2; ++g)
+            if ((rc = put(c, B->d_args[f][g], args[f][g].data(), sizeof(CartSweepArgs) * np))) return rc;
+    for (Group& G : B->groups)
+        if ((rc = put(c, G.d_tasks, G.tasks.data(), sizeof(int2) * G.tasks.size()))) return rc;
+    B->active.assign(np, 1);
+    if ((rc = put(c, B->d_active, B->active.data(), sizeof(int) * np))) return rc;
+    for (int k = 0; k < 4; ++k) {
+        if (hipStreamCreateWithFlags(&B->side[k], hipStreamNonBlocking) != hipSuccess)
+            return fail(c, SMM_EHIP, "hipStreamCreate");
+        if (hipEventCreateWithFlags(&B->ev_join[k], hipEventDisableTiming) != hipSuccess)
+            return fail(c, SMM_EHIP, "hipEventCreate");
+    }
+    if (hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming) != hipSuccess)
+        return fail(c, SMM_EHIP, "hipEventCreate");
+    return SMM_OK;
+}
+
+// Run the sweep of all active problems: one persistent launch per order, on
+// forked streams when there is more than one order.
+int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
+    smm_ctx* c = B->ctx;
+    const int f = fp64 ? 1 : 0;
+    const int ng = (int)B->groups.size();
+    if (ng > 1) {
+        HIPCHK(c, hipEventRecord(B->ev_fork, c->stream));
+        for (int k = 0; k < ng; ++k) HIPCHK(c, hipStreamWaitEvent(B->side[k % 4], B->ev_fork, 0));
+    }
+    for (int k = 0; k < ng; ++k) {
+        Group& G = B->groups[k];
+        hipStream_t s = ng > 1 ? B->side[k % 4] : c->stream;
+        HIPCHK(c, zero_ints(G.d_counter, 1, s));
+        int grid = G.grid[f] > 0 ? G.grid[f] : std::min<int>((int)G.tasks.size(), 2 * B->ncu);
+        hipError_t e = b_sweep(fp64, G.nb, G.mreg[f], G.threads, G.lds[f], grid, B->d_args[f][inflow ? 1 : 0],
+                               G.d_tasks, (int)G.tasks.size(), G.d_counter, B->d_active, s);
+        if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("batched sweep: ") + hipGetErrorString(e));
+    }
+    if (ng > 1)
+        for (int k = 0; k < std::min(ng, 4); ++k) {
+            HIPCHK(c, hipEventRecord(B->ev_join[k], B->side[k]));
+            HIPCHK(c, hipStreamWaitEvent(c->stream, B->ev_join[k], 0));
+        }
+    return SMM_OK;
+}
+
+// Autotuner: time each candidate grid (workgroups per CU) of every persistent
+// sweep launch on this batch and keep the fastest; results are cached per
+// launch shape.  The grid only changes scheduling, never the results.
+int batch_autotune(smm_batch* B, bool fp64) {
+    smm_ctx* c = B->ctx;
+    const int f = fp64 ? 1 : 0;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    for (Group& G : B->groups) {
+        if (G.grid[f] > 0) continue;
+        auto key = std::make_tuple(G.nb, G.mreg[f], G.threads, G.lds[f], G.tasks.size(), f);
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            G.grid[f] = it->second;
+            continue;
+        }
+        int best = 0;
+        float best_ms = 1e30f;
+        for (int wpc : {1, 2, 3, 4, 6}) {
+            const int grid = std::min<int>((int)G.tasks.size(), wpc * B->ncu);
+            float ms_tot = 0;
+            bool ok = true;
+            for (int rep = 0; rep < 3 && ok; ++rep) {
+                HIPCHK(c, zero_ints(G.d_counter, 1, c->stream));
+                HIPCHK(c, hipEventRecord(e0, c->stream));
+                hipError_t e = b_sweep(fp64, G.nb, G.mreg[f], G.threads, G.lds[f], grid, B->d_args[f][1], G.d_tasks,
+                                       (int)G.tasks.size(), G.d_counter, B->d_active, c->stream);
+                if (e != hipSuccess) {
+                    ok = false;
+                    (void)hipGetLastError();
+                    break;
+                }
+                HIPCHK(c, hipEventRecord(e1, c->stream));
+                HIPCHK(c, hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) ms_tot += ms;
+            }
+            if (ok && ms_tot < best_ms) {
+                best_ms = ms_tot;
+                best = grid;
+            }
+            if (grid >= (int)G.tasks.size()) break;
+        }
+        if (best == 0)
+            return fail(c, SMM_EUNSUPPORTED, "no launch configuration fits the sweep of order " +
+                                                 std::to_string(G.nb - 1) + " (workgroup or LDS limits)");
+        G.grid[f] = best;
+        tune_cache()[key] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return SMM_OK;
+}
+
+int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
+    smm_ctx* c = B->ctx;
+    const BatchLaunch L = launch_desc(B);
+    HIPCHK(c, b_cg_start(L, tol, c->stream));
+    std::vector<double> sc(16 * (size_t)B->nprob);
+    int done_its = 0, chunk = 4;
+    while (true) {
+        HIPCHK(c, hipMemcpyAsync(sc.data(), B->d_scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        bool all = true;
+        for (int b = 0; b < B->nprob; ++b) {
+            if (!B->active[b]) continue;
+            if (sc[16 * b + 6] != 0.0) return fail(c, SMM_EBREAKDOWN, "CG breakdown in problem " + std::to_string(b));
+            if (sc[16 * b + 4] == 0.0) all = false;
+        }
+        if (all || done_its >= max_inner) break;
+        const int k = std::min(chunk, max_inner - done_its);
+        HIPCHK(c, b_cg_iterations(L, k, c->stream));
+        done_its += k;
+        chunk = std::min(chunk * 2, 64);
+    }
+    its.assign(B->nprob, 0);
+    for (int b = 0; b < B->nprob; ++b) its[b] = (int)sc[16 * b + 5];
+    return SMM_OK;
+}
+
+// The outer fixed point for every problem of the batch (eq. fixed-point),
+// each problem stopping on its own relative max-norm test.
+int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varphi0, smm_solve_info* info) {
+    smm_ctx* c = B->ctx;
+    const int np = B->nprob;
+    const bool fp64 = o.precision == SMM_FP64;
+    const bool delta = o.delta_sweeps != 0;
+    auto t0 = std::chrono::steady_clock::now();
+    int rc;
+    if ((rc = batch_autotune(B, fp64))) return rc;
+    B->active.assign(np, 1);
+    if ((rc = put(c, B->d_active, B->active.data(), sizeof(int) * np))) return rc;
+    const BatchLaunch L = launch_desc(B);
+    std::vector<int> its;
+    std::vector<smm_solve_info> inf(np, smm_solve_info{});
+    // initial guesses
+    for (int b = 0; b < np; ++b) {
+        const PerProb& q = B->pp[b];
+        const size_t bytes = sizeof(double) * B->hP[b].L;
+        HIPCHK(c, hipMemsetAsync(q.varphi_prev, 0, bytes, c->stream));
+        if (o.start == SMM_START_GIVEN && varphi0 && varphi0[b]) {
+            HIPCHK(c, hipMemcpyAsync(q.varphi, varphi0[b], bytes, hipMemcpyDefault, c->stream));
+        } else if (o.start == SMM_START_DIFFUSION) {
+            HIPCHK(c, hipMemcpyAsync(q.b, q.bfix, bytes, hipMemcpyDeviceToDevice, c->stream));
+            HIPCHK(c, hipMemsetAsync(q.x, 0, bytes, c->stream));
+        } else {
+            HIPCHK(c, hipMemsetAsync(q.varphi, 0, bytes, c->stream));
+        }
+    }
+    if (o.start == SMM_START_DIFFUSION) {
+        if ((rc = batch_cg(B, o.inner_tol, o.max_inner, its))) return rc;
+        for (int b = 0; b < np; ++b) {
+            const PerProb& q = B->pp[b];
+            HIPCHK(c, hipMemcpyAsync(q.varphi, q.x, sizeof(double) * B->hP[b].L, hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    std::vector<double> ro(2 * (size_t)np);
+    int nactive = np;
+    int it;
+    for (it = 1; it <= o.max_outer && nactive > 0; ++it) {
+        const bool first = (it == 1) || !delta;
+        HIPCHK(c, b_source(fp64, L, !first, c->stream));
+        if ((rc = batch_sweep(B, fp64, first))) return rc;
+        HIPCHK(c, b_moments(fp64, L, true, first, c->stream));
+        HIPCHK(c, b_closures_rhs(L, c->stream));
+        HIPCHK(c, b_copy_x(L, c->stream));
+        if ((rc = batch_cg(B, o.inner_tol, o.max_inner, its))) return rc;
+        HIPCHK(c, b_residual(L, B->d_rout, c->stream));
+        HIPCHK(c, hipMemcpyAsync(ro.data(), B->d_rout, sizeof(double) * ro.size(), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, b_shift(L, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        bool changed = false;
+        for (int b = 0; b < np; ++b) {
+            if (!B->active[b]) continue;
+            const double rabs = ro[2 * b], xmax = ro[2 * b + 1];
+            const double r = xmax > 0 ? rabs / xmax : (rabs == 0 ? 0.0 : INFINITY);
+            inf[b].iterations = it;
+            inf[b].residual = r;
+            inf[b].residual_abs = rabs;
+            inf[b].cg_iterations_total += its[b];
+            inf[b].cg_iterations_max = std::max(inf[b].cg_iterations_max, its[b]);
+            if (!std::isfinite(r) || r < o.outer_tol) {
+                B->active[b] = 0;
+                --nactive;
+                changed = true;
+            }
+        }
+        if (changed && nactive > 0)
+            if ((rc = put(c, B->d_active, B->active.data(), sizeof(int) * np))) return rc;
+    }
+    auto t2 = std::chrono::steady_clock::now();
+    const double tsolve = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    const double tsetup = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    int status = SMM_OK;
+    for (int b = 0; b < np; ++b) {
+        inf[b].t_total_ms = tsolve;
+        inf[b].t_setup_ms = tsetup;
+        if (!std::isfinite(inf[b].residual)) status = SMM_ENAN;
+        else if (status == SMM_OK && !(inf[b].residual < o.outer_tol)) status = SMM_ENOCONV;
+    }
+    B->active.assign(np, 1);
+    (void)put(c, B->d_active, B->active.data(), sizeof(int) * np);
+    B->last_info = inf;
+    B->have_outputs = true;
+    if (info)
+        for (int b = 0; b < np; ++b) info[b] = inf[b];
+    if (status == SMM_ENAN) return fail(c, SMM_ENAN, "non-finite residual");
+    if (status == SMM_ENOCONV) return fail(c, SMM_ENOCONV, "max_outer reached");
+    return SMM_OK;
+}
+
+int batch_outputs(smm_batch* B, int b, double* varphi, double* phi, double* J, double* T, double* beta,
+                  int on_device) {
+    smm_ctx* c = B->ctx;
+    if (!B->have_outputs) return fail(c, SMM_ESTATE, "no solve has run");
+    const PerProb& q = B->pp[b];
+    const BProb& D = B->hP[b];
+    const long L = D.L;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (varphi) HIPCHK(c, hipMemcpyAsync(varphi, q.varphi, sizeof(double) * L, k, c->stream));
+    if (phi) HIPCHK(c, hipMemcpyAsync(phi, q.mom_acc, sizeof(double) * L, k, c->stream));
+    if (J) HIPCHK(c, hipMemcpyAsync(J, q.mom_acc + L, sizeof(double) * 2 * L, k, c->stream));
+    if (T) HIPCHK(c, hipMemcpyAsync(T, q.T, sizeof(double) * 3 * L, k, c->stream));
+    if (beta && D.nbf > 0) HIPCHK(c, hipMemcpyAsync(beta, q.beta, sizeof(double) * D.nbf * D.nq, k, c->stream));
+    if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SMM_OK;
+}
+
+}  // namespace
+
+namespace smm {
+
+int batch_solve_single(smm_problem* pr, const smm_solve_opts& o, const double* varphi0, smm_solve_info* info) {
+    smm_ctx* c = pr->P.ctx;
+    if (!pr->own_batch) {
+        smm_batch* B = new smm_batch();
+        B->ctx = c;
+        B->probs = {pr};
+        B->nprob = 1;
+        int rc = batch_build(B);
+        if (rc) {
+            batch_free(B);
+            return rc;
+        }
+        pr->own_batch = B;
+    }
+    double* dv0 = nullptr;
+    if (o.start == SMM_START_GIVEN) {
+        if (!varphi0) return fail(c, SMM_EINVAL, "varphi0 required");
+        dv0 = const_cast<double*>(varphi0);  // host pointer, copied with hipMemcpyDefault
+    }
+    const double* v0[1] = {dv0};
+    return batch_solve(pr->own_batch, o, v0, info);
+}
+
+int batch_outputs_single(smm_problem* pr, double* varphi, double* phi, double* J, double* T, double* beta,
+                         int on_device) {
+    if (!pr->own_batch) return fail(pr->P.ctx, SMM_ESTATE, "no solve has run");
+    return batch_outputs(pr->own_batch, 0, varphi, phi, J, T, beta, on_device);
+}
+
+void batch_release_single(smm_problem* pr) {
+    if (pr && pr->own_batch) {
+        batch_free(pr->own_batch);
+        pr->own_batch = nullptr;
+    }
+}
+
+}  // namespace smm
+
+extern "C" {
+
+int smm_batch_create(smm_ctx* ctx, smm_problem* const* probs, int n, smm_batch** out) {
+    if (!ctx || !probs || n < 1 || !out) return SMM_EINVAL;
+    if (ctx->device < 0) return fail(ctx, SMM_ESTATE, "host-only context");
+    smm_batch* B = new smm_batch();
+    B->ctx = ctx;
+    B->probs.assign(probs, probs + n);
+    B->nprob = n;
+    for (smm_problem* p : B->probs)
+        if (!p || p->P.ctx != ctx) {
+            batch_free(B);
+            return fail(ctx, SMM_EINVAL, "problems must belong to the batch's context");
+        }
+    int rc = batch_build(B);
+    if (rc) {
+        batch_free(B);
+        return rc;
+    }
+    *out = B;
+    return SMM_OK;
+}
+
+int smm_batch_destroy(smm_batch* batch) {
+    batch_free(batch);
+    return SMM_OK;
+}
+
+int smm_batch_solve(smm_batch* batch, const smm_solve_opts* opts, const double* const* varphi0,
+                    smm_solve_info* info) {
+    if (!batch) return SMM_EINVAL;
+    smm_solve_opts o;
+    smm_default_opts(&o);
+    if (opts) o = *opts;
+    return batch_solve(batch, o, varphi0, info);
+}
+
+int smm_batch_get_outputs(smm_batch* batch, int k, double* varphi, double* phi, double* J, double* T,
+                          double* beta, int on_device) {
+    if (!batch || k < 0 || k >= batch->nprob) return SMM_EINVAL;
+    return batch_outputs(batch, k, varphi, phi, J, T, beta, on_device);
+}
+
+int smm_batch_time_sweep(smm_batch* batch, int precision, int reps, double* ms_avg) {
+    if (!batch || reps < 1 || !ms_avg) return SMM_EINVAL;
+    smm_ctx* c = batch->ctx;
+    const bool fp64 = precision == SMM_FP64;
+    int rc = batch_autotune(batch, fp64);
+    if (rc) return rc;
+    const BatchLaunch L = launch_desc(batch);
+    HIPCHK(c, b_source(fp64, L, false, c->stream));
+    if ((rc = batch_sweep(batch, fp64, true))) return rc;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int k = 0; k < reps; ++k)
+        if ((rc = batch_sweep(batch, fp64, true))) return rc;
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_avg = ms / reps;
+    return SMM_OK;
+}
+
+int smm_batch_units(const smm_batch* batch, double* units) {
+    if (!batch || !units) return SMM_EINVAL;
+    double u = 0;
+    for (const smm_problem* p : batch->probs) u += (double)p->P.ne * p->P.nd * p->P.n;
+    *units = u;
+    return SMM_OK;
+}
+
+}  // extern "C"

@@ -219,7 +219,7 @@ static inline void ref_face_point(int f, double s, double& xi, double& eta) {
     }
 }
 
-int setup_geometry(Problem& P, std::string& err) {
+int setup_geometry(Problem& P, std::string& err, bool heavy) {
     const int nb = P.nb, n = P.n, nq = P.nq, m = P.m;
     const int ne = P.ne;
     const int ncx = P.nx * m + 1;
@@ -239,17 +239,17 @@ int setup_geometry(Problem& P, std::string& err) {
 
     P.xnode.assign((size_t)ne * n * 2, 0.0);
     P.area.assign(ne, 0.0);
-    P.Mk.assign((size_t)ne * n * n, 0.0);
-    P.Gxk.assign((size_t)ne * n * n, 0.0);
-    P.Gyk.assign((size_t)ne * n * n, 0.0);
+    P.Mk.assign(heavy ? (size_t)ne * n * n : 0, 0.0);
+    P.Gxk.assign(heavy ? (size_t)ne * n * n : 0, 0.0);
+    P.Gyk.assign(heavy ? (size_t)ne * n * n : 0, 0.0);
     P.nds.assign((size_t)ne * 4 * nq * 2, 0.0);
     P.dsw.assign((size_t)ne * 4 * nq, 0.0);
     P.nhat.assign((size_t)ne * 4 * nq * 2, 0.0);
     P.xf.assign((size_t)ne * 4 * nq * 2, 0.0);
     const int Q = nq * nq;
     P.vol_wJ.assign((size_t)ne * Q, 0.0);
-    P.vol_grad.assign((size_t)ne * Q * n * 2, 0.0);
-    P.face_grad.assign((size_t)ne * 4 * nq * n * 2, 0.0);
+    P.vol_grad.assign(heavy ? (size_t)ne * Q * n * 2 : 0, 0.0);
+    P.face_grad.assign(heavy ? (size_t)ne * 4 * nq * n * 2 : 0, 0.0);
     P.vol_U.assign((size_t)Q * n, 0.0);
     P.nbr.assign((size_t)ne * 4, -1);
     P.chord.assign((size_t)ne * 4 * 2, 0.0);
@@ -315,6 +315,7 @@ int setup_geometry(Problem& P, std::string& err) {
                     const double wJ = P.wq[qa] * P.wq[qb] * det;
                     P.vol_wJ[(size_t)K * Q + Qi] = wJ;
                     areaK += wJ;
+                    if (!heavy) continue;
                     for (int b = 0; b < nb; ++b)
                         for (int a = 0; a < nb; ++a) {
                             const int k = a + nb * b;
@@ -326,7 +327,7 @@ int setup_geometry(Problem& P, std::string& err) {
                         }
                 }
             P.area[K] = areaK;
-            for (int Qi = 0; Qi < Q; ++Qi) {
+            for (int Qi = 0; heavy && Qi < Q; ++Qi) {
                 const double wJ = P.vol_wJ[(size_t)K * Q + Qi];
                 for (int r = 0; r < n; ++r) {
                     const double ur = P.vol_U[Qi * n + r];
@@ -370,6 +371,7 @@ int setup_geometry(Problem& P, std::string& err) {
                     P.xf[fo * 2 + 0] = g[0];
                     P.xf[fo * 2 + 1] = g[1];
                     const double det = g[2] * g[5] - g[4] * g[3];
+                    if (!heavy) continue;
                     // solution-basis gradients at the face point
                     for (int b = 0; b < nb; ++b)
                         for (int a = 0; a < nb; ++a) {

@@ -123,15 +123,13 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-template <typename T, int NB, int MREG, int MAXT, int B>
-__global__ __launch_bounds__(MAXT) void sweep_cart2_kernel(CartSweepArgs a) {
+template <typename T, int NB, int MREG, int B>
+__device__ __forceinline__ void sweep_cart_task(const CartSweepArgs& a, const int d, unsigned char* smem) {
     constexpr int N = NB * NB;
     constexpr int ROWW = N + 2 * NB;
-    const int d = blockIdx.x;
     const int nx = a.nx, ny = a.ny, nd = a.nd;
     const long ne = (long)nx * ny;
     const int maxlen = nx < ny ? nx : ny;
-    extern __shared__ __align__(16) unsigned char smem[];
     T* xtr = reinterpret_cast<T*>(smem);  // [2][ny][NB]
     T* ytr = xtr + 2 * ny * NB;           // [2][nx][NB]
     T* sch = ytr + 2 * nx * NB;           // [2][B][maxlen][N] source of two blocks of B levels
@@ -145,7 +143,7 @@ __global__ __launch_bounds__(MAXT) void sweep_cart2_kernel(CartSweepArgs a) {
     const T* Px = reinterpret_cast<const T*>(a.Px);
     const T* Py = reinterpret_cast<const T*>(a.Py);
     const T* S = reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0);
-    T* psi = reinterpret_cast<T*>(a.psi) + (long)d * ne * N;
+    T* psi = reinterpret_cast<T*>(a.psi) + (long)d * (a.psi_ld > 0 ? a.psi_ld : ne * N);
     if constexpr (MREG != 1) {
         for (long t = threadIdx.x; t < ne; t += blockDim.x) msh[t] = a.mat[t];
     }
@@ -322,11 +320,19 @@ __global__ __launch_bounds__(MAXT) void sweep_cart2_kernel(CartSweepArgs a) {
     }
 }
 
-constexpr int CART_BLOCK = 6;  // levels whose source is fetched one block ahead
+template <typename T, int NB, int MREG, int MAXT, int B>
+__global__ __launch_bounds__(MAXT) void sweep_cart2_kernel(CartSweepArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_cart_task<T, NB, MREG, B>(a, blockIdx.x, smem);
+}
+
+// levels whose source is fetched one block ahead (fewer for large elements,
+// to keep the two staged blocks within the LDS of one workgroup)
+__host__ __device__ constexpr int cart_block(int NB) { return NB <= 3 ? 6 : 3; }
 
 template <typename T, int NB, int MREG, int MAXT>
 static hipError_t launch_cart2_t(const CartSweepArgs& a, hipStream_t s, int threads, size_t lds) {
-    constexpr int B = CART_BLOCK;
+    constexpr int B = cart_block(NB);
     auto kfn = sweep_cart2_kernel<T, NB, MREG, MAXT, B>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
@@ -350,7 +356,7 @@ static hipError_t try_cart2(const CartSweepArgs& a, hipStream_t s) {
     int mreg = 0;
     if (a.nmat == 1 && NB <= (f64 ? 3 : 4)) mreg = 1;
     else if (a.nmat == 2 && NB <= (f64 ? 2 : 3)) mreg = 2;
-    size_t lds = sizeof(T) * (2 * (size_t)(a.nx + a.ny) * NB + 2 * (size_t)CART_BLOCK * maxlen * N);
+    size_t lds = sizeof(T) * (2 * (size_t)(a.nx + a.ny) * NB + 2 * (size_t)cart_block(NB) * maxlen * N);
     if (mreg == 0) lds += sizeof(T) * (size_t)a.nmat * N * (N + 2 * NB);
     if (mreg != 1) lds += (size_t)a.nx * a.ny;
     if (lds > 160 * 1024) return hipErrorNotSupported;
@@ -1079,6 +1085,621 @@ hipError_t launch_residual(long L, const double* xn, const double* xo, double* p
                            hipStream_t s) {
     hipLaunchKernelGGL(resid_part, dim3(nblocks), dim3(256), 0, s, L, xn, xo, part, nblocks);
     hipLaunchKernelGGL(resid_final, dim3(1), dim3(256), 0, s, part, nblocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace smm
+
+// ===========================================================================
+// Batched typed-Cartesian path
+// ===========================================================================
+namespace smm {
+
+constexpr int BT = 256;  // threads of element-block kernels
+
+__device__ __forceinline__ int bsearch_prob(const long* pre, int nprob, long idx) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= idx) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// element-block mapping: problem, element K, node i (or K = -1 when idle)
+struct EB {
+    int prob, K, i, e0;
+};
+__device__ __forceinline__ EB eb_map(const BatchLaunch& B) {
+    EB r;
+    r.prob = B.blk2p[blockIdx.x];
+    const BProb& P = B.P[r.prob];
+    const int epb = BT / P.n;
+    const int le = threadIdx.x / P.n;
+    r.i = threadIdx.x - le * P.n;
+    r.e0 = le * P.n;
+    const int K = (blockIdx.x - P.blk0) * epb + le;
+    r.K = (le < epb && K < P.ne) ? K : -1;
+    return r;
+}
+
+// ---- scattering source -----------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BT) void b_source_kernel(BatchLaunch B, int delta) {
+    const EB m = eb_map(B);
+    if (!B.active[m.prob] || m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i;
+    const double c = P.sigma_s[m.K] * (1.0 / (4.0 * 3.14159265358979323846));
+    double v = delta ? c * (P.varphi[t] - P.varphi_prev[t]) : c * P.varphi[t] + P.qsrc[t];
+    reinterpret_cast<T*>(P.S)[t] = (T)v;
+}
+
+hipError_t b_source(bool fp64, const BatchLaunch& B, bool delta, hipStream_t s) {
+    if (fp64)
+        hipLaunchKernelGGL(b_source_kernel<double>, dim3(B.nblocks), dim3(BT), 0, s, B, delta ? 1 : 0);
+    else
+        hipLaunchKernelGGL(b_source_kernel<float>, dim3(B.nblocks), dim3(BT), 0, s, B, delta ? 1 : 0);
+    return hipGetLastError();
+}
+
+__global__ void zero_ints_kernel(int* p, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0;
+}
+
+hipError_t zero_ints(int* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// ---- persistent sweep over (problem, direction) tasks ------------------------
+// Workgroups take tasks from a global counter (largest tasks first) until the
+// list is exhausted; tasks of problems that have converged are skipped.
+template <typename T, int NB, int MREG, int MAXT, int Bk>
+__global__ __launch_bounds__(MAXT) void b_sweep_kernel(const CartSweepArgs* __restrict__ args,
+                                                        const int2* __restrict__ tasks, int ntasks,
+                                                        int* __restrict__ counter,
+                                                        const int* __restrict__ active) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int tsk;
+    while (true) {
+        if (threadIdx.x == 0) tsk = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = tsk;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const int2 tk = tasks[t];
+        if (!active[tk.x]) continue;
+        sweep_cart_task<T, NB, MREG, Bk>(args[tk.x], tk.y, smem);
+        __syncthreads();
+    }
+}
+
+size_t b_sweep_lds(bool fp64, int nb, int mreg, int nx, int ny, int nmat) {
+    const size_t t = fp64 ? 8 : 4;
+    const int N = nb * nb;
+    const int maxlen = nx < ny ? nx : ny;
+    size_t lds = t * (2 * (size_t)(nx + ny) * nb + 2 * (size_t)cart_block(nb) * maxlen * N);
+    if (mreg == 0) lds += t * (size_t)nmat * N * (N + 2 * nb);
+    if (mreg != 1) lds += (size_t)nx * ny;
+    return lds;
+}
+
+template <typename T, int NB, int MREG, int MAXT>
+static hipError_t b_sweep_t(int threads, size_t lds, int grid, const CartSweepArgs* args, const int2* tasks,
+                            int ntasks, int* counter, const int* active, hipStream_t s) {
+    auto kfn = b_sweep_kernel<T, NB, MREG, MAXT, cart_block(NB)>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(threads), lds, s, args, tasks, ntasks, counter, active);
+    return hipGetLastError();
+}
+
+template <typename T, int NB>
+static hipError_t b_sweep_nb(int mreg, int threads, size_t lds, int grid, const CartSweepArgs* args,
+                             const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s) {
+    constexpr bool f64 = sizeof(T) == 8;
+    // the caller sized the LDS for `mreg`; a register variant that would spill is refused
+    if (mreg == 1 && (threads > 512 || NB > (f64 ? 3 : 4))) return hipErrorInvalidValue;
+    if (threads <= 512) {
+        if (mreg == 1) return b_sweep_t<T, NB, 1, 512>(threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        return b_sweep_t<T, NB, 0, 512>(threads, lds, grid, args, tasks, ntasks, counter, active, s);
+    }
+    if (f64 && NB >= 4) return hipErrorNotSupported;
+    return b_sweep_t<T, NB, 0, 1024>(threads, lds, grid, args, tasks, ntasks, counter, active, s);
+}
+
+hipError_t b_sweep(bool fp64, int nb, int mreg, int threads, size_t lds, int grid, const CartSweepArgs* args,
+                   const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s) {
+    if (threads > 1024 || lds > 160 * 1024) return hipErrorNotSupported;
+    switch (nb) {
+        case 2: return fp64 ? b_sweep_nb<double, 2>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_nb<float, 2>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 3: return fp64 ? b_sweep_nb<double, 3>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_nb<float, 3>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 4: return fp64 ? b_sweep_nb<double, 4>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_nb<float, 4>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 5: return fp64 ? b_sweep_nb<double, 5>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_nb<float, 5>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---- moments (matrix cores), optional FP64 accumulation ----------------------
+// Wavefront w covers 64 columns of one problem (Lpad is a multiple of 4, so a
+// lane's 4 columns are 16-byte aligned; columns >= L read the zero padding).
+template <typename T>
+__global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accumulate, int first) {
+    const int lane = threadIdx.x & 63;
+    const long w = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= B.nmw) return;
+    const int prob = bsearch_prob(B.mw0, B.nprob, w);
+    if (!B.active[prob]) return;
+    const BProb& P = B.P[prob];
+    const long col0 = (w - P.mw0) * 64;
+    const int j = lane & 15, kk = lane >> 4;
+    const long c4 = col0 + 4 * j;
+    const bool colok = c4 < P.Lpad;
+    const T* psi = reinterpret_cast<const T*>(P.psi);
+    const T* W;
+    if constexpr (sizeof(T) == 4) W = reinterpret_cast<const T*>(P.W32);
+    else W = reinterpret_cast<const T*>(P.W64);
+    const int nd = P.nd;
+    double out[4][4];
+    if constexpr (sizeof(T) == 4) {
+        v4f a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
+        for (int k = 0; k < nd; k += 4) {
+            const int dk = k + kk;
+            const float av = dk < nd ? W[j * P.ldw + dk] : 0.f;
+            v4f bv = {0.f, 0.f, 0.f, 0.f};
+            if (dk < nd && colok) bv = *reinterpret_cast<const v4f*>(psi + (long)dk * P.Lpad + c4);
+            a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[0], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[1], a1, 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[2], a2, 0, 0, 0);
+            a3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[3], a3, 0, 0, 0);
+        }
+        // FP32 layout: row 4 kk + r
+        for (int r = 0; r < 4; ++r) {
+            out[r][0] = a0[r];
+            out[r][1] = a1[r];
+            out[r][2] = a2[r];
+            out[r][3] = a3[r];
+        }
+        if (kk < 2 && colok) {
+            for (int r = 0; r < 4; ++r) {
+                const int row = 4 * kk + r;
+                for (int c = 0; c < 4; ++c) {
+                    const long col = c4 + c;
+                    if (col >= P.L) break;
+                    const long o = (long)row * P.L + col;
+                    if (accumulate) P.mom_acc[o] = (first ? 0.0 : P.mom_acc[o]) + out[r][c];
+                    P.mom[o] = out[r][c];
+                }
+            }
+        }
+    } else {
+        v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0, a2 = a0, a3 = a0;
+        for (int k = 0; k < nd; k += 4) {
+            const int dk = k + kk;
+            const double av = dk < nd ? W[j * P.ldw + dk] : 0.0;
+            v2d b01 = {0.0, 0.0}, b23 = {0.0, 0.0};
+            if (dk < nd && colok) {
+                const v2d* src = reinterpret_cast<const v2d*>(psi + (long)dk * P.Lpad + c4);
+                b01 = src[0];
+                b23 = src[1];
+            }
+            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b01[0], a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b01[1], a1, 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b23[0], a2, 0, 0, 0);
+            a3 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b23[1], a3, 0, 0, 0);
+        }
+        // FP64 layout: row kk + 4 r
+        if (colok) {
+            for (int r = 0; r < 2; ++r) {
+                const int row = kk + 4 * r;
+                const double vals[4] = {a0[r], a1[r], a2[r], a3[r]};
+                for (int c = 0; c < 4; ++c) {
+                    const long col = c4 + c;
+                    if (col >= P.L) break;
+                    const long o = (long)row * P.L + col;
+                    if (accumulate) P.mom_acc[o] = (first ? 0.0 : P.mom_acc[o]) + vals[c];
+                    P.mom[o] = vals[c];
+                }
+            }
+        }
+    }
+}
+
+hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool first, hipStream_t s) {
+    const long blocks = (B.nmw + 3) / 4;
+    if (fp64)
+        hipLaunchKernelGGL(b_moments_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, B, accumulate ? 1 : 0,
+                           first ? 1 : 0);
+    else
+        hipLaunchKernelGGL(b_moments_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, B, accumulate ? 1 : 0,
+                           first ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ---- closures and right-hand side --------------------------------------------
+// T from the moments (which array: mom_acc when accumulating, else mom -- the
+// host passes that choice through BProb.mom_acc == mom when not accumulating).
+__global__ __launch_bounds__(BT) void b_T_kernel(BatchLaunch B) {
+    const EB m = eb_map(B);
+    if (!B.active[m.prob] || m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i, L = P.L;
+    const double* mom = P.mom_acc;
+    const double phi = mom[t];
+    P.T[t] = mom[3 * L + t] - phi / 3.0;
+    P.T[L + t] = mom[4 * L + t];
+    P.T[2 * L + t] = mom[5 * L + t] - phi / 3.0;
+}
+
+__global__ __launch_bounds__(256) void b_beta_kernel(BatchLaunch B) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B.nbq) return;
+    const int prob = bsearch_prob(B.bq0, B.nprob, t);
+    if (!B.active[prob]) return;
+    const BProb& P = B.P[prob];
+    const long lt = t - P.bq0;
+    const int bf = (int)(lt / P.nq), q = (int)(lt - (long)bf * P.nq);
+    const int K = P.bK[bf], f = P.bF[bf], nb = P.nb;
+    const bool xnorm = (f == 1 || f == 3);
+    const double* mom = P.mom_acc;
+    const double* row = mom + (xnorm ? 6 : 7) * P.L;
+    const double e = xnorm ? P.eb0x : P.eb0y;
+    double v = 0.0;
+    for (int c = 0; c < nb; ++c) {
+        int k;
+        switch (f) {
+            case 0: k = c; break;
+            case 1: k = (nb - 1) + nb * c; break;
+            case 2: k = c + nb * (nb - 1); break;
+            default: k = nb * c; break;
+        }
+        const long idx = (long)K * P.n + k;
+        v += P.Lf[c * P.nq + q] * (row[idx] - e * mom[idx]);
+    }
+    P.beta[lt] = v;
+}
+
+__device__ __forceinline__ int nbr_of(const BProb& P, int K, int f) {
+    switch (f) {
+        case 0: return K - P.nx;
+        case 1: return K + 1;
+        case 2: return K + P.nx;
+        default: return K - 1;
+    }
+}
+
+// b = b_fixed + C_self T_K + sum_f C_nbr T_N - sum_{boundary f} B_f beta_f
+__global__ __launch_bounds__(BT) void b_rhs_kernel(BatchLaunch B) {
+    const EB m = eb_map(B);
+    if (!B.active[m.prob] || m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const int n = P.n, n3 = 3 * n, K = m.K, i = m.i;
+    const long L = P.L;
+    double v = P.bfix[(long)K * n + i];
+    {
+        const double* row = P.c_self + ((long)P.sid[K] * n + i) * n3;
+        for (int c = 0; c < 3; ++c) {
+            const double* tv = P.T + c * L + (long)K * n;
+            for (int j = 0; j < n; ++j) v += row[c * n + j] * tv[j];
+        }
+    }
+    for (int f = 0; f < 4; ++f) {
+        const int t = P.nid[K * 4 + f];
+        if (t >= 0) {
+            const int N = nbr_of(P, K, f);
+            const double* row = P.c_nbr + ((long)t * n + i) * n3;
+            for (int c = 0; c < 3; ++c) {
+                const double* tv = P.T + c * L + (long)N * n;
+                for (int j = 0; j < n; ++j) v += row[c * n + j] * tv[j];
+            }
+        } else {
+            const int bf = P.bface_of[K * 4 + f];
+            const double* bo = P.bop + ((long)f * n + i) * P.nq;
+            const double* be = P.beta + (long)bf * P.nq;
+            for (int q = 0; q < P.nq; ++q) v -= bo[q] * be[q];
+        }
+    }
+    P.b[(long)K * n + i] = v;
+}
+
+hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s) {
+    hipLaunchKernelGGL(b_T_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
+    if (B.nbq > 0) hipLaunchKernelGGL(b_beta_kernel, dim3((unsigned)((B.nbq + 255) / 256)), dim3(256), 0, s, B);
+    hipLaunchKernelGGL(b_rhs_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BT) void b_copy_x_kernel(BatchLaunch B) {
+    const EB m = eb_map(B);
+    if (!B.active[m.prob] || m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i;
+    P.x[t] = P.varphi[t];
+}
+
+__global__ __launch_bounds__(BT) void b_shift_kernel(BatchLaunch B) {
+    const EB m = eb_map(B);
+    if (!B.active[m.prob] || m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i;
+    P.varphi_prev[t] = P.varphi[t];
+    P.varphi[t] = P.x[t];
+}
+
+hipError_t b_copy_x(const BatchLaunch& B, hipStream_t s) {
+    hipLaunchKernelGGL(b_copy_x_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
+    return hipGetLastError();
+}
+
+hipError_t b_shift(const BatchLaunch& B, hipStream_t s) {
+    hipLaunchKernelGGL(b_shift_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
+    return hipGetLastError();
+}
+
+// ---- typed block-Jacobi PCG --------------------------------------------------
+// Per-problem scalars (P.scal): 0 rz, 1 rz_old, 2 bb, 3 rr, 4 done, 5 iterations,
+// 6 breakdown, 7 tol^2 bb, 8 alpha, 9 beta.
+__device__ __forceinline__ double b_block_sum(double v, double* red) {
+    const int t = threadIdx.x;
+    red[t] = v;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] += red[t + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double typed_row(const BProb& P, const double* x, int K, int i) {
+    const int n = P.n;
+    const double* row = P.ip_self + ((long)P.sid[K] * n + i) * n;
+    const double* xv = x + (long)K * n;
+    double v = 0.0;
+    for (int j = 0; j < n; ++j) v += row[j] * xv[j];
+    for (int f = 0; f < 4; ++f) {
+        const int t = P.nid[K * 4 + f];
+        if (t < 0) continue;
+        const double* rn = P.ip_nbr + ((long)t * n + i) * n;
+        const double* xn = x + (long)nbr_of(P, K, f) * n;
+        for (int j = 0; j < n; ++j) v += rn[j] * xn[j];
+    }
+    return v;
+}
+
+__device__ __forceinline__ bool cg_skip(const BatchLaunch& B, int prob) {
+    return !B.active[prob] || B.P[prob].scal[4] != 0.0;
+}
+
+__global__ __launch_bounds__(BT) void b_cg_init1(BatchLaunch B) {
+    const EB m = eb_map(B);
+    if (!B.active[m.prob] || m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i;
+    P.r[t] = P.b[t] - typed_row(P, P.x, m.K, m.i);
+}
+
+__global__ __launch_bounds__(BT) void b_cg_init2(BatchLaunch B) {
+    __shared__ double red[BT];
+    const EB m = eb_map(B);
+    double rz = 0, rr = 0, bb = 0;
+    if (B.active[m.prob] && m.K >= 0) {
+        const BProb& P = B.P[m.prob];
+        const int n = P.n;
+        const long t = (long)m.K * n + m.i;
+        const double* D = P.dinv + ((long)P.sid[m.K] * n + m.i) * n;
+        double z = 0;
+        for (int j = 0; j < n; ++j) z += D[j] * P.r[(long)m.K * n + j];
+        P.z[t] = z;
+        P.p[t] = z;
+        rz = P.r[t] * z;
+        rr = P.r[t] * P.r[t];
+        bb = P.b[t] * P.b[t];
+    }
+    rz = b_block_sum(rz, red);
+    rr = b_block_sum(rr, red);
+    bb = b_block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        B.part[blockIdx.x] = rz;
+        B.part[B.nblocks + blockIdx.x] = rr;
+        B.part[2 * B.nblocks + blockIdx.x] = bb;
+    }
+}
+
+// one workgroup per problem: fixed-order sums of the problem's partials
+__device__ __forceinline__ double prob_sum(const BatchLaunch& B, const BProb& P, int which, double* red) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < P.nblk; k += BT) v += B.part[which * B.nblocks + P.blk0 + k];
+    return b_block_sum(v, red);
+}
+
+__global__ __launch_bounds__(BT) void b_cg_red_init(BatchLaunch B, double tol) {
+    __shared__ double red[BT];
+    const int prob = blockIdx.x;
+    const BProb& P = B.P[prob];
+    const double rz = prob_sum(B, P, 0, red), rr = prob_sum(B, P, 1, red), bb = prob_sum(B, P, 2, red);
+    if (threadIdx.x == 0) {
+        double* s = P.scal;
+        s[0] = rz;
+        s[1] = rz;
+        s[2] = bb;
+        s[3] = rr;
+        s[7] = tol * tol * bb;
+        s[4] = (!B.active[prob] || rr <= s[7]) ? 1.0 : 0.0;
+        s[5] = 0.0;
+        s[6] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(BT) void b_cg_k1(BatchLaunch B) {
+    __shared__ double red[BT];
+    const EB m = eb_map(B);
+    if (cg_skip(B, m.prob)) return;  // block-uniform
+    const BProb& P = B.P[m.prob];
+    double pq = 0;
+    if (m.K >= 0) {
+        const long t = (long)m.K * P.n + m.i;
+        const double v = typed_row(P, P.p, m.K, m.i);
+        P.q[t] = v;
+        pq = P.p[t] * v;
+    }
+    pq = b_block_sum(pq, red);
+    if (threadIdx.x == 0) B.part[blockIdx.x] = pq;
+}
+
+__global__ __launch_bounds__(BT) void b_cg_red1(BatchLaunch B) {
+    __shared__ double red[BT];
+    const int prob = blockIdx.x;
+    if (cg_skip(B, prob)) return;
+    const BProb& P = B.P[prob];
+    const double pq = prob_sum(B, P, 0, red);
+    if (threadIdx.x == 0) {
+        double* s = P.scal;
+        if (!(pq > 0.0)) {
+            s[6] = 1.0;
+            s[4] = 1.0;
+        } else {
+            s[8] = s[0] / pq;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BT) void b_cg_k2(BatchLaunch B) {
+    __shared__ double red[BT];
+    __shared__ double rl[BT];
+    const EB m = eb_map(B);
+    if (cg_skip(B, m.prob)) return;
+    const BProb& P = B.P[m.prob];
+    const double alpha = P.scal[8];
+    const int n = P.n;
+    double rnew = 0;
+    if (m.K >= 0) {
+        const long t = (long)m.K * n + m.i;
+        P.x[t] += alpha * P.p[t];
+        rnew = P.r[t] - alpha * P.q[t];
+        P.r[t] = rnew;
+    }
+    rl[threadIdx.x] = rnew;
+    __syncthreads();
+    double rz = 0, rr = 0;
+    if (m.K >= 0) {
+        const double* D = P.dinv + ((long)P.sid[m.K] * n + m.i) * n;
+        double z = 0;
+        for (int j = 0; j < n; ++j) z += D[j] * rl[m.e0 + j];
+        P.z[(long)m.K * n + m.i] = z;
+        rz = rnew * z;
+        rr = rnew * rnew;
+    }
+    rz = b_block_sum(rz, red);
+    rr = b_block_sum(rr, red);
+    if (threadIdx.x == 0) {
+        B.part[B.nblocks + blockIdx.x] = rz;
+        B.part[2 * B.nblocks + blockIdx.x] = rr;
+    }
+}
+
+__global__ __launch_bounds__(BT) void b_cg_red2(BatchLaunch B) {
+    __shared__ double red[BT];
+    const int prob = blockIdx.x;
+    if (cg_skip(B, prob)) return;
+    const BProb& P = B.P[prob];
+    const double rzn = prob_sum(B, P, 1, red), rr = prob_sum(B, P, 2, red);
+    if (threadIdx.x == 0) {
+        double* s = P.scal;
+        s[9] = rzn / s[0];
+        s[1] = s[0];
+        s[0] = rzn;
+        s[3] = rr;
+        s[5] += 1.0;
+        if (rr <= s[7]) s[4] = 1.0;
+    }
+}
+
+__global__ __launch_bounds__(BT) void b_cg_k3(BatchLaunch B) {
+    const EB m = eb_map(B);
+    if (cg_skip(B, m.prob) || m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i;
+    P.p[t] = P.z[t] + P.scal[9] * P.p[t];
+}
+
+hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(b_cg_init1, dim3(B.nblocks), dim3(BT), 0, s, B);
+    hipLaunchKernelGGL(b_cg_init2, dim3(B.nblocks), dim3(BT), 0, s, B);
+    hipLaunchKernelGGL(b_cg_red_init, dim3(B.nprob), dim3(BT), 0, s, B, tol);
+    return hipGetLastError();
+}
+
+hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s) {
+    for (int k = 0; k < iters; ++k) {
+        hipLaunchKernelGGL(b_cg_k1, dim3(B.nblocks), dim3(BT), 0, s, B);
+        hipLaunchKernelGGL(b_cg_red1, dim3(B.nprob), dim3(BT), 0, s, B);
+        hipLaunchKernelGGL(b_cg_k2, dim3(B.nblocks), dim3(BT), 0, s, B);
+        hipLaunchKernelGGL(b_cg_red2, dim3(B.nprob), dim3(BT), 0, s, B);
+        hipLaunchKernelGGL(b_cg_k3, dim3(B.nblocks), dim3(BT), 0, s, B);
+    }
+    return hipGetLastError();
+}
+
+// ---- outer residual per problem: out[2 prob] = max|x - varphi|, out[2 prob + 1] = max|x|
+__global__ __launch_bounds__(BT) void b_resid_part(BatchLaunch B) {
+    __shared__ double r0[BT], r1[BT];
+    const EB m = eb_map(B);
+    double a = 0, b = 0;
+    if (B.active[m.prob] && m.K >= 0) {
+        const BProb& P = B.P[m.prob];
+        const long t = (long)m.K * P.n + m.i;
+        const double v = P.x[t];
+        const double dv = fabs(v - P.varphi[t]);
+        a = (dv != dv) ? dv : dv;
+        b = fabs(v);
+        if (v != v) b = v;
+    }
+    r0[threadIdx.x] = a;
+    r1[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double x0 = r0[threadIdx.x + s], x1 = r1[threadIdx.x + s];
+            r0[threadIdx.x] = (x0 > r0[threadIdx.x] || x0 != x0) ? x0 : r0[threadIdx.x];
+            r1[threadIdx.x] = (x1 > r1[threadIdx.x] || x1 != x1) ? x1 : r1[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        B.part[blockIdx.x] = r0[0];
+        B.part[B.nblocks + blockIdx.x] = r1[0];
+    }
+}
+
+__global__ __launch_bounds__(64) void b_resid_final(BatchLaunch B, double* out) {
+    const int prob = blockIdx.x * 64 + threadIdx.x;
+    if (prob >= B.nprob) return;
+    const BProb& P = B.P[prob];
+    double a = 0, b = 0;
+    for (int k = 0; k < P.nblk; ++k) {
+        const double x0 = B.part[P.blk0 + k], x1 = B.part[B.nblocks + P.blk0 + k];
+        a = (x0 > a || x0 != x0) ? x0 : a;
+        b = (x1 > b || x1 != x1) ? x1 : b;
+    }
+    out[2 * prob] = a;
+    out[2 * prob + 1] = b;
+}
+
+hipError_t b_residual(const BatchLaunch& B, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(b_resid_part, dim3(B.nblocks), dim3(BT), 0, s, B);
+    hipLaunchKernelGGL(b_resid_final, dim3((B.nprob + 63) / 64), dim3(64), 0, s, B, out);
     return hipGetLastError();
 }
 

@@ -18,8 +18,9 @@ struct CartSweepArgs {
     const double* omega;         // [nd][3] (signs select the quadrant)
     const void* bx;              // [nd][ny][nb] boundary traces (or null)
     const void* by;              // [nd][nx][nb]
-    void* psi;                   // [nd][ne][n]
+    void* psi;                   // [nd][psi_ld]
     int variant;                 // 0 automatic, 1 element-row kernel only
+    long psi_ld;                 // row stride of psi (>= ne * n); 0 means ne * n
 };
 hipError_t launch_sweep_cart(bool fp64, const CartSweepArgs& a, hipStream_t s);
 
@@ -90,5 +91,56 @@ hipError_t cg_iterations(const CgState& c, int iters, double tol, hipStream_t s)
 // residual: out[0] = max|x_new - x_old|, out[1] = max|x_new|
 hipError_t launch_residual(long L, const double* xn, const double* xo, double* part, int nblocks,
                            double* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched (typed Cartesian) path.  One descriptor per problem; all pointers
+// are device pointers.  Element-block kernels use blocks of
+// epb = 256 / n whole elements, mapped to problems by blk2p.
+// ---------------------------------------------------------------------------
+struct BProb {
+    int ne, n, nb, nq, nbf, nd, nx, ldw;
+    long L;                        // ne * n
+    long Lpad;                     // psi row stride (L rounded up to a multiple of 4)
+    double eb0x, eb0y;
+    int blk0, nblk;                // element-block range
+    long bq0;                      // first flat boundary-point index
+    long mw0;                      // first moments wavefront
+    double *varphi, *varphi_prev, *x, *b, *r, *z, *p, *q;   // [L]
+    const double *bfix, *qsrc, *sigma_s;                    // [L], [L], [ne]
+    double *mom, *mom_acc, *T, *beta;                       // [8L], [8L], [3L], [nbf*nq]
+    const int *sid, *nid, *bface_of, *bK, *bF;              // [ne], [4ne], [4ne], [nbf], [nbf]
+    const double *ip_self, *ip_nbr, *dinv, *c_self, *c_nbr, *bop, *Lf;
+    double* scal;                                           // [16] CG scalars
+    void* S;                                                // [L] (sweep precision)
+    void* psi;                                              // [nd][Lpad]
+    const double* W64;                                      // [16][ldw] moment weights
+    const float* W32;                                       // [16][ldw]
+};
+
+struct BatchLaunch {
+    const BProb* P;                // device array [nprob]
+    int nprob;
+    const int* blk2p;              // [nblocks]
+    int nblocks;
+    const int* active;             // [nprob] outer iteration still running
+    double* part;                  // [3][nblocks]
+    long nbq;                      // total boundary points
+    long nmw;                      // total moments wavefronts
+    const long* bq0;               // [nprob] prefix (device copy)
+    const long* mw0;               // [nprob] prefix (device copy)
+};
+
+hipError_t b_source(bool fp64, const BatchLaunch& B, bool delta, hipStream_t s);
+hipError_t b_sweep(bool fp64, int nb, int mreg, int threads, size_t lds, int grid, const CartSweepArgs* args,
+                   const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s);
+size_t b_sweep_lds(bool fp64, int nb, int mreg, int nx, int ny, int nmat);
+hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool first, hipStream_t s);
+hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s);
+hipError_t b_copy_x(const BatchLaunch& B, hipStream_t s);               // x = varphi
+hipError_t b_shift(const BatchLaunch& B, hipStream_t s);                // varphi_prev = varphi, varphi = x
+hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s);
+hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s);
+hipError_t b_residual(const BatchLaunch& B, double* out, hipStream_t s);   // out[2*nprob]
+hipError_t zero_ints(int* p, int n, hipStream_t s);
 
 }  // namespace smm

@@ -93,11 +93,25 @@ struct Problem {
     bool lhs_ready = false;
     bool rhs_fixed_ready = false;
 
+    bool heavy_ready = false;          // per-element quadrature data present
+    bool graph_ready = false;          // per-direction sweep graph present
+
+    // typed moment-system blocks (uniform Cartesian meshes, isotropic source)
+    bool typed_ready = false;
+    int nself = 0, nnbrt = 0;
+    std::vector<int> sid;              // [ne] self-block type
+    std::vector<int> nid;              // [ne][4] neighbour-block type (-1 boundary)
+    std::vector<double> t_ip_self, t_ip_nbr, t_dinv;   // [nself|nnbrt][n][n]
+    std::vector<double> t_c_self, t_c_nbr;             // [nself|nnbrt][n][3n]
+    std::vector<double> t_bop;                         // [4][n][nq]
+    std::vector<double> t_bfix;                        // [ne][n]
+
     // device state (api.hip)
     void* dev = nullptr;
 };
 
-int setup_geometry(Problem& P, std::string& err);
+int setup_geometry(Problem& P, std::string& err, bool heavy);
+int ensure_heavy(Problem& P);   // per-element quadrature data and sweep graph, on demand
 void setup_cartesian_operators(Problem& P);
 void setup_sweep_graph(Problem& P);
 void assemble_ip(Problem& P);
@@ -105,5 +119,7 @@ void assemble_rhs_fixed(Problem& P);
 void assemble_correction_operator(Problem& P);
 void cartesian_boundary_traces(const Problem& P, std::vector<double>& bx, std::vector<double>& by);
 int lu_invert(int n, double* A);  // in-place inverse, partial pivoting; returns 0 on success
+bool typed_applicable(const Problem& P);
+int build_typed_blocks(Problem& P, std::string& err);
 
 }  // namespace smm

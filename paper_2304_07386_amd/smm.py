@@ -27,7 +27,9 @@ EXPORTED = [
     "smm_problem_destroy", "smm_get_dims", "smm_get_quadrature", "smm_get_nodes", "smm_get_bface_points",
     "smm_set_materials", "smm_set_source", "smm_set_inflow", "smm_default_opts", "smm_solve",
     "smm_get_outputs", "smm_apply_sweep", "smm_apply_moments", "smm_apply_G", "smm_debug_ip_dense",
-    "smm_set_sweep_path", "smm_time_sweep",
+    "smm_set_sweep_path", "smm_time_sweep", "smm_debug_typed_dense", "smm_debug_corr_dense",
+    "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
+    "smm_batch_time_sweep", "smm_batch_units",
 ]
 
 
@@ -43,13 +45,14 @@ class smm_mesh_desc(C.Structure):
 
 class smm_problem_dims(C.Structure):
     _fields_ = [("n_elem", C.c_int), ("n_node", C.c_int), ("n_dir", C.c_int), ("n_bface", C.c_int),
-                ("nq", C.c_int), ("cartesian", C.c_int), ("n_material", C.c_int), ("n_levels", C.c_int)]
+                ("nq", C.c_int), ("cartesian", C.c_int), ("n_material", C.c_int), ("n_levels", C.c_int),
+                ("n_self_types", C.c_int), ("n_nbr_types", C.c_int)]
 
 
 class smm_solve_opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("outer_tol", C.c_double), ("max_outer", C.c_int),
                 ("inner_tol", C.c_double), ("max_inner", C.c_int), ("start", C.c_int),
-                ("delta_sweeps", C.c_int), ("use_graph", C.c_int)]
+                ("delta_sweeps", C.c_int), ("use_graph", C.c_int), ("moment_path", C.c_int)]
 
 
 class smm_solve_info(C.Structure):
@@ -97,6 +100,14 @@ def load_library(path: str = LIB_PATH):
         "smm_debug_ip_dense": (ip, [vp, vp, vp]),
         "smm_set_sweep_path": (ip, [vp, ip]),
         "smm_time_sweep": (ip, [vp, ip, ip, dp]),
+        "smm_debug_typed_dense": (ip, [vp, vp, vp, vp]),
+        "smm_debug_corr_dense": (ip, [vp, vp]),
+        "smm_batch_create": (ip, [vp, C.POINTER(vp), ip, C.POINTER(vp)]),
+        "smm_batch_destroy": (ip, [vp]),
+        "smm_batch_solve": (ip, [vp, C.POINTER(smm_solve_opts), C.POINTER(vp), C.POINTER(smm_solve_info)]),
+        "smm_batch_get_outputs": (ip, [vp, ip, vp, vp, vp, vp, vp, ip]),
+        "smm_batch_time_sweep": (ip, [vp, ip, ip, dp]),
+        "smm_batch_units": (ip, [vp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -294,3 +305,82 @@ def smm_time_sweep(prob: Problem, precision: int, reps: int) -> float:
     ms = C.c_double()
     _check(load_library().smm_time_sweep(prob.handle, precision, reps, C.byref(ms)), prob.ctx)
     return ms.value
+
+
+def smm_debug_typed_dense(prob: Problem):
+    N = prob.n_elem * prob.n_node
+    A = np.zeros((N, N))
+    Cm = np.zeros((N, 3 * N))
+    b = np.zeros(N)
+    _check(load_library().smm_debug_typed_dense(prob.handle, _ptr(A), _ptr(Cm), _ptr(b)), prob.ctx)
+    return A, Cm, b
+
+
+def smm_debug_corr_dense(prob: Problem):
+    N = prob.n_elem * prob.n_node
+    Cm = np.zeros((N, 3 * N))
+    _check(load_library().smm_debug_corr_dense(prob.handle, _ptr(Cm)), prob.ctx)
+    return Cm
+
+
+class Batch:
+    def __init__(self, ctx, handle, probs):
+        self.ctx = ctx
+        self.handle = handle
+        self.probs = list(probs)
+
+    @property
+    def n(self):
+        return len(self.probs)
+
+
+def smm_batch_create(ctx: Context, probs) -> Batch:
+    arr = (C.c_void_p * len(probs))(*[p.handle.value for p in probs])
+    h = C.c_void_p()
+    _check(load_library().smm_batch_create(ctx.handle, arr, len(probs), C.byref(h)), ctx)
+    return Batch(ctx, h, probs)
+
+
+def smm_batch_destroy(batch: Batch):
+    load_library().smm_batch_destroy(batch.handle)
+
+
+def smm_batch_solve(batch: Batch, opts: smm_solve_opts | None = None, varphi0=None, raise_on_noconv=True):
+    """varphi0: None or a list of per-problem host arrays / device tensors (None entries allowed).
+    Returns (status, list of info dicts)."""
+    infos = (smm_solve_info * batch.n)()
+    keep = []
+    v0 = None
+    if varphi0 is not None:
+        ptrs = []
+        for a in varphi0:
+            if a is None:
+                ptrs.append(None)
+            elif isinstance(a, np.ndarray):
+                a = _f64(a)
+                keep.append(a)
+                ptrs.append(a.ctypes.data)
+            else:
+                ptrs.append(a.data_ptr())
+        v0 = (C.c_void_p * batch.n)(*ptrs)
+    rc = load_library().smm_batch_solve(batch.handle, C.byref(opts) if opts is not None else None, v0, infos)
+    if not (rc == SMM_ENOCONV and not raise_on_noconv):
+        _check(rc, batch.ctx)
+    return rc, [infos[k].as_dict() for k in range(batch.n)]
+
+
+def smm_batch_get_outputs(batch: Batch, k: int, varphi=None, phi=None, J=None, T=None, beta=None, on_device=False):
+    _check(load_library().smm_batch_get_outputs(batch.handle, k, _ptr(varphi), _ptr(phi), _ptr(J), _ptr(T),
+                                                _ptr(beta), 1 if on_device else 0), batch.ctx)
+
+
+def smm_batch_time_sweep(batch: Batch, precision: int, reps: int) -> float:
+    ms = C.c_double()
+    _check(load_library().smm_batch_time_sweep(batch.handle, precision, reps, C.byref(ms)), batch.ctx)
+    return ms.value
+
+
+def smm_batch_units(batch: Batch) -> float:
+    u = C.c_double()
+    _check(load_library().smm_batch_units(batch.handle, C.byref(u)), batch.ctx)
+    return u.value

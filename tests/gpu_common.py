@@ -22,7 +22,9 @@ def announce(msg):
 
 def make_pair(L, ctx, wl):
     """Oracle problem and HIP problem on identical inputs (the nodal source
-    and inflow tables are built once, by the oracle, and handed to both)."""
+    and inflow tables are built once, by the oracle, and handed to both; an
+    isotropic face inflow keeps its compact layout, with the same value)."""
     pr = osmm.make_problem(wl)
-    p = L.problem_from_workload(ctx, wl, q=pr.q, psibar=pr.psibar)
+    iso_inflow = isinstance(wl.inflow, tuple) and wl.inflow[0] == "iso"
+    p = L.problem_from_workload(ctx, wl, q=pr.q, psibar=None if iso_inflow else pr.psibar)
     return pr, p
