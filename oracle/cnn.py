@@ -85,24 +85,27 @@ def forward(params, x: np.ndarray, emulate_bf16: bool = True):
     return a, cache
 
 
-def loss_mse(y: np.ndarray, t: np.ndarray, mask: np.ndarray | None = None):
-    """Mean squared error over all entries (optionally masked channels)."""
+def loss_mse(y: np.ndarray, t: np.ndarray, chan_weight: np.ndarray | None = None):
+    """Weighted mean squared error: mean over all entries of w_o (y - t)^2,
+    w_o a per-output-channel weight (1 if None).  Returns (loss, d loss/dy)."""
     d = y - t
-    if mask is not None:
-        d = d * mask
-    return float(np.mean(d * d)), 2.0 * d / d.size
+    w = np.ones(y.shape[-1]) if chan_weight is None else np.asarray(chan_weight, float)
+    return float(np.mean(w * d * d)), 2.0 * w * d / d.size
 
 
 def backward(params, cache, gy: np.ndarray, emulate_bf16: bool = True):
-    """Parameter gradients [(gw, gb)] given d loss / d output."""
+    """Parameter gradients [(gw, gb)] given d loss / d output.  The output
+    gradient is rounded to bfloat16 like every gradient fed between layers;
+    the ReLU derivative is 1 where the stored (rounded) activation is
+    positive."""
     r = bf16 if emulate_bf16 else (lambda a: a)
     grads = [None] * len(params)
-    g = gy
+    g = r(gy)
     for k in range(len(params) - 1, -1, -1):
         w, b = params[k]
         a, z = cache[k]
         if k < len(params) - 1:
-            g = g * (z > 0.0)
+            g = g * (cache[k + 1][0] > 0.0)
         gx, gw, gb = conv3x3_backward(a, r(w), g)
         grads[k] = (gw, gb)
         g = r(gx)

@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -24,17 +25,19 @@ def _run(cmd):
 def build(verbose: bool = True) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src, flags in (
+    units = (
         ("host_setup.cpp", ["-x", "hip", *DEVICE_FLAGS, "-ffp-contract=off"]),
         ("api.cpp", ["-x", "hip", *DEVICE_FLAGS]),
         ("typed.cpp", ["-x", "hip", *DEVICE_FLAGS, "-ffp-contract=off"]),
         ("batch.cpp", ["-x", "hip", *DEVICE_FLAGS]),
+        ("cnn.cpp", ["-x", "hip", *DEVICE_FLAGS]),
         ("kernels.hip", DEVICE_FLAGS),
-    ):
-        obj = os.path.join(objdir, src + ".o")
-        _run([HIPCC, *COMMON, *flags, "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        ("cnn_kernels.hip", DEVICE_FLAGS),
+    )
+    objs = [os.path.join(objdir, src + ".o") for src, _ in units]
+    cmds = [[HIPCC, *COMMON, *flags, "-c", os.path.join(CSRC, src), "-o", obj] for (src, flags), obj in zip(units, objs)]
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+        list(ex.map(_run, cmds))
     tmp = OUT + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp])
     os.replace(tmp, OUT)

@@ -106,7 +106,7 @@ int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_or
 }
 
 static void dev_free(Dev& D) {
-    for (void* ptr : D.allocs) hipFree(ptr);
+    for (void* ptr : D.allocs) (void)hipFree(ptr);
     D.allocs.clear();
     D = Dev();
 }
@@ -575,6 +575,8 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     smm_ctx* c = P.ctx;
     if (c->device < 0) return fail(c, SMM_ESTATE, "host-only context");
     if (!P.have_mat) return fail(c, SMM_ESTATE, "materials not set");
+    if (o.start < SMM_START_ZERO || o.start > SMM_START_GIVEN)
+        return fail(c, SMM_EINVAL, "smm_solve: start must be ZERO, DIFFUSION or GIVEN (the learned start needs a batch)");
     if (o.moment_path == 0 && typed_applicable(P) && D.force_general != 1) {
         const int r = batch_solve_single(prob, o, varphi0, info);
         D.last_typed = (r == SMM_OK || r == SMM_ENOCONV);
@@ -802,8 +804,8 @@ int smm_time_sweep(smm_problem* prob, int precision, int reps, double* ms_avg) {
     HIPCHK(c, hipEventSynchronize(e1));
     float ms = 0;
     HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     (void)L;
     *ms_avg = ms / reps;
     return SMM_OK;

@@ -20,7 +20,9 @@
 #include <numeric>
 #include <tuple>
 
+#include "../../include/smm_cnn.h"
 #include "api_internal.hpp"
+#include "cnn_internal.hpp"
 
 namespace smm {
 int ensure_typed(smm_problem* pr);
@@ -42,6 +44,8 @@ struct PerProb {
     double *Pm64, *Px64, *Py64, *bx64, *by64;
     float *Pm32, *Px32, *Py32, *bx32, *by32;
     uint8_t* mat;
+    double* vdiff;
+    float* feat0;
 };
 
 struct Group {
@@ -53,6 +57,16 @@ struct Group {
     int2* d_tasks = nullptr;
     int* d_counter = nullptr;
 };
+
+// [blocks][rows][cols] row-major -> [blocks][cols][rows]
+std::vector<double> col_major(const std::vector<double>& a, int rows, int cols) {
+    std::vector<double> t(a.size());
+    const size_t bs = (size_t)rows * cols;
+    for (size_t b = 0; b < a.size() / bs; ++b)
+        for (int i = 0; i < rows; ++i)
+            for (int j = 0; j < cols; ++j) t[b * bs + (size_t)j * rows + i] = a[b * bs + (size_t)i * cols + j];
+    return t;
+}
 
 struct Pool {
     struct Req {
@@ -102,6 +116,12 @@ struct smm_batch {
     std::vector<smm_solve_info> last_info;
     bool have_outputs = false;
     int ncu = 256;
+    // learned warm start
+    smm_cnn* ws_net = nullptr;
+    bool have_diff = false;
+    std::vector<int> ws_used;
+    float *d_wsx = nullptr, *d_wsy = nullptr;
+    int* d_wsflag = nullptr;
 };
 
 namespace {
@@ -131,7 +151,8 @@ std::vector<float> f32(const std::vector<double>& v) {
 int check_desc(smm_ctx* c, const BProb& D, int b) {
     const void* ptrs[] = {D.varphi, D.varphi_prev, D.x, D.b, D.r, D.z, D.p, D.q, D.bfix, D.qsrc, D.sigma_s,
                           D.mom, D.mom_acc, D.T, D.beta, D.sid, D.nid, D.bface_of, D.bK, D.bF, D.ip_self,
-                          D.ip_nbr, D.dinv, D.c_self, D.c_nbr, D.bop, D.Lf, D.scal, D.S, D.psi, D.W64, D.W32};
+                          D.ip_nbr, D.dinv, D.c_self, D.c_nbr, D.bop, D.Lf, D.scal, D.S, D.psi, D.W64, D.W32,
+                          D.vdiff, D.feat0};
     for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k)
         if (!ptrs[k])
             return fail(c, SMM_EHIP, "batch descriptor " + std::to_string(b) + " field " + std::to_string(k) +
@@ -155,6 +176,8 @@ int put(smm_ctx* c, void* dst, const void* src, size_t bytes) {
 void batch_free(smm_batch* B) {
     if (!B) return;
     if (B->pool) (void)hipFree(B->pool);
+    for (void* p : {(void*)B->d_wsx, (void*)B->d_wsy, (void*)B->d_wsflag})
+        if (p) (void)hipFree(p);
     for (auto& s : B->side)
         if (s) (void)hipStreamDestroy(s);
     if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
@@ -219,6 +242,8 @@ int batch_build(smm_batch* B) {
         pool.req(&q.bx32, sizeof(float) * (size_t)P.nd * P.ny * P.nb);
         pool.req(&q.by32, sizeof(float) * (size_t)P.nd * P.nx * P.nb);
         pool.req(&q.mat, ne);
+        pool.req(&q.vdiff, sizeof(double) * L);
+        pool.req(&q.feat0, sizeof(float) * 4 * ne);
         // element blocks
         const int epb = 256 / P.n;
         const int nblk = (P.ne + epb - 1) / epb;
@@ -310,6 +335,25 @@ int batch_build(smm_batch* B) {
             const void* s;
             size_t n;
         };
+        // typed blocks go to the device column-major (lanes of one element read
+        // consecutive rows of a column)
+        const std::vector<double> ip_self_t = col_major(P.t_ip_self, P.n, P.n), ip_nbr_t = col_major(P.t_ip_nbr, P.n, P.n),
+                                  dinv_t = col_major(P.t_dinv, P.n, P.n), c_self_t = col_major(P.t_c_self, P.n, 3 * P.n),
+                                  c_nbr_t = col_major(P.t_c_nbr, P.n, 3 * P.n), bop_t = col_major(P.t_bop, P.n, P.nq);
+        // warm-start features per element: log10 sigma_t, sigma_s / sigma_t,
+        // element mean of q, distance of the element centre to the boundary
+        std::vector<float> feat0((size_t)4 * P.ne);
+        for (int K = 0; K < P.ne; ++K) {
+            const int ex = K % P.nx, ey = K / P.nx;
+            double qm = 0;
+            for (int j = 0; j < P.n; ++j) qm += P.q[(size_t)K * P.n + j];
+            const double d = std::min(std::min((ex + 0.5) * P.hx, (P.nx - ex - 0.5) * P.hx),
+                                      std::min((ey + 0.5) * P.hy, (P.ny - ey - 0.5) * P.hy));
+            feat0[4 * K] = (float)std::log10(P.sigma_t[K]);
+            feat0[4 * K + 1] = (float)(P.sigma_s[K] / P.sigma_t[K]);
+            feat0[4 * K + 2] = (float)(qm / P.n);
+            feat0[4 * K + 3] = (float)d;
+        }
         const std::vector<float> W32 = f32(W), Pm32 = f32(P.Pm), Px32 = f32(P.Px), Py32 = f32(P.Py), bx32 = f32(bx),
                                  by32 = f32(by);
         const U ups[] = {
@@ -321,12 +365,12 @@ int batch_build(smm_batch* B) {
             {q.bface_of, P.bface_of.data(), sizeof(int) * 4 * P.ne},
             {q.bK, P.bface_K.data(), sizeof(int) * P.nbf},
             {q.bF, P.bface_f.data(), sizeof(int) * P.nbf},
-            {q.ip_self, P.t_ip_self.data(), sizeof(double) * P.t_ip_self.size()},
-            {q.ip_nbr, P.t_ip_nbr.data(), sizeof(double) * P.t_ip_nbr.size()},
-            {q.dinv, P.t_dinv.data(), sizeof(double) * P.t_dinv.size()},
-            {q.c_self, P.t_c_self.data(), sizeof(double) * P.t_c_self.size()},
-            {q.c_nbr, P.t_c_nbr.data(), sizeof(double) * P.t_c_nbr.size()},
-            {q.bop, P.t_bop.data(), sizeof(double) * P.t_bop.size()},
+            {q.ip_self, ip_self_t.data(), sizeof(double) * ip_self_t.size()},
+            {q.ip_nbr, ip_nbr_t.data(), sizeof(double) * ip_nbr_t.size()},
+            {q.dinv, dinv_t.data(), sizeof(double) * dinv_t.size()},
+            {q.c_self, c_self_t.data(), sizeof(double) * c_self_t.size()},
+            {q.c_nbr, c_nbr_t.data(), sizeof(double) * c_nbr_t.size()},
+            {q.bop, bop_t.data(), sizeof(double) * bop_t.size()},
             {q.Lf, P.Lf.data(), sizeof(double) * P.Lf.size()},
             {q.W64, W.data(), sizeof(double) * W.size()},
             {q.W32, W32.data(), sizeof(float) * W32.size()},
@@ -342,6 +386,7 @@ int batch_build(smm_batch* B) {
             {q.bx32, bx32.data(), sizeof(float) * bx32.size()},
             {q.by32, by32.data(), sizeof(float) * by32.size()},
             {q.mat, P.mat_of.data(), P.mat_of.size()},
+            {q.feat0, feat0.data(), sizeof(float) * feat0.size()},
         };
         for (const U& u : ups)
             if ((rc = put(c, u.d, u.s, u.n))) return rc;
@@ -358,6 +403,7 @@ int batch_build(smm_batch* B) {
         D.scal = B->d_scal + 16 * b;
         D.S = q.S; D.psi = q.psi;
         D.W64 = q.W64; D.W32 = q.W32;
+        D.vdiff = q.vdiff; D.feat0 = q.feat0; D.hxhy = P.hx * P.hy;
         if ((rc = check_desc(c, D, b))) return rc;
         for (int f = 0; f < 2; ++f)
             for (int g = 0; g < 2; ++g) {
@@ -509,6 +555,112 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
     return SMM_OK;
 }
 
+// Warm start: every problem must share nx, ny and the order p.
+int ws_dims(smm_batch* B, int* nf, int* nt, int* ny, int* nx) {
+    const Problem& P0 = B->probs[0]->P;
+    for (const smm_problem* pr : B->probs)
+        if (pr->P.nx != P0.nx || pr->P.ny != P0.ny || pr->P.n != P0.n)
+            return fail(B->ctx, SMM_EUNSUPPORTED, "warm start needs one mesh size and order for the whole batch");
+    *nf = 5 + P0.n;
+    *nt = 2 * P0.n;
+    *ny = P0.ny;
+    *nx = P0.nx;
+    return SMM_OK;
+}
+
+// varphi_D: the moment system with zero correction source, kept per problem.
+int batch_diffusion(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
+    smm_ctx* c = B->ctx;
+    for (int b = 0; b < B->nprob; ++b) {
+        const PerProb& q = B->pp[b];
+        const size_t bytes = sizeof(double) * B->hP[b].L;
+        HIPCHK(c, hipMemcpyAsync(q.b, q.bfix, bytes, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemsetAsync(q.x, 0, bytes, c->stream));
+    }
+    int rc;
+    if ((rc = batch_cg(B, tol, max_inner, its))) return rc;
+    HIPCHK(c, b_ws_stage(launch_desc(B), 3, nullptr, c->stream));
+    B->have_diff = true;
+    return SMM_OK;
+}
+
+// First moment-system residual of the start held in varphi: one sweep, the
+// moments, closures and right-hand side b(varphi), then ||b - A varphi|| / ||b||.
+int start_residuals(smm_batch* B, bool fp64, std::vector<double>& res, std::vector<double>& sc) {
+    smm_ctx* c = B->ctx;
+    const BatchLaunch L = launch_desc(B);
+    int rc;
+    HIPCHK(c, b_source(fp64, L, false, c->stream));
+    if ((rc = batch_sweep(B, fp64, true))) return rc;
+    HIPCHK(c, b_moments(fp64, L, true, true, c->stream));
+    HIPCHK(c, b_closures_rhs(L, c->stream));
+    HIPCHK(c, b_copy_x(L, c->stream));
+    HIPCHK(c, b_cg_start(L, 0.0, c->stream));
+    sc.resize(16 * (size_t)B->nprob);
+    HIPCHK(c, hipMemcpyAsync(sc.data(), B->d_scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    res.resize(B->nprob);
+    for (int b = 0; b < B->nprob; ++b) {
+        const double rr = sc[16 * b + 3], bb = sc[16 * b + 2];
+        res[b] = bb > 0 ? std::sqrt(rr / bb) : INFINITY;
+    }
+    return SMM_OK;
+}
+
+// Learned start: the network predicts, from the features of the diffusion
+// start, the nodal flux correction and correction source; the candidate is the
+// moment system solved with the predicted source (CG started from the
+// predicted flux).  Each problem keeps the candidate (learned or diffusion)
+// with the smaller first moment-system residual.  Adds the CG iterations spent.
+int learned_start(smm_batch* B, const smm_solve_opts& o, std::vector<int>& cg_its) {
+    smm_ctx* c = B->ctx;
+    smm_cnn* net = B->ws_net;
+    const int np = B->nprob;
+    if (!net) return fail(c, SMM_ESTATE, "SMM_START_LEARNED without smm_batch_set_warmstart");
+    int nf, nt, ny, nx, rc;
+    if ((rc = ws_dims(B, &nf, &nt, &ny, &nx))) return rc;
+    if (net->ctx != c || net->ch[0] != nf || net->ch[net->L] != nt || net->H != ny || net->W != nx)
+        return fail(c, SMM_EINVAL, "warm-start network does not match the batch");
+    const long ne = (long)nx * ny;
+    if (!B->d_wsx) {
+        if (hipMalloc((void**)&B->d_wsx, sizeof(float) * np * ne * nf) != hipSuccess ||
+            hipMalloc((void**)&B->d_wsy, sizeof(float) * np * ne * nt) != hipSuccess ||
+            hipMalloc((void**)&B->d_wsflag, sizeof(int) * np) != hipSuccess)
+            return fail(c, SMM_ENOMEM, "warm-start buffers");
+    }
+    const bool fp64 = o.precision == SMM_FP64;
+    std::vector<int> its;
+    if ((rc = batch_diffusion(B, o.inner_tol, o.max_inner, its))) return rc;
+    for (int b = 0; b < np; ++b) cg_its[b] += its[b];
+    const BatchLaunch L = launch_desc(B);
+    HIPCHK(c, hipMemsetAsync(B->d_scal, 0, sizeof(double) * 16 * np, c->stream));
+    HIPCHK(c, b_ws_features(L, 0, np, B->d_wsx, nf, c->stream));
+    for (int first = 0; first < np; first += net->maxB) {
+        const int cnt = std::min(net->maxB, np - first);
+        if ((rc = cnn_forward_dev(net, B->d_wsx + first * ne * nf, cnt, nullptr, cnt, B->d_wsy + first * ne * nt)))
+            return rc;
+    }
+    HIPCHK(c, b_ws_apply(L, B->d_wsy, nt, c->stream));
+    if ((rc = batch_cg(B, o.inner_tol, o.max_inner, its))) return rc;
+    for (int b = 0; b < np; ++b) cg_its[b] += its[b];
+    std::vector<double> rl, rd, sc;
+    HIPCHK(c, b_ws_stage(L, 0, nullptr, c->stream));
+    if ((rc = start_residuals(B, fp64, rl, sc))) return rc;
+    std::vector<int> bad(np);
+    for (int b = 0; b < np; ++b) bad[b] = sc[16 * b + 11] != 0.0;
+    HIPCHK(c, b_ws_stage(L, 1, nullptr, c->stream));
+    if ((rc = start_residuals(B, fp64, rd, sc))) return rc;
+    std::vector<int> flag(np);
+    B->ws_used.assign(np, 0);
+    for (int b = 0; b < np; ++b) {
+        flag[b] = bad[b] || !(rl[b] < rd[b]);
+        B->ws_used[b] = !flag[b];
+    }
+    if ((rc = put(c, B->d_wsflag, flag.data(), sizeof(int) * np))) return rc;
+    HIPCHK(c, b_ws_stage(L, 2, B->d_wsflag, c->stream));
+    return SMM_OK;
+}
+
 // The outer fixed point for every problem of the batch (eq. fixed-point),
 // each problem stopping on its own relative max-norm test.
 int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varphi0, smm_solve_info* info) {
@@ -518,8 +670,11 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     const bool delta = o.delta_sweeps != 0;
     auto t0 = std::chrono::steady_clock::now();
     int rc;
+    if (o.start < SMM_START_ZERO || o.start > SMM_START_LEARNED)
+        return fail(c, SMM_EINVAL, "smm_batch_solve: unknown start mode");
     if ((rc = batch_autotune(B, fp64))) return rc;
     B->active.assign(np, 1);
+    B->ws_used.assign(np, 0);
     if ((rc = put(c, B->d_active, B->active.data(), sizeof(int) * np))) return rc;
     const BatchLaunch L = launch_desc(B);
     std::vector<int> its;
@@ -538,13 +693,18 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
             HIPCHK(c, hipMemsetAsync(q.varphi, 0, bytes, c->stream));
         }
     }
+    std::vector<int> start_its(np, 0);
     if (o.start == SMM_START_DIFFUSION) {
         if ((rc = batch_cg(B, o.inner_tol, o.max_inner, its))) return rc;
         for (int b = 0; b < np; ++b) {
             const PerProb& q = B->pp[b];
             HIPCHK(c, hipMemcpyAsync(q.varphi, q.x, sizeof(double) * B->hP[b].L, hipMemcpyDeviceToDevice, c->stream));
+            start_its[b] = its[b];
         }
+    } else if (o.start == SMM_START_LEARNED) {
+        if ((rc = learned_start(B, o, start_its))) return rc;
     }
+    for (int b = 0; b < np; ++b) inf[b].cg_iterations_total = start_its[b];
     auto t1 = std::chrono::steady_clock::now();
     std::vector<double> ro(2 * (size_t)np);
     int nactive = np;
@@ -585,7 +745,7 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     const double tsetup = std::chrono::duration<double, std::milli>(t1 - t0).count();
     int status = SMM_OK;
     for (int b = 0; b < np; ++b) {
-        inf[b].t_total_ms = tsolve;
+        inf[b].t_total_ms = tsolve + tsetup;
         inf[b].t_setup_ms = tsetup;
         if (!std::isfinite(inf[b].residual)) status = SMM_ENAN;
         else if (status == SMM_OK && !(inf[b].residual < o.outer_tol)) status = SMM_ENOCONV;
@@ -725,6 +885,70 @@ int smm_batch_time_sweep(smm_batch* batch, int precision, int reps, double* ms_a
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *ms_avg = ms / reps;
+    return SMM_OK;
+}
+
+int smm_batch_warmstart_dims(const smm_batch* batch, int* n_features, int* n_targets, int* height, int* width) {
+    if (!batch) return SMM_EINVAL;
+    int nf, nt, ny, nx;
+    int rc = ws_dims(const_cast<smm_batch*>(batch), &nf, &nt, &ny, &nx);
+    if (rc) return rc;
+    if (n_features) *n_features = nf;
+    if (n_targets) *n_targets = nt;
+    if (height) *height = ny;
+    if (width) *width = nx;
+    return SMM_OK;
+}
+
+int smm_batch_diffusion(smm_batch* batch, double inner_tol, int max_inner) {
+    if (!batch || !(inner_tol > 0) || max_inner < 1) return SMM_EINVAL;
+    smm_ctx* c = batch->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    batch->active.assign(batch->nprob, 1);
+    int rc;
+    if ((rc = put(c, batch->d_active, batch->active.data(), sizeof(int) * batch->nprob))) return rc;
+    std::vector<int> its;
+    if ((rc = batch_diffusion(batch, inner_tol, max_inner, its))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SMM_OK;
+}
+
+int smm_batch_warmstart_features(smm_batch* batch, int first, int count, float* features) {
+    if (!batch || !features || first < 0 || count < 1 || first + count > batch->nprob) return SMM_EINVAL;
+    smm_ctx* c = batch->ctx;
+    int nf, nt, ny, nx, rc;
+    if ((rc = ws_dims(batch, &nf, &nt, &ny, &nx))) return rc;
+    if (!batch->have_diff) return fail(c, SMM_ESTATE, "smm_batch_warmstart_features needs smm_batch_diffusion");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, b_ws_features(launch_desc(batch), first, count, features, nf, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SMM_OK;
+}
+
+int smm_batch_warmstart_targets(smm_batch* batch, int first, int count, float* targets) {
+    if (!batch || !targets || first < 0 || count < 1 || first + count > batch->nprob) return SMM_EINVAL;
+    smm_ctx* c = batch->ctx;
+    int nf, nt, ny, nx, rc;
+    if ((rc = ws_dims(batch, &nf, &nt, &ny, &nx))) return rc;
+    if (!batch->have_diff || !batch->have_outputs)
+        return fail(c, SMM_ESTATE, "smm_batch_warmstart_targets needs smm_batch_diffusion and a solve");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, b_ws_targets(launch_desc(batch), first, count, targets, nt, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SMM_OK;
+}
+
+int smm_batch_set_warmstart(smm_batch* batch, smm_cnn* net) {
+    if (!batch) return SMM_EINVAL;
+    if (net && net->ctx != batch->ctx) return fail(batch->ctx, SMM_EINVAL, "network and batch on different contexts");
+    batch->ws_net = net;
+    return SMM_OK;
+}
+
+int smm_batch_warmstart_used(const smm_batch* batch, int* used) {
+    if (!batch || !used) return SMM_EINVAL;
+    if (batch->ws_used.size() != (size_t)batch->nprob) return SMM_ESTATE;
+    for (int b = 0; b < batch->nprob; ++b) used[b] = batch->ws_used[b];
     return SMM_OK;
 }
 

@@ -1386,27 +1386,28 @@ __global__ __launch_bounds__(BT) void b_rhs_kernel(BatchLaunch B) {
     const int n = P.n, n3 = 3 * n, K = m.K, i = m.i;
     const long L = P.L;
     double v = P.bfix[(long)K * n + i];
+    // blocks are stored column-major: entry (i, col) at col * n + i
     {
-        const double* row = P.c_self + ((long)P.sid[K] * n + i) * n3;
+        const double* col = P.c_self + (long)P.sid[K] * n * n3 + i;
         for (int c = 0; c < 3; ++c) {
             const double* tv = P.T + c * L + (long)K * n;
-            for (int j = 0; j < n; ++j) v += row[c * n + j] * tv[j];
+            for (int j = 0; j < n; ++j) v += col[(c * n + j) * n] * tv[j];
         }
     }
     for (int f = 0; f < 4; ++f) {
         const int t = P.nid[K * 4 + f];
         if (t >= 0) {
             const int N = nbr_of(P, K, f);
-            const double* row = P.c_nbr + ((long)t * n + i) * n3;
+            const double* col = P.c_nbr + (long)t * n * n3 + i;
             for (int c = 0; c < 3; ++c) {
                 const double* tv = P.T + c * L + (long)N * n;
-                for (int j = 0; j < n; ++j) v += row[c * n + j] * tv[j];
+                for (int j = 0; j < n; ++j) v += col[(c * n + j) * n] * tv[j];
             }
         } else {
             const int bf = P.bface_of[K * 4 + f];
-            const double* bo = P.bop + ((long)f * n + i) * P.nq;
+            const double* bo = P.bop + (long)f * P.nq * n + i;
             const double* be = P.beta + (long)bf * P.nq;
-            for (int q = 0; q < P.nq; ++q) v -= bo[q] * be[q];
+            for (int q = 0; q < P.nq; ++q) v -= bo[q * n] * be[q];
         }
     }
     P.b[(long)K * n + i] = v;
@@ -1464,16 +1465,18 @@ __device__ __forceinline__ double b_block_sum(double v, double* red) {
 
 __device__ __forceinline__ double typed_row(const BProb& P, const double* x, int K, int i) {
     const int n = P.n;
-    const double* row = P.ip_self + ((long)P.sid[K] * n + i) * n;
+    // column-major blocks: entry (i, j) at j * n + i, so the n lanes of an
+    // element read n consecutive doubles per j
+    const double* col = P.ip_self + (long)P.sid[K] * n * n + i;
     const double* xv = x + (long)K * n;
     double v = 0.0;
-    for (int j = 0; j < n; ++j) v += row[j] * xv[j];
+    for (int j = 0; j < n; ++j) v += col[j * n] * xv[j];
     for (int f = 0; f < 4; ++f) {
         const int t = P.nid[K * 4 + f];
         if (t < 0) continue;
-        const double* rn = P.ip_nbr + ((long)t * n + i) * n;
+        const double* cn = P.ip_nbr + (long)t * n * n + i;
         const double* xn = x + (long)nbr_of(P, K, f) * n;
-        for (int j = 0; j < n; ++j) v += rn[j] * xn[j];
+        for (int j = 0; j < n; ++j) v += cn[j * n] * xn[j];
     }
     return v;
 }
@@ -1498,9 +1501,9 @@ __global__ __launch_bounds__(BT) void b_cg_init2(BatchLaunch B) {
         const BProb& P = B.P[m.prob];
         const int n = P.n;
         const long t = (long)m.K * n + m.i;
-        const double* D = P.dinv + ((long)P.sid[m.K] * n + m.i) * n;
+        const double* D = P.dinv + (long)P.sid[m.K] * n * n + m.i;
         double z = 0;
-        for (int j = 0; j < n; ++j) z += D[j] * P.r[(long)m.K * n + j];
+        for (int j = 0; j < n; ++j) z += D[j * n] * P.r[(long)m.K * n + j];
         P.z[t] = z;
         P.p[t] = z;
         rz = P.r[t] * z;
@@ -1594,9 +1597,9 @@ __global__ __launch_bounds__(BT) void b_cg_k2(BatchLaunch B) {
     __syncthreads();
     double rz = 0, rr = 0;
     if (m.K >= 0) {
-        const double* D = P.dinv + ((long)P.sid[m.K] * n + m.i) * n;
+        const double* D = P.dinv + (long)P.sid[m.K] * n * n + m.i;
         double z = 0;
-        for (int j = 0; j < n; ++j) z += D[j] * rl[m.e0 + j];
+        for (int j = 0; j < n; ++j) z += D[j * n] * rl[m.e0 + j];
         P.z[(long)m.K * n + m.i] = z;
         rz = rnew * z;
         rr = rnew * rnew;
@@ -1648,6 +1651,120 @@ hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s) {
         hipLaunchKernelGGL(b_cg_k2, dim3(B.nblocks), dim3(BT), 0, s, B);
         hipLaunchKernelGGL(b_cg_red2, dim3(B.nprob), dim3(BT), 0, s, B);
         hipLaunchKernelGGL(b_cg_k3, dim3(B.nblocks), dim3(BT), 0, s, B);
+    }
+    return hipGetLastError();
+}
+
+// ---- learned warm start -------------------------------------------------------
+// Flux scale of element K: mean of |varphi_D| over its nodes.
+__device__ __forceinline__ double ws_scale(const BProb& P, int K) {
+    double s = 0.0;
+    for (int j = 0; j < P.n; ++j) s += fabs(P.vdiff[(long)K * P.n + j]);
+    return fmax(s / P.n, 1e-300);
+}
+
+// Features of element K (pixel K of an ny x nx image): channels 0-3 from feat0,
+// 4: log10 s_K minus its problem mean (scal[10]), 5 + i: varphi_D,i / s_K - 1.
+__global__ __launch_bounds__(BT) void b_ws_features_kernel(BatchLaunch B, int first, int count, float* X, int nf) {
+    const EB m = eb_map(B);
+    if (m.K < 0 || m.prob < first || m.prob >= first + count) return;
+    const BProb& P = B.P[m.prob];
+    const double sK = ws_scale(P, m.K);
+    float* px = X + ((long)(m.prob - first) * P.ne + m.K) * nf;
+    px[5 + m.i] = (float)(P.vdiff[(long)m.K * P.n + m.i] / sK - 1.0);
+    if (m.i == 0) {
+        for (int c = 0; c < 4; ++c) px[c] = P.feat0[(long)m.K * 4 + c];
+        px[4] = (float)(log10(sK) - P.scal[10]);
+    }
+}
+
+// problem mean of log10 s_K into scal[10] (one workgroup per problem)
+__global__ __launch_bounds__(BT) void b_ws_logmean_kernel(BatchLaunch B, int first, int count) {
+    __shared__ double red[BT];
+    const int prob = first + blockIdx.x;
+    const BProb& P = B.P[prob];
+    double v = 0.0;
+    for (int K = threadIdx.x; K < P.ne; K += BT) v += log10(ws_scale(P, K));
+    v = b_block_sum(v, red);
+    if (threadIdx.x == 0) P.scal[10] = v / P.ne;
+}
+
+__global__ __launch_bounds__(BT) void b_ws_targets_kernel(BatchLaunch B, int first, int count, float* T, int nt) {
+    const EB m = eb_map(B);
+    if (m.K < 0 || m.prob < first || m.prob >= first + count) return;
+    const BProb& P = B.P[m.prob];
+    const double sK = ws_scale(P, m.K);
+    const long t = (long)m.K * P.n + m.i;
+    float* pt = T + ((long)(m.prob - first) * P.ne + m.K) * nt;
+    pt[m.i] = (float)((P.varphi[t] - P.vdiff[t]) / sK);
+    pt[P.n + m.i] = (float)((P.b[t] - P.bfix[t]) / (P.hxhy * sK));
+}
+
+// x = varphi_D + s_K y_i, b = b_fixed + h_x h_y s_K y_{n+i}; scal[11] = 1 on a
+// non-finite prediction
+__global__ __launch_bounds__(BT) void b_ws_apply_kernel(BatchLaunch B, const float* Y, int nt) {
+    const EB m = eb_map(B);
+    if (m.K < 0 || !B.active[m.prob]) return;
+    const BProb& P = B.P[m.prob];
+    const double sK = ws_scale(P, m.K);
+    const long t = (long)m.K * P.n + m.i;
+    const float* py = Y + ((long)m.prob * P.ne + m.K) * nt;
+    const double y0 = py[m.i], y1 = py[P.n + m.i];
+    if (!isfinite(y0) || !isfinite(y1)) {
+        P.scal[11] = 1.0;
+        P.x[t] = P.vdiff[t];
+        P.b[t] = P.bfix[t];
+        return;
+    }
+    P.x[t] = P.vdiff[t] + sK * y0;
+    P.b[t] = P.bfix[t] + P.hxhy * sK * y1;
+}
+
+// One kernel per staging mode (a compile-time constant): with the mode as a
+// run-time argument the compiled code stored mode 3 into varphi.
+template <int MODE>
+__global__ __launch_bounds__(BT) void b_ws_stage_kernel(BatchLaunch B, const int* flag) {
+    const EB m = eb_map(B);
+    if (m.K < 0 || !B.active[m.prob]) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i;
+    if constexpr (MODE == 0) {
+        const double v = P.x[t];
+        P.varphi_prev[t] = v;
+        P.varphi[t] = v;
+    } else if constexpr (MODE == 1) {
+        P.varphi[t] = P.vdiff[t];
+    } else if constexpr (MODE == 2) {
+        P.varphi[t] = flag[m.prob] ? P.vdiff[t] : P.varphi_prev[t];
+        P.varphi_prev[t] = 0.0;
+    } else {
+        P.vdiff[t] = P.x[t];
+    }
+}
+
+hipError_t b_ws_features(const BatchLaunch& B, int first, int count, float* X, int nf, hipStream_t s) {
+    hipLaunchKernelGGL(b_ws_logmean_kernel, dim3(count), dim3(BT), 0, s, B, first, count);
+    hipLaunchKernelGGL(b_ws_features_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, first, count, X, nf);
+    return hipGetLastError();
+}
+
+hipError_t b_ws_targets(const BatchLaunch& B, int first, int count, float* T, int nt, hipStream_t s) {
+    hipLaunchKernelGGL(b_ws_targets_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, first, count, T, nt);
+    return hipGetLastError();
+}
+
+hipError_t b_ws_apply(const BatchLaunch& B, const float* Y, int nt, hipStream_t s) {
+    hipLaunchKernelGGL(b_ws_apply_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, Y, nt);
+    return hipGetLastError();
+}
+
+hipError_t b_ws_stage(const BatchLaunch& B, int mode, const int* flag, hipStream_t s) {
+    switch (mode) {
+        case 0: hipLaunchKernelGGL(b_ws_stage_kernel<0>, dim3(B.nblocks), dim3(BT), 0, s, B, flag); break;
+        case 1: hipLaunchKernelGGL(b_ws_stage_kernel<1>, dim3(B.nblocks), dim3(BT), 0, s, B, flag); break;
+        case 2: hipLaunchKernelGGL(b_ws_stage_kernel<2>, dim3(B.nblocks), dim3(BT), 0, s, B, flag); break;
+        case 3: hipLaunchKernelGGL(b_ws_stage_kernel<3>, dim3(B.nblocks), dim3(BT), 0, s, B, flag); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -115,6 +115,9 @@ struct BProb {
     void* psi;                                              // [nd][Lpad]
     const double* W64;                                      // [16][ldw] moment weights
     const float* W32;                                       // [16][ldw]
+    double* vdiff;                                          // [L] diffusion start (warm start)
+    const float* feat0;                                     // [ne][4] per-element warm-start features
+    double hxhy;                                            // element area
 };
 
 struct BatchLaunch {
@@ -141,6 +144,14 @@ hipError_t b_shift(const BatchLaunch& B, hipStream_t s);                // varph
 hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s);
 hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s);
 hipError_t b_residual(const BatchLaunch& B, double* out, hipStream_t s);   // out[2*nprob]
+// warm start: features / targets of problems [first, first + count), start from the
+// network output, and staging of the two start candidates (mode 0: varphi_prev =
+// varphi = x; 1: varphi = vdiff; 2: varphi = flag ? vdiff : varphi_prev, varphi_prev = 0;
+// 3: vdiff = x)
+hipError_t b_ws_features(const BatchLaunch& B, int first, int count, float* X, int nf, hipStream_t s);
+hipError_t b_ws_targets(const BatchLaunch& B, int first, int count, float* T, int nt, hipStream_t s);
+hipError_t b_ws_apply(const BatchLaunch& B, const float* Y, int nt, hipStream_t s);
+hipError_t b_ws_stage(const BatchLaunch& B, int mode, const int* flag, hipStream_t s);
 hipError_t zero_ints(int* p, int n, hipStream_t s);
 
 }  // namespace smm

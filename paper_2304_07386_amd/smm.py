@@ -30,6 +30,11 @@ EXPORTED = [
     "smm_set_sweep_path", "smm_time_sweep", "smm_debug_typed_dense", "smm_debug_corr_dense",
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
     "smm_batch_time_sweep", "smm_batch_units",
+    # smm_cnn.h
+    "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
+    "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
+    "smm_batch_diffusion", "smm_batch_warmstart_features", "smm_batch_warmstart_targets",
+    "smm_batch_set_warmstart", "smm_batch_warmstart_used",
 ]
 
 
@@ -108,6 +113,20 @@ def load_library(path: str = LIB_PATH):
         "smm_batch_get_outputs": (ip, [vp, ip, vp, vp, vp, vp, vp, ip]),
         "smm_batch_time_sweep": (ip, [vp, ip, ip, dp]),
         "smm_batch_units": (ip, [vp, dp]),
+        "smm_cnn_create": (ip, [vp, ip, C.POINTER(ip), ip, ip, ip, C.POINTER(vp)]),
+        "smm_cnn_destroy": (ip, [vp]),
+        "smm_cnn_num_params": (ip, [vp, C.POINTER(C.c_size_t)]),
+        "smm_cnn_set_params": (ip, [vp, vp, C.c_size_t]),
+        "smm_cnn_get_params": (ip, [vp, vp, C.c_size_t]),
+        "smm_cnn_forward": (ip, [vp, vp, ip, vp]),
+        "smm_cnn_loss_grad": (ip, [vp, vp, vp, ip, vp, ip, vp, dp, vp]),
+        "smm_cnn_adam_step": (ip, [vp, C.c_float, C.c_float, C.c_float, C.c_float]),
+        "smm_batch_warmstart_dims": (ip, [vp, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)]),
+        "smm_batch_diffusion": (ip, [vp, C.c_double, ip]),
+        "smm_batch_warmstart_features": (ip, [vp, ip, ip, vp]),
+        "smm_batch_warmstart_targets": (ip, [vp, ip, ip, vp]),
+        "smm_batch_set_warmstart": (ip, [vp, vp]),
+        "smm_batch_warmstart_used": (ip, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -384,3 +403,96 @@ def smm_batch_units(batch: Batch) -> float:
     u = C.c_double()
     _check(load_library().smm_batch_units(batch.handle, C.byref(u)), batch.ctx)
     return u.value
+
+
+# ---- learned warm start (smm_cnn.h) -------------------------------------------------
+
+SMM_START_LEARNED = 3
+
+
+class Cnn:
+    def __init__(self, ctx, handle, channels, height, width, max_batch):
+        self.ctx = ctx
+        self.handle = handle
+        self.channels = list(channels)
+        self.height, self.width, self.max_batch = height, width, max_batch
+
+    @property
+    def n_params(self) -> int:
+        n = C.c_size_t()
+        _check(load_library().smm_cnn_num_params(self.handle, C.byref(n)), self.ctx)
+        return n.value
+
+
+def smm_cnn_create(ctx: Context, channels, height: int, width: int, max_batch: int) -> Cnn:
+    ch = (C.c_int * len(channels))(*channels)
+    h = C.c_void_p()
+    _check(load_library().smm_cnn_create(ctx.handle, len(channels) - 1, ch, height, width, max_batch, C.byref(h)), ctx)
+    return Cnn(ctx, h, channels, height, width, max_batch)
+
+
+def smm_cnn_destroy(net: Cnn):
+    load_library().smm_cnn_destroy(net.handle)
+
+
+def smm_cnn_num_params(net: Cnn) -> int:
+    return net.n_params
+
+
+def smm_cnn_set_params(net: Cnn, params):
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+    _check(load_library().smm_cnn_set_params(net.handle, _ptr(a), a.size), net.ctx)
+
+
+def smm_cnn_get_params(net: Cnn) -> np.ndarray:
+    a = np.zeros(net.n_params, dtype=np.float32)
+    _check(load_library().smm_cnn_get_params(net.handle, _ptr(a), a.size), net.ctx)
+    return a
+
+
+def smm_cnn_forward(net: Cnn, x, batch: int, y):
+    """x, y: device float32 tensors [batch][H][W][c_in] / [batch][H][W][c_out]."""
+    _check(load_library().smm_cnn_forward(net.handle, _ptr(x), batch, _ptr(y)), net.ctx)
+
+
+def smm_cnn_loss_grad(net: Cnn, x_all, t_all, idx, batch: int, chan_weight=None, want_grad=False):
+    """Returns (loss, grad or None).  idx: device int32 tensor or None."""
+    loss = C.c_double()
+    w = None if chan_weight is None else np.ascontiguousarray(np.asarray(chan_weight, dtype=np.float32))
+    g = np.zeros(net.n_params, dtype=np.float32) if want_grad else None
+    _check(load_library().smm_cnn_loss_grad(net.handle, _ptr(x_all), _ptr(t_all), int(x_all.shape[0]), _ptr(idx),
+                                            batch, _ptr(w), C.byref(loss), _ptr(g)), net.ctx)
+    return loss.value, g
+
+
+def smm_cnn_adam_step(net: Cnn, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    _check(load_library().smm_cnn_adam_step(net.handle, lr, beta1, beta2, eps), net.ctx)
+
+
+def smm_batch_warmstart_dims(batch: Batch):
+    v = [C.c_int() for _ in range(4)]
+    _check(load_library().smm_batch_warmstart_dims(batch.handle, *[C.byref(x) for x in v]), batch.ctx)
+    return tuple(x.value for x in v)   # (n_features, n_targets, height, width)
+
+
+def smm_batch_diffusion(batch: Batch, inner_tol: float = 1e-10, max_inner: int = 20000):
+    _check(load_library().smm_batch_diffusion(batch.handle, inner_tol, max_inner), batch.ctx)
+
+
+def smm_batch_warmstart_features(batch: Batch, first: int, count: int, out):
+    _check(load_library().smm_batch_warmstart_features(batch.handle, first, count, _ptr(out)), batch.ctx)
+
+
+def smm_batch_warmstart_targets(batch: Batch, first: int, count: int, out):
+    _check(load_library().smm_batch_warmstart_targets(batch.handle, first, count, _ptr(out)), batch.ctx)
+
+
+def smm_batch_set_warmstart(batch: Batch, net: Cnn | None):
+    _check(load_library().smm_batch_set_warmstart(batch.handle, net.handle if net is not None else None), batch.ctx)
+    batch._ws_net = net   # keep the network alive while attached
+
+
+def smm_batch_warmstart_used(batch: Batch) -> np.ndarray:
+    u = np.zeros(batch.n, dtype=np.int32)
+    _check(load_library().smm_batch_warmstart_used(batch.handle, _ptr(u)), batch.ctx)
+    return u

@@ -1,6 +1,6 @@
 """C-ABI library checks that need no GPU.
 
-* libsmm.so loads and exports every function declared in include/smm.h.
+* libsmm.so loads and exports every function declared in include/*.h.
 * Host-only contexts run the one-time setup; its tables equal the oracle's
   (IP operator and fixed right-hand side of eq. ipsmm, quadrature, node
   coordinates) on straight, non-uniform and curved meshes.
@@ -21,9 +21,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_library_exports_header_symbols():
     lib = L.load_library()
-    hdr = open(os.path.join(ROOT, "include", "smm.h")).read()
-    names = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(smm_\w+)\s*\(", hdr, re.M))
-    assert len(names) >= 20
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            hdr = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"^\s*(?:int|void|const char\*)\s+(smm_\w+)\s*\(", hdr, re.M))
+    assert len(names) >= 40
     for n in names:
         assert hasattr(lib, n), n
     assert set(L.EXPORTED) == names
@@ -114,3 +117,14 @@ def test_validation_errors(hctx):
     with pytest.raises(L.SmmError) as e:
         L.smm_solve(p)
     assert e.value.code == L.SMM_ESTATE
+
+
+def test_warmstart_calls_need_a_device(hctx):
+    """The network lives on a device: a host-only context is refused."""
+    lib = L.load_library()
+    import ctypes as C
+    ch = (C.c_int * 3)(14, 32, 18)
+    h = C.c_void_p()
+    assert lib.smm_cnn_create(hctx.handle, 2, ch, 8, 8, 4, C.byref(h)) == L.SMM_ESTATE
+    assert lib.smm_cnn_create(hctx.handle, 0, ch, 8, 8, 4, C.byref(h)) in (L.SMM_ESTATE, L.SMM_EINVAL)
+    assert lib.smm_batch_warmstart_used(None, None) == L.SMM_EINVAL
