@@ -1,23 +1,33 @@
 #!/usr/bin/env python3
-"""Benchmark: DG S_N sweep throughput inside the SMM outer iteration on one
-MI355X.
+"""Benchmark: the batched SMM hot path on one MI355X.
 
-Workload: the two-material channel problem on [0,10]^2, 128 x 128 quads,
-p = 2, S12 (84 directions), FP32 sweep and moments, FP64 CG and residual,
-delta sweeps (synthetic seeded inputs; see workloads.config_channel).
+Workload (value): 256 independent problems solved as one batch, seeds 0-255
+of the seeded generator (uniform Cartesian [0,1]^2 meshes of 16^2 to 128^2
+elements, orders p = 1-4, S4-S12, homogeneous sigma_t log-uniform in
+[0.1, 100], scattering ratio uniform in [0.5, 0.999], unit isotropic
+source, vacuum), FP32 sweeps and moments with delta sweeps, FP64 closures,
+PCG and residual.  Inputs are synthetic and resident on the GPU before the
+timed region.
 
-A step is one full outer iteration X -> G(X): scattering source, sweep,
-angular moments on the matrix cores, SMM closures, IP right-hand side, FP64
-PCG moment solve, residual.  value = elem*angle*DOF per second of whole
-steps.  Extra fields report the sweep kernel alone (HIP events on the
-library's stream), its roofline, and the time to a 1e-8 outer residual.
+A step is one full outer iteration X -> G(X) of every problem: scattering
+source, sweep (persistent per-order launches), angular moments on the matrix
+cores, SMM closures, right-hand side, FP64 block-Jacobi PCG, residual.
+value = elem*angle*DOF units swept per second of whole steps.
 
-The CPU baseline is the FP64 oracle's sweep on a bounded sample of the same
-workload (a few directions), single thread.
+Also reported:
+  * the time of each phase inside the steps and the roofline of the kernel of
+    the dominant phase (and of the sweep), from HIP events on the stream each
+    kernel runs on;
+  * time to a 1e-8 outer residual on held-out warm-start layouts (64 x 64,
+    p = 2, S8 blob layouts): the plain method (problems solved one after the
+    other from the zero start) against the batched solve with the learned
+    start, on identical inputs;
+  * the CPU oracle's sweep on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -28,107 +38,190 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "sweep elem*angle*DOF/s + time-to-1e-8 SMM solve, plain vs batched+warm"
 
 
-def cpu_baseline(wl, n_dirs: int = 6):
-    """Time the oracle sweep for n_dirs directions of the workload (one
-    thread).  Returns units/s and a description of the sample."""
-    try:
-        from threadpoolctl import threadpool_limits
-    except Exception:  # pragma: no cover
-        threadpool_limits = None
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(workloads, max_dirs: int = 12):
+    """The oracle's sweep (FP64, one thread) over up to max_dirs directions of
+    each given problem.  Returns (units/s, description)."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import smm as osmm, transport
 
-    pr = osmm.make_problem(wl)
-    S = np.ones((pr.ne, pr.n))
-    dirs = np.linspace(0, len(pr.w) - 1, n_dirs).astype(int)
-    ctx = threadpool_limits(1) if threadpool_limits else None
+    units, dt, parts = 0, 0.0, []
+    with threadpool_limits(1):
+        for wl in workloads:
+            pr = osmm.make_problem(wl)
+            nd = min(max_dirs, len(pr.w))
+            S = np.ones((pr.ne, pr.n))
+            t0 = time.perf_counter()
+            transport.sweep(pr.mesh, pr.omega[:nd], pr.sigma_t, S, None)
+            dt += time.perf_counter() - t0
+            units += pr.ne * nd * pr.n
+            parts.append(f"{wl.nx}^2 p={wl.p} S{wl.sn} {nd} dirs")
+    return units / dt, (f"oracle FP64 sweep, first {len(workloads)} problems of the batch ({'; '.join(parts)}): "
+                        f"{units} units in {dt:.1f} s")
+
+
+def traffic_for(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tab = json.load(f)
+    ent = tab.get(kernel)
+    if not ent:
+        return None
+    src = os.path.join(ROOT, "paper_2304_07386_amd", "csrc", ent["source"])
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != ent["sha256"]:
+        return None
+    return ent["bytes_per_launch"]
+
+
+def roofline(kernel: str, bytes_per_launch: float, ms: float):
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    tr = traffic_for(kernel)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kernel,
+            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": ms}
+
+
+def time_to_solution(L, ctx, n: int, log):
+    """Plain (one problem at a time, zero start) vs batched + learned start on
+    the held-out layouts 20000..20000+n-1; wall time to a 1e-8 residual."""
+    import numpy as np
+    import torch
+    from paper_2304_07386_amd import warmstart as W
+    from workloads import config_blobs
+
+    if not os.path.exists(W.DEFAULT_WEIGHTS):
+        log("no trained warm-start weights: skipping the time-to-solution comparison")
+        return None
+    wls = [config_blobs(20000 + k) for k in range(n)]
+    probs = [L.problem_from_workload(ctx, wl) for wl in wls]
+    opts = W.solve_opts(1e-8, start=L.SMM_START_ZERO)
+    # plain: the single-problem solve, zero start, one problem after the other
+    warm = W.solve_opts(1e-8, start=L.SMM_START_ZERO)
+    warm.max_outer = 1
+    for p in probs:                                              # one-time device set-up outside the timing
+        L.smm_solve(p, warm, raise_on_noconv=False)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    transport.sweep(pr.mesh, pr.omega[dirs], pr.sigma_t, S, None)
-    dt = time.perf_counter() - t0
-    if ctx is not None:
-        ctx.unregister() if hasattr(ctx, "unregister") else None
-    units = pr.ne * len(dirs) * pr.n
-    return units / dt, f"oracle FP64 sweep of {len(dirs)} of {len(pr.w)} directions on the full " \
-                       f"{wl.nx}x{wl.ny} p={wl.p} mesh ({units} units, {dt:.1f} s)"
+    plain_its = []
+    for p in probs:
+        rc, info = L.smm_solve(p, opts, raise_on_noconv=False)
+        plain_its.append(info["iterations"])
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log(f"plain: {n} problems in {t_plain:.2f} s, outer its mean {np.mean(plain_its):.2f}")
+    batch = L.smm_batch_create(ctx, probs)
+    net, meta = W.load(ctx, max_batch=32)
+    L.smm_batch_set_warmstart(batch, net)
+    res = {"n_problems": n, "workload": "blobs 64x64 p=2 S8, held-out seeds 20000..%d" % (20000 + n - 1),
+           "plain_s": t_plain, "plain_outer_mean": float(np.mean(plain_its))}
+    L.smm_batch_solve(batch, W.solve_opts(1e-8, start=L.SMM_START_ZERO), raise_on_noconv=False)  # autotune
+    for name, start in (("batched_zero", L.SMM_START_ZERO), ("batched_diffusion", L.SMM_START_DIFFUSION),
+                        ("batched_warm", L.SMM_START_LEARNED)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, infos = L.smm_batch_solve(batch, W.solve_opts(1e-8, start=start), raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res[name + "_s"] = t
+        res[name + "_outer_mean"] = float(np.mean([i["iterations"] for i in infos]))
+        res[name + "_converged"] = rc == L.SMM_OK
+        log(f"{name}: {t:.2f} s, outer its mean {res[name + '_outer_mean']:.2f}")
+    res["learned_start_kept"] = int(L.smm_batch_warmstart_used(batch).sum())
+    res["speedup_batched_warm_vs_plain"] = t_plain / res["batched_warm_s"]
+    L.smm_batch_set_warmstart(batch, None)
+    L.smm_batch_destroy(batch)
+    L.smm_cnn_destroy(net)
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sweep-reps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--problems", type=int, default=256)
+    ap.add_argument("--tts-problems", type=int, default=24, help="held-out problems for the time-to-solution run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 solve")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 comparison")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (the problems of a batch are "
+              "independent and would be split across GPUs by the caller)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
     import paper_2304_07386_amd as L
-    from workloads import config_channel
+    from workloads import config_batched_problem
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
-    ctx = L.smm_ctx_create(0, stream)
-    wl = config_channel()
-    prob = L.problem_from_workload(ctx, wl)
-    units = wl.units_per_sweep
-    print(f"[bench] workload channel 128x128 p=2 S12: {units} units per sweep", file=sys.stderr, flush=True)
+    ctx = L.smm_ctx_create(0, torch.cuda.current_stream())
+    t0 = time.time()
+    wls = [config_batched_problem(s) for s in range(args.problems)]
+    probs = [L.problem_from_workload(ctx, wl) for wl in wls]
+    batch = L.smm_batch_create(ctx, probs)
+    units = L.smm_batch_units(batch)
+    dofs = float(sum(p.n_elem * p.n_node for p in probs))
+    log(f"batch of {args.problems} problems: {units:.4g} units per sweep, {dofs:.4g} DOF, "
+        f"set-up {time.time() - t0:.1f} s")
 
     opts = L.smm_default_opts(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=0.0,
-                              inner_tol=1e-10, max_inner=20000)
-    # warmup (also builds the device tables)
-    opts.max_outer = max(args.warmup, 1)
-    L.smm_solve(prob, opts, raise_on_noconv=False)
+                              inner_tol=1e-10, max_inner=20000, max_outer=max(args.warmup, 1))
+    L.smm_batch_solve(batch, opts, raise_on_noconv=False)       # warm-up (also autotunes the sweep grids)
     torch.cuda.synchronize()
-    # timed steps
     opts.max_outer = args.steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rc, info = L.smm_solve(prob, opts, raise_on_noconv=False)
+    rc, infos = L.smm_batch_solve(batch, opts, raise_on_noconv=False)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    assert all(i["iterations"] == args.steps for i in infos)
     ms_per_step = 1e3 * wall / args.steps
     value = units * args.steps / wall
-    print(f"[bench] {args.steps} outer iterations: {ms_per_step:.3f} ms/step, "
-          f"CG iterations total {info['cg_iterations_total']}", file=sys.stderr, flush=True)
+    phases, cg_its = L.smm_batch_phase_times(batch)
+    names = ["source+sweep", "moments+closures+rhs", "pcg", "residual"]
+    phase = {n: ms / args.steps for n, ms in zip(names, phases)}
+    log(f"{args.steps} steps: {ms_per_step:.1f} ms/step; per step " +
+        ", ".join(f"{n} {v:.2f} ms" for n, v in phase.items()) + f"; batched PCG iterations {cg_its}")
 
-    # sweep kernel alone: HIP events around back-to-back sweeps on the library stream
-    sweep_ms = L.smm_time_sweep(prob, L.SMM_FP32_SWEEP, args.sweep_reps)
-    sweep_rate = units / (sweep_ms * 1e-3)
-    nd, n = prob.n_dir, prob.n_node
-    bytes_per_unit = 4.0 + 4.0 / nd      # psi written once (FP32) + S read once per element
-    achieved = units * bytes_per_unit / (sweep_ms * 1e-3) / 1e9
-    print(f"[bench] sweep {sweep_ms * 1e3:.1f} us -> {sweep_rate:.3e} units/s", file=sys.stderr, flush=True)
+    sweep_ms = L.smm_batch_time_kernel(batch, L.SMM_KERNEL_SWEEP_FP32, 5)
+    # sweep: psi written once in FP32 (4 B/unit) + the FP32 source read once per
+    # element and direction set (4/N_dir B/unit, N_dir per problem)
+    sweep_bytes = float(sum(p.n_elem * p.n_node * (4.0 * p.n_dir + 4.0) for p in probs))
+    rl_sweep = roofline("b_sweep_kernel", sweep_bytes, sweep_ms)
+    spmv_ms = L.smm_batch_time_kernel(batch, L.SMM_KERNEL_CG_SPMV, 50)
+    # q = A p: p read once and q written once, FP64 (16 B/DOF)
+    rl_spmv = roofline("b_cg_k1", 16.0 * dofs, spmv_ms)
+    log(f"sweep {sweep_ms:.3f} ms -> {units / sweep_ms / 1e-3:.3e} units/s, {rl_sweep['achieved']:.0f} GB/s; "
+        f"PCG q=Ap {spmv_ms * 1e3:.1f} us, {rl_spmv['achieved']:.0f} GB/s")
+    dominant = rl_spmv if phase["pcg"] > phase["source+sweep"] else rl_sweep
 
-    solve = None
+    tts = None
     if not args.no_solve:
-        o2 = L.smm_default_opts(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=1e-8,
-                                inner_tol=1e-10, max_inner=20000, max_outer=200)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc2, inf2 = L.smm_solve(prob, o2, raise_on_noconv=False)
-        torch.cuda.synchronize()
-        solve = {"ms": 1e3 * (time.perf_counter() - t0), "outer_iterations": inf2["iterations"],
-                 "cg_iterations_total": inf2["cg_iterations_total"], "residual": inf2["residual"],
-                 "converged": rc2 == L.SMM_OK, "start": "zero"}
-        print(f"[bench] time to 1e-8: {solve}", file=sys.stderr, flush=True)
+        tts = time_to_solution(L, ctx, args.tts_problems, log)
 
     cpu = None
     if not args.no_cpu_baseline:
-        rate, sample = cpu_baseline(wl)
+        rate, sample = cpu_baseline(wls[:4])
         cpu = {"value": rate, "unit": "elem*angle*DOF/s", "cores": 1, "kind": "oracle", "sample": sample,
                "cpu": platform.processor() or platform.machine()}
+        log(f"cpu baseline {rate:.3e} units/s")
 
     out = {
-        "metric": "sweep elem*angle*DOF/s (whole SMM outer iteration) + time-to-1e-8 SMM solve",
+        "metric": METRIC,
         "value": value,
         "unit": "elem*angle*DOF/s",
         "n_gpus": 1,
@@ -139,16 +232,17 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "dtype_detail": "sweep and moments f32; CG, closures, residual f64",
+        "dtype_detail": "sweep and moments f32; closures, PCG, residual f64; warm-start network bf16/f32",
         "data": "synthetic",
-        "config": {"workload": "channel two-material [0,10]^2 128x128 p=2 S12, seed 0",
-                   "units_per_sweep": units, "parallelism": "single GPU"},
-        "sweep_only": {"ms": sweep_ms, "units_per_s": sweep_rate},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sweep_cart_kernel<float,3>",
-                     "bytes_per_unit": bytes_per_unit},
-        "time_to_1e-8": solve,
+        "config": {"workload": f"batch of {args.problems} problems, seeds 0..{args.problems - 1}: "
+                               "[0,1]^2 16^2..128^2, p 1..4, S4..S12, sigma_t 10^U(-1,2), c U(0.5,0.999)",
+                   "units_per_sweep": units, "dof": dofs, "parallelism": "single GPU"},
+        "phase_ms_per_step": phase,
+        "sweep_only": {"ms": sweep_ms, "units_per_s": units / (sweep_ms * 1e-3)},
+        "roofline": dominant,
+        "roofline_sweep": rl_sweep,
+        "roofline_pcg_spmv": rl_spmv,
+        "time_to_1e-8": tts,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -244,6 +244,21 @@ int smm_batch_get_outputs(smm_batch* batch, int k, double* varphi, double* phi, 
 int smm_batch_time_sweep(smm_batch* batch, int precision, int reps, double* ms_avg);
 /* Elem*angle*DOF units of one batched sweep. */
 int smm_batch_units(const smm_batch* batch, double* units);
+/* Time of the outer-iteration phases of the last smm_batch_solve, in ms,
+ * summed over its outer iterations (HIP events on the context's stream):
+ * ms[0] scattering source and sweep, ms[1] moments, closures and right-hand
+ * side, ms[2] PCG moment solve, ms[3] residual and shift.  cg_iterations
+ * (nullable) receives the number of batched PCG iterations launched. */
+int smm_batch_phase_times(const smm_batch* batch, double* ms, long* cg_iterations);
+/* Average duration (HIP events on the stream each kernel runs on) of reps
+ * back-to-back launches of one batched kernel: SMM_KERNEL_SWEEP_FP32 /
+ * SMM_KERNEL_SWEEP_FP64 (one whole batched sweep), SMM_KERNEL_CG_SPMV (the
+ * PCG kernel q = A p with its partial dot products, on the state left by the
+ * last smm_batch_solve; SMM_ESTATE before any solve). */
+#define SMM_KERNEL_SWEEP_FP32 0
+#define SMM_KERNEL_SWEEP_FP64 1
+#define SMM_KERNEL_CG_SPMV 2
+int smm_batch_time_kernel(smm_batch* batch, int kernel, int reps, double* ms_avg);
 
 #ifdef __cplusplus
 }

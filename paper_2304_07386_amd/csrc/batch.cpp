@@ -122,6 +122,11 @@ struct smm_batch {
     std::vector<int> ws_used;
     float *d_wsx = nullptr, *d_wsy = nullptr;
     int* d_wsflag = nullptr;
+    // time of the outer-iteration phases of the last solve (ms): source + sweep,
+    // moments + closures + right-hand side, PCG, residual
+    hipEvent_t pev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double phase_ms[4] = {0, 0, 0, 0};
+    long cg_batched_its = 0;   // batched PCG iterations launched in the last solve
 };
 
 namespace {
@@ -182,6 +187,8 @@ void batch_free(smm_batch* B) {
         if (s) (void)hipStreamDestroy(s);
     if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
     for (auto& e : B->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : B->pev)
         if (e) (void)hipEventDestroy(e);
     delete B;
 }
@@ -548,6 +555,7 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
         const int k = std::min(chunk, max_inner - done_its);
         HIPCHK(c, b_cg_iterations(L, k, c->stream));
         done_its += k;
+        B->cg_batched_its += k;
         chunk = std::min(chunk * 2, 64);
     }
     its.assign(B->nprob, 0);
@@ -709,18 +717,32 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     std::vector<double> ro(2 * (size_t)np);
     int nactive = np;
     int it;
+    for (auto& e : B->pev)
+        if (!e) HIPCHK(c, hipEventCreate(&e));
+    for (double& t : B->phase_ms) t = 0;
+    B->cg_batched_its = 0;
     for (it = 1; it <= o.max_outer && nactive > 0; ++it) {
         const bool first = (it == 1) || !delta;
+        HIPCHK(c, hipEventRecord(B->pev[0], c->stream));
         HIPCHK(c, b_source(fp64, L, !first, c->stream));
         if ((rc = batch_sweep(B, fp64, first))) return rc;
+        HIPCHK(c, hipEventRecord(B->pev[1], c->stream));
         HIPCHK(c, b_moments(fp64, L, true, first, c->stream));
         HIPCHK(c, b_closures_rhs(L, c->stream));
         HIPCHK(c, b_copy_x(L, c->stream));
+        HIPCHK(c, hipEventRecord(B->pev[2], c->stream));
         if ((rc = batch_cg(B, o.inner_tol, o.max_inner, its))) return rc;
+        HIPCHK(c, hipEventRecord(B->pev[3], c->stream));
         HIPCHK(c, b_residual(L, B->d_rout, c->stream));
         HIPCHK(c, hipMemcpyAsync(ro.data(), B->d_rout, sizeof(double) * ro.size(), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, b_shift(L, c->stream));
+        HIPCHK(c, hipEventRecord(B->pev[4], c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int ph = 0; ph < 4; ++ph) {
+            float ms = 0;
+            HIPCHK(c, hipEventElapsedTime(&ms, B->pev[ph], B->pev[ph + 1]));
+            B->phase_ms[ph] += ms;
+        }
         bool changed = false;
         for (int b = 0; b < np; ++b) {
             if (!B->active[b]) continue;
@@ -949,6 +971,45 @@ int smm_batch_warmstart_used(const smm_batch* batch, int* used) {
     if (!batch || !used) return SMM_EINVAL;
     if (batch->ws_used.size() != (size_t)batch->nprob) return SMM_ESTATE;
     for (int b = 0; b < batch->nprob; ++b) used[b] = batch->ws_used[b];
+    return SMM_OK;
+}
+
+int smm_batch_phase_times(const smm_batch* batch, double* ms, long* cg_iterations) {
+    if (!batch || !ms) return SMM_EINVAL;
+    for (int k = 0; k < 4; ++k) ms[k] = batch->phase_ms[k];
+    if (cg_iterations) *cg_iterations = batch->cg_batched_its;
+    return SMM_OK;
+}
+
+int smm_batch_time_kernel(smm_batch* batch, int kernel, int reps, double* ms_avg) {
+    if (!batch || reps < 1 || !ms_avg) return SMM_EINVAL;
+    smm_ctx* c = batch->ctx;
+    int rc;
+    if (kernel == SMM_KERNEL_SWEEP_FP32 || kernel == SMM_KERNEL_SWEEP_FP64)
+        return smm_batch_time_sweep(batch, kernel == SMM_KERNEL_SWEEP_FP64 ? SMM_FP64 : SMM_FP32_SWEEP, reps, ms_avg);
+    if (kernel != SMM_KERNEL_CG_SPMV) return fail(c, SMM_EINVAL, "smm_batch_time_kernel: unknown kernel");
+    if (!batch->have_outputs) return fail(c, SMM_ESTATE, "smm_batch_time_kernel: run smm_batch_solve first");
+    HIPCHK(c, hipSetDevice(c->device));
+    batch->active.assign(batch->nprob, 1);
+    if ((rc = put(c, batch->d_active, batch->active.data(), sizeof(int) * batch->nprob))) return rc;
+    const BatchLaunch L = launch_desc(batch);
+    // a CG state on the last right-hand side (x, b, p untouched by the timed launches
+    // except q and the partial sums)
+    HIPCHK(c, b_copy_x(L, c->stream));
+    HIPCHK(c, b_cg_start(L, 0.0, c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, b_cg_spmv(L, c->stream));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int k = 0; k < reps; ++k) HIPCHK(c, b_cg_spmv(L, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_avg = ms / reps;
     return SMM_OK;
 }
 

@@ -1644,6 +1644,11 @@ hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s) {
+    hipLaunchKernelGGL(b_cg_k1, dim3(B.nblocks), dim3(BT), 0, s, B);
+    return hipGetLastError();
+}
+
 hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s) {
     for (int k = 0; k < iters; ++k) {
         hipLaunchKernelGGL(b_cg_k1, dim3(B.nblocks), dim3(BT), 0, s, B);

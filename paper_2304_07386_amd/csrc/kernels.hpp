@@ -143,6 +143,7 @@ hipError_t b_copy_x(const BatchLaunch& B, hipStream_t s);               // x = v
 hipError_t b_shift(const BatchLaunch& B, hipStream_t s);                // varphi_prev = varphi, varphi = x
 hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s);
 hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s);
+hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s);                // one q = A p launch
 hipError_t b_residual(const BatchLaunch& B, double* out, hipStream_t s);   // out[2*nprob]
 // warm start: features / targets of problems [first, first + count), start from the
 // network output, and staging of the two start candidates (mode 0: varphi_prev =

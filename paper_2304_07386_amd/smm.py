@@ -29,7 +29,7 @@ EXPORTED = [
     "smm_get_outputs", "smm_apply_sweep", "smm_apply_moments", "smm_apply_G", "smm_debug_ip_dense",
     "smm_set_sweep_path", "smm_time_sweep", "smm_debug_typed_dense", "smm_debug_corr_dense",
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
-    "smm_batch_time_sweep", "smm_batch_units",
+    "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
@@ -113,6 +113,8 @@ def load_library(path: str = LIB_PATH):
         "smm_batch_get_outputs": (ip, [vp, ip, vp, vp, vp, vp, vp, ip]),
         "smm_batch_time_sweep": (ip, [vp, ip, ip, dp]),
         "smm_batch_units": (ip, [vp, dp]),
+        "smm_batch_phase_times": (ip, [vp, dp, C.POINTER(C.c_long)]),
+        "smm_batch_time_kernel": (ip, [vp, ip, ip, dp]),
         "smm_cnn_create": (ip, [vp, ip, C.POINTER(ip), ip, ip, ip, C.POINTER(vp)]),
         "smm_cnn_destroy": (ip, [vp]),
         "smm_cnn_num_params": (ip, [vp, C.POINTER(C.c_size_t)]),
@@ -396,6 +398,23 @@ def smm_batch_get_outputs(batch: Batch, k: int, varphi=None, phi=None, J=None, T
 def smm_batch_time_sweep(batch: Batch, precision: int, reps: int) -> float:
     ms = C.c_double()
     _check(load_library().smm_batch_time_sweep(batch.handle, precision, reps, C.byref(ms)), batch.ctx)
+    return ms.value
+
+
+SMM_KERNEL_SWEEP_FP32, SMM_KERNEL_SWEEP_FP64, SMM_KERNEL_CG_SPMV = 0, 1, 2
+
+
+def smm_batch_phase_times(batch: Batch):
+    """(ms[4] of source+sweep, moments+closures+rhs, PCG, residual; batched PCG iterations)."""
+    ms = (C.c_double * 4)()
+    n = C.c_long()
+    _check(load_library().smm_batch_phase_times(batch.handle, ms, C.byref(n)), batch.ctx)
+    return list(ms), n.value
+
+
+def smm_batch_time_kernel(batch: Batch, kernel: int, reps: int) -> float:
+    ms = C.c_double()
+    _check(load_library().smm_batch_time_kernel(batch.handle, kernel, reps, C.byref(ms)), batch.ctx)
     return ms.value
 
 

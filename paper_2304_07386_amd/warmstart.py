@@ -151,6 +151,34 @@ def load(ctx, path=DEFAULT_WEIGHTS, max_batch: int = 64):
     return net, meta
 
 
+def compare_starts(ctx, net, workloads, tol=1e-8, log=print):
+    """Solve the workloads as one batch from the zero, diffusion and learned
+    starts; returns {start: {"outer": [...], "cg": [...], "ms": t, "used": n}}."""
+    import torch
+    probs = [problem_from_workload(ctx, wl) for wl in workloads]
+    batch = L.smm_batch_create(ctx, probs)
+    L.smm_batch_set_warmstart(batch, net)
+    out = {}
+    for name, start in (("zero", L.SMM_START_ZERO), ("diffusion", L.SMM_START_DIFFUSION),
+                        ("learned", L.SMM_START_LEARNED)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, infos = L.smm_batch_solve(batch, solve_opts(tol, start=start), raise_on_noconv=False)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        rec = {"status": rc, "ms": ms, "outer": [i["iterations"] for i in infos],
+               "cg": [i["cg_iterations_total"] for i in infos]}
+        if start == L.SMM_START_LEARNED:
+            rec["used"] = int(L.smm_batch_warmstart_used(batch).sum())
+        out[name] = rec
+        log(f"[warmstart] {name:9s} start: {ms:9.1f} ms, outer its mean {np.mean(rec['outer']):.2f} "
+            f"max {max(rec['outer'])}, CG its mean {np.mean(rec['cg']):.0f}"
+            + (f", learned start kept for {rec['used']}/{len(workloads)}" if "used" in rec else ""))
+    L.smm_batch_set_warmstart(batch, None)
+    L.smm_batch_destroy(batch)
+    return out
+
+
 def _seeds(spec: str):
     a, b = spec.split(":")
     return list(range(int(a), int(b)))
@@ -179,9 +207,13 @@ def main(argv=None):
     t0 = time.time()
     net, hist, w = train(ctx, X, T, epochs=a.epochs, batch=a.batch, lr=a.lr, log=log, Xval=Xv, Tval=Tv)
     ttrain = time.time() - t0
+    del X, T, Xv, Tv
+    torch.cuda.empty_cache()
+    held = compare_starts(ctx, net, [config_blobs(s) for s in va], log=log)
     save(net, a.out, {"train_seeds": a.train_seeds, "val_seeds": a.val_seeds, "epochs": a.epochs,
                       "batch": a.batch, "lr": a.lr, "history": hist, "chan_weight": w.tolist(),
-                      "workload": "blobs 64x64 p=2 S8", "t_generate_s": tgen, "t_train_s": ttrain})
+                      "workload": "blobs 64x64 p=2 S8", "t_generate_s": tgen, "t_train_s": ttrain,
+                      "held_out": held})
     log(f"[warmstart] saved {a.out} (generate {tgen:.1f} s, train {ttrain:.1f} s)")
     return 0
 
