@@ -110,10 +110,16 @@ typedef struct {
     int start;           /* SMM_START_* */
     int delta_sweeps;    /* 1: sweep only the change of the scattering source and
                             accumulate the moments in FP64 (default for FP32_SWEEP) */
-    int use_graph;       /* 1: replay each outer iteration from a captured hipGraph */
+    int use_graph;       /* 1: replay the PCG iteration chunks of the typed (batched) path
+                            from captured hipGraphs */
     int moment_path;     /* 0: typed blocks on uniform Cartesian meshes with isotropic
                             sources (batched kernels), else per-element operators;
                             1: always per-element operators */
+    double inner_adapt;  /* > 0: the moment solve of outer iteration k stops at the
+                            relative residual max(inner_tol, inner_adapt * r_{k-1})
+                            (r_0 = 1; per problem in a batch), and the solves that
+                            build a diffusion or learned start at
+                            max(inner_tol, inner_adapt); 0: always inner_tol */
 } smm_solve_opts;
 
 typedef struct {
@@ -250,6 +256,10 @@ int smm_batch_units(const smm_batch* batch, double* units);
  * side, ms[2] PCG moment solve, ms[3] residual and shift.  cg_iterations
  * (nullable) receives the number of batched PCG iterations launched. */
 int smm_batch_phase_times(const smm_batch* batch, double* ms, long* cg_iterations);
+/* Outer residual r_k (and PCG iterations, nullable) of each outer iteration of
+ * problem k in the last smm_batch_solve: the first min(max_len, *len) entries
+ * are written, *len receives the iteration count. */
+int smm_batch_history(const smm_batch* batch, int k, int max_len, double* residual, int* cg_iterations, int* len);
 /* Average duration (HIP events on the stream each kernel runs on) of reps
  * back-to-back launches of one batched kernel: SMM_KERNEL_SWEEP_FP32 /
  * SMM_KERNEL_SWEEP_FP64 (one whole batched sweep), SMM_KERNEL_CG_SPMV (the

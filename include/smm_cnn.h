@@ -6,11 +6,11 @@
  * small convolutional network that predicts, per element of a uniform
  * Cartesian mesh, the nodal correction of the converged scalar flux over the
  * diffusion start and the nodal SMM correction source (the part of the
- * right-hand side of eq. ipsmm built from T and beta).  The start is then the
- * moment system solved with that predicted correction source, warm-started
- * from the predicted flux; the diffusion start (zero correction source) is
- * the fallback, chosen per problem by the smaller first moment-system
- * residual.  The converged answer does not depend on the start.
+ * right-hand side of eq. ipsmm built from T and beta).  The start is the
+ * diffusion start (the moment system with zero correction source) plus the
+ * predicted flux correction; the correction-source channels are an auxiliary
+ * training target.  A problem whose prediction is not finite keeps the
+ * diffusion start.  The converged answer does not depend on the start.
  *
  * Network: a stack of 3x3 convolutions (zero padding, stride 1), ReLU after
  * every layer but the last, NHWC activations in bfloat16, FP32 accumulation
@@ -99,7 +99,8 @@ int smm_batch_warmstart_targets(smm_batch* batch, int first, int count, float* t
  * network must outlive its use by the batch. */
 int smm_batch_set_warmstart(smm_batch* batch, smm_cnn* net);
 /* After a solve with SMM_START_LEARNED: used[k] = 1 if problem k started
- * from the learned start, 0 if it fell back to the diffusion start. */
+ * from the learned start, 0 if it fell back to the diffusion start (non-finite
+ * prediction). */
 int smm_batch_warmstart_used(const smm_batch* batch, int* used);
 
 #ifdef __cplusplus

@@ -244,6 +244,7 @@ void smm_default_opts(smm_solve_opts* o) {
     o->delta_sweeps = 0;
     o->use_graph = 0;
     o->moment_path = 0;
+    o->inner_adapt = 0.0;
 }
 
 }  // extern "C"
@@ -607,9 +608,11 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     double r = 0, rabs = 0;
     int it = 0;
     int status = SMM_ENOCONV;
+    double r_prev = 1.0;
     for (it = 1; it <= o.max_outer; ++it) {
         int cgi = 0;
-        if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, o.inner_tol, o.max_inner, &cgi))) return rc;
+        const double tol_k = o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt * r_prev) : o.inner_tol;
+        if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, tol_k, o.max_inner, &cgi))) return rc;
         cg_total += cgi;
         cg_max = std::max(cg_max, cgi);
         // residual (a7)
@@ -624,6 +627,7 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
         r = ro[1] > 0 ? ro[0] / ro[1] : (ro[0] == 0 ? 0.0 : INFINITY);
         if (!std::isfinite(r) || !std::isfinite(rabs)) { status = SMM_ENAN; break; }
         if (r < o.outer_tol) { status = SMM_OK; break; }
+        r_prev = r;
     }
     D.last_varphi = D.varphi;
     if (it > o.max_outer) it = o.max_outer;

@@ -109,6 +109,7 @@ struct smm_batch {
     std::vector<int> active;
     double* d_scal = nullptr;
     double* d_rout = nullptr;
+    double* d_tol = nullptr;       // per-problem PCG tolerance (inner_adapt)
     std::vector<Group> groups;
     CartSweepArgs* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -121,12 +122,19 @@ struct smm_batch {
     bool have_diff = false;
     std::vector<int> ws_used;
     float *d_wsx = nullptr, *d_wsy = nullptr;
-    int* d_wsflag = nullptr;
     // time of the outer-iteration phases of the last solve (ms): source + sweep,
     // moments + closures + right-hand side, PCG, residual
     hipEvent_t pev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     double phase_ms[4] = {0, 0, 0, 0};
     long cg_batched_its = 0;   // batched PCG iterations launched in the last solve
+    bool use_ptol = false;     // PCG stops at the per-problem tolerances d_tol
+    std::vector<std::vector<double>> hist;   // per problem: outer residual of each iteration
+    std::vector<std::vector<int>> cg_hist;   // per problem: PCG iterations of each outer iteration
+    // PCG iteration chunks replayed from captured graphs (use_graph), keyed by
+    // (iterations in the chunk, per-problem tolerances on)
+    bool use_graph = false;
+    hipStream_t cap = nullptr;
+    std::map<std::pair<int, bool>, hipGraphExec_t> cg_graphs;
 };
 
 namespace {
@@ -143,6 +151,7 @@ BatchLaunch launch_desc(smm_batch* B) {
     L.nmw = B->nmw;
     L.bq0 = B->d_bq0;
     L.mw0 = B->d_mw0;
+    L.ptol = B->use_ptol ? B->d_tol : nullptr;
     return L;
 }
 
@@ -181,7 +190,7 @@ int put(smm_ctx* c, void* dst, const void* src, size_t bytes) {
 void batch_free(smm_batch* B) {
     if (!B) return;
     if (B->pool) (void)hipFree(B->pool);
-    for (void* p : {(void*)B->d_wsx, (void*)B->d_wsy, (void*)B->d_wsflag})
+    for (void* p : {(void*)B->d_wsx, (void*)B->d_wsy})
         if (p) (void)hipFree(p);
     for (auto& s : B->side)
         if (s) (void)hipStreamDestroy(s);
@@ -190,6 +199,8 @@ void batch_free(smm_batch* B) {
         if (e) (void)hipEventDestroy(e);
     for (auto& e : B->pev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& g : B->cg_graphs) (void)hipGraphExecDestroy(g.second);
+    if (B->cap) (void)hipStreamDestroy(B->cap);
     delete B;
 }
 
@@ -273,6 +284,7 @@ int batch_build(smm_batch* B) {
     pool.req(&B->d_active, sizeof(int) * np);
     pool.req(&B->d_scal, sizeof(double) * 16 * np);
     pool.req(&B->d_rout, sizeof(double) * 2 * np);
+    pool.req(&B->d_tol, sizeof(double) * np);
     for (int f = 0; f < 2; ++f)
         for (int g = 0; g < 2; ++g) pool.req(&B->d_args[f][g], sizeof(CartSweepArgs) * np);
     // sweep groups by order
@@ -553,7 +565,31 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
         }
         if (all || done_its >= max_inner) break;
         const int k = std::min(chunk, max_inner - done_its);
-        HIPCHK(c, b_cg_iterations(L, k, c->stream));
+        if (B->use_graph) {
+            // capture the chunk once on a private stream, then replay it on the
+            // context's stream (kernel nodes only)
+            const auto key = std::make_pair(k, L.ptol != nullptr);
+            auto it = B->cg_graphs.find(key);
+            if (it == B->cg_graphs.end()) {
+                if (!B->cap) HIPCHK(c, hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                hipGraphExec_t ge = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
+                const hipError_t e1 = b_cg_iterations(L, k, B->cap);
+                const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
+                if (e1 != hipSuccess || e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return fail(c, SMM_EHIP, "PCG graph capture failed");
+                }
+                const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e3 != hipSuccess) return fail(c, SMM_EHIP, "PCG graph instantiation failed");
+                it = B->cg_graphs.emplace(key, ge).first;
+            }
+            HIPCHK(c, hipGraphLaunch(it->second, c->stream));
+        } else {
+            HIPCHK(c, b_cg_iterations(L, k, c->stream));
+        }
         done_its += k;
         B->cg_batched_its += k;
         chunk = std::min(chunk * 2, 64);
@@ -587,39 +623,22 @@ int batch_diffusion(smm_batch* B, double tol, int max_inner, std::vector<int>& i
     }
     int rc;
     if ((rc = batch_cg(B, tol, max_inner, its))) return rc;
-    HIPCHK(c, b_ws_stage(launch_desc(B), 3, nullptr, c->stream));
+    HIPCHK(c, b_ws_store_diffusion(launch_desc(B), c->stream));
     B->have_diff = true;
     return SMM_OK;
 }
 
-// First moment-system residual of the start held in varphi: one sweep, the
-// moments, closures and right-hand side b(varphi), then ||b - A varphi|| / ||b||.
-int start_residuals(smm_batch* B, bool fp64, std::vector<double>& res, std::vector<double>& sc) {
-    smm_ctx* c = B->ctx;
-    const BatchLaunch L = launch_desc(B);
-    int rc;
-    HIPCHK(c, b_source(fp64, L, false, c->stream));
-    if ((rc = batch_sweep(B, fp64, true))) return rc;
-    HIPCHK(c, b_moments(fp64, L, true, true, c->stream));
-    HIPCHK(c, b_closures_rhs(L, c->stream));
-    HIPCHK(c, b_copy_x(L, c->stream));
-    HIPCHK(c, b_cg_start(L, 0.0, c->stream));
-    sc.resize(16 * (size_t)B->nprob);
-    HIPCHK(c, hipMemcpyAsync(sc.data(), B->d_scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    res.resize(B->nprob);
-    for (int b = 0; b < B->nprob; ++b) {
-        const double rr = sc[16 * b + 3], bb = sc[16 * b + 2];
-        res[b] = bb > 0 ? std::sqrt(rr / bb) : INFINITY;
-    }
-    return SMM_OK;
+// Tolerance of the moment solves that build a start (diffusion, learned): a
+// start only seeds the fixed point, so with inexact inner solves it is solved
+// to the first outer iteration's tolerance.
+double start_tol(const smm_solve_opts& o) {
+    return o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt) : o.inner_tol;
 }
 
 // Learned start: the network predicts, from the features of the diffusion
-// start, the nodal flux correction and correction source; the candidate is the
-// moment system solved with the predicted source (CG started from the
-// predicted flux).  Each problem keeps the candidate (learned or diffusion)
-// with the smaller first moment-system residual.  Adds the CG iterations spent.
+// start, the nodal correction of the converged flux over it; the start is
+// varphi_D + s_K * prediction.  A problem whose prediction is not finite keeps
+// the diffusion start.  Adds the CG iterations spent on varphi_D.
 int learned_start(smm_batch* B, const smm_solve_opts& o, std::vector<int>& cg_its) {
     smm_ctx* c = B->ctx;
     smm_cnn* net = B->ws_net;
@@ -632,13 +651,11 @@ int learned_start(smm_batch* B, const smm_solve_opts& o, std::vector<int>& cg_it
     const long ne = (long)nx * ny;
     if (!B->d_wsx) {
         if (hipMalloc((void**)&B->d_wsx, sizeof(float) * np * ne * nf) != hipSuccess ||
-            hipMalloc((void**)&B->d_wsy, sizeof(float) * np * ne * nt) != hipSuccess ||
-            hipMalloc((void**)&B->d_wsflag, sizeof(int) * np) != hipSuccess)
+            hipMalloc((void**)&B->d_wsy, sizeof(float) * np * ne * nt) != hipSuccess)
             return fail(c, SMM_ENOMEM, "warm-start buffers");
     }
-    const bool fp64 = o.precision == SMM_FP64;
     std::vector<int> its;
-    if ((rc = batch_diffusion(B, o.inner_tol, o.max_inner, its))) return rc;
+    if ((rc = batch_diffusion(B, start_tol(o), o.max_inner, its))) return rc;
     for (int b = 0; b < np; ++b) cg_its[b] += its[b];
     const BatchLaunch L = launch_desc(B);
     HIPCHK(c, hipMemsetAsync(B->d_scal, 0, sizeof(double) * 16 * np, c->stream));
@@ -649,23 +666,11 @@ int learned_start(smm_batch* B, const smm_solve_opts& o, std::vector<int>& cg_it
             return rc;
     }
     HIPCHK(c, b_ws_apply(L, B->d_wsy, nt, c->stream));
-    if ((rc = batch_cg(B, o.inner_tol, o.max_inner, its))) return rc;
-    for (int b = 0; b < np; ++b) cg_its[b] += its[b];
-    std::vector<double> rl, rd, sc;
-    HIPCHK(c, b_ws_stage(L, 0, nullptr, c->stream));
-    if ((rc = start_residuals(B, fp64, rl, sc))) return rc;
-    std::vector<int> bad(np);
-    for (int b = 0; b < np; ++b) bad[b] = sc[16 * b + 11] != 0.0;
-    HIPCHK(c, b_ws_stage(L, 1, nullptr, c->stream));
-    if ((rc = start_residuals(B, fp64, rd, sc))) return rc;
-    std::vector<int> flag(np);
+    std::vector<double> sc(16 * (size_t)np);
+    HIPCHK(c, hipMemcpyAsync(sc.data(), B->d_scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     B->ws_used.assign(np, 0);
-    for (int b = 0; b < np; ++b) {
-        flag[b] = bad[b] || !(rl[b] < rd[b]);
-        B->ws_used[b] = !flag[b];
-    }
-    if ((rc = put(c, B->d_wsflag, flag.data(), sizeof(int) * np))) return rc;
-    HIPCHK(c, b_ws_stage(L, 2, B->d_wsflag, c->stream));
+    for (int b = 0; b < np; ++b) B->ws_used[b] = sc[16 * b + 11] == 0.0;
     return SMM_OK;
 }
 
@@ -683,6 +688,11 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     if ((rc = batch_autotune(B, fp64))) return rc;
     B->active.assign(np, 1);
     B->ws_used.assign(np, 0);
+    B->use_graph = o.use_graph != 0;
+    struct GraphReset {
+        smm_batch* b;
+        ~GraphReset() { b->use_graph = false; }
+    } graph_reset{B};
     if ((rc = put(c, B->d_active, B->active.data(), sizeof(int) * np))) return rc;
     const BatchLaunch L = launch_desc(B);
     std::vector<int> its;
@@ -703,7 +713,7 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     }
     std::vector<int> start_its(np, 0);
     if (o.start == SMM_START_DIFFUSION) {
-        if ((rc = batch_cg(B, o.inner_tol, o.max_inner, its))) return rc;
+        if ((rc = batch_cg(B, start_tol(o), o.max_inner, its))) return rc;
         for (int b = 0; b < np; ++b) {
             const PerProb& q = B->pp[b];
             HIPCHK(c, hipMemcpyAsync(q.varphi, q.x, sizeof(double) * B->hP[b].L, hipMemcpyDeviceToDevice, c->stream));
@@ -715,12 +725,15 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     for (int b = 0; b < np; ++b) inf[b].cg_iterations_total = start_its[b];
     auto t1 = std::chrono::steady_clock::now();
     std::vector<double> ro(2 * (size_t)np);
+    std::vector<double> r_prev(np, 1.0), tol_k(np, o.inner_tol);
     int nactive = np;
     int it;
     for (auto& e : B->pev)
         if (!e) HIPCHK(c, hipEventCreate(&e));
     for (double& t : B->phase_ms) t = 0;
     B->cg_batched_its = 0;
+    B->hist.assign(np, {});
+    B->cg_hist.assign(np, {});
     for (it = 1; it <= o.max_outer && nactive > 0; ++it) {
         const bool first = (it == 1) || !delta;
         HIPCHK(c, hipEventRecord(B->pev[0], c->stream));
@@ -731,7 +744,14 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
         HIPCHK(c, b_closures_rhs(L, c->stream));
         HIPCHK(c, b_copy_x(L, c->stream));
         HIPCHK(c, hipEventRecord(B->pev[2], c->stream));
-        if ((rc = batch_cg(B, o.inner_tol, o.max_inner, its))) return rc;
+        if (o.inner_adapt > 0) {
+            for (int b = 0; b < np; ++b) tol_k[b] = std::max(o.inner_tol, o.inner_adapt * r_prev[b]);
+            HIPCHK(c, hipMemcpyAsync(B->d_tol, tol_k.data(), sizeof(double) * np, hipMemcpyHostToDevice, c->stream));
+            B->use_ptol = true;
+        }
+        rc = batch_cg(B, o.inner_tol, o.max_inner, its);
+        B->use_ptol = false;
+        if (rc) return rc;
         HIPCHK(c, hipEventRecord(B->pev[3], c->stream));
         HIPCHK(c, b_residual(L, B->d_rout, c->stream));
         HIPCHK(c, hipMemcpyAsync(ro.data(), B->d_rout, sizeof(double) * ro.size(), hipMemcpyDeviceToHost, c->stream));
@@ -750,6 +770,9 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
             const double r = xmax > 0 ? rabs / xmax : (rabs == 0 ? 0.0 : INFINITY);
             inf[b].iterations = it;
             inf[b].residual = r;
+            B->hist[b].push_back(r);
+            B->cg_hist[b].push_back(its[b]);
+            r_prev[b] = std::isfinite(r) ? r : 1.0;
             inf[b].residual_abs = rabs;
             inf[b].cg_iterations_total += its[b];
             inf[b].cg_iterations_max = std::max(inf[b].cg_iterations_max, its[b]);
@@ -971,6 +994,19 @@ int smm_batch_warmstart_used(const smm_batch* batch, int* used) {
     if (!batch || !used) return SMM_EINVAL;
     if (batch->ws_used.size() != (size_t)batch->nprob) return SMM_ESTATE;
     for (int b = 0; b < batch->nprob; ++b) used[b] = batch->ws_used[b];
+    return SMM_OK;
+}
+
+int smm_batch_history(const smm_batch* batch, int k, int max_len, double* residual, int* cg_iterations, int* len) {
+    if (!batch || k < 0 || k >= batch->nprob || max_len < 0 || !len) return SMM_EINVAL;
+    if (batch->hist.size() != (size_t)batch->nprob) return SMM_ESTATE;
+    const auto& h = batch->hist[k];
+    const int n = (int)std::min<size_t>(h.size(), (size_t)max_len);
+    for (int i = 0; i < n; ++i) {
+        if (residual) residual[i] = h[i];
+        if (cg_iterations) cg_iterations[i] = batch->cg_hist[k][i];
+    }
+    *len = (int)h.size();
     return SMM_OK;
 }
 

@@ -1538,27 +1538,85 @@ __global__ __launch_bounds__(BT) void b_cg_red_init(BatchLaunch B, double tol) {
         s[1] = rz;
         s[2] = bb;
         s[3] = rr;
-        s[7] = tol * tol * bb;
+        const double t = B.ptol ? B.ptol[prob] : tol;
+        s[7] = t * t * bb;
         s[4] = (!B.active[prob] || rr <= s[7]) ? 1.0 : 0.0;
         s[5] = 0.0;
         s[6] = 0.0;
     }
 }
 
+// q = A p and the block's partial sum of p.q.  The p values of the block's
+// elements and of their four neighbours are staged in LDS once; thread
+// (pair, i) then computes node i of two neighbouring elements, so one load of
+// a column entry of a typed block serves both when they share the type.
+// (The per-element blocks per workgroup, BT / n, are even for n = 4, 9, 16, 25.)
+__device__ __forceinline__ void typed_dot2(const double* __restrict__ ca, const double* __restrict__ cb, bool same,
+                                           const double* __restrict__ xa, const double* __restrict__ xb, int n,
+                                           double& ya, double& yb) {
+    if (same) {
+        for (int j = 0; j < n; ++j) {
+            const double m = ca[j * n];
+            ya += m * xa[j];
+            yb += m * xb[j];
+        }
+    } else {
+        for (int j = 0; j < n; ++j) {
+            ya += ca[j * n] * xa[j];
+            yb += cb[j * n] * xb[j];
+        }
+    }
+}
+
 __global__ __launch_bounds__(BT) void b_cg_k1(BatchLaunch B) {
     __shared__ double red[BT];
-    const EB m = eb_map(B);
-    if (cg_skip(B, m.prob)) return;  // block-uniform
-    const BProb& P = B.P[m.prob];
+    __shared__ double xs[5 * BT];  // [element][self, 4 neighbours][n]
+    const int prob = B.blk2p[blockIdx.x];
+    if (cg_skip(B, prob)) return;  // block-uniform
+    const BProb& P = B.P[prob];
+    const int n = P.n, epb = BT / n, t = threadIdx.x;
+    const int K0 = (blockIdx.x - P.blk0) * epb;
+    {
+        const int le = t / n, i = t - le * n, K = K0 + le;
+        if (le < epb && K < P.ne) {
+            double* xk = xs + le * 5 * n;
+            xk[i] = P.p[(long)K * n + i];
+            for (int f = 0; f < 4; ++f)
+                xk[(f + 1) * n + i] = P.nid[K * 4 + f] >= 0 ? P.p[(long)nbr_of(P, K, f) * n + i] : 0.0;
+        }
+    }
+    __syncthreads();
     double pq = 0;
-    if (m.K >= 0) {
-        const long t = (long)m.K * P.n + m.i;
-        const double v = typed_row(P, P.p, m.K, m.i);
-        P.q[t] = v;
-        pq = P.p[t] * v;
+    const int pr = t / n, i = t - pr * n;
+    const int la = 2 * pr, lb = la + 1, Ka = K0 + la, Kb = K0 + lb;
+    if (la < epb && Ka < P.ne) {
+        const bool vb = lb < epb && Kb < P.ne;
+        const double* xa = xs + la * 5 * n;
+        const double* xb = vb ? xs + lb * 5 * n : xa;
+        const int Kc = vb ? Kb : Ka;
+        double ya = 0, yb = 0;
+        const int sa = P.sid[Ka], sb = P.sid[Kc];
+        typed_dot2(P.ip_self + (long)sa * n * n + i, P.ip_self + (long)sb * n * n + i, sa == sb, xa, xb, n, ya, yb);
+        for (int f = 0; f < 4; ++f) {
+            const int ta = P.nid[Ka * 4 + f], tb = P.nid[Kc * 4 + f];
+            if (ta >= 0 && tb >= 0) {
+                typed_dot2(P.ip_nbr + (long)ta * n * n + i, P.ip_nbr + (long)tb * n * n + i, ta == tb,
+                           xa + (f + 1) * n, xb + (f + 1) * n, n, ya, yb);
+            } else {
+                double dummy = 0;
+                if (ta >= 0) typed_dot2(P.ip_nbr + (long)ta * n * n + i, nullptr, true, xa + (f + 1) * n, xa + (f + 1) * n, n, ya, dummy);
+                if (tb >= 0) typed_dot2(P.ip_nbr + (long)tb * n * n + i, nullptr, true, xb + (f + 1) * n, xb + (f + 1) * n, n, yb, dummy);
+            }
+        }
+        P.q[(long)Ka * n + i] = ya;
+        pq = xa[i] * ya;
+        if (vb) {
+            P.q[(long)Kb * n + i] = yb;
+            pq += xb[i] * yb;
+        }
     }
     pq = b_block_sum(pq, red);
-    if (threadIdx.x == 0) B.part[blockIdx.x] = pq;
+    if (t == 0) B.part[blockIdx.x] = pq;
 }
 
 __global__ __launch_bounds__(BT) void b_cg_red1(BatchLaunch B) {
@@ -1578,35 +1636,51 @@ __global__ __launch_bounds__(BT) void b_cg_red1(BatchLaunch B) {
     }
 }
 
+// x += alpha p, r -= alpha q, z = D^-1 r (block-Jacobi; two elements per
+// thread as in b_cg_k1) and the partial sums of r.z and r.r.
 __global__ __launch_bounds__(BT) void b_cg_k2(BatchLaunch B) {
     __shared__ double red[BT];
     __shared__ double rl[BT];
-    const EB m = eb_map(B);
-    if (cg_skip(B, m.prob)) return;
-    const BProb& P = B.P[m.prob];
+    const int prob = B.blk2p[blockIdx.x];
+    if (cg_skip(B, prob)) return;  // block-uniform
+    const BProb& P = B.P[prob];
     const double alpha = P.scal[8];
-    const int n = P.n;
-    double rnew = 0;
-    if (m.K >= 0) {
-        const long t = (long)m.K * n + m.i;
-        P.x[t] += alpha * P.p[t];
-        rnew = P.r[t] - alpha * P.q[t];
-        P.r[t] = rnew;
-    }
-    rl[threadIdx.x] = rnew;
-    __syncthreads();
-    double rz = 0, rr = 0;
-    if (m.K >= 0) {
-        const double* D = P.dinv + (long)P.sid[m.K] * n * n + m.i;
-        double z = 0;
-        for (int j = 0; j < n; ++j) z += D[j * n] * rl[m.e0 + j];
-        P.z[(long)m.K * n + m.i] = z;
-        rz = rnew * z;
+    const int n = P.n, epb = BT / n, t = threadIdx.x;
+    const int K0 = (blockIdx.x - P.blk0) * epb;
+    double rr = 0;
+    {
+        const int le = t / n, i = t - le * n, K = K0 + le;
+        double rnew = 0;
+        if (le < epb && K < P.ne) {
+            const long g = (long)K * n + i;
+            P.x[g] += alpha * P.p[g];
+            rnew = P.r[g] - alpha * P.q[g];
+            P.r[g] = rnew;
+        }
+        rl[t] = rnew;
         rr = rnew * rnew;
+    }
+    __syncthreads();
+    double rz = 0;
+    const int pr = t / n, i = t - pr * n;
+    const int la = 2 * pr, lb = la + 1, Ka = K0 + la, Kb = K0 + lb;
+    if (la < epb && Ka < P.ne) {
+        const bool vb = lb < epb && Kb < P.ne;
+        const double* ra = rl + la * n;
+        const double* rb = vb ? rl + lb * n : ra;
+        const int sa = P.sid[Ka], sb = P.sid[vb ? Kb : Ka];
+        double za = 0, zb = 0;
+        typed_dot2(P.dinv + (long)sa * n * n + i, P.dinv + (long)sb * n * n + i, sa == sb, ra, rb, n, za, zb);
+        P.z[(long)Ka * n + i] = za;
+        rz = ra[i] * za;
+        if (vb) {
+            P.z[(long)Kb * n + i] = zb;
+            rz += rb[i] * zb;
+        }
     }
     rz = b_block_sum(rz, red);
     rr = b_block_sum(rr, red);
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         B.part[B.nblocks + blockIdx.x] = rz;
         B.part[2 * B.nblocks + blockIdx.x] = rr;
     }
@@ -1705,46 +1779,40 @@ __global__ __launch_bounds__(BT) void b_ws_targets_kernel(BatchLaunch B, int fir
     pt[P.n + m.i] = (float)((P.b[t] - P.bfix[t]) / (P.hxhy * sK));
 }
 
-// x = varphi_D + s_K y_i, b = b_fixed + h_x h_y s_K y_{n+i}; scal[11] = 1 on a
-// non-finite prediction
+// Learned start: varphi = varphi_D + s_K y_i (the predicted flux correction);
+// a non-finite prediction keeps varphi_D for the element and sets scal[11] = 1.
 __global__ __launch_bounds__(BT) void b_ws_apply_kernel(BatchLaunch B, const float* Y, int nt) {
     const EB m = eb_map(B);
     if (m.K < 0 || !B.active[m.prob]) return;
     const BProb& P = B.P[m.prob];
     const double sK = ws_scale(P, m.K);
     const long t = (long)m.K * P.n + m.i;
-    const float* py = Y + ((long)m.prob * P.ne + m.K) * nt;
-    const double y0 = py[m.i], y1 = py[P.n + m.i];
-    if (!isfinite(y0) || !isfinite(y1)) {
+    const double y = Y[((long)m.prob * P.ne + m.K) * nt + m.i];
+    if (!isfinite(y)) {
         P.scal[11] = 1.0;
-        P.x[t] = P.vdiff[t];
-        P.b[t] = P.bfix[t];
+        P.varphi[t] = P.vdiff[t];
         return;
     }
-    P.x[t] = P.vdiff[t] + sK * y0;
-    P.b[t] = P.bfix[t] + P.hxhy * sK * y1;
+    P.varphi[t] = P.vdiff[t] + sK * y;
 }
 
-// One kernel per staging mode (a compile-time constant): with the mode as a
-// run-time argument the compiled code stored mode 3 into varphi.
-template <int MODE>
-__global__ __launch_bounds__(BT) void b_ws_stage_kernel(BatchLaunch B, const int* flag) {
+// a problem with any non-finite prediction starts from varphi_D everywhere
+__global__ __launch_bounds__(BT) void b_ws_fallback_kernel(BatchLaunch B) {
+    const EB m = eb_map(B);
+    if (m.K < 0 || !B.active[m.prob]) return;
+    const BProb& P = B.P[m.prob];
+    if (P.scal[11] == 0.0) return;
+    const long t = (long)m.K * P.n + m.i;
+    P.varphi[t] = P.vdiff[t];
+}
+
+// varphi_D = x (after the diffusion solve)
+__global__ __launch_bounds__(BT) void b_ws_store_diffusion_kernel(BatchLaunch B) {
     const EB m = eb_map(B);
     if (m.K < 0 || !B.active[m.prob]) return;
     const BProb& P = B.P[m.prob];
     const long t = (long)m.K * P.n + m.i;
-    if constexpr (MODE == 0) {
-        const double v = P.x[t];
-        P.varphi_prev[t] = v;
-        P.varphi[t] = v;
-    } else if constexpr (MODE == 1) {
-        P.varphi[t] = P.vdiff[t];
-    } else if constexpr (MODE == 2) {
-        P.varphi[t] = flag[m.prob] ? P.vdiff[t] : P.varphi_prev[t];
-        P.varphi_prev[t] = 0.0;
-    } else {
-        P.vdiff[t] = P.x[t];
-    }
+    P.vdiff[t] = P.x[t];
 }
 
 hipError_t b_ws_features(const BatchLaunch& B, int first, int count, float* X, int nf, hipStream_t s) {
@@ -1760,17 +1828,12 @@ hipError_t b_ws_targets(const BatchLaunch& B, int first, int count, float* T, in
 
 hipError_t b_ws_apply(const BatchLaunch& B, const float* Y, int nt, hipStream_t s) {
     hipLaunchKernelGGL(b_ws_apply_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, Y, nt);
+    hipLaunchKernelGGL(b_ws_fallback_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
     return hipGetLastError();
 }
 
-hipError_t b_ws_stage(const BatchLaunch& B, int mode, const int* flag, hipStream_t s) {
-    switch (mode) {
-        case 0: hipLaunchKernelGGL(b_ws_stage_kernel<0>, dim3(B.nblocks), dim3(BT), 0, s, B, flag); break;
-        case 1: hipLaunchKernelGGL(b_ws_stage_kernel<1>, dim3(B.nblocks), dim3(BT), 0, s, B, flag); break;
-        case 2: hipLaunchKernelGGL(b_ws_stage_kernel<2>, dim3(B.nblocks), dim3(BT), 0, s, B, flag); break;
-        case 3: hipLaunchKernelGGL(b_ws_stage_kernel<3>, dim3(B.nblocks), dim3(BT), 0, s, B, flag); break;
-        default: return hipErrorInvalidValue;
-    }
+hipError_t b_ws_store_diffusion(const BatchLaunch& B, hipStream_t s) {
+    hipLaunchKernelGGL(b_ws_store_diffusion_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
     return hipGetLastError();
 }
 

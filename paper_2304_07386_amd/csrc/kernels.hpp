@@ -131,6 +131,7 @@ struct BatchLaunch {
     long nmw;                      // total moments wavefronts
     const long* bq0;               // [nprob] prefix (device copy)
     const long* mw0;               // [nprob] prefix (device copy)
+    const double* ptol;            // [nprob] per-problem PCG tolerance (nullable: the scalar one)
 };
 
 hipError_t b_source(bool fp64, const BatchLaunch& B, bool delta, hipStream_t s);
@@ -145,14 +146,12 @@ hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s);
 hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s);
 hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s);                // one q = A p launch
 hipError_t b_residual(const BatchLaunch& B, double* out, hipStream_t s);   // out[2*nprob]
-// warm start: features / targets of problems [first, first + count), start from the
-// network output, and staging of the two start candidates (mode 0: varphi_prev =
-// varphi = x; 1: varphi = vdiff; 2: varphi = flag ? vdiff : varphi_prev, varphi_prev = 0;
-// 3: vdiff = x)
+// warm start: features / targets of problems [first, first + count), the start from
+// the network output (varphi = varphi_D + s_K y), and varphi_D = x
 hipError_t b_ws_features(const BatchLaunch& B, int first, int count, float* X, int nf, hipStream_t s);
 hipError_t b_ws_targets(const BatchLaunch& B, int first, int count, float* T, int nt, hipStream_t s);
 hipError_t b_ws_apply(const BatchLaunch& B, const float* Y, int nt, hipStream_t s);
-hipError_t b_ws_stage(const BatchLaunch& B, int mode, const int* flag, hipStream_t s);
+hipError_t b_ws_store_diffusion(const BatchLaunch& B, hipStream_t s);
 hipError_t zero_ints(int* p, int n, hipStream_t s);
 
 }  // namespace smm

@@ -30,6 +30,7 @@ EXPORTED = [
     "smm_set_sweep_path", "smm_time_sweep", "smm_debug_typed_dense", "smm_debug_corr_dense",
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
+    "smm_batch_history",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
@@ -57,7 +58,8 @@ class smm_problem_dims(C.Structure):
 class smm_solve_opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("outer_tol", C.c_double), ("max_outer", C.c_int),
                 ("inner_tol", C.c_double), ("max_inner", C.c_int), ("start", C.c_int),
-                ("delta_sweeps", C.c_int), ("use_graph", C.c_int), ("moment_path", C.c_int)]
+                ("delta_sweeps", C.c_int), ("use_graph", C.c_int), ("moment_path", C.c_int),
+                ("inner_adapt", C.c_double)]
 
 
 class smm_solve_info(C.Structure):
@@ -115,6 +117,7 @@ def load_library(path: str = LIB_PATH):
         "smm_batch_units": (ip, [vp, dp]),
         "smm_batch_phase_times": (ip, [vp, dp, C.POINTER(C.c_long)]),
         "smm_batch_time_kernel": (ip, [vp, ip, ip, dp]),
+        "smm_batch_history": (ip, [vp, ip, ip, vp, vp, C.POINTER(ip)]),
         "smm_cnn_create": (ip, [vp, ip, C.POINTER(ip), ip, ip, ip, C.POINTER(vp)]),
         "smm_cnn_destroy": (ip, [vp]),
         "smm_cnn_num_params": (ip, [vp, C.POINTER(C.c_size_t)]),
@@ -410,6 +413,16 @@ def smm_batch_phase_times(batch: Batch):
     n = C.c_long()
     _check(load_library().smm_batch_phase_times(batch.handle, ms, C.byref(n)), batch.ctx)
     return list(ms), n.value
+
+
+def smm_batch_history(batch: Batch, k: int):
+    """(outer residuals, PCG iterations) of each outer iteration of problem k."""
+    n = C.c_int()
+    _check(load_library().smm_batch_history(batch.handle, k, 0, None, None, C.byref(n)), batch.ctx)
+    r = np.zeros(n.value)
+    c = np.zeros(n.value, dtype=np.int32)
+    _check(load_library().smm_batch_history(batch.handle, k, n.value, _ptr(r), _ptr(c), C.byref(n)), batch.ctx)
+    return r, c
 
 
 def smm_batch_time_kernel(batch: Batch, kernel: int, reps: int) -> float:

@@ -4,7 +4,9 @@ library's own network kernels, and weight files.
 Data: for each layout, the diffusion start varphi_D and the converged SMM
 solution give the network's features and targets (see include/smm_cnn.h).
 Training: Adam on the weighted mean squared error, channel weights 1/variance
-of each target channel over the training set.  Weights are stored as .npz
+of each target channel over the training set, the correction-source channels
+(an auxiliary target: the start uses the flux channels) scaled down by
+AUX_WEIGHT.  Weights are stored as .npz
 (float32 parameters plus JSON metadata), loaded without pickle.
 
 Usage (GPU):
@@ -27,6 +29,7 @@ from .workload_io import problem_from_workload
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart_blobs64_p2_s8.npz")
 HIDDEN = (32, 32, 32)
+AUX_WEIGHT = 0.25
 
 
 def he_init(channels, seed: int) -> np.ndarray:
@@ -39,10 +42,13 @@ def he_init(channels, seed: int) -> np.ndarray:
     return np.concatenate(out).astype(np.float32)
 
 
-def solve_opts(tol=1e-8, precision=L.SMM_FP32_SWEEP, start=L.SMM_START_DIFFUSION):
+def solve_opts(tol=1e-8, precision=L.SMM_FP32_SWEEP, start=L.SMM_START_DIFFUSION, inner_adapt=1e-2):
+    """Solve options used for data generation and the start comparisons:
+    inexact moment solves tied to the outer residual, PCG chunks from graphs."""
     o = L.smm_default_opts(precision=precision, outer_tol=tol, max_outer=200,
                            inner_tol=1e-10 if precision != L.SMM_FP64 else 1e-13, max_inner=20000,
-                           delta_sweeps=1 if precision != L.SMM_FP64 else 0)
+                           delta_sweeps=1 if precision != L.SMM_FP64 else 0, use_graph=1,
+                           inner_adapt=inner_adapt)
     o.start = start
     return o
 
@@ -63,8 +69,10 @@ def generate(ctx, workloads, chunk: int = 250, log=print):
         if X is None:
             X = torch.empty((n, ny, nx, nf), dtype=torch.float32, device="cuda")
             T = torch.empty((n, ny, nx, nt), dtype=torch.float32, device="cuda")
-        L.smm_batch_diffusion(batch, 1e-10, 20000)
-        rc, infos = L.smm_batch_solve(batch, solve_opts(), raise_on_noconv=False)
+        o = solve_opts()
+        # the diffusion start as the learned start builds it (same tolerance)
+        L.smm_batch_diffusion(batch, max(o.inner_tol, o.inner_adapt), o.max_inner)
+        rc, infos = L.smm_batch_solve(batch, o, raise_on_noconv=False)
         L.smm_batch_warmstart_features(batch, 0, len(wls), X[first:first + len(wls)])
         L.smm_batch_warmstart_targets(batch, 0, len(wls), T[first:first + len(wls)])
         its = [i["iterations"] for i in infos]
@@ -77,9 +85,12 @@ def generate(ctx, workloads, chunk: int = 250, log=print):
 
 
 def channel_weights(T) -> np.ndarray:
-    """1 / variance of each target channel (over all images and pixels)."""
+    """1 / variance of each target channel (over all images and pixels); the
+    second half (correction source) scaled by AUX_WEIGHT."""
     v = T.reshape(-1, T.shape[-1]).double().var(dim=0).cpu().numpy()
-    return (1.0 / np.maximum(v, 1e-12)).astype(np.float32)
+    w = 1.0 / np.maximum(v, 1e-12)
+    w[T.shape[-1] // 2:] *= AUX_WEIGHT
+    return w.astype(np.float32)
 
 
 def train(ctx, X, T, epochs=60, batch=32, lr=2e-3, seed=0, log=print, Xval=None, Tval=None):
@@ -191,7 +202,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--train-seeds", default="10000:12000")
     ap.add_argument("--val-seeds", default="20000:20200")
-    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--epochs", type=int, default=200)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)

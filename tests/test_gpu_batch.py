@@ -126,3 +126,58 @@ def test_batch_given_start_is_resume(ctx):
         L.smm_batch_get_outputs(batch, k, varphi=v)
         assert rel_l2(v, sols[k]) < 1e-11
     L.smm_batch_destroy(batch)
+
+
+def test_graph_replay_is_bitwise_eager(ctx):
+    """PCG chunks replayed from captured hipGraphs give bitwise the eager
+    results, on repeated solves (several replays of each graph, with eager work
+    and synchronisations between them)."""
+    announce("batch: PCG graph replay vs eager, fp64 and fp32")
+    wls = _batch_members()
+    probs = [make_pair(L, ctx, wl)[1] for wl in wls]
+    batch = L.smm_batch_create(ctx, probs)
+    for prec, tol in ((0, 1e-12), (1, 1e-8)):
+        ref = None
+        for use_graph in (0, 1, 1, 0, 1):
+            o = _opts(prec, tol, delta=prec)
+            o.use_graph = use_graph
+            rc, infos = L.smm_batch_solve(batch, o)
+            assert rc == L.SMM_OK
+            outs = []
+            for k, p in enumerate(probs):
+                v = np.zeros(p.n_elem * p.n_node)
+                L.smm_batch_get_outputs(batch, k, varphi=v)
+                outs.append(v)
+            its = [(i["iterations"], i["cg_iterations_total"]) for i in infos]
+            if ref is None:
+                ref = (outs, its)
+            else:
+                assert its == ref[1]
+                for a, b in zip(outs, ref[0]):
+                    assert np.array_equal(a, b)
+    L.smm_batch_destroy(batch)
+
+
+def test_adaptive_inner_tolerance(ctx):
+    """Inexact moment solves (tolerance tied to the last outer residual) reach
+    the same converged answer with fewer PCG iterations."""
+    announce("batch: adaptive inner tolerance, fp64")
+    wls = _batch_members()
+    pairs = [make_pair(L, ctx, wl) for wl in wls]
+    batch = L.smm_batch_create(ctx, [p for _, p in pairs])
+    rc, tight = L.smm_batch_solve(batch, _opts(0, 1e-12))
+    ref = []
+    for k, (_, p) in enumerate(pairs):
+        v = np.zeros(p.n_elem * p.n_node)
+        L.smm_batch_get_outputs(batch, k, varphi=v)
+        ref.append(v)
+    o = _opts(0, 1e-12)
+    o.inner_adapt = 1e-2
+    rc, loose = L.smm_batch_solve(batch, o)
+    assert rc == L.SMM_OK
+    for k, (pr, p) in enumerate(pairs):
+        v = np.zeros(p.n_elem * p.n_node)
+        L.smm_batch_get_outputs(batch, k, varphi=v)
+        assert rel_l2(v, ref[k]) < 1e-10, k
+    assert sum(i["cg_iterations_total"] for i in loose) < sum(i["cg_iterations_total"] for i in tight)
+    L.smm_batch_destroy(batch)

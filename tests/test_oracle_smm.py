@@ -18,6 +18,8 @@
   counts (soft pin; the counts printed in Table tab:tdl_orthog are 10/8/5/4,
   the oracle takes 8/5/3/2 -- see the readings in the design notes).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -150,3 +152,9 @@ def test_thick_diffusion_limit_iterations():
         counts.append(it)
     assert counts == sorted(counts, reverse=True)
     assert max(counts) <= 10 and min(counts) >= 2
+    # the paper's counts (golden fixture): same trend, within 3 iterations (the
+    # paper's start and stopping norm are not stated)
+    gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "tdl_orthog_smm_iterations.txt"))
+    assert np.allclose(gold[:, 0], [1e-1, 1e-2, 1e-3, 1e-4])
+    assert np.all(np.abs(np.array(counts) - gold[:, 1]) <= 3)
+    assert np.all(np.diff(gold[:, 1]) <= 0)
