@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <map>
 #include <numeric>
 #include <tuple>
@@ -110,6 +111,12 @@ struct smm_batch {
     double* d_scal = nullptr;
     double* d_rout = nullptr;
     double* d_tol = nullptr;       // per-problem PCG tolerance (inner_adapt)
+    // PCG type groups (see BatchLaunch)
+    int ngroups = 0;
+    std::vector<int> h_gprob, h_gcount, h_gty, h_gelem;
+    int *d_gprob = nullptr, *d_gcount = nullptr, *d_gty = nullptr, *d_gelem = nullptr;
+    double* d_gpart = nullptr;
+    bool grouped = false;          // groups filled densely enough for the grouped PCG kernels
     std::vector<Group> groups;
     CartSweepArgs* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -152,6 +159,13 @@ BatchLaunch launch_desc(smm_batch* B) {
     L.bq0 = B->d_bq0;
     L.mw0 = B->d_mw0;
     L.ptol = B->use_ptol ? B->d_tol : nullptr;
+    L.ngroups = B->ngroups;
+    L.g_prob = B->d_gprob;
+    L.g_count = B->d_gcount;
+    L.g_ty = B->d_gty;
+    L.g_elem = B->d_gelem;
+    L.gpart = B->d_gpart;
+    L.grouped = B->grouped ? 1 : 0;
     return L;
 }
 
@@ -276,6 +290,44 @@ int batch_build(smm_batch* B) {
     B->nblocks = (int)B->blk2p.size();
     B->nbq = bq;
     B->nmw = mw;
+    // PCG type groups: per problem, the elements with one (self, 4 face) type
+    // tuple, in chunks of 64 (one wave each)
+    B->h_gprob.clear();
+    B->h_gcount.clear();
+    B->h_gty.clear();
+    B->h_gelem.clear();
+    for (int b = 0; b < np; ++b) {
+        const Problem& P = B->probs[b]->P;
+        std::map<std::array<int, 5>, std::vector<int>> tup;
+        for (int K = 0; K < P.ne; ++K)
+            tup[{P.sid[K], P.nid[4 * K], P.nid[4 * K + 1], P.nid[4 * K + 2], P.nid[4 * K + 3]}].push_back(K);
+        B->hP[b].g0 = (int)B->h_gprob.size();
+        for (const auto& kv : tup) {
+            const std::vector<int>& el = kv.second;
+            for (size_t s0 = 0; s0 < el.size(); s0 += 64) {
+                const int cnt = (int)std::min<size_t>(64, el.size() - s0);
+                B->h_gprob.push_back(b);
+                B->h_gcount.push_back(cnt);
+                for (int t : kv.first) B->h_gty.push_back(t);
+                for (int k = 0; k < 64; ++k) B->h_gelem.push_back(k < cnt ? el[s0 + k] : el[s0]);
+            }
+        }
+        B->hP[b].ng = (int)B->h_gprob.size() - B->hP[b].g0;
+    }
+    B->ngroups = (int)B->h_gprob.size();
+    {
+        // one wave per group pays off when the groups are mostly full (large,
+        // piecewise-homogeneous meshes); sparse groups (many material
+        // interfaces, small meshes) run the per-node kernels
+        long ne_tot = 0;
+        for (int b = 0; b < np; ++b) ne_tot += B->probs[b]->P.ne;
+        B->grouped = B->ngroups > 0 && (double)ne_tot >= 0.75 * 64.0 * B->ngroups;
+    }
+    pool.req(&B->d_gprob, sizeof(int) * B->ngroups);
+    pool.req(&B->d_gcount, sizeof(int) * B->ngroups);
+    pool.req(&B->d_gty, sizeof(int) * 5 * B->ngroups);
+    pool.req(&B->d_gelem, sizeof(int) * 64 * B->ngroups);
+    pool.req(&B->d_gpart, sizeof(double) * 3 * B->ngroups);
     pool.req(&B->dP, sizeof(BProb) * np);
     pool.req(&B->d_blk2p, sizeof(int) * B->nblocks);
     pool.req(&B->part, sizeof(double) * 3 * std::max(B->nblocks, np));
@@ -443,6 +495,20 @@ int batch_build(smm_batch* B) {
                 if ((rc = check_args(c, A))) return rc;
             }
     }
+    for (int g = 0; g < B->ngroups; ++g) {
+        const Problem& P = B->probs[B->h_gprob[g]]->P;
+        if (B->h_gcount[g] < 1 || B->h_gcount[g] > 64) return fail(c, SMM_EHIP, "bad type group");
+        for (int k = 0; k < 64; ++k)
+            if (B->h_gelem[64 * (size_t)g + k] < 0 || B->h_gelem[64 * (size_t)g + k] >= P.ne)
+                return fail(c, SMM_EHIP, "type group element out of range");
+        if (B->h_gty[5 * (size_t)g] < 0 || B->h_gty[5 * (size_t)g] >= P.nself) return fail(c, SMM_EHIP, "bad group type");
+        for (int f = 1; f < 5; ++f)
+            if (B->h_gty[5 * (size_t)g + f] >= P.nnbrt) return fail(c, SMM_EHIP, "bad group neighbour type");
+    }
+    if ((rc = put(c, B->d_gprob, B->h_gprob.data(), sizeof(int) * B->ngroups))) return rc;
+    if ((rc = put(c, B->d_gcount, B->h_gcount.data(), sizeof(int) * B->ngroups))) return rc;
+    if ((rc = put(c, B->d_gty, B->h_gty.data(), sizeof(int) * 5 * B->ngroups))) return rc;
+    if ((rc = put(c, B->d_gelem, B->h_gelem.data(), sizeof(int) * 64 * B->ngroups))) return rc;
     if ((rc = put(c, B->dP, B->hP.data(), sizeof(BProb) * np))) return rc;
     if ((rc = put(c, B->d_blk2p, B->blk2p.data(), sizeof(int) * B->nblocks))) return rc;
     if ((rc = put(c, B->d_bq0, B->bq0.data(), sizeof(long) * np))) return rc;

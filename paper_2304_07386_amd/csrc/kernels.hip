@@ -1546,6 +1546,124 @@ __global__ __launch_bounds__(BT) void b_cg_red_init(BatchLaunch B, double tol) {
     }
 }
 
+// ---- grouped PCG kernels -----------------------------------------------------
+// One wave per type group: its (up to 64) elements share the typed blocks of
+// their self and four face couplings, so the block entries are wave-uniform and
+// come through scalar loads (SGPR operands of the FMAs), while each lane keeps
+// one element's vectors in registers.
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// y += A x with A column-major [N][N] (entry (i, j) at j N + i) and x read
+// from memory one entry per step (rolled loop over j, y in registers).  A is
+// wave-uniform and read-only for the whole kernel: it is read through the
+// constant address space, so its entries arrive by scalar loads and enter
+// the FMAs as SGPR operands.
+typedef const double __attribute__((address_space(4)))* cdptr;
+
+__device__ __forceinline__ cdptr as_const(const double* p) {
+    const unsigned long v = (unsigned long)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return (cdptr)(((unsigned long)hi << 32) | lo);
+}
+
+template <int N>
+__device__ __forceinline__ void block_mv(const double* Ag, const double* __restrict__ x, double (&y)[N]) {
+    const cdptr A = as_const(Ag);
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+        const double xj = x[j];
+#pragma unroll
+        for (int i = 0; i < N; ++i) y[i] += A[j * N + i] * xj;
+    }
+}
+
+// LDS of a grouped kernel: one slice per wave holding one vector per element
+// of the group, row stride N | 1 doubles (odd, so the 64 lanes' rows fall in
+// distinct banks).  Global vectors move in and out of it with element-major
+// flat indices t = e N + j, so those accesses are coalesced.
+constexpr int GSLICE = 64 * 25;
+
+__device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+template <int NB>
+__device__ __forceinline__ void k1_group(const BatchLaunch& B, const BProb& P, int g, int cnt, double* xs) {
+    constexpr int N = NB * NB, S = N | 1;
+    const int lane = threadIdx.x & 63;
+    const int* ty = B.g_ty + g * 5;
+    const int myK = B.g_elem[g * 64 + lane];  // every slot holds a valid element
+    const int tot = cnt * N;
+    double y[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) y[i] = 0.0;
+    for (int f = 0; f < 5; ++f) {
+        const int t = ty[f];
+        if (f > 0 && t < 0) continue;  // wave-uniform: boundary face of every element of the group
+        // flat index u = e N + j over the group's vectors: lane-consecutive, so
+        // the global reads are coalesced; all N rounds are issued before use
+        double v[N];
+#pragma unroll
+        for (int it = 0; it < N; ++it) {
+            const int u = lane + 64 * it;
+            const int e = u / N < 64 ? u / N : 63;
+            const int K = __shfl(myK, e);
+            const long src = f == 0 ? K : nbr_of(P, K, f - 1);
+            v[it] = u < tot ? P.p[src * N + (u - (u / N) * N)] : 0.0;
+        }
+#pragma unroll
+        for (int it = 0; it < N; ++it) {
+            const int u = lane + 64 * it;
+            if (u < tot) xs[(u / N) * S + (u - (u / N) * N)] = v[it];
+        }
+        lds_wave_sync();
+        block_mv<N>((f == 0 ? P.ip_self : P.ip_nbr) + (long)t * N * N, xs + lane * S, y);
+        lds_wave_sync();
+    }
+    if (lane < cnt)
+#pragma unroll
+        for (int i = 0; i < N; ++i) xs[lane * S + i] = y[i];
+    lds_wave_sync();
+    double pq = 0.0;
+#pragma unroll
+    for (int it = 0; it < N; ++it) {
+        const int u = lane + 64 * it;
+        const int e = u / N < 64 ? u / N : 63;
+        const int K = __shfl(myK, e);
+        if (u < tot) {
+            const long o = (long)K * N + (u - (u / N) * N);
+            const double qv = xs[(u / N) * S + (u - (u / N) * N)];
+            P.q[o] = qv;
+            pq += P.p[o] * qv;
+        }
+    }
+    pq = wave_sum(pq);
+    if (lane == 0) B.gpart[g] = pq;
+}
+
+// q = A p and the group's partial sum of p.q
+__global__ __launch_bounds__(256) void b_cg_k1(BatchLaunch B) {
+    __shared__ double lds[4 * GSLICE];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = blockIdx.x * 4 + w;
+    if (g >= B.ngroups) return;  // wave-uniform; no workgroup barriers below
+    const int prob = B.g_prob[g];
+    if (cg_skip(B, prob)) return;
+    const BProb& P = B.P[prob];
+    const int cnt = B.g_count[g];
+    double* xs = lds + w * GSLICE;
+    switch (P.nb) {
+        case 2: k1_group<2>(B, P, g, cnt, xs); break;
+        case 3: k1_group<3>(B, P, g, cnt, xs); break;
+        case 4: k1_group<4>(B, P, g, cnt, xs); break;
+        default: k1_group<5>(B, P, g, cnt, xs); break;
+    }
+}
+
+// ---- per-node PCG kernels (element blocks of BT threads; used when the type
+// groups of a batch are sparsely filled) ----------------------------------------
 // q = A p and the block's partial sum of p.q.  The p values of the block's
 // elements and of their four neighbours are staged in LDS once; thread
 // (pair, i) then computes node i of two neighbouring elements, so one load of
@@ -1568,7 +1686,7 @@ __device__ __forceinline__ void typed_dot2(const double* __restrict__ ca, const 
     }
 }
 
-__global__ __launch_bounds__(BT) void b_cg_k1(BatchLaunch B) {
+__global__ __launch_bounds__(BT) void b_cg_k1n(BatchLaunch B) {
     __shared__ double red[BT];
     __shared__ double xs[5 * BT];  // [element][self, 4 neighbours][n]
     const int prob = B.blk2p[blockIdx.x];
@@ -1619,26 +1737,9 @@ __global__ __launch_bounds__(BT) void b_cg_k1(BatchLaunch B) {
     if (t == 0) B.part[blockIdx.x] = pq;
 }
 
-__global__ __launch_bounds__(BT) void b_cg_red1(BatchLaunch B) {
-    __shared__ double red[BT];
-    const int prob = blockIdx.x;
-    if (cg_skip(B, prob)) return;
-    const BProb& P = B.P[prob];
-    const double pq = prob_sum(B, P, 0, red);
-    if (threadIdx.x == 0) {
-        double* s = P.scal;
-        if (!(pq > 0.0)) {
-            s[6] = 1.0;
-            s[4] = 1.0;
-        } else {
-            s[8] = s[0] / pq;
-        }
-    }
-}
-
 // x += alpha p, r -= alpha q, z = D^-1 r (block-Jacobi; two elements per
 // thread as in b_cg_k1) and the partial sums of r.z and r.r.
-__global__ __launch_bounds__(BT) void b_cg_k2(BatchLaunch B) {
+__global__ __launch_bounds__(BT) void b_cg_k2n(BatchLaunch B) {
     __shared__ double red[BT];
     __shared__ double rl[BT];
     const int prob = B.blk2p[blockIdx.x];
@@ -1686,12 +1787,107 @@ __global__ __launch_bounds__(BT) void b_cg_k2(BatchLaunch B) {
     }
 }
 
+// fixed-order sum of a problem's group partials (one workgroup per problem)
+__device__ __forceinline__ double group_sum(const BatchLaunch& B, const BProb& P, int which, double* red) {
+    if (!B.grouped) return prob_sum(B, P, which, red);
+    double v = 0.0;
+    for (int k = threadIdx.x; k < P.ng; k += BT) v += B.gpart[which * B.ngroups + P.g0 + k];
+    return b_block_sum(v, red);
+}
+
+__global__ __launch_bounds__(BT) void b_cg_red1(BatchLaunch B) {
+    __shared__ double red[BT];
+    const int prob = blockIdx.x;
+    if (cg_skip(B, prob)) return;
+    const BProb& P = B.P[prob];
+    const double pq = group_sum(B, P, 0, red);
+    if (threadIdx.x == 0) {
+        double* s = P.scal;
+        if (!(pq > 0.0)) {
+            s[6] = 1.0;
+            s[4] = 1.0;
+        } else {
+            s[8] = s[0] / pq;
+        }
+    }
+}
+
+template <int NB>
+__device__ __forceinline__ void k2_group(const BatchLaunch& B, const BProb& P, int g, int cnt, double* xs) {
+    constexpr int N = NB * NB, S = N | 1;
+    const int lane = threadIdx.x & 63;
+    const int myK = B.g_elem[g * 64 + lane];
+    const int tot = cnt * N;
+    const double alpha = P.scal[8];
+    double rr = 0.0, rz = 0.0;
+#pragma unroll
+    for (int it = 0; it < N; ++it) {
+        const int u = lane + 64 * it;
+        const int e = u / N < 64 ? u / N : 63;
+        const int K = __shfl(myK, e);
+        if (u < tot) {
+            const long o = (long)K * N + (u - (u / N) * N);
+            P.x[o] += alpha * P.p[o];
+            const double r = P.r[o] - alpha * P.q[o];
+            P.r[o] = r;
+            rr += r * r;
+            xs[(u / N) * S + (u - (u / N) * N)] = r;
+        }
+    }
+    lds_wave_sync();
+    double z[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) z[i] = 0.0;
+    block_mv<N>(P.dinv + (long)B.g_ty[g * 5] * N * N, xs + lane * S, z);
+    if (lane < cnt)
+#pragma unroll
+        for (int i = 0; i < N; ++i) rz += xs[lane * S + i] * z[i];
+    lds_wave_sync();
+    if (lane < cnt)
+#pragma unroll
+        for (int i = 0; i < N; ++i) xs[lane * S + i] = z[i];
+    lds_wave_sync();
+#pragma unroll
+    for (int it = 0; it < N; ++it) {
+        const int u = lane + 64 * it;
+        const int e = u / N < 64 ? u / N : 63;
+        const int K = __shfl(myK, e);
+        if (u < tot) P.z[(long)K * N + (u - (u / N) * N)] = xs[(u / N) * S + (u - (u / N) * N)];
+    }
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    if (lane == 0) {
+        B.gpart[B.ngroups + g] = rz;
+        B.gpart[2 * B.ngroups + g] = rr;
+    }
+}
+
+// x += alpha p, r -= alpha q, z = D^-1 r (block-Jacobi) and the group's partial
+// sums of r.z and r.r
+__global__ __launch_bounds__(256) void b_cg_k2(BatchLaunch B) {
+    __shared__ double lds[4 * GSLICE];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = blockIdx.x * 4 + w;
+    if (g >= B.ngroups) return;
+    const int prob = B.g_prob[g];
+    if (cg_skip(B, prob)) return;
+    const BProb& P = B.P[prob];
+    const int cnt = B.g_count[g];
+    double* xs = lds + w * GSLICE;
+    switch (P.nb) {
+        case 2: k2_group<2>(B, P, g, cnt, xs); break;
+        case 3: k2_group<3>(B, P, g, cnt, xs); break;
+        case 4: k2_group<4>(B, P, g, cnt, xs); break;
+        default: k2_group<5>(B, P, g, cnt, xs); break;
+    }
+}
+
 __global__ __launch_bounds__(BT) void b_cg_red2(BatchLaunch B) {
     __shared__ double red[BT];
     const int prob = blockIdx.x;
     if (cg_skip(B, prob)) return;
     const BProb& P = B.P[prob];
-    const double rzn = prob_sum(B, P, 1, red), rr = prob_sum(B, P, 2, red);
+    const double rzn = group_sum(B, P, 1, red), rr = group_sum(B, P, 2, red);
     if (threadIdx.x == 0) {
         double* s = P.scal;
         s[9] = rzn / s[0];
@@ -1719,15 +1915,24 @@ hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s) {
 }
 
 hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s) {
-    hipLaunchKernelGGL(b_cg_k1, dim3(B.nblocks), dim3(BT), 0, s, B);
+    if (B.grouped)
+        hipLaunchKernelGGL(b_cg_k1, dim3((B.ngroups + 3) / 4), dim3(256), 0, s, B);
+    else
+        hipLaunchKernelGGL(b_cg_k1n, dim3(B.nblocks), dim3(BT), 0, s, B);
     return hipGetLastError();
 }
 
 hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s) {
     for (int k = 0; k < iters; ++k) {
-        hipLaunchKernelGGL(b_cg_k1, dim3(B.nblocks), dim3(BT), 0, s, B);
+        if (B.grouped)
+            hipLaunchKernelGGL(b_cg_k1, dim3((B.ngroups + 3) / 4), dim3(256), 0, s, B);
+        else
+            hipLaunchKernelGGL(b_cg_k1n, dim3(B.nblocks), dim3(BT), 0, s, B);
         hipLaunchKernelGGL(b_cg_red1, dim3(B.nprob), dim3(BT), 0, s, B);
-        hipLaunchKernelGGL(b_cg_k2, dim3(B.nblocks), dim3(BT), 0, s, B);
+        if (B.grouped)
+            hipLaunchKernelGGL(b_cg_k2, dim3((B.ngroups + 3) / 4), dim3(256), 0, s, B);
+        else
+            hipLaunchKernelGGL(b_cg_k2n, dim3(B.nblocks), dim3(BT), 0, s, B);
         hipLaunchKernelGGL(b_cg_red2, dim3(B.nprob), dim3(BT), 0, s, B);
         hipLaunchKernelGGL(b_cg_k3, dim3(B.nblocks), dim3(BT), 0, s, B);
     }

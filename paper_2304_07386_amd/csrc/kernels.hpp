@@ -118,6 +118,7 @@ struct BProb {
     double* vdiff;                                          // [L] diffusion start (warm start)
     const float* feat0;                                     // [ne][4] per-element warm-start features
     double hxhy;                                            // element area
+    int g0, ng;                                             // type-group range (PCG kernels)
 };
 
 struct BatchLaunch {
@@ -132,6 +133,15 @@ struct BatchLaunch {
     const long* bq0;               // [nprob] prefix (device copy)
     const long* mw0;               // [nprob] prefix (device copy)
     const double* ptol;            // [nprob] per-problem PCG tolerance (nullable: the scalar one)
+    // type groups: up to 64 elements of one problem that share the typed blocks
+    // of their self and four face couplings (one wave per group)
+    int ngroups;
+    const int* g_prob;             // [ngroups]
+    const int* g_count;            // [ngroups]
+    const int* g_ty;               // [ngroups][5] self type, neighbour types (-1: boundary face)
+    const int* g_elem;             // [ngroups][64]
+    double* gpart;                 // [3][ngroups] per-group partial sums
+    int grouped;                   // 1: PCG on the type groups, 0: per-node element blocks
 };
 
 hipError_t b_source(bool fp64, const BatchLaunch& B, bool delta, hipStream_t s);
