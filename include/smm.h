@@ -69,6 +69,10 @@ extern "C" {
 #define SMM_INFLOW_ISO_FACE 1/* psibar[n_bface]: isotropic, constant per boundary face */
 #define SMM_INFLOW_FULL 2    /* psibar[n_bface][nq][n_dir] at the boundary face points */
 
+/* preconditioners of the moment solve */
+#define SMM_PRECOND_BJ 0
+#define SMM_PRECOND_TWOLEVEL 1
+
 /* initial guess for smm_solve */
 #define SMM_START_ZERO 0
 #define SMM_START_DIFFUSION 1 /* moment system with zero transport corrections */
@@ -115,6 +119,9 @@ typedef struct {
     int moment_path;     /* 0: typed blocks on uniform Cartesian meshes with isotropic
                             sources (batched kernels), else per-element operators;
                             1: always per-element operators */
+    int precond;         /* SMM_PRECOND_BJ: block-Jacobi PCG; SMM_PRECOND_TWOLEVEL: block-Jacobi
+                            plus a continuous Q1 coarse correction on the element vertices,
+                            solved by one vertex multigrid V-cycle (typed path only) */
     double inner_adapt;  /* > 0: the moment solve of outer iteration k stops at the
                             relative residual max(inner_tol, inner_adapt * r_{k-1})
                             (r_0 = 1; per problem in a batch), and the solves that
@@ -226,6 +233,17 @@ int smm_time_sweep(smm_problem* prob, int precision, int reps, double* ms_avg);
 int smm_debug_typed_dense(smm_problem* prob, double* A, double* C, double* b_fixed);
 /* The same correction-source operator [N][3N] from the per-element assembly. */
 int smm_debug_corr_dense(smm_problem* prob, double* C);
+/* Host-only inspection of the two-level preconditioner: the 9-point stencil
+ * [9][nvx*nvy] (entry k = (dy+1)*3 + (dx+1) couples vertex (x, y) to
+ * (x+dx, y+dy)) of multigrid level `level` (0: the Galerkin operator of the
+ * continuous Q1 space on the element vertices).  A9 may be NULL to query the
+ * grid size. */
+int smm_debug_mg_level(smm_problem* prob, int level, double* A9, int* nvx, int* nvy);
+/* Testing hook: z = M^-1 r for every problem of a batch with the PCG
+ * preconditioner `precond` (SMM_PRECOND_*); r and z are n host pointers of
+ * n_elem * n_node values each.  Overwrites the batch's PCG work vectors (the
+ * outputs of the last solve become unavailable). */
+int smm_debug_batch_precond(smm_batch* batch, int precond, const double* const* r, double* const* z);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems (uniform Cartesian meshes, isotropic

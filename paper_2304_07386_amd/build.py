@@ -31,6 +31,7 @@ def build(verbose: bool = True) -> str:
         ("typed.cpp", ["-x", "hip", *DEVICE_FLAGS, "-ffp-contract=off"]),
         ("batch.cpp", ["-x", "hip", *DEVICE_FLAGS]),
         ("cnn.cpp", ["-x", "hip", *DEVICE_FLAGS]),
+        ("mg.cpp", ["-x", "hip", *DEVICE_FLAGS]),
         ("kernels.hip", DEVICE_FLAGS),
         ("cnn_kernels.hip", DEVICE_FLAGS),
     )

@@ -245,6 +245,7 @@ void smm_default_opts(smm_solve_opts* o) {
     o->use_graph = 0;
     o->moment_path = 0;
     o->inner_adapt = 0.0;
+    o->precond = SMM_PRECOND_BJ;
 }
 
 }  // extern "C"

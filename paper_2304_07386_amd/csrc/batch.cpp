@@ -24,6 +24,7 @@
 #include "../../include/smm_cnn.h"
 #include "api_internal.hpp"
 #include "cnn_internal.hpp"
+#include "mg_internal.hpp"
 
 namespace smm {
 int ensure_typed(smm_problem* pr);
@@ -47,6 +48,7 @@ struct PerProb {
     uint8_t* mat;
     double* vdiff;
     float* feat0;
+    double* gll;
 };
 
 struct Group {
@@ -117,6 +119,17 @@ struct smm_batch {
     int *d_gprob = nullptr, *d_gcount = nullptr, *d_gty = nullptr, *d_gelem = nullptr;
     double* d_gpart = nullptr;
     bool grouped = false;          // groups filled densely enough for the grouped PCG kernels
+    // two-level preconditioner (precond = 1): per-level flat vertex arrays
+    bool use_mg = false;
+    std::string mg_error;          // why the two-level preconditioner is unavailable (empty: available)
+    std::vector<std::vector<double>> gll_host;
+    MGLaunch mgl{};
+    int* d_mg_off[MG_MAXLEV] = {};
+    int* d_mg_dims[MG_MAXLEV] = {};
+    double* d_mg_A[MG_MAXLEV] = {};
+    double *d_mg_x[MG_MAXLEV] = {}, *d_mg_t[MG_MAXLEV] = {}, *d_mg_b[MG_MAXLEV] = {};
+    int *d_mg_lc = nullptr, *d_mg_coff = nullptr;
+    double* d_mg_cinv = nullptr;
     std::vector<Group> groups;
     CartSweepArgs* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -141,7 +154,7 @@ struct smm_batch {
     // (iterations in the chunk, per-problem tolerances on)
     bool use_graph = false;
     hipStream_t cap = nullptr;
-    std::map<std::pair<int, bool>, hipGraphExec_t> cg_graphs;
+    std::map<std::tuple<int, bool, bool>, hipGraphExec_t> cg_graphs;
 };
 
 namespace {
@@ -166,6 +179,7 @@ BatchLaunch launch_desc(smm_batch* B) {
     L.g_elem = B->d_gelem;
     L.gpart = B->d_gpart;
     L.grouped = B->grouped ? 1 : 0;
+    L.mg = B->use_mg ? 1 : 0;
     return L;
 }
 
@@ -314,6 +328,53 @@ int batch_build(smm_batch* B) {
         }
         B->hP[b].ng = (int)B->h_gprob.size() - B->hP[b].g0;
     }
+    // two-level preconditioner hierarchies (host), flattened per level
+    // (a problem it cannot be built for leaves the batch without it: solves
+    // that ask for it then fail with the recorded reason)
+    std::vector<MGHost> mgh(np);
+    B->mg_error.clear();
+    for (int b = 0; b < np && B->mg_error.empty(); ++b) {
+        std::string err;
+        if (build_mg(B->probs[b]->P, mgh[b], err))
+            B->mg_error = "two-level preconditioner of problem " + std::to_string(b) + ": " + err;
+    }
+    int mg_nlev = 0;
+    for (const MGHost& m : mgh) mg_nlev = std::max(mg_nlev, (int)m.lev.size());
+    if (mg_nlev > MG_MAXLEV) B->mg_error = "mesh too large for the multigrid level table";
+    if (!B->mg_error.empty()) {
+        mg_nlev = 0;
+        for (MGHost& m : mgh) m = MGHost{};
+    }
+    std::vector<std::vector<int>> mg_off(mg_nlev, std::vector<int>(np + 1, 0)), mg_dims(mg_nlev, std::vector<int>(2 * np, 0));
+    std::vector<int> mg_lc(np), mg_coff(np);
+    int cinv_tot = 0;
+    for (int l = 0; l < mg_nlev; ++l)
+        for (int b = 0; b < np; ++b) {
+            const bool has = l < (int)mgh[b].lev.size();
+            mg_off[l][b + 1] = mg_off[l][b] + (has ? mgh[b].lev[l].nvx * mgh[b].lev[l].nvy : 0);
+            mg_dims[l][2 * b] = has ? mgh[b].lev[l].nvx : 0;
+            mg_dims[l][2 * b + 1] = has ? mgh[b].lev[l].nvy : 0;
+        }
+    for (int b = 0; b < np; ++b) {
+        mg_lc[b] = std::max((int)mgh[b].lev.size() - 1, 0);
+        mg_coff[b] = cinv_tot;
+        cinv_tot += (int)mgh[b].cinv.size();
+    }
+    for (int l = 0; l < mg_nlev; ++l) {
+        const size_t nv = (size_t)std::max(mg_off[l][np], 1);
+        pool.req(&B->d_mg_off[l], sizeof(int) * (np + 1));
+        pool.req(&B->d_mg_dims[l], sizeof(int) * 2 * np);
+        pool.req(&B->d_mg_A[l], sizeof(double) * 9 * nv);
+        pool.req(&B->d_mg_x[l], sizeof(double) * nv);
+        pool.req(&B->d_mg_t[l], sizeof(double) * nv);
+        pool.req(&B->d_mg_b[l], sizeof(double) * nv);
+    }
+    pool.req(&B->d_mg_lc, sizeof(int) * np);
+    pool.req(&B->d_mg_coff, sizeof(int) * np);
+    pool.req(&B->d_mg_cinv, sizeof(double) * std::max(cinv_tot, 1));
+    for (int b = 0; b < np; ++b) pool.req(&B->pp[b].gll, sizeof(double) * B->probs[b]->P.nb);
+    B->gll_host.assign(np, {});
+    for (int b = 0; b < np; ++b) gauss_lobatto01(B->probs[b]->P.p, B->gll_host[b]);
     B->ngroups = (int)B->h_gprob.size();
     {
         // one wave per group pays off when the groups are mostly full (large,
@@ -509,6 +570,45 @@ int batch_build(smm_batch* B) {
     if ((rc = put(c, B->d_gcount, B->h_gcount.data(), sizeof(int) * B->ngroups))) return rc;
     if ((rc = put(c, B->d_gty, B->h_gty.data(), sizeof(int) * 5 * B->ngroups))) return rc;
     if ((rc = put(c, B->d_gelem, B->h_gelem.data(), sizeof(int) * 64 * B->ngroups))) return rc;
+    // multigrid tables
+    for (int l = 0; l < mg_nlev; ++l) {
+        if ((rc = put(c, B->d_mg_off[l], mg_off[l].data(), sizeof(int) * (np + 1)))) return rc;
+        if ((rc = put(c, B->d_mg_dims[l], mg_dims[l].data(), sizeof(int) * 2 * np))) return rc;
+        const int nvl = mg_off[l][np];
+        std::vector<double> A((size_t)9 * std::max(nvl, 1), 0.0);
+        for (int b = 0; b < np; ++b) {
+            if (l >= (int)mgh[b].lev.size()) continue;
+            const MGLevelHost& H = mgh[b].lev[l];
+            const int nv = H.nvx * H.nvy;
+            for (int k = 0; k < 9; ++k)
+                for (int v = 0; v < nv; ++v) A[(size_t)k * nvl + mg_off[l][b] + v] = H.A[(size_t)k * nv + v];
+        }
+        if ((rc = put(c, B->d_mg_A[l], A.data(), sizeof(double) * 9 * nvl))) return rc;
+        MGLevelDev& D = B->mgl.lev[l];
+        D.off = B->d_mg_off[l];
+        D.dims = B->d_mg_dims[l];
+        D.A = B->d_mg_A[l];
+        D.x = B->d_mg_x[l];
+        D.t = B->d_mg_t[l];
+        D.b = B->d_mg_b[l];
+        D.nv = nvl;
+    }
+    {
+        std::vector<double> cinv;
+        for (int b = 0; b < np; ++b) cinv.insert(cinv.end(), mgh[b].cinv.begin(), mgh[b].cinv.end());
+        if ((rc = put(c, B->d_mg_lc, mg_lc.data(), sizeof(int) * np))) return rc;
+        if ((rc = put(c, B->d_mg_coff, mg_coff.data(), sizeof(int) * np))) return rc;
+        if ((rc = put(c, B->d_mg_cinv, cinv.data(), sizeof(double) * cinv.size()))) return rc;
+        for (int b = 0; b < np; ++b) {
+            if ((rc = put(c, B->pp[b].gll, B->gll_host[b].data(), sizeof(double) * B->gll_host[b].size()))) return rc;
+            B->hP[b].gll = B->pp[b].gll;
+        }
+        B->mgl.nlev = mg_nlev;
+        B->mgl.lc = B->d_mg_lc;
+        B->mgl.coff = B->d_mg_coff;
+        B->mgl.cinv = B->d_mg_cinv;
+        B->mgl.omega = 2.0 / 3.0;
+    }
     if ((rc = put(c, B->dP, B->hP.data(), sizeof(BProb) * np))) return rc;
     if ((rc = put(c, B->d_blk2p, B->blk2p.data(), sizeof(int) * B->nblocks))) return rc;
     if ((rc = put(c, B->d_bq0, B->bq0.data(), sizeof(long) * np))) return rc;
@@ -617,7 +717,7 @@ int batch_autotune(smm_batch* B, bool fp64) {
 int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
     smm_ctx* c = B->ctx;
     const BatchLaunch L = launch_desc(B);
-    HIPCHK(c, b_cg_start(L, tol, c->stream));
+    HIPCHK(c, b_cg_start(L, tol, c->stream, &B->mgl));
     std::vector<double> sc(16 * (size_t)B->nprob);
     int done_its = 0, chunk = 4;
     while (true) {
@@ -634,14 +734,14 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
         if (B->use_graph) {
             // capture the chunk once on a private stream, then replay it on the
             // context's stream (kernel nodes only)
-            const auto key = std::make_pair(k, L.ptol != nullptr);
+            const auto key = std::make_tuple(k, L.ptol != nullptr, L.mg != 0);
             auto it = B->cg_graphs.find(key);
             if (it == B->cg_graphs.end()) {
                 if (!B->cap) HIPCHK(c, hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
                 hipGraph_t g = nullptr;
                 hipGraphExec_t ge = nullptr;
                 HIPCHK(c, hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
-                const hipError_t e1 = b_cg_iterations(L, k, B->cap);
+                const hipError_t e1 = b_cg_iterations(L, k, B->cap, &B->mgl);
                 const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
                 if (e1 != hipSuccess || e2 != hipSuccess) {
                     if (g) (void)hipGraphDestroy(g);
@@ -654,7 +754,7 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
             }
             HIPCHK(c, hipGraphLaunch(it->second, c->stream));
         } else {
-            HIPCHK(c, b_cg_iterations(L, k, c->stream));
+            HIPCHK(c, b_cg_iterations(L, k, c->stream, &B->mgl));
         }
         done_its += k;
         B->cg_batched_its += k;
@@ -754,10 +854,17 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     if ((rc = batch_autotune(B, fp64))) return rc;
     B->active.assign(np, 1);
     B->ws_used.assign(np, 0);
+    if (o.precond != SMM_PRECOND_BJ && o.precond != SMM_PRECOND_TWOLEVEL)
+        return fail(c, SMM_EINVAL, "smm_batch_solve: unknown preconditioner");
+    if (o.precond == SMM_PRECOND_TWOLEVEL && !B->mg_error.empty()) return fail(c, SMM_EUNSUPPORTED, B->mg_error);
     B->use_graph = o.use_graph != 0;
+    B->use_mg = o.precond == SMM_PRECOND_TWOLEVEL;
     struct GraphReset {
         smm_batch* b;
-        ~GraphReset() { b->use_graph = false; }
+        ~GraphReset() {
+            b->use_graph = false;
+            b->use_mg = false;
+        }
     } graph_reset{B};
     if ((rc = put(c, B->d_active, B->active.data(), sizeof(int) * np))) return rc;
     const BatchLaunch L = launch_desc(B);
@@ -1098,7 +1205,7 @@ int smm_batch_time_kernel(smm_batch* batch, int kernel, int reps, double* ms_avg
     // a CG state on the last right-hand side (x, b, p untouched by the timed launches
     // except q and the partial sums)
     HIPCHK(c, b_copy_x(L, c->stream));
-    HIPCHK(c, b_cg_start(L, 0.0, c->stream));
+    HIPCHK(c, b_cg_start(L, 0.0, c->stream, &batch->mgl));
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -1112,6 +1219,44 @@ int smm_batch_time_kernel(smm_batch* batch, int kernel, int reps, double* ms_avg
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *ms_avg = ms / reps;
+    return SMM_OK;
+}
+
+int smm_debug_batch_precond(smm_batch* batch, int precond, const double* const* r, double* const* z) {
+    if (!batch || !r || !z) return SMM_EINVAL;
+    smm_ctx* c = batch->ctx;
+    if (precond == SMM_PRECOND_TWOLEVEL && !batch->mg_error.empty()) return fail(c, SMM_EUNSUPPORTED, batch->mg_error);
+    HIPCHK(c, hipSetDevice(c->device));
+    batch->active.assign(batch->nprob, 1);
+    int rc;
+    if ((rc = put(c, batch->d_active, batch->active.data(), sizeof(int) * batch->nprob))) return rc;
+    HIPCHK(c, hipMemset(batch->d_scal, 0, sizeof(double) * 16 * batch->nprob));
+    for (int b = 0; b < batch->nprob; ++b)
+        if ((rc = put(c, batch->pp[b].r, r[b], sizeof(double) * batch->hP[b].L))) return rc;
+    batch->use_mg = precond == SMM_PRECOND_TWOLEVEL;
+    const BatchLaunch L = launch_desc(batch);
+    batch->use_mg = false;
+    HIPCHK(c, b_precond(L, &batch->mgl, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < batch->nprob; ++b)
+        HIPCHK(c, hipMemcpy(z[b], batch->pp[b].z, sizeof(double) * batch->hP[b].L, hipMemcpyDeviceToHost));
+    batch->have_outputs = false;
+    return SMM_OK;
+}
+
+int smm_debug_mg_level(smm_problem* prob, int level, double* A9, int* nvx, int* nvy) {
+    if (!prob || level < 0 || !nvx || !nvy) return SMM_EINVAL;
+    smm_ctx* c = prob->P.ctx;
+    int rc = smm::ensure_typed(prob);
+    if (rc) return rc;
+    MGHost M;
+    std::string err;
+    if ((rc = build_mg(prob->P, M, err))) return fail(c, rc, err);
+    if (level >= (int)M.lev.size()) return fail(c, SMM_EINVAL, "level beyond the coarsest");
+    const MGLevelHost& L = M.lev[level];
+    *nvx = L.nvx;
+    *nvy = L.nvy;
+    if (A9) std::copy(L.A.begin(), L.A.end(), A9);
     return SMM_OK;
 }
 

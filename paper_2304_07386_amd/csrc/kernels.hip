@@ -1887,7 +1887,8 @@ __global__ __launch_bounds__(BT) void b_cg_red2(BatchLaunch B) {
     const int prob = blockIdx.x;
     if (cg_skip(B, prob)) return;
     const BProb& P = B.P[prob];
-    const double rzn = group_sum(B, P, 1, red), rr = group_sum(B, P, 2, red);
+    const double rzn = B.mg ? prob_sum(B, P, 1, red) : group_sum(B, P, 1, red);
+    const double rr = group_sum(B, P, 2, red);
     if (threadIdx.x == 0) {
         double* s = P.scal;
         s[9] = rzn / s[0];
@@ -1907,10 +1908,31 @@ __global__ __launch_bounds__(BT) void b_cg_k3(BatchLaunch B) {
     P.p[t] = P.z[t] + P.scal[9] * P.p[t];
 }
 
-hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s) {
+// a new PCG start: clear the done and breakdown flags left by the previous
+// solve (the start kernels run for every active problem)
+__global__ void b_cg_clear_kernel(BatchLaunch B) {
+    const int prob = blockIdx.x * blockDim.x + threadIdx.x;
+    if (prob >= B.nprob) return;
+    double* s = B.P[prob].scal;
+    s[4] = 0.0;
+    s[6] = 0.0;
+}
+
+hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s, const MGLaunch* M) {
+    hipLaunchKernelGGL(b_cg_clear_kernel, dim3((B.nprob + 255) / 256), dim3(256), 0, s, B);
     hipLaunchKernelGGL(b_cg_init1, dim3(B.nblocks), dim3(BT), 0, s, B);
     hipLaunchKernelGGL(b_cg_init2, dim3(B.nblocks), dim3(BT), 0, s, B);
+    if (B.mg) {
+        const hipError_t e = b_mg_apply(B, *M, true, s);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(b_cg_red_init, dim3(B.nprob), dim3(BT), 0, s, B, tol);
+    return hipGetLastError();
+}
+
+hipError_t b_precond(const BatchLaunch& B, const MGLaunch* M, hipStream_t s) {
+    hipLaunchKernelGGL(b_cg_init2, dim3(B.nblocks), dim3(BT), 0, s, B);
+    if (B.mg) return b_mg_apply(B, *M, true, s);
     return hipGetLastError();
 }
 
@@ -1922,7 +1944,7 @@ hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s) {
+hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const MGLaunch* M) {
     for (int k = 0; k < iters; ++k) {
         if (B.grouped)
             hipLaunchKernelGGL(b_cg_k1, dim3((B.ngroups + 3) / 4), dim3(256), 0, s, B);
@@ -1933,6 +1955,10 @@ hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s) {
             hipLaunchKernelGGL(b_cg_k2, dim3((B.ngroups + 3) / 4), dim3(256), 0, s, B);
         else
             hipLaunchKernelGGL(b_cg_k2n, dim3(B.nblocks), dim3(BT), 0, s, B);
+        if (B.mg) {
+            const hipError_t e = b_mg_apply(B, *M, false, s);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(b_cg_red2, dim3(B.nprob), dim3(BT), 0, s, B);
         hipLaunchKernelGGL(b_cg_k3, dim3(B.nblocks), dim3(BT), 0, s, B);
     }
@@ -2039,6 +2065,223 @@ hipError_t b_ws_apply(const BatchLaunch& B, const float* Y, int nt, hipStream_t 
 
 hipError_t b_ws_store_diffusion(const BatchLaunch& B, hipStream_t s) {
     hipLaunchKernelGGL(b_ws_store_diffusion_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
+    return hipGetLastError();
+}
+
+// ---- two-level preconditioner: vertex multigrid on the Q1 coarse space --------
+__device__ __forceinline__ int mg_prob(const int* off, int nprob, int v) {
+    int lo = 0, hi = nprob - 1;  // last p with off[p] <= v
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int mg_ccount(int nf) { return nf <= 3 ? nf : nf / 2 + 1; }
+
+// parents of fine vertex i (grid of nf vertices): c0 (w0), c1 (w1; -1 if none)
+__device__ __forceinline__ void mg_parents(int i, int nf, int& c0, double& w0, int& c1, double& w1) {
+    c1 = -1;
+    w1 = 0.0;
+    if (nf <= 3) {
+        c0 = i;
+        w0 = 1.0;
+    } else if (i == nf - 1) {
+        c0 = mg_ccount(nf) - 1;
+        w0 = 1.0;
+    } else if ((i & 1) == 0) {
+        c0 = i >> 1;
+        w0 = 1.0;
+    } else {
+        c0 = (i - 1) >> 1;
+        w0 = 0.5;
+        c1 = (i + 1) >> 1;
+        w1 = 0.5;
+    }
+}
+
+__device__ __forceinline__ double mg_weight(int i, int nf, int c) {
+    int c0, c1;
+    double w0, w1;
+    mg_parents(i, nf, c0, w0, c1, w1);
+    return c0 == c ? w0 : (c1 == c ? w1 : 0.0);
+}
+
+// (A x)[v] on a level: 9-point stencil within the problem's vertex grid
+__device__ __forceinline__ double mg_apply(const MGLevelDev& L, int o, int nvx, int nvy, int ix, int iy,
+                                           const double* x) {
+    double s = 0.0;
+    const int v = o + iy * nvx + ix;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int jx = ix + k % 3 - 1, jy = iy + k / 3 - 1;
+        if (jx < 0 || jy < 0 || jx >= nvx || jy >= nvy) continue;
+        s += L.A[(long)k * L.nv + v] * x[o + jy * nvx + jx];
+    }
+    return s;
+}
+
+// level 0 right-hand side: b_v = sum over the (<= 4) elements at vertex v and
+// their nodes of hat_v(node) r(node)
+__global__ __launch_bounds__(BT) void mg_restrict0_kernel(BatchLaunch B, MGLaunch M) {
+    const MGLevelDev& L = M.lev[0];
+    const int v = blockIdx.x * BT + threadIdx.x;
+    if (v >= L.nv) return;
+    const int prob = mg_prob(L.off, B.nprob, v);
+    if (cg_skip(B, prob)) return;
+    const BProb& P = B.P[prob];
+    const int o = L.off[prob], nvx = L.dims[2 * prob], loc = v - o;
+    const int ix = loc % nvx, iy = loc / nvx;
+    const int nb = P.nb, n = P.n, nx = nvx - 1, ny = L.dims[2 * prob + 1] - 1;
+    double s = 0.0;
+    for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+            const int ex = ix - cx, ey = iy - cy;
+            if (ex < 0 || ey < 0 || ex >= nx || ey >= ny) continue;
+            const double* r = P.r + ((long)ey * nx + ex) * n;
+            for (int b = 0; b < nb; ++b) {
+                const double hy = cy ? P.gll[b] : 1.0 - P.gll[b];
+                double t = 0.0;
+                for (int a = 0; a < nb; ++a) t += (cx ? P.gll[a] : 1.0 - P.gll[a]) * r[a + nb * b];
+                s += hy * t;
+            }
+        }
+    L.b[v] = s;
+}
+
+// damped Jacobi: xout = omega b / d (first) or xin + omega (b - A xin) / d
+__global__ __launch_bounds__(BT) void mg_smooth_kernel(BatchLaunch B, MGLaunch M, int l, int first, const double* xin,
+                                                       double* xout) {
+    const MGLevelDev& L = M.lev[l];
+    const int v = blockIdx.x * BT + threadIdx.x;
+    if (v >= L.nv) return;
+    const int prob = mg_prob(L.off, B.nprob, v);
+    if (cg_skip(B, prob) || M.lc[prob] <= l) return;
+    const int o = L.off[prob], nvx = L.dims[2 * prob], nvy = L.dims[2 * prob + 1], loc = v - o;
+    const double d = L.A[4L * L.nv + v];
+    if (first) {
+        xout[v] = M.omega * L.b[v] / d;
+    } else {
+        const double ax = mg_apply(L, o, nvx, nvy, loc % nvx, loc / nvx, xin);
+        xout[v] = xin[v] + M.omega * (L.b[v] - ax) / d;
+    }
+}
+
+// b_{l+1}[c] = sum over fine f of w(f, c) (b_l - A_l x)[f]
+__global__ __launch_bounds__(BT) void mg_restrict_kernel(BatchLaunch B, MGLaunch M, int l, const double* x) {
+    const MGLevelDev& F = M.lev[l];
+    const MGLevelDev& C = M.lev[l + 1];
+    const int c = blockIdx.x * BT + threadIdx.x;
+    if (c >= C.nv) return;
+    const int prob = mg_prob(C.off, B.nprob, c);
+    if (cg_skip(B, prob) || M.lc[prob] <= l) return;
+    const int fo = F.off[prob], fnx = F.dims[2 * prob], fny = F.dims[2 * prob + 1];
+    const int cnx = C.dims[2 * prob], loc = c - C.off[prob];
+    const int cx = loc % cnx, cy = loc / cnx;
+    // fine vertices with parent c lie within two of its image 2c (or, for the
+    // last coarse vertex of an odd grid, at the fine end)
+    const int bx = fnx <= 3 ? cx : (cx == cnx - 1 ? fnx - 1 : 2 * cx);
+    const int by = fny <= 3 ? cy : (cy == C.dims[2 * prob + 1] - 1 ? fny - 1 : 2 * cy);
+    double s = 0.0;
+    for (int fy = by - 2; fy <= by + 2; ++fy) {
+        if (fy < 0 || fy >= fny) continue;
+        const double wy = mg_weight(fy, fny, cy);
+        if (wy == 0.0) continue;
+        for (int fx = bx - 2; fx <= bx + 2; ++fx) {
+            if (fx < 0 || fx >= fnx) continue;
+            const double wx = mg_weight(fx, fnx, cx);
+            if (wx == 0.0) continue;
+            const int f = fo + fy * fnx + fx;
+            s += wx * wy * (F.b[f] - mg_apply(F, fo, fnx, fny, fx, fy, x));
+        }
+    }
+    C.b[c] = s;
+}
+
+// dense solve at each problem's coarsest level (one workgroup per problem)
+__global__ __launch_bounds__(64) void mg_coarse_kernel(BatchLaunch B, MGLaunch M) {
+    const int prob = blockIdx.x;
+    if (cg_skip(B, prob)) return;
+    const int l = M.lc[prob];
+    const MGLevelDev& L = M.lev[l];
+    const int o = L.off[prob], nc = L.dims[2 * prob] * L.dims[2 * prob + 1];
+    const double* Ci = M.cinv + M.coff[prob];
+    const int i = threadIdx.x;
+    if (i < nc) {
+        double s = 0.0;
+        for (int j = 0; j < nc; ++j) s += Ci[i * nc + j] * L.b[o + j];
+        L.x[o + i] = s;
+    }
+}
+
+// x_l[f] += sum over parents c of w(f, c) x_{l+1}[c]; the coarse iterate is in x
+// where level l+1 is the problem's coarsest, else in t
+__global__ __launch_bounds__(BT) void mg_prolong_kernel(BatchLaunch B, MGLaunch M, int l, double* xf) {
+    const MGLevelDev& F = M.lev[l];
+    const MGLevelDev& C = M.lev[l + 1];
+    const int f = blockIdx.x * BT + threadIdx.x;
+    if (f >= F.nv) return;
+    const int prob = mg_prob(F.off, B.nprob, f);
+    if (cg_skip(B, prob) || M.lc[prob] <= l) return;
+    const int fnx = F.dims[2 * prob], fny = F.dims[2 * prob + 1], loc = f - F.off[prob];
+    const int cnx = C.dims[2 * prob], co = C.off[prob];
+    const double* xc = M.lc[prob] == l + 1 ? C.x : C.t;
+    int x0, x1, y0, y1;
+    double wx0, wx1, wy0, wy1;
+    mg_parents(loc % fnx, fnx, x0, wx0, x1, wx1);
+    mg_parents(loc / fnx, fny, y0, wy0, y1, wy1);
+    double s = wx0 * wy0 * xc[co + y0 * cnx + x0];
+    if (x1 >= 0) s += wx1 * wy0 * xc[co + y0 * cnx + x1];
+    if (y1 >= 0) s += wx0 * wy1 * xc[co + y1 * cnx + x0];
+    if (x1 >= 0 && y1 >= 0) s += wx1 * wy1 * xc[co + y1 * cnx + x1];
+    xf[f] += s;
+}
+
+// z += P0 x_0 (bilinear interpolation at the nodes), partial sums of r.z
+__global__ __launch_bounds__(BT) void mg_finish_kernel(BatchLaunch B, MGLaunch M, int init) {
+    __shared__ double red[BT];
+    const EB m = eb_map(B);
+    double rz = 0.0;
+    if (m.K >= 0 && !cg_skip(B, m.prob)) {
+        const BProb& P = B.P[m.prob];
+        const MGLevelDev& L = M.lev[0];
+        const double* x0 = M.lc[m.prob] == 0 ? L.x : L.t;
+        const int o = L.off[m.prob], nvx = L.dims[2 * m.prob];
+        const int ex = m.K % P.nx, ey = m.K / P.nx;
+        const int a = m.i % P.nb, b = m.i / P.nb;
+        const double xa = P.gll[a], yb = P.gll[b];
+        const double* xv = x0 + o + ey * nvx + ex;
+        const double c = (1.0 - xa) * (1.0 - yb) * xv[0] + xa * (1.0 - yb) * xv[1] + (1.0 - xa) * yb * xv[nvx] +
+                         xa * yb * xv[nvx + 1];
+        const long t = (long)m.K * P.n + m.i;
+        const double z = P.z[t] + c;
+        P.z[t] = z;
+        if (init) P.p[t] = z;
+        rz = P.r[t] * z;
+    }
+    rz = b_block_sum(rz, red);
+    if (threadIdx.x == 0) B.part[(init ? 0 : 1) * B.nblocks + blockIdx.x] = rz;
+}
+
+hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStream_t s) {
+    auto grid = [](int n) { return dim3((unsigned)((n + BT - 1) / BT)); };
+    hipLaunchKernelGGL(mg_restrict0_kernel, grid(M.lev[0].nv), dim3(BT), 0, s, B, M);
+    for (int l = 0; l + 1 < M.nlev; ++l) {
+        const MGLevelDev& L = M.lev[l];
+        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 1, (const double*)L.x, L.x);
+        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.x, L.t);
+        hipLaunchKernelGGL(mg_restrict_kernel, grid(M.lev[l + 1].nv), dim3(BT), 0, s, B, M, l, (const double*)L.t);
+    }
+    hipLaunchKernelGGL(mg_coarse_kernel, dim3(B.nprob), dim3(64), 0, s, B, M);
+    for (int l = M.nlev - 2; l >= 0; --l) {
+        const MGLevelDev& L = M.lev[l];
+        hipLaunchKernelGGL(mg_prolong_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, L.t);
+        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.t, L.x);
+        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.x, L.t);
+    }
+    hipLaunchKernelGGL(mg_finish_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M, init ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -119,6 +119,7 @@ struct BProb {
     const float* feat0;                                     // [ne][4] per-element warm-start features
     double hxhy;                                            // element area
     int g0, ng;                                             // type-group range (PCG kernels)
+    const double* gll;                                      // [nb] Gauss-Lobatto points on [0,1]
 };
 
 struct BatchLaunch {
@@ -142,7 +143,31 @@ struct BatchLaunch {
     const int* g_elem;             // [ngroups][64]
     double* gpart;                 // [3][ngroups] per-group partial sums
     int grouped;                   // 1: PCG on the type groups, 0: per-node element blocks
+    int mg;                        // 1: two-level preconditioner (r.z from b_mg_apply)
 };
+
+// Two-level preconditioner: continuous Q1 coarse space on the element vertices
+// and a vertex multigrid V-cycle for it (one launch per level and step covers
+// every problem that has that level).
+constexpr int MG_MAXLEV = 12;
+struct MGLevelDev {
+    const int* off;   // [nprob+1] vertex offsets of this level (0 vertices: problem absent)
+    const int* dims;  // [nprob][2] vertex grid
+    const double* A;  // [9][nv] stencil, entry k = (dy+1)*3 + (dx+1)
+    double *x, *t, *b;
+    int nv;
+};
+struct MGLaunch {
+    int nlev;                   // levels of the deepest problem
+    MGLevelDev lev[MG_MAXLEV];
+    const int* lc;              // [nprob] coarsest level of each problem
+    const int* coff;            // [nprob] offset of its dense coarsest inverse
+    const double* cinv;
+    double omega;               // Jacobi damping
+};
+// z += P0 V(P0^T r) after the block-Jacobi z = D^-1 r; the partial sums of
+// r.z go to part[init ? 0 : 1][block], and with init p = z
+hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStream_t s);
 
 hipError_t b_source(bool fp64, const BatchLaunch& B, bool delta, hipStream_t s);
 hipError_t b_sweep(bool fp64, int nb, int mreg, int threads, size_t lds, int grid, const CartSweepArgs* args,
@@ -152,9 +177,10 @@ hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool firs
 hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s);
 hipError_t b_copy_x(const BatchLaunch& B, hipStream_t s);               // x = varphi
 hipError_t b_shift(const BatchLaunch& B, hipStream_t s);                // varphi_prev = varphi, varphi = x
-hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s);
-hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s);
+hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s, const MGLaunch* M);
+hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const MGLaunch* M);
 hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s);                // one q = A p launch
+hipError_t b_precond(const BatchLaunch& B, const MGLaunch* M, hipStream_t s); // z = M^-1 r (and p = z)
 hipError_t b_residual(const BatchLaunch& B, double* out, hipStream_t s);   // out[2*nprob]
 // warm start: features / targets of problems [first, first + count), the start from
 // the network output (varphi = varphi_D + s_K y), and varphi_D = x

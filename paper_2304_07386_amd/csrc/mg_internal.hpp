@@ -1,0 +1,27 @@
+// Host-side hierarchy of the two-level preconditioner (see mg.cpp).
+#pragma once
+
+#include <string>
+#include <vector>
+
+namespace smm {
+
+struct Problem;
+
+constexpr int MG_MAX_COARSE = 16;  // unknowns of the dense coarsest solve
+
+struct MGLevelHost {
+    int nvx = 0, nvy = 0;
+    std::vector<double> A;  // [9][nvx*nvy] stencil, entry k = (dy+1)*3 + (dx+1)
+};
+
+struct MGHost {
+    std::vector<MGLevelHost> lev;  // lev[0]: element vertices
+    std::vector<double> cinv;      // dense inverse of the coarsest level
+    std::vector<double> gll;       // Gauss-Lobatto points on [0,1] (nb)
+};
+
+int build_mg(const Problem& P, MGHost& M, std::string& err);
+int mg_coarse_count(int nf);
+
+}  // namespace smm

@@ -30,7 +30,7 @@ EXPORTED = [
     "smm_set_sweep_path", "smm_time_sweep", "smm_debug_typed_dense", "smm_debug_corr_dense",
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
-    "smm_batch_history",
+    "smm_batch_history", "smm_debug_mg_level", "smm_debug_batch_precond",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
@@ -59,7 +59,7 @@ class smm_solve_opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("outer_tol", C.c_double), ("max_outer", C.c_int),
                 ("inner_tol", C.c_double), ("max_inner", C.c_int), ("start", C.c_int),
                 ("delta_sweeps", C.c_int), ("use_graph", C.c_int), ("moment_path", C.c_int),
-                ("inner_adapt", C.c_double)]
+                ("precond", C.c_int), ("inner_adapt", C.c_double)]
 
 
 class smm_solve_info(C.Structure):
@@ -118,6 +118,8 @@ def load_library(path: str = LIB_PATH):
         "smm_batch_phase_times": (ip, [vp, dp, C.POINTER(C.c_long)]),
         "smm_batch_time_kernel": (ip, [vp, ip, ip, dp]),
         "smm_batch_history": (ip, [vp, ip, ip, vp, vp, C.POINTER(ip)]),
+        "smm_debug_mg_level": (ip, [vp, ip, vp, C.POINTER(ip), C.POINTER(ip)]),
+        "smm_debug_batch_precond": (ip, [vp, ip, C.POINTER(vp), C.POINTER(vp)]),
         "smm_cnn_create": (ip, [vp, ip, C.POINTER(ip), ip, ip, ip, C.POINTER(vp)]),
         "smm_cnn_destroy": (ip, [vp]),
         "smm_cnn_num_params": (ip, [vp, C.POINTER(C.c_size_t)]),
@@ -440,6 +442,27 @@ def smm_batch_units(batch: Batch) -> float:
 # ---- learned warm start (smm_cnn.h) -------------------------------------------------
 
 SMM_START_LEARNED = 3
+SMM_PRECOND_BJ, SMM_PRECOND_TWOLEVEL = 0, 1
+
+
+def smm_debug_batch_precond(batch, precond: int, rs):
+    """z = M^-1 r per problem (host arrays) with the given PCG preconditioner."""
+    rs = [_f64(r) for r in rs]
+    zs = [np.zeros_like(r) for r in rs]
+    rp = (C.c_void_p * len(rs))(*[r.ctypes.data for r in rs])
+    zp = (C.c_void_p * len(zs))(*[z.ctypes.data for z in zs])
+    _check(load_library().smm_debug_batch_precond(batch.handle, precond, rp, zp), batch.ctx)
+    return zs
+
+
+def smm_debug_mg_level(prob, level: int):
+    """9-point stencil [9][nvy*nvx] of a multigrid level of the two-level preconditioner."""
+    nx, ny = C.c_int(), C.c_int()
+    lib = load_library()
+    _check(lib.smm_debug_mg_level(prob.handle, level, None, C.byref(nx), C.byref(ny)), prob.ctx)
+    A = np.zeros((9, nx.value * ny.value))
+    _check(lib.smm_debug_mg_level(prob.handle, level, _ptr(A), C.byref(nx), C.byref(ny)), prob.ctx)
+    return A, nx.value, ny.value
 
 
 class Cnn:
