@@ -1,0 +1,130 @@
+"""HBM traffic of the dominant kernels from rocprofv3 counters.
+
+Two steps.  On the GPU, under rocprofv3 (one counter per run):
+
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_fetch> -o pmc -- \\
+        python -m paper_2304_07386_amd.counters run
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_write> -o pmc -- \\
+        python -m paper_2304_07386_amd.counters run
+
+`run` builds the 256-problem batch of bench.py, runs one short solve (so the
+PCG vectors hold a real state), then launches the batched sweep and the PCG
+kernel q = A p a few times each and copies a buffer of known size with
+hipMemcpy (calibration).  Then, anywhere:
+
+    python -m paper_2304_07386_amd.counters parse <dir_fetch> <dir_write> --out <json>
+
+reads the per-dispatch counters (KiB), scales each counter by what it reads
+for the copy of known size, and writes the HBM bytes per launch of each
+kernel, with the SHA-256 of the kernel source they were taken on.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_BYTES = 512 << 20
+SWEEP_REPS = 2
+SPMV_REPS = 5
+
+
+def run():
+    import torch
+    from . import smm as L
+    from .workload_io import problem_from_workload
+    sys.path.insert(0, os.path.dirname(HERE))
+    from workloads import config_batched_problem
+
+    ctx = L.smm_ctx_create(0, torch.cuda.current_stream())
+    probs = [problem_from_workload(ctx, config_batched_problem(s)) for s in range(256)]
+    batch = L.smm_batch_create(ctx, probs)
+    o = L.smm_default_opts(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=0.0, inner_tol=1e-10,
+                           max_inner=2, max_outer=1, precond=L.SMM_PRECOND_TWOLEVEL)
+    L.smm_batch_solve(batch, o, raise_on_noconv=False)
+    L.smm_batch_time_kernel(batch, L.SMM_KERNEL_SWEEP_FP32, SWEEP_REPS)
+    L.smm_batch_time_kernel(batch, L.SMM_KERNEL_CG_SPMV, SPMV_REPS)
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("[counters] done", flush=True)
+
+
+def _rows(d):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def _per_dispatch(rows):
+    """[(kernel name, value)] in dispatch order (values summed over dimensions)."""
+    acc = {}
+    order = []
+    for r in rows:
+        key = int(r.get("Dispatch_Id", r.get("Correlation_Id", 0)))
+        if key not in acc:
+            acc[key] = [r["Kernel_Name"], 0.0]
+            order.append(key)
+        acc[key][1] += float(r["Counter_Value"])
+    return [tuple(acc[k]) for k in sorted(order)]
+
+
+def parse(dir_fetch, dir_write, out):
+    res = {}
+    for which, d in (("fetch", dir_fetch), ("write", dir_write)):
+        disp = _per_dispatch(_rows(d))
+        copies = [v for n, v in disp if "copyBuffer" in n or "copy" in n.lower() and "smm" not in n]
+        big = max(copies) if copies else None
+        if not big:
+            raise RuntimeError("no calibration copy found")
+        scale = (COPY_BYTES / 1024.0) / big           # KiB of the copy / KiB the counter read
+        spmv = [v for n, v in disp if "b_cg_k1" in n][-SPMV_REPS:]
+        sweeps = [v for n, v in disp if "b_sweep_kernel" in n]
+        # the timed sweeps: the last SWEEP_REPS * (orders) dispatches
+        norders = len({n for n, v in disp if "b_sweep_kernel" in n})
+        sw = sweeps[-SWEEP_REPS * norders:]
+        res[which] = {"scale": scale, "copy_kib": big,
+                      "b_cg_k1": 1024.0 * scale * sum(spmv) / len(spmv),
+                      "b_sweep_kernel": 1024.0 * scale * sum(sw) / SWEEP_REPS}
+    src = os.path.join(HERE, "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    table = {}
+    for k in ("b_cg_k1", "b_sweep_kernel"):
+        table[k] = {"bytes_per_launch": res["fetch"][k] + res["write"][k],
+                    "fetch_bytes": res["fetch"][k], "write_bytes": res["write"][k],
+                    "source": "kernels.hip", "sha256": sha}
+    table["_calibration"] = {"copy_bytes": COPY_BYTES, "fetch_scale": res["fetch"]["scale"],
+                             "write_scale": res["write"]["scale"]}
+    with open(out, "w") as f:
+        json.dump(table, f, indent=1)
+    print(json.dumps(table, indent=1))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub.add_parser("run")
+    p = sub.add_parser("parse")
+    p.add_argument("dir_fetch")
+    p.add_argument("dir_write")
+    p.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "run":
+        run()
+    else:
+        parse(a.dir_fetch, a.dir_write, a.out)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
