@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--problems", type=int, default=256)
     ap.add_argument("--tts-problems", type=int, default=24, help="held-out problems for the time-to-solution run")
     ap.add_argument("--precond", type=int, default=1, help="0 block-Jacobi, 1 two-level PCG")
+    ap.add_argument("--anderson", type=int, default=2, help="Anderson mixing depth of the outer iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 comparison")
     args = ap.parse_args()
@@ -181,7 +182,7 @@ def main():
 
     opts = L.smm_default_opts(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=0.0,
                               inner_tol=1e-10, max_inner=20000, max_outer=max(args.warmup, 1),
-                              precond=args.precond, use_graph=1)
+                              precond=args.precond, use_graph=1, anderson=args.anderson)
     L.smm_batch_solve(batch, opts, raise_on_noconv=False)       # warm-up (also autotunes the sweep grids)
     torch.cuda.synchronize()
     opts.max_outer = args.steps

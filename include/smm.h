@@ -119,6 +119,8 @@ typedef struct {
     int moment_path;     /* 0: typed blocks on uniform Cartesian meshes with isotropic
                             sources (batched kernels), else per-element operators;
                             1: always per-element operators */
+    int anderson;        /* 0: plain fixed point X <- G(X); 1 or 2: Anderson mixing of the
+                            last anderson + 1 iterates (typed path only) */
     int precond;         /* SMM_PRECOND_BJ: block-Jacobi PCG; SMM_PRECOND_TWOLEVEL: block-Jacobi
                             plus a continuous Q1 coarse correction on the element vertices,
                             solved by one vertex multigrid V-cycle (typed path only) */

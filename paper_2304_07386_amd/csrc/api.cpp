@@ -246,6 +246,7 @@ void smm_default_opts(smm_solve_opts* o) {
     o->moment_path = 0;
     o->inner_adapt = 0.0;
     o->precond = SMM_PRECOND_BJ;
+    o->anderson = 0;
 }
 
 }  // extern "C"
@@ -577,6 +578,8 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     smm_ctx* c = P.ctx;
     if (c->device < 0) return fail(c, SMM_ESTATE, "host-only context");
     if (!P.have_mat) return fail(c, SMM_ESTATE, "materials not set");
+    if (o.anderson != 0 && !(o.moment_path == 0 && typed_applicable(P) && D.force_general != 1))
+        return fail(c, SMM_EUNSUPPORTED, "smm_solve: Anderson mixing needs the typed (batched) path");
     if (o.start < SMM_START_ZERO || o.start > SMM_START_GIVEN)
         return fail(c, SMM_EINVAL, "smm_solve: start must be ZERO, DIFFUSION or GIVEN (the learned start needs a batch)");
     if (o.moment_path == 0 && typed_applicable(P) && D.force_general != 1) {

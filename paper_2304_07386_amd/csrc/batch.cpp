@@ -49,6 +49,7 @@ struct PerProb {
     double* vdiff;
     float* feat0;
     double* gll;
+    double *aG, *aF;
 };
 
 struct Group {
@@ -129,6 +130,9 @@ struct smm_batch {
     double* d_mg_A[MG_MAXLEV] = {};
     double *d_mg_x[MG_MAXLEV] = {}, *d_mg_t[MG_MAXLEV] = {}, *d_mg_b[MG_MAXLEV] = {};
     int *d_mg_lc = nullptr, *d_mg_coff = nullptr;
+    double* d_mg_corner = nullptr;
+    // Anderson mixing
+    double *d_aapart = nullptr, *d_aadot = nullptr, *d_aacoef = nullptr;
     double* d_mg_cinv = nullptr;
     std::vector<Group> groups;
     CartSweepArgs* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -289,6 +293,8 @@ int batch_build(smm_batch* B) {
         pool.req(&q.by32, sizeof(float) * (size_t)P.nd * P.nx * P.nb);
         pool.req(&q.mat, ne);
         pool.req(&q.vdiff, sizeof(double) * L);
+        pool.req(&q.aG, sizeof(double) * 3 * L);
+        pool.req(&q.aF, sizeof(double) * 3 * L);
         pool.req(&q.feat0, sizeof(float) * 4 * ne);
         // element blocks
         const int epb = 256 / P.n;
@@ -370,6 +376,16 @@ int batch_build(smm_batch* B) {
         pool.req(&B->d_mg_b[l], sizeof(double) * nv);
     }
     pool.req(&B->d_mg_lc, sizeof(int) * np);
+    pool.req(&B->d_aadot, sizeof(double) * 6 * np);
+    pool.req(&B->d_aacoef, sizeof(double) * 3 * np);
+    {
+        long ne_all = 0;
+        for (int b = 0; b < np; ++b) {
+            B->hP[b].e_off = ne_all;
+            ne_all += B->probs[b]->P.ne;
+        }
+        pool.req(&B->d_mg_corner, sizeof(double) * 4 * std::max(ne_all, 1L));
+    }
     pool.req(&B->d_mg_coff, sizeof(int) * np);
     pool.req(&B->d_mg_cinv, sizeof(double) * std::max(cinv_tot, 1));
     for (int b = 0; b < np; ++b) pool.req(&B->pp[b].gll, sizeof(double) * B->probs[b]->P.nb);
@@ -392,6 +408,7 @@ int batch_build(smm_batch* B) {
     pool.req(&B->dP, sizeof(BProb) * np);
     pool.req(&B->d_blk2p, sizeof(int) * B->nblocks);
     pool.req(&B->part, sizeof(double) * 3 * std::max(B->nblocks, np));
+    pool.req(&B->d_aapart, sizeof(double) * 6 * B->nblocks);
     pool.req(&B->d_bq0, sizeof(long) * np);
     pool.req(&B->d_mw0, sizeof(long) * np);
     pool.req(&B->d_active, sizeof(int) * np);
@@ -536,6 +553,7 @@ int batch_build(smm_batch* B) {
         D.S = q.S; D.psi = q.psi;
         D.W64 = q.W64; D.W32 = q.W32;
         D.vdiff = q.vdiff; D.feat0 = q.feat0; D.hxhy = P.hx * P.hy;
+        D.aG = q.aG; D.aF = q.aF;
         if ((rc = check_desc(c, D, b))) return rc;
         for (int f = 0; f < 2; ++f)
             for (int g = 0; g < 2; ++g) {
@@ -608,6 +626,7 @@ int batch_build(smm_batch* B) {
         B->mgl.coff = B->d_mg_coff;
         B->mgl.cinv = B->d_mg_cinv;
         B->mgl.omega = 2.0 / 3.0;
+        B->mgl.corner = B->d_mg_corner;
     }
     if ((rc = put(c, B->dP, B->hP.data(), sizeof(BProb) * np))) return rc;
     if ((rc = put(c, B->d_blk2p, B->blk2p.data(), sizeof(int) * B->nblocks))) return rc;
@@ -899,6 +918,8 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     auto t1 = std::chrono::steady_clock::now();
     std::vector<double> ro(2 * (size_t)np);
     std::vector<double> r_prev(np, 1.0), tol_k(np, o.inner_tol);
+    const int aa = std::max(0, std::min(o.anderson, 2));
+    std::vector<double> gram(6 * (size_t)np), coef(3 * (size_t)np);
     int nactive = np;
     int it;
     for (auto& e : B->pev)
@@ -928,9 +949,74 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
         HIPCHK(c, hipEventRecord(B->pev[3], c->stream));
         HIPCHK(c, b_residual(L, B->d_rout, c->stream));
         HIPCHK(c, hipMemcpyAsync(ro.data(), B->d_rout, sizeof(double) * ro.size(), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, b_shift(L, c->stream));
+        const int slot = (it - 1) % 3;
+        if (aa > 0) {
+            HIPCHK(c, b_aa_store(L, slot, c->stream));
+            HIPCHK(c, b_aa_gram(L, B->d_aapart, B->d_aadot, c->stream));
+            HIPCHK(c, hipMemcpyAsync(gram.data(), B->d_aadot, sizeof(double) * gram.size(), hipMemcpyDeviceToHost,
+                                     c->stream));
+        } else {
+            HIPCHK(c, b_shift(L, c->stream));
+        }
         HIPCHK(c, hipEventRecord(B->pev[4], c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (aa > 0) {
+            // X_{k+1} = sum_i alpha_i G(X_{k-i}), sum alpha_i = 1, minimising
+            // |sum alpha_i f_{k-i}|_2 over the last min(k, aa) + 1 iterates
+            const int q = std::min(it - 1, aa) + 1;
+            for (int b = 0; b < np; ++b) {
+                double* cf = &coef[3 * (size_t)b];
+                cf[0] = cf[1] = cf[2] = 0.0;
+                cf[slot] = 1.0;
+                if (!B->active[b] || q < 2) continue;
+                const double rb = ro[2 * b + 1] > 0 ? ro[2 * b] / ro[2 * b + 1] : 0.0;
+                if (!(rb >= o.outer_tol)) continue;  // converging now: keep G(X_k)
+                const double* gm = &gram[6 * (size_t)b];
+                auto dot = [&](int i, int j) {
+                    if (i > j) std::swap(i, j);
+                    static const int idx[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+                    return gm[idx[i][j]];
+                };
+                int sl[3];
+                for (int i = 0; i < q; ++i) sl[i] = ((slot - i) % 3 + 3) % 3;
+                double H[9], tr = 0;
+                for (int i = 0; i < q; ++i)
+                    for (int j = 0; j < q; ++j) H[i * q + j] = dot(sl[i], sl[j]);
+                for (int i = 0; i < q; ++i) tr += H[i * q + i];
+                for (int i = 0; i < q; ++i) H[i * q + i] += 1e-10 * tr;
+                double y[3] = {1, 1, 1};
+                // Gaussian elimination (q <= 3), H symmetric positive semidefinite + shift
+                bool ok = tr > 0 && std::isfinite(tr);
+                for (int col = 0; ok && col < q; ++col) {
+                    const double pv = H[col * q + col];
+                    if (!(std::fabs(pv) > 0)) {
+                        ok = false;
+                        break;
+                    }
+                    for (int r = col + 1; r < q; ++r) {
+                        const double f = H[r * q + col] / pv;
+                        for (int k2 = col; k2 < q; ++k2) H[r * q + k2] -= f * H[col * q + k2];
+                        y[r] -= f * y[col];
+                    }
+                }
+                double al[3] = {0, 0, 0};
+                for (int r = q - 1; ok && r >= 0; --r) {
+                    double v = y[r];
+                    for (int k2 = r + 1; k2 < q; ++k2) v -= H[r * q + k2] * al[k2];
+                    al[r] = v / H[r * q + r];
+                }
+                double ssum = 0, sabs = 0;
+                for (int i = 0; i < q; ++i) {
+                    ssum += al[i];
+                    sabs += std::fabs(al[i]);
+                }
+                if (!ok || !std::isfinite(ssum) || ssum == 0 || sabs / std::fabs(ssum) > 1e3) continue;
+                for (int i = 0; i < q; ++i) cf[sl[i]] = al[i] / ssum;
+            }
+            if ((rc = put(c, B->d_aacoef, coef.data(), sizeof(double) * coef.size()))) return rc;
+            HIPCHK(c, b_aa_mix(L, B->d_aacoef, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));  // before the host updates the active flags
+        }
         for (int ph = 0; ph < 4; ++ph) {
             float ms = 0;
             HIPCHK(c, hipEventElapsedTime(&ms, B->pev[ph], B->pev[ph + 1]));

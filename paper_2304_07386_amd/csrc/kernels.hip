@@ -2123,9 +2123,34 @@ __device__ __forceinline__ double mg_apply(const MGLevelDev& L, int o, int nvx, 
     return s;
 }
 
-// level 0 right-hand side: b_v = sum over the (<= 4) elements at vertex v and
-// their nodes of hat_v(node) r(node)
-__global__ __launch_bounds__(BT) void mg_restrict0_kernel(BatchLaunch B, MGLaunch M) {
+// level 0 right-hand side, in two steps: the corner sums of every element,
+// c[K][corner] = sum over its nodes of hat_corner(node) r(node) (one thread per
+// node, reduced over the element's threads in LDS), then per vertex the sum of
+// the (<= 4) corner sums at it.
+__global__ __launch_bounds__(BT) void mg_corner_kernel(BatchLaunch B, double* corner) {
+    __shared__ double w[4][BT];
+    const EB m = eb_map(B);
+    const bool on = m.K >= 0 && !cg_skip(B, m.prob);
+    if (on) {
+        const BProb& P = B.P[m.prob];
+        const int a = m.i % P.nb, b = m.i / P.nb;
+        const double xa = P.gll[a], yb = P.gll[b];
+        const double r = P.r[(long)m.K * P.n + m.i];
+        w[0][threadIdx.x] = (1.0 - xa) * (1.0 - yb) * r;
+        w[1][threadIdx.x] = xa * (1.0 - yb) * r;
+        w[2][threadIdx.x] = (1.0 - xa) * yb * r;
+        w[3][threadIdx.x] = xa * yb * r;
+    }
+    __syncthreads();
+    if (on && m.i < 4) {
+        const BProb& P = B.P[m.prob];
+        double s = 0.0;
+        for (int j = 0; j < P.n; ++j) s += w[m.i][m.e0 + j];
+        corner[4L * (P.e_off + m.K) + m.i] = s;
+    }
+}
+
+__global__ __launch_bounds__(BT) void mg_restrict0_kernel(BatchLaunch B, MGLaunch M, const double* corner) {
     const MGLevelDev& L = M.lev[0];
     const int v = blockIdx.x * BT + threadIdx.x;
     if (v >= L.nv) return;
@@ -2134,19 +2159,14 @@ __global__ __launch_bounds__(BT) void mg_restrict0_kernel(BatchLaunch B, MGLaunc
     const BProb& P = B.P[prob];
     const int o = L.off[prob], nvx = L.dims[2 * prob], loc = v - o;
     const int ix = loc % nvx, iy = loc / nvx;
-    const int nb = P.nb, n = P.n, nx = nvx - 1, ny = L.dims[2 * prob + 1] - 1;
+    const int nx = nvx - 1, ny = L.dims[2 * prob + 1] - 1;
+    const double* c = corner + 4L * P.e_off;
     double s = 0.0;
     for (int cy = 0; cy < 2; ++cy)
         for (int cx = 0; cx < 2; ++cx) {
             const int ex = ix - cx, ey = iy - cy;
             if (ex < 0 || ey < 0 || ex >= nx || ey >= ny) continue;
-            const double* r = P.r + ((long)ey * nx + ex) * n;
-            for (int b = 0; b < nb; ++b) {
-                const double hy = cy ? P.gll[b] : 1.0 - P.gll[b];
-                double t = 0.0;
-                for (int a = 0; a < nb; ++a) t += (cx ? P.gll[a] : 1.0 - P.gll[a]) * r[a + nb * b];
-                s += hy * t;
-            }
+            s += c[4L * (ey * nx + ex) + cx + 2 * cy];
         }
     L.b[v] = s;
 }
@@ -2267,7 +2287,8 @@ __global__ __launch_bounds__(BT) void mg_finish_kernel(BatchLaunch B, MGLaunch M
 
 hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStream_t s) {
     auto grid = [](int n) { return dim3((unsigned)((n + BT - 1) / BT)); };
-    hipLaunchKernelGGL(mg_restrict0_kernel, grid(M.lev[0].nv), dim3(BT), 0, s, B, M);
+    hipLaunchKernelGGL(mg_corner_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M.corner);
+    hipLaunchKernelGGL(mg_restrict0_kernel, grid(M.lev[0].nv), dim3(BT), 0, s, B, M, (const double*)M.corner);
     for (int l = 0; l + 1 < M.nlev; ++l) {
         const MGLevelDev& L = M.lev[l];
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 1, (const double*)L.x, L.x);
@@ -2282,6 +2303,79 @@ hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStr
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.x, L.t);
     }
     hipLaunchKernelGGL(mg_finish_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M, init ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ---- Anderson mixing of the outer fixed point ------------------------------------
+__global__ __launch_bounds__(BT) void b_aa_store_kernel(BatchLaunch B, int slot) {
+    const EB m = eb_map(B);
+    if (!B.active[m.prob] || m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i, o = (long)slot * P.L + t;
+    const double g = P.x[t];
+    P.aG[o] = g;
+    P.aF[o] = g - P.varphi[t];
+}
+
+__global__ __launch_bounds__(BT) void b_aa_gram_part(BatchLaunch B, double* part6) {
+    __shared__ double red[BT];
+    const EB m = eb_map(B);
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (B.active[m.prob] && m.K >= 0) {
+        const BProb& P = B.P[m.prob];
+        const long t = (long)m.K * P.n + m.i;
+        const double f0 = P.aF[t], f1 = P.aF[P.L + t], f2 = P.aF[2 * P.L + t];
+        v[0] = f0 * f0;
+        v[1] = f0 * f1;
+        v[2] = f0 * f2;
+        v[3] = f1 * f1;
+        v[4] = f1 * f2;
+        v[5] = f2 * f2;
+    }
+    for (int k = 0; k < 6; ++k) {
+        const double s = b_block_sum(v[k], red);
+        if (threadIdx.x == 0) part6[(long)k * B.nblocks + blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(BT) void b_aa_gram_final(BatchLaunch B, const double* part6, double* out) {
+    __shared__ double red[BT];
+    const int prob = blockIdx.x;
+    const BProb& P = B.P[prob];
+    for (int k = 0; k < 6; ++k) {
+        double v = 0.0;
+        for (int j = threadIdx.x; j < P.nblk; j += BT) v += part6[(long)k * B.nblocks + P.blk0 + j];
+        v = b_block_sum(v, red);
+        if (threadIdx.x == 0) out[6 * prob + k] = v;
+    }
+}
+
+__global__ __launch_bounds__(BT) void b_aa_mix_kernel(BatchLaunch B, const double* coef) {
+    const EB m = eb_map(B);
+    if (!B.active[m.prob] || m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i;
+    const double* c = coef + 3 * m.prob;
+    double v = c[0] * P.aG[t];
+    if (c[1] != 0.0) v += c[1] * P.aG[P.L + t];
+    if (c[2] != 0.0) v += c[2] * P.aG[2 * P.L + t];
+    P.varphi_prev[t] = P.varphi[t];
+    P.varphi[t] = v;
+}
+
+hipError_t b_aa_store(const BatchLaunch& B, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(b_aa_store_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, slot);
+    return hipGetLastError();
+}
+
+hipError_t b_aa_gram(const BatchLaunch& B, double* part6, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(b_aa_gram_part, dim3(B.nblocks), dim3(BT), 0, s, B, part6);
+    hipLaunchKernelGGL(b_aa_gram_final, dim3(B.nprob), dim3(BT), 0, s, B, (const double*)part6, out);
+    return hipGetLastError();
+}
+
+hipError_t b_aa_mix(const BatchLaunch& B, const double* coef, hipStream_t s) {
+    hipLaunchKernelGGL(b_aa_mix_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, coef);
     return hipGetLastError();
 }
 

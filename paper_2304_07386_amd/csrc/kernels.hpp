@@ -120,6 +120,8 @@ struct BProb {
     double hxhy;                                            // element area
     int g0, ng;                                             // type-group range (PCG kernels)
     const double* gll;                                      // [nb] Gauss-Lobatto points on [0,1]
+    long e_off;                                             // first element in batch-wide element arrays
+    double *aG, *aF;                                        // [3][L] Anderson history: G(X) and G(X) - X
 };
 
 struct BatchLaunch {
@@ -164,6 +166,7 @@ struct MGLaunch {
     const int* coff;            // [nprob] offset of its dense coarsest inverse
     const double* cinv;
     double omega;               // Jacobi damping
+    double* corner;             // [4][batch elements] corner sums of the residual
 };
 // z += P0 V(P0^T r) after the block-Jacobi z = D^-1 r; the partial sums of
 // r.z go to part[init ? 0 : 1][block], and with init p = z
@@ -182,6 +185,13 @@ hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const
 hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s);                // one q = A p launch
 hipError_t b_precond(const BatchLaunch& B, const MGLaunch* M, hipStream_t s); // z = M^-1 r (and p = z)
 hipError_t b_residual(const BatchLaunch& B, double* out, hipStream_t s);   // out[2*nprob]
+// Anderson mixing of the outer fixed point: store G(X) = x and f = x - varphi in
+// history slot `slot`; the Gram matrix of the three f slots (out[6*nprob]:
+// f0.f0, f0.f1, f0.f2, f1.f1, f1.f2, f2.f2); and varphi_prev = varphi,
+// varphi = sum_i coef[3*prob + i] G_i
+hipError_t b_aa_store(const BatchLaunch& B, int slot, hipStream_t s);
+hipError_t b_aa_gram(const BatchLaunch& B, double* part6, double* out, hipStream_t s);
+hipError_t b_aa_mix(const BatchLaunch& B, const double* coef, hipStream_t s);
 // warm start: features / targets of problems [first, first + count), the start from
 // the network output (varphi = varphi_D + s_K y), and varphi_D = x
 hipError_t b_ws_features(const BatchLaunch& B, int first, int count, float* X, int nf, hipStream_t s);

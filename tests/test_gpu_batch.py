@@ -215,3 +215,34 @@ def test_two_level_preconditioner(ctx, prec):
         ref, _ = osmm.solve(pr, tol=1e-13, max_it=200)
         assert rel_l2(outs["mg"][k], ref) < (1e-11 if prec == 0 else 1e-5), k
     L.smm_batch_destroy(batch)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_anderson_mixing(ctx, prec):
+    """Anderson mixing of the outer fixed point reaches the same converged
+    answers (oracle parity) in fewer outer iterations."""
+    announce(f"batch: Anderson mixing, precision {prec}")
+    wls = _batch_members() + [config_blobs(20005, n=20), config_channel(n=20, side=1.6)]
+    pairs = [make_pair(L, ctx, wl) for wl in wls]
+    batch = L.smm_batch_create(ctx, [p for _, p in pairs])
+    tol = 1e-12 if prec == 0 else 1e-8
+    its, outs = {}, {}
+    for depth in (0, 1, 2):
+        o = _opts(prec, tol, delta=prec)
+        o.precond = L.SMM_PRECOND_TWOLEVEL
+        o.anderson = depth
+        rc, infos = L.smm_batch_solve(batch, o)
+        assert rc == L.SMM_OK, depth
+        its[depth] = sum(i["iterations"] for i in infos)
+        outs[depth] = []
+        for k, (_, p) in enumerate(pairs):
+            v = np.zeros(p.n_elem * p.n_node)
+            L.smm_batch_get_outputs(batch, k, varphi=v)
+            outs[depth].append(v)
+    print("outer iterations by Anderson depth", its)
+    assert its[2] < its[0] and its[1] < its[0]
+    for k, (pr, _) in enumerate(pairs):
+        ref, _ = osmm.solve(pr, tol=1e-13, max_it=200)
+        for depth in (1, 2):
+            assert rel_l2(outs[depth][k], ref) < (1e-10 if prec == 0 else 1e-5), (depth, k)
+    L.smm_batch_destroy(batch)
