@@ -1,10 +1,10 @@
 // Batched SMM solves on uniform Cartesian meshes: many problems of different
 // size, order p and S_N set share each kernel launch.
 //
-//  * the sweep runs as one persistent launch per order p, whose workgroups
-//    take (problem, direction) tasks from a queue ordered by decreasing cost;
-//    the launches of the different orders run concurrently on forked
-//    streams;
+//  * the sweep runs as one persistent launch per order p and workgroup size
+//    (64-slot chunks of the longest anti-diagonal), whose workgroups take
+//    (problem, direction) tasks from a queue ordered by decreasing cost; the
+//    launches run concurrently on forked streams;
 //  * moments, closures, right-hand side, block-Jacobi PCG and the outer
 //    residual run as single launches over all problems, with per-problem
 //    reductions and convergence flags (problems that have converged drop out
@@ -53,8 +53,8 @@ struct PerProb {
 };
 
 struct Group {
-    int nb = 0, mreg_any = 1, threads = 0;
-    int mreg[2] = {0, 0};                  // per precision: 1 register-resident rows, 0 LDS tables
+    int nb = 0, threads = 0;
+    bool multi = false;                    // some problem has several materials
     size_t lds[2] = {0, 0};
     int grid[2] = {0, 0};
     std::vector<int2> tasks;
@@ -135,6 +135,7 @@ struct smm_batch {
     double *d_aapart = nullptr, *d_aadot = nullptr, *d_aacoef = nullptr;
     double* d_mg_cinv = nullptr;
     std::vector<Group> groups;
+    int* d_sweep_counters = nullptr;  // [groups] task counters of the persistent sweeps
     CartSweepArgs* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -417,32 +418,45 @@ int batch_build(smm_batch* B) {
     pool.req(&B->d_tol, sizeof(double) * np);
     for (int f = 0; f < 2; ++f)
         for (int g = 0; g < 2; ++g) pool.req(&B->d_args[f][g], sizeof(CartSweepArgs) * np);
-    // sweep groups by order
-    std::map<int, int> gi;
+    // sweep groups by order and anti-diagonal chunks (64 slots each): the
+    // workgroup of a group is NB waves per chunk of its longest anti-diagonal
+    std::map<std::pair<int, int>, int> gi;
     B->groups.clear();
     for (int b = 0; b < np; ++b) {
         const Problem& P = B->probs[b]->P;
-        if (!gi.count(P.nb)) {
-            gi[P.nb] = (int)B->groups.size();
+        const int th = b_sweep_threads(P.nb, P.nx, P.ny);
+        if (th > 1024) return fail(c, SMM_EUNSUPPORTED, "anti-diagonal too long for one workgroup");
+        const auto key = std::make_pair(P.nb, th);
+        if (!gi.count(key)) {
+            gi[key] = (int)B->groups.size();
             B->groups.push_back(Group{});
             B->groups.back().nb = P.nb;
-            B->groups.back().mreg_any = 1;
+            B->groups.back().threads = th;
         }
-        Group& G = B->groups[gi[P.nb]];
-        const int maxlen = std::min(P.nx, P.ny);
-        G.threads = std::max(G.threads, (maxlen * P.nb + 63) / 64 * 64);
-        if (P.nmat != 1) G.mreg_any = 0;
+        Group& G = B->groups[gi[key]];
+        if (P.nmat != 1) G.multi = true;
         for (int d = 0; d < P.nd; ++d) G.tasks.push_back(make_int2(b, d));
     }
+    // most work first: with more groups than side streams, the small groups
+    // queue behind the large ones instead of the other way round
+    {
+        auto work = [&](const Group& G) {
+            double w = 0;
+            for (const int2& t : G.tasks) {
+                const Problem& P = B->probs[t.x]->P;
+                w += (double)P.ne * P.n;
+            }
+            return w;
+        };
+        std::stable_sort(B->groups.begin(), B->groups.end(),
+                         [&](const Group& a, const Group& b) { return work(a) > work(b); });
+    }
     for (Group& G : B->groups) {
-        if (G.threads > 1024) return fail(c, SMM_EUNSUPPORTED, "anti-diagonal too long for one workgroup");
         for (int f = 0; f < 2; ++f) {
-            // same rule as the launcher: register rows only where they do not spill
-            G.mreg[f] = (G.mreg_any && G.threads <= 512 && G.nb <= (f == 1 ? 3 : 4)) ? 1 : 0;
             size_t lds = 0;
             for (const int2& t : G.tasks) {
                 const Problem& P = B->probs[t.x]->P;
-                lds = std::max(lds, b_sweep_lds(f == 1, G.nb, G.mreg[f], P.nx, P.ny, P.nmat));
+                lds = std::max(lds, b_sweep_lds(f == 1, G.nb, G.multi, P.nx, P.ny));
             }
             G.lds[f] = lds;
         }
@@ -455,10 +469,12 @@ int batch_build(smm_batch* B) {
             return ca > cb;
         });
         pool.req(&G.d_tasks, sizeof(int2) * G.tasks.size());
-        pool.req(&G.d_counter, sizeof(int) * 4);
     }
+    // task counters of all groups in one block (cleared by one launch)
+    pool.req(&B->d_sweep_counters, sizeof(int) * std::max<size_t>(B->groups.size(), 1));
     if (hipMalloc(&B->pool, pool.total) != hipSuccess) return fail(c, SMM_ENOMEM, "batch pool allocation");
     for (const auto& r : pool.reqs) *r.dst = static_cast<char*>(B->pool) + r.off;
+    for (size_t k = 0; k < B->groups.size(); ++k) B->groups[k].d_counter = B->d_sweep_counters + k;
     if (hipMemset(B->pool, 0, pool.total) != hipSuccess) return fail(c, SMM_EHIP, "hipMemset");
     // uploads and descriptors
     std::vector<CartSweepArgs> args[2][2];
@@ -627,6 +643,26 @@ int batch_build(smm_batch* B) {
         B->mgl.cinv = B->d_mg_cinv;
         B->mgl.omega = 2.0 / 3.0;
         B->mgl.corner = B->d_mg_corner;
+        // first level from which every problem's remaining levels fit in the
+        // LDS of one workgroup (three vectors per level)
+        B->mgl.ls = mg_nlev;
+        B->mgl.lds = 0;
+        for (int l = 1; l < mg_nlev; ++l) {
+            size_t need = 0;
+            for (int b = 0; b < np; ++b) {
+                size_t sz = 0;
+                for (int k = l; k < (int)mgh[b].lev.size(); ++k)
+                    sz += 3 * sizeof(double) * (size_t)mgh[b].lev[k].nvx * mgh[b].lev[k].nvy;
+                need = std::max(need, sz);
+            }
+            if (need <= MG_LDS_CAP) {
+                B->mgl.ls = l;
+                B->mgl.lds = need;
+                break;
+            }
+        }
+        if (B->mgl.ls < mg_nlev && mg_prepare(B->mgl.lds) != hipSuccess)
+            return fail(c, SMM_EHIP, "multigrid workgroup LDS size");
     }
     if ((rc = put(c, B->dP, B->hP.data(), sizeof(BProb) * np))) return rc;
     if ((rc = put(c, B->d_blk2p, B->blk2p.data(), sizeof(int) * B->nblocks))) return rc;
@@ -656,6 +692,7 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
     smm_ctx* c = B->ctx;
     const int f = fp64 ? 1 : 0;
     const int ng = (int)B->groups.size();
+    HIPCHK(c, zero_ints(B->d_sweep_counters, ng, c->stream));
     if (ng > 1) {
         HIPCHK(c, hipEventRecord(B->ev_fork, c->stream));
         for (int k = 0; k < ng; ++k) HIPCHK(c, hipStreamWaitEvent(B->side[k % 4], B->ev_fork, 0));
@@ -663,9 +700,8 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
     for (int k = 0; k < ng; ++k) {
         Group& G = B->groups[k];
         hipStream_t s = ng > 1 ? B->side[k % 4] : c->stream;
-        HIPCHK(c, zero_ints(G.d_counter, 1, s));
         int grid = G.grid[f] > 0 ? G.grid[f] : std::min<int>((int)G.tasks.size(), 2 * B->ncu);
-        hipError_t e = b_sweep(fp64, G.nb, G.mreg[f], G.threads, G.lds[f], grid, B->d_args[f][inflow ? 1 : 0],
+        hipError_t e = b_sweep(fp64, G.nb, G.multi, G.threads, G.lds[f], grid, B->d_args[f][inflow ? 1 : 0],
                                G.d_tasks, (int)G.tasks.size(), G.d_counter, B->d_active, s);
         if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("batched sweep: ") + hipGetErrorString(e));
     }
@@ -688,7 +724,7 @@ int batch_autotune(smm_batch* B, bool fp64) {
     HIPCHK(c, hipEventCreate(&e1));
     for (Group& G : B->groups) {
         if (G.grid[f] > 0) continue;
-        auto key = std::make_tuple(G.nb, G.mreg[f], G.threads, G.lds[f], G.tasks.size(), f);
+        auto key = std::make_tuple(G.nb, (int)G.multi, G.threads, G.lds[f], G.tasks.size(), f);
         auto it = tune_cache().find(key);
         if (it != tune_cache().end()) {
             G.grid[f] = it->second;
@@ -703,7 +739,7 @@ int batch_autotune(smm_batch* B, bool fp64) {
             for (int rep = 0; rep < 3 && ok; ++rep) {
                 HIPCHK(c, zero_ints(G.d_counter, 1, c->stream));
                 HIPCHK(c, hipEventRecord(e0, c->stream));
-                hipError_t e = b_sweep(fp64, G.nb, G.mreg[f], G.threads, G.lds[f], grid, B->d_args[f][1], G.d_tasks,
+                hipError_t e = b_sweep(fp64, G.nb, G.multi, G.threads, G.lds[f], grid, B->d_args[f][1], G.d_tasks,
                                        (int)G.tasks.size(), G.d_counter, B->d_active, c->stream);
                 if (e != hipSuccess) {
                     ok = false;

@@ -18,6 +18,23 @@ namespace smm {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// Global-address-space views of buffer pointers that reach a kernel through a
+// descriptor in memory.  Through a generic pointer the compiler emits flat
+// instructions, which also count as LDS operations: every wait for the LDS
+// before a barrier would then wait for the outstanding HBM loads and stores.
+template <typename T>
+using gptr = T __attribute__((address_space(1)))*;
+template <typename T>
+using gcptr = const T __attribute__((address_space(1)))*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+    return (gptr<T>)(unsigned long)p;
+}
+template <typename T>
+__device__ __forceinline__ gcptr<T> as_global(const T* p) {
+    return (gcptr<T>)(unsigned long)p;
+}
+
 // ---------------------------------------------------------------------------
 // Cartesian sweep.
 // For direction d in quadrant (sx, sy), element (i, j) receives its x-face
@@ -142,10 +159,11 @@ __device__ __forceinline__ void sweep_cart_task(const CartSweepArgs& a, const in
     const T* Pm = reinterpret_cast<const T*>(a.Pm);
     const T* Px = reinterpret_cast<const T*>(a.Px);
     const T* Py = reinterpret_cast<const T*>(a.Py);
-    const T* S = reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0);
-    T* psi = reinterpret_cast<T*>(a.psi) + (long)d * (a.psi_ld > 0 ? a.psi_ld : ne * N);
+    const auto S = as_global(reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0));
+    const auto psi = as_global(reinterpret_cast<T*>(a.psi) + (long)d * (a.psi_ld > 0 ? a.psi_ld : ne * N));
     if constexpr (MREG != 1) {
-        for (long t = threadIdx.x; t < ne; t += blockDim.x) msh[t] = a.mat[t];
+        const auto mat = as_global(a.mat);
+        for (long t = threadIdx.x; t < ne; t += blockDim.x) msh[t] = mat[t];
     }
 
     // operator rows of this thread's node column
@@ -179,8 +197,8 @@ __device__ __forceinline__ void sweep_cart_task(const CartSweepArgs& a, const in
             }
         }
     }
-    const T* bx = reinterpret_cast<const T*>(a.bx);
-    const T* by = reinterpret_cast<const T*>(a.by);
+    const auto bx = as_global(reinterpret_cast<const T*>(a.bx));
+    const auto by = as_global(reinterpret_cast<const T*>(a.by));
     for (int t = threadIdx.x; t < ny * NB; t += blockDim.x) {
         const T v = bx ? bx[(long)d * ny * NB + t] : T(0);
         xtr[t] = v;
@@ -1155,9 +1173,237 @@ hipError_t zero_ints(int* p, int n, hipStream_t s) {
 }
 
 // ---- persistent sweep over (problem, direction) tasks ------------------------
+// Lane-per-element Cartesian sweep.  Wave w of the workgroup owns node column
+// ca = w mod NB of the elements in slots 64 (w / NB) + lane of each
+// anti-diagonal, i.e. rows ca + NB b (b < NB) of the element's local solution.
+// The operator rows of that column, [Pm | Px | Py], are then the same for all
+// lanes of the wave (one material): they are read through the constant address
+// space, arrive by scalar loads and enter the FMAs as SGPR operands, so neither
+// registers nor LDS hold per-lane copies of the operator.  Waves holding
+// elements of several materials make one pass per material present.
+// Source and angular flux move between HBM and LDS with element-major flat
+// indices (consecutive lanes, consecutive words of one element's block): the
+// source of level m + D is loaded into registers during level m and parked in
+// LDS during level m + D - 1; the flux of level m is staged in LDS and stored
+// during level m + 1.  LDS rows have odd strides, so the lanes' rows fall in
+// distinct banks.
+template <typename T>
+using cptr = const T __attribute__((address_space(4)))*;
+
+// Wave-uniform pointer into the constant address space.  The empty asm makes
+// the value opaque, so loads through it are not hoisted out of the level loop:
+// the operator is re-read from the scalar cache each level instead of being
+// pinned in (far too many) SGPRs.
+template <typename T>
+__device__ __forceinline__ cptr<T> uniform_rows(const T* p) {
+    const unsigned long v = (unsigned long)p;
+    unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return (cptr<T>)(((unsigned long)hi << 32) | lo);
+}
+
+// Word w of a global array whose byte size is below 4 GiB: the 32-bit byte
+// offset lets loads and stores use a scalar base plus a vector offset.
+template <typename T>
+__device__ __forceinline__ T ld_at(gcptr<T> p, unsigned w) {
+    return *(gcptr<T>)((const char __attribute__((address_space(1)))*)p + w * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st_at(gptr<T> p, unsigned w, T v) {
+    *(gptr<T>)((char __attribute__((address_space(1)))*)p + w * (unsigned)sizeof(T)) = v;
+}
+
+__host__ __device__ constexpr int lane_ns(int nb) { return (nb * nb) | 1; }  // LDS row stride of a block
+__host__ __device__ constexpr int lane_ts(int nb) { return nb | 1; }         // LDS row stride of a trace
+constexpr int LANE_PREFETCH = 3;  // levels between a source load and its use
+
+template <typename T, int NB, bool MULTI, int D>
+__device__ __forceinline__ void sweep_lane_task(const CartSweepArgs& a, const int d, unsigned char* smem) {
+    constexpr int N = NB * NB;
+    constexpr int NS = lane_ns(NB);
+    constexpr int TS = lane_ts(NB);
+    const int nx = a.nx, ny = a.ny, nd = a.nd;
+    const long ne = (long)nx * ny;
+    const int maxlen = nx < ny ? nx : ny;
+    const int nlev = nx + ny - 1;
+    const int nthr = blockDim.x;
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ca = w % NB;
+    const int chunk0 = (w / NB) * 64;  // first slot of this wave
+    const int slot = chunk0 + (tid & 63);
+    const int rslot = slot < maxlen ? slot : maxlen - 1;
+    T* xtr = reinterpret_cast<T*>(smem);  // [2][ny][TS]
+    T* ytr = xtr + 2 * ny * TS;           // [2][nx][TS]
+    T* sch = ytr + 2 * nx * TS;           // [2][maxlen][NS] source of a level (by parity)
+    T* pst = sch + 2 * maxlen * NS;       // [2][maxlen][NS] flux of a level (by parity)
+    uint8_t* msh = reinterpret_cast<uint8_t*>(pst + 2 * maxlen * NS);  // [ne] (MULTI)
+    const auto om = as_global(a.omega);
+    const double ox = om[d * 3], oy = om[d * 3 + 1];
+    const bool sx = ox > 0.0, sy = oy > 0.0;
+    const auto S = as_global(reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0));
+    const auto psi = as_global(reinterpret_cast<T*>(a.psi) + (long)d * (a.psi_ld > 0 ? a.psi_ld : ne * N));
+    const T* Pm = reinterpret_cast<const T*>(a.Pm);
+    const T* Px = reinterpret_cast<const T*>(a.Px);
+    const T* Py = reinterpret_cast<const T*>(a.Py);
+    if constexpr (MULTI) {
+        const auto mat = as_global(a.mat);
+        for (long t = tid; t < ne; t += nthr) msh[t] = mat[t];
+    }
+    const auto bx = as_global(reinterpret_cast<const T*>(a.bx));
+    const auto by = as_global(reinterpret_cast<const T*>(a.by));
+    for (int t = tid; t < ny * NB; t += nthr) {
+        const int j = t / NB, c = t - j * NB;
+        const T v = bx ? bx[(long)d * ny * NB + t] : T(0);
+        xtr[j * TS + c] = v;
+        xtr[(ny + j) * TS + c] = v;
+    }
+    for (int t = tid; t < nx * NB; t += nthr) {
+        const int i = t / NB, c = t - i * NB;
+        const T v = by ? by[(long)d * nx * NB + t] : T(0);
+        ytr[i * TS + c] = v;
+        ytr[(nx + i) * TS + c] = v;
+    }
+    // level geometry: first x index on the quadrant-oriented grid and length
+    auto lev_i0 = [&](int l) { return l - (ny - 1) > 0 ? l - (ny - 1) : 0; };
+    auto lev_len = [&](int l) {
+        const int i1 = l < nx - 1 ? l : nx - 1;
+        return l < nlev ? i1 - lev_i0(l) + 1 : 0;
+    };
+    // The element of slot s at level l is K0(s) + acc(l): K0(s) is its index
+    // at level 0 (outside the grid for s > 0) and acc(l) the wave-uniform sum
+    // of the steps from level to level (+-nx while the first slot of a level
+    // moves along y, +-1 once it moves along x).  ne N < 2^31 words per
+    // direction, so word offsets are 32-bit.
+    const int dyK = sy ? nx : -nx, dxK = sx ? 1 : -1;
+    auto acc_of = [&](int l) { return l <= ny - 1 ? l * dyK : (ny - 1) * dyK + (l - (ny - 1)) * dxK; };
+    auto K0 = [&](int s) { return (sy ? -s : ny - 1 + s) * nx + (sx ? s : nx - 1 - s); };
+    // flat element-major indices of this thread: f = tid + nthr r covers
+    // maxlen * N <= nthr * NB words of a level; word f of a level lies at
+    // global word wb[r] + acc(l) N and LDS word lb[r]
+    int fe[NB], wb[NB], lb[NB];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+        const int f = tid + nthr * r;
+        fe[r] = f / N;
+        const int c = f - fe[r] * N;
+        wb[r] = K0(fe[r]) * N + c;
+        lb[r] = fe[r] * NS + c;
+    }
+    // loads are issued unconditionally (word 0 stands in for an empty slot)
+    auto fetch = [&](int l, T(&dst)[NB]) {
+        const int len = lev_len(l), a = acc_of(l) * N;
+#pragma unroll
+        for (int r = 0; r < NB; ++r) dst[r] = ld_at(S, fe[r] < len ? (unsigned)(wb[r] + a) : 0u);
+    };
+    auto park = [&](int l, const T(&src)[NB]) {
+        const int len = lev_len(l);
+        T* dst = sch + (l & 1) * maxlen * NS;
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+            if (fe[r] < len) dst[lb[r]] = src[r];
+    };
+    auto flush = [&](int l) {
+        const int len = lev_len(l), a = acc_of(l) * N;
+        const T* src = pst + (l & 1) * maxlen * NS;
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+            if (fe[r] < len) st_at(psi, (unsigned)(wb[r] + a), src[lb[r]]);
+    };
+    // grid coordinates of this thread's own slot: i = ib + isg i0(l),
+    // j = jb + jsg (l - i0(l))
+    const int ib = sx ? slot : nx - 1 - slot, isg = sx ? 1 : -1;
+    const int jb = sy ? -slot : ny - 1 + slot, jsg = sy ? 1 : -1;
+    const int aout = sx ? NB - 1 : 0;
+    const int bout = sy ? NB - 1 : 0;
+    T pre[D][NB];
+#pragma unroll
+    for (int u = 0; u < D; ++u) fetch(u, pre[u]);
+    park(0, pre[0]);
+    lds_barrier();
+    for (int m0 = 0; m0 < nlev; m0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int m = m0 + u;
+            if (m >= nlev) break;
+            const int cur = m & 1, nxt = cur ^ 1;
+            const int len = lev_len(m);
+            fetch(m + D, pre[u]);  // this slot's level m was parked during level m - 1
+            if (chunk0 < len) {    // wave-uniform: the wave holds elements of this level
+                const bool act = slot < len;
+                const int i0 = lev_i0(m);
+                const int ci = act ? ib + isg * i0 : 0;
+                const int cj = act ? jb + jsg * (m - i0) : 0;
+                T sv[N], tx[NB], ty[NB];
+                const T* sp = sch + (cur * maxlen + rslot) * NS;
+#pragma unroll
+                for (int c = 0; c < N; ++c) sv[c] = sp[c];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    tx[c] = xtr[(cur * ny + cj) * TS + c];
+                    ty[c] = ytr[(cur * nx + ci) * TS + c];
+                }
+                T acc[NB];
+                auto apply = [&](int mat, T(&out)[NB]) {
+                    const long o = (long)mat * nd + d;
+                    const cptr<T> pm = uniform_rows(Pm + (o * N + ca) * N);
+                    const cptr<T> px = uniform_rows(Px + (o * N + ca) * NB);
+                    const cptr<T> py = uniform_rows(Py + (o * N + ca) * NB);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        T v = T(0);
+#pragma unroll
+                        for (int c = 0; c < N; ++c) v += pm[b * NB * N + c] * sv[c];
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) v += px[b * NB * NB + c] * tx[c];
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) v += py[b * NB * NB + c] * ty[c];
+                        out[b] = v;
+                    }
+                };
+                if constexpr (!MULTI) {
+                    apply(0, acc);
+                } else {
+                    // one pass per material present in the wave (spatially
+                    // coherent layouts: usually one, two at interfaces)
+                    const int cm = act ? (int)msh[cj * nx + ci] : -1;
+                    unsigned long long todo = __ballot(act);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) acc[b] = T(0);
+                    while (todo) {
+                        const int lead = __builtin_ctzll(todo);
+                        const int mm = __builtin_amdgcn_readfirstlane(__shfl(cm, lead));
+                        T tmp[NB];
+                        apply(mm, tmp);
+                        const bool mine = cm == mm;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) acc[b] = mine ? tmp[b] : acc[b];
+                        todo &= ~__ballot(mine);
+                    }
+                }
+                if (act) {
+                    T* pp = pst + (cur * maxlen + slot) * NS + ca;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) pp[NB * b] = acc[b];
+                    if (ca == aout) {
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) xtr[(nxt * ny + cj) * TS + b] = acc[b];
+                    }
+                    ytr[(nxt * nx + ci) * TS + ca] = acc[bout];
+                }
+            }
+            if (m > 0) flush(m - 1);
+            if (m + 1 < nlev) park(m + 1, pre[(u + 1) % D]);
+            lds_barrier();
+        }
+    }
+    flush(nlev - 1);
+}
+
 // Workgroups take tasks from a global counter (largest tasks first) until the
 // list is exhausted; tasks of problems that have converged are skipped.
-template <typename T, int NB, int MREG, int MAXT, int Bk>
+template <typename T, int NB, bool MULTI, int MAXT>
 __global__ __launch_bounds__(MAXT) void b_sweep_kernel(const CartSweepArgs* __restrict__ args,
                                                         const int2* __restrict__ tasks, int ntasks,
                                                         int* __restrict__ counter,
@@ -1172,25 +1418,28 @@ __global__ __launch_bounds__(MAXT) void b_sweep_kernel(const CartSweepArgs* __re
         if (t >= ntasks) break;
         const int2 tk = tasks[t];
         if (!active[tk.x]) continue;
-        sweep_cart_task<T, NB, MREG, Bk>(args[tk.x], tk.y, smem);
+        sweep_lane_task<T, NB, MULTI, LANE_PREFETCH>(args[tk.x], tk.y, smem);
         __syncthreads();
     }
 }
 
-size_t b_sweep_lds(bool fp64, int nb, int mreg, int nx, int ny, int nmat) {
-    const size_t t = fp64 ? 8 : 4;
-    const int N = nb * nb;
+int b_sweep_threads(int nb, int nx, int ny) {
     const int maxlen = nx < ny ? nx : ny;
-    size_t lds = t * (2 * (size_t)(nx + ny) * nb + 2 * (size_t)cart_block(nb) * maxlen * N);
-    if (mreg == 0) lds += t * (size_t)nmat * N * (N + 2 * nb);
-    if (mreg != 1) lds += (size_t)nx * ny;
+    return 64 * nb * ((maxlen + 63) / 64);
+}
+
+size_t b_sweep_lds(bool fp64, int nb, bool multi, int nx, int ny) {
+    const size_t t = fp64 ? 8 : 4;
+    const int maxlen = nx < ny ? nx : ny;
+    size_t lds = t * (2 * (size_t)(nx + ny) * lane_ts(nb) + 4 * (size_t)maxlen * lane_ns(nb));
+    if (multi) lds += (size_t)nx * ny;
     return lds;
 }
 
-template <typename T, int NB, int MREG, int MAXT>
+template <typename T, int NB, bool MULTI, int MAXT>
 static hipError_t b_sweep_t(int threads, size_t lds, int grid, const CartSweepArgs* args, const int2* tasks,
                             int ntasks, int* counter, const int* active, hipStream_t s) {
-    auto kfn = b_sweep_kernel<T, NB, MREG, MAXT, cart_block(NB)>;
+    auto kfn = b_sweep_kernel<T, NB, MULTI, MAXT>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1201,31 +1450,29 @@ static hipError_t b_sweep_t(int threads, size_t lds, int grid, const CartSweepAr
 }
 
 template <typename T, int NB>
-static hipError_t b_sweep_nb(int mreg, int threads, size_t lds, int grid, const CartSweepArgs* args,
+static hipError_t b_sweep_nb(bool multi, int threads, size_t lds, int grid, const CartSweepArgs* args,
                              const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s) {
-    constexpr bool f64 = sizeof(T) == 8;
-    // the caller sized the LDS for `mreg`; a register variant that would spill is refused
-    if (mreg == 1 && (threads > 512 || NB > (f64 ? 3 : 4))) return hipErrorInvalidValue;
-    if (threads <= 512) {
-        if (mreg == 1) return b_sweep_t<T, NB, 1, 512>(threads, lds, grid, args, tasks, ntasks, counter, active, s);
-        return b_sweep_t<T, NB, 0, 512>(threads, lds, grid, args, tasks, ntasks, counter, active, s);
-    }
-    if (f64 && NB >= 4) return hipErrorNotSupported;
-    return b_sweep_t<T, NB, 0, 1024>(threads, lds, grid, args, tasks, ntasks, counter, active, s);
+    if (threads <= 512)
+        return multi ? b_sweep_t<T, NB, true, 512>(threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                     : b_sweep_t<T, NB, false, 512>(threads, lds, grid, args, tasks, ntasks, counter, active, s);
+    return multi ? b_sweep_t<T, NB, true, 1024>(threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                 : b_sweep_t<T, NB, false, 1024>(threads, lds, grid, args, tasks, ntasks, counter, active, s);
 }
 
-hipError_t b_sweep(bool fp64, int nb, int mreg, int threads, size_t lds, int grid, const CartSweepArgs* args,
+hipError_t b_sweep(bool fp64, int nb, bool multi, int threads, size_t lds, int grid, const CartSweepArgs* args,
                    const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s) {
-    if (threads > 1024 || lds > 160 * 1024) return hipErrorNotSupported;
+    // the workgroup must be the NB waves of every 64-slot chunk of the longest
+    // anti-diagonal of every task (checked by the caller against each problem)
+    if (threads > 1024 || threads % (64 * nb) != 0 || lds > 160 * 1024) return hipErrorNotSupported;
     switch (nb) {
-        case 2: return fp64 ? b_sweep_nb<double, 2>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s)
-                            : b_sweep_nb<float, 2>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s);
-        case 3: return fp64 ? b_sweep_nb<double, 3>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s)
-                            : b_sweep_nb<float, 3>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s);
-        case 4: return fp64 ? b_sweep_nb<double, 4>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s)
-                            : b_sweep_nb<float, 4>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s);
-        case 5: return fp64 ? b_sweep_nb<double, 5>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s)
-                            : b_sweep_nb<float, 5>(mreg, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 2: return fp64 ? b_sweep_nb<double, 2>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_nb<float, 2>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 3: return fp64 ? b_sweep_nb<double, 3>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_nb<float, 3>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 4: return fp64 ? b_sweep_nb<double, 4>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_nb<float, 4>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 5: return fp64 ? b_sweep_nb<double, 5>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_nb<float, 5>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -2225,6 +2472,7 @@ __global__ __launch_bounds__(64) void mg_coarse_kernel(BatchLaunch B, MGLaunch M
     const int prob = blockIdx.x;
     if (cg_skip(B, prob)) return;
     const int l = M.lc[prob];
+    if (l >= M.ls) return;  // solved inside the workgroup V-cycle
     const MGLevelDev& L = M.lev[l];
     const int o = L.off[prob], nc = L.dims[2 * prob] * L.dims[2 * prob + 1];
     const double* Ci = M.cinv + M.coff[prob];
@@ -2233,6 +2481,126 @@ __global__ __launch_bounds__(64) void mg_coarse_kernel(BatchLaunch B, MGLaunch M
         double s = 0.0;
         for (int j = 0; j < nc; ++j) s += Ci[i * nc + j] * L.b[o + j];
         L.x[o + i] = s;
+    }
+}
+
+// Levels ls..lc of one problem's V-cycle in one workgroup, with the level
+// vectors in LDS (the stencils stay in global memory and are cached): the same
+// steps as the per-level launches, separated by barriers instead of launches.
+// Input b_ls (global), output the level-ls iterate in t_ls, or in x_ls when ls
+// is the problem's coarsest level.
+__global__ __launch_bounds__(1024) void mg_vcycle_lds_kernel(BatchLaunch B, MGLaunch M) {
+    extern __shared__ __align__(16) double vec[];
+    __shared__ int lo[MG_MAXLEV], lnx[MG_MAXLEV], lny[MG_MAXLEV];
+    const int prob = blockIdx.x;
+    if (cg_skip(B, prob)) return;
+    const int lc = M.lc[prob], ls = M.ls;
+    if (lc < ls) return;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) {
+        int o = 0;
+        for (int l = ls; l <= lc; ++l) {
+            lo[l] = o;
+            lnx[l] = M.lev[l].dims[2 * prob];
+            lny[l] = M.lev[l].dims[2 * prob + 1];
+            o += 3 * lnx[l] * lny[l];
+        }
+    }
+    __syncthreads();
+    // level l: x at vec + lo[l], t after it, b after t
+    auto X = [&](int l) { return vec + lo[l]; };
+    auto Tv = [&](int l) { return vec + lo[l] + lnx[l] * lny[l]; };
+    auto Bv = [&](int l) { return vec + lo[l] + 2 * lnx[l] * lny[l]; };
+    auto apply = [&](int l, const double* x, int ix, int iy) {
+        const MGLevelDev& L = M.lev[l];
+        const int nvx = lnx[l], nvy = lny[l];
+        const int v = L.off[prob] + iy * nvx + ix;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int jx = ix + k % 3 - 1, jy = iy + k / 3 - 1;
+            if (jx < 0 || jy < 0 || jx >= nvx || jy >= nvy) continue;
+            s += L.A[(long)k * L.nv + v] * x[jy * nvx + jx];
+        }
+        return s;
+    };
+    auto diag = [&](int l, int v) { return M.lev[l].A[4L * M.lev[l].nv + M.lev[l].off[prob] + v]; };
+    const double om = M.omega;
+    {
+        const double* bg = M.lev[ls].b + M.lev[ls].off[prob];
+        double* b = Bv(ls);
+        for (int v = tid; v < lnx[ls] * lny[ls]; v += nt) b[v] = bg[v];
+    }
+    __syncthreads();
+    for (int l = ls; l < lc; ++l) {
+        const int nvx = lnx[l], nv = lnx[l] * lny[l];
+        double *x = X(l), *t = Tv(l), *b = Bv(l);
+        for (int v = tid; v < nv; v += nt) x[v] = om * b[v] / diag(l, v);
+        __syncthreads();
+        for (int v = tid; v < nv; v += nt) t[v] = x[v] + om * (b[v] - apply(l, x, v % nvx, v / nvx)) / diag(l, v);
+        __syncthreads();
+        // residual of the smoothed iterate into x (free until the post-smoothing)
+        for (int v = tid; v < nv; v += nt) x[v] = b[v] - apply(l, t, v % nvx, v / nvx);
+        __syncthreads();
+        const int fnx = nvx, fny = lny[l], cnx = lnx[l + 1], cny = lny[l + 1];
+        double* bc = Bv(l + 1);
+        for (int c = tid; c < cnx * cny; c += nt) {
+            const int cx = c % cnx, cy = c / cnx;
+            const int bx = fnx <= 3 ? cx : (cx == cnx - 1 ? fnx - 1 : 2 * cx);
+            const int by = fny <= 3 ? cy : (cy == cny - 1 ? fny - 1 : 2 * cy);
+            double s = 0.0;
+            for (int fy = by - 2; fy <= by + 2; ++fy) {
+                if (fy < 0 || fy >= fny) continue;
+                const double wy = mg_weight(fy, fny, cy);
+                if (wy == 0.0) continue;
+                for (int fx = bx - 2; fx <= bx + 2; ++fx) {
+                    if (fx < 0 || fx >= fnx) continue;
+                    const double wx = mg_weight(fx, fnx, cx);
+                    if (wx == 0.0) continue;
+                    s += wx * wy * x[fy * fnx + fx];
+                }
+            }
+            bc[c] = s;
+        }
+        __syncthreads();
+    }
+    {
+        const int nc = lnx[lc] * lny[lc];
+        const double* Ci = M.cinv + M.coff[prob];
+        const double* b = Bv(lc);
+        if (tid < nc) {
+            double s = 0.0;
+            for (int j = 0; j < nc; ++j) s += Ci[tid * nc + j] * b[j];
+            X(lc)[tid] = s;
+        }
+    }
+    __syncthreads();
+    for (int l = lc - 1; l >= ls; --l) {
+        const int fnx = lnx[l], fny = lny[l], nv = fnx * fny, cnx = lnx[l + 1];
+        double *x = X(l), *t = Tv(l), *b = Bv(l);
+        const double* xc = l + 1 == lc ? X(l + 1) : Tv(l + 1);
+        for (int f = tid; f < nv; f += nt) {
+            int x0, x1, y0, y1;
+            double wx0, wx1, wy0, wy1;
+            mg_parents(f % fnx, fnx, x0, wx0, x1, wx1);
+            mg_parents(f / fnx, fny, y0, wy0, y1, wy1);
+            double s = wx0 * wy0 * xc[y0 * cnx + x0];
+            if (x1 >= 0) s += wx1 * wy0 * xc[y0 * cnx + x1];
+            if (y1 >= 0) s += wx0 * wy1 * xc[y1 * cnx + x0];
+            if (x1 >= 0 && y1 >= 0) s += wx1 * wy1 * xc[y1 * cnx + x1];
+            t[f] += s;
+        }
+        __syncthreads();
+        for (int v = tid; v < nv; v += nt) x[v] = t[v] + om * (b[v] - apply(l, t, v % fnx, v / fnx)) / diag(l, v);
+        __syncthreads();
+        for (int v = tid; v < nv; v += nt) t[v] = x[v] + om * (b[v] - apply(l, x, v % fnx, v / fnx)) / diag(l, v);
+        __syncthreads();
+    }
+    {
+        const MGLevelDev& L = M.lev[ls];
+        const double* src = ls == lc ? X(ls) : Tv(ls);
+        double* dst = (ls == lc ? L.x : L.t) + L.off[prob];
+        for (int v = tid; v < lnx[ls] * lny[ls]; v += nt) dst[v] = src[v];
     }
 }
 
@@ -2287,16 +2655,20 @@ __global__ __launch_bounds__(BT) void mg_finish_kernel(BatchLaunch B, MGLaunch M
 
 hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStream_t s) {
     auto grid = [](int n) { return dim3((unsigned)((n + BT - 1) / BT)); };
+    // per-level launches above level ls, one workgroup per problem below
+    const int top = M.ls < M.nlev - 1 ? M.ls : M.nlev - 1;
     hipLaunchKernelGGL(mg_corner_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M.corner);
     hipLaunchKernelGGL(mg_restrict0_kernel, grid(M.lev[0].nv), dim3(BT), 0, s, B, M, (const double*)M.corner);
-    for (int l = 0; l + 1 < M.nlev; ++l) {
+    for (int l = 0; l < top; ++l) {
         const MGLevelDev& L = M.lev[l];
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 1, (const double*)L.x, L.x);
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.x, L.t);
         hipLaunchKernelGGL(mg_restrict_kernel, grid(M.lev[l + 1].nv), dim3(BT), 0, s, B, M, l, (const double*)L.t);
     }
+    if (M.ls < M.nlev)
+        hipLaunchKernelGGL(mg_vcycle_lds_kernel, dim3(B.nprob), dim3(1024), M.lds, s, B, M);
     hipLaunchKernelGGL(mg_coarse_kernel, dim3(B.nprob), dim3(64), 0, s, B, M);
-    for (int l = M.nlev - 2; l >= 0; --l) {
+    for (int l = top - 1; l >= 0; --l) {
         const MGLevelDev& L = M.lev[l];
         hipLaunchKernelGGL(mg_prolong_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, L.t);
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.t, L.x);
@@ -2304,6 +2676,12 @@ hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStr
     }
     hipLaunchKernelGGL(mg_finish_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M, init ? 1 : 0);
     return hipGetLastError();
+}
+
+hipError_t mg_prepare(size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(mg_vcycle_lds_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 // ---- Anderson mixing of the outer fixed point ------------------------------------

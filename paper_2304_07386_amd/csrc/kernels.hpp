@@ -167,15 +167,23 @@ struct MGLaunch {
     const double* cinv;
     double omega;               // Jacobi damping
     double* corner;             // [4][batch elements] corner sums of the residual
+    int ls;                     // levels >= ls run in one workgroup per problem (nlev: none)
+    size_t lds;                 // LDS bytes of that workgroup
 };
+// allows the LDS size of the workgroup V-cycle kernel
+hipError_t mg_prepare(size_t lds);
 // z += P0 V(P0^T r) after the block-Jacobi z = D^-1 r; the partial sums of
 // r.z go to part[init ? 0 : 1][block], and with init p = z
 hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStream_t s);
 
 hipError_t b_source(bool fp64, const BatchLaunch& B, bool delta, hipStream_t s);
-hipError_t b_sweep(bool fp64, int nb, int mreg, int threads, size_t lds, int grid, const CartSweepArgs* args,
+// Persistent batched sweep over (problem, direction) tasks.  `threads` is
+// b_sweep_threads of the largest problem of the task list, `lds` the largest
+// b_sweep_lds; `multi` selects the variant for problems with several materials.
+hipError_t b_sweep(bool fp64, int nb, bool multi, int threads, size_t lds, int grid, const CartSweepArgs* args,
                    const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s);
-size_t b_sweep_lds(bool fp64, int nb, int mreg, int nx, int ny, int nmat);
+int b_sweep_threads(int nb, int nx, int ny);
+size_t b_sweep_lds(bool fp64, int nb, bool multi, int nx, int ny);
 hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool first, hipStream_t s);
 hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s);
 hipError_t b_copy_x(const BatchLaunch& B, hipStream_t s);               // x = varphi

@@ -9,6 +9,7 @@ namespace smm {
 struct Problem;
 
 constexpr int MG_MAX_COARSE = 16;  // unknowns of the dense coarsest solve
+constexpr size_t MG_LDS_CAP = 150 * 1024;  // LDS of the one-workgroup V-cycle on the coarse levels
 
 struct MGLevelHost {
     int nvx = 0, nvy = 0;
