@@ -86,11 +86,14 @@ def traffic_for(kernel: str):
     return ent["bytes_per_launch"]
 
 
-def roofline(kernel: str, bytes_per_launch: float, ms: float):
+def roofline(kernel: str, what: str, bytes_per_launch: float, ms: float):
+    """`kernel` is the name prefix of the launches timed together as one
+    operation (`what`): one sweep, or one q = A p, runs one launch per order
+    present in the batch."""
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
     tr = traffic_for(kernel)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kernel,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kernel, "operation": what,
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": ms}
 
 
@@ -204,10 +207,12 @@ def main():
     # sweep: psi written once in FP32 (4 B/unit) + the FP32 source read once per
     # element and direction set (4/N_dir B/unit, N_dir per problem)
     sweep_bytes = float(sum(p.n_elem * p.n_node * (4.0 * p.n_dir + 4.0) for p in probs))
-    rl_sweep = roofline("b_sweep_kernel", sweep_bytes, sweep_ms)
+    rl_sweep = roofline("b_sweep_kernel", "one batched sweep (the per-order launches b_sweep_kernel<T, NB, ...>)",
+                        sweep_bytes, sweep_ms)
     spmv_ms = L.smm_batch_time_kernel(batch, L.SMM_KERNEL_CG_SPMV, 50)
     # q = A p: p read once and q written once, FP64 (16 B/DOF)
-    rl_spmv = roofline("b_cg_k1", 16.0 * dofs, spmv_ms)
+    rl_spmv = roofline("b_cg_k1", "one q = A p over the batch (the per-order launches b_cg_k1<NB>)",
+                       16.0 * dofs, spmv_ms)
     log(f"sweep {sweep_ms:.3f} ms -> {units / sweep_ms / 1e-3:.3e} units/s, {rl_sweep['achieved']:.0f} GB/s; "
         f"PCG q=Ap {spmv_ms * 1e3:.1f} us, {rl_spmv['achieved']:.0f} GB/s")
     dominant = rl_spmv if phase["pcg"] > phase["source+sweep"] else rl_sweep

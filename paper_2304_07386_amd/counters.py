@@ -87,13 +87,17 @@ def parse(dir_fetch, dir_write, out):
         if not big:
             raise RuntimeError("no calibration copy found")
         scale = (COPY_BYTES / 1024.0) / big           # KiB of the copy / KiB the counter read
-        spmv = [v for n, v in disp if "b_cg_k1" in n][-SPMV_REPS:]
+        # one q = A p is one launch per order present (b_cg_k1<NB>), or the
+        # per-node kernel b_cg_k1n: the last SPMV_REPS rounds of them
+        k1 = [(n, v) for n, v in disp if "b_cg_k1" in n]
+        nvar = len({n for n, v in k1})
+        spmv = [v for n, v in k1[-SPMV_REPS * nvar:]]
         sweeps = [v for n, v in disp if "b_sweep_kernel" in n]
         # the timed sweeps: the last SWEEP_REPS * (orders) dispatches
         norders = len({n for n, v in disp if "b_sweep_kernel" in n})
         sw = sweeps[-SWEEP_REPS * norders:]
         res[which] = {"scale": scale, "copy_kib": big,
-                      "b_cg_k1": 1024.0 * scale * sum(spmv) / len(spmv),
+                      "b_cg_k1": 1024.0 * scale * sum(spmv) / SPMV_REPS,
                       "b_sweep_kernel": 1024.0 * scale * sum(sw) / SWEEP_REPS}
     src = os.path.join(HERE, "csrc", "kernels.hip")
     with open(src, "rb") as f:

@@ -4,13 +4,14 @@
 //  * the sweep runs as one persistent launch per order p and workgroup size
 //    (64-slot chunks of the longest anti-diagonal), whose workgroups take
 //    (problem, direction) tasks from a queue ordered by decreasing cost; the
-//    launches run concurrently on forked streams;
+//    launches run one after the other or concurrently on forked streams;
 //  * moments, closures, right-hand side, block-Jacobi PCG and the outer
 //    residual run as single launches over all problems, with per-problem
 //    reductions and convergence flags (problems that have converged drop out
 //    of every later launch);
-//  * the grid of each persistent sweep launch is chosen by timing the
-//    candidates on the batch itself (cached per launch shape).
+//  * the grid of each persistent sweep launch, and whether the launches
+//    share the GPU concurrently, are chosen by timing the candidates on the
+//    batch itself (grids cached per launch shape).
 // A single problem on the typed path is a batch of one.
 #include <algorithm>
 #include <chrono>
@@ -45,6 +46,8 @@ struct PerProb {
     double* omega;
     double *Pm64, *Px64, *Py64, *bx64, *by64;
     float *Pm32, *Px32, *Py32, *bx32, *by32;
+    double* tab64;                   // operator rows in the batched sweep's layout
+    float* tab32;
     uint8_t* mat;
     double* vdiff;
     float* feat0;
@@ -116,6 +119,7 @@ struct smm_batch {
     double* d_tol = nullptr;       // per-problem PCG tolerance (inner_adapt)
     // PCG type groups (see BatchLaunch)
     int ngroups = 0;
+    int g_nb0[7] = {0, 0, 0, 0, 0, 0, 0};  // group ranges per nb (see BatchLaunch)
     std::vector<int> h_gprob, h_gcount, h_gty, h_gelem;
     int *d_gprob = nullptr, *d_gcount = nullptr, *d_gty = nullptr, *d_gelem = nullptr;
     double* d_gpart = nullptr;
@@ -136,6 +140,7 @@ struct smm_batch {
     double* d_mg_cinv = nullptr;
     std::vector<Group> groups;
     int* d_sweep_counters = nullptr;  // [groups] task counters of the persistent sweeps
+    int sweep_streams[2] = {0, 0};    // per precision: streams the groups run on (0: not tuned yet)
     CartSweepArgs* d_args[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -183,8 +188,10 @@ BatchLaunch launch_desc(smm_batch* B) {
     L.g_ty = B->d_gty;
     L.g_elem = B->d_gelem;
     L.gpart = B->d_gpart;
+    for (int k = 0; k < 7; ++k) L.g_nb0[k] = B->g_nb0[k];
     L.grouped = B->grouped ? 1 : 0;
     L.mg = B->use_mg ? 1 : 0;
+    L.mg_corner = B->use_mg ? B->d_mg_corner : nullptr;
     return L;
 }
 
@@ -288,6 +295,9 @@ int batch_build(smm_batch* B) {
         pool.req(&q.Pm32, sizeof(float) * P.Pm.size());
         pool.req(&q.Px32, sizeof(float) * P.Px.size());
         pool.req(&q.Py32, sizeof(float) * P.Py.size());
+        const size_t ntab = (size_t)P.nmat * P.nd * P.n * lane_rw(P.nb);
+        pool.req(&q.tab64, sizeof(double) * ntab);
+        pool.req(&q.tab32, sizeof(float) * ntab);
         pool.req(&q.bx64, sizeof(double) * (size_t)P.nd * P.ny * P.nb);
         pool.req(&q.by64, sizeof(double) * (size_t)P.nd * P.nx * P.nb);
         pool.req(&q.bx32, sizeof(float) * (size_t)P.nd * P.ny * P.nb);
@@ -317,7 +327,13 @@ int batch_build(smm_batch* B) {
     B->h_gcount.clear();
     B->h_gty.clear();
     B->h_gelem.clear();
-    for (int b = 0; b < np; ++b) {
+    // problems in order of nb, so the groups of one order are contiguous
+    std::vector<int> by_nb(np);
+    for (int b = 0; b < np; ++b) by_nb[b] = b;
+    std::stable_sort(by_nb.begin(), by_nb.end(),
+                     [&](int a, int b) { return B->probs[a]->P.nb < B->probs[b]->P.nb; });
+    for (int k = 0; k < 7; ++k) B->g_nb0[k] = 0;
+    for (int b : by_nb) {
         const Problem& P = B->probs[b]->P;
         std::map<std::array<int, 5>, std::vector<int>> tup;
         for (int K = 0; K < P.ne; ++K)
@@ -334,6 +350,7 @@ int batch_build(smm_batch* B) {
             }
         }
         B->hP[b].ng = (int)B->h_gprob.size() - B->hP[b].g0;
+        for (int k = P.nb + 1; k < 7; ++k) B->g_nb0[k] = (int)B->h_gprob.size();
     }
     // two-level preconditioner hierarchies (host), flattened per level
     // (a problem it cannot be built for leaves the batch without it: solves
@@ -521,6 +538,22 @@ int batch_build(smm_batch* B) {
         }
         const std::vector<float> W32 = f32(W), Pm32 = f32(P.Pm), Px32 = f32(P.Px), Py32 = f32(P.Py), bx32 = f32(bx),
                                  by32 = f32(by);
+        // sweep table: per (material, direction) and node column ca the rows
+        // ca + nb b, each [Pm row | Px row | Py row] zero-padded to lane_rw
+        const int rw = lane_rw(P.nb);
+        std::vector<double> tab((size_t)P.nmat * P.nd * P.n * rw, 0.0);
+        for (int o = 0; o < P.nmat * P.nd; ++o)
+            for (int ca = 0; ca < P.nb; ++ca)
+                for (int bb = 0; bb < P.nb; ++bb) {
+                    const int r = ca + P.nb * bb;
+                    double* row = &tab[(((size_t)o * P.nb + ca) * P.nb + bb) * rw];
+                    for (int cc = 0; cc < P.n; ++cc) row[cc] = P.Pm[((size_t)o * P.n + r) * P.n + cc];
+                    for (int cc = 0; cc < P.nb; ++cc) {
+                        row[P.n + cc] = P.Px[((size_t)o * P.n + r) * P.nb + cc];
+                        row[P.n + P.nb + cc] = P.Py[((size_t)o * P.n + r) * P.nb + cc];
+                    }
+                }
+        const std::vector<float> tab32 = f32(tab);
         const U ups[] = {
             {q.bfix, P.t_bfix.data(), sizeof(double) * L},
             {q.qsrc, P.q.data(), sizeof(double) * L},
@@ -546,6 +579,8 @@ int batch_build(smm_batch* B) {
             {q.Pm32, Pm32.data(), sizeof(float) * Pm32.size()},
             {q.Px32, Px32.data(), sizeof(float) * Px32.size()},
             {q.Py32, Py32.data(), sizeof(float) * Py32.size()},
+            {q.tab64, tab.data(), sizeof(double) * tab.size()},
+            {q.tab32, tab32.data(), sizeof(float) * tab32.size()},
             {q.bx64, bx.data(), sizeof(double) * bx.size()},
             {q.by64, by.data(), sizeof(double) * by.size()},
             {q.bx32, bx32.data(), sizeof(float) * bx32.size()},
@@ -579,6 +614,7 @@ int batch_build(smm_batch* B) {
                 A.Pm = f ? (const void*)q.Pm64 : (const void*)q.Pm32;
                 A.Px = f ? (const void*)q.Px64 : (const void*)q.Px32;
                 A.Py = f ? (const void*)q.Py64 : (const void*)q.Py32;
+                A.tab = f ? (const void*)q.tab64 : (const void*)q.tab32;
                 A.mat = q.mat;
                 A.omega = q.omega;
                 const bool inflow = g == 1 && P.inflow_layout != SMM_INFLOW_VACUUM;
@@ -692,21 +728,25 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
     smm_ctx* c = B->ctx;
     const int f = fp64 ? 1 : 0;
     const int ng = (int)B->groups.size();
+    // groups one after the other on the caller's stream, or forked over
+    // nstr side streams (chosen by the autotuner)
+    const int nstr = std::min(B->sweep_streams[f] > 0 ? B->sweep_streams[f] : 1, 4);
+    const bool fork = ng > 1 && nstr > 1;
     HIPCHK(c, zero_ints(B->d_sweep_counters, ng, c->stream));
-    if (ng > 1) {
+    if (fork) {
         HIPCHK(c, hipEventRecord(B->ev_fork, c->stream));
-        for (int k = 0; k < ng; ++k) HIPCHK(c, hipStreamWaitEvent(B->side[k % 4], B->ev_fork, 0));
+        for (int k = 0; k < std::min(ng, nstr); ++k) HIPCHK(c, hipStreamWaitEvent(B->side[k], B->ev_fork, 0));
     }
     for (int k = 0; k < ng; ++k) {
         Group& G = B->groups[k];
-        hipStream_t s = ng > 1 ? B->side[k % 4] : c->stream;
+        hipStream_t s = fork ? B->side[k % nstr] : c->stream;
         int grid = G.grid[f] > 0 ? G.grid[f] : std::min<int>((int)G.tasks.size(), 2 * B->ncu);
         hipError_t e = b_sweep(fp64, G.nb, G.multi, G.threads, G.lds[f], grid, B->d_args[f][inflow ? 1 : 0],
                                G.d_tasks, (int)G.tasks.size(), G.d_counter, B->d_active, s);
         if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("batched sweep: ") + hipGetErrorString(e));
     }
-    if (ng > 1)
-        for (int k = 0; k < std::min(ng, 4); ++k) {
+    if (fork)
+        for (int k = 0; k < std::min(ng, nstr); ++k) {
             HIPCHK(c, hipEventRecord(B->ev_join[k], B->side[k]));
             HIPCHK(c, hipStreamWaitEvent(c->stream, B->ev_join[k], 0));
         }
@@ -763,6 +803,33 @@ int batch_autotune(smm_batch* B, bool fp64) {
                                                  std::to_string(G.nb - 1) + " (workgroup or LDS limits)");
         G.grid[f] = best;
         tune_cache()[key] = best;
+    }
+    // the groups one after the other, or concurrently on side streams
+    if (B->sweep_streams[f] == 0) {
+        B->sweep_streams[f] = 1;
+        if (B->groups.size() > 1) {
+            float best_ms = 1e30f;
+            int best = 1;
+            for (int ns : {1, 2, 4}) {
+                B->sweep_streams[f] = ns;
+                float ms_tot = 0;
+                for (int rep = 0; rep < 3; ++rep) {
+                    HIPCHK(c, hipEventRecord(e0, c->stream));
+                    int rc = batch_sweep(B, fp64, true);
+                    if (rc) return rc;
+                    HIPCHK(c, hipEventRecord(e1, c->stream));
+                    HIPCHK(c, hipEventSynchronize(e1));
+                    float ms = 0;
+                    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                    if (rep > 0) ms_tot += ms;
+                }
+                if (ms_tot < best_ms) {
+                    best_ms = ms_tot;
+                    best = ns;
+                }
+            }
+            B->sweep_streams[f] = best;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

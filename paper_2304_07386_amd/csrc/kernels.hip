@@ -1214,6 +1214,16 @@ __device__ __forceinline__ void st_at(gptr<T> p, unsigned w, T v) {
     *(gptr<T>)((char __attribute__((address_space(1)))*)p + w * (unsigned)sizeof(T)) = v;
 }
 
+// Wave-uniform pointer into the constant address space, without the barrier:
+// loads through it may be hoisted and kept in SGPRs.
+template <typename T>
+__device__ __forceinline__ cptr<T> uniform_ptr(const T* p) {
+    const unsigned long v = (unsigned long)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return (cptr<T>)(((unsigned long)hi << 32) | lo);
+}
+
 __host__ __device__ constexpr int lane_ns(int nb) { return (nb * nb) | 1; }  // LDS row stride of a block
 __host__ __device__ constexpr int lane_ts(int nb) { return nb | 1; }         // LDS row stride of a trace
 constexpr int LANE_PREFETCH = 3;  // levels between a source load and its use
@@ -1244,9 +1254,11 @@ __device__ __forceinline__ void sweep_lane_task(const CartSweepArgs& a, const in
     const bool sx = ox > 0.0, sy = oy > 0.0;
     const auto S = as_global(reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0));
     const auto psi = as_global(reinterpret_cast<T*>(a.psi) + (long)d * (a.psi_ld > 0 ? a.psi_ld : ne * N));
-    const T* Pm = reinterpret_cast<const T*>(a.Pm);
-    const T* Px = reinterpret_cast<const T*>(a.Px);
-    const T* Py = reinterpret_cast<const T*>(a.Py);
+    // operator rows: one scalar-loaded block per wave; small tables (one
+    // material, few rows) stay in SGPRs for the whole task
+    constexpr int RW = lane_rw(NB);
+    constexpr bool HOIST = !MULTI && NB * RW * (int)sizeof(T) <= 64 * 4;
+    const T* tab = reinterpret_cast<const T*>(a.tab);
     if constexpr (MULTI) {
         const auto mat = as_global(a.mat);
         for (long t = tid; t < ne; t += nthr) msh[t] = mat[t];
@@ -1346,19 +1358,18 @@ __device__ __forceinline__ void sweep_lane_task(const CartSweepArgs& a, const in
                 }
                 T acc[NB];
                 auto apply = [&](int mat, T(&out)[NB]) {
-                    const long o = (long)mat * nd + d;
-                    const cptr<T> pm = uniform_rows(Pm + (o * N + ca) * N);
-                    const cptr<T> px = uniform_rows(Px + (o * N + ca) * NB);
-                    const cptr<T> py = uniform_rows(Py + (o * N + ca) * NB);
+                    // this wave's NB rows, contiguous: row b at b RW
+                    const T* rows = tab + (((long)mat * nd + d) * NB + ca) * NB * RW;
+                    const cptr<T> tr = HOIST ? uniform_ptr(rows) : uniform_rows(rows);
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         T v = T(0);
 #pragma unroll
-                        for (int c = 0; c < N; ++c) v += pm[b * NB * N + c] * sv[c];
+                        for (int c = 0; c < N; ++c) v += tr[b * RW + c] * sv[c];
 #pragma unroll
-                        for (int c = 0; c < NB; ++c) v += px[b * NB * NB + c] * tx[c];
+                        for (int c = 0; c < NB; ++c) v += tr[b * RW + N + c] * tx[c];
 #pragma unroll
-                        for (int c = 0; c < NB; ++c) v += py[b * NB * NB + c] * ty[c];
+                        for (int c = 0; c < NB; ++c) v += tr[b * RW + N + NB + c] * ty[c];
                         out[b] = v;
                     }
                 };
@@ -1832,7 +1843,6 @@ __device__ __forceinline__ void block_mv(const double* Ag, const double* __restr
 // of the group, row stride N | 1 doubles (odd, so the 64 lanes' rows fall in
 // distinct banks).  Global vectors move in and out of it with element-major
 // flat indices t = e N + j, so those accesses are coalesced.
-constexpr int GSLICE = 64 * 25;
 
 __device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
@@ -1846,67 +1856,216 @@ __device__ __forceinline__ void k1_group(const BatchLaunch& B, const BProb& P, i
     double y[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) y[i] = 0.0;
-    for (int f = 0; f < 5; ++f) {
-        const int t = ty[f];
-        if (f > 0 && t < 0) continue;  // wave-uniform: boundary face of every element of the group
-        // flat index u = e N + j over the group's vectors: lane-consecutive, so
-        // the global reads are coalesced; all N rounds are issued before use
-        double v[N];
+    // flat index u = e N + j over the group's vectors of face f (0: the
+    // elements themselves, 1-4: their neighbours): lane-consecutive, so the
+    // global reads are coalesced
+    const auto pg = as_global((const double*)P.p);
+    auto load_face = [&](int f, double(&v)[N]) {
 #pragma unroll
         for (int it = 0; it < N; ++it) {
             const int u = lane + 64 * it;
             const int e = u / N < 64 ? u / N : 63;
             const int K = __shfl(myK, e);
-            const long src = f == 0 ? K : nbr_of(P, K, f - 1);
-            v[it] = u < tot ? P.p[src * N + (u - (u / N) * N)] : 0.0;
+            const int src = f == 0 ? K : nbr_of(P, K, f - 1);
+            v[it] = ld_at(pg, u < tot ? (unsigned)(src * N + (u - (u / N) * N)) : 0u);
         }
+    };
+    // faces with a neighbour type (wave-uniform: a boundary face of one
+    // element of the group is a boundary face of all of them)
+    auto next_face = [&](int f) {
+        ++f;
+        while (f < 5 && ty[f] < 0) ++f;
+        return f;
+    };
+    double v[N];
+    load_face(0, v);
+    for (int f = 0; f < 5;) {
+        const int fn = next_face(f);
+        // the next face's vectors are loaded while this face is multiplied
+        double vn[N];
+        if (fn < 5) load_face(fn, vn);
 #pragma unroll
         for (int it = 0; it < N; ++it) {
             const int u = lane + 64 * it;
             if (u < tot) xs[(u / N) * S + (u - (u / N) * N)] = v[it];
         }
         lds_wave_sync();
-        block_mv<N>((f == 0 ? P.ip_self : P.ip_nbr) + (long)t * N * N, xs + lane * S, y);
+        block_mv<N>((f == 0 ? P.ip_self : P.ip_nbr) + (long)ty[f] * N * N, xs + lane * S, y);
         lds_wave_sync();
+        if (fn < 5)
+#pragma unroll
+            for (int it = 0; it < N; ++it) v[it] = vn[it];
+        f = fn;
     }
     if (lane < cnt)
 #pragma unroll
         for (int i = 0; i < N; ++i) xs[lane * S + i] = y[i];
     lds_wave_sync();
     double pq = 0.0;
+    const auto qg = as_global(P.q);
 #pragma unroll
     for (int it = 0; it < N; ++it) {
         const int u = lane + 64 * it;
         const int e = u / N < 64 ? u / N : 63;
         const int K = __shfl(myK, e);
         if (u < tot) {
-            const long o = (long)K * N + (u - (u / N) * N);
+            const unsigned o = (unsigned)(K * N + (u - (u / N) * N));
             const double qv = xs[(u / N) * S + (u - (u / N) * N)];
-            P.q[o] = qv;
-            pq += P.p[o] * qv;
+            st_at(qg, o, qv);
+            pq += ld_at(pg, o) * qv;
         }
     }
     pq = wave_sum(pq);
     if (lane == 0) B.gpart[g] = pq;
 }
 
-// q = A p and the group's partial sum of p.q
-__global__ __launch_bounds__(256) void b_cg_k1(BatchLaunch B) {
-    __shared__ double lds[4 * GSLICE];
+// q = A p of one group on the FP64 matrix cores.  Per face the group's block
+// product Y (N x 64) += A_f (N x N) X_f (N x 64) is a dense contraction, done
+// in 16 x 16 x 4 tiles (rows padded to MB 16, the contraction to KS 4 with
+// zeros): A fragments come from global memory (the typed blocks are shared by
+// all groups, so they are cache hits) and are loaded before the next face's
+// vectors, so waiting for them never waits for the prefetch; X fragments come
+// from the face's vectors staged in LDS.  Tile layouts (v_mfma_f64_16x16x4):
+// lane (i, k) = (lane % 16, lane / 16) holds A[i][k] and B[k][i]; element r
+// of the result holds D[4 r + k][i].
+template <int NB>
+__device__ __forceinline__ void k1_group_mfma(const BatchLaunch& B, const BProb& P, int g, int cnt, double* xs) {
+    constexpr int N = NB * NB, S = N | 1;
+    constexpr int MB = (N + 15) / 16, KS = (N + 3) / 4;
+    const int lane = threadIdx.x & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int* ty = B.g_ty + g * 5;
+    const int myK = B.g_elem[g * 64 + lane];  // every slot holds a valid element
+    const int tot = cnt * N;
+    const auto pg = as_global((const double*)P.p);
+    // the flat indices are recomputed where used (an opaque copy of the lane
+    // index keeps the compiler from hoisting N of them per use out of the face
+    // loop, which would pin ~4 N registers)
+    auto lane_now = [&]() {
+        int l = lane;
+        asm volatile("" : "+v"(l));
+        return l;
+    };
+    auto load_face = [&](int f, double(&v)[N]) {
+        const int ln = lane_now();
+#pragma unroll
+        for (int it = 0; it < N; ++it) {
+            const int u = ln + 64 * it;
+            const int e = u / N < 64 ? u / N : 63;
+            const int K = __shfl(myK, e);
+            const int src = f == 0 ? K : nbr_of(P, K, f - 1);
+            v[it] = ld_at(pg, u < tot ? (unsigned)(src * N + (u - (u / N) * N)) : 0u);
+        }
+    };
+    auto next_face = [&](int f) {
+        ++f;
+        while (f < 5 && ty[f] < 0) ++f;
+        return f;
+    };
+    v4d acc[MB][4];
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+    // block entries of face f (column-major: (i, k) at k N + i) as A tiles
+    auto load_blocks = [&](int f, double(&a)[KS][MB]) {
+        const auto A = as_global((f == 0 ? P.ip_self : P.ip_nbr) + (long)ty[f] * N * N);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb) {
+                const int k = 4 * s + kq, r = 16 * rb + i16;
+                const bool in = k < N && r < N;
+                a[s][rb] = ld_at(A, in ? (unsigned)(k * N + r) : 0u);
+                if (!in) a[s][rb] = 0.0;
+            }
+    };
+    double v[N];
+    double a[KS][MB];
+    load_blocks(0, a);
+    load_face(0, v);
+    for (int f = 0; f < 5;) {
+        const int fn = next_face(f);
+        {
+            const int ln = lane_now();
+#pragma unroll
+            for (int it = 0; it < N; ++it) {
+                const int u = ln + 64 * it;
+                if (u < tot) xs[(u / N) * S + (u - (u / N) * N)] = v[it];
+            }
+        }
+        lds_wave_sync();
+        // the next face's blocks and vectors are loaded while this face's
+        // tiles run (unconditionally: after the last face, face 0 again,
+        // unused), so the values just staged are dead and their registers
+        // are reused
+        double an[KS][MB];
+        load_blocks(fn < 5 ? fn : 0, an);
+        load_face(fn < 5 ? fn : 0, v);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + kq;
+            double bf[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bf[cb] = k < N ? xs[(16 * cb + i16) * S + k] : 0.0;
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][rb], bf[cb], acc[rb][cb], 0, 0, 0);
+        }
+        lds_wave_sync();
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb) a[s][rb] = an[s][rb];
+        f = fn;
+    }
+    // result tiles to LDS (element e = 16 cb + i16, row 16 rb + 4 r + kq)
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rb + 4 * r + kq, e = 16 * cb + i16;
+                if (row < N && e < cnt) xs[e * S + row] = acc[rb][cb][r];
+            }
+    lds_wave_sync();
+    double pq = 0.0;
+    const auto qg = as_global(P.q);
+#pragma unroll
+    for (int it = 0; it < N; ++it) {
+        const int u = lane + 64 * it;
+        const int e = u / N < 64 ? u / N : 63;
+        const int K = __shfl(myK, e);
+        if (u < tot) {
+            const unsigned o = (unsigned)(K * N + (u - (u / N) * N));
+            const double qv = xs[(u / N) * S + (u - (u / N) * N)];
+            st_at(qg, o, qv);
+            pq += ld_at(pg, o) * qv;
+        }
+    }
+    pq = wave_sum(pq);
+    if (lane == 0) B.gpart[g] = pq;
+}
+
+// One launch per order: the groups of order NB are [g_nb0[NB], g_nb0[NB + 1]),
+// so each order gets its own register and LDS footprint.
+template <int NB>
+__global__ __launch_bounds__(256, 2) void b_cg_k1(BatchLaunch B) {
+    constexpr int SL = 64 * (NB * NB | 1);
+    __shared__ double lds[4 * SL];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = blockIdx.x * 4 + w;
-    if (g >= B.ngroups) return;  // wave-uniform; no workgroup barriers below
+    const int g = B.g_nb0[NB] + blockIdx.x * 4 + w;
+    if (g >= B.g_nb0[NB + 1]) return;  // wave-uniform; no workgroup barriers below
     const int prob = B.g_prob[g];
     if (cg_skip(B, prob)) return;
     const BProb& P = B.P[prob];
-    const int cnt = B.g_count[g];
-    double* xs = lds + w * GSLICE;
-    switch (P.nb) {
-        case 2: k1_group<2>(B, P, g, cnt, xs); break;
-        case 3: k1_group<3>(B, P, g, cnt, xs); break;
-        case 4: k1_group<4>(B, P, g, cnt, xs); break;
-        default: k1_group<5>(B, P, g, cnt, xs); break;
-    }
+    if constexpr (NB >= 3)
+        k1_group_mfma<NB>(B, P, g, B.g_count[g], lds + w * SL);
+    else
+        k1_group<NB>(B, P, g, B.g_count[g], lds + w * SL);
 }
 
 // ---- per-node PCG kernels (element blocks of BT threads; used when the type
@@ -2009,6 +2168,18 @@ __global__ __launch_bounds__(BT) void b_cg_k2n(BatchLaunch B) {
         rr = rnew * rnew;
     }
     __syncthreads();
+    if (B.mg_corner) {
+        // corner sums of r for the coarse correction (thread i < 4 of an element)
+        const int le = t / n, i = t - le * n, K = K0 + le;
+        if (i < 4 && le < epb && K < P.ne) {
+            double c = 0.0;
+            for (int j = 0; j < n; ++j) {
+                const double xa = P.gll[j % P.nb], yb = P.gll[j / P.nb];
+                c += ((i & 1) ? xa : 1.0 - xa) * ((i & 2) ? yb : 1.0 - yb) * rl[le * n + j];
+            }
+            B.mg_corner[4L * (P.e_off + K) + i] = c;
+        }
+    }
     double rz = 0;
     const int pr = t / n, i = t - pr * n;
     const int la = 2 * pr, lb = la + 1, Ka = K0 + la, Kb = K0 + lb;
@@ -2089,6 +2260,26 @@ __device__ __forceinline__ void k2_group(const BatchLaunch& B, const BProb& P, i
     if (lane < cnt)
 #pragma unroll
         for (int i = 0; i < N; ++i) rz += xs[lane * S + i] * z[i];
+    if (B.mg_corner && lane < cnt) {
+        // corner sums of r for the coarse correction: sum over the nodes of
+        // hat_corner(node) r(node), corner = cx + 2 cy
+        double c[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const double yb = P.gll[b];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                const double xa = P.gll[a], r = xs[lane * S + a + NB * b];
+                c[0] += (1.0 - xa) * (1.0 - yb) * r;
+                c[1] += xa * (1.0 - yb) * r;
+                c[2] += (1.0 - xa) * yb * r;
+                c[3] += xa * yb * r;
+            }
+        }
+        double* co = B.mg_corner + 4L * (P.e_off + myK);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) co[k] = c[k];
+    }
     lds_wave_sync();
     if (lane < cnt)
 #pragma unroll
@@ -2111,30 +2302,65 @@ __device__ __forceinline__ void k2_group(const BatchLaunch& B, const BProb& P, i
 
 // x += alpha p, r -= alpha q, z = D^-1 r (block-Jacobi) and the group's partial
 // sums of r.z and r.r
+template <int NB>
 __global__ __launch_bounds__(256) void b_cg_k2(BatchLaunch B) {
-    __shared__ double lds[4 * GSLICE];
+    constexpr int SL = 64 * (NB * NB | 1);
+    __shared__ double lds[4 * SL];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = blockIdx.x * 4 + w;
-    if (g >= B.ngroups) return;
+    const int g = B.g_nb0[NB] + blockIdx.x * 4 + w;
+    if (g >= B.g_nb0[NB + 1]) return;
     const int prob = B.g_prob[g];
     if (cg_skip(B, prob)) return;
     const BProb& P = B.P[prob];
-    const int cnt = B.g_count[g];
-    double* xs = lds + w * GSLICE;
-    switch (P.nb) {
-        case 2: k2_group<2>(B, P, g, cnt, xs); break;
-        case 3: k2_group<3>(B, P, g, cnt, xs); break;
-        case 4: k2_group<4>(B, P, g, cnt, xs); break;
-        default: k2_group<5>(B, P, g, cnt, xs); break;
-    }
+    k2_group<NB>(B, P, g, B.g_count[g], lds + w * SL);
 }
 
-__global__ __launch_bounds__(BT) void b_cg_red2(BatchLaunch B) {
+// grouped launches, one per order present
+static void b_cg_k1_all(const BatchLaunch& B, hipStream_t s) {
+    auto go = [&](auto kfn, int nb) {
+        const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
+        if (ng > 0) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B);
+    };
+    go(b_cg_k1<2>, 2);
+    go(b_cg_k1<3>, 3);
+    go(b_cg_k1<4>, 4);
+    go(b_cg_k1<5>, 5);
+}
+
+static void b_cg_k2_all(const BatchLaunch& B, hipStream_t s) {
+    auto go = [&](auto kfn, int nb) {
+        const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
+        if (ng > 0) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B);
+    };
+    go(b_cg_k2<2>, 2);
+    go(b_cg_k2<3>, 3);
+    go(b_cg_k2<4>, 4);
+    go(b_cg_k2<5>, 5);
+}
+
+// coarse iterate of a problem on the vertex grid after b_mg_apply
+__device__ __forceinline__ const double* mg_x0(const MGLaunch& M, int prob) {
+    const MGLevelDev& L = M.lev[0];
+    return (M.lc[prob] == 0 ? L.x : L.t) + L.off[prob];
+}
+
+// r.z = r.(D^-1 r) + r.(P0 x0), and r.(P0 x0) = (P0^T r).x0 with P0^T r the
+// level-0 right-hand side of the coarse correction
+__global__ __launch_bounds__(BT) void b_cg_red2(BatchLaunch B, MGLaunch M) {
     __shared__ double red[BT];
     const int prob = blockIdx.x;
     if (cg_skip(B, prob)) return;
     const BProb& P = B.P[prob];
-    const double rzn = B.mg ? prob_sum(B, P, 1, red) : group_sum(B, P, 1, red);
+    double rzn = group_sum(B, P, 1, red);
+    if (B.mg) {
+        const MGLevelDev& L = M.lev[0];
+        const int nv = L.dims[2 * prob] * L.dims[2 * prob + 1];
+        const double* b0 = L.b + L.off[prob];
+        const double* x0 = mg_x0(M, prob);
+        double v = 0.0;
+        for (int k = threadIdx.x; k < nv; k += BT) v += b0[k] * x0[k];
+        rzn += b_block_sum(v, red);
+    }
     const double rr = group_sum(B, P, 2, red);
     if (threadIdx.x == 0) {
         double* s = P.scal;
@@ -2147,12 +2373,22 @@ __global__ __launch_bounds__(BT) void b_cg_red2(BatchLaunch B) {
     }
 }
 
-__global__ __launch_bounds__(BT) void b_cg_k3(BatchLaunch B) {
+// p = z + beta p, with z = D^-1 r + P0 x0 under the two-level preconditioner
+__global__ __launch_bounds__(BT) void b_cg_k3(BatchLaunch B, MGLaunch M) {
     const EB m = eb_map(B);
     if (cg_skip(B, m.prob) || m.K < 0) return;
     const BProb& P = B.P[m.prob];
     const long t = (long)m.K * P.n + m.i;
-    P.p[t] = P.z[t] + P.scal[9] * P.p[t];
+    double z = P.z[t];
+    if (B.mg) {
+        const int nvx = M.lev[0].dims[2 * m.prob];
+        const int ex = m.K % P.nx, ey = m.K / P.nx;
+        const double xa = P.gll[m.i % P.nb], yb = P.gll[m.i / P.nb];
+        const double* xv = mg_x0(M, m.prob) + ey * nvx + ex;
+        z += (1.0 - xa) * (1.0 - yb) * xv[0] + xa * (1.0 - yb) * xv[1] + (1.0 - xa) * yb * xv[nvx] +
+             xa * yb * xv[nvx + 1];
+    }
+    P.p[t] = z + P.scal[9] * P.p[t];
 }
 
 // a new PCG start: clear the done and breakdown flags left by the previous
@@ -2185,7 +2421,7 @@ hipError_t b_precond(const BatchLaunch& B, const MGLaunch* M, hipStream_t s) {
 
 hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s) {
     if (B.grouped)
-        hipLaunchKernelGGL(b_cg_k1, dim3((B.ngroups + 3) / 4), dim3(256), 0, s, B);
+        b_cg_k1_all(B, s);
     else
         hipLaunchKernelGGL(b_cg_k1n, dim3(B.nblocks), dim3(BT), 0, s, B);
     return hipGetLastError();
@@ -2194,20 +2430,21 @@ hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s) {
 hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const MGLaunch* M) {
     for (int k = 0; k < iters; ++k) {
         if (B.grouped)
-            hipLaunchKernelGGL(b_cg_k1, dim3((B.ngroups + 3) / 4), dim3(256), 0, s, B);
+            b_cg_k1_all(B, s);
         else
             hipLaunchKernelGGL(b_cg_k1n, dim3(B.nblocks), dim3(BT), 0, s, B);
         hipLaunchKernelGGL(b_cg_red1, dim3(B.nprob), dim3(BT), 0, s, B);
         if (B.grouped)
-            hipLaunchKernelGGL(b_cg_k2, dim3((B.ngroups + 3) / 4), dim3(256), 0, s, B);
+            b_cg_k2_all(B, s);
         else
             hipLaunchKernelGGL(b_cg_k2n, dim3(B.nblocks), dim3(BT), 0, s, B);
         if (B.mg) {
             const hipError_t e = b_mg_apply(B, *M, false, s);
             if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(b_cg_red2, dim3(B.nprob), dim3(BT), 0, s, B);
-        hipLaunchKernelGGL(b_cg_k3, dim3(B.nblocks), dim3(BT), 0, s, B);
+        const MGLaunch Mv = B.mg ? *M : MGLaunch{};
+        hipLaunchKernelGGL(b_cg_red2, dim3(B.nprob), dim3(BT), 0, s, B, Mv);
+        hipLaunchKernelGGL(b_cg_k3, dim3(B.nblocks), dim3(BT), 0, s, B, Mv);
     }
     return hipGetLastError();
 }
@@ -2657,7 +2894,7 @@ hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStr
     auto grid = [](int n) { return dim3((unsigned)((n + BT - 1) / BT)); };
     // per-level launches above level ls, one workgroup per problem below
     const int top = M.ls < M.nlev - 1 ? M.ls : M.nlev - 1;
-    hipLaunchKernelGGL(mg_corner_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M.corner);
+    if (init) hipLaunchKernelGGL(mg_corner_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M.corner);
     hipLaunchKernelGGL(mg_restrict0_kernel, grid(M.lev[0].nv), dim3(BT), 0, s, B, M, (const double*)M.corner);
     for (int l = 0; l < top; ++l) {
         const MGLevelDev& L = M.lev[l];
@@ -2674,7 +2911,7 @@ hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStr
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.t, L.x);
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.x, L.t);
     }
-    hipLaunchKernelGGL(mg_finish_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M, init ? 1 : 0);
+    if (init) hipLaunchKernelGGL(mg_finish_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M, 1);
     return hipGetLastError();
 }
 

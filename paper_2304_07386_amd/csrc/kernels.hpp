@@ -21,7 +21,11 @@ struct CartSweepArgs {
     void* psi;                   // [nd][psi_ld]
     int variant;                 // 0 automatic, 1 element-row kernel only
     long psi_ld;                 // row stride of psi (>= ne * n); 0 means ne * n
+    const void* tab;             // batched sweep: [nmat][nd][nb][nb][lane_rw(nb)] rows
+                                 // [Pm | Px | Py] of node column ca (third index), row ca + nb b
 };
+// padded length of one operator row [Pm | Px | Py] in the batched sweep table
+constexpr int lane_rw(int nb) { return (nb * nb + 2 * nb + 7) & ~7; }
 hipError_t launch_sweep_cart(bool fp64, const CartSweepArgs& a, hipStream_t s);
 
 // General (curved) sweep: per element and direction, assemble the local
@@ -144,8 +148,10 @@ struct BatchLaunch {
     const int* g_ty;               // [ngroups][5] self type, neighbour types (-1: boundary face)
     const int* g_elem;             // [ngroups][64]
     double* gpart;                 // [3][ngroups] per-group partial sums
+    int g_nb0[7];                  // groups of order nb - 1 are [g_nb0[nb], g_nb0[nb + 1]) (nb = 2..5)
     int grouped;                   // 1: PCG on the type groups, 0: per-node element blocks
     int mg;                        // 1: two-level preconditioner (r.z from b_mg_apply)
+    double* mg_corner;             // two-level: [4][batch elements] corner sums of r, written by the r update
 };
 
 // Two-level preconditioner: continuous Q1 coarse space on the element vertices
@@ -172,8 +178,11 @@ struct MGLaunch {
 };
 // allows the LDS size of the workgroup V-cycle kernel
 hipError_t mg_prepare(size_t lds);
-// z += P0 V(P0^T r) after the block-Jacobi z = D^-1 r; the partial sums of
-// r.z go to part[init ? 0 : 1][block], and with init p = z
+// Coarse correction x0 = V(P0^T r) on the vertex grid (level 0).  With init,
+// the corner sums of r are formed first and the correction is added to the
+// block-Jacobi z = D^-1 r: z += P0 x0, p = z, partial sums of r.z in part[0].
+// Without init (inside the PCG loop) the corner sums come from the r update
+// and z is left as D^-1 r: the iteration adds P0 x0 where it uses z.
 hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStream_t s);
 
 hipError_t b_source(bool fp64, const BatchLaunch& B, bool delta, hipStream_t s);
