@@ -38,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64, matrix cores and vector units alike
 METRIC = "sweep elem*angle*DOF/s + time-to-1e-8 SMM solve, plain vs batched+warm"
 
 
@@ -95,6 +96,18 @@ def roofline(kernel: str, what: str, bytes_per_launch: float, ms: float):
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kernel, "operation": what,
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": ms}
+
+
+def roofline_flops(kernel: str, what: str, flops_per_launch: float, bytes_per_launch: float, ms: float):
+    """FP64 compute roofline (the binding one for q = A p, whose ridge point
+    9.8 flop/B is below its 11.5 flop/B), with the HBM figures beside it."""
+    achieved = flops_per_launch / (ms * 1e-3) / 1e12
+    gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_for(kernel), "kernel": kernel,
+            "operation": what, "algorithmic_flops_per_launch": flops_per_launch,
+            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": ms,
+            "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
 
 
 def time_to_solution(L, ctx, n: int, log):
@@ -211,10 +224,14 @@ def main():
                         sweep_bytes, sweep_ms)
     spmv_ms = L.smm_batch_time_kernel(batch, L.SMM_KERNEL_CG_SPMV, 50)
     # q = A p: p read once and q written once, FP64 (16 B/DOF)
-    rl_spmv = roofline("b_cg_k1", "one q = A p over the batch (the per-order launches b_cg_k1<NB>)",
-                       16.0 * dofs, spmv_ms)
+    # q = A p: p read once and q written once, FP64 (16 B/DOF); 2 N^2 flops per
+    # nonzero block (the element's own block and one per interior face)
+    spmv_flops = float(sum(2.0 * (wl.p + 1) ** 4 * (wl.nx * wl.ny + 2 * (2 * wl.nx * wl.ny - wl.nx - wl.ny))
+                           for wl in wls))
+    rl_spmv = roofline_flops("b_cg_k1", "one q = A p over the batch (the per-order launches b_cg_k1<NB>)",
+                             spmv_flops, 16.0 * dofs, spmv_ms)
     log(f"sweep {sweep_ms:.3f} ms -> {units / sweep_ms / 1e-3:.3e} units/s, {rl_sweep['achieved']:.0f} GB/s; "
-        f"PCG q=Ap {spmv_ms * 1e3:.1f} us, {rl_spmv['achieved']:.0f} GB/s")
+        f"PCG q=Ap {spmv_ms * 1e3:.1f} us, {rl_spmv['achieved']:.2f} TFLOP/s, {rl_spmv['hbm_achieved_gbs']:.0f} GB/s")
     dominant = rl_spmv if phase["pcg"] > phase["source+sweep"] else rl_sweep
 
     tts = None

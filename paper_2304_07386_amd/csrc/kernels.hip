@@ -1142,6 +1142,11 @@ __device__ __forceinline__ EB eb_map(const BatchLaunch& B) {
     return r;
 }
 
+// grouped FP64 matrix-core block-row products (defined with the PCG kernels):
+// MODE 0: r = b - A x (PCG start), MODE 1: IP right-hand side
+template <int MODE>
+static void b_group_rows_all(const BatchLaunch& B, hipStream_t s);
+
 // ---- scattering source -----------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BT) void b_source_kernel(BatchLaunch B, int delta) {
@@ -1511,15 +1516,27 @@ __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accum
     double out[4][4];
     if constexpr (sizeof(T) == 4) {
         v4f a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
-        for (int k = 0; k < nd; k += 4) {
-            const int dk = k + kk;
-            const float av = dk < nd ? W[j * P.ldw + dk] : 0.f;
-            v4f bv = {0.f, 0.f, 0.f, 0.f};
-            if (dk < nd && colok) bv = *reinterpret_cast<const v4f*>(psi + (long)dk * P.Lpad + c4);
-            a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[0], a0, 0, 0, 0);
-            a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[1], a1, 0, 0, 0);
-            a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[2], a2, 0, 0, 0);
-            a3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[3], a3, 0, 0, 0);
+        // U steps of 4 directions per round, all their loads issued first
+        constexpr int U = 4;
+        const auto pg = as_global(reinterpret_cast<const v4f*>(psi));
+        for (int k0 = 0; k0 < nd; k0 += 4 * U) {
+            v4f bv[U];
+            float av[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int dk = k0 + 4 * u + kk;
+                const bool in = dk < nd && colok;
+                bv[u] = pg[in ? ((long)dk * P.Lpad + c4) / 4 : 0];
+                if (!in) bv[u] = v4f{0.f, 0.f, 0.f, 0.f};
+                av[u] = dk < nd ? W[j * P.ldw + dk] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][0], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][1], a1, 0, 0, 0);
+                a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][2], a2, 0, 0, 0);
+                a3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][3], a3, 0, 0, 0);
+            }
         }
         // FP32 layout: row 4 kk + r
         for (int r = 0; r < 4; ++r) {
@@ -1536,7 +1553,7 @@ __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accum
                     if (col >= P.L) break;
                     const long o = (long)row * P.L + col;
                     if (accumulate) P.mom_acc[o] = (first ? 0.0 : P.mom_acc[o]) + out[r][c];
-                    P.mom[o] = out[r][c];
+                    else P.mom[o] = out[r][c];
                 }
             }
         }
@@ -1566,7 +1583,7 @@ __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accum
                     if (col >= P.L) break;
                     const long o = (long)row * P.L + col;
                     if (accumulate) P.mom_acc[o] = (first ? 0.0 : P.mom_acc[o]) + vals[c];
-                    P.mom[o] = vals[c];
+                    else P.mom[o] = vals[c];
                 }
             }
         }
@@ -1641,6 +1658,7 @@ __global__ __launch_bounds__(BT) void b_rhs_kernel(BatchLaunch B) {
     const EB m = eb_map(B);
     if (!B.active[m.prob] || m.K < 0) return;
     const BProb& P = B.P[m.prob];
+    if (B.grouped && P.nb >= 3) return;  // on the matrix cores (rhs_group_mfma)
     const int n = P.n, n3 = 3 * n, K = m.K, i = m.i;
     const long L = P.L;
     double v = P.bfix[(long)K * n + i];
@@ -1675,6 +1693,7 @@ hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s) {
     hipLaunchKernelGGL(b_T_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
     if (B.nbq > 0) hipLaunchKernelGGL(b_beta_kernel, dim3((unsigned)((B.nbq + 255) / 256)), dim3(256), 0, s, B);
     hipLaunchKernelGGL(b_rhs_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
+    if (B.grouped) b_group_rows_all<1>(B, s);
     return hipGetLastError();
 }
 
@@ -1747,6 +1766,7 @@ __global__ __launch_bounds__(BT) void b_cg_init1(BatchLaunch B) {
     const EB m = eb_map(B);
     if (!B.active[m.prob] || m.K < 0) return;
     const BProb& P = B.P[m.prob];
+    if (B.grouped && P.nb >= 3) return;  // on the matrix cores (init1_group_mfma)
     const long t = (long)m.K * P.n + m.i;
     P.r[t] = P.b[t] - typed_row(P, P.x, m.K, m.i);
 }
@@ -1936,6 +1956,111 @@ __device__ __forceinline__ void k1_group_mfma(const BatchLaunch& B, const BProb&
     const int i16 = lane & 15, kq = lane >> 4;
     const int* ty = B.g_ty + g * 5;
     const int myK = B.g_elem[g * 64 + lane];  // every slot holds a valid element
+    const auto pg = as_global((const double*)P.p);
+    // lane = element: its vector of face f (0: the element itself, 1-4: its
+    // neighbours) is N consecutive words, loaded at immediate offsets
+    auto load_face = [&](int f, double(&v)[N]) {
+        const int src = f == 0 ? myK : nbr_of(P, myK, f - 1);
+        const auto row = pg + (unsigned)(src * N);
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = row[j];
+    };
+    auto next_face = [&](int f) {
+        ++f;
+        while (f < 5 && ty[f] < 0) ++f;
+        return f;
+    };
+    // block entries of face f (column-major: (i, k) at k N + i) as A tiles
+    auto load_blocks = [&](int f, double(&a)[KS][MB]) {
+        const auto A = as_global((f == 0 ? P.ip_self : P.ip_nbr) + (long)ty[f] * N * N);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb) {
+                const int k = 4 * s + kq, r = 16 * rb + i16;
+                const bool in = k < N && r < N;
+                a[s][rb] = ld_at(A, in ? (unsigned)(k * N + r) : 0u);
+                if (!in) a[s][rb] = 0.0;
+            }
+    };
+    v4d acc[MB][4];
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+    double v[N];
+    double a[KS][MB];
+    load_blocks(0, a);
+    load_face(0, v);
+    for (int f = 0; f < 5;) {
+        const int fn = next_face(f);
+#pragma unroll
+        for (int j = 0; j < N; ++j) xs[lane * S + j] = v[j];
+        lds_wave_sync();
+        // the next face's blocks and vectors are loaded while this face's
+        // tiles run (unconditionally: after the last face, face 0 again,
+        // unused), so the values just staged are dead and their registers
+        // are reused
+        double an[KS][MB];
+        load_blocks(fn < 5 ? fn : 0, an);
+        load_face(fn < 5 ? fn : 0, v);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + kq;
+            double bf[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bf[cb] = k < N ? xs[(16 * cb + i16) * S + k] : 0.0;
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][rb], bf[cb], acc[rb][cb], 0, 0, 0);
+        }
+        lds_wave_sync();
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb) a[s][rb] = an[s][rb];
+        f = fn;
+    }
+    // result tiles to LDS (element e = 16 cb + i16, row 16 rb + 4 r + kq),
+    // then each lane stores its element's q and forms its part of p.q
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rb + 4 * r + kq;
+                if (row < N) xs[(16 * cb + i16) * S + row] = acc[rb][cb][r];
+            }
+    lds_wave_sync();
+    double pq = 0.0;
+    if (lane < cnt) {
+        const auto qrow = as_global(P.q) + (unsigned)(myK * N);
+        const auto prow = pg + (unsigned)(myK * N);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const double qv = xs[lane * S + j];
+            qrow[j] = qv;
+            pq += prow[j] * qv;
+        }
+    }
+    pq = wave_sum(pq);
+    if (lane == 0) B.gpart[g] = pq;
+}
+
+// The same product with the face vectors loaded element-major and flat
+// (lane-consecutive words): fewer cache lines per load, more index arithmetic
+// per word; the better choice when N is a power of two.
+template <int NB>
+__device__ __forceinline__ void k1_group_mfma_flat(const BatchLaunch& B, const BProb& P, int g, int cnt, double* xs) {
+    constexpr int N = NB * NB, S = N | 1;
+    constexpr int MB = (N + 15) / 16, KS = (N + 3) / 4;
+    const int lane = threadIdx.x & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int* ty = B.g_ty + g * 5;
+    const int myK = B.g_elem[g * 64 + lane];  // every slot holds a valid element
     const int tot = cnt * N;
     const auto pg = as_global((const double*)P.p);
     // the flat indices are recomputed where used (an opaque copy of the lane
@@ -2050,6 +2175,207 @@ __device__ __forceinline__ void k1_group_mfma(const BatchLaunch& B, const BProb&
     if (lane == 0) B.gpart[g] = pq;
 }
 
+// Block-row product of one group on the FP64 matrix cores, general form:
+// Y (N x 64) = sum over items t < NT of A_t (N x N, column-major) X_t (N x 64),
+// item t being (face f(t), vector v(t)): X_t holds, for element e of the
+// group, the N words at v(t) + N K_f(e), K_f(e) the element itself (f = 0) or
+// its neighbour across face f - 1.  Items whose face is a boundary face of
+// the group are skipped.  Same tiles and staging as k1_group_mfma; the result
+// is left in LDS, row e = lane of element e (stride S = N | 1).
+template <int NB, int NT, class Item>
+__device__ __forceinline__ void group_rows_mfma(const BatchLaunch& B, const BProb& P, int g, double* xs,
+                                                Item item) {
+    constexpr int N = NB * NB, S = N | 1;
+    constexpr int MB = (N + 15) / 16, KS = (N + 3) / 4;
+    const int lane = threadIdx.x & 63;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int* ty = B.g_ty + g * 5;
+    const int myK = B.g_elem[g * 64 + lane];
+    // item t: face f, block pointer blk, vector base vec
+    auto valid = [&](int t) {
+        int f;
+        const double* blk;
+        const double* vec;
+        item(t, f, blk, vec);
+        return f == 0 || ty[f] >= 0;
+    };
+    auto next_item = [&](int t) {
+        ++t;
+        while (t < NT && !valid(t)) ++t;
+        return t;
+    };
+    auto load_item = [&](int t, double(&a)[KS][MB], double(&v)[N]) {
+        int f;
+        const double* blk;
+        const double* vec;
+        item(t, f, blk, vec);
+        const auto A = as_global(blk);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb) {
+                const int k = 4 * s + kq, r = 16 * rb + i16;
+                const bool in = k < N && r < N;
+                a[s][rb] = ld_at(A, in ? (unsigned)(k * N + r) : 0u);
+                if (!in) a[s][rb] = 0.0;
+            }
+        const int src = f == 0 ? myK : nbr_of(P, myK, f - 1);
+        const auto row = as_global(vec) + (unsigned)(src * N);
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = row[j];
+    };
+    v4d acc[MB][4];
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+    double v[N];
+    double a[KS][MB];
+    int t = valid(0) ? 0 : next_item(0);
+    if (t < NT) load_item(t, a, v);
+    while (t < NT) {
+        const int tn = next_item(t);
+#pragma unroll
+        for (int j = 0; j < N; ++j) xs[lane * S + j] = v[j];
+        lds_wave_sync();
+        double an[KS][MB];
+        load_item(tn < NT ? tn : t, an, v);  // unconditional: the staged values are dead
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + kq;
+            double bf[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bf[cb] = k < N ? xs[(16 * cb + i16) * S + k] : 0.0;
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][rb], bf[cb], acc[rb][cb], 0, 0, 0);
+        }
+        lds_wave_sync();
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb) a[s][rb] = an[s][rb];
+        t = tn;
+    }
+#pragma unroll
+    for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rb + 4 * r + kq;
+                if (row < N) xs[(16 * cb + i16) * S + row] = acc[rb][cb][r];
+            }
+    lds_wave_sync();
+}
+
+// Flat element-major store of a group's rows held in LDS (row e at e S):
+// out[K_e N + j] = op(j-th word of row e, in[K_e N + j]), consecutive lanes on
+// consecutive words, so the stores are coalesced.
+template <int NB, class Op>
+__device__ __forceinline__ void group_store_flat(const BatchLaunch& B, int g, int cnt, const double* xs,
+                                                 const double* in, double* out, Op op) {
+    constexpr int N = NB * NB, S = N | 1;
+    const int lane = threadIdx.x & 63;
+    const int myK = B.g_elem[g * 64 + lane];
+    const int tot = cnt * N;
+    const auto ig = as_global(in);
+    const auto og = as_global(out);
+#pragma unroll
+    for (int it = 0; it < N; ++it) {
+        const int u = lane + 64 * it;
+        const int e = u / N < 64 ? u / N : 63;
+        const int j = u - (u / N) * N;
+        const int K = __shfl(myK, e);
+        if (u < tot) {
+            const unsigned o = (unsigned)(K * N + j);
+            st_at(og, o, op(xs[e * S + j], ld_at(ig, o)));
+        }
+    }
+}
+
+// r = b - A x for one group (the PCG start), with group_rows_mfma
+template <int NB>
+__device__ __forceinline__ void init1_group_mfma(const BatchLaunch& B, const BProb& P, int g, int cnt, double* xs) {
+    constexpr int N = NB * NB;
+    const int* ty = B.g_ty + g * 5;
+    group_rows_mfma<NB, 5>(B, P, g, xs, [&](int t, int& f, const double*& blk, const double*& vec) {
+        f = t;
+        blk = (t == 0 ? P.ip_self : P.ip_nbr) + (long)ty[t] * N * N;
+        vec = P.x;
+    });
+    group_store_flat<NB>(B, g, cnt, xs, P.b, P.r, [](double ax, double b) { return b - ax; });
+}
+
+// IP right-hand side of one group: b = bfix + sum over faces and closure
+// components c of C_f[:, c] T_c (C_f column-major n x 3n, so component c is
+// the n x n block at offset c n^2), minus the boundary terms of the group's
+// boundary faces (all its elements share them)
+template <int NB>
+__device__ __forceinline__ void rhs_group_mfma(const BatchLaunch& B, const BProb& P, int g, int cnt, double* xs) {
+    constexpr int N = NB * NB, S = N | 1;
+    const int* ty = B.g_ty + g * 5;
+    const long L = P.L;
+    group_rows_mfma<NB, 15>(B, P, g, xs, [&](int t, int& f, const double*& blk, const double*& vec) {
+        f = t / 3;
+        const int c = t - 3 * f;
+        blk = (f == 0 ? P.c_self : P.c_nbr) + ((long)ty[f] * 3 + c) * N * N;
+        vec = P.T + c * L;
+    });
+    const int lane = threadIdx.x & 63;
+    bool bnd = false;
+    for (int f = 0; f < 4; ++f) bnd = bnd || ty[f + 1] < 0;
+    if (bnd) {  // wave-uniform: boundary terms on the element's row in LDS
+        if (lane < cnt) {
+            const int K = B.g_elem[g * 64 + lane];
+            for (int f = 0; f < 4; ++f) {
+                if (ty[f + 1] >= 0) continue;
+                const int bf = P.bface_of[K * 4 + f];
+                const double* bo = P.bop + (long)f * P.nq * N;
+                const double* be = P.beta + (long)bf * P.nq;
+                for (int q = 0; q < P.nq; ++q) {
+                    const double w = be[q];
+#pragma unroll
+                    for (int j = 0; j < N; ++j) xs[lane * S + j] -= bo[q * N + j] * w;
+                }
+            }
+        }
+        lds_wave_sync();
+    }
+    group_store_flat<NB>(B, g, cnt, xs, P.bfix, P.b, [](double y, double bfix) { return bfix + y; });
+}
+
+template <int NB, int MODE>
+__global__ __launch_bounds__(256, 2) void b_group_rows(BatchLaunch B) {
+    constexpr int SL = 64 * (NB * NB | 1);
+    __shared__ double lds[4 * SL];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = B.g_nb0[NB] + blockIdx.x * 4 + w;
+    if (g >= B.g_nb0[NB + 1]) return;
+    const int prob = B.g_prob[g];
+    if (!B.active[prob]) return;
+    const BProb& P = B.P[prob];
+    if constexpr (MODE == 0)
+        init1_group_mfma<NB>(B, P, g, B.g_count[g], lds + w * SL);
+    else
+        rhs_group_mfma<NB>(B, P, g, B.g_count[g], lds + w * SL);
+}
+
+// grouped launches of b_group_rows (orders with NB >= 3; order 1 stays on the
+// per-node kernel, which the caller launches)
+template <int MODE>
+static void b_group_rows_all(const BatchLaunch& B, hipStream_t s) {
+    auto go = [&](auto kfn, int nb) {
+        const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
+        if (ng > 0) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B);
+    };
+    go(b_group_rows<3, MODE>, 3);
+    go(b_group_rows<4, MODE>, 4);
+    go(b_group_rows<5, MODE>, 5);
+}
+
 // One launch per order: the groups of order NB are [g_nb0[NB], g_nb0[NB + 1]),
 // so each order gets its own register and LDS footprint.
 template <int NB>
@@ -2062,7 +2388,9 @@ __global__ __launch_bounds__(256, 2) void b_cg_k1(BatchLaunch B) {
     const int prob = B.g_prob[g];
     if (cg_skip(B, prob)) return;
     const BProb& P = B.P[prob];
-    if constexpr (NB >= 3)
+    if constexpr (NB == 4)
+        k1_group_mfma_flat<NB>(B, P, g, B.g_count[g], lds + w * SL);
+    else if constexpr (NB >= 3)
         k1_group_mfma<NB>(B, P, g, B.g_count[g], lds + w * SL);
     else
         k1_group<NB>(B, P, g, B.g_count[g], lds + w * SL);
@@ -2238,16 +2566,20 @@ __device__ __forceinline__ void k2_group(const BatchLaunch& B, const BProb& P, i
     const int tot = cnt * N;
     const double alpha = P.scal[8];
     double rr = 0.0, rz = 0.0;
+    const auto xg = as_global(P.x);
+    const auto rg = as_global(P.r);
+    const auto pg = as_global((const double*)P.p);
+    const auto qg = as_global((const double*)P.q);
 #pragma unroll
     for (int it = 0; it < N; ++it) {
         const int u = lane + 64 * it;
         const int e = u / N < 64 ? u / N : 63;
         const int K = __shfl(myK, e);
         if (u < tot) {
-            const long o = (long)K * N + (u - (u / N) * N);
-            P.x[o] += alpha * P.p[o];
-            const double r = P.r[o] - alpha * P.q[o];
-            P.r[o] = r;
+            const unsigned o = (unsigned)(K * N + (u - (u / N) * N));
+            st_at(xg, o, ld_at(xg, o) + alpha * ld_at(pg, o));
+            const double r = ld_at(rg, o) - alpha * ld_at(qg, o);
+            st_at(rg, o, r);
             rr += r * r;
             xs[(u / N) * S + (u - (u / N) * N)] = r;
         }
@@ -2276,7 +2608,7 @@ __device__ __forceinline__ void k2_group(const BatchLaunch& B, const BProb& P, i
                 c[3] += xa * yb * r;
             }
         }
-        double* co = B.mg_corner + 4L * (P.e_off + myK);
+        const auto co = as_global(B.mg_corner) + (unsigned)(4 * (P.e_off + myK));
 #pragma unroll
         for (int k = 0; k < 4; ++k) co[k] = c[k];
     }
@@ -2290,7 +2622,7 @@ __device__ __forceinline__ void k2_group(const BatchLaunch& B, const BProb& P, i
         const int u = lane + 64 * it;
         const int e = u / N < 64 ? u / N : 63;
         const int K = __shfl(myK, e);
-        if (u < tot) P.z[(long)K * N + (u - (u / N) * N)] = xs[(u / N) * S + (u - (u / N) * N)];
+        if (u < tot) st_at(as_global(P.z), (unsigned)(K * N + (u - (u / N) * N)), xs[(u / N) * S + (u - (u / N) * N)]);
     }
     rz = wave_sum(rz);
     rr = wave_sum(rr);
@@ -2404,6 +2736,7 @@ __global__ void b_cg_clear_kernel(BatchLaunch B) {
 hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s, const MGLaunch* M) {
     hipLaunchKernelGGL(b_cg_clear_kernel, dim3((B.nprob + 255) / 256), dim3(256), 0, s, B);
     hipLaunchKernelGGL(b_cg_init1, dim3(B.nblocks), dim3(BT), 0, s, B);
+    if (B.grouped) b_group_rows_all<0>(B, s);
     hipLaunchKernelGGL(b_cg_init2, dim3(B.nblocks), dim3(BT), 0, s, B);
     if (B.mg) {
         const hipError_t e = b_mg_apply(B, *M, true, s);
