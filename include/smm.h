@@ -246,6 +246,16 @@ int smm_debug_mg_level(smm_problem* prob, int level, double* A9, int* nvx, int* 
  * n_elem * n_node values each.  Overwrites the batch's PCG work vectors (the
  * outputs of the last solve become unavailable). */
 int smm_debug_batch_precond(smm_batch* batch, int precond, const double* const* r, double* const* z);
+/* Testing hook: y = A x, A the typed IP moment matrix (eq. ipsmm) of every
+ * problem of a batch, with the batch's current PCG kernels; x and y are n
+ * host pointers of n_elem * n_node values each.  Overwrites the batch's PCG
+ * work vectors. */
+int smm_debug_batch_spmv(smm_batch* batch, const double* const* x, double* const* y);
+/* Testing hook: choose the batch's PCG kernels: 1 the type-group kernels
+ * (one wave per group of elements sharing their blocks), 0 the per-node
+ * kernels, -1 the automatic choice (group fill).  Results agree up to the
+ * summation order.  SMM_EUNSUPPORTED if the batch has no type groups. */
+int smm_debug_batch_grouped(smm_batch* batch, int grouped);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems (uniform Cartesian meshes, isotropic

@@ -124,6 +124,7 @@ struct smm_batch {
     int *d_gprob = nullptr, *d_gcount = nullptr, *d_gty = nullptr, *d_gelem = nullptr;
     double* d_gpart = nullptr;
     bool grouped = false;          // groups filled densely enough for the grouped PCG kernels
+    bool grouped_auto = false;     // that choice before any testing override
     // two-level preconditioner (precond = 1): per-level flat vertex arrays
     bool use_mg = false;
     std::string mg_error;          // why the two-level preconditioner is unavailable (empty: available)
@@ -417,6 +418,7 @@ int batch_build(smm_batch* B) {
         long ne_tot = 0;
         for (int b = 0; b < np; ++b) ne_tot += B->probs[b]->P.ne;
         B->grouped = B->ngroups > 0 && (double)ne_tot >= 0.75 * 64.0 * B->ngroups;
+        B->grouped_auto = B->grouped;
     }
     pool.req(&B->d_gprob, sizeof(int) * B->ngroups);
     pool.req(&B->d_gcount, sizeof(int) * B->ngroups);
@@ -1430,6 +1432,32 @@ int smm_debug_batch_precond(smm_batch* batch, int precond, const double* const* 
     for (int b = 0; b < batch->nprob; ++b)
         HIPCHK(c, hipMemcpy(z[b], batch->pp[b].z, sizeof(double) * batch->hP[b].L, hipMemcpyDeviceToHost));
     batch->have_outputs = false;
+    return SMM_OK;
+}
+
+int smm_debug_batch_spmv(smm_batch* batch, const double* const* x, double* const* y) {
+    if (!batch || !x || !y) return SMM_EINVAL;
+    smm_ctx* c = batch->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    batch->active.assign(batch->nprob, 1);
+    int rc;
+    if ((rc = put(c, batch->d_active, batch->active.data(), sizeof(int) * batch->nprob))) return rc;
+    HIPCHK(c, hipMemset(batch->d_scal, 0, sizeof(double) * 16 * batch->nprob));
+    for (int b = 0; b < batch->nprob; ++b)
+        if ((rc = put(c, batch->pp[b].p, x[b], sizeof(double) * batch->hP[b].L))) return rc;
+    const BatchLaunch L = launch_desc(batch);
+    HIPCHK(c, b_cg_spmv(L, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < batch->nprob; ++b)
+        HIPCHK(c, hipMemcpy(y[b], batch->pp[b].q, sizeof(double) * batch->hP[b].L, hipMemcpyDeviceToHost));
+    batch->have_outputs = false;
+    return SMM_OK;
+}
+
+int smm_debug_batch_grouped(smm_batch* batch, int grouped) {
+    if (!batch || grouped < -1 || grouped > 1) return SMM_EINVAL;
+    if (grouped == 1 && batch->ngroups == 0) return fail(batch->ctx, SMM_EUNSUPPORTED, "batch has no type groups");
+    batch->grouped = grouped < 0 ? batch->grouped_auto : grouped == 1;
     return SMM_OK;
 }
 

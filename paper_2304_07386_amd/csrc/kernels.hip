@@ -1658,7 +1658,7 @@ __global__ __launch_bounds__(BT) void b_rhs_kernel(BatchLaunch B) {
     const EB m = eb_map(B);
     if (!B.active[m.prob] || m.K < 0) return;
     const BProb& P = B.P[m.prob];
-    if (B.grouped && P.nb >= 3) return;  // on the matrix cores (rhs_group_mfma)
+    if (B.grouped) return;  // on the matrix cores (rhs_group_mfma)
     const int n = P.n, n3 = 3 * n, K = m.K, i = m.i;
     const long L = P.L;
     double v = P.bfix[(long)K * n + i];
@@ -1692,8 +1692,10 @@ __global__ __launch_bounds__(BT) void b_rhs_kernel(BatchLaunch B) {
 hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s) {
     hipLaunchKernelGGL(b_T_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
     if (B.nbq > 0) hipLaunchKernelGGL(b_beta_kernel, dim3((unsigned)((B.nbq + 255) / 256)), dim3(256), 0, s, B);
-    hipLaunchKernelGGL(b_rhs_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
-    if (B.grouped) b_group_rows_all<1>(B, s);
+    if (B.grouped)
+        b_group_rows_all<1>(B, s);
+    else
+        hipLaunchKernelGGL(b_rhs_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
     return hipGetLastError();
 }
 
@@ -1766,7 +1768,7 @@ __global__ __launch_bounds__(BT) void b_cg_init1(BatchLaunch B) {
     const EB m = eb_map(B);
     if (!B.active[m.prob] || m.K < 0) return;
     const BProb& P = B.P[m.prob];
-    if (B.grouped && P.nb >= 3) return;  // on the matrix cores (init1_group_mfma)
+    if (B.grouped) return;  // on the matrix cores (init1_group_mfma)
     const long t = (long)m.K * P.n + m.i;
     P.r[t] = P.b[t] - typed_row(P, P.x, m.K, m.i);
 }
@@ -2363,14 +2365,14 @@ __global__ __launch_bounds__(256, 2) void b_group_rows(BatchLaunch B) {
         rhs_group_mfma<NB>(B, P, g, B.g_count[g], lds + w * SL);
 }
 
-// grouped launches of b_group_rows (orders with NB >= 3; order 1 stays on the
-// per-node kernel, which the caller launches)
+// grouped launches of b_group_rows, one per order present
 template <int MODE>
 static void b_group_rows_all(const BatchLaunch& B, hipStream_t s) {
     auto go = [&](auto kfn, int nb) {
         const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
         if (ng > 0) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B);
     };
+    go(b_group_rows<2, MODE>, 2);
     go(b_group_rows<3, MODE>, 3);
     go(b_group_rows<4, MODE>, 4);
     go(b_group_rows<5, MODE>, 5);
@@ -2632,10 +2634,122 @@ __device__ __forceinline__ void k2_group(const BatchLaunch& B, const BProb& P, i
     }
 }
 
+// The update with z = D^-1 r on the FP64 matrix cores (vectors still moved
+// flat and coalesced)
+template <int NB>
+__device__ __forceinline__ void k2_group_mfma(const BatchLaunch& B, const BProb& P, int g, int cnt, double* xs) {
+    constexpr int N = NB * NB, S = N | 1;
+    const int lane = threadIdx.x & 63;
+    const int myK = B.g_elem[g * 64 + lane];
+    const int tot = cnt * N;
+    const double alpha = P.scal[8];
+    double rr = 0.0, rz = 0.0;
+    const auto xg = as_global(P.x);
+    const auto rg = as_global(P.r);
+    const auto pg = as_global((const double*)P.p);
+    const auto qg = as_global((const double*)P.q);
+#pragma unroll
+    for (int it = 0; it < N; ++it) {
+        const int u = lane + 64 * it;
+        const int e = u / N < 64 ? u / N : 63;
+        const int K = __shfl(myK, e);
+        if (u < tot) {
+            const unsigned o = (unsigned)(K * N + (u - (u / N) * N));
+            st_at(xg, o, ld_at(xg, o) + alpha * ld_at(pg, o));
+            const double r = ld_at(rg, o) - alpha * ld_at(qg, o);
+            st_at(rg, o, r);
+            rr += r * r;
+            xs[(u / N) * S + (u - (u / N) * N)] = r;
+        }
+    }
+    lds_wave_sync();
+    if (B.mg_corner && lane < cnt) {
+        // corner sums of r for the coarse correction: sum over the nodes of
+        // hat_corner(node) r(node), corner = cx + 2 cy
+        double c[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const double yb = P.gll[b];
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                const double xa = P.gll[a], r = xs[lane * S + a + NB * b];
+                c[0] += (1.0 - xa) * (1.0 - yb) * r;
+                c[1] += xa * (1.0 - yb) * r;
+                c[2] += (1.0 - xa) * yb * r;
+                c[3] += xa * yb * r;
+            }
+        }
+        const auto co = as_global(B.mg_corner) + (unsigned)(4 * (P.e_off + myK));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) co[k] = c[k];
+    }
+    // z = D^-1 r on the FP64 matrix cores: tiles as in k1_group_mfma, A the
+    // group's block-Jacobi inverse (column-major), B the staged r
+    {
+        constexpr int MB = (N + 15) / 16, KS = (N + 3) / 4;
+        const int i16 = lane & 15, kq = lane >> 4;
+        const auto A = as_global(P.dinv + (long)B.g_ty[g * 5] * N * N);
+        v4d acc[MB][4];
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int k = 4 * s + kq;
+            double a[MB], bf[4];
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb) {
+                const int r = 16 * rb + i16;
+                const bool in = k < N && r < N;
+                a[rb] = ld_at(A, in ? (unsigned)(k * N + r) : 0u);
+                if (!in) a[rb] = 0.0;
+            }
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bf[cb] = k < N ? xs[(16 * cb + i16) * S + k] : 0.0;
+#pragma unroll
+            for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], bf[cb], acc[rb][cb], 0, 0, 0);
+        }
+        lds_wave_sync();
+        // each tile entry (row, e) belongs to one lane: r.z from the staged r,
+        // then z in its place
+#pragma unroll
+        for (int rb = 0; rb < MB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * rb + 4 * r + kq, e = 16 * cb + i16;
+                    if (row < N && e < cnt) {
+                        double* cell = xs + e * S + row;
+                        rz += *cell * acc[rb][cb][r];
+                        *cell = acc[rb][cb][r];
+                    }
+                }
+    }
+    lds_wave_sync();
+#pragma unroll
+    for (int it = 0; it < N; ++it) {
+        const int u = lane + 64 * it;
+        const int e = u / N < 64 ? u / N : 63;
+        const int K = __shfl(myK, e);
+        if (u < tot) st_at(as_global(P.z), (unsigned)(K * N + (u - (u / N) * N)), xs[(u / N) * S + (u - (u / N) * N)]);
+    }
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    if (lane == 0) {
+        B.gpart[B.ngroups + g] = rz;
+        B.gpart[2 * B.ngroups + g] = rr;
+    }
+}
+
 // x += alpha p, r -= alpha q, z = D^-1 r (block-Jacobi) and the group's partial
 // sums of r.z and r.r
 template <int NB>
-__global__ __launch_bounds__(256) void b_cg_k2(BatchLaunch B) {
+__global__ __launch_bounds__(256, 2) void b_cg_k2(BatchLaunch B) {
     constexpr int SL = 64 * (NB * NB | 1);
     __shared__ double lds[4 * SL];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -2644,7 +2758,10 @@ __global__ __launch_bounds__(256) void b_cg_k2(BatchLaunch B) {
     const int prob = B.g_prob[g];
     if (cg_skip(B, prob)) return;
     const BProb& P = B.P[prob];
-    k2_group<NB>(B, P, g, B.g_count[g], lds + w * SL);
+    if constexpr (NB >= 3)
+        k2_group_mfma<NB>(B, P, g, B.g_count[g], lds + w * SL);
+    else
+        k2_group<NB>(B, P, g, B.g_count[g], lds + w * SL);
 }
 
 // grouped launches, one per order present
@@ -2723,6 +2840,55 @@ __global__ __launch_bounds__(BT) void b_cg_k3(BatchLaunch B, MGLaunch M) {
     P.p[t] = z + P.scal[9] * P.p[t];
 }
 
+// p = z + beta p (z = D^-1 r + P0 x0 with the two-level preconditioner) over
+// one type group, flat element-major (coalesced) like the update kernel
+template <int NB>
+__global__ __launch_bounds__(256) void b_cg_k3g(BatchLaunch B, MGLaunch M) {
+    constexpr int N = NB * NB;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = B.g_nb0[NB] + blockIdx.x * 4 + w;
+    if (g >= B.g_nb0[NB + 1]) return;
+    const int prob = B.g_prob[g];
+    if (cg_skip(B, prob)) return;
+    const BProb& P = B.P[prob];
+    const int lane = threadIdx.x & 63;
+    const int cnt = B.g_count[g], tot = cnt * N;
+    const int myK = B.g_elem[g * 64 + lane];
+    const double beta = P.scal[9];
+    const auto zg = as_global((const double*)P.z);
+    const auto pg = as_global(P.p);
+    // vertex of the element's lower-left corner on the level-0 grid
+    int nvx = 0, myV = 0;
+    const double* x0 = nullptr;
+    double gl[NB];
+    if (B.mg) {
+        nvx = M.lev[0].dims[2 * prob];
+        myV = (myK / P.nx) * nvx + myK % P.nx;
+        x0 = mg_x0(M, prob);
+#pragma unroll
+        for (int a = 0; a < NB; ++a) gl[a] = P.gll[a];
+    }
+#pragma unroll
+    for (int it = 0; it < N; ++it) {
+        const int u = lane + 64 * it;
+        const int e = u / N < 64 ? u / N : 63;
+        const int j = u - (u / N) * N;
+        const int K = __shfl(myK, e);
+        const int V = __shfl(myV, e);
+        if (u < tot) {
+            const unsigned o = (unsigned)(K * N + j);
+            double z = ld_at(zg, o);
+            if (B.mg) {
+                const double xa = gl[j % NB], yb = gl[j / NB];
+                const double* xv = x0 + V;
+                z += (1.0 - xa) * (1.0 - yb) * xv[0] + xa * (1.0 - yb) * xv[1] + (1.0 - xa) * yb * xv[nvx] +
+                     xa * yb * xv[nvx + 1];
+            }
+            st_at(pg, o, z + beta * ld_at(pg, o));
+        }
+    }
+}
+
 // a new PCG start: clear the done and breakdown flags left by the previous
 // solve (the start kernels run for every active problem)
 __global__ void b_cg_clear_kernel(BatchLaunch B) {
@@ -2735,8 +2901,10 @@ __global__ void b_cg_clear_kernel(BatchLaunch B) {
 
 hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s, const MGLaunch* M) {
     hipLaunchKernelGGL(b_cg_clear_kernel, dim3((B.nprob + 255) / 256), dim3(256), 0, s, B);
-    hipLaunchKernelGGL(b_cg_init1, dim3(B.nblocks), dim3(BT), 0, s, B);
-    if (B.grouped) b_group_rows_all<0>(B, s);
+    if (B.grouped)
+        b_group_rows_all<0>(B, s);
+    else
+        hipLaunchKernelGGL(b_cg_init1, dim3(B.nblocks), dim3(BT), 0, s, B);
     hipLaunchKernelGGL(b_cg_init2, dim3(B.nblocks), dim3(BT), 0, s, B);
     if (B.mg) {
         const hipError_t e = b_mg_apply(B, *M, true, s);
@@ -2777,7 +2945,18 @@ hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const
         }
         const MGLaunch Mv = B.mg ? *M : MGLaunch{};
         hipLaunchKernelGGL(b_cg_red2, dim3(B.nprob), dim3(BT), 0, s, B, Mv);
-        hipLaunchKernelGGL(b_cg_k3, dim3(B.nblocks), dim3(BT), 0, s, B, Mv);
+        if (B.grouped) {
+            auto go = [&](auto kfn, int nb) {
+                const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
+                if (ng > 0) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B, Mv);
+            };
+            go(b_cg_k3g<2>, 2);
+            go(b_cg_k3g<3>, 3);
+            go(b_cg_k3g<4>, 4);
+            go(b_cg_k3g<5>, 5);
+        } else {
+            hipLaunchKernelGGL(b_cg_k3, dim3(B.nblocks), dim3(BT), 0, s, B, Mv);
+        }
     }
     return hipGetLastError();
 }
@@ -2988,8 +3167,9 @@ __global__ __launch_bounds__(BT) void mg_restrict0_kernel(BatchLaunch B, MGLaunc
     L.b[v] = s;
 }
 
-// damped Jacobi: xout = omega b / d (first) or xin + omega (b - A xin) / d
-__global__ __launch_bounds__(BT) void mg_smooth_kernel(BatchLaunch B, MGLaunch M, int l, int first, const double* xin,
+// damped Jacobi: xout = omega b / d (mode 1, the first step from zero) or
+// xin + omega (b - A xin) / d (mode 0); mode 2: the residual xout = b - A xin
+__global__ __launch_bounds__(BT) void mg_smooth_kernel(BatchLaunch B, MGLaunch M, int l, int mode, const double* xin,
                                                        double* xout) {
     const MGLevelDev& L = M.lev[l];
     const int v = blockIdx.x * BT + threadIdx.x;
@@ -2997,17 +3177,19 @@ __global__ __launch_bounds__(BT) void mg_smooth_kernel(BatchLaunch B, MGLaunch M
     const int prob = mg_prob(L.off, B.nprob, v);
     if (cg_skip(B, prob) || M.lc[prob] <= l) return;
     const int o = L.off[prob], nvx = L.dims[2 * prob], nvy = L.dims[2 * prob + 1], loc = v - o;
-    const double d = L.A[4L * L.nv + v];
-    if (first) {
-        xout[v] = M.omega * L.b[v] / d;
-    } else {
-        const double ax = mg_apply(L, o, nvx, nvy, loc % nvx, loc / nvx, xin);
-        xout[v] = xin[v] + M.omega * (L.b[v] - ax) / d;
+    if (mode == 1) {
+        xout[v] = M.omega * L.b[v] / L.A[4L * L.nv + v];
+        return;
     }
+    const double ax = mg_apply(L, o, nvx, nvy, loc % nvx, loc / nvx, xin);
+    if (mode == 2)
+        xout[v] = L.b[v] - ax;
+    else
+        xout[v] = xin[v] + M.omega * (L.b[v] - ax) / L.A[4L * L.nv + v];
 }
 
-// b_{l+1}[c] = sum over fine f of w(f, c) (b_l - A_l x)[f]
-__global__ __launch_bounds__(BT) void mg_restrict_kernel(BatchLaunch B, MGLaunch M, int l, const double* x) {
+// b_{l+1}[c] = sum over fine f of w(f, c) res[f], res the fine residual
+__global__ __launch_bounds__(BT) void mg_restrict_kernel(BatchLaunch B, MGLaunch M, int l, const double* res) {
     const MGLevelDev& F = M.lev[l];
     const MGLevelDev& C = M.lev[l + 1];
     const int c = blockIdx.x * BT + threadIdx.x;
@@ -3031,7 +3213,7 @@ __global__ __launch_bounds__(BT) void mg_restrict_kernel(BatchLaunch B, MGLaunch
             const double wx = mg_weight(fx, fnx, cx);
             if (wx == 0.0) continue;
             const int f = fo + fy * fnx + fx;
-            s += wx * wy * (F.b[f] - mg_apply(F, fo, fnx, fny, fx, fy, x));
+            s += wx * wy * res[f];
         }
     }
     C.b[c] = s;
@@ -3233,7 +3415,9 @@ hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStr
         const MGLevelDev& L = M.lev[l];
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 1, (const double*)L.x, L.x);
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.x, L.t);
-        hipLaunchKernelGGL(mg_restrict_kernel, grid(M.lev[l + 1].nv), dim3(BT), 0, s, B, M, l, (const double*)L.t);
+        // residual of the smoothed iterate into x (free until the post-smoothing)
+        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 2, (const double*)L.t, L.x);
+        hipLaunchKernelGGL(mg_restrict_kernel, grid(M.lev[l + 1].nv), dim3(BT), 0, s, B, M, l, (const double*)L.x);
     }
     if (M.ls < M.nlev)
         hipLaunchKernelGGL(mg_vcycle_lds_kernel, dim3(B.nprob), dim3(1024), M.lds, s, B, M);

@@ -30,7 +30,8 @@ EXPORTED = [
     "smm_set_sweep_path", "smm_time_sweep", "smm_debug_typed_dense", "smm_debug_corr_dense",
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
-    "smm_batch_history", "smm_debug_mg_level", "smm_debug_batch_precond",
+    "smm_batch_history", "smm_debug_mg_level", "smm_debug_batch_precond", "smm_debug_batch_spmv",
+    "smm_debug_batch_grouped",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
@@ -120,6 +121,8 @@ def load_library(path: str = LIB_PATH):
         "smm_batch_history": (ip, [vp, ip, ip, vp, vp, C.POINTER(ip)]),
         "smm_debug_mg_level": (ip, [vp, ip, vp, C.POINTER(ip), C.POINTER(ip)]),
         "smm_debug_batch_precond": (ip, [vp, ip, C.POINTER(vp), C.POINTER(vp)]),
+        "smm_debug_batch_spmv": (ip, [vp, C.POINTER(vp), C.POINTER(vp)]),
+        "smm_debug_batch_grouped": (ip, [vp, ip]),
         "smm_cnn_create": (ip, [vp, ip, C.POINTER(ip), ip, ip, ip, C.POINTER(vp)]),
         "smm_cnn_destroy": (ip, [vp]),
         "smm_cnn_num_params": (ip, [vp, C.POINTER(C.c_size_t)]),
@@ -453,6 +456,21 @@ def smm_debug_batch_precond(batch, precond: int, rs):
     zp = (C.c_void_p * len(zs))(*[z.ctypes.data for z in zs])
     _check(load_library().smm_debug_batch_precond(batch.handle, precond, rp, zp), batch.ctx)
     return zs
+
+
+def smm_debug_batch_spmv(batch, xs):
+    """y = A x per problem (host arrays) with the batch's current PCG kernels."""
+    xs = [_f64(x) for x in xs]
+    ys = [np.zeros_like(x) for x in xs]
+    xp = (C.c_void_p * len(xs))(*[x.ctypes.data for x in xs])
+    yp = (C.c_void_p * len(ys))(*[y.ctypes.data for y in ys])
+    _check(load_library().smm_debug_batch_spmv(batch.handle, xp, yp), batch.ctx)
+    return ys
+
+
+def smm_debug_batch_grouped(batch, grouped: int):
+    """Force the type-group (1) or per-node (0) PCG kernels, or the automatic choice (-1)."""
+    _check(load_library().smm_debug_batch_grouped(batch.handle, grouped), batch.ctx)
 
 
 def smm_debug_mg_level(prob, level: int):
