@@ -57,6 +57,20 @@ def run():
     print("[counters] done", flush=True)
 
 
+def sweep_launches(nprob=256):
+    """Persistent launches per batched sweep: one per (order, workgroup size),
+    the workgroup being NB waves per 64-slot chunk of the longest
+    anti-diagonal (as the library groups the tasks)."""
+    sys.path.insert(0, os.path.dirname(HERE))
+    from workloads import config_batched_problem
+    groups = set()
+    for s in range(nprob):
+        wl = config_batched_problem(s)
+        nb = wl.p + 1
+        groups.add((nb, 64 * nb * ((min(wl.nx, wl.ny) + 63) // 64)))
+    return len(groups)
+
+
 def _rows(d):
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not files:
@@ -93,9 +107,8 @@ def parse(dir_fetch, dir_write, out):
         nvar = len({n for n, v in k1})
         spmv = [v for n, v in k1[-SPMV_REPS * nvar:]]
         sweeps = [v for n, v in disp if "b_sweep_kernel" in n]
-        # the timed sweeps: the last SWEEP_REPS * (orders) dispatches
-        norders = len({n for n, v in disp if "b_sweep_kernel" in n})
-        sw = sweeps[-SWEEP_REPS * norders:]
+        # the timed sweeps: the last SWEEP_REPS * (launches per sweep) dispatches
+        sw = sweeps[-SWEEP_REPS * sweep_launches():]
         res[which] = {"scale": scale, "copy_kib": big,
                       "b_cg_k1": 1024.0 * scale * sum(spmv) / SPMV_REPS,
                       "b_sweep_kernel": 1024.0 * scale * sum(sw) / SWEEP_REPS}

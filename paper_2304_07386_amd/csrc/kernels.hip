@@ -2037,15 +2037,22 @@ __device__ __forceinline__ void k1_group_mfma(const BatchLaunch& B, const BProb&
                 if (row < N) xs[(16 * cb + i16) * S + row] = acc[rb][cb][r];
             }
     lds_wave_sync();
+    // q stored flat element-major (coalesced: per-lane rows would write each
+    // cache line in many partial pieces)
     double pq = 0.0;
-    if (lane < cnt) {
-        const auto qrow = as_global(P.q) + (unsigned)(myK * N);
-        const auto prow = pg + (unsigned)(myK * N);
+    const auto qg = as_global(P.q);
+    const int tot = cnt * N;
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const double qv = xs[lane * S + j];
-            qrow[j] = qv;
-            pq += prow[j] * qv;
+    for (int it = 0; it < N; ++it) {
+        const int u = lane + 64 * it;
+        const int e = u / N < 64 ? u / N : 63;
+        const int j = u - (u / N) * N;
+        const int K = __shfl(myK, e);
+        if (u < tot) {
+            const unsigned o = (unsigned)(K * N + j);
+            const double qv = xs[e * S + j];
+            st_at(qg, o, qv);
+            pq += ld_at(pg, o) * qv;
         }
     }
     pq = wave_sum(pq);
