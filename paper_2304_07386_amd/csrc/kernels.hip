@@ -1147,6 +1147,16 @@ __device__ __forceinline__ EB eb_map(const BatchLaunch& B) {
 template <int MODE>
 static void b_group_rows_all(const BatchLaunch& B, hipStream_t s);
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  This maps them so that each XCD takes one contiguous range of logical
+// workgroup indices: consecutive type groups (neighbouring element rows, whose
+// vectors the neighbour faces read again) then share one L2.
+__device__ __forceinline__ int xcd_block() {
+    const int nwg = gridDim.x, b = blockIdx.x;
+    const int k = b & 7, q = nwg >> 3, r = nwg & 7;
+    return k * q + (k < r ? k : r) + (b >> 3);
+}
+
 // ---- scattering source -----------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BT) void b_source_kernel(BatchLaunch B, int delta) {
@@ -2361,7 +2371,7 @@ __global__ __launch_bounds__(256, 2) void b_group_rows(BatchLaunch B) {
     constexpr int SL = 64 * (NB * NB | 1);
     __shared__ double lds[4 * SL];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = B.g_nb0[NB] + blockIdx.x * 4 + w;
+    const int g = B.g_nb0[NB] + xcd_block() * 4 + w;
     if (g >= B.g_nb0[NB + 1]) return;
     const int prob = B.g_prob[g];
     if (!B.active[prob]) return;
@@ -2392,7 +2402,7 @@ __global__ __launch_bounds__(256, 2) void b_cg_k1(BatchLaunch B) {
     constexpr int SL = 64 * (NB * NB | 1);
     __shared__ double lds[4 * SL];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = B.g_nb0[NB] + blockIdx.x * 4 + w;
+    const int g = B.g_nb0[NB] + xcd_block() * 4 + w;
     if (g >= B.g_nb0[NB + 1]) return;  // wave-uniform; no workgroup barriers below
     const int prob = B.g_prob[g];
     if (cg_skip(B, prob)) return;
@@ -2760,7 +2770,7 @@ __global__ __launch_bounds__(256, 2) void b_cg_k2(BatchLaunch B) {
     constexpr int SL = 64 * (NB * NB | 1);
     __shared__ double lds[4 * SL];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = B.g_nb0[NB] + blockIdx.x * 4 + w;
+    const int g = B.g_nb0[NB] + xcd_block() * 4 + w;
     if (g >= B.g_nb0[NB + 1]) return;
     const int prob = B.g_prob[g];
     if (cg_skip(B, prob)) return;
@@ -2853,7 +2863,7 @@ template <int NB>
 __global__ __launch_bounds__(256) void b_cg_k3g(BatchLaunch B, MGLaunch M) {
     constexpr int N = NB * NB;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = B.g_nb0[NB] + blockIdx.x * 4 + w;
+    const int g = B.g_nb0[NB] + xcd_block() * 4 + w;
     if (g >= B.g_nb0[NB + 1]) return;
     const int prob = B.g_prob[g];
     if (cg_skip(B, prob)) return;
@@ -3285,6 +3295,7 @@ __global__ __launch_bounds__(1024) void mg_vcycle_lds_kernel(BatchLaunch B, MGLa
     };
     auto diag = [&](int l, int v) { return M.lev[l].A[4L * M.lev[l].nv + M.lev[l].off[prob] + v]; };
     const double om = M.omega;
+    const int nu = M.nu;
     {
         const double* bg = M.lev[ls].b + M.lev[ls].off[prob];
         double* b = Bv(ls);
@@ -3296,10 +3307,17 @@ __global__ __launch_bounds__(1024) void mg_vcycle_lds_kernel(BatchLaunch B, MGLa
         double *x = X(l), *t = Tv(l), *b = Bv(l);
         for (int v = tid; v < nv; v += nt) x[v] = om * b[v] / diag(l, v);
         __syncthreads();
-        for (int v = tid; v < nv; v += nt) t[v] = x[v] + om * (b[v] - apply(l, x, v % nvx, v / nvx)) / diag(l, v);
-        __syncthreads();
-        // residual of the smoothed iterate into x (free until the post-smoothing)
-        for (int v = tid; v < nv; v += nt) x[v] = b[v] - apply(l, t, v % nvx, v / nvx);
+        for (int k = 1; k < nu; ++k) {
+            const double* src = (k & 1) ? x : t;
+            double* dst = (k & 1) ? t : x;
+            for (int v = tid; v < nv; v += nt) dst[v] = src[v] + om * (b[v] - apply(l, src, v % nvx, v / nvx)) / diag(l, v);
+            __syncthreads();
+        }
+        // residual of the pre-smoothed iterate into the other vector (free
+        // until the post-smoothing)
+        double* it = (nu & 1) ? x : t;
+        double* res = (nu & 1) ? t : x;
+        for (int v = tid; v < nv; v += nt) res[v] = b[v] - apply(l, it, v % nvx, v / nvx);
         __syncthreads();
         const int fnx = nvx, fny = lny[l], cnx = lnx[l + 1], cny = lny[l + 1];
         double* bc = Bv(l + 1);
@@ -3316,7 +3334,7 @@ __global__ __launch_bounds__(1024) void mg_vcycle_lds_kernel(BatchLaunch B, MGLa
                     if (fx < 0 || fx >= fnx) continue;
                     const double wx = mg_weight(fx, fnx, cx);
                     if (wx == 0.0) continue;
-                    s += wx * wy * x[fy * fnx + fx];
+                    s += wx * wy * res[fy * fnx + fx];
                 }
             }
             bc[c] = s;
@@ -3337,6 +3355,8 @@ __global__ __launch_bounds__(1024) void mg_vcycle_lds_kernel(BatchLaunch B, MGLa
     for (int l = lc - 1; l >= ls; --l) {
         const int fnx = lnx[l], fny = lny[l], nv = fnx * fny, cnx = lnx[l + 1];
         double *x = X(l), *t = Tv(l), *b = Bv(l);
+        double* it = (nu & 1) ? x : t;
+        double* other = (nu & 1) ? t : x;
         const double* xc = l + 1 == lc ? X(l + 1) : Tv(l + 1);
         for (int f = tid; f < nv; f += nt) {
             int x0, x1, y0, y1;
@@ -3347,13 +3367,15 @@ __global__ __launch_bounds__(1024) void mg_vcycle_lds_kernel(BatchLaunch B, MGLa
             if (x1 >= 0) s += wx1 * wy0 * xc[y0 * cnx + x1];
             if (y1 >= 0) s += wx0 * wy1 * xc[y1 * cnx + x0];
             if (x1 >= 0 && y1 >= 0) s += wx1 * wy1 * xc[y1 * cnx + x1];
-            t[f] += s;
+            it[f] += s;
         }
         __syncthreads();
-        for (int v = tid; v < nv; v += nt) x[v] = t[v] + om * (b[v] - apply(l, t, v % fnx, v / fnx)) / diag(l, v);
-        __syncthreads();
-        for (int v = tid; v < nv; v += nt) t[v] = x[v] + om * (b[v] - apply(l, x, v % fnx, v / fnx)) / diag(l, v);
-        __syncthreads();
+        for (int k = 0; k < nu; ++k) {
+            const double* src = (k & 1) ? other : it;
+            double* dst = (k & 1) ? it : other;
+            for (int v = tid; v < nv; v += nt) dst[v] = src[v] + om * (b[v] - apply(l, src, v % fnx, v / fnx)) / diag(l, v);
+            __syncthreads();
+        }
     }
     {
         const MGLevelDev& L = M.lev[ls];
@@ -3418,22 +3440,37 @@ hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStr
     const int top = M.ls < M.nlev - 1 ? M.ls : M.nlev - 1;
     if (init) hipLaunchKernelGGL(mg_corner_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M.corner);
     hipLaunchKernelGGL(mg_restrict0_kernel, grid(M.lev[0].nv), dim3(BT), 0, s, B, M, (const double*)M.corner);
+    // nu damped Jacobi steps before and after the coarse correction,
+    // alternating between x and t; the pre-smoothed iterate ends in x (nu
+    // odd) or t (nu even), the residual goes to the other one, and after the
+    // post-smoothing the level's result is in t either way
+    const int nu = M.nu;
     for (int l = 0; l < top; ++l) {
         const MGLevelDev& L = M.lev[l];
         hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 1, (const double*)L.x, L.x);
-        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.x, L.t);
-        // residual of the smoothed iterate into x (free until the post-smoothing)
-        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 2, (const double*)L.t, L.x);
-        hipLaunchKernelGGL(mg_restrict_kernel, grid(M.lev[l + 1].nv), dim3(BT), 0, s, B, M, l, (const double*)L.x);
+        for (int k = 1; k < nu; ++k) {
+            double* src = (k & 1) ? L.x : L.t;
+            hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)src,
+                               (k & 1) ? L.t : L.x);
+        }
+        double* it = (nu & 1) ? L.x : L.t;
+        double* other = (nu & 1) ? L.t : L.x;
+        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 2, (const double*)it, other);
+        hipLaunchKernelGGL(mg_restrict_kernel, grid(M.lev[l + 1].nv), dim3(BT), 0, s, B, M, l, (const double*)other);
     }
     if (M.ls < M.nlev)
         hipLaunchKernelGGL(mg_vcycle_lds_kernel, dim3(B.nprob), dim3(1024), M.lds, s, B, M);
     hipLaunchKernelGGL(mg_coarse_kernel, dim3(B.nprob), dim3(64), 0, s, B, M);
     for (int l = top - 1; l >= 0; --l) {
         const MGLevelDev& L = M.lev[l];
-        hipLaunchKernelGGL(mg_prolong_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, L.t);
-        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.t, L.x);
-        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)L.x, L.t);
+        double* it = (nu & 1) ? L.x : L.t;
+        hipLaunchKernelGGL(mg_prolong_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, it);
+        for (int k = 0; k < nu; ++k) {
+            const bool from_it = (k & 1) == 0;
+            double* src = from_it ? it : (it == L.x ? L.t : L.x);
+            double* dst = from_it ? (it == L.x ? L.t : L.x) : it;
+            hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)src, dst);
+        }
     }
     if (init) hipLaunchKernelGGL(mg_finish_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M, 1);
     return hipGetLastError();
