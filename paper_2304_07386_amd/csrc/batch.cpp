@@ -680,6 +680,7 @@ int batch_build(smm_batch* B) {
         B->mgl.coff = B->d_mg_coff;
         B->mgl.cinv = B->d_mg_cinv;
         B->mgl.omega = 2.0 / 3.0;
+        B->mgl.nu = MG_NU;
         B->mgl.corner = B->d_mg_corner;
         // first level from which every problem's remaining levels fit in the
         // LDS of one workgroup (three vectors per level)

@@ -172,6 +172,7 @@ struct MGLaunch {
     const int* coff;            // [nprob] offset of its dense coarsest inverse
     const double* cinv;
     double omega;               // Jacobi damping
+    int nu;                     // damped Jacobi steps before and after the coarse correction (>= 1)
     double* corner;             // [4][batch elements] corner sums of the residual
     int ls;                     // levels >= ls run in one workgroup per problem (nlev: none)
     size_t lds;                 // LDS bytes of that workgroup
