@@ -165,7 +165,7 @@ struct smm_batch {
     // (iterations in the chunk, per-problem tolerances on)
     bool use_graph = false;
     hipStream_t cap = nullptr;
-    std::map<std::tuple<int, bool, bool>, hipGraphExec_t> cg_graphs;
+    std::map<std::tuple<int, bool, bool, int>, hipGraphExec_t> cg_graphs;  // (chunk, tolerances, two-level, orders)
 };
 
 namespace {
@@ -190,6 +190,7 @@ BatchLaunch launch_desc(smm_batch* B) {
     L.g_elem = B->d_gelem;
     L.gpart = B->d_gpart;
     for (int k = 0; k < 7; ++k) L.g_nb0[k] = B->g_nb0[k];
+    L.order_mask = ~0;
     L.grouped = B->grouped ? 1 : 0;
     L.mg = B->use_mg ? 1 : 0;
     L.mg_corner = B->use_mg ? B->d_mg_corner : nullptr;
@@ -849,24 +850,32 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
         HIPCHK(c, hipMemcpyAsync(sc.data(), B->d_scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         bool all = true;
+        int mask = 0;  // orders with problems still iterating
         for (int b = 0; b < B->nprob; ++b) {
             if (!B->active[b]) continue;
             if (sc[16 * b + 6] != 0.0) return fail(c, SMM_EBREAKDOWN, "CG breakdown in problem " + std::to_string(b));
-            if (sc[16 * b + 4] == 0.0) all = false;
+            if (sc[16 * b + 4] == 0.0) {
+                all = false;
+                mask |= 1 << B->probs[b]->P.nb;
+            }
         }
         if (all || done_its >= max_inner) break;
         const int k = std::min(chunk, max_inner - done_its);
+        // the grouped kernels of orders whose problems have all converged are
+        // not launched (they would only check the flags and return)
+        BatchLaunch Lk = L;
+        Lk.order_mask = mask;
         if (B->use_graph) {
             // capture the chunk once on a private stream, then replay it on the
             // context's stream (kernel nodes only)
-            const auto key = std::make_tuple(k, L.ptol != nullptr, L.mg != 0);
+            const auto key = std::make_tuple(k, L.ptol != nullptr, L.mg != 0, mask);
             auto it = B->cg_graphs.find(key);
             if (it == B->cg_graphs.end()) {
                 if (!B->cap) HIPCHK(c, hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
                 hipGraph_t g = nullptr;
                 hipGraphExec_t ge = nullptr;
                 HIPCHK(c, hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
-                const hipError_t e1 = b_cg_iterations(L, k, B->cap, &B->mgl);
+                const hipError_t e1 = b_cg_iterations(Lk, k, B->cap, &B->mgl);
                 const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
                 if (e1 != hipSuccess || e2 != hipSuccess) {
                     if (g) (void)hipGraphDestroy(g);
@@ -879,11 +888,14 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
             }
             HIPCHK(c, hipGraphLaunch(it->second, c->stream));
         } else {
-            HIPCHK(c, b_cg_iterations(L, k, c->stream, &B->mgl));
+            HIPCHK(c, b_cg_iterations(Lk, k, c->stream, &B->mgl));
         }
         done_its += k;
         B->cg_batched_its += k;
-        chunk = std::min(chunk * 2, 64);
+        // convergence is checked between chunks: larger chunks cost fewer
+        // host round trips, smaller ones fewer iterations past the last
+        // problem's convergence
+        chunk = std::min(chunk * 2, 16);
     }
     its.assign(B->nprob, 0);
     for (int b = 0; b < B->nprob; ++b) its[b] = (int)sc[16 * b + 5];

@@ -2785,7 +2785,7 @@ __global__ __launch_bounds__(256, 2) void b_cg_k2(BatchLaunch B) {
 static void b_cg_k1_all(const BatchLaunch& B, hipStream_t s) {
     auto go = [&](auto kfn, int nb) {
         const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
-        if (ng > 0) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B);
+        if (ng > 0 && (B.order_mask >> nb & 1)) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B);
     };
     go(b_cg_k1<2>, 2);
     go(b_cg_k1<3>, 3);
@@ -2796,7 +2796,7 @@ static void b_cg_k1_all(const BatchLaunch& B, hipStream_t s) {
 static void b_cg_k2_all(const BatchLaunch& B, hipStream_t s) {
     auto go = [&](auto kfn, int nb) {
         const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
-        if (ng > 0) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B);
+        if (ng > 0 && (B.order_mask >> nb & 1)) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B);
     };
     go(b_cg_k2<2>, 2);
     go(b_cg_k2<3>, 3);
@@ -2965,7 +2965,8 @@ hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const
         if (B.grouped) {
             auto go = [&](auto kfn, int nb) {
                 const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
-                if (ng > 0) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B, Mv);
+                if (ng > 0 && (B.order_mask >> nb & 1))
+                    hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B, Mv);
             };
             go(b_cg_k3g<2>, 2);
             go(b_cg_k3g<3>, 3);

@@ -149,6 +149,7 @@ struct BatchLaunch {
     const int* g_elem;             // [ngroups][64]
     double* gpart;                 // [3][ngroups] per-group partial sums
     int g_nb0[7];                  // groups of order nb - 1 are [g_nb0[nb], g_nb0[nb + 1]) (nb = 2..5)
+    int order_mask;                // bit nb: the PCG iterations launch the grouped kernels of that order
     int grouped;                   // 1: PCG on the type groups, 0: per-node element blocks
     int mg;                        // 1: two-level preconditioner (r.z from b_mg_apply)
     double* mg_corner;             // two-level: [4][batch elements] corner sums of r, written by the r update
