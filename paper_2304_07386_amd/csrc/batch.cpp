@@ -48,6 +48,7 @@ struct PerProb {
     float *Pm32, *Px32, *Py32, *bx32, *by32;
     double* tab64;                   // operator rows in the batched sweep's layout
     float* tab32;
+    double *cgw = nullptr, *cgdc = nullptr;  // continuous-space preconditioner term
     uint8_t* mat;
     double* vdiff;
     float* feat0;
@@ -135,6 +136,8 @@ struct smm_batch {
     double* d_mg_A[MG_MAXLEV] = {};
     double *d_mg_x[MG_MAXLEV] = {}, *d_mg_t[MG_MAXLEV] = {}, *d_mg_b[MG_MAXLEV] = {};
     int *d_mg_lc = nullptr, *d_mg_coff = nullptr;
+    int *d_cg_blk2p = nullptr, *d_cg_blk0 = nullptr;  // continuous-space term: node blocks
+    std::vector<int> cg_blk2p, cg_blk0, cg_n;         // [blocks], [np], [np] nodes per problem
     double* d_mg_corner = nullptr;
     // Anderson mixing
     double *d_aapart = nullptr, *d_aadot = nullptr, *d_aacoef = nullptr;
@@ -408,6 +411,23 @@ int batch_build(smm_batch* B) {
     }
     pool.req(&B->d_mg_coff, sizeof(int) * np);
     pool.req(&B->d_mg_cinv, sizeof(double) * std::max(cinv_tot, 1));
+    // continuous-space term (orders >= 2, with the two-level preconditioner):
+    // the continuous Q_p grid of each problem, in blocks of 256 nodes
+    B->cg_blk2p.clear();
+    B->cg_blk0.assign(np, 0);
+    B->cg_n.assign(np, 0);
+    for (int b = 0; b < np; ++b) {
+        const Problem& P = B->probs[b]->P;
+        B->cg_blk0[b] = (int)B->cg_blk2p.size();
+        if (!B->mg_error.empty() || P.nb < 3) continue;
+        const int p = P.nb - 1;
+        B->cg_n[b] = (P.nx * p + 1) * (P.ny * p + 1);
+        for (int k = 0; k < (B->cg_n[b] + CG_BLOCK - 1) / CG_BLOCK; ++k) B->cg_blk2p.push_back(b);
+        pool.req(&B->pp[b].cgw, sizeof(double) * B->cg_n[b]);
+        pool.req(&B->pp[b].cgdc, sizeof(double) * B->cg_n[b]);
+    }
+    pool.req(&B->d_cg_blk2p, sizeof(int) * std::max<size_t>(B->cg_blk2p.size(), 1));
+    pool.req(&B->d_cg_blk0, sizeof(int) * np);
     for (int b = 0; b < np; ++b) pool.req(&B->pp[b].gll, sizeof(double) * B->probs[b]->P.nb);
     B->gll_host.assign(np, {});
     for (int b = 0; b < np; ++b) gauss_lobatto01(B->probs[b]->P.p, B->gll_host[b]);
@@ -682,6 +702,52 @@ int batch_build(smm_batch* B) {
         B->mgl.cinv = B->d_mg_cinv;
         B->mgl.omega = 2.0 / 3.0;
         B->mgl.nu = MG_NU;
+        // continuous-space term: D_c = diag(P_c^T A P_c) from the typed blocks
+        // (row-major on the host): each node's element copies contribute
+        // their own diagonal entries, and each face-neighbour pair of copies
+        // its coupling entry
+        for (int b = 0; b < np; ++b) {
+            if (!B->cg_n[b]) continue;
+            const Problem& P = B->probs[b]->P;
+            const int nb = P.nb, n = P.n, p = nb - 1, nx = P.nx, gx = nx * p + 1;
+            std::vector<double> dc((size_t)B->cg_n[b], 0.0);
+            auto node = [&](int K, int a) { return ((K / nx) * p + a / nb) * gx + (K % nx) * p + a % nb; };
+            const int dK[4] = {-nx, 1, nx, -1};
+            for (int K = 0; K < P.ne; ++K) {
+                const double* As = &P.t_ip_self[(size_t)P.sid[K] * n * n];
+                for (int a = 0; a < n; ++a) dc[node(K, a)] += As[(size_t)a * n + a];
+                for (int f = 0; f < 4; ++f) {
+                    const int t = P.nid[4 * K + f];
+                    if (t < 0) continue;
+                    const int N = K + dK[f];
+                    const double* An = &P.t_ip_nbr[(size_t)t * n * n];
+                    for (int k = 0; k < nb; ++k) {
+                        // face node k of K and the node of N at the same place
+                        int aK, aN;
+                        if (f == 0) { aK = k; aN = k + nb * p; }
+                        else if (f == 1) { aK = p + nb * k; aN = nb * k; }
+                        else if (f == 2) { aK = k + nb * p; aN = k; }
+                        else { aK = nb * k; aN = p + nb * k; }
+                        if (node(K, aK) != node(N, aN)) return fail(c, SMM_EHIP, "continuous-space node map");
+                        dc[node(K, aK)] += An[(size_t)aK * n + aN];
+                    }
+                }
+            }
+            for (double v : dc)
+                if (!(v > 0.0)) return fail(c, SMM_EHIP, "continuous-space diagonal not positive");
+            if ((rc = put(c, B->pp[b].cgdc, dc.data(), sizeof(double) * dc.size()))) return rc;
+        }
+        if (!B->cg_blk2p.empty() &&
+            (rc = put(c, B->d_cg_blk2p, B->cg_blk2p.data(), sizeof(int) * B->cg_blk2p.size())))
+            return rc;
+        if ((rc = put(c, B->d_cg_blk0, B->cg_blk0.data(), sizeof(int) * np))) return rc;
+        B->mgl.cg_blk2p = B->d_cg_blk2p;
+        B->mgl.cg_blk0 = B->d_cg_blk0;
+        B->mgl.cg_nblocks = (int)B->cg_blk2p.size();
+        for (int b = 0; b < np; ++b) {
+            B->hP[b].cgw = B->cg_n[b] ? B->pp[b].cgw : nullptr;
+            B->hP[b].cgdc = B->cg_n[b] ? B->pp[b].cgdc : nullptr;
+        }
         B->mgl.corner = B->d_mg_corner;
         // first level from which every problem's remaining levels fit in the
         // LDS of one workgroup (three vectors per level)

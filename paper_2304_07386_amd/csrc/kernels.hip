@@ -1770,6 +1770,13 @@ __device__ __forceinline__ double typed_row(const BProb& P, const double* x, int
     return v;
 }
 
+// node of the continuous Q_p grid ((nx p + 1) x (ny p + 1)) that DG node j of
+// element K sits on
+__device__ __forceinline__ int cg_node(const BProb& P, int K, int j) {
+    const int p = P.nb - 1, gx = P.nx * p + 1;
+    return ((K / P.nx) * p + j / P.nb) * gx + (K % P.nx) * p + j % P.nb;
+}
+
 __device__ __forceinline__ bool cg_skip(const BatchLaunch& B, int prob) {
     return !B.active[prob] || B.P[prob].scal[4] != 0.0;
 }
@@ -2818,6 +2825,13 @@ __global__ __launch_bounds__(BT) void b_cg_red2(BatchLaunch B, MGLaunch M) {
     if (cg_skip(B, prob)) return;
     const BProb& P = B.P[prob];
     double rzn = group_sum(B, P, 1, red);
+    if (B.mg && P.cgw) {
+        // r.(P_c w) = (P_c^T r).w = w D_c w
+        const int p = P.nb - 1, ncg = (P.nx * p + 1) * (P.ne / P.nx * p + 1);
+        double v = 0.0;
+        for (int k = threadIdx.x; k < ncg; k += BT) v += P.cgw[k] * P.cgdc[k] * P.cgw[k];
+        rzn += b_block_sum(v, red);
+    }
     if (B.mg) {
         const MGLevelDev& L = M.lev[0];
         const int nv = L.dims[2 * prob] * L.dims[2 * prob + 1];
@@ -2853,6 +2867,7 @@ __global__ __launch_bounds__(BT) void b_cg_k3(BatchLaunch B, MGLaunch M) {
         const double* xv = mg_x0(M, m.prob) + ey * nvx + ex;
         z += (1.0 - xa) * (1.0 - yb) * xv[0] + xa * (1.0 - yb) * xv[1] + (1.0 - xa) * yb * xv[nvx] +
              xa * yb * xv[nvx + 1];
+        if (P.cgw) z += P.cgw[cg_node(P, m.K, m.i)];
     }
     P.p[t] = z + P.scal[9] * P.p[t];
 }
@@ -2900,6 +2915,7 @@ __global__ __launch_bounds__(256) void b_cg_k3g(BatchLaunch B, MGLaunch M) {
                 const double* xv = x0 + V;
                 z += (1.0 - xa) * (1.0 - yb) * xv[0] + xa * (1.0 - yb) * xv[1] + (1.0 - xa) * yb * xv[nvx] +
                      xa * yb * xv[nvx + 1];
+                if (P.cgw) z += P.cgw[cg_node(P, K, j)];
             }
             st_at(pg, o, z + beta * ld_at(pg, o));
         }
@@ -2924,7 +2940,9 @@ hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s, const MGL
         hipLaunchKernelGGL(b_cg_init1, dim3(B.nblocks), dim3(BT), 0, s, B);
     hipLaunchKernelGGL(b_cg_init2, dim3(B.nblocks), dim3(BT), 0, s, B);
     if (B.mg) {
-        const hipError_t e = b_mg_apply(B, *M, true, s);
+        hipError_t e = b_cgl_apply(B, *M, s);
+        if (e != hipSuccess) return e;
+        e = b_mg_apply(B, *M, true, s);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(b_cg_red_init, dim3(B.nprob), dim3(BT), 0, s, B, tol);
@@ -2933,7 +2951,11 @@ hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s, const MGL
 
 hipError_t b_precond(const BatchLaunch& B, const MGLaunch* M, hipStream_t s) {
     hipLaunchKernelGGL(b_cg_init2, dim3(B.nblocks), dim3(BT), 0, s, B);
-    if (B.mg) return b_mg_apply(B, *M, true, s);
+    if (B.mg) {
+        const hipError_t e = b_cgl_apply(B, *M, s);
+        if (e != hipSuccess) return e;
+        return b_mg_apply(B, *M, true, s);
+    }
     return hipGetLastError();
 }
 
@@ -2957,7 +2979,9 @@ hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const
         else
             hipLaunchKernelGGL(b_cg_k2n, dim3(B.nblocks), dim3(BT), 0, s, B);
         if (B.mg) {
-            const hipError_t e = b_mg_apply(B, *M, false, s);
+            hipError_t e = b_cgl_apply(B, *M, s);
+            if (e != hipSuccess) return e;
+            e = b_mg_apply(B, *M, false, s);
             if (e != hipSuccess) return e;
         }
         const MGLaunch Mv = B.mg ? *M : MGLaunch{};
@@ -3423,8 +3447,9 @@ __global__ __launch_bounds__(BT) void mg_finish_kernel(BatchLaunch B, MGLaunch M
         const int a = m.i % P.nb, b = m.i / P.nb;
         const double xa = P.gll[a], yb = P.gll[b];
         const double* xv = x0 + o + ey * nvx + ex;
-        const double c = (1.0 - xa) * (1.0 - yb) * xv[0] + xa * (1.0 - yb) * xv[1] + (1.0 - xa) * yb * xv[nvx] +
-                         xa * yb * xv[nvx + 1];
+        double c = (1.0 - xa) * (1.0 - yb) * xv[0] + xa * (1.0 - yb) * xv[1] + (1.0 - xa) * yb * xv[nvx] +
+                   xa * yb * xv[nvx + 1];
+        if (P.cgw) c += P.cgw[cg_node(P, m.K, m.i)];
         const long t = (long)m.K * P.n + m.i;
         const double z = P.z[t] + c;
         P.z[t] = z;
@@ -3433,6 +3458,41 @@ __global__ __launch_bounds__(BT) void mg_finish_kernel(BatchLaunch B, MGLaunch M
     }
     rz = b_block_sum(rz, red);
     if (threadIdx.x == 0) B.part[(init ? 0 : 1) * B.nblocks + blockIdx.x] = rz;
+}
+
+// Continuous-space term of the two-level preconditioner (orders >= 2).  P_c
+// injects a continuous Q_p function (values at the Gauss-Lobatto nodes shared
+// across element faces) into the DG space; P_c^T r sums the residual over the
+// (up to four) element copies of a node.  w = D_c^-1 P_c^T r, D_c the diagonal
+// of P_c^T A P_c (host set-up), so the term adds P_c w to z.
+__global__ __launch_bounds__(BT) void cgl_kernel(BatchLaunch B, MGLaunch M) {
+    const int prob = M.cg_blk2p[blockIdx.x];
+    if (cg_skip(B, prob)) return;
+    const BProb& P = B.P[prob];
+    if (!P.cgw) return;
+    const int p = P.nb - 1, nx = P.nx, ny = P.ne / P.nx;
+    const int gx = nx * p + 1, gy = ny * p + 1;
+    const int i = (blockIdx.x - M.cg_blk0[prob]) * BT + threadIdx.x;
+    if (i >= gx * gy) return;
+    const int gi = i % gx, gj = i / gx;
+    double rc = 0.0;
+    for (int cy = 0; cy < 2; ++cy) {
+        const int ey = gj / p - cy;
+        if (ey < 0 || ey >= ny || (cy == 1 && gj % p != 0)) continue;
+        const int by = gj - ey * p;
+        for (int cx = 0; cx < 2; ++cx) {
+            const int ex = gi / p - cx;
+            if (ex < 0 || ex >= nx || (cx == 1 && gi % p != 0)) continue;
+            const int ax = gi - ex * p;
+            rc += P.r[(long)(ey * nx + ex) * P.n + ax + P.nb * by];
+        }
+    }
+    P.cgw[i] = rc / P.cgdc[i];
+}
+
+hipError_t b_cgl_apply(const BatchLaunch& B, const MGLaunch& M, hipStream_t s) {
+    if (M.cg_nblocks > 0) hipLaunchKernelGGL(cgl_kernel, dim3(M.cg_nblocks), dim3(BT), 0, s, B, M);
+    return hipGetLastError();
 }
 
 hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStream_t s) {

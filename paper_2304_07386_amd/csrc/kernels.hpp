@@ -126,6 +126,11 @@ struct BProb {
     const double* gll;                                      // [nb] Gauss-Lobatto points on [0,1]
     long e_off;                                             // first element in batch-wide element arrays
     double *aG, *aF;                                        // [3][L] Anderson history: G(X) and G(X) - X
+    // two-level preconditioner, continuous-space term (orders >= 2; null
+    // otherwise): w = D_c^-1 P_c^T r on the continuous Q_p nodes of the mesh,
+    // a (nx p + 1) x (ny p + 1) grid, D_c the diagonal of P_c^T A P_c
+    double* cgw;                                            // [ncg]
+    const double* cgdc;                                     // [ncg]
 };
 
 struct BatchLaunch {
@@ -177,6 +182,10 @@ struct MGLaunch {
     double* corner;             // [4][batch elements] corner sums of the residual
     int ls;                     // levels >= ls run in one workgroup per problem (nlev: none)
     size_t lds;                 // LDS bytes of that workgroup
+    // continuous-space term: blocks of 256 nodes of the Q_p grids, per problem
+    const int* cg_blk2p;        // [cg_nblocks] problem of each block
+    const int* cg_blk0;         // [nprob] first block of each problem
+    int cg_nblocks;
 };
 // allows the LDS size of the workgroup V-cycle kernel
 hipError_t mg_prepare(size_t lds);
@@ -186,6 +195,8 @@ hipError_t mg_prepare(size_t lds);
 // Without init (inside the PCG loop) the corner sums come from the r update
 // and z is left as D^-1 r: the iteration adds P0 x0 where it uses z.
 hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStream_t s);
+// w = D_c^-1 P_c^T r for every problem with the continuous-space term
+hipError_t b_cgl_apply(const BatchLaunch& B, const MGLaunch& M, hipStream_t s);
 
 hipError_t b_source(bool fp64, const BatchLaunch& B, bool delta, hipStream_t s);
 // Persistent batched sweep over (problem, direction) tasks.  `threads` is

@@ -11,6 +11,7 @@ struct Problem;
 constexpr int MG_MAX_COARSE = 16;  // unknowns of the dense coarsest solve
 constexpr size_t MG_LDS_CAP = 150 * 1024;  // LDS of the one-workgroup V-cycle on the coarse levels
 constexpr int MG_NU = 1;                   // damped Jacobi steps before and after each coarse correction
+constexpr int CG_BLOCK = 256;              // nodes per block of the continuous-space kernel (its block size)
 
 struct MGLevelHost {
     int nvx = 0, nvy = 0;

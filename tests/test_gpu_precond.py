@@ -3,11 +3,14 @@
 z = M^-1 r for a batch of problems of different sizes and orders:
 * block-Jacobi: z = D^-1 r with D the element diagonal blocks of the typed IP
   matrix;
-* two-level: z = D^-1 r + P0 V(P0^T r), V one V-cycle (one damped Jacobi
-  sweep before and one after the coarse correction, weight 2/3, the first
-  from zero; restriction the transpose of linear interpolation; dense solve on
-  the coarsest grid) on the level stencils of the host set-up (pinned in
-  test_mg_host.py).
+* two-level: z = D^-1 r + P_c D_c^-1 P_c^T r + P0 V(P0^T r).  P_c injects
+  the continuous Q_p functions (nodal values at the Gauss-Lobatto points,
+  shared across element faces) into the DG space, D_c is the diagonal of
+  P_c^T A P_c (built here from the dense A; orders >= 2 only); V is one
+  V-cycle (one damped Jacobi sweep before and one after the coarse
+  correction, weight 2/3, the first from zero; restriction the transpose of
+  linear interpolation; dense solve on the coarsest grid) on the level
+  stencils of the host set-up (pinned in test_mg_host.py).
 Bar: relative L2 1e-12 (FP64, only the summation order differs).
 """
 import numpy as np
@@ -69,7 +72,26 @@ def _emulate(hctx, wl, r, two_level):
         return x
 
     P0 = _p0(wl.nx, wl.ny, wl.p)
-    return z + P0 @ vcycle(0, P0.T @ r)
+    z = z + P0 @ vcycle(0, P0.T @ r)
+    if wl.p >= 2:
+        Pc = _pc(wl.nx, wl.ny, wl.p)
+        dc = np.diag(Pc.T @ A @ Pc)
+        z = z + Pc @ ((Pc.T @ r) / dc)
+    return z
+
+
+def _pc(nx, ny, p):
+    """Injection of the continuous Q_p space (nodes of a (nx p + 1) x (ny p + 1)
+    grid) into the DG space, element-major with nodes x fastest."""
+    nb, gx = p + 1, nx * p + 1
+    n = nb * nb
+    P = np.zeros((nx * ny * n, gx * (ny * p + 1)))
+    for K in range(nx * ny):
+        ex, ey = K % nx, K // nx
+        for b in range(nb):
+            for a in range(nb):
+                P[K * n + a + nb * b, (ey * p + b) * gx + ex * p + a] = 1.0
+    return P
 
 
 @pytest.mark.parametrize("precond", [0, 1], ids=["block_jacobi", "two_level"])
