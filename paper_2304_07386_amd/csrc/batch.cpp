@@ -137,6 +137,7 @@ struct smm_batch {
     double *d_mg_x[MG_MAXLEV] = {}, *d_mg_t[MG_MAXLEV] = {}, *d_mg_b[MG_MAXLEV] = {};
     int *d_mg_lc = nullptr, *d_mg_coff = nullptr;
     int *d_cg_blk2p = nullptr, *d_cg_blk0 = nullptr;  // continuous-space term: node blocks
+    double* d_cg_part = nullptr;                      // its per-block partial sums
     std::vector<int> cg_blk2p, cg_blk0, cg_n;         // [blocks], [np], [np] nodes per problem
     double* d_mg_corner = nullptr;
     // Anderson mixing
@@ -414,7 +415,7 @@ int batch_build(smm_batch* B) {
     // continuous-space term (orders >= 2, with the two-level preconditioner):
     // the continuous Q_p grid of each problem, in blocks of 256 nodes
     B->cg_blk2p.clear();
-    B->cg_blk0.assign(np, 0);
+    B->cg_blk0.assign(np + 1, 0);
     B->cg_n.assign(np, 0);
     for (int b = 0; b < np; ++b) {
         const Problem& P = B->probs[b]->P;
@@ -426,8 +427,10 @@ int batch_build(smm_batch* B) {
         pool.req(&B->pp[b].cgw, sizeof(double) * B->cg_n[b]);
         pool.req(&B->pp[b].cgdc, sizeof(double) * B->cg_n[b]);
     }
+    B->cg_blk0[np] = (int)B->cg_blk2p.size();
     pool.req(&B->d_cg_blk2p, sizeof(int) * std::max<size_t>(B->cg_blk2p.size(), 1));
-    pool.req(&B->d_cg_blk0, sizeof(int) * np);
+    pool.req(&B->d_cg_blk0, sizeof(int) * (np + 1));
+    pool.req(&B->d_cg_part, sizeof(double) * std::max<size_t>(B->cg_blk2p.size(), 1));
     for (int b = 0; b < np; ++b) pool.req(&B->pp[b].gll, sizeof(double) * B->probs[b]->P.nb);
     B->gll_host.assign(np, {});
     for (int b = 0; b < np; ++b) gauss_lobatto01(B->probs[b]->P.p, B->gll_host[b]);
@@ -740,9 +743,10 @@ int batch_build(smm_batch* B) {
         if (!B->cg_blk2p.empty() &&
             (rc = put(c, B->d_cg_blk2p, B->cg_blk2p.data(), sizeof(int) * B->cg_blk2p.size())))
             return rc;
-        if ((rc = put(c, B->d_cg_blk0, B->cg_blk0.data(), sizeof(int) * np))) return rc;
+        if ((rc = put(c, B->d_cg_blk0, B->cg_blk0.data(), sizeof(int) * (np + 1)))) return rc;
         B->mgl.cg_blk2p = B->d_cg_blk2p;
         B->mgl.cg_blk0 = B->d_cg_blk0;
+        B->mgl.cg_part = B->d_cg_part;
         B->mgl.cg_nblocks = (int)B->cg_blk2p.size();
         for (int b = 0; b < np; ++b) {
             B->hP[b].cgw = B->cg_n[b] ? B->pp[b].cgw : nullptr;

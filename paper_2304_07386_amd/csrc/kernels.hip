@@ -2826,10 +2826,9 @@ __global__ __launch_bounds__(BT) void b_cg_red2(BatchLaunch B, MGLaunch M) {
     const BProb& P = B.P[prob];
     double rzn = group_sum(B, P, 1, red);
     if (B.mg && P.cgw) {
-        // r.(P_c w) = (P_c^T r).w = w D_c w
-        const int p = P.nb - 1, ncg = (P.nx * p + 1) * (P.ne / P.nx * p + 1);
+        // r.(P_c w) = (P_c^T r).w, from the node kernel's block partials
         double v = 0.0;
-        for (int k = threadIdx.x; k < ncg; k += BT) v += P.cgw[k] * P.cgdc[k] * P.cgw[k];
+        for (int k = M.cg_blk0[prob] + threadIdx.x; k < M.cg_blk0[prob + 1]; k += BT) v += M.cg_part[k];
         rzn += b_block_sum(v, red);
     }
     if (B.mg) {
@@ -3465,29 +3464,52 @@ __global__ __launch_bounds__(BT) void mg_finish_kernel(BatchLaunch B, MGLaunch M
 // across element faces) into the DG space; P_c^T r sums the residual over the
 // (up to four) element copies of a node.  w = D_c^-1 P_c^T r, D_c the diagonal
 // of P_c^T A P_c (host set-up), so the term adds P_c w to z.
+template <int PO>
+__device__ __forceinline__ double cgl_node(const BProb& P, int i, int nx, int ny, int gx) {
+    // PO = p: the divisions by the order are by a constant
+    const int gi = i % gx, gj = i / gx;
+    const auto rg = as_global((const double*)P.r);
+    double rc = 0.0;
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy) {
+        const int ey = gj / PO - cy;
+        if (ey < 0 || ey >= ny || (cy == 1 && gj % PO != 0)) continue;
+        const int by = gj - ey * PO;
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+            const int ex = gi / PO - cx;
+            if (ex < 0 || ex >= nx || (cx == 1 && gi % PO != 0)) continue;
+            const int ax = gi - ex * PO;
+            rc += ld_at(rg, (unsigned)((ey * nx + ex) * (PO + 1) * (PO + 1) + ax + (PO + 1) * by));
+        }
+    }
+    return rc;
+}
+
+// w = D_c^-1 P_c^T r per node, and per block of nodes the partial sum of
+// (P_c^T r).w, summed per problem (in block order) by the r.z reduction
 __global__ __launch_bounds__(BT) void cgl_kernel(BatchLaunch B, MGLaunch M) {
+    __shared__ double red[BT];
     const int prob = M.cg_blk2p[blockIdx.x];
-    if (cg_skip(B, prob)) return;
+    if (cg_skip(B, prob)) return;  // block-uniform
     const BProb& P = B.P[prob];
-    if (!P.cgw) return;
     const int p = P.nb - 1, nx = P.nx, ny = P.ne / P.nx;
     const int gx = nx * p + 1, gy = ny * p + 1;
     const int i = (blockIdx.x - M.cg_blk0[prob]) * BT + threadIdx.x;
-    if (i >= gx * gy) return;
-    const int gi = i % gx, gj = i / gx;
-    double rc = 0.0;
-    for (int cy = 0; cy < 2; ++cy) {
-        const int ey = gj / p - cy;
-        if (ey < 0 || ey >= ny || (cy == 1 && gj % p != 0)) continue;
-        const int by = gj - ey * p;
-        for (int cx = 0; cx < 2; ++cx) {
-            const int ex = gi / p - cx;
-            if (ex < 0 || ex >= nx || (cx == 1 && gi % p != 0)) continue;
-            const int ax = gi - ex * p;
-            rc += P.r[(long)(ey * nx + ex) * P.n + ax + P.nb * by];
+    double part = 0.0;
+    if (i < gx * gy) {
+        double rc;
+        switch (p) {
+            case 2: rc = cgl_node<2>(P, i, nx, ny, gx); break;
+            case 3: rc = cgl_node<3>(P, i, nx, ny, gx); break;
+            default: rc = cgl_node<4>(P, i, nx, ny, gx); break;
         }
+        const double w = rc / P.cgdc[i];
+        P.cgw[i] = w;
+        part = rc * w;
     }
-    P.cgw[i] = rc / P.cgdc[i];
+    part = b_block_sum(part, red);
+    if (threadIdx.x == 0) M.cg_part[blockIdx.x] = part;
 }
 
 hipError_t b_cgl_apply(const BatchLaunch& B, const MGLaunch& M, hipStream_t s) {

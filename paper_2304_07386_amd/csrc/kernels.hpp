@@ -184,7 +184,8 @@ struct MGLaunch {
     size_t lds;                 // LDS bytes of that workgroup
     // continuous-space term: blocks of 256 nodes of the Q_p grids, per problem
     const int* cg_blk2p;        // [cg_nblocks] problem of each block
-    const int* cg_blk0;         // [nprob] first block of each problem
+    const int* cg_blk0;         // [nprob + 1] first block of each problem
+    double* cg_part;            // [cg_nblocks] per-block partial sums of (P_c^T r).w
     int cg_nblocks;
 };
 // allows the LDS size of the workgroup V-cycle kernel
