@@ -11,7 +11,8 @@ Modules
   quadrature  level-symmetric S_N sets; Gauss-Legendre / Gauss-Lobatto rules
   fem         Q_p nodal basis, Q_m mesh map, element and face data (Sec. 3)
   transport   upwind DG sweep and angular moments / SMM closures (Sec. 4)
-  smm         interior-penalty SMM moment system and the fixed point (Sec. 2.3, 5.1)
+  smm         interior-penalty and continuous (CG) SMM moment systems and the
+              fixed point (Sec. 2.3, 5.1)
   cnn         plain convolutional network forward/backward for the warm start
 
 Functions whose result the tests cannot tie to the paper or to mathematics

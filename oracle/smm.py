@@ -9,6 +9,11 @@
 * The reduced fixed point X = G(X), G(X) = D^{-1} b(L^{-1}(sigma_s/(4 pi) X + q))
   (eq. moment:smm_fp), iterated as X^{k+1} = G(X^k) (eq. fixed-point) until
   the relative max-norm of the change falls below a tolerance.
+* The continuous finite element (CG) SMM moment system (Sec. 5.1): the same
+  forms with test and trial functions restricted to the continuous space V_p.
+  Jumps of V_p functions vanish on interior faces, so every interior-face term
+  that carries [u] or [varphi] drops out; the term {grad u / sigma_t}.[T n]
+  stays because T is discontinuous.  Selected by ``disc="cg"``.
 * Extra modes used only to pin the oracle: plain source iteration on the
   transport equation, a Krylov solve of the DG S_N system with scattering, and
   the fixed point found as the solution of the linear system X = G(X).
@@ -38,6 +43,7 @@ class OracleProblem:
     q: np.ndarray                 # nodal source per steradian: [ne, n] or [nd, ne, n]
     psibar: np.ndarray | None     # [n_bf, nq, nd] or None (vacuum)
     kappa_scale: float = 1.0
+    disc: str = "ip"              # moment discretisation: "ip" (Y_p) or "cg" (V_p)
     cache: dict = field(default_factory=dict)
 
     @property
@@ -49,9 +55,12 @@ class OracleProblem:
         return (self.mesh.p + 1) ** 2
 
 
-def make_problem(wl, kappa_scale: float = 1.0) -> OracleProblem:
+def make_problem(wl, kappa_scale: float = 1.0, disc: str = "ip") -> OracleProblem:
     """Build the oracle's view of a workload (mesh data, S_N set, nodal
-    source, inflow at boundary face points)."""
+    source, inflow at boundary face points).  ``disc`` picks the moment
+    discretisation: "ip" (interior penalty, Y_p) or "cg" (continuous, V_p)."""
+    if disc not in ("ip", "cg"):
+        raise ValueError(disc)
     mesh = fem.build_mesh(wl.ctrl, wl.nx, wl.ny, wl.m, wl.p)
     omega, w = level_symmetric_2d(wl.sn)
     ne, n = wl.nx * wl.ny, (wl.p + 1) ** 2
@@ -62,7 +71,7 @@ def make_problem(wl, kappa_scale: float = 1.0) -> OracleProblem:
         q = np.repeat(np.asarray(wl.q_elem, dtype=float)[:, None], n, axis=1)
     psibar = transport.inflow_at_points(mesh, omega, wl.inflow)
     return OracleProblem(mesh, omega, w, np.asarray(wl.sigma_t, float),
-                         np.asarray(wl.sigma_s, float), q, psibar, kappa_scale)
+                         np.asarray(wl.sigma_s, float), q, psibar, kappa_scale, disc)
 
 
 # ----------------------------------------------------------------------------
@@ -220,16 +229,67 @@ def rhs_correction(prob: OracleProblem, T: np.ndarray, beta: np.ndarray) -> np.n
 
 
 # ----------------------------------------------------------------------------
+# Continuous (CG) moment system: test and trial spaces V_p (Sec. 5.1)
+# ----------------------------------------------------------------------------
+
+def cg_space(mesh) -> sp.csr_matrix:
+    """P_c [ne*n, nc]: the DG nodal values of the continuous function with
+    unknowns c.  V_p is the subspace of Y_p whose members are continuous
+    (Sec. 3.3); with a nodal Gauss-Lobatto basis a member of Y_p is
+    continuous exactly when the DG nodes of neighbouring elements that sit at
+    the same point carry the same value, so V_p has one unknown per distinct
+    node position.  The positions are matched geometrically (within 1e-10 of
+    the domain size)."""
+    from scipy.sparse.csgraph import connected_components
+    from scipy.spatial import cKDTree
+    x = mesh.xnode.reshape(-1, 2)
+    N = len(x)
+    tol = 1e-10 * max(np.ptp(x[:, 0]), np.ptp(x[:, 1]), 1e-300)
+    pairs = cKDTree(x).query_pairs(tol, output_type="ndarray")
+    G = sp.csr_matrix((np.ones(len(pairs)), (pairs[:, 0], pairs[:, 1])), shape=(N, N))
+    nc, label = connected_components(G, directed=False)
+    return sp.csr_matrix((np.ones(N), (np.arange(N), label)), shape=(N, nc))
+
+
+def cg_matrix(prob: OracleProblem) -> sp.csr_matrix:
+    """The CG SMM bilinear form on V_p: the IP form with both arguments
+    restricted to V_p, A_c = P_c^T A_IP P_c."""
+    Pc = cg_space(prob.mesh)
+    return (Pc.T @ ip_matrix(prob) @ Pc).tocsr()
+
+
+# ----------------------------------------------------------------------------
 # Fixed point
 # ----------------------------------------------------------------------------
 
 def _lhs_factor(prob: OracleProblem):
+    """Factorisation of the moment system of the problem's discretisation and
+    its fixed right-hand side (in Y_p).  The moment solve maps a Y_p
+    right-hand side b to the DG vector of the solution: A_IP^-1 b for IP,
+    P_c (P_c^T A_IP P_c)^-1 P_c^T b for CG."""
     if "lu" not in prob.cache:
-        A = ip_matrix(prob).tocsc()
+        if prob.disc == "cg":
+            Pc = cg_space(prob.mesh)
+            A = cg_matrix(prob).tocsc()
+            lu = spla.splu(A)
+            prob.cache["lu"] = _Restricted(lu, Pc)
+        else:
+            A = ip_matrix(prob).tocsc()
+            prob.cache["lu"] = spla.splu(A)
         prob.cache["A"] = A
-        prob.cache["lu"] = spla.splu(A)
         prob.cache["bfix"] = rhs_fixed(prob)
     return prob.cache["lu"], prob.cache["bfix"]
+
+
+class _Restricted:
+    """Moment solve on V_p: restrict the Y_p right-hand side by P_c^T, solve,
+    and return the DG nodal values P_c c."""
+
+    def __init__(self, lu, Pc):
+        self.lu, self.Pc = lu, Pc
+
+    def solve(self, b):
+        return self.Pc @ self.lu.solve(self.Pc.T @ b)
 
 
 def scattering_source(prob: OracleProblem, varphi: np.ndarray) -> np.ndarray:
