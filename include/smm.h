@@ -73,6 +73,10 @@ extern "C" {
 #define SMM_PRECOND_BJ 0
 #define SMM_PRECOND_TWOLEVEL 1
 
+/* moment-system discretisation (Sec. 5.1) */
+#define SMM_DISC_IP 0   /* interior penalty on the DG space Y_p (eq. ipsmm) */
+#define SMM_DISC_CG 1   /* continuous finite elements: the same forms on V_p */
+
 /* initial guess for smm_solve */
 #define SMM_START_ZERO 0
 #define SMM_START_DIFFUSION 1 /* moment system with zero transport corrections */
@@ -129,6 +133,12 @@ typedef struct {
                             (r_0 = 1; per problem in a batch), and the solves that
                             build a diffusion or learned start at
                             max(inner_tol, inner_adapt); 0: always inner_tol */
+    int discretization;  /* SMM_DISC_IP (default) or SMM_DISC_CG.  SMM_DISC_CG solves the
+                            continuous moment system of Sec. 5.1 (one unknown per node of the
+                            (nx p + 1) x (ny p + 1) grid of V_p) by FP64 Jacobi-preconditioned
+                            CG on the per-element path of smm_solve; varphi is returned at the
+                            DG nodes (continuous).  `precond` does not apply; Anderson mixing
+                            and batches return SMM_EUNSUPPORTED */
 } smm_solve_opts;
 
 typedef struct {
@@ -215,6 +225,20 @@ int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, doubl
  * dense row-major [N][N] with N = n_elem*n_node (small problems only), and
  * the fixed right-hand side [N]. */
 int smm_debug_ip_dense(const smm_problem* prob, double* A, double* b_fixed);
+
+/* Host-only inspection of the continuous (CG) moment system of Sec. 5.1.
+ * Writes *nc (continuous unknowns) and *nnz; when rowptr is non-NULL also
+ * the CSR matrix A_c (rowptr[nc + 1], col[nnz], val[nnz], columns ascending)
+ * and map[n_elem * n_node], the continuous unknown of each DG node (so the DG
+ * values of a continuous vector c are c[map[t]]).  All arrays are host memory
+ * owned by the caller. */
+int smm_debug_cg_system(smm_problem* prob, int* nc, int* nnz, int* rowptr, int* col, double* val, int* map);
+/* y = A_c x with the device product kernel of the CG moment solve; x and y are
+ * host arrays of nc doubles (nc from smm_debug_cg_system). */
+int smm_debug_cg_spmv(smm_problem* prob, const double* x, double* y);
+/* Average time in ms of `reps` back-to-back launches of that product kernel
+ * on the context stream (HIP events), x = 1. */
+int smm_time_cg_spmv(smm_problem* prob, int reps, double* ms_avg);
 
 /* Sweep kernel selection: 0 = automatic (tabulated operators on uniform
  * Cartesian meshes, otherwise per-element assembly and elimination);

@@ -32,6 +32,8 @@ def build(verbose: bool = True) -> str:
         ("batch.cpp", ["-x", "hip", *DEVICE_FLAGS]),
         ("cnn.cpp", ["-x", "hip", *DEVICE_FLAGS]),
         ("mg.cpp", ["-x", "hip", *DEVICE_FLAGS]),
+        ("cg_smm.cpp", ["-x", "hip", *DEVICE_FLAGS, "-ffp-contract=off"]),
+        ("cg_smm.hip", DEVICE_FLAGS),
         ("kernels.hip", DEVICE_FLAGS),
         ("cnn_kernels.hip", DEVICE_FLAGS),
     )

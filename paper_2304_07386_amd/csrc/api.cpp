@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "api_internal.hpp"
+#include "cg_smm.hpp"
 
 using namespace smm;
 
@@ -171,6 +172,7 @@ int smm_set_materials(smm_problem* prob, const double* sigma_t, const double* si
     P.sigma_s.assign(sigma_s, sigma_s + P.ne);
     P.have_mat = true;
     P.lhs_ready = false;
+    P.cg_ready = false;
     P.rhs_fixed_ready = false;
     P.typed_ready = false;
     P.Pm.clear();
@@ -247,6 +249,7 @@ void smm_default_opts(smm_solve_opts* o) {
     o->inner_adapt = 0.0;
     o->precond = SMM_PRECOND_BJ;
     o->anderson = 0;
+    o->discretization = SMM_DISC_IP;
 }
 
 }  // extern "C"
@@ -501,6 +504,77 @@ static CgState cg_state(smm_problem* pr) {
 
 // Solve the IP system for b (already in D.b) starting from D.x.  Returns the
 // CG iteration count in *its.
+// Continuous (CG) moment system on the device: host assembly on first use or
+// after a material change, then upload.
+static int ensure_cg(smm_problem* pr) {
+    Problem& P = pr->P;
+    Dev& D = pr->D;
+    smm_ctx* c = P.ctx;
+    if (!P.cg_ready) {
+        assemble_cg(P);
+        D.cg_dirty = true;
+    }
+    if (D.cg_dirty) {
+        UP(D.cg_rowptr, P.cg_rowptr);
+        UP(D.cg_col, P.cg_col);
+        UP(D.cg_val, P.cg_val);
+        UP(D.cg_dinv, P.cg_dinv);
+        UP(D.cg_tab, P.cg_tab);
+        UP(D.cg_map, P.cg_map);
+        const size_t nc = (size_t)P.cg_nc;
+        double** vecs[] = {&D.cg_b, &D.cg_x, &D.cg_r, &D.cg_z, &D.cg_p, &D.cg_q};
+        int rc;
+        for (double** v : vecs)
+            if ((rc = alloc(c, D, v, sizeof(double) * nc))) return rc;
+        const size_t vb = (nc + 255) / 256, sb = (nc + CGS_SPMV_ROWS - 1) / CGS_SPMV_ROWS;
+        if ((rc = alloc(c, D, &D.cg_part, sizeof(double) * (sb + 3 * vb)))) return rc;
+        if ((rc = alloc(c, D, &D.cg_scal, sizeof(double) * 16))) return rc;
+        D.cg_dirty = false;
+    }
+    return SMM_OK;
+}
+
+static CgsArgs cgs_args(smm_problem* pr) {
+    Problem& P = pr->P;
+    Dev& D = pr->D;
+    CgsArgs a{};
+    a.nc = P.cg_nc;
+    a.L = (long)P.ne * P.n;
+    a.rowptr = D.cg_rowptr; a.col = D.cg_col; a.val = D.cg_val; a.dinv = D.cg_dinv;
+    a.tab = D.cg_tab; a.map = D.cg_map;
+    a.b = D.cg_b; a.x = D.cg_x; a.r = D.cg_r; a.z = D.cg_z; a.p = D.cg_p; a.q = D.cg_q;
+    a.part = D.cg_part; a.scal = D.cg_scal;
+    a.vblocks = (P.cg_nc + 255) / 256;
+    a.sblocks = (P.cg_nc + CGS_SPMV_ROWS - 1) / CGS_SPMV_ROWS;
+    return a;
+}
+
+// The CG moment solve: restrict the DG right-hand side D.b to V_p, start from
+// the DG iterate in D.x (continuous after the first CG solve, so its node
+// values are exact), Jacobi-PCG, and return the DG values P_c c in D.x.
+static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its) {
+    Dev& D = pr->D;
+    smm_ctx* c = pr->P.ctx;
+    const CgsArgs a = cgs_args(pr);
+    HIPCHK(c, cgs_gather(a, D.b, c->stream));
+    HIPCHK(c, cgs_pick(a, D.x, c->stream));
+    HIPCHK(c, cgs_start(a, tol, c->stream));
+    double sc[8];
+    int chunk = 4, done = 0;
+    while (true) {
+        HIPCHK(c, hipMemcpyAsync(sc, D.cg_scal, sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        done = (int)sc[5];
+        if (sc[6] != 0.0) return fail(c, SMM_EBREAKDOWN, "CG breakdown (continuous moment system)");
+        if (sc[4] != 0.0 || done >= max_inner) break;
+        HIPCHK(c, cgs_iterations(a, std::min(chunk, max_inner - done), c->stream));
+        chunk = std::min(chunk * 2, 64);
+    }
+    HIPCHK(c, cgs_scatter(a, D.x, c->stream));
+    *its = done;
+    return SMM_OK;
+}
+
 static int moment_solve(smm_problem* pr, double tol, int max_inner, int* its) {
     Problem& P = pr->P;
     Dev& D = pr->D;
@@ -528,7 +602,7 @@ static int moment_solve(smm_problem* pr, double tol, int max_inner, int* its) {
 // One evaluation of G from D.varphi into D.x (b, closures, moments updated).
 // psi_cur / psi_prev are sweep buffers; delta mode sweeps sigma_s/(4pi)(varphi - varphi_prev).
 static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, double inner_tol, int max_inner,
-                  int* cg_its) {
+                  int* cg_its, bool cgdisc = false) {
     Problem& P = pr->P;
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
@@ -563,7 +637,7 @@ static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, d
                          c->stream));
     // moment solve (a6), warm-started from the current iterate
     HIPCHK(c, hipMemcpyAsync(D.x, D.varphi, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
-    return moment_solve(pr, inner_tol, max_inner, cg_its);
+    return cgdisc ? cg_moment_solve(pr, inner_tol, max_inner, cg_its) : moment_solve(pr, inner_tol, max_inner, cg_its);
 }
 
 extern "C" {
@@ -578,11 +652,16 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     smm_ctx* c = P.ctx;
     if (c->device < 0) return fail(c, SMM_ESTATE, "host-only context");
     if (!P.have_mat) return fail(c, SMM_ESTATE, "materials not set");
+    if (o.discretization != SMM_DISC_IP && o.discretization != SMM_DISC_CG)
+        return fail(c, SMM_EINVAL, "smm_solve: discretization must be SMM_DISC_IP or SMM_DISC_CG");
+    const bool cgdisc = o.discretization == SMM_DISC_CG;
+    if (cgdisc && o.anderson != 0)
+        return fail(c, SMM_EUNSUPPORTED, "smm_solve: Anderson mixing runs on the typed path, IP discretisation only");
     if (o.anderson != 0 && !(o.moment_path == 0 && typed_applicable(P) && D.force_general != 1))
         return fail(c, SMM_EUNSUPPORTED, "smm_solve: Anderson mixing needs the typed (batched) path");
     if (o.start < SMM_START_ZERO || o.start > SMM_START_GIVEN)
         return fail(c, SMM_EINVAL, "smm_solve: start must be ZERO, DIFFUSION or GIVEN (the learned start needs a batch)");
-    if (o.moment_path == 0 && typed_applicable(P) && D.force_general != 1) {
+    if (!cgdisc && o.moment_path == 0 && typed_applicable(P) && D.force_general != 1) {
         const int r = batch_solve_single(prob, o, varphi0, info);
         D.last_typed = (r == SMM_OK || r == SMM_ENOCONV);
         return r;
@@ -591,6 +670,7 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     auto t0 = std::chrono::steady_clock::now();
     int rc = ensure_device(prob, true, D.force_general == 1);
     if (rc) return rc;
+    if (cgdisc && (rc = ensure_cg(prob))) return rc;
     auto t1 = std::chrono::steady_clock::now();
     const long L = (long)P.ne * P.n;
     const bool fp64 = o.precision == SMM_FP64;
@@ -602,7 +682,9 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     } else if (o.start == SMM_START_DIFFUSION) {
         HIPCHK(c, hipMemcpyAsync(D.b, D.bfix, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemsetAsync(D.x, 0, sizeof(double) * L, c->stream));
-        if ((rc = moment_solve(prob, o.inner_tol, o.max_inner, &its))) return rc;
+        rc = cgdisc ? cg_moment_solve(prob, o.inner_tol, o.max_inner, &its)
+                    : moment_solve(prob, o.inner_tol, o.max_inner, &its);
+        if (rc) return rc;
         HIPCHK(c, hipMemcpyAsync(D.varphi, D.x, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
     } else {
         HIPCHK(c, hipMemsetAsync(D.varphi, 0, sizeof(double) * L, c->stream));
@@ -616,7 +698,7 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     for (it = 1; it <= o.max_outer; ++it) {
         int cgi = 0;
         const double tol_k = o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt * r_prev) : o.inner_tol;
-        if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, tol_k, o.max_inner, &cgi))) return rc;
+        if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, tol_k, o.max_inner, &cgi, cgdisc))) return rc;
         cg_total += cgi;
         cg_max = std::max(cg_max, cgi);
         // residual (a7)
@@ -713,6 +795,69 @@ int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, doubl
     D.have_outputs = true;
     D.last_varphi = D.x;
     D.last_typed = false;
+    return SMM_OK;
+}
+
+int smm_debug_cg_system(smm_problem* prob, int* nc, int* nnz, int* rowptr, int* col, double* val, int* map) {
+    if (!prob || !nc || !nnz) return SMM_EINVAL;
+    int rc = ensure_host(prob);
+    if (rc) return rc;
+    Problem& P = prob->P;
+    if (!P.cg_ready) {
+        assemble_cg(P);
+        prob->D.cg_dirty = true;
+    }
+    *nc = P.cg_nc;
+    *nnz = (int)P.cg_col.size();
+    if (rowptr) {
+        if (!col || !val || !map) return fail(P.ctx, SMM_EINVAL, "smm_debug_cg_system: col, val and map needed");
+        std::memcpy(rowptr, P.cg_rowptr.data(), sizeof(int) * P.cg_rowptr.size());
+        std::memcpy(col, P.cg_col.data(), sizeof(int) * P.cg_col.size());
+        std::memcpy(val, P.cg_val.data(), sizeof(double) * P.cg_val.size());
+        std::memcpy(map, P.cg_map.data(), sizeof(int) * P.cg_map.size());
+    }
+    return SMM_OK;
+}
+
+int smm_debug_cg_spmv(smm_problem* prob, const double* x, double* y) {
+    if (!prob || !x || !y) return SMM_EINVAL;
+    int rc = ensure_device(prob, true, prob->D.force_general == 1);
+    if (rc) return rc;
+    if ((rc = ensure_cg(prob))) return rc;
+    smm_ctx* c = prob->P.ctx;
+    Dev& D = prob->D;
+    const CgsArgs a = cgs_args(prob);
+    const size_t bytes = sizeof(double) * (size_t)a.nc;
+    HIPCHK(c, hipMemcpyAsync(D.cg_p, x, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, cgs_spmv(a, D.cg_p, D.cg_q, c->stream));
+    HIPCHK(c, hipMemcpyAsync(y, D.cg_q, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SMM_OK;
+}
+
+int smm_time_cg_spmv(smm_problem* prob, int reps, double* ms_avg) {
+    if (!prob || !ms_avg || reps < 1) return SMM_EINVAL;
+    int rc = ensure_device(prob, true, prob->D.force_general == 1);
+    if (rc) return rc;
+    if ((rc = ensure_cg(prob))) return rc;
+    smm_ctx* c = prob->P.ctx;
+    Dev& D = prob->D;
+    const CgsArgs a = cgs_args(prob);
+    std::vector<double> ones((size_t)a.nc, 1.0);
+    HIPCHK(c, hipMemcpyAsync(D.cg_p, ones.data(), sizeof(double) * ones.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, cgs_spmv(a, D.cg_p, D.cg_q, c->stream));  // warm-up
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int k = 0; k < reps; ++k) HIPCHK(c, cgs_spmv(a, D.cg_p, D.cg_q, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_avg = ms / reps;
     return SMM_OK;
 }
 

@@ -53,6 +53,11 @@ struct Dev {
     void* psi[2] = {nullptr, nullptr};  // sweep outputs (sized for fp64)
     double *mom = nullptr, *mom_acc = nullptr, *T = nullptr, *beta = nullptr;
     int cg_blocks = 0, r_blocks = 0;
+    // continuous (CG) moment system
+    int *cg_rowptr = nullptr, *cg_col = nullptr, *cg_tab = nullptr, *cg_map = nullptr;
+    double *cg_val = nullptr, *cg_dinv = nullptr, *cg_b = nullptr, *cg_x = nullptr, *cg_r = nullptr,
+           *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_part = nullptr, *cg_scal = nullptr;
+    bool cg_dirty = true;   // host CG system rebuilt since the last upload
     bool have_outputs = false;
     bool last_typed = false;       // last solve ran on the typed (batched) path
     bool gen_sweep_built = false;  // per-element sweep data uploaded

@@ -1346,6 +1346,8 @@ int smm_batch_solve(smm_batch* batch, const smm_solve_opts* opts, const double* 
     smm_solve_opts o;
     smm_default_opts(&o);
     if (opts) o = *opts;
+    if (o.discretization != SMM_DISC_IP)
+        return fail(batch->ctx, SMM_EUNSUPPORTED, "smm_batch_solve: batches solve the IP moment system only");
     return batch_solve(batch, o, varphi0, info);
 }
 

@@ -668,36 +668,50 @@ static void face_values(const Problem& P, int f, int q, std::vector<double>& u) 
     }
 }
 
+// Element terms of the moment system's bilinear form, added into the n x n
+// block blk: int grad u . D grad phi + int sigma_a u phi over element K.
+void add_volume_block(const Problem& P, int K, double* blk) {
+    const int n = P.n, Q = P.nq * P.nq;
+    const double DK = 1.0 / (3.0 * P.sigma_t[K]);
+    const double saK = P.sigma_t[K] - P.sigma_s[K];
+    for (int Qi = 0; Qi < Q; ++Qi) {
+        const double wJ = P.vol_wJ[(size_t)K * Q + Qi];
+        const double* G = &P.vol_grad[((size_t)K * Q + Qi) * n * 2];
+        const double* U = &P.vol_U[Qi * n];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                blk[i * n + j] += wJ * (DK * (G[i * 2] * G[j * 2] + G[i * 2 + 1] * G[j * 2 + 1]) + saK * U[i] * U[j]);
+    }
+}
+
+// Marshak boundary term int E_b0 u phi on boundary face f of element K.
+void add_boundary_block(const Problem& P, int K, int f, double* blk) {
+    const int n = P.n, nq = P.nq;
+    std::vector<double> uK;
+    const double e = (f == 1 || f == 3) ? P.eb0x : P.eb0y;
+    for (int q = 0; q < nq; ++q) {
+        face_values(P, f, q, uK);
+        const double s = P.dsw[((size_t)K * 4 + f) * nq + q] * e;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) blk[i * n + j] += s * uK[i] * uK[j];
+    }
+}
+
 void assemble_ip(Problem& P) {
-    const int n = P.n, nq = P.nq, ne = P.ne, Q = nq * nq;
+    const int n = P.n, nq = P.nq, ne = P.ne;
     P.bsr_col.assign((size_t)ne * 5, -1);
     P.bsr_val.assign((size_t)ne * 5 * n * n, 0.0);
     std::vector<double> uK, uN;
     const double pp = (P.p + 1.0) * (P.p + 1.0);
     for (int K = 0; K < ne; ++K) {
         const double DK = 1.0 / (3.0 * P.sigma_t[K]);
-        const double saK = P.sigma_t[K] - P.sigma_s[K];
         double* blk0 = &P.bsr_val[((size_t)K * 5) * n * n];
         P.bsr_col[K * 5] = K;
-        for (int Qi = 0; Qi < Q; ++Qi) {
-            const double wJ = P.vol_wJ[(size_t)K * Q + Qi];
-            const double* G = &P.vol_grad[((size_t)K * Q + Qi) * n * 2];
-            const double* U = &P.vol_U[Qi * n];
-            for (int i = 0; i < n; ++i)
-                for (int j = 0; j < n; ++j)
-                    blk0[i * n + j] += wJ * (DK * (G[i * 2] * G[j * 2] + G[i * 2 + 1] * G[j * 2 + 1]) +
-                                             saK * U[i] * U[j]);
-        }
+        add_volume_block(P, K, blk0);
         for (int f = 0; f < 4; ++f) {
             const int N = P.nbr[K * 4 + f];
             if (N < 0) {
-                const double e = (f == 1 || f == 3) ? P.eb0x : P.eb0y;
-                for (int q = 0; q < nq; ++q) {
-                    face_values(P, f, q, uK);
-                    const double s = P.dsw[((size_t)K * 4 + f) * nq + q] * e;
-                    for (int i = 0; i < n; ++i)
-                        for (int j = 0; j < n; ++j) blk0[i * n + j] += s * uK[i] * uK[j];
-                }
+                add_boundary_block(P, K, f, blk0);
                 continue;
             }
             P.bsr_col[K * 5 + 1 + f] = N;

@@ -106,6 +106,14 @@ struct Problem {
     std::vector<double> t_bop;                         // [4][n][nq]
     std::vector<double> t_bfix;                        // [ne][n]
 
+    // continuous (CG) moment system on V_p (cg_smm.cpp)
+    bool cg_ready = false;
+    int cg_nc = 0;                     // (nx p + 1)(ny p + 1) continuous nodes
+    std::vector<int> cg_map;           // [ne][n] DG node -> continuous node
+    std::vector<int> cg_tab;           // [nc][4] DG nodes at each continuous node, ascending, -1 padded
+    std::vector<int> cg_rowptr, cg_col;// CSR of A_c = P_c^T A P_c (element and boundary terms)
+    std::vector<double> cg_val, cg_dinv;
+
     // device state (api.hip)
     void* dev = nullptr;
 };
@@ -115,6 +123,9 @@ int ensure_heavy(Problem& P);   // per-element quadrature data and sweep graph, 
 void setup_cartesian_operators(Problem& P);
 void setup_sweep_graph(Problem& P);
 void assemble_ip(Problem& P);
+void add_volume_block(const Problem& P, int K, double* blk);
+void add_boundary_block(const Problem& P, int K, int f, double* blk);
+void assemble_cg(Problem& P);
 void assemble_rhs_fixed(Problem& P);
 void assemble_correction_operator(Problem& P);
 void cartesian_boundary_traces(const Problem& P, std::vector<double>& bx, std::vector<double>& by);

@@ -21,12 +21,14 @@ SMM_FP64, SMM_FP32_SWEEP = 0, 1
 SMM_SRC_ISO, SMM_SRC_ANISO = 0, 1
 SMM_INFLOW_VACUUM, SMM_INFLOW_ISO_FACE, SMM_INFLOW_FULL = 0, 1, 2
 SMM_START_ZERO, SMM_START_DIFFUSION, SMM_START_GIVEN = 0, 1, 2
+SMM_DISC_IP, SMM_DISC_CG = 0, 1
 
 EXPORTED = [
     "smm_strerror", "smm_ctx_create", "smm_ctx_destroy", "smm_last_error", "smm_problem_create",
     "smm_problem_destroy", "smm_get_dims", "smm_get_quadrature", "smm_get_nodes", "smm_get_bface_points",
     "smm_set_materials", "smm_set_source", "smm_set_inflow", "smm_default_opts", "smm_solve",
     "smm_get_outputs", "smm_apply_sweep", "smm_apply_moments", "smm_apply_G", "smm_debug_ip_dense",
+    "smm_debug_cg_system", "smm_debug_cg_spmv", "smm_time_cg_spmv",
     "smm_set_sweep_path", "smm_time_sweep", "smm_debug_typed_dense", "smm_debug_corr_dense",
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
@@ -60,7 +62,8 @@ class smm_solve_opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("outer_tol", C.c_double), ("max_outer", C.c_int),
                 ("inner_tol", C.c_double), ("max_inner", C.c_int), ("start", C.c_int),
                 ("delta_sweeps", C.c_int), ("use_graph", C.c_int), ("moment_path", C.c_int),
-                ("anderson", C.c_int), ("precond", C.c_int), ("inner_adapt", C.c_double)]
+                ("anderson", C.c_int), ("precond", C.c_int), ("inner_adapt", C.c_double),
+                ("discretization", C.c_int)]
 
 
 class smm_solve_info(C.Structure):
@@ -106,6 +109,9 @@ def load_library(path: str = LIB_PATH):
         "smm_apply_moments": (ip, [vp, ip, vp, vp]),
         "smm_apply_G": (ip, [vp, ip, vp, vp, C.c_double, ip]),
         "smm_debug_ip_dense": (ip, [vp, vp, vp]),
+        "smm_debug_cg_system": (ip, [vp, vp, vp, vp, vp, vp, vp]),
+        "smm_debug_cg_spmv": (ip, [vp, vp, vp]),
+        "smm_time_cg_spmv": (ip, [vp, ip, dp]),
         "smm_set_sweep_path": (ip, [vp, ip]),
         "smm_time_sweep": (ip, [vp, ip, ip, dp]),
         "smm_debug_typed_dense": (ip, [vp, vp, vp, vp]),
@@ -324,6 +330,35 @@ def smm_debug_ip_dense(prob: Problem):
     b = np.zeros(N)
     _check(load_library().smm_debug_ip_dense(prob.handle, _ptr(A), _ptr(b)), prob.ctx)
     return A, b
+
+
+def smm_debug_cg_system(prob: Problem):
+    """The continuous (CG) moment system as assembled by the library:
+    (rowptr, col, val, map) of the CSR matrix A_c and the continuous unknown
+    of each DG node."""
+    nc, nnz = C.c_int(), C.c_int()
+    lib = load_library()
+    _check(lib.smm_debug_cg_system(prob.handle, C.byref(nc), C.byref(nnz), None, None, None, None), prob.ctx)
+    rowptr = np.zeros(nc.value + 1, dtype=np.int32)
+    col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value)
+    cmap = np.zeros(prob.n_elem * prob.n_node, dtype=np.int32)
+    _check(lib.smm_debug_cg_system(prob.handle, C.byref(nc), C.byref(nnz), _ptr(rowptr), _ptr(col), _ptr(val),
+                                   _ptr(cmap)), prob.ctx)
+    return rowptr, col, val, cmap
+
+
+def smm_debug_cg_spmv(prob: Problem, x):
+    x = _f64(x)
+    y = np.zeros_like(x)
+    _check(load_library().smm_debug_cg_spmv(prob.handle, _ptr(x), _ptr(y)), prob.ctx)
+    return y
+
+
+def smm_time_cg_spmv(prob: Problem, reps: int) -> float:
+    ms = C.c_double()
+    _check(load_library().smm_time_cg_spmv(prob.handle, int(reps), C.byref(ms)), prob.ctx)
+    return ms.value
 
 
 def smm_set_sweep_path(prob: Problem, path: int):
