@@ -22,6 +22,9 @@ Also reported:
     p = 2, S8 blob layouts): the plain method (problems solved one after the
     other from the zero start) against the batched solve with the learned
     start, on identical inputs;
+  * the IP and the continuous (CG) moment systems on the multi-material
+    channel problem: time to a 1e-8 outer residual, and the roofline of the
+    CG product kernel;
   * the CPU oracle's sweep on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -163,6 +166,46 @@ def time_to_solution(L, ctx, n: int, log):
     return res
 
 
+def moment_discretisations(L, ctx, log):
+    """IP versus CG moment system (Sec. 5.1) on the multi-material channel
+    problem (128 x 128, p = 2, S12, FP32 sweep): wall time to a 1e-8 outer
+    residual from the zero start, and the roofline of the CG product kernel
+    (FP64 CSR, HBM-bound: 12 B per stored entry, the row pointers, x read
+    once and y written once)."""
+    import torch
+    from workloads import config_channel
+
+    wl = config_channel(n=128, p=2, sn=12)
+    common = dict(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=1e-8, inner_tol=1e-10, inner_adapt=1e-2,
+                  max_inner=20000, max_outer=60, use_graph=1)
+    variants = (("ip_two_level", dict(precond=1), "IP, typed path, two-level PCG"),
+                ("ip_block_jacobi", dict(moment_path=1), "IP, per-element path, block-Jacobi PCG"),
+                ("cg_jacobi", dict(discretization=L.SMM_DISC_CG), "CG, per-element path, Jacobi PCG"))
+    res = {"workload": "channel 128x128 p=2 S12 (two materials), FP32 sweep, zero start, outer 1e-8"}
+    for name, kw, what in variants:
+        p = L.problem_from_workload(ctx, wl)
+        L.smm_solve(p, L.smm_default_opts(**{**common, **kw, "max_outer": 1}), raise_on_noconv=False)  # set-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, info = L.smm_solve(p, L.smm_default_opts(**common, **kw), raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res[name] = {"what": what, "s": t, "converged": rc == L.SMM_OK, "outer": info["iterations"],
+                     "inner_total": info["cg_iterations_total"]}
+        log(f"{what}: {t * 1e3:.1f} ms, {info['iterations']} outer, {info['cg_iterations_total']} inner")
+        if name == "cg_jacobi":
+            rowptr, col, _, _ = L.smm_debug_cg_system(p)
+            nc, nnz = len(rowptr) - 1, len(col)
+            res["cg_unknowns"], res["ip_unknowns"] = nc, wl.n_elem * (wl.p + 1) ** 2
+            ms = L.smm_time_cg_spmv(p, 200)
+            by = 12.0 * nnz + 4.0 * (nc + 1) + 16.0 * nc
+            res["roofline_cg_spmv"] = roofline("cgs_spmv_kernel", "y = A_c x, continuous moment system "
+                                               f"({nc} rows, {nnz} entries)", by, ms)
+            log(f"CG product: {ms * 1e3:.2f} us, {res['roofline_cg_spmv']['achieved']:.0f} GB/s")
+        L.smm_problem_destroy(p)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,7 +216,9 @@ def main():
     ap.add_argument("--precond", type=int, default=1, help="0 block-Jacobi, 1 two-level PCG")
     ap.add_argument("--anderson", type=int, default=2, help="Anderson mixing depth of the outer iteration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 comparison")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 comparisons")
+    ap.add_argument("--disc-only", action="store_true",
+                    help="run only the IP versus CG moment-system comparison and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the problems of a batch are "
@@ -187,6 +232,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ctx = L.smm_ctx_create(0, torch.cuda.current_stream())
+    if args.disc_only:
+        print(json.dumps(moment_discretisations(L, ctx, log)))
+        return
     t0 = time.time()
     wls = [config_batched_problem(s) for s in range(args.problems)]
     probs = [L.problem_from_workload(ctx, wl) for wl in wls]
@@ -235,8 +283,10 @@ def main():
     dominant = rl_spmv if phase["pcg"] > phase["source+sweep"] else rl_sweep
 
     tts = None
+    disc = None
     if not args.no_solve:
         tts = time_to_solution(L, ctx, args.tts_problems, log)
+        disc = moment_discretisations(L, ctx, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -268,6 +318,7 @@ def main():
         "roofline_sweep": rl_sweep,
         "roofline_pcg_spmv": rl_spmv,
         "time_to_1e-8": tts,
+        "moment_discretisations": disc,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -119,7 +119,7 @@ typedef struct {
     int delta_sweeps;    /* 1: sweep only the change of the scattering source and
                             accumulate the moments in FP64 (default for FP32_SWEEP) */
     int use_graph;       /* 1: replay the PCG iteration chunks of the typed (batched) path
-                            from captured hipGraphs */
+                            and of the CG moment solve from captured hipGraphs */
     int moment_path;     /* 0: typed blocks on uniform Cartesian meshes with isotropic
                             sources (batched kernels), else per-element operators;
                             1: always per-element operators */

@@ -107,6 +107,8 @@ int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_or
 }
 
 static void dev_free(Dev& D) {
+    for (auto& g : D.cg_graphs) (void)hipGraphExecDestroy(g.second);
+    if (D.cg_cap) (void)hipStreamDestroy(D.cg_cap);
     for (void* ptr : D.allocs) (void)hipFree(ptr);
     D.allocs.clear();
     D = Dev();
@@ -552,7 +554,7 @@ static CgsArgs cgs_args(smm_problem* pr) {
 // The CG moment solve: restrict the DG right-hand side D.b to V_p, start from
 // the DG iterate in D.x (continuous after the first CG solve, so its node
 // values are exact), Jacobi-PCG, and return the DG values P_c c in D.x.
-static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its) {
+static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its, bool graph) {
     Dev& D = pr->D;
     smm_ctx* c = pr->P.ctx;
     const CgsArgs a = cgs_args(pr);
@@ -567,7 +569,32 @@ static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its)
         done = (int)sc[5];
         if (sc[6] != 0.0) return fail(c, SMM_EBREAKDOWN, "CG breakdown (continuous moment system)");
         if (sc[4] != 0.0 || done >= max_inner) break;
-        HIPCHK(c, cgs_iterations(a, std::min(chunk, max_inner - done), c->stream));
+        const int k = std::min(chunk, max_inner - done);
+        if (graph) {
+            // capture the chunk of k iterations once on a private stream
+            // (kernel nodes only), then replay it on the context's stream
+            hipGraphExec_t ge = nullptr;
+            for (auto& e : D.cg_graphs)
+                if (e.first == k) ge = e.second;
+            if (!ge) {
+                if (!D.cg_cap) HIPCHK(c, hipStreamCreateWithFlags(&D.cg_cap, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(D.cg_cap, hipStreamCaptureModeRelaxed));
+                const hipError_t e1 = cgs_iterations(a, k, D.cg_cap);
+                const hipError_t e2 = hipStreamEndCapture(D.cg_cap, &g);
+                if (e1 != hipSuccess || e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return fail(c, SMM_EHIP, "CG graph capture failed");
+                }
+                const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e3 != hipSuccess) return fail(c, SMM_EHIP, "CG graph instantiation failed");
+                D.cg_graphs.emplace_back(k, ge);
+            }
+            HIPCHK(c, hipGraphLaunch(ge, c->stream));
+        } else {
+            HIPCHK(c, cgs_iterations(a, k, c->stream));
+        }
         chunk = std::min(chunk * 2, 64);
     }
     HIPCHK(c, cgs_scatter(a, D.x, c->stream));
@@ -602,7 +629,7 @@ static int moment_solve(smm_problem* pr, double tol, int max_inner, int* its) {
 // One evaluation of G from D.varphi into D.x (b, closures, moments updated).
 // psi_cur / psi_prev are sweep buffers; delta mode sweeps sigma_s/(4pi)(varphi - varphi_prev).
 static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, double inner_tol, int max_inner,
-                  int* cg_its, bool cgdisc = false) {
+                  int* cg_its, bool cgdisc = false, bool graph = false) {
     Problem& P = pr->P;
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
@@ -637,7 +664,8 @@ static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, d
                          c->stream));
     // moment solve (a6), warm-started from the current iterate
     HIPCHK(c, hipMemcpyAsync(D.x, D.varphi, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
-    return cgdisc ? cg_moment_solve(pr, inner_tol, max_inner, cg_its) : moment_solve(pr, inner_tol, max_inner, cg_its);
+    return cgdisc ? cg_moment_solve(pr, inner_tol, max_inner, cg_its, graph)
+                  : moment_solve(pr, inner_tol, max_inner, cg_its);
 }
 
 extern "C" {
@@ -682,7 +710,7 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     } else if (o.start == SMM_START_DIFFUSION) {
         HIPCHK(c, hipMemcpyAsync(D.b, D.bfix, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemsetAsync(D.x, 0, sizeof(double) * L, c->stream));
-        rc = cgdisc ? cg_moment_solve(prob, o.inner_tol, o.max_inner, &its)
+        rc = cgdisc ? cg_moment_solve(prob, o.inner_tol, o.max_inner, &its, o.use_graph != 0)
                     : moment_solve(prob, o.inner_tol, o.max_inner, &its);
         if (rc) return rc;
         HIPCHK(c, hipMemcpyAsync(D.varphi, D.x, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
@@ -698,7 +726,8 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     for (it = 1; it <= o.max_outer; ++it) {
         int cgi = 0;
         const double tol_k = o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt * r_prev) : o.inner_tol;
-        if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, tol_k, o.max_inner, &cgi, cgdisc))) return rc;
+        if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, tol_k, o.max_inner, &cgi, cgdisc, o.use_graph != 0)))
+            return rc;
         cg_total += cgi;
         cg_max = std::max(cg_max, cgi);
         // residual (a7)

@@ -58,6 +58,8 @@ struct Dev {
     double *cg_val = nullptr, *cg_dinv = nullptr, *cg_b = nullptr, *cg_x = nullptr, *cg_r = nullptr,
            *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_part = nullptr, *cg_scal = nullptr;
     bool cg_dirty = true;   // host CG system rebuilt since the last upload
+    hipStream_t cg_cap = nullptr;                 // private stream for graph capture
+    std::vector<std::pair<int, hipGraphExec_t>> cg_graphs;  // captured chunks of k iterations
     bool have_outputs = false;
     bool last_typed = false;       // last solve ran on the typed (batched) path
     bool gen_sweep_built = false;  // per-element sweep data uploaded

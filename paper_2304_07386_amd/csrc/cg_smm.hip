@@ -12,10 +12,14 @@
 // * vector updates one thread per node; every reduction goes through block
 //   partials and a one-block kernel that adds them in block order, so each
 //   sum (and the iteration) is the same on every run.
-// One PCG iteration is five launches: q = A p with partials of p.q; alpha;
-// x += alpha p, r -= alpha q, z = r / diag with partials of r.z and r.r;
-// beta and the convergence test; p = z + beta p.  A stopped solve (converged,
-// breakdown) makes every later launch of the chunk return at once.
+// One PCG iteration is four launches: q = A p with partials of p.q; alpha
+// from those partials, x += alpha p, r -= alpha q, z = r / diag with partials
+// of r.z and r.r; beta from those and p = z + beta p; a one-block launch that
+// records r.z, the iteration count and the convergence test.  The scalar
+// reductions are repeated by every block that needs them (a few thousand
+// partials, read from cache), which saves two launches per iteration.  A
+// stopped solve (converged, breakdown) makes every later launch of the chunk
+// return at once.
 #include "cg_smm.hpp"
 
 namespace smm {
@@ -151,26 +155,21 @@ __global__ __launch_bounds__(CGS_T) void cgs_k1(CgsArgs a) {
     if (threadIdx.x == 0) a.part[blockIdx.x] = pq;
 }
 
-// alpha = r.z / p.q (stop on p.q <= 0)
-__global__ __launch_bounds__(CGS_T) void cgs_alpha(CgsArgs a) {
-    __shared__ double red[CGS_T];
-    if (a.scal[4] != 0.0) return;
-    const double pq = cgs_sum_parts(a.part, a.sblocks, red);
-    if (threadIdx.x == 0) {
-        if (!(pq > 0.0)) {
-            a.scal[6] = 1.0;
-            a.scal[4] = 1.0;
-        } else {
-            a.scal[7] = a.scal[0] / pq;
-        }
-    }
-}
-
-// x += alpha p, r -= alpha q, z = r / diag; partials of r.z and r.r
+// alpha = r.z / p.q from the product kernel's partials (every block forms
+// the same sum in the same order; p.q <= 0 stops the solve); x += alpha p,
+// r -= alpha q, z = r / diag; partials of r.z and r.r
 __global__ __launch_bounds__(CGS_T) void cgs_k2(CgsArgs a) {
     __shared__ double red[CGS_T];
     if (a.scal[4] != 0.0) return;
-    const double alpha = a.scal[7];
+    const double pq = cgs_sum_parts(a.part, a.sblocks, red);
+    if (!(pq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.scal[6] = 1.0;
+            a.scal[4] = 1.0;
+        }
+        return;
+    }
+    const double alpha = a.scal[0] / pq;
     const int g = blockIdx.x * CGS_T + threadIdx.x;
     double rz = 0.0, rr = 0.0;
     if (g < a.nc) {
@@ -189,27 +188,32 @@ __global__ __launch_bounds__(CGS_T) void cgs_k2(CgsArgs a) {
     }
 }
 
-// beta = r.z_new / r.z_old; convergence test ||r|| <= tol ||b||
-__global__ __launch_bounds__(CGS_T) void cgs_beta(CgsArgs a) {
+// beta = r.z_new / r.z_old and the test ||r|| <= tol ||b|| from the update
+// kernel's partials (every block alike); p = z + beta p unless converged.
+// r.z_old stays in scal[0] until the next launch records the new one.
+__global__ __launch_bounds__(CGS_T) void cgs_k3(CgsArgs a) {
+    __shared__ double red[CGS_T];
+    if (a.scal[4] != 0.0) return;
+    const double rzn = cgs_sum_parts(vpart(a, 0), a.vblocks, red);
+    const double rr = cgs_sum_parts(vpart(a, 1), a.vblocks, red);
+    const double rzo = a.scal[0];
+    const bool conv = rr <= a.scal[3];
+    const int g = blockIdx.x * CGS_T + threadIdx.x;
+    if (!conv && g < a.nc) a.p[g] = a.z[g] + (rzn / rzo) * a.p[g];
+}
+
+// one-block bookkeeping after cgs_k3: r.z, r.r, iteration count, stop flag
+__global__ __launch_bounds__(CGS_T) void cgs_note(CgsArgs a) {
     __shared__ double red[CGS_T];
     if (a.scal[4] != 0.0) return;
     const double rzn = cgs_sum_parts(vpart(a, 0), a.vblocks, red);
     const double rr = cgs_sum_parts(vpart(a, 1), a.vblocks, red);
     if (threadIdx.x == 0) {
-        a.scal[8] = rzn / a.scal[0];
         a.scal[0] = rzn;
         a.scal[2] = rr;
         a.scal[5] += 1.0;
         if (rr <= a.scal[3]) a.scal[4] = 1.0;
     }
-}
-
-// p = z + beta p
-__global__ __launch_bounds__(CGS_T) void cgs_k3(CgsArgs a) {
-    if (a.scal[4] != 0.0) return;
-    const double beta = a.scal[8];
-    const int g = blockIdx.x * CGS_T + threadIdx.x;
-    if (g < a.nc) a.p[g] = a.z[g] + beta * a.p[g];
 }
 
 }  // namespace
@@ -245,10 +249,9 @@ hipError_t cgs_start(const CgsArgs& a, double tol, hipStream_t s) {
 hipError_t cgs_iterations(const CgsArgs& a, int iters, hipStream_t s) {
     for (int t = 0; t < iters; ++t) {
         hipLaunchKernelGGL(cgs_k1, dim3(a.sblocks), dim3(CGS_T), 0, s, a);
-        hipLaunchKernelGGL(cgs_alpha, dim3(1), dim3(CGS_T), 0, s, a);
         hipLaunchKernelGGL(cgs_k2, dim3(a.vblocks), dim3(CGS_T), 0, s, a);
-        hipLaunchKernelGGL(cgs_beta, dim3(1), dim3(CGS_T), 0, s, a);
         hipLaunchKernelGGL(cgs_k3, dim3(a.vblocks), dim3(CGS_T), 0, s, a);
+        hipLaunchKernelGGL(cgs_note, dim3(1), dim3(CGS_T), 0, s, a);
     }
     return hipGetLastError();
 }

@@ -23,7 +23,7 @@ struct CgsArgs {
 };
 
 // scal: 0 r.z, 1 bb, 2 r.r, 3 tol^2 bb, 4 converged or stopped (1), 5 iterations
-// done, 6 breakdown (p.Ap <= 0), 7 alpha, 8 beta
+// done, 6 breakdown (p.Ap <= 0)
 constexpr int CGS_SPMV_ROWS = 32;  // rows per 256-thread block, 8 lanes per row
 
 hipError_t cgs_gather(const CgsArgs& a, const double* b_dg, hipStream_t s);   // b = P_c^T b_dg

@@ -136,3 +136,21 @@ def test_cg_refused_combinations(ctx):
         L.smm_batch_solve(b, _opts())
     assert e.value.code == L.SMM_EUNSUPPORTED
     L.smm_batch_destroy(b)
+
+
+def test_cg_graph_replay_is_bitwise_eager(ctx):
+    """Graph-replayed PCG chunks equal the eager launches bit for bit, on
+    repeated solves with eager work (a solve without graphs) in between."""
+    announce("CG SMM graph replay vs eager")
+    wl = config_channel(n=8, p=2, sn=4, side=1.3)
+    _, p = _pair(ctx, wl)
+    o_eager = _opts(precision=L.SMM_FP64, outer_tol=1e-12, inner_tol=1e-13, max_inner=20000, use_graph=0)
+    o_graph = _opts(precision=L.SMM_FP64, outer_tol=1e-12, inner_tol=1e-13, max_inner=20000, use_graph=1)
+    L.smm_solve(p, o_eager)
+    ref = L.smm_get_outputs_host(p)["varphi"]
+    for rep in range(3):
+        L.smm_solve(p, o_graph)
+        got = L.smm_get_outputs_host(p)["varphi"]
+        assert np.array_equal(got, ref), rep
+        L.smm_solve(p, o_eager)
+        assert np.array_equal(L.smm_get_outputs_host(p)["varphi"], ref), rep
