@@ -44,7 +44,15 @@ class OracleProblem:
     psibar: np.ndarray | None     # [n_bf, nq, nd] or None (vacuum)
     kappa_scale: float = 1.0
     disc: str = "ip"              # moment discretisation: "ip" (Y_p) or "cg" (V_p)
+    tiles: tuple | None = None    # (tx, ty): parallel block Jacobi sweep over tiles
     cache: dict = field(default_factory=dict)
+
+    @property
+    def block(self):
+        """Block id per element for the block Jacobi sweep, or None."""
+        if self.tiles is None:
+            return None
+        return transport.block_ids(self.mesh, *self.tiles)
 
     @property
     def ne(self):
@@ -55,10 +63,12 @@ class OracleProblem:
         return (self.mesh.p + 1) ** 2
 
 
-def make_problem(wl, kappa_scale: float = 1.0, disc: str = "ip") -> OracleProblem:
+def make_problem(wl, kappa_scale: float = 1.0, disc: str = "ip", tiles=None) -> OracleProblem:
     """Build the oracle's view of a workload (mesh data, S_N set, nodal
     source, inflow at boundary face points).  ``disc`` picks the moment
-    discretisation: "ip" (interior penalty, Y_p) or "cg" (continuous, V_p)."""
+    discretisation: "ip" (interior penalty, Y_p) or "cg" (continuous, V_p);
+    ``tiles`` = (tx, ty) replaces the sweep by the parallel block Jacobi
+    sweep over tiles of tx x ty elements (Sec. 6.5)."""
     if disc not in ("ip", "cg"):
         raise ValueError(disc)
     mesh = fem.build_mesh(wl.ctrl, wl.nx, wl.ny, wl.m, wl.p)
@@ -71,7 +81,8 @@ def make_problem(wl, kappa_scale: float = 1.0, disc: str = "ip") -> OracleProble
         q = np.repeat(np.asarray(wl.q_elem, dtype=float)[:, None], n, axis=1)
     psibar = transport.inflow_at_points(mesh, omega, wl.inflow)
     return OracleProblem(mesh, omega, w, np.asarray(wl.sigma_t, float),
-                         np.asarray(wl.sigma_s, float), q, psibar, kappa_scale, disc)
+                         np.asarray(wl.sigma_s, float), q, psibar, kappa_scale, disc,
+                         None if tiles is None else (int(tiles[0]), int(tiles[1])))
 
 
 # ----------------------------------------------------------------------------
@@ -311,7 +322,7 @@ def apply_G(prob: OracleProblem, varphi: np.ndarray, psi_lag=None):
     solve.  Returns (varphi_new, dict of intermediates)."""
     lu, bfix = _lhs_factor(prob)
     S = scattering_source(prob, varphi)
-    psi = transport.sweep(prob.mesh, prob.omega, prob.sigma_t, S, prob.psibar, psi_lag)
+    psi = transport.sweep(prob.mesh, prob.omega, prob.sigma_t, S, prob.psibar, psi_lag, prob.block)
     phi, J, T, beta = closures(prob, psi)
     b = bfix + rhs_correction(prob, T, beta)
     return lu.solve(b), {"psi": psi, "phi": phi, "J": J, "T": T, "beta": beta, "b": b}

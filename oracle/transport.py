@@ -19,6 +19,11 @@ whose pointwise inflow comes from a neighbour that the graph places
 downstream -- possible only on curved faces -- reads that neighbour's previous
 sweep (the lagging of upper-triangular couplings described for the curved
 triple-point mesh in Sec. 6.2).
+
+Parallel block Jacobi sweep (Sec. 6.5, weak scaling): the mesh is split into
+blocks, each block is swept on its own in upwind order, and inflow across a
+face between two blocks is the neighbour's previous sweep.  The graph then
+has edges only inside blocks.  Selected by passing a block id per element.
 """
 from __future__ import annotations
 
@@ -41,8 +46,18 @@ def chord_normals(mesh: Mesh) -> np.ndarray:
     return out
 
 
-def sweep_graph(mesh: Mesh, om: np.ndarray):
-    """Upwind element graph for direction om.
+def block_ids(mesh: Mesh, tx: int, ty: int) -> np.ndarray:
+    """Block of each element when the nx x ny element grid is cut into tiles
+    of tx x ty elements (the last row and column of tiles may be smaller);
+    tiles numbered row by row."""
+    i = np.arange(mesh.nx * mesh.ny) % mesh.nx
+    j = np.arange(mesh.nx * mesh.ny) // mesh.nx
+    return (i // tx) + (j // ty) * (-(-mesh.nx // tx))
+
+
+def sweep_graph(mesh: Mesh, om: np.ndarray, block: np.ndarray | None = None):
+    """Upwind element graph for direction om (edges only between elements of
+    the same block when ``block`` is given).
 
     Returns (upstream[K, f] bool: the neighbour across f is a graph
     predecessor; level[K]: longest-path level from Kahn's algorithm)."""
@@ -50,6 +65,12 @@ def sweep_graph(mesh: Mesh, om: np.ndarray):
     cn = chord_normals(mesh)
     flux = cn[..., 0] * om[0] + cn[..., 1] * om[1]       # [K, 4]
     interior = mesh.nbr >= 0
+    if block is not None:
+        same = np.zeros_like(interior)
+        for f in range(4):
+            N = mesh.nbr[:, f]
+            same[:, f] = (N >= 0) & (block[np.maximum(N, 0)] == block)
+        interior = same
     upstream = interior & (flux < 0.0)
     indeg = upstream.sum(axis=1)
     level = np.zeros(ne, dtype=np.int64)
@@ -62,7 +83,7 @@ def sweep_graph(mesh: Mesh, om: np.ndarray):
             seen += 1
             for f in range(4):
                 N = mesh.nbr[K, f]
-                if N >= 0 and flux[K, f] > 0.0:     # K -> N
+                if interior[K, f] and flux[K, f] > 0.0:     # K -> N
                     level[N] = max(level[N], level[K] + 1)
                     indeg[N] -= 1
                     if indeg[N] == 0:
@@ -74,12 +95,16 @@ def sweep_graph(mesh: Mesh, om: np.ndarray):
 
 
 def sweep(mesh: Mesh, omega: np.ndarray, sigma_t: np.ndarray, S: np.ndarray,
-          psibar: np.ndarray | None, psi_lag: np.ndarray | None = None) -> np.ndarray:
-    """One application of L^{-1}: psi[d, K, :] for every direction.
+          psibar: np.ndarray | None, psi_lag: np.ndarray | None = None,
+          block: np.ndarray | None = None) -> np.ndarray:
+    """One application of L^{-1} (of its block Jacobi approximation when
+    ``block`` is given): psi[d, K, :] for every direction.
 
     S: nodal source [ne, n] (shared by all directions) or [n_dir, ne, n].
     psibar: inflow at boundary face points [n_bface, nq, n_dir] (None = vacuum).
-    psi_lag: previous sweep, read only at lagged curved-face points (None = 0).
+    psi_lag: previous sweep, read at lagged face points: curved faces against
+    the graph, and faces between blocks (None = 0).
+    block: block id per element, or None for the full sweep.
     """
     nd = omega.shape[0]
     ne, n = mesh.nx * mesh.ny, (mesh.p + 1) ** 2
@@ -88,7 +113,7 @@ def sweep(mesh: Mesh, omega: np.ndarray, sigma_t: np.ndarray, S: np.ndarray,
     for d in range(nd):
         ox, oy = omega[d, 0], omega[d, 1]
         Sd = S if S.ndim == 2 else S[d]
-        upstream, level = sweep_graph(mesh, omega[d])
+        upstream, level = sweep_graph(mesh, omega[d], block)
         lag = psi_lag[d] if psi_lag is not None else np.zeros((ne, n))
         for L in range(level.max() + 1):
             Ks = np.nonzero(level == L)[0]
