@@ -25,6 +25,8 @@ Also reported:
   * the IP and the continuous (CG) moment systems on the multi-material
     channel problem: time to a 1e-8 outer residual, and the roofline of the
     CG product kernel;
+  * the parallel block Jacobi sweep on the same problem: sweep time and
+    outer iterations per tile size;
   * the CPU oracle's sweep on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -206,6 +208,49 @@ def moment_discretisations(L, ctx, log):
     return res
 
 
+def block_jacobi_sweeps(L, ctx, log):
+    """Parallel block Jacobi sweep (Sec. 6.5) on the channel problem (128 x
+    128, p = 2, S12): time of one FP32 sweep of the per-element kernel (one
+    workgroup per direction and tile) for several tile sizes, outer
+    iterations and wall time to a 1e-8 outer residual (CG moment system,
+    FP32 delta sweeps), beside the tabulated Cartesian sweep, which has no
+    tiled form.  The per-element kernel assembles and eliminates every
+    element and direction: 165 flops per elem*angle*DOF at p = 2, on the FP32
+    vector units."""
+    import torch
+    from workloads import config_channel
+
+    wl = config_channel(n=128, p=2, sn=12)
+    common = dict(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=1e-8, inner_tol=1e-10, inner_adapt=1e-2,
+                  max_inner=20000, max_outer=400, use_graph=1, discretization=L.SMM_DISC_CG)
+    units = float(wl.n_elem * (wl.p + 1) ** 2 * 84)
+    res = {"workload": "channel 128x128 p=2 S12, FP32 delta sweeps, CG moment system, outer 1e-8",
+           "units_per_sweep": units, "runs": []}
+    for tiles in ((0, 0), (128, 128), (32, 32), (16, 16), (8, 8)):
+        p = L.problem_from_workload(ctx, wl)
+        if tiles != (0, 0):
+            L.smm_set_sweep_tiles(p, *tiles)
+        ms = L.smm_time_sweep(p, L.SMM_FP32_SWEEP, 5)
+        L.smm_solve(p, L.smm_default_opts(**{**common, "max_outer": 1}), raise_on_noconv=False)  # set-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, info = L.smm_solve(p, L.smm_default_opts(**common), raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        kind = "tabulated Cartesian sweep (full)" if tiles == (0, 0) else \
+            f"per-element sweep, tiles {tiles[0]}x{tiles[1]}"
+        run = {"kernel": kind, "tiles": list(tiles), "sweep_ms": ms, "units_per_s": units / (ms * 1e-3),
+               "solve_s": t, "converged": rc == L.SMM_OK, "outer": info["iterations"]}
+        if tiles != (0, 0):
+            tf = 165.0 * units / (ms * 1e-3) / 1e12
+            run["roofline"] = {"bound": "alu", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
+                               "traffic": None, "kernel": "sweep_general_kernel"}
+        res["runs"].append(run)
+        log(f"{kind}: sweep {ms:.3f} ms, solve {t * 1e3:.1f} ms, {info['iterations']} outer")
+        L.smm_problem_destroy(p)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +264,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-1e-8 comparisons")
     ap.add_argument("--disc-only", action="store_true",
                     help="run only the IP versus CG moment-system comparison and print its JSON")
+    ap.add_argument("--tiles-only", action="store_true",
+                    help="run only the block Jacobi sweep comparison and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the problems of a batch are "
@@ -234,6 +281,9 @@ def main():
     ctx = L.smm_ctx_create(0, torch.cuda.current_stream())
     if args.disc_only:
         print(json.dumps(moment_discretisations(L, ctx, log)))
+        return
+    if args.tiles_only:
+        print(json.dumps(block_jacobi_sweeps(L, ctx, log)))
         return
     t0 = time.time()
     wls = [config_batched_problem(s) for s in range(args.problems)]
@@ -284,9 +334,11 @@ def main():
 
     tts = None
     disc = None
+    tiles = None
     if not args.no_solve:
         tts = time_to_solution(L, ctx, args.tts_problems, log)
         disc = moment_discretisations(L, ctx, log)
+        tiles = block_jacobi_sweeps(L, ctx, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -319,6 +371,7 @@ def main():
         "roofline_pcg_spmv": rl_spmv,
         "time_to_1e-8": tts,
         "moment_discretisations": disc,
+        "block_jacobi_sweeps": tiles,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -247,6 +247,17 @@ int smm_time_cg_spmv(smm_problem* prob, int reps, double* ms_avg);
  * cross-checking the kernels against each other). */
 int smm_set_sweep_path(smm_problem* prob, int path);
 
+/* Parallel block Jacobi sweep (Sec. 6.5, weak scaling): the element grid is
+ * cut into tiles of tile_nx x tile_ny elements (the last row and column of
+ * tiles may be smaller), each tile is swept on its own in upwind order, and
+ * inflow across a face between tiles is the previous sweep's (zero on the
+ * first sweep; in delta sweeps, the previous delta).  The SMM fixed point is
+ * unchanged; the outer iteration count grows with the number of tiles.  Runs
+ * on the per-element sweep path, one workgroup per (direction, tile).
+ * (0, 0) restores the full sweep.  Problems with tiles cannot join a batch
+ * (SMM_EUNSUPPORTED).  SMM_EINVAL for negative sizes or only one size 0. */
+int smm_set_sweep_tiles(smm_problem* prob, int tile_nx, int tile_ny);
+
 /* Time one sweep configuration on device (average ms over `reps` launches
  * measured with HIP events on the context stream); used by the benchmark. */
 int smm_time_sweep(smm_problem* prob, int precision, int reps, double* ms_avg);

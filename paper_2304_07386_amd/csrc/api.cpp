@@ -230,6 +230,28 @@ int smm_set_inflow(smm_problem* prob, const double* psibar, int layout) {
     return SMM_OK;
 }
 
+int smm_set_sweep_tiles(smm_problem* prob, int tile_nx, int tile_ny) {
+    if (!prob) return SMM_EINVAL;
+    Problem& P = prob->P;
+    Dev& D = prob->D;
+    if (tile_nx < 0 || tile_ny < 0 || (tile_nx == 0) != (tile_ny == 0))
+        return fail(P.ctx, SMM_EINVAL, "smm_set_sweep_tiles: tile sizes must both be positive, or both 0");
+    if (P.tile_x == tile_nx && P.tile_y == tile_ny) return SMM_OK;
+    P.tile_x = tile_nx;
+    P.tile_y = tile_ny;
+    P.graph_ready = false;
+    // the level tables change size: their device copies are rebuilt
+    void** tabs[] = {(void**)&D.upflag, (void**)&D.lev_ptr, (void**)&D.lev_elem};
+    for (void** t : tabs)
+        if (*t) {
+            (void)hipFree(*t);
+            D.allocs.erase(std::find(D.allocs.begin(), D.allocs.end(), *t));
+            *t = nullptr;
+        }
+    D.gen_sweep_built = false;
+    return SMM_OK;
+}
+
 int smm_set_sweep_path(smm_problem* prob, int force_general) {
     if (!prob) return SMM_EINVAL;
     if (force_general < 0 || force_general > 2) return SMM_EINVAL;
@@ -335,7 +357,7 @@ static int ensure_device(smm_problem* pr, bool gen_moment, bool gen_sweep) {
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
     if (c->device < 0) return fail(c, SMM_ESTATE, "host-only context");
-    if (!P.cartesian) gen_sweep = true;
+    if (!P.cartesian || P.tile_x > 0) gen_sweep = true;
     int rc = ensure_host(pr, gen_moment || gen_sweep);
     if (rc) return rc;
     const long L = (long)P.ne * P.n;
@@ -452,7 +474,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
     hipError_t e;
-    if (P.cartesian && D.force_general != 1) {
+    if (P.cartesian && D.force_general != 1 && P.tile_x == 0) {
         CartSweepArgs a{};
         a.nx = P.nx; a.ny = P.ny; a.nd = P.nd; a.nb = P.nb; a.nmat = P.nmat;
         a.s_aniso = s_aniso;
@@ -470,6 +492,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
     } else {
         GenSweepArgs a{};
         a.ne = P.ne; a.nd = P.nd; a.nb = P.nb; a.nq = P.nq; a.nbf = P.nbf; a.nlev = P.nlev_max;
+        a.ntiles = P.ntiles;
         a.s_aniso = s_aniso;
         a.S = S;
         a.Mk = fp64 ? D.Mk64 : D.Mk32;
@@ -685,11 +708,11 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     const bool cgdisc = o.discretization == SMM_DISC_CG;
     if (cgdisc && o.anderson != 0)
         return fail(c, SMM_EUNSUPPORTED, "smm_solve: Anderson mixing runs on the typed path, IP discretisation only");
-    if (o.anderson != 0 && !(o.moment_path == 0 && typed_applicable(P) && D.force_general != 1))
+    if (o.anderson != 0 && !(o.moment_path == 0 && typed_applicable(P) && D.force_general != 1 && P.tile_x == 0))
         return fail(c, SMM_EUNSUPPORTED, "smm_solve: Anderson mixing needs the typed (batched) path");
     if (o.start < SMM_START_ZERO || o.start > SMM_START_GIVEN)
         return fail(c, SMM_EINVAL, "smm_solve: start must be ZERO, DIFFUSION or GIVEN (the learned start needs a batch)");
-    if (!cgdisc && o.moment_path == 0 && typed_applicable(P) && D.force_general != 1) {
+    if (!cgdisc && o.moment_path == 0 && typed_applicable(P) && D.force_general != 1 && P.tile_x == 0) {
         const int r = batch_solve_single(prob, o, varphi0, info);
         D.last_typed = (r == SMM_OK || r == SMM_ENOCONV);
         return r;

@@ -1325,6 +1325,9 @@ int smm_batch_create(smm_ctx* ctx, smm_problem* const* probs, int n, smm_batch**
         if (!p || p->P.ctx != ctx) {
             batch_free(B);
             return fail(ctx, SMM_EINVAL, "problems must belong to the batch's context");
+        } else if (p->P.tile_x > 0) {
+            batch_free(B);
+            return fail(ctx, SMM_EUNSUPPORTED, "batches sweep whole meshes: a problem has sweep tiles set");
         }
     int rc = batch_build(B);
     if (rc) {

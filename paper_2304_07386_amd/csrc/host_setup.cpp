@@ -583,21 +583,33 @@ void cartesian_boundary_traces(const Problem& P, std::vector<double>& bx, std::v
 // Sweep graph per direction: edge N -> K across face f of K when the chord
 // flux Omega . int_f n_K ds < 0; levels = longest path (Kahn's algorithm).
 // ---------------------------------------------------------------------------
+// Per direction, the upwind element graph from the chord normals and its
+// levels by Kahn's algorithm.  With tiles (the parallel block Jacobi sweep of
+// Sec. 6.5) only faces inside a tile are edges; inflow across a tile face is
+// the previous sweep's.  Level lists per (direction, tile): lev_ptr holds the
+// offsets into the direction's element list, which is ordered by tile, then
+// level, then element.
 void setup_sweep_graph(Problem& P) {
     const int ne = P.ne, nd = P.nd;
-    std::vector<std::vector<int>> lv(nd);
+    const int tx = P.tile_x > 0 ? P.tile_x : P.nx, ty = P.tile_y > 0 ? P.tile_y : P.ny;
+    const int ntx = (P.nx + tx - 1) / tx, nty = (P.ny + ty - 1) / ty;
+    P.ntiles = ntx * nty;
+    std::vector<int> tile(ne);
+    for (int K = 0; K < ne; ++K) tile[K] = (K % P.nx) / tx + ((K / P.nx) / ty) * ntx;
+    auto edge = [&](int K, int f) {
+        const int N = P.nbr[K * 4 + f];
+        return N >= 0 && tile[N] == tile[K];
+    };
     P.upflag.assign((size_t)nd * ne, 0);
-    std::vector<std::vector<int>> per_level_counts(nd);
     P.nlev_max = 0;
-    std::vector<int> level(ne), indeg(ne), order;
-    std::vector<std::vector<int>> elems_by_level;
-    std::vector<std::vector<std::vector<int>>> all(nd);
+    std::vector<int> level(ne), indeg(ne);
+    std::vector<std::vector<int>> lev_of(nd);
     for (int d = 0; d < nd; ++d) {
         const double ox = P.omega[d * 3], oy = P.omega[d * 3 + 1];
         for (int K = 0; K < ne; ++K) {
             uint8_t bits = 0;
             for (int f = 0; f < 4; ++f) {
-                if (P.nbr[K * 4 + f] < 0) continue;
+                if (!edge(K, f)) continue;
                 const double fl = ox * P.chord[(K * 4 + f) * 2] + oy * P.chord[(K * 4 + f) * 2 + 1];
                 if (fl < 0.0) bits |= (uint8_t)(1u << f);
             }
@@ -608,13 +620,12 @@ void setup_sweep_graph(Problem& P) {
         std::vector<int> frontier, next;
         for (int K = 0; K < ne; ++K)
             if (indeg[K] == 0) frontier.push_back(K);
-        int maxl = 0;
         while (!frontier.empty()) {
             next.clear();
             for (int K : frontier)
                 for (int f = 0; f < 4; ++f) {
+                    if (!edge(K, f)) continue;
                     const int N = P.nbr[K * 4 + f];
-                    if (N < 0) continue;
                     const double fl = ox * P.chord[(K * 4 + f) * 2] + oy * P.chord[(K * 4 + f) * 2 + 1];
                     if (fl > 0.0) {
                         level[N] = std::max(level[N], level[K] + 1);
@@ -624,21 +635,30 @@ void setup_sweep_graph(Problem& P) {
             std::sort(next.begin(), next.end());
             frontier.swap(next);
         }
-        for (int K = 0; K < ne; ++K) maxl = std::max(maxl, level[K]);
-        all[d].assign(maxl + 1, {});
-        for (int K = 0; K < ne; ++K) all[d][level[K]].push_back(K);
-        P.nlev_max = std::max(P.nlev_max, maxl + 1);
+        for (int K = 0; K < ne; ++K) P.nlev_max = std::max(P.nlev_max, level[K] + 1);
+        lev_of[d] = level;
     }
-    P.lev_ptr.assign((size_t)nd * (P.nlev_max + 1), 0);
+    const int nl = P.nlev_max, nt = P.ntiles;
+    P.lev_ptr.assign((size_t)nd * nt * (nl + 1), 0);
     P.lev_elem.assign((size_t)nd * ne, 0);
+    std::vector<int> cnt((size_t)nt * nl);
     for (int d = 0; d < nd; ++d) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int K = 0; K < ne; ++K) ++cnt[(size_t)tile[K] * nl + lev_of[d][K]];
         int pos = 0;
-        for (int l = 0; l < P.nlev_max; ++l) {
-            P.lev_ptr[(size_t)d * (P.nlev_max + 1) + l] = pos;
-            if (l < (int)all[d].size())
-                for (int K : all[d][l]) P.lev_elem[(size_t)d * ne + pos++] = K;
+        std::vector<int> start((size_t)nt * nl);
+        for (int t = 0; t < nt; ++t)
+            for (int l = 0; l <= nl; ++l) {
+                P.lev_ptr[((size_t)d * nt + t) * (nl + 1) + l] = pos;
+                if (l < nl) {
+                    start[(size_t)t * nl + l] = pos;
+                    pos += cnt[(size_t)t * nl + l];
+                }
+            }
+        for (int K = 0; K < ne; ++K) {
+            int& at = start[(size_t)tile[K] * nl + lev_of[d][K]];
+            P.lev_elem[(size_t)d * ne + at++] = K;
         }
-        P.lev_ptr[(size_t)d * (P.nlev_max + 1) + P.nlev_max] = pos;
     }
 }
 

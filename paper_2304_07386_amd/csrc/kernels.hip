@@ -418,6 +418,9 @@ hipError_t launch_sweep_cart(bool fp64, const CartSweepArgs& a, hipStream_t s) {
 // the chord graph, else the previous sweep) or the inflow on the boundary.
 // One wavefront per element: assembly, elimination without pivoting (the
 // symmetric part of A is positive definite) and back substitution in LDS.
+// One workgroup per (direction, tile): tiles of the parallel block Jacobi
+// sweep are independent within a sweep (the graph has no edges between
+// them), so each walks its own levels; without tiles the mesh is one tile.
 // ---------------------------------------------------------------------------
 constexpr int GEN_WAVES = 4;
 constexpr int GEN_MAXQ = 12;
@@ -464,7 +467,7 @@ __global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepA
     const T* pbar = reinterpret_cast<const T*>(a.psibar);
     const T* plag = reinterpret_cast<const T*>(a.psi_lag);
     T* psi = reinterpret_cast<T*>(a.psi);
-    const int* lp = a.lev_ptr + (long)d * (a.nlev + 1);
+    const int* lp = a.lev_ptr + ((long)d * a.ntiles + blockIdx.y) * (a.nlev + 1);
     const int* le = a.lev_elem + (long)d * ne;
     for (int l = 0; l < a.nlev; ++l) {
         const int beg = lp[l], end = lp[l + 1];
@@ -557,7 +560,7 @@ __global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepA
 template <typename T, int NB>
 static hipError_t launch_gen_t(const GenSweepArgs& a, hipStream_t s) {
     if (a.nq > GEN_MAXQ || 4 * a.nq > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_general_kernel<T, NB>), dim3(a.nd), dim3(64 * GEN_WAVES), 0, s, a);
+    hipLaunchKernelGGL((sweep_general_kernel<T, NB>), dim3(a.nd, a.ntiles), dim3(64 * GEN_WAVES), 0, s, a);
     return hipGetLastError();
 }
 

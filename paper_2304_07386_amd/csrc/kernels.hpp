@@ -32,6 +32,7 @@ hipError_t launch_sweep_cart(bool fp64, const CartSweepArgs& a, hipStream_t s);
 // upwind matrix in LDS and eliminate it.
 struct GenSweepArgs {
     int ne, nd, nb, nq, nbf, nlev;
+    int ntiles;                  // independent element tiles (1: the full sweep)
     int s_aniso;
     const void* S;
     const void* Mk;              // [ne][n][n]
@@ -43,8 +44,8 @@ struct GenSweepArgs {
     const int* nbr;              // [ne][4]
     const int* bface_of;         // [ne][4]
     const uint8_t* upflag;       // [nd][ne]
-    const int* lev_ptr;          // [nd][nlev+1]
-    const int* lev_elem;         // [nd][ne]
+    const int* lev_ptr;          // [nd][ntiles][nlev+1] offsets into the direction's list
+    const int* lev_elem;         // [nd][ne], tile-major, then level
     const double* omega;         // [nd][3]
     const void* psibar;          // [nd][nbf][nq] or null
     const void* psi_lag;         // [nd][ne][n] or null

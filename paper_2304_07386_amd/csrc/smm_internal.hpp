@@ -70,9 +70,11 @@ struct Problem {
     std::vector<uint8_t> mat_of;           // [ne]
     std::vector<double> Pm, Px, Py;        // [nmat][nd][n][n], [nmat][nd][n][nb] x2
 
-    // general-path sweep graph
-    std::vector<int> lev_ptr;              // [nd][nlev_max+1]
-    std::vector<int> lev_elem;             // [nd][ne]
+    // general-path sweep graph; with tiles (parallel block Jacobi sweep) the
+    // graph has edges only inside tiles of tile_x x tile_y elements
+    int tile_x = 0, tile_y = 0, ntiles = 1;
+    std::vector<int> lev_ptr;              // [nd][ntiles][nlev_max+1]
+    std::vector<int> lev_elem;             // [nd][ne], tile-major, then level
     std::vector<uint8_t> upflag;           // [nd][ne] bit f: neighbour across f is upstream
 
     // materials, sources, inflow

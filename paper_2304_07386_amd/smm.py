@@ -28,7 +28,7 @@ EXPORTED = [
     "smm_problem_destroy", "smm_get_dims", "smm_get_quadrature", "smm_get_nodes", "smm_get_bface_points",
     "smm_set_materials", "smm_set_source", "smm_set_inflow", "smm_default_opts", "smm_solve",
     "smm_get_outputs", "smm_apply_sweep", "smm_apply_moments", "smm_apply_G", "smm_debug_ip_dense",
-    "smm_debug_cg_system", "smm_debug_cg_spmv", "smm_time_cg_spmv",
+    "smm_debug_cg_system", "smm_debug_cg_spmv", "smm_time_cg_spmv", "smm_set_sweep_tiles",
     "smm_set_sweep_path", "smm_time_sweep", "smm_debug_typed_dense", "smm_debug_corr_dense",
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
         "smm_debug_cg_system": (ip, [vp, vp, vp, vp, vp, vp, vp]),
         "smm_debug_cg_spmv": (ip, [vp, vp, vp]),
         "smm_time_cg_spmv": (ip, [vp, ip, dp]),
+        "smm_set_sweep_tiles": (ip, [vp, ip, ip]),
         "smm_set_sweep_path": (ip, [vp, ip]),
         "smm_time_sweep": (ip, [vp, ip, ip, dp]),
         "smm_debug_typed_dense": (ip, [vp, vp, vp, vp]),
@@ -359,6 +360,10 @@ def smm_time_cg_spmv(prob: Problem, reps: int) -> float:
     ms = C.c_double()
     _check(load_library().smm_time_cg_spmv(prob.handle, int(reps), C.byref(ms)), prob.ctx)
     return ms.value
+
+
+def smm_set_sweep_tiles(prob: Problem, tile_nx: int, tile_ny: int):
+    _check(load_library().smm_set_sweep_tiles(prob.handle, int(tile_nx), int(tile_ny)), prob.ctx)
 
 
 def smm_set_sweep_path(prob: Problem, path: int):
