@@ -2776,7 +2776,7 @@ __device__ __forceinline__ void k2_group_mfma(const BatchLaunch& B, const BProb&
 // x += alpha p, r -= alpha q, z = D^-1 r (block-Jacobi) and the group's partial
 // sums of r.z and r.r
 template <int NB>
-__global__ __launch_bounds__(256, 2) void b_cg_k2(BatchLaunch B) {
+__global__ __launch_bounds__(256, NB == 5 ? 3 : 2) void b_cg_k2(BatchLaunch B) {
     constexpr int SL = 64 * (NB * NB | 1);
     __shared__ double lds[4 * SL];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
