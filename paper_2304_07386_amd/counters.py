@@ -16,7 +16,9 @@ hipMemcpy (calibration).  Then, anywhere:
 
 reads the per-dispatch counters (KiB), scales each counter by what it reads
 for the copy of known size, and writes the HBM bytes per launch of each
-kernel, with the SHA-256 of the kernel source they were taken on.
+kernel, with the SHA-256 of the kernel source they were taken on.  Besides
+q = A p and the sweep it records the other kernels of one PCG iteration (the
+update, the direction update and the continuous-space term), per iteration.
 """
 from __future__ import annotations
 
@@ -112,11 +114,20 @@ def parse(dir_fetch, dir_write, out):
         res[which] = {"scale": scale, "copy_kib": big,
                       "b_cg_k1": 1024.0 * scale * sum(spmv) / SPMV_REPS,
                       "b_sweep_kernel": 1024.0 * scale * sum(sw) / SWEEP_REPS}
+        # the other kernels of one PCG iteration, from the short solve (every
+        # problem still iterating): the mean dispatch of each kernel, summed
+        # over the per-order launches
+        for k in ("b_cg_k2", "b_cg_k3g", "cgl_kernel"):
+            per = {}
+            for n, v in disp:
+                if k + "<" in n or (k == "cgl_kernel" and k in n):
+                    per.setdefault(n, []).append(v)
+            res[which][k] = 1024.0 * scale * sum(sum(v) / len(v) for v in per.values())
     src = os.path.join(HERE, "csrc", "kernels.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     table = {}
-    for k in ("b_cg_k1", "b_sweep_kernel"):
+    for k in ("b_cg_k1", "b_sweep_kernel", "b_cg_k2", "b_cg_k3g", "cgl_kernel"):
         table[k] = {"bytes_per_launch": res["fetch"][k] + res["write"][k],
                     "fetch_bytes": res["fetch"][k], "write_bytes": res["write"][k],
                     "source": "kernels.hip", "sha256": sha}
