@@ -2079,131 +2079,6 @@ __device__ __forceinline__ void k1_group_mfma(const BatchLaunch& B, const BProb&
     if (lane == 0) B.gpart[g] = pq;
 }
 
-// The same product with the face vectors loaded element-major and flat
-// (lane-consecutive words): fewer cache lines per load, more index arithmetic
-// per word; the better choice when N is a power of two.
-template <int NB>
-__device__ __forceinline__ void k1_group_mfma_flat(const BatchLaunch& B, const BProb& P, int g, int cnt, double* xs) {
-    constexpr int N = NB * NB, S = N | 1;
-    constexpr int MB = (N + 15) / 16, KS = (N + 3) / 4;
-    const int lane = threadIdx.x & 63;
-    const int i16 = lane & 15, kq = lane >> 4;
-    const int* ty = B.g_ty + g * 5;
-    const int myK = B.g_elem[g * 64 + lane];  // every slot holds a valid element
-    const int tot = cnt * N;
-    const auto pg = as_global((const double*)P.p);
-    // the flat indices are recomputed where used (an opaque copy of the lane
-    // index keeps the compiler from hoisting N of them per use out of the face
-    // loop, which would pin ~4 N registers)
-    auto lane_now = [&]() {
-        int l = lane;
-        asm volatile("" : "+v"(l));
-        return l;
-    };
-    auto load_face = [&](int f, double(&v)[N]) {
-        const int ln = lane_now();
-#pragma unroll
-        for (int it = 0; it < N; ++it) {
-            const int u = ln + 64 * it;
-            const int e = u / N < 64 ? u / N : 63;
-            const int K = __shfl(myK, e);
-            const int src = f == 0 ? K : nbr_of(P, K, f - 1);
-            v[it] = ld_at(pg, u < tot ? (unsigned)(src * N + (u - (u / N) * N)) : 0u);
-        }
-    };
-    auto next_face = [&](int f) {
-        ++f;
-        while (f < 5 && ty[f] < 0) ++f;
-        return f;
-    };
-    v4d acc[MB][4];
-#pragma unroll
-    for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = v4d{0.0, 0.0, 0.0, 0.0};
-    // block entries of face f (column-major: (i, k) at k N + i) as A tiles
-    auto load_blocks = [&](int f, double(&a)[KS][MB]) {
-        const auto A = as_global((f == 0 ? P.ip_self : P.ip_nbr) + (long)ty[f] * N * N);
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-#pragma unroll
-            for (int rb = 0; rb < MB; ++rb) {
-                const int k = 4 * s + kq, r = 16 * rb + i16;
-                const bool in = k < N && r < N;
-                a[s][rb] = ld_at(A, in ? (unsigned)(k * N + r) : 0u);
-                if (!in) a[s][rb] = 0.0;
-            }
-    };
-    double v[N];
-    double a[KS][MB];
-    load_blocks(0, a);
-    load_face(0, v);
-    for (int f = 0; f < 5;) {
-        const int fn = next_face(f);
-        {
-            const int ln = lane_now();
-#pragma unroll
-            for (int it = 0; it < N; ++it) {
-                const int u = ln + 64 * it;
-                if (u < tot) xs[(u / N) * S + (u - (u / N) * N)] = v[it];
-            }
-        }
-        lds_wave_sync();
-        // the next face's blocks and vectors are loaded while this face's
-        // tiles run (unconditionally: after the last face, face 0 again,
-        // unused), so the values just staged are dead and their registers
-        // are reused
-        double an[KS][MB];
-        load_blocks(fn < 5 ? fn : 0, an);
-        load_face(fn < 5 ? fn : 0, v);
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int k = 4 * s + kq;
-            double bf[4];
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb) bf[cb] = k < N ? xs[(16 * cb + i16) * S + k] : 0.0;
-#pragma unroll
-            for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][rb], bf[cb], acc[rb][cb], 0, 0, 0);
-        }
-        lds_wave_sync();
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-#pragma unroll
-            for (int rb = 0; rb < MB; ++rb) a[s][rb] = an[s][rb];
-        f = fn;
-    }
-    // result tiles to LDS (element e = 16 cb + i16, row 16 rb + 4 r + kq)
-#pragma unroll
-    for (int rb = 0; rb < MB; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * rb + 4 * r + kq, e = 16 * cb + i16;
-                if (row < N && e < cnt) xs[e * S + row] = acc[rb][cb][r];
-            }
-    lds_wave_sync();
-    double pq = 0.0;
-    const auto qg = as_global(P.q);
-#pragma unroll
-    for (int it = 0; it < N; ++it) {
-        const int u = lane + 64 * it;
-        const int e = u / N < 64 ? u / N : 63;
-        const int K = __shfl(myK, e);
-        if (u < tot) {
-            const unsigned o = (unsigned)(K * N + (u - (u / N) * N));
-            const double qv = xs[(u / N) * S + (u - (u / N) * N)];
-            st_at(qg, o, qv);
-            pq += ld_at(pg, o) * qv;
-        }
-    }
-    pq = wave_sum(pq);
-    if (lane == 0) B.gpart[g] = pq;
-}
-
 // Block-row product of one group on the FP64 matrix cores, general form:
 // Y (N x 64) = sum over items t < NT of A_t (N x N, column-major) X_t (N x 64),
 // item t being (face f(t), vector v(t)): X_t holds, for element e of the
@@ -2417,9 +2292,7 @@ __global__ __launch_bounds__(256, 2) void b_cg_k1(BatchLaunch B) {
     const int prob = B.g_prob[g];
     if (cg_skip(B, prob)) return;
     const BProb& P = B.P[prob];
-    if constexpr (NB == 4)
-        k1_group_mfma_flat<NB>(B, P, g, B.g_count[g], lds + w * SL);
-    else if constexpr (NB >= 3)
+    if constexpr (NB >= 3)
         k1_group_mfma<NB>(B, P, g, B.g_count[g], lds + w * SL);
     else
         k1_group<NB>(B, P, g, B.g_count[g], lds + w * SL);
