@@ -493,6 +493,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
         GenSweepArgs a{};
         a.ne = P.ne; a.nd = P.nd; a.nb = P.nb; a.nq = P.nq; a.nbf = P.nbf; a.nlev = P.nlev_max;
         a.ntiles = P.ntiles;
+        a.maxw = P.lev_wmax;
         a.s_aniso = s_aniso;
         a.S = S;
         a.Mk = fp64 ? D.Mk64 : D.Mk32;

@@ -642,9 +642,11 @@ void setup_sweep_graph(Problem& P) {
     P.lev_ptr.assign((size_t)nd * nt * (nl + 1), 0);
     P.lev_elem.assign((size_t)nd * ne, 0);
     std::vector<int> cnt((size_t)nt * nl);
+    P.lev_wmax = 0;
     for (int d = 0; d < nd; ++d) {
         std::fill(cnt.begin(), cnt.end(), 0);
         for (int K = 0; K < ne; ++K) ++cnt[(size_t)tile[K] * nl + lev_of[d][K]];
+        for (int c : cnt) P.lev_wmax = std::max(P.lev_wmax, c);
         int pos = 0;
         std::vector<int> start((size_t)nt * nl);
         for (int t = 0; t < nt; ++t)

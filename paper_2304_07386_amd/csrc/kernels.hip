@@ -422,8 +422,16 @@ hipError_t launch_sweep_cart(bool fp64, const CartSweepArgs& a, hipStream_t s) {
 // sweep are independent within a sweep (the graph has no edges between
 // them), so each walks its own levels; without tiles the mesh is one tile.
 // ---------------------------------------------------------------------------
-constexpr int GEN_WAVES = 4;
 constexpr int GEN_MAXQ = 12;
+// waves per workgroup (one element each): as many as keep the per-wave LDS
+// (the augmented n x (n+1) system, the solution, face data) within 64 KB
+template <typename T, int NB>
+constexpr int gen_waves() {
+    constexpr int N = NB * NB;
+    constexpr int per = (int)sizeof(T) * (N * (N + 1) + N + 8 * GEN_MAXQ);
+    constexpr int w = (64 * 1024) / per;
+    return w >= 16 ? 16 : (w >= 8 ? 8 : 4);
+}
 
 template <int NB>
 __device__ __forceinline__ int face_pos(int f, int i) {
@@ -446,7 +454,7 @@ __device__ __forceinline__ int face_node(int f, int c) {
     }
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int GEN_WAVES = gen_waves<T, NB>()>
 __global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepArgs a) {
     constexpr int N = NB * NB;
     const int d = blockIdx.x;
@@ -560,7 +568,14 @@ __global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepA
 template <typename T, int NB>
 static hipError_t launch_gen_t(const GenSweepArgs& a, hipStream_t s) {
     if (a.nq > GEN_MAXQ || 4 * a.nq > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_general_kernel<T, NB>), dim3(a.nd, a.ntiles), dim3(64 * GEN_WAVES), 0, s, a);
+    // few workgroups (whole-mesh sweeps: one per direction) take the widest
+    // workgroup their levels fill; many (tiles) take 4 waves, so that more
+    // workgroups share each CU
+    constexpr int WV = gen_waves<T, NB>();
+    if (a.nd * a.ntiles < 512 && a.maxw > 4)
+        hipLaunchKernelGGL((sweep_general_kernel<T, NB, WV>), dim3(a.nd, a.ntiles), dim3(64 * WV), 0, s, a);
+    else
+        hipLaunchKernelGGL((sweep_general_kernel<T, NB, 4>), dim3(a.nd, a.ntiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

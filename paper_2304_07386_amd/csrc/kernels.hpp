@@ -33,6 +33,7 @@ hipError_t launch_sweep_cart(bool fp64, const CartSweepArgs& a, hipStream_t s);
 struct GenSweepArgs {
     int ne, nd, nb, nq, nbf, nlev;
     int ntiles;                  // independent element tiles (1: the full sweep)
+    int maxw;                    // most elements in one level of one (direction, tile)
     int s_aniso;
     const void* S;
     const void* Mk;              // [ne][n][n]

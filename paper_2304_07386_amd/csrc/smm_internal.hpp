@@ -73,6 +73,7 @@ struct Problem {
     // general-path sweep graph; with tiles (parallel block Jacobi sweep) the
     // graph has edges only inside tiles of tile_x x tile_y elements
     int tile_x = 0, tile_y = 0, ntiles = 1;
+    int lev_wmax = 0;                      // most elements in one level of one (direction, tile)
     std::vector<int> lev_ptr;              // [nd][ntiles][nlev_max+1]
     std::vector<int> lev_elem;             // [nd][ne], tile-major, then level
     std::vector<uint8_t> upflag;           // [nd][ne] bit f: neighbour across f is upstream
