@@ -92,6 +92,19 @@ def traffic_for(kernel: str):
     return ent["bytes_per_launch"]
 
 
+def issued_for(kernel: str, ms: float):
+    """Issued floating-point rate from the committed counter table (taken on
+    the current kernel source), or None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if traffic_for(kernel) is None or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        ent = json.load(f).get(kernel, {})
+    if "issued_flops_per_launch" not in ent:
+        return None
+    return {"issued_tflops": ent["issued_flops_per_launch"] / (ms * 1e-3) / 1e12, "kind": ent["kind"]}
+
+
 def roofline(kernel: str, what: str, bytes_per_launch: float, ms: float):
     """`kernel` is the name prefix of the launches timed together as one
     operation (`what`): one sweep, or one q = A p, runs one launch per order
@@ -100,7 +113,8 @@ def roofline(kernel: str, what: str, bytes_per_launch: float, ms: float):
     tr = traffic_for(kernel)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": kernel, "operation": what,
-            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": ms}
+            "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": ms,
+            "counted": issued_for(kernel, ms)}
 
 
 def roofline_flops(kernel: str, what: str, flops_per_launch: float, bytes_per_launch: float, ms: float):
@@ -112,7 +126,7 @@ def roofline_flops(kernel: str, what: str, flops_per_launch: float, bytes_per_la
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_for(kernel), "kernel": kernel,
             "operation": what, "algorithmic_flops_per_launch": flops_per_launch,
             "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": ms,
-            "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+            "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "counted": issued_for(kernel, ms)}
 
 
 def time_to_solution(L, ctx, n: int, log):

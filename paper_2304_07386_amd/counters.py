@@ -16,7 +16,9 @@ hipMemcpy (calibration).  Then, anywhere:
 
 reads the per-dispatch counters (KiB), scales each counter by what it reads
 for the copy of known size, and writes the HBM bytes per launch of each
-kernel, with the SHA-256 of the kernel source they were taken on.  Besides
+kernel, with the SHA-256 of the kernel source they were taken on.  An
+optional third pass (`--pmc` with FLOP_COUNTERS, parsed with `--flops`) adds
+the floating-point work the hardware issued for q = A p and the sweep.  Besides
 q = A p and the sweep it records the other kernels of one PCG iteration (the
 update, the direction update and the continuous-space term), per iteration.
 """
@@ -94,7 +96,41 @@ def _per_dispatch(rows):
     return [tuple(acc[k]) for k in sorted(order)]
 
 
-def parse(dir_fetch, dir_write, out):
+FLOP_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32",
+                 "SQ_INSTS_VALU_MUL_F32")
+
+
+def _per_dispatch_counters(rows):
+    """[(kernel name, {counter: value})] in dispatch order."""
+    acc = {}
+    for r in rows:
+        key = int(r.get("Dispatch_Id", r.get("Correlation_Id", 0)))
+        ent = acc.setdefault(key, [r["Kernel_Name"], {}])
+        ent[1][r["Counter_Name"]] = ent[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [tuple(acc[k]) for k in sorted(acc)]
+
+
+def issued_flops(dir_flops):
+    """Issued floating-point work per operation from a third counter pass
+    (FLOP_COUNTERS): FP64 matrix-core work is SQ_INSTS_VALU_MFMA_MOPS_F64 x
+    512 (the counter's unit); FP32 vector work counts every lane of the
+    issued FMA (2 flops), ADD and MUL instructions (64 lanes each: an upper
+    bound where waves are partly masked)."""
+    disp = _per_dispatch_counters(_rows(dir_flops))
+    k1 = [(n, c) for n, c in disp if "b_cg_k1" in n]
+    nvar = len({n for n, c in k1})
+    spmv = [c for n, c in k1[-SPMV_REPS * nvar:]]
+    sw = [c for n, c in disp if "b_sweep_kernel" in n][-SWEEP_REPS * sweep_launches():]
+    mfma = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for c in spmv) * 512.0 / SPMV_REPS
+    f32 = sum(64.0 * (2.0 * c.get("SQ_INSTS_VALU_FMA_F32", 0.0) + c.get("SQ_INSTS_VALU_ADD_F32", 0.0)
+                      + c.get("SQ_INSTS_VALU_MUL_F32", 0.0)) for c in sw) / SWEEP_REPS
+    fma_insts = sum(c.get("SQ_INSTS_VALU_FMA_F32", 0.0) for c in sw) / SWEEP_REPS
+    return {"b_cg_k1": {"issued_flops_per_launch": mfma, "kind": "FP64 MFMA (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512)"},
+            "b_sweep_kernel": {"issued_flops_per_launch": f32, "fma_wave_instructions": fma_insts,
+                               "kind": "FP32 VALU lane slots (64 x (2 FMA + ADD + MUL) instructions)"}}
+
+
+def parse(dir_fetch, dir_write, out, dir_flops=None):
     res = {}
     for which, d in (("fetch", dir_fetch), ("write", dir_write)):
         disp = _per_dispatch(_rows(d))
@@ -131,6 +167,9 @@ def parse(dir_fetch, dir_write, out):
         table[k] = {"bytes_per_launch": res["fetch"][k] + res["write"][k],
                     "fetch_bytes": res["fetch"][k], "write_bytes": res["write"][k],
                     "source": "kernels.hip", "sha256": sha}
+    if dir_flops:
+        for k, v in issued_flops(dir_flops).items():
+            table[k].update(v)
     table["_calibration"] = {"copy_bytes": COPY_BYTES, "fetch_scale": res["fetch"]["scale"],
                              "write_scale": res["write"]["scale"]}
     with open(out, "w") as f:
@@ -145,12 +184,13 @@ def main(argv=None):
     p = sub.add_parser("parse")
     p.add_argument("dir_fetch")
     p.add_argument("dir_write")
+    p.add_argument("--flops", default=None, help="directory of a third pass with the FLOP_COUNTERS")
     p.add_argument("--out", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "run":
         run()
     else:
-        parse(a.dir_fetch, a.dir_write, a.out)
+        parse(a.dir_fetch, a.dir_write, a.out, a.flops)
     return 0
 
 
