@@ -45,6 +45,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64, matrix cores and vector units alike
 METRIC = "sweep elem*angle*DOF/s + time-to-1e-8 SMM solve, plain vs batched+warm"
+# The paper's own figures (CPU runs), as context only: derived sweep rate of
+# the weak-scaling study on one processor (crooked pipe, p = 2, S12: scalar
+# DOF x 84 directions / average sweep time per outer iteration, Table
+# tab:weak_time) and its outer iterations with the parallel block Jacobi sweep
+# (Table tab:weak_itr).
+PAPER_CONTEXT = {
+    "sweep_units_per_s": 3.57e5,
+    "sweep_units_per_s_1024_procs": 2.31e8,
+    "hardware": "Intel Xeon E5-2695 nodes (LLNL rztopaz), one processor / 1024 processors; precision not stated",
+    "workload": "crooked pipe, p = 2, S12, parallel block Jacobi sweep, 4032 DOF per processor",
+    "block_jacobi_outer_iterations_1_to_1024_procs": [32, 55, 80, 135, 277, 592],
+    "source": "Tables tab:weak_time and tab:weak_itr (Sec. 6.5)",
+}
 
 
 def log(msg):
@@ -383,6 +396,7 @@ def main():
         "roofline": dominant,
         "roofline_sweep": rl_sweep,
         "roofline_pcg_spmv": rl_spmv,
+        "paper_context": PAPER_CONTEXT,
         "time_to_1e-8": tts,
         "moment_discretisations": disc,
         "block_jacobi_sweeps": tiles,
