@@ -128,3 +128,25 @@ def test_warmstart_calls_need_a_device(hctx):
     assert lib.smm_cnn_create(hctx.handle, 2, ch, 8, 8, 4, C.byref(h)) == L.SMM_ESTATE
     assert lib.smm_cnn_create(hctx.handle, 0, ch, 8, 8, 4, C.byref(h)) in (L.SMM_ESTATE, L.SMM_EINVAL)
     assert lib.smm_batch_warmstart_used(None, None) == L.SMM_EINVAL
+
+
+def test_tiles_and_cg_calls_on_the_host(hctx):
+    """smm_set_sweep_tiles validates its sizes; the continuous system and
+    the tiles are set-up work, so a host-only context accepts them, while the
+    device calls that use them are refused."""
+    wl = config_plain(n=4, p=2)
+    p = L.problem_from_workload(hctx, wl)
+    for bad in ((-1, 2), (2, 0), (0, 3)):
+        with pytest.raises(L.SmmError) as e:
+            L.smm_set_sweep_tiles(p, *bad)
+        assert e.value.code == L.SMM_EINVAL
+    L.smm_set_sweep_tiles(p, 2, 2)
+    L.smm_set_sweep_tiles(p, 0, 0)
+    rowptr, col, val, cmap = L.smm_debug_cg_system(p)
+    assert len(rowptr) == (4 * 2 + 1) ** 2 + 1 and cmap.max() == (4 * 2 + 1) ** 2 - 1
+    with pytest.raises(L.SmmError) as e:
+        L.smm_debug_cg_spmv(p, np.ones(len(rowptr) - 1))
+    assert e.value.code == L.SMM_ESTATE
+    with pytest.raises(L.SmmError) as e:
+        L.smm_solve(p, L.smm_default_opts(discretization=L.SMM_DISC_CG))
+    assert e.value.code == L.SMM_ESTATE
