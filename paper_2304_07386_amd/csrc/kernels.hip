@@ -3482,9 +3482,19 @@ __global__ __launch_bounds__(BT) void b_aa_gram_part(BatchLaunch B, double* part
         v[4] = f1 * f2;
         v[5] = f2 * f2;
     }
+    // the six sums in one pass: within each wave by shuffles, then the four
+    // wave sums in wave order
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const double s = b_block_sum(v[k], red);
-        if (threadIdx.x == 0) part6[(long)k * B.nblocks + blockIdx.x] = s;
+        v[k] = wave_sum(v[k]);
+        if (lane == 0) red[k * (BT / 64) + wv] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double s = 0.0;
+        for (int w = 0; w < BT / 64; ++w) s += red[threadIdx.x * (BT / 64) + w];
+        part6[(long)threadIdx.x * B.nblocks + blockIdx.x] = s;
     }
 }
 
@@ -3560,23 +3570,38 @@ __global__ __launch_bounds__(BT) void b_resid_part(BatchLaunch B) {
     }
 }
 
-__global__ __launch_bounds__(64) void b_resid_final(BatchLaunch B, double* out) {
-    const int prob = blockIdx.x * 64 + threadIdx.x;
-    if (prob >= B.nprob) return;
+// one workgroup per problem: max over the problem's block partials (a
+// maximum does not depend on the order, NaN propagates)
+__global__ __launch_bounds__(BT) void b_resid_final(BatchLaunch B, double* out) {
+    __shared__ double r0[BT], r1[BT];
+    const int prob = blockIdx.x;
     const BProb& P = B.P[prob];
     double a = 0, b = 0;
-    for (int k = 0; k < P.nblk; ++k) {
+    for (int k = threadIdx.x; k < P.nblk; k += BT) {
         const double x0 = B.part[P.blk0 + k], x1 = B.part[B.nblocks + P.blk0 + k];
         a = (x0 > a || x0 != x0) ? x0 : a;
         b = (x1 > b || x1 != x1) ? x1 : b;
     }
-    out[2 * prob] = a;
-    out[2 * prob + 1] = b;
+    r0[threadIdx.x] = a;
+    r1[threadIdx.x] = b;
+    __syncthreads();
+    for (int st = BT / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            const double x0 = r0[threadIdx.x + st], x1 = r1[threadIdx.x + st];
+            r0[threadIdx.x] = (x0 > r0[threadIdx.x] || x0 != x0) ? x0 : r0[threadIdx.x];
+            r1[threadIdx.x] = (x1 > r1[threadIdx.x] || x1 != x1) ? x1 : r1[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * prob] = r0[0];
+        out[2 * prob + 1] = r1[0];
+    }
 }
 
 hipError_t b_residual(const BatchLaunch& B, double* out, hipStream_t s) {
     hipLaunchKernelGGL(b_resid_part, dim3(B.nblocks), dim3(BT), 0, s, B);
-    hipLaunchKernelGGL(b_resid_final, dim3((B.nprob + 63) / 64), dim3(64), 0, s, B, out);
+    hipLaunchKernelGGL(b_resid_final, dim3(B.nprob), dim3(BT), 0, s, B, out);
     return hipGetLastError();
 }
 
