@@ -1160,6 +1160,12 @@ __device__ __forceinline__ EB eb_map(const BatchLaunch& B) {
     return r;
 }
 
+// sum over the 64 lanes of a wave (butterfly; every lane gets the sum)
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // grouped FP64 matrix-core block-row products (defined with the PCG kernels):
 // MODE 0: r = b - A x (PCG start), MODE 1: IP right-hand side
 template <int MODE>
@@ -1808,30 +1814,44 @@ __global__ __launch_bounds__(BT) void b_cg_init1(BatchLaunch B) {
     P.r[t] = P.b[t] - typed_row(P, P.x, m.K, m.i);
 }
 
+// z = D^-1 r, p = z, and the block's partial sums of r.z, r.r, b.b.  The
+// block's residuals are staged in LDS (one coalesced load each), the three
+// sums reduced in one pass: by shuffles within each wave, then over the
+// waves in wave order.
 __global__ __launch_bounds__(BT) void b_cg_init2(BatchLaunch B) {
-    __shared__ double red[BT];
+    __shared__ double red[3 * (BT / 64)];
+    __shared__ double rl[BT];
     const EB m = eb_map(B);
-    double rz = 0, rr = 0, bb = 0;
-    if (B.active[m.prob] && m.K >= 0) {
-        const BProb& P = B.P[m.prob];
+    const bool act = B.active[m.prob] && m.K >= 0;
+    const BProb& P = B.P[m.prob];
+    const long t = act ? (long)m.K * P.n + m.i : 0;
+    const double rv = act ? P.r[t] : 0.0;
+    rl[threadIdx.x] = rv;
+    __syncthreads();
+    double v[3] = {0.0, 0.0, 0.0};
+    if (act) {
         const int n = P.n;
-        const long t = (long)m.K * n + m.i;
         const double* D = P.dinv + (long)P.sid[m.K] * n * n + m.i;
         double z = 0;
-        for (int j = 0; j < n; ++j) z += D[j * n] * P.r[(long)m.K * n + j];
+        for (int j = 0; j < n; ++j) z += D[j * n] * rl[m.e0 + j];
         P.z[t] = z;
         P.p[t] = z;
-        rz = P.r[t] * z;
-        rr = P.r[t] * P.r[t];
-        bb = P.b[t] * P.b[t];
+        const double bv = P.b[t];
+        v[0] = rv * z;
+        v[1] = rv * rv;
+        v[2] = bv * bv;
     }
-    rz = b_block_sum(rz, red);
-    rr = b_block_sum(rr, red);
-    bb = b_block_sum(bb, red);
-    if (threadIdx.x == 0) {
-        B.part[blockIdx.x] = rz;
-        B.part[B.nblocks + blockIdx.x] = rr;
-        B.part[2 * B.nblocks + blockIdx.x] = bb;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = wave_sum(v[k]);
+        if (lane == 0) red[k * (BT / 64) + wv] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double sum = 0.0;
+        for (int w = 0; w < BT / 64; ++w) sum += red[threadIdx.x * (BT / 64) + w];
+        B.part[(long)threadIdx.x * B.nblocks + blockIdx.x] = sum;
     }
 }
 
@@ -1866,10 +1886,6 @@ __global__ __launch_bounds__(BT) void b_cg_red_init(BatchLaunch B, double tol) {
 // their self and four face couplings, so the block entries are wave-uniform and
 // come through scalar loads (SGPR operands of the FMAs), while each lane keeps
 // one element's vectors in registers.
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
 
 // y += A x with A column-major [N][N] (entry (i, j) at j N + i) and x read
 // from memory one entry per step (rolled loop over j, y in registers).  A is
