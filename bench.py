@@ -347,6 +347,12 @@ def main():
     sweep_bytes = float(sum(p.n_elem * p.n_node * (4.0 * p.n_dir + 4.0) for p in probs))
     rl_sweep = roofline("b_sweep_kernel", "one batched sweep (the per-order launches b_sweep_kernel<T, NB, ...>)",
                         sweep_bytes, sweep_ms)
+    # the same sweep against the unit-rate roofline of the method: 8 B per
+    # elem*angle*DOF in FP32 (psi written by the sweep and read back by the
+    # moment contraction) at 8 TB/s is 1.0e12 units/s
+    rl_sweep["units_per_s"] = units / (sweep_ms * 1e-3)
+    rl_sweep["units_roofline"] = HBM_PEAK_GBS * 1e9 / 8.0
+    rl_sweep["units_frac"] = rl_sweep["units_per_s"] / rl_sweep["units_roofline"]
     spmv_ms = L.smm_batch_time_kernel(batch, L.SMM_KERNEL_CG_SPMV, 50)
     # q = A p: p read once and q written once, FP64 (16 B/DOF)
     # q = A p: p read once and q written once, FP64 (16 B/DOF); 2 N^2 flops per
