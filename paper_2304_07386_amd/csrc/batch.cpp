@@ -915,6 +915,12 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
     const BatchLaunch L = launch_desc(B);
     HIPCHK(c, b_cg_start(L, tol, c->stream, &B->mgl));
     std::vector<double> sc(16 * (size_t)B->nprob);
+    // per problem, r.r and the iteration count at the previous check: their
+    // ratio gives the residual's reduction per iteration, from which the
+    // next chunk is sized so that it ends about when the slowest problem
+    // converges (a chunk that overshoots runs iterations with nothing left
+    // to do; one that falls short costs one more host round trip)
+    std::vector<double> rr_prev(B->nprob, -1.0), it_prev(B->nprob, 0.0);
     int done_its = 0, chunk = 4;
     while (true) {
         HIPCHK(c, hipMemcpyAsync(sc.data(), B->d_scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, c->stream));
@@ -930,6 +936,27 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
             }
         }
         if (all || done_its >= max_inner) break;
+        if (done_its > 0) {
+            int need = 1;
+            for (int b = 0; b < B->nprob; ++b) {
+                const double* q = &sc[16 * (size_t)b];
+                if (!B->active[b] || q[4] != 0.0) continue;
+                const double rr = q[3], target = q[7], di = q[5] - it_prev[b];
+                int nb = 16;
+                if (rr_prev[b] > 0.0 && rr > 0.0 && rr < rr_prev[b] && di > 0.0 && target > 0.0) {
+                    const double per = std::log(rr / rr_prev[b]) / di;  // < 0
+                    nb = (int)std::ceil(std::log(target / rr) / per);
+                }
+                need = std::max(need, std::min(std::max(nb, 1), 16));
+            }
+            // a power of two at most need (few distinct chunk graphs)
+            chunk = 1;
+            while (chunk * 2 <= need) chunk *= 2;
+        }
+        for (int b = 0; b < B->nprob; ++b) {
+            rr_prev[b] = sc[16 * (size_t)b + 3];
+            it_prev[b] = sc[16 * (size_t)b + 5];
+        }
         const int k = std::min(chunk, max_inner - done_its);
         // the grouped kernels of orders whose problems have all converged are
         // not launched (they would only check the flags and return)
@@ -962,10 +989,6 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
         }
         done_its += k;
         B->cg_batched_its += k;
-        // convergence is checked between chunks: larger chunks cost fewer
-        // host round trips, smaller ones fewer iterations past the last
-        // problem's convergence
-        chunk = std::min(chunk * 2, 16);
     }
     its.assign(B->nprob, 0);
     for (int b = 0; b < B->nprob; ++b) its[b] = (int)sc[16 * b + 5];
