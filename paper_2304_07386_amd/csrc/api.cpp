@@ -765,7 +765,11 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
         rabs = ro[0];
         r = ro[1] > 0 ? ro[0] / ro[1] : (ro[0] == 0 ? 0.0 : INFINITY);
         if (!std::isfinite(r) || !std::isfinite(rabs)) { status = SMM_ENAN; break; }
-        if (r < o.outer_tol) { status = SMM_OK; break; }
+        // with adaptive inner tolerances, convergence counts only from a
+        // moment solve as tight as the target residual asks for (a looser
+        // solve can stop before moving X); else one more, tighter, iteration
+        const double tight = o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt * o.outer_tol) : o.inner_tol;
+        if (r < o.outer_tol && tol_k <= tight) { status = SMM_OK; break; }
         r_prev = r;
     }
     D.last_varphi = D.varphi;

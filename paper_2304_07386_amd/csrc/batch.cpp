@@ -1246,7 +1246,14 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
             inf[b].residual_abs = rabs;
             inf[b].cg_iterations_total += its[b];
             inf[b].cg_iterations_max = std::max(inf[b].cg_iterations_max, its[b]);
-            if (!std::isfinite(r) || r < o.outer_tol) {
+            // with adaptive inner tolerances a small change can come from a
+            // moment solve that stopped early (its start was already within
+            // the loose tolerance); convergence counts only from a solve as
+            // tight as the one the target residual itself would ask for,
+            // else one more iteration runs, with that tolerance
+            const double tight = o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt * o.outer_tol) : o.inner_tol;
+            const bool trusted = o.inner_adapt <= 0 || tol_k[b] <= tight;
+            if (!std::isfinite(r) || (r < o.outer_tol && trusted)) {
                 B->active[b] = 0;
                 --nactive;
                 changed = true;

@@ -1,0 +1,75 @@
+"""The full 256-problem batch in the configuration bench.py times, and a
+degenerate case, against the oracle.
+
+* The batch of seeds 0..255 (16^2..128^2, p = 1..4, S4..S12) solved to a
+  1e-8 outer residual with FP32 delta sweeps, two-level PCG, Anderson mixing
+  and graph-replayed PCG chunks: every problem converges to finite values,
+  and three members the oracle can solve in seconds (seeds 133, 196, 10:
+  17^2 p = 1 S4, 16^2 p = 2 S6, 19^2 p = 3 S4), solved inside that batch,
+  match the oracle's converged flux to the FP32 bar (1e-5 relative L2).
+* No scattering (sigma_s = 0): G does not depend on X, so the second outer
+  iterate equals the first (up to the rounding of the second moment solve),
+  and the transport scalar flux is one sweep of q.
+"""
+import numpy as np
+import pytest
+
+from oracle import smm as osmm
+from oracle import transport
+from workloads import config_batched_problem, config_channel
+
+from .gpu_common import announce, rel_l2
+
+torch = pytest.importorskip("torch")
+L = pytest.importorskip("paper_2304_07386_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return L.smm_ctx_create(0, torch.cuda.current_stream())
+
+
+def test_full_batch_sampled_members(ctx):
+    announce("full 256-problem batch, FP32 delta sweeps, two-level PCG, Anderson, graphs; sampled members")
+    wls = [config_batched_problem(s) for s in range(256)]
+    probs = [L.problem_from_workload(ctx, wl) for wl in wls]
+    batch = L.smm_batch_create(ctx, probs)
+    opts = L.smm_default_opts(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=1e-8, inner_tol=1e-10,
+                              inner_adapt=1e-2, max_inner=20000, max_outer=80, precond=L.SMM_PRECOND_TWOLEVEL,
+                              use_graph=1, anderson=2)
+    rc, infos = L.smm_batch_solve(batch, opts)
+    assert rc == L.SMM_OK and all(i["residual"] < 1e-8 for i in infos)
+    for k in range(256):
+        v = np.zeros(probs[k].n_elem * probs[k].n_node)
+        L.smm_batch_get_outputs(batch, k, varphi=v)
+        assert np.all(np.isfinite(v)) and v.max() > 0, k
+    for s in (133, 196, 10):
+        ref, info = osmm.solve(osmm.make_problem(wls[s]), tol=1e-11, max_it=100)
+        assert info["converged"]
+        v = np.zeros(probs[s].n_elem * probs[s].n_node)
+        L.smm_batch_get_outputs(batch, s, varphi=v)
+        assert rel_l2(v, ref) < 1e-5, (s, rel_l2(v, ref))
+    L.smm_batch_destroy(batch)
+
+
+def test_no_scattering_two_iterations(ctx):
+    announce("sigma_s = 0: two outer iterations, phi = one sweep of q")
+    wl = config_channel(n=8, p=2, sn=4, side=1.3)
+    wl.sigma_s = np.zeros(wl.n_elem)
+    pr = osmm.make_problem(wl)
+    p = L.problem_from_workload(ctx, wl, q=pr.q)
+    rc, info = L.smm_solve(p, L.smm_default_opts(precision=L.SMM_FP64, outer_tol=1e-12, inner_tol=1e-15,
+                                                  max_inner=5000))
+    # the second moment solve starts from the first's answer: the change is
+    # rounding only (well below the 1e-12 outer tolerance)
+    assert rc == L.SMM_OK and info["iterations"] == 2 and info["residual"] < 1e-13
+    out = L.smm_get_outputs_host(p)
+    psi = transport.sweep(pr.mesh, pr.omega, pr.sigma_t, pr.q, pr.psibar)
+    phi = np.einsum("d,dkn->kn", pr.w, psi).ravel()
+    assert rel_l2(out["phi"], phi) < 1e-12
+    ref, _ = osmm.solve(pr, tol=1e-14, max_it=5)
+    assert rel_l2(out["varphi"], ref) < 1e-12
