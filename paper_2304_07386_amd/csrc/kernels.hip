@@ -2795,13 +2795,19 @@ __global__ __launch_bounds__(256) void b_cg_k3g(BatchLaunch B, MGLaunch M) {
     const double beta = P.scal[9];
     const auto zg = as_global((const double*)P.z);
     const auto pg = as_global(P.p);
-    // vertex of the element's lower-left corner on the level-0 grid
-    int nvx = 0, myV = 0;
+    // per lane (element): the vertex of its lower-left corner on the level-0
+    // grid and its lower-left node on the continuous grid; a node (a, b) of
+    // the element is then base + b gx + a (NB is a constant, so no division
+    // per node)
+    int nvx = 0, myV = 0, myC = 0, gx = 0;
     const double* x0 = nullptr;
     double gl[NB];
     if (B.mg) {
         nvx = M.lev[0].dims[2 * prob];
-        myV = (myK / P.nx) * nvx + myK % P.nx;
+        const int ey = myK / P.nx, ex = myK - ey * P.nx;
+        myV = ey * nvx + ex;
+        gx = P.nx * (NB - 1) + 1;
+        myC = ey * (NB - 1) * gx + ex * (NB - 1);
         x0 = mg_x0(M, prob);
 #pragma unroll
         for (int a = 0; a < NB; ++a) gl[a] = P.gll[a];
@@ -2813,6 +2819,7 @@ __global__ __launch_bounds__(256) void b_cg_k3g(BatchLaunch B, MGLaunch M) {
         const int j = u - (u / N) * N;
         const int K = __shfl(myK, e);
         const int V = __shfl(myV, e);
+        const int Cb = __shfl(myC, e);
         if (u < tot) {
             const unsigned o = (unsigned)(K * N + j);
             double z = ld_at(zg, o);
@@ -2821,7 +2828,7 @@ __global__ __launch_bounds__(256) void b_cg_k3g(BatchLaunch B, MGLaunch M) {
                 const double* xv = x0 + V;
                 z += (1.0 - xa) * (1.0 - yb) * xv[0] + xa * (1.0 - yb) * xv[1] + (1.0 - xa) * yb * xv[nvx] +
                      xa * yb * xv[nvx + 1];
-                if (P.cgw) z += P.cgw[cg_node(P, K, j)];
+                if (P.cgw) z += P.cgw[Cb + (j / NB) * gx + j % NB];
             }
             st_at(pg, o, z + beta * ld_at(pg, o));
         }
