@@ -578,7 +578,7 @@ static CgsArgs cgs_args(smm_problem* pr) {
 // The CG moment solve: restrict the DG right-hand side D.b to V_p, start from
 // the DG iterate in D.x (continuous after the first CG solve, so its node
 // values are exact), Jacobi-PCG, and return the DG values P_c c in D.x.
-static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its, bool graph) {
+static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its, bool graph, bool* conv = nullptr) {
     Dev& D = pr->D;
     smm_ctx* c = pr->P.ctx;
     const CgsArgs a = cgs_args(pr);
@@ -623,10 +623,11 @@ static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its,
     }
     HIPCHK(c, cgs_scatter(a, D.x, c->stream));
     *its = done;
+    if (conv) *conv = sc[4] != 0.0;
     return SMM_OK;
 }
 
-static int moment_solve(smm_problem* pr, double tol, int max_inner, int* its) {
+static int moment_solve(smm_problem* pr, double tol, int max_inner, int* its, bool* conv = nullptr) {
     Problem& P = pr->P;
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
@@ -647,13 +648,14 @@ static int moment_solve(smm_problem* pr, double tol, int max_inner, int* its) {
         chunk = std::min(chunk * 2, 64);
     }
     *its = done_its;
+    if (conv) *conv = sc[4] != 0.0 && sc[6] == 0.0;
     return SMM_OK;
 }
 
 // One evaluation of G from D.varphi into D.x (b, closures, moments updated).
 // psi_cur / psi_prev are sweep buffers; delta mode sweeps sigma_s/(4pi)(varphi - varphi_prev).
 static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, double inner_tol, int max_inner,
-                  int* cg_its, bool cgdisc = false, bool graph = false) {
+                  int* cg_its, bool cgdisc = false, bool graph = false, bool* conv = nullptr) {
     Problem& P = pr->P;
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
@@ -688,8 +690,8 @@ static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, d
                          c->stream));
     // moment solve (a6), warm-started from the current iterate
     HIPCHK(c, hipMemcpyAsync(D.x, D.varphi, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
-    return cgdisc ? cg_moment_solve(pr, inner_tol, max_inner, cg_its, graph)
-                  : moment_solve(pr, inner_tol, max_inner, cg_its);
+    return cgdisc ? cg_moment_solve(pr, inner_tol, max_inner, cg_its, graph, conv)
+                  : moment_solve(pr, inner_tol, max_inner, cg_its, conv);
 }
 
 extern "C" {
@@ -750,7 +752,9 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     for (it = 1; it <= o.max_outer; ++it) {
         int cgi = 0;
         const double tol_k = o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt * r_prev) : o.inner_tol;
-        if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, tol_k, o.max_inner, &cgi, cgdisc, o.use_graph != 0)))
+        bool inner_ok = true;
+        if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, tol_k, o.max_inner, &cgi, cgdisc, o.use_graph != 0,
+                         &inner_ok)))
             return rc;
         cg_total += cgi;
         cg_max = std::max(cg_max, cgi);
@@ -769,7 +773,7 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
         // moment solve as tight as the target residual asks for (a looser
         // solve can stop before moving X); else one more, tighter, iteration
         const double tight = o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt * o.outer_tol) : o.inner_tol;
-        if (r < o.outer_tol && tol_k <= tight) { status = SMM_OK; break; }
+        if (r < o.outer_tol && tol_k <= tight && inner_ok) { status = SMM_OK; break; }
         r_prev = r;
     }
     D.last_varphi = D.varphi;

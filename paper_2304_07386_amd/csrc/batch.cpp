@@ -170,6 +170,7 @@ struct smm_batch {
     bool use_graph = false;
     hipStream_t cap = nullptr;
     std::map<std::tuple<int, bool, bool, int>, hipGraphExec_t> cg_graphs;  // (chunk, tolerances, two-level, orders)
+    std::vector<uint8_t> cg_conv;  // per problem: the last PCG reached its tolerance
 };
 
 namespace {
@@ -991,7 +992,11 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
         B->cg_batched_its += k;
     }
     its.assign(B->nprob, 0);
-    for (int b = 0; b < B->nprob; ++b) its[b] = (int)sc[16 * b + 5];
+    B->cg_conv.assign(B->nprob, 0);
+    for (int b = 0; b < B->nprob; ++b) {
+        its[b] = (int)sc[16 * b + 5];
+        B->cg_conv[b] = sc[16 * b + 4] != 0.0 ? 1 : 0;
+    }
     return SMM_OK;
 }
 
@@ -1252,7 +1257,9 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
             // tight as the one the target residual itself would ask for,
             // else one more iteration runs, with that tolerance
             const double tight = o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt * o.outer_tol) : o.inner_tol;
-            const bool trusted = o.inner_adapt <= 0 || tol_k[b] <= tight;
+            // and only from a moment solve that reached its tolerance (not
+            // one stopped by max_inner)
+            const bool trusted = (o.inner_adapt <= 0 || tol_k[b] <= tight) && B->cg_conv[b];
             if (!std::isfinite(r) || (r < o.outer_tol && trusted)) {
                 B->active[b] = 0;
                 --nactive;

@@ -73,3 +73,20 @@ def test_no_scattering_two_iterations(ctx):
     assert rel_l2(out["phi"], phi) < 1e-12
     ref, _ = osmm.solve(pr, tol=1e-14, max_it=5)
     assert rel_l2(out["varphi"], ref) < 1e-12
+
+
+@pytest.mark.parametrize("path", ["typed", "per_element", "cg"])
+def test_capped_inner_solve_never_converges(ctx, path):
+    """Moment solves stopped by max_inner (one PCG iteration each) do not
+    count as converged outer iterations: the solve ends with SMM_ENOCONV and
+    valid outputs, whatever the outer change."""
+    announce(f"capped inner solves ({path}) -> SMM_ENOCONV")
+    wl = config_channel(n=6, p=2, sn=4, side=1.3)
+    pr = osmm.make_problem(wl)
+    p = L.problem_from_workload(ctx, wl, q=pr.q)
+    kw = {"typed": {}, "per_element": dict(moment_path=1), "cg": dict(discretization=L.SMM_DISC_CG)}[path]
+    opts = L.smm_default_opts(precision=L.SMM_FP64, outer_tol=1e-3, inner_tol=1e-12, max_inner=1, max_outer=12,
+                              **kw)
+    rc, info = L.smm_solve(p, opts, raise_on_noconv=False)
+    assert rc == L.SMM_ENOCONV and info["iterations"] == 12
+    assert np.all(np.isfinite(L.smm_get_outputs_host(p)["varphi"]))
