@@ -86,6 +86,18 @@ def cpu_baseline(workloads, max_dirs: int = 12):
                         f"{units} units in {dt:.1f} s")
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), else the machine type."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def traffic_for(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
@@ -377,7 +389,7 @@ def main():
     if not args.no_cpu_baseline:
         rate, sample = cpu_baseline(wls[:4])
         cpu = {"value": rate, "unit": "elem*angle*DOF/s", "cores": 1, "kind": "oracle", "sample": sample,
-               "cpu": platform.processor() or platform.machine()}
+               "cpu": cpu_model(), "host_cpus": os.cpu_count()}
         log(f"cpu baseline {rate:.3e} units/s")
 
     out = {
