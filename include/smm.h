@@ -255,7 +255,9 @@ int smm_set_sweep_path(smm_problem* prob, int path);
  * unchanged; the outer iteration count grows with the number of tiles.  Runs
  * on the per-element sweep path, one workgroup per (direction, tile).
  * (0, 0) restores the full sweep.  Problems with tiles cannot join a batch
- * (SMM_EUNSUPPORTED).  SMM_EINVAL for negative sizes or only one size 0. */
+ * (SMM_EUNSUPPORTED); tiles set on a problem after it joined a batch apply
+ * to its own smm_solve calls, not to the batch, which sweeps whole meshes.
+ * SMM_EINVAL for negative sizes or only one size 0. */
 int smm_set_sweep_tiles(smm_problem* prob, int tile_nx, int tile_ny);
 
 /* Time one sweep configuration on device (average ms over `reps` launches
