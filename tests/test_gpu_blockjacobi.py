@@ -8,6 +8,8 @@
   full sweep (1e-12 / 1e-5 against the oracle's untiled solution), and more
   tiles need more outer iterations.
 * Tiles off again gives the full sweep; batches refuse tiled problems.
+* Full size (channel 128², p = 2, S12): 32² tiles reach the full sweep's
+  fixed point within the FP32 bar.
 """
 import numpy as np
 import pytest
@@ -126,3 +128,25 @@ def test_tiles_off_and_batch_refusal(ctx):
     with pytest.raises(L.SmmError) as e:
         L.smm_set_sweep_tiles(p, 2, 0)
     assert e.value.code == L.SMM_EINVAL
+
+
+def test_full_size_tiles_reach_the_untiled_fixed_point(ctx):
+    """Full-size channel problem (128 x 128, p = 2, S12, FP32 delta sweeps,
+    CG moment system): the tabulated full sweep and the per-element sweep on
+    32 x 32 tiles converge to the same fixed point (a property of the block
+    Jacobi iteration at any size), within the FP32 bar."""
+    announce("channel 128x128 p2 S12: 32x32 tiles vs full sweep, converged")
+    wl = config_channel()
+    out = []
+    for tiles in ((0, 0), (32, 32)):
+        p = L.problem_from_workload(ctx, wl)
+        if tiles != (0, 0):
+            L.smm_set_sweep_tiles(p, *tiles)
+        rc, info = L.smm_solve(p, L.smm_default_opts(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=1e-9,
+                                                     inner_tol=1e-12, max_inner=20000, max_outer=200,
+                                                     discretization=L.SMM_DISC_CG))
+        assert rc == L.SMM_OK
+        out.append((L.smm_get_outputs_host(p)["varphi"], info["iterations"]))
+        L.smm_problem_destroy(p)
+    assert rel_l2(out[1][0], out[0][0]) < 1e-5, rel_l2(out[1][0], out[0][0])
+    assert out[1][1] > out[0][1]
