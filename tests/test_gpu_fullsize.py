@@ -7,6 +7,8 @@ degenerate case, against the oracle.
   and three members the oracle can solve in seconds (seeds 133, 196, 10:
   17^2 p = 1 S4, 16^2 p = 2 S6, 19^2 p = 3 S4), solved inside that batch,
   match the oracle's converged flux to the FP32 bar (1e-5 relative L2).
+* The full-size channel problem: FP32 sweeps within 1e-5 of the all-FP64
+  solve.
 * No scattering (sigma_s = 0): G does not depend on X, so the second outer
   iterate equals the first (up to the rounding of the second moment solve),
   and the transport scalar flux is one sweep of q.
@@ -90,3 +92,22 @@ def test_capped_inner_solve_never_converges(ctx, path):
     rc, info = L.smm_solve(p, opts, raise_on_noconv=False)
     assert rc == L.SMM_ENOCONV and info["iterations"] == 12
     assert np.all(np.isfinite(L.smm_get_outputs_host(p)["varphi"]))
+
+
+def test_full_size_fp32_sweep_within_the_fp32_bar(ctx):
+    """Full-size channel problem (128 x 128, p = 2, S12), converged: FP32
+    delta sweeps with FP64 moments, PCG and residual against the all-FP64
+    solve (whose kernels match the oracle at the sizes it can check), within
+    1e-5 relative L2."""
+    announce("channel 128x128 p2 S12: FP32 sweeps vs FP64, converged")
+    wl = config_channel()
+    out = []
+    for prec, delta in ((L.SMM_FP64, 0), (L.SMM_FP32_SWEEP, 1)):
+        p = L.problem_from_workload(ctx, wl)
+        rc, _ = L.smm_solve(p, L.smm_default_opts(precision=prec, delta_sweeps=delta, outer_tol=1e-10,
+                                                  inner_tol=1e-13, max_inner=20000, max_outer=200,
+                                                  precond=L.SMM_PRECOND_TWOLEVEL))
+        assert rc == L.SMM_OK
+        out.append(L.smm_get_outputs_host(p)["varphi"])
+        L.smm_problem_destroy(p)
+    assert rel_l2(out[1], out[0]) < 1e-5, rel_l2(out[1], out[0])
