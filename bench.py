@@ -27,6 +27,8 @@ Also reported:
     CG product kernel;
   * the parallel block Jacobi sweep on the same problem: sweep time and
     outer iterations per tile size;
+  * the sweep on curved meshes (per-element assembly and elimination) at
+    p = 2, 3, 4;
   * the CPU oracle's sweep on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -293,6 +295,34 @@ def block_jacobi_sweeps(L, ctx, log):
     return res
 
 
+def curved_sweeps(L, ctx, log):
+    """The sweep on curved meshes (the manufactured problem: 32 x 32 elements
+    with an order-p map, S8), where every element and direction is assembled
+    and eliminated by the per-element kernel: time per sweep, units/s, and
+    the rate against the FP32 vector peak at the assembly and elimination
+    work per DOF (165 / 344 / 664 flops for p = 2 / 3 / 4)."""
+    from workloads import config_curved_mms
+
+    flops = {2: 165.0, 3: 344.0, 4: 664.0}
+    res = {"workload": "curved manufactured problem, 32x32 elements, order-p map, S8 (40 directions)", "runs": []}
+    for p in (2, 3, 4):
+        wl = config_curved_mms(32, p, 8)
+        prob = L.problem_from_workload(ctx, wl)
+        units = float(wl.n_elem * (p + 1) ** 2 * 40)
+        run = {"p": p, "units_per_sweep": units}
+        for name, prec in (("fp32", L.SMM_FP32_SWEEP), ("fp64", L.SMM_FP64)):
+            ms = L.smm_time_sweep(prob, prec, 5)
+            run[name + "_ms"] = ms
+            run[name + "_units_per_s"] = units / (ms * 1e-3)
+        tf = flops[p] * units / (run["fp32_ms"] * 1e-3) / 1e12
+        run["roofline_fp32"] = {"bound": "alu", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
+                                "traffic": None, "kernel": "sweep_general_kernel"}
+        log(f"curved 32^2 p={p} S8: FP32 sweep {run['fp32_ms']:.3f} ms, FP64 {run['fp64_ms']:.3f} ms")
+        res["runs"].append(run)
+        L.smm_problem_destroy(prob)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,10 +413,12 @@ def main():
     tts = None
     disc = None
     tiles = None
+    curved = None
     if not args.no_solve:
         tts = time_to_solution(L, ctx, args.tts_problems, log)
         disc = moment_discretisations(L, ctx, log)
         tiles = block_jacobi_sweeps(L, ctx, log)
+        curved = curved_sweeps(L, ctx, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -421,6 +453,7 @@ def main():
         "time_to_1e-8": tts,
         "moment_discretisations": disc,
         "block_jacobi_sweeps": tiles,
+        "curved_sweeps": curved,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
