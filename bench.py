@@ -255,7 +255,7 @@ def moment_discretisations(L, ctx, log):
 def block_jacobi_sweeps(L, ctx, log):
     """Parallel block Jacobi sweep (Sec. 6.5) on the channel problem (128 x
     128, p = 2, S12): time of one FP32 sweep of the per-element kernel (one
-    workgroup per direction and tile) for several tile sizes, outer
+    workgroup per direction and tile, one lane per element) for several tile sizes, outer
     iterations and wall time to a 1e-8 outer residual (CG moment system,
     FP32 delta sweeps), beside the tabulated Cartesian sweep, which has no
     tiled form.  The per-element kernel assembles and eliminates every
@@ -288,7 +288,7 @@ def block_jacobi_sweeps(L, ctx, log):
         if tiles != (0, 0):
             tf = 165.0 * units / (ms * 1e-3) / 1e12
             run["roofline"] = {"bound": "alu", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
-                               "traffic": None, "kernel": "sweep_general_kernel"}
+                               "traffic": None, "kernel": "sweep_lane_general_kernel"}
         res["runs"].append(run)
         log(f"{kind}: sweep {ms:.3f} ms, solve {t * 1e3:.1f} ms, {info['iterations']} outer")
         L.smm_problem_destroy(p)
@@ -298,7 +298,8 @@ def block_jacobi_sweeps(L, ctx, log):
 def curved_sweeps(L, ctx, log):
     """The sweep on curved meshes (the manufactured problem: 32 x 32 elements
     with an order-p map, S8), where every element and direction is assembled
-    and eliminated by the per-element kernel: time per sweep, units/s, and
+    and eliminated by the per-element kernel (one lane per element at p = 2,
+    one wave per element at p = 3, 4): time per sweep, units/s, and
     the rate against the FP32 vector peak at the assembly and elimination
     work per DOF (165 / 344 / 664 flops for p = 2 / 3 / 4)."""
     from workloads import config_curved_mms
@@ -316,7 +317,8 @@ def curved_sweeps(L, ctx, log):
             run[name + "_units_per_s"] = units / (ms * 1e-3)
         tf = flops[p] * units / (run["fp32_ms"] * 1e-3) / 1e12
         run["roofline_fp32"] = {"bound": "alu", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
-                                "traffic": None, "kernel": "sweep_general_kernel"}
+                                "traffic": None,
+                                "kernel": "sweep_lane_general_kernel" if p <= 2 else "sweep_general_kernel"}
         log(f"curved 32^2 p={p} S8: FP32 sweep {run['fp32_ms']:.3f} ms, FP64 {run['fp64_ms']:.3f} ms")
         res["runs"].append(run)
         L.smm_problem_destroy(prob)

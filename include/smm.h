@@ -241,10 +241,13 @@ int smm_debug_cg_spmv(smm_problem* prob, const double* x, double* y);
 int smm_time_cg_spmv(smm_problem* prob, int reps, double* ms_avg);
 
 /* Sweep kernel selection: 0 = automatic (tabulated operators on uniform
- * Cartesian meshes, otherwise per-element assembly and elimination);
- * 1 = always the per-element assembly/elimination kernel; 2 = on Cartesian
- * meshes, the element-row kernel instead of the column-per-thread one (for
- * cross-checking the kernels against each other). */
+ * Cartesian meshes, otherwise per-element assembly and elimination: one lane
+ * per element for p <= 2, one wave per element for p >= 3); 1 = always the
+ * per-element kernel (solve form as in 0); 2 = on Cartesian meshes, the
+ * element-row kernel instead of the column-per-thread one; 3 = the
+ * per-element kernel with one wave per element at every order.  2 and 3
+ * are for cross-checking the kernels against each other.  Returns
+ * SMM_EINVAL outside 0..3. */
 int smm_set_sweep_path(smm_problem* prob, int path);
 
 /* Parallel block Jacobi sweep (Sec. 6.5, weak scaling): the element grid is

@@ -252,9 +252,12 @@ int smm_set_sweep_tiles(smm_problem* prob, int tile_nx, int tile_ny) {
     return SMM_OK;
 }
 
+// sweep paths 1 and 3 force the per-element kernel (3 also its wave-wide solve)
+static bool per_element_forced(const Dev& D) { return D.force_general == 1 || D.force_general == 3; }
+
 int smm_set_sweep_path(smm_problem* prob, int force_general) {
     if (!prob) return SMM_EINVAL;
-    if (force_general < 0 || force_general > 2) return SMM_EINVAL;
+    if (force_general < 0 || force_general > 3) return SMM_EINVAL;
     prob->D.force_general = force_general;
     return SMM_OK;
 }
@@ -474,7 +477,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
     hipError_t e;
-    if (P.cartesian && D.force_general != 1 && P.tile_x == 0) {
+    if (P.cartesian && !per_element_forced(D) && P.tile_x == 0) {
         CartSweepArgs a{};
         a.nx = P.nx; a.ny = P.ny; a.nd = P.nd; a.nb = P.nb; a.nmat = P.nmat;
         a.s_aniso = s_aniso;
@@ -494,6 +497,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
         a.ne = P.ne; a.nd = P.nd; a.nb = P.nb; a.nq = P.nq; a.nbf = P.nbf; a.nlev = P.nlev_max;
         a.ntiles = P.ntiles;
         a.maxw = P.lev_wmax;
+        a.wave_solve = D.force_general == 3 ? 1 : 0;
         a.s_aniso = s_aniso;
         a.S = S;
         a.Mk = fp64 ? D.Mk64 : D.Mk32;
@@ -711,18 +715,18 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     const bool cgdisc = o.discretization == SMM_DISC_CG;
     if (cgdisc && o.anderson != 0)
         return fail(c, SMM_EUNSUPPORTED, "smm_solve: Anderson mixing runs on the typed path, IP discretisation only");
-    if (o.anderson != 0 && !(o.moment_path == 0 && typed_applicable(P) && D.force_general != 1 && P.tile_x == 0))
+    if (o.anderson != 0 && !(o.moment_path == 0 && typed_applicable(P) && !per_element_forced(D) && P.tile_x == 0))
         return fail(c, SMM_EUNSUPPORTED, "smm_solve: Anderson mixing needs the typed (batched) path");
     if (o.start < SMM_START_ZERO || o.start > SMM_START_GIVEN)
         return fail(c, SMM_EINVAL, "smm_solve: start must be ZERO, DIFFUSION or GIVEN (the learned start needs a batch)");
-    if (!cgdisc && o.moment_path == 0 && typed_applicable(P) && D.force_general != 1 && P.tile_x == 0) {
+    if (!cgdisc && o.moment_path == 0 && typed_applicable(P) && !per_element_forced(D) && P.tile_x == 0) {
         const int r = batch_solve_single(prob, o, varphi0, info);
         D.last_typed = (r == SMM_OK || r == SMM_ENOCONV);
         return r;
     }
     D.last_typed = false;
     auto t0 = std::chrono::steady_clock::now();
-    int rc = ensure_device(prob, true, D.force_general == 1);
+    int rc = ensure_device(prob, true, per_element_forced(D));
     if (rc) return rc;
     if (cgdisc && (rc = ensure_cg(prob))) return rc;
     auto t1 = std::chrono::steady_clock::now();
@@ -820,7 +824,7 @@ int smm_apply_sweep(smm_problem* prob, int precision, const void* S, int s_layou
     if (!prob || !S || !psi_out) return SMM_EINVAL;
     if (precision != SMM_FP64 && precision != SMM_FP32_SWEEP) return SMM_EINVAL;
     if (s_layout != SMM_SRC_ISO && s_layout != SMM_SRC_ANISO) return SMM_EINVAL;
-    int rc = ensure_device(prob, false, prob->D.force_general == 1);
+    int rc = ensure_device(prob, false, per_element_forced(prob->D));
     if (rc) return rc;
     return run_sweep(prob, precision == SMM_FP64, S, s_layout == SMM_SRC_ANISO ? 1 : 0, psi_lag, psi_out,
                      with_inflow != 0);
@@ -842,7 +846,7 @@ int smm_apply_moments(smm_problem* prob, int precision, const void* psi, double*
 int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, double* varphi_out, double inner_tol,
                 int max_inner) {
     if (!prob || !varphi_in || !varphi_out) return SMM_EINVAL;
-    int rc = ensure_device(prob, true, prob->D.force_general == 1);
+    int rc = ensure_device(prob, true, per_element_forced(prob->D));
     if (rc) return rc;
     Problem& P = prob->P;
     Dev& D = prob->D;
@@ -882,7 +886,7 @@ int smm_debug_cg_system(smm_problem* prob, int* nc, int* nnz, int* rowptr, int* 
 
 int smm_debug_cg_spmv(smm_problem* prob, const double* x, double* y) {
     if (!prob || !x || !y) return SMM_EINVAL;
-    int rc = ensure_device(prob, true, prob->D.force_general == 1);
+    int rc = ensure_device(prob, true, per_element_forced(prob->D));
     if (rc) return rc;
     if ((rc = ensure_cg(prob))) return rc;
     smm_ctx* c = prob->P.ctx;
@@ -898,7 +902,7 @@ int smm_debug_cg_spmv(smm_problem* prob, const double* x, double* y) {
 
 int smm_time_cg_spmv(smm_problem* prob, int reps, double* ms_avg) {
     if (!prob || !ms_avg || reps < 1) return SMM_EINVAL;
-    int rc = ensure_device(prob, true, prob->D.force_general == 1);
+    int rc = ensure_device(prob, true, per_element_forced(prob->D));
     if (rc) return rc;
     if ((rc = ensure_cg(prob))) return rc;
     smm_ctx* c = prob->P.ctx;
@@ -999,7 +1003,7 @@ int smm_debug_corr_dense(smm_problem* prob, double* C) {
 
 int smm_time_sweep(smm_problem* prob, int precision, int reps, double* ms_avg) {
     if (!prob || !ms_avg || reps < 1) return SMM_EINVAL;
-    int rc = ensure_device(prob, false, prob->D.force_general == 1);
+    int rc = ensure_device(prob, false, per_element_forced(prob->D));
     if (rc) return rc;
     Problem& P = prob->P;
     Dev& D = prob->D;

@@ -6,6 +6,8 @@
 //  * sweep_general_kernel Curved meshes: per (element, direction) the local
 //                         upwind DG matrix is assembled in LDS and eliminated
 //                         by one wavefront; levels come from the sweep graph.
+//  * sweep_lane_general_kernel  The same at p <= 2 with one lane per element:
+//                         the augmented system stays in registers.
 //  * moments_kernel       Angular moments mom = W psi on the matrix cores.
 //  * closure / rhs / cg   SMM correction tensor and boundary factor, the IP
 //                         right-hand side, FP64 block-Jacobi PCG.
@@ -565,6 +567,106 @@ __global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepA
     }
 }
 
+// The same per-element solve with one lane per element (p <= 2: the n x
+// (n+1) augmented system stays in registers): a level's elements are spread
+// over the workgroup's lanes, so a level of m elements costs one pass of
+// ceil(m / 256) waves instead of m wave-solves.  Same assembly (volume, then
+// faces in order), elimination without pivoting (one multiplier per row) and
+// back substitution by rows.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a) {
+    constexpr int N = NB * NB;
+    const int d = blockIdx.x;
+    const int nq = a.nq, ne = a.ne;
+    const T ox = (T)a.omega[d * 3], oy = (T)a.omega[d * 3 + 1];
+    const T* S = reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0);
+    const T* Mk = reinterpret_cast<const T*>(a.Mk);
+    const T* Gx = reinterpret_cast<const T*>(a.Gx);
+    const T* Gy = reinterpret_cast<const T*>(a.Gy);
+    const T* nds = reinterpret_cast<const T*>(a.nds);
+    const T* Lf = reinterpret_cast<const T*>(a.Lf);
+    const T* st = reinterpret_cast<const T*>(a.sigma_t);
+    const T* pbar = reinterpret_cast<const T*>(a.psibar);
+    const T* plag = reinterpret_cast<const T*>(a.psi_lag);
+    T* psi = reinterpret_cast<T*>(a.psi);
+    const int* lp = a.lev_ptr + ((long)d * a.ntiles + blockIdx.y) * (a.nlev + 1);
+    const int* le = a.lev_elem + (long)d * ne;
+    for (int l = 0; l < a.nlev; ++l) {
+        const int beg = lp[l], end = lp[l + 1];
+        for (int e = beg + (int)threadIdx.x; e < end; e += (int)blockDim.x) {
+            const int K = le[e];
+            const T sK = st[K];
+            const T* M = Mk + (long)K * N * N;
+            const T* gx = Gx + (long)K * N * N;
+            const T* gy = Gy + (long)K * N * N;
+            const T* sk = S + (long)K * N;
+            T A[N][N + 1];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T b = T(0);
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    const T m = M[i * N + j];
+                    A[i][j] = sK * m - ox * gx[i * N + j] - oy * gy[i * N + j];
+                    b += m * sk[j];
+                }
+                A[i][N] = b;
+            }
+            const uint8_t up = a.upflag[(long)d * ne + K];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int Nb = a.nbr[K * 4 + f];
+                const T* src = nullptr;
+                if (Nb >= 0) src = ((up >> f) & 1) ? psi : plag;
+                const int fN = (f + 2) & 3;
+                for (int q = 0; q < nq; ++q) {
+                    const T* nn = nds + (((long)K * 4 + f) * nq + q) * 2;
+                    const T on = ox * nn[0] + oy * nn[1];
+                    if (on > T(0)) {
+#pragma unroll
+                        for (int c = 0; c < NB; ++c)
+#pragma unroll
+                            for (int c2 = 0; c2 < NB; ++c2)
+                                A[face_node<NB>(f, c)][face_node<NB>(f, c2)] += on * Lf[c * nq + q] * Lf[c2 * nq + q];
+                    } else if (on < T(0)) {
+                        T val = T(0);
+                        if (Nb < 0) {
+                            if (pbar) val = pbar[((long)d * a.nbf + a.bface_of[K * 4 + f]) * nq + q];
+                        } else if (src) {
+                            const T* sN = src + ((long)d * ne + Nb) * N;
+#pragma unroll
+                            for (int c = 0; c < NB; ++c) val += Lf[c * nq + q] * sN[face_node<NB>(fN, c)];
+                        }
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) A[face_node<NB>(f, c)][N] -= on * Lf[c * nq + q] * val;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+#pragma unroll
+                for (int i = k + 1; i < N; ++i) {
+                    const T m = A[i][k] / A[k][k];
+#pragma unroll
+                    for (int j = k + 1; j <= N; ++j) A[i][j] -= m * A[k][j];
+                }
+            }
+            T x[N];
+#pragma unroll
+            for (int k = N - 1; k >= 0; --k) {
+                T v = A[k][N];
+#pragma unroll
+                for (int j = k + 1; j < N; ++j) v -= A[k][j] * x[j];
+                x[k] = v / A[k][k];
+            }
+            T* out = psi + ((long)d * ne + K) * N;
+#pragma unroll
+            for (int i = 0; i < N; ++i) out[i] = x[i];
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T, int NB>
 static hipError_t launch_gen_t(const GenSweepArgs& a, hipStream_t s) {
     if (a.nq > GEN_MAXQ || 4 * a.nq > 64) return hipErrorInvalidValue;
@@ -572,6 +674,17 @@ static hipError_t launch_gen_t(const GenSweepArgs& a, hipStream_t s) {
     // workgroup their levels fill; many (tiles) take 4 waves, so that more
     // workgroups share each CU
     constexpr int WV = gen_waves<T, NB>();
+    // p <= 2: one lane per element, in a workgroup of as many waves as the
+    // widest level needs (at most 4), so that idle waves take no CU slots;
+    // with 8 x 8 tiles (levels of at most 8 elements) this still beats the
+    // wave-wide solve, since 8 such workgroups share a CU
+    if constexpr (NB <= 3) {
+        if (a.wave_solve != 1) {
+            const int threads = std::min(256, std::max(64, (a.maxw + 63) / 64 * 64));
+            hipLaunchKernelGGL((sweep_lane_general_kernel<T, NB>), dim3(a.nd, a.ntiles), dim3(threads), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (a.nd * a.ntiles < 512 && a.maxw > 4)
         hipLaunchKernelGGL((sweep_general_kernel<T, NB, WV>), dim3(a.nd, a.ntiles), dim3(64 * WV), 0, s, a);
     else

@@ -34,6 +34,7 @@ struct GenSweepArgs {
     int ne, nd, nb, nq, nbf, nlev;
     int ntiles;                  // independent element tiles (1: the full sweep)
     int maxw;                    // most elements in one level of one (direction, tile)
+    int wave_solve;              // 1: one wave per element also at p <= 2 (else one lane per element)
     int s_aniso;
     const void* S;
     const void* Mk;              // [ne][n][n]

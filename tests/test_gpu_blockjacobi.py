@@ -33,12 +33,13 @@ def ctx():
     return L.smm_ctx_create(0, torch.cuda.current_stream())
 
 
-def _pair(ctx, wl, tiles):
+def _pair(ctx, wl, tiles, path=0):
     pr = osmm.make_problem(wl, tiles=tiles)
     iso = isinstance(wl.inflow, tuple) and wl.inflow[0] == "iso"
     p = L.problem_from_workload(ctx, wl, q=pr.q, psibar=None if iso else pr.psibar)
     if tiles is not None:
         L.smm_set_sweep_tiles(p, *tiles)
+    L.smm_set_sweep_path(p, path)
     return pr, p
 
 
@@ -48,20 +49,24 @@ def _two_mat(n=7, p=2, sn=4):
     return wl
 
 
+# (workload factory, tiles, sweep path: 0 automatic, i.e. one lane per element
+# at p <= 2; 3 one wave per element at every order)
 SWEEPS = {
-    "twomat7_p2_t3x2": (lambda: _two_mat(), (3, 2)),
-    "twomat7_p1_t1x1": (lambda: _two_mat(p=1), (1, 1)),
-    "plain6_p4_t4x4": (lambda: config_plain(6, 4, 6), (4, 4)),
-    "curved4_p2_t2x3": (lambda: config_curved_mms(4, 2, 8), (2, 3)),
+    "twomat7_p2_t3x2": (lambda: _two_mat(), (3, 2), 0),
+    "twomat7_p2_t3x2_wavesolve": (lambda: _two_mat(), (3, 2), 3),
+    "twomat7_p1_t1x1": (lambda: _two_mat(p=1), (1, 1), 0),
+    "plain6_p4_t4x4": (lambda: config_plain(6, 4, 6), (4, 4), 0),
+    "curved4_p2_t2x3": (lambda: config_curved_mms(4, 2, 8), (2, 3), 0),
+    "curved4_p2_t2x3_wavesolve": (lambda: config_curved_mms(4, 2, 8), (2, 3), 3),
 }
 
 
 @pytest.mark.parametrize("case", list(SWEEPS))
 def test_block_sweep_with_lag_fp64(ctx, case):
-    factory, tiles = SWEEPS[case]
+    factory, tiles, path = SWEEPS[case]
     announce(f"block Jacobi sweep {case}")
     wl = factory()
-    pr, p = _pair(ctx, wl, tiles)
+    pr, p = _pair(ctx, wl, tiles, path)
     rng = np.random.default_rng(4)
     S = rng.uniform(0.5, 1.5, size=(pr.ne, pr.n))
     lag = rng.uniform(0.0, 1.0, size=(len(pr.w), pr.ne, pr.n))

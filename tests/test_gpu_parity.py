@@ -44,7 +44,8 @@ def _sweep_gpu(p, prec, S, lag=None, inflow=True):
 
 
 SWEEP_CASES = [
-    # (name, workload factory, sweep path: 0 auto, 1 per-element kernel, 2 element-row kernel)
+    # (name, workload factory, sweep path: 0 auto, 1 per-element kernel, 2 element-row
+    # kernel, 3 per-element kernel with one wave per element also at p <= 2)
     ("plain8_p1_s4", lambda: config_plain(8, 1, 4), 0),
     ("plain8_p1_s4_general", lambda: config_plain(8, 1, 4), 1),
     ("plain8_p1_s4_rowkernel", lambda: config_plain(8, 1, 4), 2),
@@ -56,6 +57,9 @@ SWEEP_CASES = [
     ("ragged7x3_p3_s6_general", lambda: _rect(7, 3, 3, 6), 1),
     ("single_p2_s8", lambda: _rect(1, 1, 2, 8), 0),
     ("curved4_p2_s8", lambda: config_curved_mms(4, 2, 8, amplitude=0.09), 0),
+    ("curved4_p2_s8_wavesolve", lambda: config_curved_mms(4, 2, 8, amplitude=0.09), 3),
+    ("plain8_p2_s4_general", lambda: config_plain(8, 2, 4), 1),
+    ("plain8_p1_s4_wavesolve", lambda: config_plain(8, 1, 4), 3),
     ("curved3_p4_s4", lambda: config_curved_mms(3, 4, 4), 0),
 ]
 
