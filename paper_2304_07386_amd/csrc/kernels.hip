@@ -571,7 +571,7 @@ __global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepA
 // (n+1) augmented system stays in registers): a level's elements are spread
 // over the workgroup's lanes, so a level of m elements costs one pass of
 // ceil(m / 256) waves instead of m wave-solves.  Same assembly (volume, then
-// faces in order), elimination without pivoting (one multiplier per row) and
+// faces in order), elimination without pivoting (one division per pivot) and
 // back substitution by rows.
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a) {
@@ -642,11 +642,15 @@ __global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a)
                     }
                 }
             }
+            // one division per pivot; its reciprocal scales the multipliers
+            // and the back substitution
+            T inv[N];
 #pragma unroll
             for (int k = 0; k < N; ++k) {
+                inv[k] = T(1) / A[k][k];
 #pragma unroll
                 for (int i = k + 1; i < N; ++i) {
-                    const T m = A[i][k] / A[k][k];
+                    const T m = A[i][k] * inv[k];
 #pragma unroll
                     for (int j = k + 1; j <= N; ++j) A[i][j] -= m * A[k][j];
                 }
@@ -657,7 +661,7 @@ __global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a)
                 T v = A[k][N];
 #pragma unroll
                 for (int j = k + 1; j < N; ++j) v -= A[k][j] * x[j];
-                x[k] = v / A[k][k];
+                x[k] = v * inv[k];
             }
             T* out = psi + ((long)d * ne + K) * N;
 #pragma unroll
