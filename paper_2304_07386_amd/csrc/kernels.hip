@@ -544,11 +544,11 @@ __global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepA
             }
             __builtin_amdgcn_wave_barrier();
             for (int k = 0; k < N; ++k) {
-                const T piv = Aug[wv][k][k];
+                const T rp = T(1) / Aug[wv][k][k];  // one division per lane and pivot
                 const int w = N - k;  // columns k+1 .. N
                 for (int idx = lane; idx < (N - 1 - k) * w; idx += 64) {
                     const int i = k + 1 + idx / w, j = k + 1 + idx % w;
-                    Aug[wv][i][j] -= Aug[wv][i][k] / piv * Aug[wv][k][j];
+                    Aug[wv][i][j] -= Aug[wv][i][k] * rp * Aug[wv][k][j];
                 }
                 __builtin_amdgcn_wave_barrier();
             }
