@@ -340,9 +340,11 @@ def main():
                     help="run only the IP versus CG moment-system comparison and print its JSON")
     ap.add_argument("--tiles-only", action="store_true",
                     help="run only the block Jacobi sweep comparison and print its JSON")
+    ap.add_argument("--curved-only", action="store_true",
+                    help="run only the curved-mesh sweep timings and print their JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the problems of a batch are "
+        print("bench.py measures one GPU: there is no multi-GPU path (the problems of a batch are "
               "independent and would be split across GPUs by the caller)", file=sys.stderr)
         sys.exit(2)
 
@@ -358,6 +360,9 @@ def main():
         return
     if args.tiles_only:
         print(json.dumps(block_jacobi_sweeps(L, ctx, log)))
+        return
+    if args.curved_only:
+        print(json.dumps(curved_sweeps(L, ctx, log)))
         return
     t0 = time.time()
     wls = [config_batched_problem(s) for s in range(args.problems)]
