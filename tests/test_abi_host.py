@@ -131,9 +131,9 @@ def test_warmstart_calls_need_a_device(hctx):
 
 
 def test_tiles_and_cg_calls_on_the_host(hctx):
-    """smm_set_sweep_tiles validates its sizes; the continuous system and
-    the tiles are set-up work, so a host-only context accepts them, while the
-    device calls that use them are refused."""
+    """smm_set_sweep_tiles and smm_set_sweep_path validate their arguments;
+    the continuous system and the tiles are set-up work, so a host-only
+    context accepts them, while the device calls that use them are refused."""
     wl = config_plain(n=4, p=2)
     p = L.problem_from_workload(hctx, wl)
     for bad in ((-1, 2), (2, 0), (0, 3)):
@@ -142,6 +142,13 @@ def test_tiles_and_cg_calls_on_the_host(hctx):
         assert e.value.code == L.SMM_EINVAL
     L.smm_set_sweep_tiles(p, 2, 2)
     L.smm_set_sweep_tiles(p, 0, 0)
+    # sweep kernel selection: 0..3 (3 = one wave per element at every order)
+    for bad in (-1, 4):
+        with pytest.raises(L.SmmError) as e:
+            L.smm_set_sweep_path(p, bad)
+        assert e.value.code == L.SMM_EINVAL
+    for path in (3, 0):
+        L.smm_set_sweep_path(p, path)
     rowptr, col, val, cmap = L.smm_debug_cg_system(p)
     assert len(rowptr) == (4 * 2 + 1) ** 2 + 1 and cmap.max() == (4 * 2 + 1) ** 2 - 1
     with pytest.raises(L.SmmError) as e:
