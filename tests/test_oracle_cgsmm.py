@@ -17,7 +17,7 @@ functions restricted to V_p (Sec. 5.1).  These tests tie it to:
   meshes (Sec. 6.1: all four methods are optimal) and O(h^{p+1}) distance to
   the DG S_N scalar flux (eq. snconv);
 * the thick-diffusion-limit iteration counts of Table tab:tdl_orthog, CG
-  column (golden fixture; the same tolerance of 3 as the IP pin).
+  column (golden fixture): a trend pin with no parity weight, as for IP.
 """
 import os
 
@@ -153,9 +153,9 @@ def test_cg_one_element_is_ip():
     assert np.abs(x_cg - x_ip).max() < 1e-13 * np.abs(x_ip).max()
 
 
-@pytest.mark.parametrize("curved", [False, True])
-def test_cg_infinite_medium_fixed_point(curved):
-    wl = config_curved_mms(n=4, p=2, sn=4) if curved else config_plain(n=4, p=2, sn=6)
+@pytest.mark.parametrize("curved,p", [(False, 2), (True, 2), (True, 4)])
+def test_cg_infinite_medium_fixed_point(curved, p):
+    wl = config_curved_mms(n=4, p=p, sn=4) if curved else config_plain(n=4, p=p, sn=6)
     ne = wl.n_elem
     st, ss, q = 2.0, 1.5, 1.0
     wl.sigma_t, wl.sigma_s, wl.q_elem, wl.q_fn = np.full(ne, st), np.full(ne, ss), np.full(ne, q), None
@@ -180,11 +180,11 @@ def test_cg_patch_linear_anisotropy(p):
     assert np.abs(x - ex).max() < 1e-13 * ex.max()
 
 
-@pytest.mark.parametrize("p", [1, 2])
-def test_cg_mms_curved_order(p):
+@pytest.mark.parametrize("p,sn", [(1, 8), (2, 8), (3, 4), (4, 4)])
+def test_cg_mms_curved_order(p, sn):
     errs = []
     for n in (4, 8, 16):
-        prob = smm.make_problem(config_curved_mms(n=n, p=p, sn=8), disc="cg")
+        prob = smm.make_problem(config_curved_mms(n=n, p=p, sn=sn), disc="cg")
         x, info = smm.solve(prob, tol=1e-11, max_it=60)
         assert info["converged"]
         errs.append(fem.l2_error(prob.mesh, x.reshape(prob.ne, prob.n), mms_phi))
@@ -218,4 +218,4 @@ def test_cg_thick_diffusion_limit_iterations():
     assert counts == sorted(counts, reverse=True)
     gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "tdl_orthog_cg_smm_iterations.txt"))
     assert np.allclose(gold[:, 0], [1e-1, 1e-2, 1e-3, 1e-4])
-    assert np.all(np.abs(np.array(counts) - gold[:, 1]) <= 3)
+    assert np.all(np.array(counts) <= gold[:, 1])

@@ -12,11 +12,17 @@
   (I - G_lin) X = G(0).
 * IP matrix: symmetric and positive definite.
 * Manufactured solution on curved meshes: || varphi - phi_ex || = O(h^{p+1})
-  (Sec. 6.1).
+  (Sec. 6.1) for p = 1..4 on order-p maps (m = p).
+* Curved face and volume gradients: the nodal interpolant of an affine field
+  is that field exactly when m <= p, so its physical gradient at every volume
+  and face point is the constant gradient, at any order.
 * SMM versus the DG S_N solution: difference O(h^{p+1}) (eq. snconv).
-* Thick diffusion limit (Sec. 6.2): bounded, epsilon-robust outer iteration
-  counts (soft pin; the counts printed in Table tab:tdl_orthog are 10/8/5/4,
-  the oracle takes 8/5/3/2 -- see the readings in the design notes).
+* Thick diffusion limit (Sec. 6.2): bounded outer iteration counts that
+  fall as epsilon falls.  Trend only, with no parity weight: Table
+  tab:tdl_orthog prints 10/8/5/4, the oracle takes 8/5/3/2 (its contraction
+  per iteration is faster at every epsilon; the table's start, stopping norm
+  and transport discretisation are not stated), so the test checks the trend
+  and that the oracle needs no more iterations than the table.
 """
 import os
 
@@ -28,9 +34,9 @@ from workloads import (Workload, config_curved_mms, config_plain, config_tdl,
                        mms_phi, structured_ctrl)
 
 
-@pytest.mark.parametrize("curved", [False, True])
-def test_infinite_medium_fixed_point(curved):
-    wl = config_curved_mms(n=4, p=2, sn=4) if curved else config_plain(n=4, p=2, sn=6)
+@pytest.mark.parametrize("curved,p", [(False, 2), (True, 2), (True, 4)])
+def test_infinite_medium_fixed_point(curved, p):
+    wl = config_curved_mms(n=4, p=p, sn=4) if curved else config_plain(n=4, p=p, sn=6)
     ne = wl.n_elem
     st, ss, q = 2.0, 1.5, 1.0
     wl.sigma_t, wl.sigma_s, wl.q_elem, wl.q_fn = np.full(ne, st), np.full(ne, ss), np.full(ne, q), None
@@ -105,16 +111,34 @@ def test_ip_matrix_spd(curved):
     assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
 
 
-@pytest.mark.parametrize("p", [1, 2])
-def test_mms_curved_order(p):
+@pytest.mark.parametrize("p,sn", [(1, 8), (2, 8), (3, 4), (4, 4)])
+def test_mms_curved_order(p, sn):
+    # the manufactured psi is quadratic in Omega_x, which every level-symmetric
+    # set integrates exactly, so S4 serves as well as S8 at p = 3, 4
     errs = []
     for n in (4, 8, 16):
-        prob = smm.make_problem(config_curved_mms(n=n, p=p, sn=8))
+        prob = smm.make_problem(config_curved_mms(n=n, p=p, sn=sn))
         x, info = smm.solve(prob, tol=1e-11, max_it=60)
         assert info["converged"]
         errs.append(fem.l2_error(prob.mesh, x.reshape(prob.ne, prob.n), mms_phi))
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert orders[-1] > p + 1 - 0.15, orders
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_affine_field_gradients_curved(p):
+    wl = config_curved_mms(n=3, p=p, sn=4, amplitude=0.09)
+    mesh = fem.build_mesh(wl.ctrl, wl.nx, wl.ny, wl.m, wl.p)
+    g = np.array([0.7, -1.3])
+    u = 0.4 + mesh.xnode @ g                                    # [K, n] nodal values
+    vol = np.einsum("kqna,kn->kqa", mesh.gradU, u)
+    face = np.einsum("kfqna,kn->kfqa", mesh.gradUf, u)
+    assert np.abs(vol - g).max() < 1e-12
+    assert np.abs(face - g).max() < 1e-12
+    # values at the points reproduce the field too
+    assert np.abs(u @ mesh.U.T - (0.4 + mesh.xq @ g)).max() < 1e-13
+    for f in range(4):
+        assert np.abs(u @ mesh.Uf[f].T - (0.4 + mesh.xf[:, f] @ g)).max() < 1e-13
 
 
 def test_smm_converges_to_sn_solution():
@@ -151,10 +175,11 @@ def test_thick_diffusion_limit_iterations():
                 break
         counts.append(it)
     assert counts == sorted(counts, reverse=True)
-    assert max(counts) <= 10 and min(counts) >= 2
-    # the paper's counts (golden fixture): same trend, within 3 iterations (the
-    # paper's start and stopping norm are not stated)
+    assert min(counts) >= 2
+    # the paper's counts (golden fixture): the same trend, and no count above
+    # the table's (a trend pin: the discretisation details behind the table's
+    # exact counts are not stated)
     gold = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "tdl_orthog_smm_iterations.txt"))
     assert np.allclose(gold[:, 0], [1e-1, 1e-2, 1e-3, 1e-4])
-    assert np.all(np.abs(np.array(counts) - gold[:, 1]) <= 3)
     assert np.all(np.diff(gold[:, 1]) <= 0)
+    assert np.all(np.array(counts) <= gold[:, 1])
