@@ -226,6 +226,15 @@ int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, doubl
  * the fixed right-hand side [N]. */
 int smm_debug_ip_dense(const smm_problem* prob, double* A, double* b_fixed);
 
+/* Host-only inspection of the sweep graph of Sec. 4 (built from the chord
+ * normals; with tiles, edges only inside tiles): level [n_dir][n_elem] gets
+ * each element's wavefront level (longest upwind path, Kahn's algorithm) and
+ * upstream [n_dir][n_elem] a bit mask whose bit f is set when the neighbour
+ * across local face f is a graph predecessor (faces without that bit read
+ * inflow, or the lagged previous sweep).  Either pointer may be NULL.
+ * SMM_EUNSUPPORTED when the graph has a cycle. */
+int smm_debug_sweep_graph(smm_problem* prob, int* level, unsigned char* upstream);
+
 /* Host-only inspection of the continuous (CG) moment system of Sec. 5.1.
  * Writes *nc (continuous unknowns) and *nnz; when rowptr is non-NULL also
  * the CSR matrix A_c (rowptr[nc + 1], col[nnz], val[nnz], columns ascending)
@@ -291,6 +300,15 @@ int smm_debug_batch_precond(smm_batch* batch, int precond, const double* const* 
  * host pointers of n_elem * n_node values each.  Overwrites the batch's PCG
  * work vectors. */
 int smm_debug_batch_spmv(smm_batch* batch, const double* const* x, double* const* y);
+/* Testing hook: one batched sweep (Sec. 4) of every problem of the batch, in
+ * the launch configuration smm_batch_solve uses (one persistent launch per
+ * order and workgroup shape, tuned grids and streams, the same task queue),
+ * on the isotropic scattering sources S: n host pointers of
+ * [n_elem][n_node] doubles (NULL entry: zero source), rounded to the sweep
+ * precision, with each problem's own boundary inflow.  psi_k (host,
+ * [n_dir][n_elem][n_node] doubles) receives problem k's angular flux.
+ * Overwrites the batch's sweep buffers (outputs of the last solve stay). */
+int smm_batch_apply_sweep(smm_batch* batch, int precision, const double* const* S, int k, double* psi_k);
 /* Testing hook: choose the batch's PCG kernels: 1 the type-group kernels
  * (one wave per group of elements sharing their blocks), 0 the per-node
  * kernels, -1 the automatic choice (group fill).  Results agree up to the

@@ -97,9 +97,9 @@ int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_or
     }
     // curved or irregular meshes need the per-element quadrature data and the
     // sweep graph at once; uniform Cartesian meshes build them only on demand
-    if (!P.cartesian && (rc = ensure_heavy(P)) != SMM_OK) {
+    if (!P.cartesian && (rc = ensure_heavy(P, &err)) != SMM_OK) {
         delete pr;
-        return fail(ctx, rc, "geometry setup failed");
+        return fail(ctx, rc, err.empty() ? std::string("geometry setup failed") : err);
     }
     P.q.assign((size_t)P.ne * P.n, 0.0);
     *out = pr;
@@ -292,8 +292,9 @@ static int ensure_host(smm_problem* pr, bool general = true) {
     if (P.psibar.empty()) P.psibar.assign((size_t)P.nbf * P.nq * P.nd, 0.0);
     if (P.cartesian && P.Pm.empty()) setup_cartesian_operators(P);
     if (general) {
-        int rc = ensure_heavy(P);
-        if (rc) return fail(P.ctx, rc, "geometry setup failed");
+        std::string err;
+        int rc = ensure_heavy(P, &err);
+        if (rc) return fail(P.ctx, rc, err.empty() ? std::string("geometry setup failed") : err);
         if (!P.lhs_ready) {
             assemble_ip(P);
             assemble_correction_operator(P);
@@ -947,6 +948,26 @@ int smm_debug_ip_dense(const smm_problem* prob_c, double* A, double* b_fixed) {
             }
     }
     if (b_fixed) std::memcpy(b_fixed, P.b_fixed.data(), sizeof(double) * N);
+    return SMM_OK;
+}
+
+int smm_debug_sweep_graph(smm_problem* prob, int* level, unsigned char* upstream) {
+    if (!prob) return SMM_EINVAL;
+    Problem& P = prob->P;
+    std::string err;
+    int rc = ensure_heavy(P, &err);
+    if (rc) return fail(P.ctx, rc, err.empty() ? std::string("geometry setup failed") : err);
+    const int nl = P.nlev_max, nt = P.ntiles;
+    for (int d = 0; d < P.nd; ++d) {
+        if (level)
+            for (int t = 0; t < nt; ++t) {
+                const int* lp = &P.lev_ptr[((size_t)d * nt + t) * (nl + 1)];
+                for (int l = 0; l < nl; ++l)
+                    for (int e = lp[l]; e < lp[l + 1]; ++e) level[(size_t)d * P.ne + P.lev_elem[(size_t)d * P.ne + e]] = l;
+            }
+        if (upstream)
+            for (int K = 0; K < P.ne; ++K) upstream[(size_t)d * P.ne + K] = P.upflag[(size_t)d * P.ne + K];
+    }
     return SMM_OK;
 }
 

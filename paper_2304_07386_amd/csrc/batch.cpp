@@ -1137,6 +1137,9 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     const int aa = std::max(0, std::min(o.anderson, 2));
     std::vector<double> gram(6 * (size_t)np), coef(3 * (size_t)np);
     int nactive = np;
+    // per problem: stopped on the outer test with a trusted moment solve
+    // (the final status comes from this flag, not from the last residual)
+    std::vector<uint8_t> converged(np, 0);
     int it;
     for (auto& e : B->pev)
         if (!e) HIPCHK(c, hipEventCreate(&e));
@@ -1261,6 +1264,7 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
             // one stopped by max_inner)
             const bool trusted = (o.inner_adapt <= 0 || tol_k[b] <= tight) && B->cg_conv[b];
             if (!std::isfinite(r) || (r < o.outer_tol && trusted)) {
+                converged[b] = std::isfinite(r) ? 1 : 0;
                 B->active[b] = 0;
                 --nactive;
                 changed = true;
@@ -1277,7 +1281,7 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
         inf[b].t_total_ms = tsolve + tsetup;
         inf[b].t_setup_ms = tsetup;
         if (!std::isfinite(inf[b].residual)) status = SMM_ENAN;
-        else if (status == SMM_OK && !(inf[b].residual < o.outer_tol)) status = SMM_ENOCONV;
+        else if (status == SMM_OK && !converged[b]) status = SMM_ENOCONV;
     }
     B->active.assign(np, 1);
     (void)put(c, B->d_active, B->active.data(), sizeof(int) * np);
@@ -1535,6 +1539,49 @@ int smm_batch_time_kernel(smm_batch* batch, int kernel, int reps, double* ms_avg
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *ms_avg = ms / reps;
+    return SMM_OK;
+}
+
+int smm_batch_apply_sweep(smm_batch* batch, int precision, const double* const* S, int k, double* psi_k) {
+    if (!batch || !psi_k) return SMM_EINVAL;
+    smm_ctx* c = batch->ctx;
+    if (precision != SMM_FP64 && precision != SMM_FP32_SWEEP)
+        return fail(c, SMM_EINVAL, "smm_batch_apply_sweep: unknown precision");
+    if (k < 0 || k >= batch->nprob) return fail(c, SMM_EINVAL, "smm_batch_apply_sweep: problem index out of range");
+    const bool fp64 = precision == SMM_FP64;
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc;
+    // the launch configuration of smm_batch_solve: tuned grids and streams
+    if ((rc = batch_autotune(batch, fp64))) return rc;
+    batch->active.assign(batch->nprob, 1);
+    if ((rc = put(c, batch->d_active, batch->active.data(), sizeof(int) * batch->nprob))) return rc;
+    for (int b = 0; b < batch->nprob; ++b) {
+        const long L = batch->hP[b].L;
+        if (fp64) {
+            std::vector<double> h(L, 0.0);
+            if (S && S[b]) std::copy(S[b], S[b] + L, h.begin());
+            if ((rc = put(c, batch->pp[b].S, h.data(), sizeof(double) * L))) return rc;
+        } else {
+            std::vector<float> h(L, 0.0f);
+            if (S && S[b])
+                for (long t = 0; t < L; ++t) h[t] = (float)S[b][t];
+            if ((rc = put(c, batch->pp[b].S, h.data(), sizeof(float) * L))) return rc;
+        }
+    }
+    if ((rc = batch_sweep(batch, fp64, true))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const BProb& D = batch->hP[k];
+    const size_t cnt = (size_t)D.nd * D.Lpad;
+    if (fp64) {
+        std::vector<double> h(cnt);
+        HIPCHK(c, hipMemcpy(h.data(), batch->pp[k].psi, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+        for (int d = 0; d < D.nd; ++d) std::copy(&h[(size_t)d * D.Lpad], &h[(size_t)d * D.Lpad] + D.L, psi_k + (size_t)d * D.L);
+    } else {
+        std::vector<float> h(cnt);
+        HIPCHK(c, hipMemcpy(h.data(), batch->pp[k].psi, sizeof(float) * cnt, hipMemcpyDeviceToHost));
+        for (int d = 0; d < D.nd; ++d)
+            for (long t = 0; t < D.L; ++t) psi_k[(size_t)d * D.L + t] = h[(size_t)d * D.Lpad + t];
+    }
     return SMM_OK;
 }
 

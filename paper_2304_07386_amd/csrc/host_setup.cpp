@@ -588,8 +588,12 @@ void cartesian_boundary_traces(const Problem& P, std::vector<double>& bx, std::v
 // Sec. 6.5) only faces inside a tile are edges; inflow across a tile face is
 // the previous sweep's.  Level lists per (direction, tile): lev_ptr holds the
 // offsets into the direction's element list, which is ordered by tile, then
-// level, then element.
-void setup_sweep_graph(Problem& P) {
+// level, then element.  Kahn's algorithm must reach every element: a cycle
+// (possible only when some chord quadrilateral is not convex) leaves the
+// elements on it and downstream of it unvisited, and the sweep could not
+// order them, so the problem is refused (SMM_EUNSUPPORTED) rather than swept
+// with a same-level read of a neighbour still being written.
+int setup_sweep_graph(Problem& P, std::string& err) {
     const int ne = P.ne, nd = P.nd;
     const int tx = P.tile_x > 0 ? P.tile_x : P.nx, ty = P.tile_y > 0 ? P.tile_y : P.ny;
     const int ntx = (P.nx + tx - 1) / tx, nty = (P.ny + ty - 1) / ty;
@@ -620,8 +624,10 @@ void setup_sweep_graph(Problem& P) {
         std::vector<int> frontier, next;
         for (int K = 0; K < ne; ++K)
             if (indeg[K] == 0) frontier.push_back(K);
+        int visited = 0;
         while (!frontier.empty()) {
             next.clear();
+            visited += (int)frontier.size();
             for (int K : frontier)
                 for (int f = 0; f < 4; ++f) {
                     if (!edge(K, f)) continue;
@@ -634,6 +640,12 @@ void setup_sweep_graph(Problem& P) {
                 }
             std::sort(next.begin(), next.end());
             frontier.swap(next);
+        }
+        if (visited != ne) {
+            P.upflag.clear();
+            err = "the upwind graph of direction " + std::to_string(d) + " has a cycle (" +
+                  std::to_string(ne - visited) + " elements unordered): a chord quadrilateral is not convex";
+            return SMM_EUNSUPPORTED;
         }
         for (int K = 0; K < ne; ++K) P.nlev_max = std::max(P.nlev_max, level[K] + 1);
         lev_of[d] = level;
@@ -662,6 +674,7 @@ void setup_sweep_graph(Problem& P) {
             P.lev_elem[(size_t)d * ne + at++] = K;
         }
     }
+    return SMM_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -122,9 +122,9 @@ struct Problem {
 };
 
 int setup_geometry(Problem& P, std::string& err, bool heavy);
-int ensure_heavy(Problem& P);   // per-element quadrature data and sweep graph, on demand
+int ensure_heavy(Problem& P, std::string* err = nullptr);   // per-element quadrature data and sweep graph, on demand
 void setup_cartesian_operators(Problem& P);
-void setup_sweep_graph(Problem& P);
+int setup_sweep_graph(Problem& P, std::string& err);  // SMM_EUNSUPPORTED on a cycle
 void assemble_ip(Problem& P);
 void add_volume_block(const Problem& P, int K, double* blk);
 void add_boundary_block(const Problem& P, int K, int f, double* blk);

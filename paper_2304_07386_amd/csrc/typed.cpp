@@ -28,15 +28,22 @@ bool typed_applicable(const Problem& P) {
            (P.inflow_layout == SMM_INFLOW_VACUUM || P.inflow_layout == SMM_INFLOW_ISO_FACE);
 }
 
-int ensure_heavy(Problem& P) {
+int ensure_heavy(Problem& P, std::string* err_out) {
+    std::string err;
     if (!P.heavy_ready) {
-        std::string err;
         int rc = setup_geometry(P, err, true);
-        if (rc != SMM_OK) return rc;
+        if (rc != SMM_OK) {
+            if (err_out) *err_out = err;
+            return rc;
+        }
         P.heavy_ready = true;
     }
     if (!P.graph_ready) {
-        setup_sweep_graph(P);
+        int rc = setup_sweep_graph(P, err);
+        if (rc != SMM_OK) {
+            if (err_out) *err_out = err;
+            return rc;
+        }
         P.graph_ready = true;
     }
     return SMM_OK;

@@ -33,7 +33,7 @@ EXPORTED = [
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
     "smm_batch_history", "smm_debug_mg_level", "smm_debug_batch_precond", "smm_debug_batch_spmv",
-    "smm_debug_batch_grouped",
+    "smm_debug_batch_grouped", "smm_debug_sweep_graph", "smm_batch_apply_sweep",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
@@ -117,6 +117,8 @@ def load_library(path: str = LIB_PATH):
         "smm_time_sweep": (ip, [vp, ip, ip, dp]),
         "smm_debug_typed_dense": (ip, [vp, vp, vp, vp]),
         "smm_debug_corr_dense": (ip, [vp, vp]),
+        "smm_debug_sweep_graph": (ip, [vp, vp, vp]),
+        "smm_batch_apply_sweep": (ip, [vp, ip, C.POINTER(vp), ip, vp]),
         "smm_batch_create": (ip, [vp, C.POINTER(vp), ip, C.POINTER(vp)]),
         "smm_batch_destroy": (ip, [vp]),
         "smm_batch_solve": (ip, [vp, C.POINTER(smm_solve_opts), C.POINTER(vp), C.POINTER(smm_solve_info)]),
@@ -370,6 +372,14 @@ def smm_set_sweep_path(prob: Problem, path: int):
     _check(load_library().smm_set_sweep_path(prob.handle, int(path)), prob.ctx)
 
 
+def smm_debug_sweep_graph(prob: Problem):
+    """(level [n_dir, n_elem], upstream bits [n_dir, n_elem]) of the sweep graph."""
+    lev = np.zeros((prob.n_dir, prob.n_elem), dtype=np.int32)
+    up = np.zeros((prob.n_dir, prob.n_elem), dtype=np.uint8)
+    _check(load_library().smm_debug_sweep_graph(prob.handle, _ptr(lev), _ptr(up)), prob.ctx)
+    return lev, up
+
+
 def smm_time_sweep(prob: Problem, precision: int, reps: int) -> float:
     ms = C.c_double()
     _check(load_library().smm_time_sweep(prob.handle, precision, reps, C.byref(ms)), prob.ctx)
@@ -506,6 +516,21 @@ def smm_debug_batch_spmv(batch, xs):
     yp = (C.c_void_p * len(ys))(*[y.ctypes.data for y in ys])
     _check(load_library().smm_debug_batch_spmv(batch.handle, xp, yp), batch.ctx)
     return ys
+
+
+def smm_batch_apply_sweep(batch, precision: int, sources, k: int):
+    """One batched sweep of every problem on the isotropic sources `sources`
+    (a list of host arrays [n_elem*n_node], None entries = zero); returns
+    problem k's angular flux as a host array [n_dir, n_elem, n_node]."""
+    srcs = [None if a is None else _f64(a) for a in sources]
+    assert len(srcs) == batch.n
+    for a, p in zip(srcs, batch.probs):
+        assert a is None or a.size == p.n_elem * p.n_node
+    arr = (C.c_void_p * batch.n)(*[None if a is None else a.ctypes.data for a in srcs])
+    pk = batch.probs[k]
+    psi = np.zeros((pk.n_dir, pk.n_elem, pk.n_node))
+    _check(load_library().smm_batch_apply_sweep(batch.handle, precision, arr, int(k), _ptr(psi)), batch.ctx)
+    return psi
 
 
 def smm_debug_batch_grouped(batch, grouped: int):

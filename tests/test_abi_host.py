@@ -4,6 +4,9 @@
 * Host-only contexts run the one-time setup; its tables equal the oracle's
   (IP operator and fixed right-hand side of eq. ipsmm, quadrature, node
   coordinates) on straight, non-uniform and curved meshes.
+* The sweep graph (levels and upstream faces per direction, Sec. 4) equals
+  the oracle's bit for bit on curved meshes and with tiles; a mesh whose
+  upwind graph has a cycle is refused.
 * Argument validation and error codes (forced from the host).
 """
 import os
@@ -157,3 +160,49 @@ def test_tiles_and_cg_calls_on_the_host(hctx):
     with pytest.raises(L.SmmError) as e:
         L.smm_solve(p, L.smm_default_opts(discretization=L.SMM_DISC_CG))
     assert e.value.code == L.SMM_ESTATE
+
+
+def _graph_compare(p, pr, block=None):
+    from oracle import transport
+    lev, up = L.smm_debug_sweep_graph(p)
+    for d in range(len(pr.w)):
+        ups, lv = transport.sweep_graph(pr.mesh, pr.omega[d], block)
+        bits = (ups.astype(np.uint8) << np.arange(4, dtype=np.uint8)).sum(axis=1).astype(np.uint8)
+        assert np.array_equal(lev[d], lv), d
+        assert np.array_equal(up[d], bits), d
+
+
+@pytest.mark.parametrize("amp,p", [(0.09, 2), (0.09, 3), (0.0, 1)])
+def test_sweep_graph_matches_oracle(hctx, amp, p):
+    wl = config_curved_mms(n=7, p=p, sn=8, amplitude=amp)
+    pr = osmm.make_problem(wl)
+    _graph_compare(L.problem_from_workload(hctx, wl, q=pr.q, psibar=pr.psibar), pr)
+
+
+def test_sweep_graph_tiles_match_oracle(hctx):
+    from oracle import transport
+    wl = config_curved_mms(n=9, p=2, sn=6, amplitude=0.09)
+    pr = osmm.make_problem(wl, tiles=(4, 3))
+    p = L.problem_from_workload(hctx, wl, q=pr.q, psibar=pr.psibar)
+    L.smm_set_sweep_tiles(p, 4, 3)
+    _graph_compare(p, pr, transport.block_ids(pr.mesh, 4, 3))
+
+
+def test_cyclic_sweep_graph_refused(hctx):
+    # 2 x 2 straight elements whose shared vertex sits inside the triangle of
+    # element 0's other three corners: that chord quadrilateral has a reflex
+    # angle there (det J stays positive at the Gauss points), the four faces
+    # around the vertex span less than 180 degrees, and directions across
+    # them circulate 0 -> 1 -> 3 -> 2 -> 0
+    from oracle import fem, transport
+    from workloads import Workload
+    ctrl = structured_ctrl(np.array([0.0, 1.0, 2.0]), np.array([0.0, 1.0, 2.0]), 1)
+    ctrl[1, 1] = (0.48, 0.48)
+    wl = Workload("dart", 2, 2, 1, 1, 4, ctrl, np.ones(4), np.full(4, 0.5), q_elem=np.ones(4))
+    pr = osmm.make_problem(wl)
+    with pytest.raises(RuntimeError, match="cycle"):
+        for d in range(len(pr.w)):
+            transport.sweep_graph(pr.mesh, pr.omega[d])
+    with pytest.raises(L.SmmError) as e:
+        L.smm_problem_create(hctx, 2, 2, 1, ctrl, 1, 4)
+    assert e.value.code == L.SMM_EUNSUPPORTED and "cycle" in str(e.value)

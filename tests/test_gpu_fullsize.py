@@ -7,6 +7,13 @@ degenerate case, against the oracle.
   and three members the oracle can solve in seconds (seeds 133, 196, 10:
   17^2 p = 1 S4, 16^2 p = 2 S6, 19^2 p = 3 S4), solved inside that batch,
   match the oracle's converged flux to the FP32 bar (1e-5 relative L2).
+* The batched sweep kernel, in the launch configuration of that batch (the
+  per-order persistent launches whose anti-diagonals span several 64-slot
+  chunks), on seeded sources: sampled directions of members 9 (93^2 p = 4
+  S6), 12 (81^2 p = 4), 0 (115^2 p = 2), 19 (99^2 p = 1) and 23 (118^2 p = 3)
+  against the oracle's sweep, FP64 to 1e-12 and FP32 to 1e-5 relative L2;
+  and the two-material 128^2 channel problem (the several-materials path of
+  that kernel) likewise.
 * The full-size channel problem: FP32 sweeps within 1e-5 of the all-FP64
   solve.
 * No scattering (sigma_s = 0): G does not depend on X, so the second outer
@@ -58,6 +65,44 @@ def test_full_batch_sampled_members(ctx):
     L.smm_batch_destroy(batch)
 
 
+def _batched_sweep_vs_oracle(ctx, wls, members, dirs_per_member, seed):
+    probs = [L.problem_from_workload(ctx, wl) for wl in wls]
+    batch = L.smm_batch_create(ctx, probs)
+    rng = np.random.default_rng(seed)
+    srcs = [None] * len(wls)
+    for k in members:
+        srcs[k] = rng.uniform(0.5, 1.5, size=probs[k].n_elem * probs[k].n_node)
+    worst = {}
+    for k in members:
+        pr = osmm.make_problem(wls[k])
+        nd = len(pr.w)
+        dirs = sorted({(nd * j) // dirs_per_member for j in range(dirs_per_member)} | {nd - 1})
+        ref = transport.sweep(pr.mesh, pr.omega[dirs], pr.sigma_t, srcs[k].reshape(pr.ne, pr.n), pr.psibar)
+        for prec, bar in ((L.SMM_FP64, 1e-12), (L.SMM_FP32_SWEEP, 1e-5)):
+            announce(f"batched sweep member {k} ({wls[k].nx}^2 p={wls[k].p} S{wls[k].sn}) precision {prec}")
+            psi = L.smm_batch_apply_sweep(batch, prec, srcs, k)
+            assert np.all(np.isfinite(psi))
+            for j, d in enumerate(dirs):
+                e = rel_l2(psi[d], ref[j])
+                worst[(k, prec)] = max(worst.get((k, prec), 0.0), e)
+                assert e < bar, (k, prec, d, e)
+    L.smm_batch_destroy(batch)
+    return worst
+
+
+def test_bench_batch_sweep_full_width_vs_oracle(ctx):
+    announce("full 256-problem batch: batched sweep kernel vs oracle on sampled members and directions")
+    wls = [config_batched_problem(s) for s in range(256)]
+    worst = _batched_sweep_vs_oracle(ctx, wls, (9, 12, 0, 19, 23), 4, 2024)
+    print("worst rel L2 per (member, precision):", worst, flush=True)
+
+
+def test_channel_batched_sweep_vs_oracle(ctx):
+    announce("channel 128^2 p=2 S12 (two materials) as a batch: batched sweep vs oracle")
+    worst = _batched_sweep_vs_oracle(ctx, [config_channel()], (0,), 4, 77)
+    print("worst rel L2 per (member, precision):", worst, flush=True)
+
+
 def test_no_scattering_two_iterations(ctx):
     announce("sigma_s = 0: two outer iterations, phi = one sweep of q")
     wl = config_channel(n=8, p=2, sn=4, side=1.3)
@@ -77,18 +122,21 @@ def test_no_scattering_two_iterations(ctx):
     assert rel_l2(out["varphi"], ref) < 1e-12
 
 
-@pytest.mark.parametrize("path", ["typed", "per_element", "cg"])
-def test_capped_inner_solve_never_converges(ctx, path):
+@pytest.mark.parametrize("path,outer_tol", [("typed", 1e-3), ("per_element", 1e-3), ("cg", 1e-3),
+                                            ("typed", 0.5), ("per_element", 0.5)])
+def test_capped_inner_solve_never_converges(ctx, path, outer_tol):
     """Moment solves stopped by max_inner (one PCG iteration each) do not
     count as converged outer iterations: the solve ends with SMM_ENOCONV and
-    valid outputs, whatever the outer change."""
-    announce(f"capped inner solves ({path}) -> SMM_ENOCONV")
+    valid outputs, whatever the outer change -- also when the last outer
+    change is below a loose outer tolerance (the status comes from the
+    per-problem convergence flag, not from the last residual)."""
+    announce(f"capped inner solves ({path}, outer_tol {outer_tol}) -> SMM_ENOCONV")
     wl = config_channel(n=6, p=2, sn=4, side=1.3)
     pr = osmm.make_problem(wl)
     p = L.problem_from_workload(ctx, wl, q=pr.q)
     kw = {"typed": {}, "per_element": dict(moment_path=1), "cg": dict(discretization=L.SMM_DISC_CG)}[path]
-    opts = L.smm_default_opts(precision=L.SMM_FP64, outer_tol=1e-3, inner_tol=1e-12, max_inner=1, max_outer=12,
-                              **kw)
+    opts = L.smm_default_opts(precision=L.SMM_FP64, outer_tol=outer_tol, inner_tol=1e-12, max_inner=1,
+                              max_outer=12, **kw)
     rc, info = L.smm_solve(p, opts, raise_on_noconv=False)
     assert rc == L.SMM_ENOCONV and info["iterations"] == 12
     assert np.all(np.isfinite(L.smm_get_outputs_host(p)["varphi"]))
