@@ -221,6 +221,24 @@ int smm_apply_moments(smm_problem* prob, int precision, const void* psi, double*
 int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, double* varphi_out,
                 double inner_tol, int max_inner);
 
+/* The same evaluation of G as smm_apply_G, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): this call allocates nothing.  Its work vectors
+ * (scattering source, angular flux, moments, closures, right-hand side, CG
+ * vectors and partial sums) live in one fixed array of 32 MiB per device,
+ * held by the library from the first context on that device until the
+ * process ends.  varphi_in and varphi_out (device, [n_elem*n_node]) stay the
+ * caller's.  The problem's own tables must already be on the device: call
+ * smm_apply_G once after the last smm_set_* change, else SMM_ESTATE.
+ * SMM_EINVAL when the work vectors exceed the array (8 * n_elem*n_node *
+ * (n_dir + 20) bytes, about, with an isotropic source).  Every call on one
+ * device shares that device's array, whose contents are whatever the last
+ * call left (each buffer is written before it is read): calls that overlap
+ * on one device, from any context or stream, race.  smm_get_outputs is not
+ * changed by this call. */
+int smm_apply_G_noalloc(smm_problem* prob, int precision, const double* varphi_in, double* varphi_out,
+                        double inner_tol, int max_inner);
+
 /* Host-only inspection of the setup tables (for tests): the IP matrix as
  * dense row-major [N][N] with N = n_elem*n_node (small problems only), and
  * the fixed right-hand side [N]. */

@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,32 @@ int smm::fail(smm_ctx* c, int code, const std::string& msg) {
     if (c) c->last_error = msg;
     return code;
 }
+
+// ---------------------------------------------------------------------------
+// Work memory of smm_apply_G_noalloc: one fixed array per device, for callers
+// that cannot allocate.  In host code `scratch` only names the symbol; its
+// device address is looked up once per device (with that device current)
+// when a context is created there, and only that address is ever passed to
+// kernels and copies.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the calling thread's current device must be `device`
+int scratch_lookup(int device) {
+    if (device < 0 || device >= kMaxDevices) return SMM_OK;  // the no-allocation entry point refuses it
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return SMM_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SMM_EHIP;
+    g_scratch_ptr[device] = ptr;
+    return SMM_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -48,7 +75,7 @@ int smm_ctx_create(int device, void* hip_stream, smm_ctx** out) {
             delete c;
             return SMM_EHIP;
         }
-        if (hipSetDevice(device) != hipSuccess) {
+        if (hipSetDevice(device) != hipSuccess || scratch_lookup(device) != SMM_OK) {
             delete c;
             return SMM_EHIP;
         }
@@ -861,6 +888,70 @@ int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, doubl
     D.have_outputs = true;
     D.last_varphi = D.x;
     D.last_typed = false;
+    return SMM_OK;
+}
+
+int smm_apply_G_noalloc(smm_problem* prob, int precision, const double* varphi_in, double* varphi_out,
+                        double inner_tol, int max_inner) {
+    if (!prob || !varphi_in || !varphi_out) return SMM_EINVAL;
+    Problem& P = prob->P;
+    Dev& D = prob->D;
+    smm_ctx* c = P.ctx;
+    if (precision != SMM_FP64 && precision != SMM_FP32_SWEEP)
+        return fail(c, SMM_EINVAL, "smm_apply_G_noalloc: unknown precision");
+    if (c->device < 0) return fail(c, SMM_ESTATE, "host-only context");
+    if (c->device >= kMaxDevices) return fail(c, SMM_EUNSUPPORTED, "smm_apply_G_noalloc: device index too large");
+    // every table must already be on the device (this call uploads nothing)
+    const bool gen_sweep = !P.cartesian || P.tile_x > 0 || per_element_forced(D);
+    if (!D.built || D.tables_dirty || D.src_dirty || D.gen_dirty || !P.lhs_ready || !P.rhs_fixed_ready ||
+        (gen_sweep && !D.gen_sweep_built) || !P.graph_ready)
+        return fail(c, SMM_ESTATE, "smm_apply_G_noalloc: the problem's tables are not on the device; call smm_apply_G "
+                                   "once after the last change of materials, source or inflow");
+    void* base;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = g_scratch_ptr[c->device];
+    }
+    if (!base) return fail(c, SMM_ESTATE, "smm_apply_G_noalloc: no scratch address for this device");
+    // carve the work vectors of one evaluation of G out of the array
+    const size_t L = (size_t)P.ne * P.n;
+    const size_t nd_q = P.src_layout == SMM_SRC_ANISO ? (size_t)P.nd : 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return static_cast<unsigned char*>(base) + at;
+    };
+    Dev saved = D;
+    struct Restore {
+        Dev& d;
+        Dev& s;
+        ~Restore() {
+            d.varphi = s.varphi; d.S = s.S; d.psi[0] = s.psi[0]; d.mom = s.mom; d.T = s.T; d.beta = s.beta;
+            d.x = s.x; d.b = s.b; d.r = s.r; d.z = s.z; d.p = s.p; d.qv = s.qv; d.part = s.part; d.scal = s.scal;
+            d.last_mom = s.last_mom; d.last_varphi = s.last_varphi;
+        }
+    } restore{D, saved};
+    D.varphi = reinterpret_cast<double*>(take(sizeof(double) * L));
+    D.S = take(sizeof(double) * nd_q * L);
+    D.psi[0] = take(sizeof(double) * (size_t)P.nd * L);
+    D.mom = reinterpret_cast<double*>(take(sizeof(double) * 8 * L));
+    D.T = reinterpret_cast<double*>(take(sizeof(double) * 3 * L));
+    D.beta = reinterpret_cast<double*>(take(sizeof(double) * (size_t)std::max(1, P.nbf * P.nq)));
+    double** vecs[] = {&D.x, &D.b, &D.r, &D.z, &D.p, &D.qv};
+    for (double** v : vecs) *v = reinterpret_cast<double*>(take(sizeof(double) * L));
+    D.part = reinterpret_cast<double*>(take(sizeof(double) * 3 * (size_t)D.cg_blocks));
+    D.scal = reinterpret_cast<double*>(take(sizeof(double) * 16));
+    if (off > kScratchBytes)
+        return fail(c, SMM_EINVAL, "smm_apply_G_noalloc: the problem needs " + std::to_string(off) +
+                                       " bytes of work memory, more than the " + std::to_string(kScratchBytes) +
+                                       " the no-allocation entry point holds");
+    HIPCHK(c, hipMemcpyAsync(D.varphi, varphi_in, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
+    int its = 0;
+    int rc = eval_G(prob, precision == SMM_FP64, false, true, 0, inner_tol, max_inner, &its);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(varphi_out, D.x, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return SMM_OK;
 }
 

@@ -33,7 +33,7 @@ EXPORTED = [
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
     "smm_batch_history", "smm_debug_mg_level", "smm_debug_batch_precond", "smm_debug_batch_spmv",
-    "smm_debug_batch_grouped", "smm_debug_sweep_graph", "smm_batch_apply_sweep",
+    "smm_debug_batch_grouped", "smm_debug_sweep_graph", "smm_batch_apply_sweep", "smm_apply_G_noalloc",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "smm_apply_sweep": (ip, [vp, ip, vp, ip, vp, vp, ip]),
         "smm_apply_moments": (ip, [vp, ip, vp, vp]),
         "smm_apply_G": (ip, [vp, ip, vp, vp, C.c_double, ip]),
+        "smm_apply_G_noalloc": (ip, [vp, ip, vp, vp, C.c_double, ip]),
         "smm_debug_ip_dense": (ip, [vp, vp, vp]),
         "smm_debug_cg_system": (ip, [vp, vp, vp, vp, vp, vp, vp]),
         "smm_debug_cg_spmv": (ip, [vp, vp, vp]),
@@ -325,6 +326,15 @@ def smm_apply_G(prob: Problem, precision: int, varphi_in, varphi_out, inner_tol:
                 max_inner: int = 100000):
     _check(load_library().smm_apply_G(prob.handle, precision, _ptr(varphi_in), _ptr(varphi_out), inner_tol,
                                       max_inner), prob.ctx)
+
+
+def smm_apply_G_noalloc(prob: Problem, precision: int, varphi_in, varphi_out, inner_tol: float = 1e-14,
+                        max_inner: int = 100000):
+    """smm_apply_G without any device allocation (work vectors in the
+    library's fixed per-device array); the problem's tables must be on the
+    device already (one smm_apply_G call)."""
+    _check(load_library().smm_apply_G_noalloc(prob.handle, precision, _ptr(varphi_in), _ptr(varphi_out),
+                                              inner_tol, max_inner), prob.ctx)
 
 
 def smm_debug_ip_dense(prob: Problem):
