@@ -71,9 +71,15 @@ def make_problem(wl, kappa_scale: float = 1.0, disc: str = "ip", tiles=None) -> 
     sweep over tiles of tx x ty elements (Sec. 6.5)."""
     if disc not in ("ip", "cg"):
         raise ValueError(disc)
-    mesh = fem.build_mesh(wl.ctrl, wl.nx, wl.ny, wl.m, wl.p)
-    omega, w = level_symmetric_2d(wl.sn)
-    ne, n = wl.nx * wl.ny, (wl.p + 1) ** 2
+    if getattr(wl, "elem_ctrl", None) is not None:
+        mesh = fem.build_mesh_general(wl.elem_ctrl, wl.nbr, wl.m, wl.p, wl.bdr_attr)
+    else:
+        mesh = fem.build_mesh(wl.ctrl, wl.nx, wl.ny, wl.m, wl.p)
+    if getattr(wl, "quad", None) is not None:
+        omega, w = np.asarray(wl.quad[0], float), np.asarray(wl.quad[1], float)
+    else:
+        omega, w = level_symmetric_2d(wl.sn)
+    ne, n = mesh.nx * mesh.ny, (wl.p + 1) ** 2
     if wl.q_fn is not None:
         xn = mesh.xnode
         q = np.stack([wl.q_fn(xn[..., 0], xn[..., 1], om[0], om[1]) for om in omega])
@@ -90,15 +96,23 @@ def make_problem(wl, kappa_scale: float = 1.0, disc: str = "ip", tiles=None) -> 
 # ----------------------------------------------------------------------------
 
 def _interior_faces(mesh):
-    """(K1, f1, K2, f2) for each interior face, K1 below/left of K2; the
-    normal of K1's face points from K1 to K2."""
+    """(K1, f1, K2, f2) for each interior face once, K1 < K2 (on a structured
+    grid: K1 below or left of K2); the normal of K1's face points from K1 to
+    K2, and the face points are K1's."""
     out = []
-    for K in range(mesh.nx * mesh.ny):
-        for f in (1, 2):
+    for K in range(len(mesh.nbr)):
+        for f in range(4):
             N = mesh.nbr[K, f]
-            if N >= 0:
-                out.append((K, f, N, fem.OPPOSITE[f]))
+            if N > K:
+                out.append((K, f, N, int(mesh.nbr_face[K, f])))
     return out
+
+
+def _side2(mesh, K1, f1, K2, f2):
+    """Basis values [q, n] and physical gradients [q, n, 2] of K2 on the
+    shared face, at K1's face points."""
+    U, G = mesh.Uf[f2], mesh.gradUf[K2, f2]
+    return (U[::-1], G[::-1]) if mesh.flip[K1, f1] else (U, G)
 
 
 def penalty(prob: OracleProblem, K1: int, K2: int) -> float:
@@ -138,8 +152,9 @@ def ip_matrix(prob: OracleProblem) -> sp.csr_matrix:
         kap = penalty(prob, K1, K2)
         nh = mesh.nhat[K1, f1]                              # [q, 2]
         dsw = mesh.dsw[K1, f1]
+        U2, G2 = _side2(mesh, K1, f1, K2, f2)
         side = {0: (K1, mesh.Uf[f1], mesh.gradUf[K1, f1], 1.0),
-                1: (K2, mesh.Uf[f2], mesh.gradUf[K2, f2], -1.0)}
+                1: (K2, U2, G2, -1.0)}
         for su in (0, 1):
             Ku, Uu, Gu, sgu = side[su]
             dnu = np.einsum("qia,qa->qi", Gu, nh)          # grad u . n
@@ -191,11 +206,12 @@ def rhs_fixed(prob: OracleProblem) -> np.ndarray:
                 b[K] -= 2.0 * np.einsum("q,qi,q->i", mesh.dsw[K, f], mesh.Uf[f], jin[bf])
     for K1, f1, K2, f2 in _interior_faces(mesh):
         nh, dsw = mesh.nhat[K1, f1], mesh.dsw[K1, f1]
+        U2, _ = _side2(mesh, K1, f1, K2, f2)
         q1a = np.stack([mesh.Uf[f1] @ Q1[0, K1], mesh.Uf[f1] @ Q1[1, K1]], axis=1)
-        q1b = np.stack([mesh.Uf[f2] @ Q1[0, K2], mesh.Uf[f2] @ Q1[1, K2]], axis=1)
+        q1b = np.stack([U2 @ Q1[0, K2], U2 @ Q1[1, K2]], axis=1)
         avg = 0.5 * (np.sum(q1a * nh, 1) / st[K1] + np.sum(q1b * nh, 1) / st[K2])
         b[K1] -= np.einsum("q,qi,q->i", dsw, mesh.Uf[f1], avg)
-        b[K2] += np.einsum("q,qi,q->i", dsw, mesh.Uf[f2], avg)
+        b[K2] += np.einsum("q,qi,q->i", dsw, U2, avg)
     return b.reshape(-1)
 
 
@@ -224,18 +240,19 @@ def rhs_correction(prob: OracleProblem, T: np.ndarray, beta: np.ndarray) -> np.n
                 b[K] -= np.einsum("q,qi,q->i", mesh.dsw[K, f], mesh.Uf[f], beta[bf])
     for K1, f1, K2, f2 in _interior_faces(mesh):
         nh, dsw = mesh.nhat[K1, f1], mesh.dsw[K1, f1]
+        U2, G2 = _side2(mesh, K1, f1, K2, f2)
         d1 = _divT(mesh.gradUf[K1, f1], T[:, K1, :])
-        d2 = _divT(mesh.gradUf[K2, f2], T[:, K2, :])
+        d2 = _divT(G2, T[:, K2, :])
         avg = 0.5 * (np.sum(d1 * nh, 1) / st[K1] + np.sum(d2 * nh, 1) / st[K2])
         t1 = np.stack([mesh.Uf[f1] @ T[c, K1] for c in range(3)], axis=1)   # [q, 3]
-        t2 = np.stack([mesh.Uf[f2] @ T[c, K2] for c in range(3)], axis=1)
+        t2 = np.stack([U2 @ T[c, K2] for c in range(3)], axis=1)
         tn = lambda t: np.stack([t[:, 0] * nh[:, 0] + t[:, 1] * nh[:, 1],
                                  t[:, 1] * nh[:, 0] + t[:, 2] * nh[:, 1]], axis=1)
         jump = tn(t1) - tn(t2)                                            # [T n]
         b[K1] += np.einsum("q,qi,q->i", dsw, mesh.Uf[f1], avg)
-        b[K2] -= np.einsum("q,qi,q->i", dsw, mesh.Uf[f2], avg)
+        b[K2] -= np.einsum("q,qi,q->i", dsw, U2, avg)
         b[K1] += 0.5 * np.einsum("q,qia,qa->i", dsw, mesh.gradUf[K1, f1], jump) / st[K1]
-        b[K2] += 0.5 * np.einsum("q,qia,qa->i", dsw, mesh.gradUf[K2, f2], jump) / st[K2]
+        b[K2] += 0.5 * np.einsum("q,qia,qa->i", dsw, G2, jump) / st[K2]
     return b.reshape(-1)
 
 

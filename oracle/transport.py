@@ -29,7 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .fem import Mesh, OPPOSITE
+from .fem import Mesh, neighbour_trace
 
 
 def chord_normals(mesh: Mesh) -> np.ndarray:
@@ -133,7 +133,7 @@ def sweep(mesh: Mesh, omega: np.ndarray, sigma_t: np.ndarray, S: np.ndarray,
                             val[t] = psibar[mesh.bface_id[K, f], :, d]
                     else:
                         src = psi[d, N] if upstream[K, f] else lag[N]
-                        val[t] = Uf[OPPOSITE[f]] @ src
+                        val[t] = neighbour_trace(mesh, K, f, src)
                 rhs += np.einsum("kq,qi,kq->ki", neg, Uf[f], val)
             psi[d, Ks] = np.linalg.solve(A, rhs[..., None])[..., 0]
     return psi
@@ -197,8 +197,9 @@ def inflow_current(mesh: Mesh, omega: np.ndarray, w: np.ndarray, psibar) -> np.n
 
 def inflow_at_points(mesh: Mesh, omega: np.ndarray, inflow) -> np.ndarray | None:
     """Tabulate an inflow description at boundary face points
-    [n_bf, nq, n_dir].  ``inflow`` is "vacuum", ("iso", value) or
-    ("fn", f(x, y, ox, oy))."""
+    [n_bf, nq, n_dir].  ``inflow`` is "vacuum", ("iso", value),
+    ("attr", values) -- isotropic, values[a] on the faces of boundary
+    attribute a -- or ("fn", f(x, y, ox, oy))."""
     if inflow is None or (isinstance(inflow, str) and inflow == "vacuum"):
         return None
     nbf = len(mesh.bfaces)
@@ -208,6 +209,8 @@ def inflow_at_points(mesh: Mesh, omega: np.ndarray, inflow) -> np.ndarray | None
         x = mesh.xf[K, f]
         if kind == "iso":
             out[b] = val
+        elif kind == "attr":
+            out[b] = val[mesh.bdr_attr[K, f]]
         else:
             out[b] = val(x[:, 0:1], x[:, 1:2], omega[None, :, 0], omega[None, :, 1])
     return out

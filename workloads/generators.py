@@ -23,6 +23,8 @@ __all__ = [
     "Workload", "config_plain", "config_curved_mms", "config_channel",
     "batched_params", "config_batched_problem", "config_blobs", "config_tdl",
     "mms_psi", "mms_source", "mms_phi", "absorber_inflow", "chebyshev_vertices",
+    "rotate_elements", "elements_from_corners", "inner_square_mesh", "general_workload",
+    "product_quadrature_2d",
 ]
 
 _MASK64 = (1 << 64) - 1
@@ -128,6 +130,15 @@ class Workload:
     q_fn: object = None
     inflow: object = "vacuum"
     meta: dict = field(default_factory=dict)
+    # a mesh given element by element (any conforming quadrilateral mesh):
+    # control points [ne][(m+1)^2][2], neighbours [ne][4] (-1: boundary) and
+    # boundary attributes [ne][4]; then nx = ne, ny = 1 and ctrl is unused
+    elem_ctrl: np.ndarray | None = None
+    nbr: np.ndarray | None = None
+    bdr_attr: np.ndarray | None = None
+    # an explicit angular quadrature (omega [n_dir][3], w [n_dir]) instead of
+    # the level-symmetric set of order sn
+    quad: tuple | None = None
 
     @property
     def n_elem(self) -> int:
@@ -139,6 +150,8 @@ class Workload:
 
     @property
     def n_dir(self) -> int:
+        if self.quad is not None:
+            return len(self.quad[1])
         return self.sn * (self.sn + 2) // 2
 
 
@@ -313,3 +326,128 @@ def config_blobs(seed: int, n: int = 64, p: int = 2, sn: int = 8) -> Workload:
     ne = n * n
     return Workload(f"blobs{seed}", n, n, 1, p, sn, _uniform_square(n, 1), st, st * c,
                     q_elem=np.full(ne, 1.0), meta={"seed": seed, "regions": reg})
+
+
+# ----------------------------------------------------------------------------
+# Meshes given element by element (unstructured, or with rotated local
+# numbering), and a non-level-symmetric angular set.
+# ----------------------------------------------------------------------------
+
+def rotate_elements(elem_ctrl: np.ndarray, nbr: np.ndarray, rot) -> tuple:
+    """Renumber element K's local frame by rot[K] quarter turns (the same
+    physical element): the new face f is the old face f + 1 (mod 4), i.e.
+    the new reference point (xi', eta') is the old (1 - eta', xi')."""
+    elem_ctrl = np.array(elem_ctrl, dtype=float)
+    nbr = np.array(nbr, dtype=np.int64)
+    m = int(round(np.sqrt(elem_ctrl.shape[1]))) - 1
+    for K, r in enumerate(rot):
+        for _ in range(int(r) % 4):
+            old = elem_ctrl[K].copy()
+            for b2 in range(m + 1):
+                for a2 in range(m + 1):
+                    elem_ctrl[K, a2 + (m + 1) * b2] = old[(m - b2) + (m + 1) * a2]
+            nbr[K] = np.roll(nbr[K], -1)
+    return elem_ctrl, nbr
+
+
+def elements_from_corners(corners: np.ndarray, m: int, displace=None):
+    """Elements from their four corners [ne][4][2] (counter-clockwise, local
+    corner order (0,0), (1,0), (1,1), (0,1)): the Gauss-Lobatto control
+    points of each bilinear quadrilateral, moved by displace(x, y) -> (dx, dy)
+    when given; neighbours found by matching face end points."""
+    corners = np.asarray(corners, dtype=float)
+    g = lobatto_points_unit(m)
+    ne = len(corners)
+    ctrl = np.zeros((ne, (m + 1) ** 2, 2))
+    for K in range(ne):
+        c = corners[K]
+        for b in range(m + 1):
+            for a in range(m + 1):
+                u, v = g[a], g[b]
+                ctrl[K, a + (m + 1) * b] = ((1 - u) * (1 - v) * c[0] + u * (1 - v) * c[1]
+                                            + u * v * c[2] + (1 - u) * v * c[3])
+    if displace is not None:
+        dx, dy = displace(ctrl[..., 0], ctrl[..., 1])
+        ctrl = ctrl + np.stack([dx, dy], axis=-1)
+    ends = {0: (0, 1), 1: (1, 2), 2: (3, 2), 3: (0, 3)}
+    key = lambda P: (round(float(P[0]), 9), round(float(P[1]), 9))
+    faces = {}
+    for K in range(ne):
+        for f, (a, b) in ends.items():
+            faces.setdefault(frozenset((key(corners[K, a]), key(corners[K, b]))), []).append((K, f))
+    nbr = -np.ones((ne, 4), dtype=np.int64)
+    for lst in faces.values():
+        if len(lst) == 2:
+            (K1, f1), (K2, f2) = lst
+            nbr[K1, f1], nbr[K2, f2] = K2, K1
+    return ctrl, nbr
+
+
+def inner_square_mesh(k: int, m: int = 1, r: float = 0.22, theta: float = 0.3, displace=None):
+    """The unit square split into a rotated inner square (half-width r,
+    angle theta, centre (0.5, 0.5)) and four quadrilaterals joining its edges
+    to the outer edges, each cut into k x k elements by bilinear
+    subdivision: an unstructured conforming mesh whose inner-square corners
+    are shared by three macro quadrilaterals.  Boundary attribute: the
+    outer side (0 bottom, 1 right, 2 top, 3 left)."""
+    ct, st = np.cos(theta), np.sin(theta)
+    inner = [np.array([0.5 + (x * ct - y * st), 0.5 + (x * st + y * ct)])
+             for x, y in ((-r, -r), (r, -r), (r, r), (-r, r))]
+    outer = [np.array(v, float) for v in ((0, 0), (1, 0), (1, 1), (0, 1))]
+    macros = [inner]
+    for s in range(4):
+        a, b = s, (s + 1) % 4
+        macros.append([outer[a], outer[b], inner[b], inner[a]])
+    corners = []
+    for M in macros:
+        for j in range(k):
+            for i in range(k):
+                def at(u, v):
+                    return ((1 - u) * (1 - v) * M[0] + u * (1 - v) * M[1] + u * v * M[2] + (1 - u) * v * M[3])
+                u0, u1, v0, v1 = i / k, (i + 1) / k, j / k, (j + 1) / k
+                corners.append([at(u0, v0), at(u1, v0), at(u1, v1), at(u0, v1)])
+    corners = np.array(corners)
+    ctrl, nbr = elements_from_corners(corners, m, displace)
+    attr = -np.ones((len(corners), 4), dtype=np.int64)
+    for K in range(len(corners)):
+        for f, (a, b) in {0: (0, 1), 1: (1, 2), 2: (3, 2), 3: (0, 3)}.items():
+            if nbr[K, f] >= 0:
+                continue
+            mid = 0.5 * (corners[K, a] + corners[K, b])
+            if abs(mid[1]) < 1e-12:
+                attr[K, f] = 0
+            elif abs(mid[0] - 1) < 1e-12:
+                attr[K, f] = 1
+            elif abs(mid[1] - 1) < 1e-12:
+                attr[K, f] = 2
+            else:
+                attr[K, f] = 3
+    return ctrl, nbr, attr
+
+
+def general_workload(name, elem_ctrl, nbr, m, p, sn, sigma_t, sigma_s, bdr_attr=None, q_elem=None, q_fn=None,
+                     inflow="vacuum", quad=None) -> Workload:
+    """A problem on a mesh given element by element."""
+    ne = len(elem_ctrl)
+    return Workload(name, ne, 1, m, p, sn, None, np.asarray(sigma_t, float), np.asarray(sigma_s, float),
+                    q_elem=q_elem, q_fn=q_fn, inflow=inflow, elem_ctrl=np.asarray(elem_ctrl, float),
+                    nbr=np.asarray(nbr, np.int64), bdr_attr=None if bdr_attr is None else np.asarray(bdr_attr),
+                    quad=quad)
+
+
+def product_quadrature_2d(n_polar: int, n_azim: int):
+    """A product angular set on the upper half sphere (Omega_z > 0): Gauss-
+    Legendre in mu = Omega_z on (0, 1) with n_polar points, and n_azim equally
+    spaced azimuths offset by half a step; weights doubled for the lower half
+    so that they sum to 4 pi (the 2D reduction of Sec. 4).  Directions are
+    ordered by azimuth."""
+    x, w = np.polynomial.legendre.leggauss(n_polar)
+    mu, wm = 0.5 * (x + 1.0), 0.5 * w
+    phis = (np.arange(n_azim) + 0.5) * 2.0 * np.pi / n_azim
+    om, wt = [], []
+    for ph in phis:
+        for c, wc in zip(mu, wm):
+            s = np.sqrt(1.0 - c * c)
+            om.append((s * np.cos(ph), s * np.sin(ph), c))
+            wt.append(2.0 * wc * 2.0 * np.pi / n_azim)
+    return np.array(om), np.array(wt)
