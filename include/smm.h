@@ -26,7 +26,9 @@
  *    smm_get_quadrature() returns them.
  *  - Boundary faces are enumerated by element K, then local face
  *    (0 bottom, 1 right, 2 top, 3 left); each carries nq = p+m+1 Gauss points
- *    ordered by increasing x (faces 0, 2) or increasing y (faces 1, 3).
+ *    ordered by increasing x (faces 0, 2) or increasing y (faces 1, 3) -- on
+ *    a mesh given element by element, by the element's own reference
+ *    coordinate along the face.
  *  - Ownership: the caller owns every array passed in or out.  Inputs given to
  *    smm_set_* are copied before the call returns.  Arguments documented as
  *    "device" must be device pointers on the context's device; they are read
@@ -51,7 +53,7 @@ extern "C" {
 #define SMM_ENOMEM -2        /* device or host allocation failed */
 #define SMM_EHIP -3          /* a HIP runtime call failed */
 #define SMM_ENOCONV -4       /* outer iteration hit max_outer; outputs hold the last iterate */
-#define SMM_ENAN -5          /* NaN or Inf in the outer residual */
+#define SMM_ENAN -5          /* NaN or Inf in the outer residual or in the moment solve */
 #define SMM_EBREAKDOWN -6    /* CG breakdown: p.Ap <= 0 (moment operator not positive definite) */
 #define SMM_EUNSUPPORTED -7  /* valid input the library does not handle (e.g. slanted boundary) */
 #define SMM_ESTATE -8        /* call order violated (e.g. solve before set_materials) */
@@ -68,6 +70,11 @@ extern "C" {
 #define SMM_INFLOW_VACUUM 0  /* psibar = 0 (pointer ignored) */
 #define SMM_INFLOW_ISO_FACE 1/* psibar[n_bface]: isotropic, constant per boundary face */
 #define SMM_INFLOW_FULL 2    /* psibar[n_bface][nq][n_dir] at the boundary face points */
+#define SMM_INFLOW_ISO_ATTR 3/* psibar[n_bdr_attr]: isotropic, one value per boundary attribute */
+
+/* angular quadrature kinds (Sec. 4) */
+#define SMM_QUAD_LEVEL_SYMMETRIC 0
+#define SMM_QUAD_EXPLICIT 1
 
 /* preconditioners of the moment solve */
 #define SMM_PRECOND_BJ 0
@@ -96,6 +103,40 @@ typedef struct {
     const double* ctrl;
 } smm_mesh_desc;
 
+/* Mesh given element by element (Sec. 3.1): any conforming quadrilateral
+ * mesh.  ctrl (host) [n_elem][(m+1)^2][2]: the Gauss-Lobatto control points
+ * of each element's Q_m map, index a + (m+1) b with a along the reference
+ * xi axis; every element must be counter-clockwise (det J > 0).  nbr (host)
+ * [n_elem][4]: the element across local face f (0: eta = 0, 1: xi = 1,
+ * 2: eta = 1, 3: xi = 0), or -1 on the domain boundary; neighbours must
+ * name each other and carry the same face control points (the library
+ * matches the faces and their orientation; SMM_EINVAL if they do not
+ * match).  bdr_attr (host, nullable) [n_elem][4]: a boundary attribute
+ * >= 0 on each boundary face (read on boundary faces only; NULL: the local
+ * face index).  Element order, local numbering and boundary-face order
+ * (element, then local face) are the caller's; DOFs follow them. */
+typedef struct {
+    int n_elem;
+    int m;
+    const double* ctrl;
+    const int* nbr;
+    const int* bdr_attr;
+} smm_mesh_general_desc;
+
+/* Angular quadrature (Sec. 4).  SMM_QUAD_LEVEL_SYMMETRIC: the 2D
+ * half-sphere level-symmetric set of order sn_order in {4, 6, 8, 10, 12}.
+ * SMM_QUAD_EXPLICIT: n_dir directions omega (host, [n_dir][3] unit vectors
+ * with Omega_z >= 0 and nonzero in-plane components) and weights w (host,
+ * [n_dir], positive, summing to 4 pi within 1e-12 relative), in the order
+ * the caller gives them. */
+typedef struct {
+    int kind;
+    int sn_order;
+    int n_dir;
+    const double* omega;
+    const double* w;
+} smm_quad_desc;
+
 typedef struct {
     int n_elem;      /* nx * ny */
     int n_node;      /* (p+1)^2 DOF per element */
@@ -107,6 +148,8 @@ typedef struct {
     int n_levels;    /* max sweep wavefront levels over directions */
     int n_self_types;/* typed Cartesian path: distinct element blocks (0 until built) */
     int n_nbr_types; /* typed Cartesian path: distinct neighbour blocks */
+    int general;     /* 1: mesh given element by element (smm_problem_create_general) */
+    int n_bdr_attr;  /* boundary attributes 0 .. n_bdr_attr - 1 */
 } smm_problem_dims;
 
 typedef struct {
@@ -139,6 +182,11 @@ typedef struct {
                             CG on the per-element path of smm_solve; varphi is returned at the
                             DG nodes (continuous).  `precond` does not apply; Anderson mixing
                             and batches return SMM_EUNSUPPORTED */
+    double kappa_scale;  /* factor on the IP penalty kappa = {(p+1)^2 / (sigma_t h)} (Sec. 6; the
+                            paper scales it on its distorted mesh), >= 0, default 1.  A new value
+                            re-assembles the moment system; a batch keeps the value its problems had
+                            when it was created (another value: SMM_EUNSUPPORTED).  A value that
+                            makes the operator indefinite ends the solve with SMM_EBREAKDOWN. */
 } smm_solve_opts;
 
 typedef struct {
@@ -149,6 +197,13 @@ typedef struct {
     int cg_iterations_max;
     double t_total_ms;       /* wall time of the solve (host clock) */
     double t_setup_ms;       /* one-time setup at the first solve (device tables) */
+    /* device time of the outer-iteration phases, summed over the outer
+     * iterations (HIP events on the context's stream; in a batch, the batch's
+     * launches, which cover every problem): */
+    double t_sweep_ms;       /* scattering source and sweep */
+    double t_moments_ms;     /* angular moments, closures and right-hand side */
+    double t_cg_ms;          /* moment solve (CG) */
+    double t_residual_ms;    /* residual, mixing and shift of the iterates */
 } smm_solve_info;
 
 const char* smm_strerror(int code);
@@ -162,9 +217,25 @@ const char* smm_last_error(smm_ctx* ctx);
 
 /* Geometry, quadrature and basis setup (Sec. 3, Sec. 4).  p in 1..4;
  * sn_order in {4, 6, 8, 10, 12}.  SMM_EINVAL if det J <= 0 at a volume
- * quadrature point or if the boundary is not axis-aligned. */
+ * quadrature point; SMM_EUNSUPPORTED if the upwind graph of a direction has
+ * a cycle (a chord quadrilateral that is not convex).  Boundary attributes
+ * of a structured mesh: the local face index (0 bottom, 1 right, 2 top,
+ * 3 left). */
 int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_order,
                        smm_problem** out);
+/* The same for any conforming quadrilateral mesh given element by element
+ * and any angular quadrature (mesh and quad as documented at their types).
+ * Such a problem runs on the per-element paths: per-element assembly and
+ * elimination in the sweep, the block-sparse IP moment system (eq. ipsmm)
+ * with block-Jacobi PCG, and beta at every boundary point from its own
+ * normal (Sec. 4); batches, tiles, the CG moment system and Anderson mixing
+ * return SMM_EUNSUPPORTED on it.  A structured mesh descriptor with an
+ * explicit quadrature goes through smm_problem_create_q. */
+int smm_problem_create_general(smm_ctx* ctx, const smm_mesh_general_desc* mesh, int p, const smm_quad_desc* quad,
+                               smm_problem** out);
+/* smm_problem_create with a quadrature descriptor. */
+int smm_problem_create_q(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, const smm_quad_desc* quad,
+                         smm_problem** out);
 int smm_problem_destroy(smm_problem* prob);
 int smm_get_dims(const smm_problem* prob, smm_problem_dims* out);
 
@@ -188,9 +259,19 @@ void smm_default_opts(smm_solve_opts* opts);
 
 /* Fixed-point solve X^{k+1} = G(X^k) (eq. fixed-point).  varphi0 (host,
  * [n_elem*n_node]) is read when opts->start == SMM_START_GIVEN.  Returns
- * SMM_ENOCONV with valid outputs when max_outer is reached. */
+ * SMM_ENOCONV with valid outputs when max_outer is reached, SMM_ENAN when a
+ * residual or the moment solve turns non-finite (a non-finite varphi0, say),
+ * SMM_EBREAKDOWN when the moment solve meets p.Ap <= 0.  opts->start ==
+ * SMM_START_LEARNED (smm_cnn.h) uses the network set by smm_set_warmstart
+ * (uniform Cartesian meshes with an isotropic source). */
 int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varphi0,
               smm_solve_info* info);
+
+/* Outer residual r_k (and CG iterations of that outer iteration's moment
+ * solve, nullable) of each outer iteration of the last smm_solve: the first
+ * min(max_len, *len) entries are written (host), *len receives the
+ * iteration count. */
+int smm_solve_history(const smm_problem* prob, int max_len, double* residual, int* cg_iterations, int* len);
 
 /* Results of the last smm_solve or smm_apply_G.  Any pointer may be NULL.
  * varphi, phi [n_elem*n_node]; J [2][n_elem*n_node]; T [3][n_elem*n_node]
@@ -327,6 +408,14 @@ int smm_debug_batch_spmv(smm_batch* batch, const double* const* x, double* const
  * [n_dir][n_elem][n_node] doubles) receives problem k's angular flux.
  * Overwrites the batch's sweep buffers (outputs of the last solve stay). */
 int smm_batch_apply_sweep(smm_batch* batch, int precision, const double* const* S, int k, double* psi_k);
+/* Testing hook: force the kernel shape of the batch's persistent sweep
+ * launches: 0 column-wave (the NB waves of a 64-slot chunk split each
+ * element's node columns), 1 element-lane (one wave per chunk, each lane a
+ * whole element; anti-diagonals of at most 256 slots, else
+ * SMM_EUNSUPPORTED), -1 the autotuner's choice per launch.  Grids are tuned
+ * again at the next solve or sweep.  Both shapes apply each element's
+ * operator rows in the same order. */
+int smm_debug_batch_sweep_shape(smm_batch* batch, int shape);
 /* Testing hook: choose the batch's PCG kernels: 1 the type-group kernels
  * (one wave per group of elements sharing their blocks), 0 the per-node
  * kernels, -1 the automatic choice (group fill).  Results agree up to the

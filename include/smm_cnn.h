@@ -31,8 +31,9 @@
 extern "C" {
 #endif
 
-/* start mode for smm_batch_solve: the network attached by
- * smm_batch_set_warmstart (falls back to SMM_START_DIFFUSION per problem) */
+/* start mode for smm_batch_solve (and smm_solve): the network attached by
+ * smm_batch_set_warmstart (smm_set_warmstart); falls back to
+ * SMM_START_DIFFUSION per problem whose prediction is not finite */
 #define SMM_START_LEARNED 3
 
 typedef struct smm_cnn smm_cnn;
@@ -98,6 +99,12 @@ int smm_batch_warmstart_targets(smm_batch* batch, int first, int count, float* t
  * input and output channel counts must match smm_batch_warmstart_dims.  The
  * network must outlive its use by the batch. */
 int smm_batch_set_warmstart(smm_batch* batch, smm_cnn* net);
+/* The same network for smm_solve on one problem (SMM_START_LEARNED), which
+ * runs as a batch of one: the problem must be a uniform Cartesian mesh with
+ * an isotropic source, and the network must match it (height ny, width nx,
+ * the channel counts of smm_batch_warmstart_dims).  NULL detaches it.  The
+ * network must outlive its use by the problem. */
+int smm_set_warmstart(smm_problem* prob, smm_cnn* net);
 /* After a solve with SMM_START_LEARNED: used[k] = 1 if problem k started
  * from the learned start, 0 if it fell back to the diffusion start (non-finite
  * prediction). */

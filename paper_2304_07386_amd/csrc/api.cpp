@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/smm_cnn.h"
 #include "api_internal.hpp"
 #include "cg_smm.hpp"
 
@@ -91,31 +92,48 @@ int smm_ctx_destroy(smm_ctx* ctx) {
 
 const char* smm_last_error(smm_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
 
-int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_order, smm_problem** out) {
-    if (!ctx || !mesh || !out || !mesh->ctrl) return fail(ctx, SMM_EINVAL, "null argument");
-    if (p < 1 || p > 4) return fail(ctx, SMM_EINVAL, "p must be in 1..4");
-    if (mesh->nx < 1 || mesh->ny < 1 || mesh->m < 1 || mesh->m > 6)
-        return fail(ctx, SMM_EINVAL, "bad mesh sizes");
-    smm_problem* pr = new (std::nothrow) smm_problem();
-    if (!pr) return SMM_ENOMEM;
-    Problem& P = pr->P;
-    P.ctx = ctx;
-    P.nx = mesh->nx;
-    P.ny = mesh->ny;
-    P.m = mesh->m;
-    P.p = p;
-    P.nb = p + 1;
-    P.n = P.nb * P.nb;
-    P.nq = p + mesh->m + 1;
-    P.ne = P.nx * P.ny;
-    P.sn = sn_order;
-    if (level_symmetric(sn_order, P.omega, P.w) != 0) {
-        delete pr;
-        return fail(ctx, SMM_EINVAL, "S_N order must be 4, 6, 8, 10 or 12");
+}  // extern "C"
+
+// Directions and weights of a quadrature descriptor (Sec. 4).
+static int quad_from_desc(smm_ctx* ctx, const smm_quad_desc* q, Problem& P) {
+    if (!q) return fail(ctx, SMM_EINVAL, "null quadrature descriptor");
+    if (q->kind == SMM_QUAD_LEVEL_SYMMETRIC) {
+        P.sn = q->sn_order;
+        if (level_symmetric(q->sn_order, P.omega, P.w) != 0)
+            return fail(ctx, SMM_EINVAL, "S_N order must be 4, 6, 8, 10 or 12");
+        P.nd = (int)P.w.size();
+        return SMM_OK;
     }
-    P.nd = (int)P.w.size();
-    const size_t nctrl = (size_t)(P.ny * P.m + 1) * (P.nx * P.m + 1) * 2;
-    P.ctrl.assign(mesh->ctrl, mesh->ctrl + nctrl);
+    if (q->kind != SMM_QUAD_EXPLICIT) return fail(ctx, SMM_EINVAL, "unknown quadrature kind");
+    if (q->n_dir < 1 || q->n_dir > 4096 || !q->omega || !q->w)
+        return fail(ctx, SMM_EINVAL, "explicit quadrature: n_dir in 1..4096 and both arrays required");
+    double sw = 0;
+    for (int d = 0; d < q->n_dir; ++d) {
+        const double* o = &q->omega[d * 3];
+        const double nrm = std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+        if (!(std::fabs(nrm - 1.0) <= 1e-12) || !(o[2] >= 0.0) || !(q->w[d] > 0.0) || !std::isfinite(q->w[d]))
+            return fail(ctx, SMM_EINVAL, "explicit quadrature: direction " + std::to_string(d) +
+                                             " is not a unit vector with Omega_z >= 0 and a positive weight");
+        if (o[0] == 0.0 || o[1] == 0.0)
+            return fail(ctx, SMM_EUNSUPPORTED, "explicit quadrature: direction " + std::to_string(d) +
+                                                   " has a zero in-plane component");
+        sw += q->w[d];
+    }
+    const double fourpi = 16.0 * std::atan(1.0);
+    if (!(std::fabs(sw - fourpi) <= 1e-12 * fourpi))
+        return fail(ctx, SMM_EINVAL, "explicit quadrature: weights must sum to 4 pi");
+    P.sn = 0;
+    P.nd = q->n_dir;
+    P.omega.assign(q->omega, q->omega + 3 * (size_t)q->n_dir);
+    P.w.assign(q->w, q->w + q->n_dir);
+    P.quad_explicit = true;
+    return SMM_OK;
+}
+
+// Geometry set-up shared by the creation calls (P's sizes, mesh data and
+// quadrature filled in).
+static int create_common(smm_ctx* ctx, smm_problem* pr, smm_problem** out) {
+    Problem& P = pr->P;
     std::string err;
     int rc = setup_geometry(P, err, false);
     if (rc != SMM_OK) {
@@ -133,7 +151,84 @@ int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_or
     return SMM_OK;
 }
 
+static int create_structured(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, const smm_quad_desc* quad,
+                             smm_problem** out) {
+    if (!ctx || !mesh || !out || !mesh->ctrl) return fail(ctx, SMM_EINVAL, "null argument");
+    if (p < 1 || p > 4) return fail(ctx, SMM_EINVAL, "p must be in 1..4");
+    if (mesh->nx < 1 || mesh->ny < 1 || mesh->m < 1 || mesh->m > 6)
+        return fail(ctx, SMM_EINVAL, "bad mesh sizes");
+    smm_problem* pr = new (std::nothrow) smm_problem();
+    if (!pr) return SMM_ENOMEM;
+    Problem& P = pr->P;
+    P.ctx = ctx;
+    P.nx = mesh->nx;
+    P.ny = mesh->ny;
+    P.m = mesh->m;
+    P.p = p;
+    P.nb = p + 1;
+    P.n = P.nb * P.nb;
+    P.nq = p + mesh->m + 1;
+    P.ne = P.nx * P.ny;
+    int rc = quad_from_desc(ctx, quad, P);
+    if (rc) {
+        delete pr;
+        return rc;
+    }
+    const size_t nctrl = (size_t)(P.ny * P.m + 1) * (P.nx * P.m + 1) * 2;
+    P.ctrl.assign(mesh->ctrl, mesh->ctrl + nctrl);
+    return create_common(ctx, pr, out);
+}
+
+extern "C" {
+
+int smm_problem_create(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, int sn_order, smm_problem** out) {
+    smm_quad_desc q{SMM_QUAD_LEVEL_SYMMETRIC, sn_order, 0, nullptr, nullptr};
+    return create_structured(ctx, mesh, p, &q, out);
+}
+
+int smm_problem_create_q(smm_ctx* ctx, const smm_mesh_desc* mesh, int p, const smm_quad_desc* quad,
+                         smm_problem** out) {
+    return create_structured(ctx, mesh, p, quad, out);
+}
+
+int smm_problem_create_general(smm_ctx* ctx, const smm_mesh_general_desc* mesh, int p, const smm_quad_desc* quad,
+                               smm_problem** out) {
+    if (!ctx || !mesh || !out || !mesh->ctrl || !mesh->nbr) return fail(ctx, SMM_EINVAL, "null argument");
+    if (p < 1 || p > 4) return fail(ctx, SMM_EINVAL, "p must be in 1..4");
+    if (mesh->n_elem < 1 || mesh->m < 1 || mesh->m > 6) return fail(ctx, SMM_EINVAL, "bad mesh sizes");
+    smm_problem* pr = new (std::nothrow) smm_problem();
+    if (!pr) return SMM_ENOMEM;
+    Problem& P = pr->P;
+    P.ctx = ctx;
+    P.general = true;
+    P.ne = mesh->n_elem;
+    P.nx = mesh->n_elem;
+    P.ny = 1;
+    P.m = mesh->m;
+    P.p = p;
+    P.nb = p + 1;
+    P.n = P.nb * P.nb;
+    P.nq = p + mesh->m + 1;
+    int rc = quad_from_desc(ctx, quad, P);
+    if (rc) {
+        delete pr;
+        return rc;
+    }
+    const size_t mm = (size_t)(P.m + 1) * (P.m + 1);
+    P.ctrl_e.assign(mesh->ctrl, mesh->ctrl + (size_t)P.ne * mm * 2);
+    P.nbr_in.assign(mesh->nbr, mesh->nbr + (size_t)P.ne * 4);
+    for (int v : P.nbr_in)
+        if (v < -1 || v >= P.ne) {
+            delete pr;
+            return fail(ctx, SMM_EINVAL, "neighbour index out of range");
+        }
+    if (mesh->bdr_attr) P.bdr_attr_in.assign(mesh->bdr_attr, mesh->bdr_attr + (size_t)P.ne * 4);
+    return create_common(ctx, pr, out);
+}
+
 static void dev_free(Dev& D) {
+    for (auto& e : D.ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto& g : D.cg_graphs) (void)hipGraphExecDestroy(g.second);
     if (D.cg_cap) (void)hipStreamDestroy(D.cg_cap);
     for (void* ptr : D.allocs) (void)hipFree(ptr);
@@ -162,6 +257,8 @@ int smm_get_dims(const smm_problem* prob, smm_problem_dims* out) {
     out->n_levels = P.cartesian ? P.nx + P.ny - 1 : P.nlev_max;
     out->n_self_types = P.nself;
     out->n_nbr_types = P.nnbrt;
+    out->general = P.general ? 1 : 0;
+    out->n_bdr_attr = P.n_bdr_attr;
     return SMM_OK;
 }
 
@@ -244,6 +341,16 @@ int smm_set_inflow(smm_problem* prob, const double* psibar, int layout) {
     } else if (layout == SMM_INFLOW_FULL) {
         if (!psibar) return SMM_EINVAL;
         P.psibar.assign(psibar, psibar + full);
+    } else if (layout == SMM_INFLOW_ISO_ATTR) {
+        // one isotropic value per boundary attribute: stored as the face-wise
+        // isotropic layout it is
+        if (!psibar) return SMM_EINVAL;
+        P.psibar.assign(full, 0.0);
+        for (int bf = 0; bf < P.nbf; ++bf)
+            for (int q = 0; q < P.nq; ++q)
+                for (int d = 0; d < P.nd; ++d)
+                    P.psibar[((size_t)bf * P.nq + q) * P.nd + d] = psibar[P.bface_attr[bf]];
+        layout = SMM_INFLOW_ISO_FACE;
     } else {
         return fail(P.ctx, SMM_EINVAL, "bad inflow layout");
     }
@@ -263,6 +370,8 @@ int smm_set_sweep_tiles(smm_problem* prob, int tile_nx, int tile_ny) {
     Dev& D = prob->D;
     if (tile_nx < 0 || tile_ny < 0 || (tile_nx == 0) != (tile_ny == 0))
         return fail(P.ctx, SMM_EINVAL, "smm_set_sweep_tiles: tile sizes must both be positive, or both 0");
+    if (P.general && tile_nx > 0)
+        return fail(P.ctx, SMM_EUNSUPPORTED, "smm_set_sweep_tiles: tiles need a structured mesh");
     if (P.tile_x == tile_nx && P.tile_y == tile_ny) return SMM_OK;
     P.tile_x = tile_nx;
     P.tile_y = tile_ny;
@@ -304,6 +413,7 @@ void smm_default_opts(smm_solve_opts* o) {
     o->precond = SMM_PRECOND_BJ;
     o->anderson = 0;
     o->discretization = SMM_DISC_IP;
+    o->kappa_scale = 1.0;
 }
 
 }  // extern "C"
@@ -408,6 +518,22 @@ static int ensure_device(smm_problem* pr, bool gen_moment, bool gen_sweep) {
         std::vector<float> f;
         UP(D.Lf64, P.Lf); f = to_f32(P.Lf); UP(D.Lf32, f);
         UP(D.nbr, P.nbr);
+        if (P.general) {
+            std::vector<uint8_t> nf(P.nbr_face.size());
+            for (size_t k = 0; k < nf.size(); ++k) nf[k] = P.nbr_face[k] < 0 ? 0 : (uint8_t)P.nbr_face[k];
+            UP(D.nbr_face, nf);
+        }
+        if (!P.axis_bdr && P.nbf > 0) {
+            std::vector<double> nb2((size_t)P.nbf * P.nq * 2);
+            for (int bf = 0; bf < P.nbf; ++bf)
+                for (int q = 0; q < P.nq; ++q)
+                    for (int k = 0; k < 2; ++k)
+                        nb2[((size_t)bf * P.nq + q) * 2 + k] =
+                            P.nhat[(((size_t)P.bface_K[bf] * 4 + P.bface_f[bf]) * P.nq + q) * 2 + k];
+            UP(D.nhat_b, nb2);
+            UP(D.eb0_pt, P.eb0_pt);
+            UP(D.w64, P.w);
+        }
         UP(D.bface_of, P.bface_of);
         UP(D.bface_K, P.bface_K);
         UP(D.bface_f, P.bface_f);
@@ -535,6 +661,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
         a.Lf = fp64 ? D.Lf64 : D.Lf32;
         a.sigma_t = fp64 ? D.st64 : D.st32;
         a.nbr = D.nbr;
+        a.nbr_face = P.general ? D.nbr_face : nullptr;
         a.bface_of = D.bface_of;
         a.upflag = D.upflag;
         a.lev_ptr = D.lev_ptr;
@@ -565,6 +692,7 @@ static CgState cg_state(smm_problem* pr) {
 // Continuous (CG) moment system on the device: host assembly on first use or
 // after a material change, then upload.
 static int ensure_cg(smm_problem* pr) {
+    if (pr->P.general) return fail(pr->P.ctx, SMM_EUNSUPPORTED, "the CG moment system needs a structured mesh");
     Problem& P = pr->P;
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
@@ -623,6 +751,7 @@ static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its,
         HIPCHK(c, hipMemcpyAsync(sc, D.cg_scal, sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         done = (int)sc[5];
+        if (sc[6] == 2.0) return fail(c, SMM_ENAN, "non-finite values in the moment solve (continuous system)");
         if (sc[6] != 0.0) return fail(c, SMM_EBREAKDOWN, "CG breakdown (continuous moment system)");
         if (sc[4] != 0.0 || done >= max_inner) break;
         const int k = std::min(chunk, max_inner - done);
@@ -672,6 +801,7 @@ static int moment_solve(smm_problem* pr, double tol, int max_inner, int* its, bo
         HIPCHK(c, hipMemcpyAsync(sc, D.scal, sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         done_its = (int)sc[5];
+        if (sc[6] == 2.0) return fail(c, SMM_ENAN, "non-finite values in the moment solve");
         if (sc[6] != 0.0) return fail(c, SMM_EBREAKDOWN, "CG breakdown");
         if (sc[4] != 0.0) break;
         if (done_its >= max_inner) break;
@@ -687,7 +817,7 @@ static int moment_solve(smm_problem* pr, double tol, int max_inner, int* its, bo
 // One evaluation of G from D.varphi into D.x (b, closures, moments updated).
 // psi_cur / psi_prev are sweep buffers; delta mode sweeps sigma_s/(4pi)(varphi - varphi_prev).
 static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, double inner_tol, int max_inner,
-                  int* cg_its, bool cgdisc = false, bool graph = false, bool* conv = nullptr) {
+                  int* cg_its, bool cgdisc = false, bool graph = false, bool* conv = nullptr, bool timed = false) {
     Problem& P = pr->P;
     Dev& D = pr->D;
     smm_ctx* c = P.ctx;
@@ -695,6 +825,7 @@ static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, d
     const bool aniso = P.src_layout == SMM_SRC_ANISO;
     const int nd_q = aniso ? P.nd : 1;
     int rc;
+    if (timed) HIPCHK(c, hipEventRecord(D.ev[0], c->stream));
     // scattering source (a1)
     if (!delta || first) {
         HIPCHK(c, launch_source(fp64, P.ne, P.n, nd_q, D.sigma_s, D.varphi, nullptr, D.q, D.S, c->stream));
@@ -706,6 +837,7 @@ static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, d
     void* out = D.psi[cur];
     const void* lag = first ? nullptr : D.psi[cur ^ 1];
     if ((rc = run_sweep(pr, fp64, D.S, s_aniso ? 1 : 0, lag, out, !delta || first))) return rc;
+    if (timed) HIPCHK(c, hipEventRecord(D.ev[1], c->stream));
     // moments (a3)
     HIPCHK(c, launch_moments(fp64, out, P.nd, L, fp64 ? D.W64 : D.W32, D.ldw, D.mom, c->stream));
     const double* mom = D.mom;
@@ -716,14 +848,21 @@ static int eval_G(smm_problem* pr, bool fp64, bool delta, bool first, int cur, d
     }
     D.last_mom = mom;
     // closures (a4) and right-hand side (a5)
-    HIPCHK(c, launch_closures(P.ne, P.n, P.nb, P.nq, P.nbf, mom, D.bface_K, D.bface_f, (const double*)D.Lf64,
-                              P.eb0x, P.eb0y, D.T, D.beta, c->stream));
+    HIPCHK(c, launch_closures(P.ne, P.n, P.nb, P.nq, P.axis_bdr ? P.nbf : 0, mom, D.bface_K, D.bface_f,
+                              (const double*)D.Lf64, P.eb0x, P.eb0y, D.T, D.beta, c->stream));
+    if (!P.axis_bdr)   // beta from psi itself, accumulated over delta sweeps like the moments
+        HIPCHK(c, launch_beta_general(fp64, P.nd, P.ne, P.n, P.nb, P.nq, P.nbf, out, D.omega, D.w64, D.bface_K,
+                                      D.bface_f, D.nhat_b, D.eb0_pt, (const double*)D.Lf64, delta && !first,
+                                      D.beta, c->stream));
     HIPCHK(c, launch_rhs(P.ne, P.n, P.nq, D.bfix, D.bsr_col, D.corr, D.T, D.bface_of, D.beta_op, D.beta, D.b,
                          c->stream));
     // moment solve (a6), warm-started from the current iterate
     HIPCHK(c, hipMemcpyAsync(D.x, D.varphi, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
-    return cgdisc ? cg_moment_solve(pr, inner_tol, max_inner, cg_its, graph, conv)
-                  : moment_solve(pr, inner_tol, max_inner, cg_its, conv);
+    if (timed) HIPCHK(c, hipEventRecord(D.ev[2], c->stream));
+    rc = cgdisc ? cg_moment_solve(pr, inner_tol, max_inner, cg_its, graph, conv)
+                : moment_solve(pr, inner_tol, max_inner, cg_its, conv);
+    if (!rc && timed) HIPCHK(c, hipEventRecord(D.ev[3], c->stream));
+    return rc;
 }
 
 extern "C" {
@@ -741,17 +880,36 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     if (o.discretization != SMM_DISC_IP && o.discretization != SMM_DISC_CG)
         return fail(c, SMM_EINVAL, "smm_solve: discretization must be SMM_DISC_IP or SMM_DISC_CG");
     const bool cgdisc = o.discretization == SMM_DISC_CG;
+    if (cgdisc && P.general)
+        return fail(c, SMM_EUNSUPPORTED, "smm_solve: the CG moment system needs a structured mesh");
     if (cgdisc && o.anderson != 0)
         return fail(c, SMM_EUNSUPPORTED, "smm_solve: Anderson mixing runs on the typed path, IP discretisation only");
     if (o.anderson != 0 && !(o.moment_path == 0 && typed_applicable(P) && !per_element_forced(D) && P.tile_x == 0))
         return fail(c, SMM_EUNSUPPORTED, "smm_solve: Anderson mixing needs the typed (batched) path");
-    if (o.start < SMM_START_ZERO || o.start > SMM_START_GIVEN)
-        return fail(c, SMM_EINVAL, "smm_solve: start must be ZERO, DIFFUSION or GIVEN (the learned start needs a batch)");
-    if (!cgdisc && o.moment_path == 0 && typed_applicable(P) && !per_element_forced(D) && P.tile_x == 0) {
+    if (o.start < SMM_START_ZERO || o.start > SMM_START_LEARNED)
+        return fail(c, SMM_EINVAL, "smm_solve: unknown start mode");
+    if (!(o.kappa_scale >= 0.0) || !std::isfinite(o.kappa_scale))
+        return fail(c, SMM_EINVAL, "smm_solve: kappa_scale must be finite and >= 0");
+    if (o.kappa_scale != P.kappa_scale) {
+        // a new penalty: the moment system is assembled again
+        P.kappa_scale = o.kappa_scale;
+        P.lhs_ready = false;
+        P.typed_ready = false;
+        batch_release_single(prob);
+        D.gen_dirty = true;
+    }
+    const bool typed = !cgdisc && o.moment_path == 0 && typed_applicable(P) && !per_element_forced(D) && P.tile_x == 0;
+    if (o.start == SMM_START_LEARNED && !typed)
+        return fail(c, SMM_EUNSUPPORTED, "smm_solve: the learned start needs the typed path (uniform Cartesian mesh, "
+                                         "isotropic source, IP moment system)");
+    if (typed) {
         const int r = batch_solve_single(prob, o, varphi0, info);
         D.last_typed = (r == SMM_OK || r == SMM_ENOCONV);
+        batch_history_single(prob, D.hist_r, D.hist_cg);
         return r;
     }
+    D.hist_r.clear();
+    D.hist_cg.clear();
     D.last_typed = false;
     auto t0 = std::chrono::steady_clock::now();
     int rc = ensure_device(prob, true, per_element_forced(D));
@@ -776,6 +934,9 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
         HIPCHK(c, hipMemsetAsync(D.varphi, 0, sizeof(double) * L, c->stream));
     }
     HIPCHK(c, hipMemsetAsync(D.varphi_prev, 0, sizeof(double) * L, c->stream));
+    for (auto& e : D.ev)
+        if (!e) HIPCHK(c, hipEventCreate(&e));
+    D.phase_ms[0] = D.phase_ms[1] = D.phase_ms[2] = D.phase_ms[3] = 0.0;
     int cg_total = 0, cg_max = 0;
     double r = 0, rabs = 0;
     int it = 0;
@@ -786,7 +947,7 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
         const double tol_k = o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt * r_prev) : o.inner_tol;
         bool inner_ok = true;
         if ((rc = eval_G(prob, fp64, delta, it == 1, it & 1, tol_k, o.max_inner, &cgi, cgdisc, o.use_graph != 0,
-                         &inner_ok)))
+                         &inner_ok, true)))
             return rc;
         cg_total += cgi;
         cg_max = std::max(cg_max, cgi);
@@ -797,9 +958,17 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
         // shift iterates: varphi_prev <- varphi, varphi <- x
         std::swap(D.varphi_prev, D.varphi);
         std::swap(D.varphi, D.x);
+        HIPCHK(c, hipEventRecord(D.ev[4], c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int ph = 0; ph < 4; ++ph) {
+            float ms = 0;
+            HIPCHK(c, hipEventElapsedTime(&ms, D.ev[ph], D.ev[ph + 1]));
+            D.phase_ms[ph] += ms;
+        }
         rabs = ro[0];
         r = ro[1] > 0 ? ro[0] / ro[1] : (ro[0] == 0 ? 0.0 : INFINITY);
+        D.hist_r.push_back(r);
+        D.hist_cg.push_back(cgi);
         if (!std::isfinite(r) || !std::isfinite(rabs)) { status = SMM_ENAN; break; }
         // with adaptive inner tolerances, convergence counts only from a
         // moment solve as tight as the target residual asks for (a looser
@@ -820,9 +989,23 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
         info->cg_iterations_max = cg_max;
         info->t_total_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
         info->t_setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        info->t_sweep_ms = D.phase_ms[0];
+        info->t_moments_ms = D.phase_ms[1];
+        info->t_cg_ms = D.phase_ms[2];
+        info->t_residual_ms = D.phase_ms[3];
     }
     if (status == SMM_ENAN) return fail(c, SMM_ENAN, "non-finite residual");
     if (status == SMM_ENOCONV) return fail(c, SMM_ENOCONV, "max_outer reached");
+    return SMM_OK;
+}
+
+int smm_solve_history(const smm_problem* prob, int max_len, double* residual, int* cg_iterations, int* len) {
+    if (!prob || !len || max_len < 0) return SMM_EINVAL;
+    const Dev& D = prob->D;
+    *len = (int)D.hist_r.size();
+    const int k = std::min(max_len, *len);
+    if (residual) std::copy(D.hist_r.begin(), D.hist_r.begin() + k, residual);
+    if (cg_iterations) std::copy(D.hist_cg.begin(), D.hist_cg.begin() + k, cg_iterations);
     return SMM_OK;
 }
 
@@ -957,6 +1140,7 @@ int smm_apply_G_noalloc(smm_problem* prob, int precision, const double* varphi_i
 
 int smm_debug_cg_system(smm_problem* prob, int* nc, int* nnz, int* rowptr, int* col, double* val, int* map) {
     if (!prob || !nc || !nnz) return SMM_EINVAL;
+    if (prob->P.general) return fail(prob->P.ctx, SMM_EUNSUPPORTED, "the CG moment system needs a structured mesh");
     int rc = ensure_host(prob);
     if (rc) return rc;
     Problem& P = prob->P;

@@ -38,6 +38,8 @@ struct Dev {
     void *Mk64 = nullptr, *Gx64 = nullptr, *Gy64 = nullptr, *nds64 = nullptr, *Lf64 = nullptr, *st64 = nullptr;
     int *nbr = nullptr, *bface_of = nullptr, *lev_ptr = nullptr, *lev_elem = nullptr;
     uint8_t* upflag = nullptr;
+    uint8_t* nbr_face = nullptr;          // [ne][4] (meshes given element by element)
+    double *w64 = nullptr, *nhat_b = nullptr, *eb0_pt = nullptr;  // boundaries not along x or y
     void *pbar32 = nullptr, *pbar64 = nullptr;
     // materials, source
     double* sigma_s = nullptr;
@@ -65,6 +67,10 @@ struct Dev {
     bool gen_sweep_built = false;  // per-element sweep data uploaded
     bool gen_dirty = true;         // per-element moment system needs (re)upload
     int force_general = 0;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // phase timing of smm_solve
+    double phase_ms[4] = {0, 0, 0, 0};  // source + sweep, moments + closures + rhs, CG, residual
+    std::vector<double> hist_r;         // outer residual of each outer iteration of the last smm_solve
+    std::vector<int> hist_cg;           // and its CG iterations
     const double* last_mom = nullptr;   // moments of the last G evaluation
     const double* last_varphi = nullptr;
 };
@@ -72,11 +78,13 @@ struct Dev {
 }  // namespace smm
 
 struct smm_batch;
+struct smm_cnn;
 
 struct smm_problem {
     smm::Problem P;
     smm::Dev D;
     smm_batch* own_batch = nullptr;   // batch of one used by smm_solve on the typed path
+    smm_cnn* ws_net = nullptr;        // warm-start network for SMM_START_LEARNED (smm_set_warmstart)
 };
 
 
@@ -86,6 +94,7 @@ int batch_solve_single(smm_problem* pr, const smm_solve_opts& o, const double* v
 int batch_outputs_single(smm_problem* pr, double* varphi, double* phi, double* J, double* T, double* beta,
                          int on_device);
 void batch_release_single(smm_problem* pr);
+void batch_history_single(smm_problem* pr, std::vector<double>& r, std::vector<int>& cg);
 }  // namespace smm
 
 #define HIPCHK(ctx, call)                                                                        \

@@ -61,6 +61,10 @@ struct Group {
     bool multi = false;                    // some problem has several materials
     size_t lds[2] = {0, 0};
     int grid[2] = {0, 0};
+    // kernel shape per precision: 0 column-wave (b_sweep_kernel), 1 element-lane
+    // (b_sweep_elem_kernel, one wave of ethreads / 64 per chunk); -1 not tuned
+    int shape[2] = {-1, -1};
+    int ethreads = 0;
     std::vector<int2> tasks;
     int2* d_tasks = nullptr;
     int* d_counter = nullptr;
@@ -90,8 +94,9 @@ struct Pool {
     }
 };
 
-std::map<std::tuple<int, int, int, size_t, size_t, int>, int>& tune_cache() {
-    static std::map<std::tuple<int, int, int, size_t, size_t, int>, int> m;
+// tuned (grid, kernel shape) per launch shape
+std::map<std::tuple<int, int, int, size_t, size_t, int>, std::pair<int, int>>& tune_cache() {
+    static std::map<std::tuple<int, int, int, size_t, size_t, int>, std::pair<int, int>> m;
     return m;
 }
 
@@ -478,6 +483,7 @@ int batch_build(smm_batch* B) {
             B->groups.back().threads = th;
         }
         Group& G = B->groups[gi[key]];
+        G.ethreads = th / P.nb;          // one wave per chunk
         if (P.nmat != 1) G.multi = true;
         for (int d = 0; d < P.nd; ++d) G.tasks.push_back(make_int2(b, d));
     }
@@ -797,6 +803,16 @@ int batch_build(smm_batch* B) {
     return SMM_OK;
 }
 
+// One persistent launch of group G in kernel shape `shape`.
+hipError_t group_sweep(smm_batch* B, Group& G, bool fp64, int shape, int grid, const CartSweepArgs* args,
+                       hipStream_t s) {
+    if (shape == 1)
+        return b_sweep_elem(fp64, G.nb, G.multi, G.ethreads, grid, args, G.d_tasks, (int)G.tasks.size(), G.d_counter,
+                            B->d_active, s);
+    return b_sweep(fp64, G.nb, G.multi, G.threads, G.lds[fp64 ? 1 : 0], grid, args, G.d_tasks, (int)G.tasks.size(),
+                   G.d_counter, B->d_active, s);
+}
+
 // Run the sweep of all active problems: one persistent launch per order, on
 // forked streams when there is more than one order.
 int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
@@ -816,8 +832,7 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
         Group& G = B->groups[k];
         hipStream_t s = fork ? B->side[k % nstr] : c->stream;
         int grid = G.grid[f] > 0 ? G.grid[f] : std::min<int>((int)G.tasks.size(), 2 * B->ncu);
-        hipError_t e = b_sweep(fp64, G.nb, G.multi, G.threads, G.lds[f], grid, B->d_args[f][inflow ? 1 : 0],
-                               G.d_tasks, (int)G.tasks.size(), G.d_counter, B->d_active, s);
+        hipError_t e = group_sweep(B, G, fp64, G.shape[f] == 1 ? 1 : 0, grid, B->d_args[f][inflow ? 1 : 0], s);
         if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("batched sweep: ") + hipGetErrorString(e));
     }
     if (fork)
@@ -828,9 +843,12 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
     return SMM_OK;
 }
 
-// Autotuner: time each candidate grid (workgroups per CU) of every persistent
-// sweep launch on this batch and keep the fastest; results are cached per
-// launch shape.  The grid only changes scheduling, never the results.
+// Autotuner: for every persistent sweep launch, time each candidate kernel
+// shape (column-wave: NB waves per 64-slot chunk, the node columns of an
+// element spread over waves; element-lane: one wave per chunk, each lane a
+// whole element) and each grid (workgroups per CU), and keep the fastest;
+// results are cached per launch shape.  Shape and grid only change
+// scheduling and the order of the FMAs within an element, within rounding.
 int batch_autotune(smm_batch* B, bool fp64) {
     smm_ctx* c = B->ctx;
     const int f = fp64 ? 1 : 0;
@@ -838,46 +856,55 @@ int batch_autotune(smm_batch* B, bool fp64) {
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     for (Group& G : B->groups) {
-        if (G.grid[f] > 0) continue;
+        if (G.grid[f] > 0 && G.shape[f] >= 0) continue;
         auto key = std::make_tuple(G.nb, (int)G.multi, G.threads, G.lds[f], G.tasks.size(), f);
         auto it = tune_cache().find(key);
-        if (it != tune_cache().end()) {
-            G.grid[f] = it->second;
+        if (it != tune_cache().end() && G.shape[f] < 0) {
+            G.grid[f] = it->second.first;
+            G.shape[f] = it->second.second;
             continue;
         }
-        int best = 0;
+        int best = 0, best_shape = 0;
         float best_ms = 1e30f;
-        for (int wpc : {1, 2, 3, 4, 6}) {
-            const int grid = std::min<int>((int)G.tasks.size(), wpc * B->ncu);
-            float ms_tot = 0;
-            bool ok = true;
-            for (int rep = 0; rep < 3 && ok; ++rep) {
-                HIPCHK(c, zero_ints(G.d_counter, 1, c->stream));
-                HIPCHK(c, hipEventRecord(e0, c->stream));
-                hipError_t e = b_sweep(fp64, G.nb, G.multi, G.threads, G.lds[f], grid, B->d_args[f][1], G.d_tasks,
-                                       (int)G.tasks.size(), G.d_counter, B->d_active, c->stream);
-                if (e != hipSuccess) {
-                    ok = false;
-                    (void)hipGetLastError();
-                    break;
+        const int forced = G.shape[f];   // a shape forced by the testing hook: tune its grid only
+        for (int shape = 0; shape < 2; ++shape) {
+            if (forced >= 0 && shape != forced) continue;
+            if (shape == 1 && (G.ethreads < 64 || G.ethreads > 256)) continue;
+            const std::vector<int> wpcs = shape == 0 ? std::vector<int>{1, 2, 3, 4, 6}
+                                                     : std::vector<int>{2, 4, 8, 12, 16};
+            for (int wpc : wpcs) {
+                const int grid = std::min<int>((int)G.tasks.size(), wpc * B->ncu);
+                float ms_tot = 0;
+                bool ok = true;
+                for (int rep = 0; rep < 3 && ok; ++rep) {
+                    HIPCHK(c, zero_ints(G.d_counter, 1, c->stream));
+                    HIPCHK(c, hipEventRecord(e0, c->stream));
+                    hipError_t e = group_sweep(B, G, fp64, shape, grid, B->d_args[f][1], c->stream);
+                    if (e != hipSuccess) {
+                        ok = false;
+                        (void)hipGetLastError();
+                        break;
+                    }
+                    HIPCHK(c, hipEventRecord(e1, c->stream));
+                    HIPCHK(c, hipEventSynchronize(e1));
+                    float ms = 0;
+                    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+                    if (rep > 0) ms_tot += ms;
                 }
-                HIPCHK(c, hipEventRecord(e1, c->stream));
-                HIPCHK(c, hipEventSynchronize(e1));
-                float ms = 0;
-                HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-                if (rep > 0) ms_tot += ms;
+                if (ok && ms_tot < best_ms) {
+                    best_ms = ms_tot;
+                    best = grid;
+                    best_shape = shape;
+                }
+                if (grid >= (int)G.tasks.size()) break;
             }
-            if (ok && ms_tot < best_ms) {
-                best_ms = ms_tot;
-                best = grid;
-            }
-            if (grid >= (int)G.tasks.size()) break;
         }
         if (best == 0)
             return fail(c, SMM_EUNSUPPORTED, "no launch configuration fits the sweep of order " +
                                                  std::to_string(G.nb - 1) + " (workgroup or LDS limits)");
         G.grid[f] = best;
-        tune_cache()[key] = best;
+        G.shape[f] = best_shape;
+        if (forced < 0) tune_cache()[key] = std::make_pair(best, best_shape);
     }
     // the groups one after the other, or concurrently on side streams
     if (B->sweep_streams[f] == 0) {
@@ -930,6 +957,8 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
         int mask = 0;  // orders with problems still iterating
         for (int b = 0; b < B->nprob; ++b) {
             if (!B->active[b]) continue;
+            if (sc[16 * b + 6] == 2.0)
+                return fail(c, SMM_ENAN, "non-finite values in the moment solve of problem " + std::to_string(b));
             if (sc[16 * b + 6] != 0.0) return fail(c, SMM_EBREAKDOWN, "CG breakdown in problem " + std::to_string(b));
             if (sc[16 * b + 4] == 0.0) {
                 all = false;
@@ -1086,6 +1115,10 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     int rc;
     if (o.start < SMM_START_ZERO || o.start > SMM_START_LEARNED)
         return fail(c, SMM_EINVAL, "smm_batch_solve: unknown start mode");
+    for (const smm_problem* pr : B->probs)
+        if (o.kappa_scale != pr->P.kappa_scale)
+            return fail(c, SMM_EUNSUPPORTED, "smm_batch_solve: a batch keeps the penalty scale its problems had when "
+                                             "it was created");
     if ((rc = batch_autotune(B, fp64))) return rc;
     B->active.assign(np, 1);
     B->ws_used.assign(np, 0);
@@ -1280,6 +1313,10 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     for (int b = 0; b < np; ++b) {
         inf[b].t_total_ms = tsolve + tsetup;
         inf[b].t_setup_ms = tsetup;
+        inf[b].t_sweep_ms = B->phase_ms[0];
+        inf[b].t_moments_ms = B->phase_ms[1];
+        inf[b].t_cg_ms = B->phase_ms[2];
+        inf[b].t_residual_ms = B->phase_ms[3];
         if (!std::isfinite(inf[b].residual)) status = SMM_ENAN;
         else if (status == SMM_OK && !converged[b]) status = SMM_ENOCONV;
     }
@@ -1335,7 +1372,17 @@ int batch_solve_single(smm_problem* pr, const smm_solve_opts& o, const double* v
         dv0 = const_cast<double*>(varphi0);  // host pointer, copied with hipMemcpyDefault
     }
     const double* v0[1] = {dv0};
+    pr->own_batch->ws_net = pr->ws_net;
     return batch_solve(pr->own_batch, o, v0, info);
+}
+
+void batch_history_single(smm_problem* pr, std::vector<double>& r, std::vector<int>& cg) {
+    r.clear();
+    cg.clear();
+    if (pr->own_batch && !pr->own_batch->hist.empty()) {
+        r = pr->own_batch->hist[0];
+        cg = pr->own_batch->cg_hist[0];
+    }
 }
 
 int batch_outputs_single(smm_problem* pr, double* varphi, double* phi, double* J, double* T, double* beta,
@@ -1483,6 +1530,13 @@ int smm_batch_set_warmstart(smm_batch* batch, smm_cnn* net) {
     return SMM_OK;
 }
 
+int smm_set_warmstart(smm_problem* prob, smm_cnn* net) {
+    if (!prob) return SMM_EINVAL;
+    if (net && net->ctx != prob->P.ctx) return fail(prob->P.ctx, SMM_EINVAL, "network and problem on different contexts");
+    prob->ws_net = net;
+    return SMM_OK;
+}
+
 int smm_batch_warmstart_used(const smm_batch* batch, int* used) {
     if (!batch || !used) return SMM_EINVAL;
     if (batch->ws_used.size() != (size_t)batch->nprob) return SMM_ESTATE;
@@ -1623,6 +1677,20 @@ int smm_debug_batch_spmv(smm_batch* batch, const double* const* x, double* const
     for (int b = 0; b < batch->nprob; ++b)
         HIPCHK(c, hipMemcpy(y[b], batch->pp[b].q, sizeof(double) * batch->hP[b].L, hipMemcpyDeviceToHost));
     batch->have_outputs = false;
+    return SMM_OK;
+}
+
+int smm_debug_batch_sweep_shape(smm_batch* batch, int shape) {
+    if (!batch || shape < -1 || shape > 1) return SMM_EINVAL;
+    for (Group& G : batch->groups) {
+        if (shape == 1 && (G.ethreads < 64 || G.ethreads > 256))
+            return fail(batch->ctx, SMM_EUNSUPPORTED, "element-lane sweep: anti-diagonal longer than 256 slots");
+        for (int f = 0; f < 2; ++f) {
+            G.shape[f] = shape;
+            G.grid[f] = 0;
+        }
+    }
+    for (int f = 0; f < 2; ++f) batch->sweep_streams[f] = 0;
     return SMM_OK;
 }
 

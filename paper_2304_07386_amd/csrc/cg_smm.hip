@@ -164,7 +164,7 @@ __global__ __launch_bounds__(CGS_T) void cgs_k2(CgsArgs a) {
     const double pq = cgs_sum_parts(a.part, a.sblocks, red);
     if (!(pq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.scal[6] = 1.0;
+            a.scal[6] = pq <= 0.0 ? 1.0 : 2.0;  // 2: not a number (a non-finite right-hand side)
             a.scal[4] = 1.0;
         }
         return;

@@ -264,15 +264,21 @@ int setup_geometry(Problem& P, std::string& err, bool heavy) {
     bool cart = true;
     double hx0 = 0, hy0 = 0;
 
+    if (P.general) cart = false;  // the Cartesian kernels index a structured grid
     for (int j = 0; j < P.ny; ++j)
         for (int i = 0; i < P.nx; ++i) {
             const int K = j * P.nx + i;
-            for (int b = 0; b <= m; ++b)
-                for (int a = 0; a <= m; ++a) {
-                    const double* c = &P.ctrl[((size_t)(j * m + b) * ncx + (i * m + a)) * 2];
-                    X[(a + (m + 1) * b) * 2 + 0] = c[0];
-                    X[(a + (m + 1) * b) * 2 + 1] = c[1];
-                }
+            if (P.general) {
+                std::copy(&P.ctrl_e[(size_t)K * (m + 1) * (m + 1) * 2],
+                          &P.ctrl_e[(size_t)(K + 1) * (m + 1) * (m + 1) * 2], X.begin());
+            } else {
+                for (int b = 0; b <= m; ++b)
+                    for (int a = 0; a <= m; ++a) {
+                        const double* c = &P.ctrl[((size_t)(j * m + b) * ncx + (i * m + a)) * 2];
+                        X[(a + (m + 1) * b) * 2 + 0] = c[0];
+                        X[(a + (m + 1) * b) * 2 + 1] = c[1];
+                    }
+            }
             // generic evaluator: geometry at (xi, eta) from 1D tables
             auto eval = [&](const double* la, const double* dla, const double* lb, const double* dlb,
                             int sa, int sb, double out[6]) {
@@ -421,31 +427,110 @@ int setup_geometry(Problem& P, std::string& err, bool heavy) {
                 else if (std::fabs(hx - hx0) > 1e-12 * hx0 || std::fabs(hy - hy0) > 1e-12 * hy0)
                     cart = false;
             }
-            if (j > 0) P.nbr[K * 4 + 0] = K - P.nx;
-            if (i < P.nx - 1) P.nbr[K * 4 + 1] = K + 1;
-            if (j < P.ny - 1) P.nbr[K * 4 + 2] = K + P.nx;
-            if (i > 0) P.nbr[K * 4 + 3] = K - 1;
+            if (P.general) {
+                for (int f = 0; f < 4; ++f) P.nbr[K * 4 + f] = P.nbr_in[(size_t)K * 4 + f];
+            } else {
+                if (j > 0) P.nbr[K * 4 + 0] = K - P.nx;
+                if (i < P.nx - 1) P.nbr[K * 4 + 1] = K + 1;
+                if (j < P.ny - 1) P.nbr[K * 4 + 2] = K + P.nx;
+                if (i > 0) P.nbr[K * 4 + 3] = K - 1;
+            }
         }
-    // boundary faces, ordered by element then local face; require axis-aligned normals
+    // interior faces: the neighbour's face across f and whether the two
+    // parameterisations run the same way, from the face control points (a
+    // structured grid: always the opposite face, the same way)
+    P.nbr_face.assign((size_t)ne * 4, -1);
+    {
+        double amax = 0;
+        for (int K = 0; K < ne; ++K) amax = std::max(amax, P.area[K]);
+        const double tol = 1e-10 * std::sqrt(amax);
+        const int mm = m + 1;
+        auto fctrl = [&](int K, int f, int t) -> const double* {   // control point t along face f
+            int a, b;
+            switch (f) {
+                case 0: a = t; b = 0; break;
+                case 1: a = m; b = t; break;
+                case 2: a = t; b = m; break;
+                default: a = 0; b = t; break;
+            }
+            const double* base = P.general ? &P.ctrl_e[(size_t)K * mm * mm * 2] : nullptr;
+            if (base) return base + (a + mm * b) * 2;
+            const int i = K % P.nx, j = K / P.nx;
+            return &P.ctrl[((size_t)(j * m + b) * ncx + (i * m + a)) * 2];
+        };
+        for (int K = 0; K < ne; ++K)
+            for (int f = 0; f < 4; ++f) {
+                const int N = P.nbr[K * 4 + f];
+                if (N < 0) continue;
+                if (N >= ne || N == K) {
+                    err = "element " + std::to_string(K) + " face " + std::to_string(f) + ": bad neighbour";
+                    return SMM_EINVAL;
+                }
+                int code = -1;
+                for (int g = 0; g < 4 && code < 0; ++g) {
+                    if (P.nbr[N * 4 + g] != K) continue;
+                    bool same = true, rev = true;
+                    for (int t = 0; t <= m; ++t) {
+                        const double* a = fctrl(K, f, t);
+                        const double* b = fctrl(N, g, t);
+                        const double* br = fctrl(N, g, m - t);
+                        same = same && std::fabs(a[0] - b[0]) <= tol && std::fabs(a[1] - b[1]) <= tol;
+                        rev = rev && std::fabs(a[0] - br[0]) <= tol && std::fabs(a[1] - br[1]) <= tol;
+                    }
+                    if (same) code = g;
+                    else if (rev) code = g | 4;
+                }
+                if (code < 0) {
+                    err = "element " + std::to_string(K) + " face " + std::to_string(f) +
+                          " does not match a face of its neighbour " + std::to_string(N);
+                    return SMM_EINVAL;
+                }
+                P.nbr_face[K * 4 + f] = code;
+            }
+    }
+    // boundary faces, ordered by element then local face, with their
+    // attributes; E_b0 at every boundary point (eq. eb0_disc: it depends on
+    // the normal), and whether all boundary normals are axis-aligned
     P.bface_of.assign((size_t)ne * 4, -1);
     P.bface_K.clear();
     P.bface_f.clear();
+    P.bface_attr.clear();
+    P.axis_bdr = true;
+    P.n_bdr_attr = 0;
     for (int K = 0; K < ne; ++K)
         for (int f = 0; f < 4; ++f)
             if (P.nbr[K * 4 + f] < 0) {
                 P.bface_of[K * 4 + f] = (int)P.bface_K.size();
                 P.bface_K.push_back(K);
                 P.bface_f.push_back(f);
+                const int attr = P.general && !P.bdr_attr_in.empty() ? P.bdr_attr_in[(size_t)K * 4 + f] : f;
+                if (attr < 0) {
+                    err = "element " + std::to_string(K) + " face " + std::to_string(f) + ": negative boundary attribute";
+                    return SMM_EINVAL;
+                }
+                P.bface_attr.push_back(attr);
+                P.n_bdr_attr = std::max(P.n_bdr_attr, attr + 1);
                 for (int q = 0; q < nq; ++q) {
                     const double* nh = &P.nhat[(((size_t)K * 4 + f) * nq + q) * 2];
                     const double off = (f == 0 || f == 2) ? nh[0] : nh[1];
-                    if (std::fabs(off) > 1e-10) {
-                        err = "boundary face normal is not axis-aligned";
-                        return SMM_EUNSUPPORTED;
-                    }
+                    if (std::fabs(off) > 1e-10) P.axis_bdr = false;
                 }
             }
     P.nbf = (int)P.bface_K.size();
+    P.eb0_pt.assign((size_t)P.nbf * nq, 0.0);
+    {
+        double sw = 0;
+        for (int d = 0; d < P.nd; ++d) sw += P.w[d];
+        for (int bf = 0; bf < P.nbf; ++bf)
+            for (int q = 0; q < nq; ++q) {
+                const double* nh = &P.nhat[(((size_t)P.bface_K[bf] * 4 + P.bface_f[bf]) * nq + q) * 2];
+                double se = 0;
+                for (int d = 0; d < P.nd; ++d)
+                    se += P.w[d] * std::fabs(P.omega[d * 3] * nh[0] + P.omega[d * 3 + 1] * nh[1]);
+                P.eb0_pt[(size_t)bf * nq + q] = se / sw;
+            }
+    }
+    if (!P.axis_bdr) cart = false;
     P.cartesian = cart;
     P.hx = hx0;
     P.hy = hy0;
@@ -685,7 +770,6 @@ int setup_sweep_graph(Problem& P, std::string& err) {
 //   interior (self):  kappa u_i u_j - D_K/2 u_i dn u_j - D_K/2 dn u_i u_j
 //   interior (nbr):  -kappa u_i v_j - D_N/2 u_i dn v_j + D_K/2 dn u_i v_j
 // ---------------------------------------------------------------------------
-static inline int opp(int f) { return (f + 2) & 3; }
 
 static void face_values(const Problem& P, int f, int q, std::vector<double>& u) {
     // basis values at face point q of face f (only face nodes are non-zero)
@@ -723,9 +807,11 @@ void add_volume_block(const Problem& P, int K, double* blk) {
 void add_boundary_block(const Problem& P, int K, int f, double* blk) {
     const int n = P.n, nq = P.nq;
     std::vector<double> uK;
-    const double e = (f == 1 || f == 3) ? P.eb0x : P.eb0y;
+    const double e_axis = (f == 1 || f == 3) ? P.eb0x : P.eb0y;
+    const int bf = P.bface_of[K * 4 + f];
     for (int q = 0; q < nq; ++q) {
         face_values(P, f, q, uK);
+        const double e = P.axis_bdr ? e_axis : P.eb0_pt[(size_t)bf * nq + q];
         const double s = P.dsw[((size_t)K * 4 + f) * nq + q] * e;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) blk[i * n + j] += s * uK[i] * uK[j];
@@ -752,14 +838,15 @@ void assemble_ip(Problem& P) {
             P.bsr_col[K * 5 + 1 + f] = N;
             double* blkN = &P.bsr_val[((size_t)K * 5 + 1 + f) * n * n];
             const double DN = 1.0 / (3.0 * P.sigma_t[N]);
-            const double kap = 0.5 * (pp / (P.sigma_t[K] * std::sqrt(P.area[K])) +
-                                      pp / (P.sigma_t[N] * std::sqrt(P.area[N])));
-            const int fN = opp(f);
+            const double kap = P.kappa_scale * 0.5 * (pp / (P.sigma_t[K] * std::sqrt(P.area[K])) +
+                                                      pp / (P.sigma_t[N] * std::sqrt(P.area[N])));
             for (int q = 0; q < nq; ++q) {
+                int fN, qN;
+                nbr_point(P, K, f, q, fN, qN);
                 face_values(P, f, q, uK);
-                face_values(P, fN, q, uN);
+                face_values(P, fN, qN, uN);
                 const size_t fo = ((size_t)K * 4 + f) * nq + q;
-                const size_t foN = ((size_t)N * 4 + fN) * nq + q;
+                const size_t foN = ((size_t)N * 4 + fN) * nq + qN;
                 const double nxh = P.nhat[fo * 2], nyh = P.nhat[fo * 2 + 1], s = P.dsw[fo];
                 std::vector<double> dnK(n), dnN(n);
                 for (int i = 0; i < n; ++i) {
@@ -826,7 +913,9 @@ void assemble_rhs_fixed(Problem& P) {
                 const double nxh = P.nhat[fo * 2], nyh = P.nhat[fo * 2 + 1], s = P.dsw[fo];
                 face_values(P, f, q, uK);
                 if (N >= 0) {
-                    face_values(P, opp(f), q, uN);
+                    int fN, qN;
+                    nbr_point(P, K, f, q, fN, qN);
+                    face_values(P, fN, qN, uN);
                     double ak = 0, an = 0;
                     for (int j = 0; j < n; ++j) {
                         ak += uK[j] * (Q1x[(size_t)K * n + j] * nxh + Q1y[(size_t)K * n + j] * nyh);
@@ -880,13 +969,14 @@ void assemble_correction_operator(Problem& P) {
             if (N < 0) continue;
             const double iN = 1.0 / P.sigma_t[N];
             double* cN = &P.corr_val[((size_t)K * 5 + 1 + f) * n * n3];
-            const int fN = opp(f);
             for (int q = 0; q < nq; ++q) {
+                int fN, qN;
+                nbr_point(P, K, f, q, fN, qN);
                 const size_t fo = ((size_t)K * 4 + f) * nq + q;
-                const size_t foN = ((size_t)N * 4 + fN) * nq + q;
+                const size_t foN = ((size_t)N * 4 + fN) * nq + qN;
                 const double nx_ = P.nhat[fo * 2], ny_ = P.nhat[fo * 2 + 1], s = P.dsw[fo];
                 face_values(P, f, q, uK);
-                face_values(P, fN, q, uN);
+                face_values(P, fN, qN, uN);
                 for (int i = 0; i < n; ++i) {
                     const double gix = P.face_grad[(fo * n + i) * 2], giy = P.face_grad[(fo * n + i) * 2 + 1];
                     for (int j = 0; j < n; ++j) {

@@ -499,9 +499,10 @@ __global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepA
                         const bool up = (a.upflag[(long)d * ne + K] >> f) & 1;
                         const T* src = up ? psi : plag;
                         if (src) {
-                            const int fN = (f + 2) & 3;
+                            const int code = a.nbr_face ? (int)a.nbr_face[K * 4 + f] : ((f + 2) & 3);
+                            const int fN = code & 3, qN = (code & 4) ? nq - 1 - q : q;
                             const T* sN = src + ((long)d * ne + Nb) * N;
-                            for (int c = 0; c < NB; ++c) val += Lf[c * nq + q] * sN[face_node<NB>(fN, c)];
+                            for (int c = 0; c < NB; ++c) val += Lf[c * nq + qN] * sN[face_node<NB>(fN, c)];
                         }
                     }
                 }
@@ -618,7 +619,9 @@ __global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a)
                 const int Nb = a.nbr[K * 4 + f];
                 const T* src = nullptr;
                 if (Nb >= 0) src = ((up >> f) & 1) ? psi : plag;
-                const int fN = (f + 2) & 3;
+                const int code = a.nbr_face ? (int)a.nbr_face[K * 4 + f] : ((f + 2) & 3);
+                const int fN = code & 3;
+                const bool rev = (code & 4) != 0;
                 for (int q = 0; q < nq; ++q) {
                     const T* nn = nds + (((long)K * 4 + f) * nq + q) * 2;
                     const T on = ox * nn[0] + oy * nn[1];
@@ -634,8 +637,9 @@ __global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a)
                             if (pbar) val = pbar[((long)d * a.nbf + a.bface_of[K * 4 + f]) * nq + q];
                         } else if (src) {
                             const T* sN = src + ((long)d * ne + Nb) * N;
+                            const int qN = rev ? nq - 1 - q : q;
 #pragma unroll
-                            for (int c = 0; c < NB; ++c) val += Lf[c * nq + q] * sN[face_node<NB>(fN, c)];
+                            for (int c = 0; c < NB; ++c) val += Lf[c * nq + qN] * sN[face_node<NB>(fN, c)];
                         }
 #pragma unroll
                         for (int c = 0; c < NB; ++c) A[face_node<NB>(f, c)][N] -= on * Lf[c * nq + q] * val;
@@ -931,6 +935,60 @@ __global__ void closures_beta_kernel(int n, int nb, int nq, int nbf, long L, con
     beta[t] = v;
 }
 
+// beta on boundaries whose normal is not along x or y: at each boundary
+// point, sum over directions of w (|Omega.n| - E_b0(n)) times the element's
+// trace of psi (eq. bdr_correction_factor_disc), from psi itself (the moment
+// rows hold |Omega_x| and |Omega_y| weights only).  accumulate: add to beta
+// (delta sweeps: beta is linear in psi).
+template <typename T>
+__global__ void closures_beta_general_kernel(int nd, int n, int nb, int nq, int nbf, long ld,
+                                             const T* __restrict__ psi, const double* __restrict__ omega,
+                                             const double* __restrict__ w, const int* __restrict__ bK,
+                                             const int* __restrict__ bF, const double* __restrict__ nhat_b,
+                                             const double* __restrict__ eb0_pt, const double* __restrict__ Lf,
+                                             int accumulate, double* __restrict__ beta) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbf * nq) return;
+    const int bf = t / nq, q = t - bf * nq;
+    const int K = bK[bf], f = bF[bf];
+    const double nx = nhat_b[2 * t], ny = nhat_b[2 * t + 1], e = eb0_pt[t];
+    double v = 0.0;
+    for (int d = 0; d < nd; ++d) {
+        const T* pd = psi + (long)d * ld + (long)K * n;
+        double tr = 0.0;
+        for (int c = 0; c < nb; ++c) {
+            int k;
+            switch (f) {
+                case 0: k = c; break;
+                case 1: k = (nb - 1) + nb * c; break;
+                case 2: k = c + nb * (nb - 1); break;
+                default: k = nb * c; break;
+            }
+            tr += Lf[c * nq + q] * (double)pd[k];
+        }
+        v += w[d] * (std::fabs(omega[d * 3] * nx + omega[d * 3 + 1] * ny) - e) * tr;
+    }
+    beta[t] = accumulate ? beta[t] + v : v;
+}
+
+hipError_t launch_beta_general(bool fp64, int nd, int ne, int n, int nb, int nq, int nbf, const void* psi,
+                               const double* omega, const double* w, const int* bface_K, const int* bface_f,
+                               const double* nhat_b, const double* eb0_pt, const double* Lf, bool accumulate,
+                               double* beta, hipStream_t s) {
+    if (nbf <= 0) return hipSuccess;
+    const long ld = (long)ne * n;
+    const dim3 g((nbf * nq + 255) / 256), b(256);
+    if (fp64)
+        hipLaunchKernelGGL(closures_beta_general_kernel<double>, g, b, 0, s, nd, n, nb, nq, nbf, ld,
+                           (const double*)psi, omega, w, bface_K, bface_f, nhat_b, eb0_pt, Lf, accumulate ? 1 : 0,
+                           beta);
+    else
+        hipLaunchKernelGGL(closures_beta_general_kernel<float>, g, b, 0, s, nd, n, nb, nq, nbf, ld,
+                           (const float*)psi, omega, w, bface_K, bface_f, nhat_b, eb0_pt, Lf, accumulate ? 1 : 0,
+                           beta);
+    return hipGetLastError();
+}
+
 hipError_t launch_closures(int ne, int n, int nb, int nq, int nbf, const double* mom, const int* bface_K,
                            const int* bface_f, const double* Lf, double eb0x, double eb0y, double* T,
                            double* beta, hipStream_t s) {
@@ -988,7 +1046,7 @@ hipError_t launch_rhs(int ne, int n, int nq, const double* bfix, const int* bsr_
 // Blocks cover whole elements (epb = 256 / n elements each) so the
 // preconditioner can be applied from LDS.  Device scalars:
 //   scal[0] rz   scal[1] rz_old   scal[2] bb   scal[3] rr
-//   scal[4] done scal[5] iterations   scal[6] breakdown   scal[7] tol^2 bb
+//   scal[4] done scal[5] iterations   scal[6] breakdown (1: p.Ap <= 0, 2: non-finite)   scal[7] tol^2 bb
 // Reductions are per-block partials summed by every block in a fixed order,
 // so results are bitwise reproducible.
 // ---------------------------------------------------------------------------
@@ -1112,7 +1170,7 @@ __global__ __launch_bounds__(CG_THREADS) void cg_k2(CgState c) {
     const double rz = c.scal[0];
     if (!(pq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            c.scal[6] = 1.0;
+            c.scal[6] = pq <= 0.0 ? 1.0 : 2.0;  // 2: not a number (a non-finite right-hand side)
             c.scal[4] = 1.0;
         }
         return;
@@ -1587,6 +1645,191 @@ __global__ __launch_bounds__(MAXT) void b_sweep_kernel(const CartSweepArgs* __re
         if (!active[tk.x]) continue;
         sweep_lane_task<T, NB, MULTI, LANE_PREFETCH>(args[tk.x], tk.y, smem);
         __syncthreads();
+    }
+}
+
+// ---- persistent sweep, element-lane shape ------------------------------------
+// The same per-element operator as above, another mapping: each lane solves a
+// whole element of an anti-diagonal (all N nodes; the N x (N + 2 NB) operator
+// rows are wave-uniform scalar operands, as above), a workgroup is one wave per
+// 64-slot chunk.  The inflow traces of level m come from level m - 1: the x
+// trace from the element left of this one, the y trace from the one below it,
+// i.e. from this lane or its neighbour (which one depends only on whether the
+// first slot of the level moved along x), passed by lane shuffles; only the
+// traces that cross a chunk boundary go through LDS, with one barrier per level
+// when the workgroup has several waves.  No other LDS: source and flux move
+// straight between HBM and registers.
+template <typename T, int NB, bool MULTI>
+__device__ __forceinline__ void sweep_elem_task(const CartSweepArgs& a, const int d, T* xb, T* yb) {
+    constexpr int N = NB * NB;
+    constexpr int RW = lane_rw(NB);
+    const int nx = a.nx, ny = a.ny, nd = a.nd;
+    const long ne = (long)nx * ny;
+    const int nlev = nx + ny - 1;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nw = blockDim.x >> 6;
+    const int slot = wv * 64 + lane;
+    const auto om = as_global(a.omega);
+    const double ox = om[d * 3], oy = om[d * 3 + 1];
+    const bool sx = ox > 0.0, sy = oy > 0.0;
+    const auto S = as_global(reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0));
+    const auto psi = as_global(reinterpret_cast<T*>(a.psi) + (long)d * (a.psi_ld > 0 ? a.psi_ld : ne * N));
+    const auto bx = as_global(reinterpret_cast<const T*>(a.bx));
+    const auto by = as_global(reinterpret_cast<const T*>(a.by));
+    const T* tab = reinterpret_cast<const T*>(a.tab);
+    const int aout = sx ? NB - 1 : 0;   // outflow x face: node column aout
+    const int bout = sy ? NB - 1 : 0;   // outflow y face: node row bout
+    T xo[NB], yo[NB];                    // this lane's last outflow traces
+#pragma unroll
+    for (int c = 0; c < NB; ++c) xo[c] = yo[c] = T(0);
+    for (int m = 0; m < nlev; ++m) {
+        const int i0 = m - (ny - 1) > 0 ? m - (ny - 1) : 0;
+        const int i1 = m < nx - 1 ? m : nx - 1;
+        const int len = i1 - i0 + 1;
+        const bool moved_x = m > 0 && m - 1 - (ny - 1) >= 0;  // i0(m) = i0(m - 1) + 1
+        // traces of level m - 1 from the neighbouring lanes (all lanes take part)
+        T xl[NB], yr[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            xl[c] = __shfl_up(xo[c], 1);
+            yr[c] = __shfl_down(yo[c], 1);
+        }
+        if (nw > 1 && m > 0) {
+            const int pb = (m - 1) & 1;
+            if (lane == 0 && wv > 0)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) xl[c] = xb[(pb * 4 + wv - 1) * NB + c];
+            if (lane == 63 && wv + 1 < nw)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) yr[c] = yb[(pb * 4 + wv + 1) * NB + c];
+        }
+        if (wv * 64 < len) {             // wave-uniform: the wave holds elements of this level
+            const bool act = slot < len;
+            const int ip = i0 + slot;            // quadrant-oriented grid coordinates
+            const int jp = m - ip;
+            const int ci = act ? (sx ? ip : nx - 1 - ip) : 0;
+            const int cj = act ? (sy ? jp : ny - 1 - jp) : 0;
+            const unsigned K = (unsigned)(cj * nx + ci);
+            T tx[NB], ty[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                // x inflow: the left neighbour was this lane (first slot moved) or the one before
+                T vx = moved_x ? xo[c] : xl[c];
+                T vy = moved_x ? yr[c] : yo[c];
+                if (ip == 0) vx = bx ? bx[((long)d * ny + cj) * NB + c] : T(0);
+                if (jp == 0) vy = by ? by[((long)d * nx + ci) * NB + c] : T(0);
+                tx[c] = vx;
+                ty[c] = vy;
+            }
+            T sv[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) sv[c] = ld_at(S, act ? K * N + c : 0u);
+            T out[N];
+            auto apply = [&](int mat, T(&o)[N]) {
+                const T* blk = tab + ((long)mat * nd + d) * N * RW;
+                const cptr<T> tr = uniform_rows(blk);
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    const int row = ((r % NB) * NB + r / NB) * RW;   // row r = ca + NB b of the table
+                    T v = T(0);
+#pragma unroll
+                    for (int c = 0; c < N; ++c) v += tr[row + c] * sv[c];
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) v += tr[row + N + c] * tx[c];
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) v += tr[row + N + NB + c] * ty[c];
+                    o[r] = v;
+                }
+            };
+            if constexpr (!MULTI) {
+                apply(0, out);
+            } else {
+                const auto mat = as_global(a.mat);
+                const int cm = act ? (int)mat[K] : -1;
+                unsigned long long todo = __ballot(act);
+#pragma unroll
+                for (int r = 0; r < N; ++r) out[r] = T(0);
+                while (todo) {
+                    const int lead = __builtin_ctzll(todo);
+                    const int mm = __builtin_amdgcn_readfirstlane(__shfl(cm, lead));
+                    T tmp[N];
+                    apply(mm, tmp);
+                    const bool mine = cm == mm;
+#pragma unroll
+                    for (int r = 0; r < N; ++r) out[r] = mine ? tmp[r] : out[r];
+                    todo &= ~__ballot(mine);
+                }
+            }
+            if (act) {
+#pragma unroll
+                for (int r = 0; r < N; ++r) st_at(psi, K * N + r, out[r]);
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    xo[c] = out[aout + NB * c];
+                    yo[c] = out[c + NB * bout];
+                }
+            }
+        }
+        if (nw > 1) {
+            const int pb = m & 1;
+            if (lane == 63)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) xb[(pb * 4 + wv) * NB + c] = xo[c];
+            if (lane == 0)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) yb[(pb * 4 + wv) * NB + c] = yo[c];
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T, int NB, bool MULTI>
+__global__ __launch_bounds__(256) void b_sweep_elem_kernel(const CartSweepArgs* __restrict__ args,
+                                                            const int2* __restrict__ tasks, int ntasks,
+                                                            int* __restrict__ counter,
+                                                            const int* __restrict__ active) {
+    __shared__ T xb[2 * 4 * NB], yb[2 * 4 * NB];   // chunk-boundary traces, by level parity
+    __shared__ int tsk;
+    while (true) {
+        if (threadIdx.x == 0) tsk = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = tsk;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const int2 tk = tasks[t];
+        if (!active[tk.x]) continue;
+        sweep_elem_task<T, NB, MULTI>(args[tk.x], tk.y, xb, yb);
+        __syncthreads();
+    }
+}
+
+template <typename T, int NB>
+static hipError_t b_sweep_elem_nb(bool multi, int threads, int grid, const CartSweepArgs* args, const int2* tasks,
+                                  int ntasks, int* counter, const int* active, hipStream_t s) {
+    if (multi)
+        hipLaunchKernelGGL((b_sweep_elem_kernel<T, NB, true>), dim3(grid), dim3(threads), 0, s, args, tasks, ntasks,
+                           counter, active);
+    else
+        hipLaunchKernelGGL((b_sweep_elem_kernel<T, NB, false>), dim3(grid), dim3(threads), 0, s, args, tasks, ntasks,
+                           counter, active);
+    return hipGetLastError();
+}
+
+hipError_t b_sweep_elem(bool fp64, int nb, bool multi, int threads, int grid, const CartSweepArgs* args,
+                        const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s) {
+    // one wave per 64-slot chunk of the longest anti-diagonal, at most four
+    if (threads < 64 || threads > 256 || threads % 64 != 0) return hipErrorNotSupported;
+    switch (nb) {
+        case 2: return fp64 ? b_sweep_elem_nb<double, 2>(multi, threads, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_elem_nb<float, 2>(multi, threads, grid, args, tasks, ntasks, counter, active, s);
+        case 3: return fp64 ? b_sweep_elem_nb<double, 3>(multi, threads, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_elem_nb<float, 3>(multi, threads, grid, args, tasks, ntasks, counter, active, s);
+        case 4: return fp64 ? b_sweep_elem_nb<double, 4>(multi, threads, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_elem_nb<float, 4>(multi, threads, grid, args, tasks, ntasks, counter, active, s);
+        case 5: return fp64 ? b_sweep_elem_nb<double, 5>(multi, threads, grid, args, tasks, ntasks, counter, active, s)
+                            : b_sweep_elem_nb<float, 5>(multi, threads, grid, args, tasks, ntasks, counter, active, s);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -2600,7 +2843,7 @@ __global__ __launch_bounds__(BT) void b_cg_red1(BatchLaunch B) {
     if (threadIdx.x == 0) {
         double* s = P.scal;
         if (!(pq > 0.0)) {
-            s[6] = 1.0;
+            s[6] = pq <= 0.0 ? 1.0 : 2.0;  // 2: not a number (a non-finite right-hand side)
             s[4] = 1.0;
         } else {
             s[8] = s[0] / pq;

@@ -44,6 +44,8 @@ struct GenSweepArgs {
     const void* Lf;              // [nb][nq]
     const void* sigma_t;         // [ne]
     const int* nbr;              // [ne][4]
+    const uint8_t* nbr_face;     // [ne][4] neighbour's face | 4 (its face points run the other way);
+                                 //   null: the opposite face, same way (structured grids)
     const int* bface_of;         // [ne][4]
     const uint8_t* upflag;       // [nd][ne]
     const int* lev_ptr;          // [nd][ntiles][nlev+1] offsets into the direction's list
@@ -67,6 +69,10 @@ hipError_t launch_source(bool fp64, int ne, int n, int nd_q, const double* sigma
 hipError_t launch_axpy_mom(long L, const double* a, double* acc, hipStream_t s);  // acc += a
 
 // T and beta from the 8 moment rows
+hipError_t launch_beta_general(bool fp64, int nd, int ne, int n, int nb, int nq, int nbf, const void* psi,
+                               const double* omega, const double* w, const int* bface_K, const int* bface_f,
+                               const double* nhat_b, const double* eb0_pt, const double* Lf, bool accumulate,
+                               double* beta, hipStream_t s);
 hipError_t launch_closures(int ne, int n, int nb, int nq, int nbf, const double* mom,
                            const int* bface_K, const int* bface_f, const double* Lf,
                            double eb0x, double eb0y, double* T, double* beta, hipStream_t s);
@@ -206,6 +212,10 @@ hipError_t b_source(bool fp64, const BatchLaunch& B, bool delta, hipStream_t s);
 // Persistent batched sweep over (problem, direction) tasks.  `threads` is
 // b_sweep_threads of the largest problem of the task list, `lds` the largest
 // b_sweep_lds; `multi` selects the variant for problems with several materials.
+// element-lane shape of the batched sweep: threads = 64 per 64-slot chunk of the
+// longest anti-diagonal (at most 4 chunks), no dynamic LDS
+hipError_t b_sweep_elem(bool fp64, int nb, bool multi, int threads, int grid, const CartSweepArgs* args,
+                        const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s);
 hipError_t b_sweep(bool fp64, int nb, bool multi, int threads, size_t lds, int grid, const CartSweepArgs* args,
                    const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s);
 int b_sweep_threads(int nb, int nx, int ny);

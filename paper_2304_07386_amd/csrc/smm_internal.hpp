@@ -44,6 +44,14 @@ struct Problem {
     std::vector<double> Lf, dLf;           // [nb][nq] 1D basis at Gauss points
     double eb0x = 0, eb0y = 0;             // E_b0 for x- and y-normal boundary faces
 
+    // mesh given element by element (smm_problem_create_general): per-element
+    // control points [ne][(m+1)^2][2], neighbours [ne][4] and boundary
+    // attributes [ne][4] as given; nx = ne, ny = 1
+    bool general = false;
+    std::vector<double> ctrl_e;
+    std::vector<int> nbr_in, bdr_attr_in;
+    bool quad_explicit = false;            // directions given by the caller (not level-symmetric)
+
     // geometry (general path data, FP64)
     std::vector<double> ctrl;              // copy of control points
     std::vector<double> xnode;             // [ne][n][2]
@@ -58,6 +66,12 @@ struct Problem {
     std::vector<double> face_grad;         // [ne][4][nq][n][2]
     std::vector<double> vol_U;             // [nq*nq][n]
     std::vector<int> nbr;                  // [ne][4]
+    std::vector<int> nbr_face;             // [ne][4] neighbour's local face | 4 if its parameter runs the
+                                           //   other way (its point nq-1-q is this element's q); -1 boundary
+    std::vector<int> bface_attr;           // [nbf] boundary attribute
+    int n_bdr_attr = 0;
+    bool axis_bdr = true;                  // every boundary normal along x or y (E_b0 one constant per axis)
+    std::vector<double> eb0_pt;            // [nbf][nq] E_b0 at each boundary point (eq. eb0_disc)
     std::vector<int> bface_of;             // [ne][4] -> boundary face id or -1
     std::vector<int> bface_K, bface_f;     // [nbf]
     std::vector<double> chord;             // [ne][4][2] integral of n ds (from end points)
@@ -77,6 +91,8 @@ struct Problem {
     std::vector<int> lev_ptr;              // [nd][ntiles][nlev_max+1]
     std::vector<int> lev_elem;             // [nd][ne], tile-major, then level
     std::vector<uint8_t> upflag;           // [nd][ne] bit f: neighbour across f is upstream
+
+    double kappa_scale = 1.0;              // factor on the IP penalty (solve option)
 
     // materials, sources, inflow
     bool have_mat = false;
@@ -122,6 +138,12 @@ struct Problem {
 };
 
 int setup_geometry(Problem& P, std::string& err, bool heavy);
+// the neighbour's face and its point that coincide with point q of face f of K
+inline void nbr_point(const Problem& P, int K, int f, int q, int& fN, int& qN) {
+    const int code = P.nbr_face[(size_t)K * 4 + f];
+    fN = code & 3;
+    qN = (code & 4) ? P.nq - 1 - q : q;
+}
 int ensure_heavy(Problem& P, std::string* err = nullptr);   // per-element quadrature data and sweep graph, on demand
 void setup_cartesian_operators(Problem& P);
 int setup_sweep_graph(Problem& P, std::string& err);  // SMM_EUNSUPPORTED on a cycle

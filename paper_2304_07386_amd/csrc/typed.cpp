@@ -24,7 +24,9 @@
 namespace smm {
 
 bool typed_applicable(const Problem& P) {
-    return P.cartesian && P.src_layout == SMM_SRC_ISO &&
+    // (the typed right-hand side also relies on the symmetry of the
+    // level-symmetric set: sum w Omega q = 0 for an isotropic q)
+    return P.cartesian && !P.general && !P.quad_explicit && P.src_layout == SMM_SRC_ISO &&
            (P.inflow_layout == SMM_INFLOW_VACUUM || P.inflow_layout == SMM_INFLOW_ISO_FACE);
 }
 
@@ -86,6 +88,7 @@ int patch_blocks(const Problem& P, int i, int j, std::vector<double>& ip_self, s
     Q.nq = P.nq;
     Q.ne = px * py;
     Q.sn = P.sn;
+    Q.kappa_scale = P.kappa_scale;
     Q.omega = P.omega;
     Q.w = P.w;
     Q.nd = P.nd;

@@ -19,12 +19,14 @@ SMM_OK, SMM_EINVAL, SMM_ENOMEM, SMM_EHIP, SMM_ENOCONV, SMM_ENAN, SMM_EBREAKDOWN,
     0, -1, -2, -3, -4, -5, -6, -7, -8)
 SMM_FP64, SMM_FP32_SWEEP = 0, 1
 SMM_SRC_ISO, SMM_SRC_ANISO = 0, 1
-SMM_INFLOW_VACUUM, SMM_INFLOW_ISO_FACE, SMM_INFLOW_FULL = 0, 1, 2
+SMM_INFLOW_VACUUM, SMM_INFLOW_ISO_FACE, SMM_INFLOW_FULL, SMM_INFLOW_ISO_ATTR = 0, 1, 2, 3
+SMM_QUAD_LEVEL_SYMMETRIC, SMM_QUAD_EXPLICIT = 0, 1
 SMM_START_ZERO, SMM_START_DIFFUSION, SMM_START_GIVEN = 0, 1, 2
 SMM_DISC_IP, SMM_DISC_CG = 0, 1
 
 EXPORTED = [
     "smm_strerror", "smm_ctx_create", "smm_ctx_destroy", "smm_last_error", "smm_problem_create",
+    "smm_problem_create_general", "smm_problem_create_q",
     "smm_problem_destroy", "smm_get_dims", "smm_get_quadrature", "smm_get_nodes", "smm_get_bface_points",
     "smm_set_materials", "smm_set_source", "smm_set_inflow", "smm_default_opts", "smm_solve",
     "smm_get_outputs", "smm_apply_sweep", "smm_apply_moments", "smm_apply_G", "smm_debug_ip_dense",
@@ -33,12 +35,13 @@ EXPORTED = [
     "smm_batch_create", "smm_batch_destroy", "smm_batch_solve", "smm_batch_get_outputs",
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
     "smm_batch_history", "smm_debug_mg_level", "smm_debug_batch_precond", "smm_debug_batch_spmv",
-    "smm_debug_batch_grouped", "smm_debug_sweep_graph", "smm_batch_apply_sweep", "smm_apply_G_noalloc",
+    "smm_debug_batch_grouped", "smm_debug_sweep_graph", "smm_batch_apply_sweep", "smm_apply_G_noalloc", "smm_solve_history",
+    "smm_debug_batch_sweep_shape",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
     "smm_batch_diffusion", "smm_batch_warmstart_features", "smm_batch_warmstart_targets",
-    "smm_batch_set_warmstart", "smm_batch_warmstart_used",
+    "smm_batch_set_warmstart", "smm_batch_warmstart_used", "smm_set_warmstart",
 ]
 
 
@@ -52,10 +55,20 @@ class smm_mesh_desc(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("m", C.c_int), ("ctrl", C.POINTER(C.c_double))]
 
 
+class smm_mesh_general_desc(C.Structure):
+    _fields_ = [("n_elem", C.c_int), ("m", C.c_int), ("ctrl", C.POINTER(C.c_double)), ("nbr", C.POINTER(C.c_int)),
+                ("bdr_attr", C.POINTER(C.c_int))]
+
+
+class smm_quad_desc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("sn_order", C.c_int), ("n_dir", C.c_int), ("omega", C.POINTER(C.c_double)),
+                ("w", C.POINTER(C.c_double))]
+
+
 class smm_problem_dims(C.Structure):
     _fields_ = [("n_elem", C.c_int), ("n_node", C.c_int), ("n_dir", C.c_int), ("n_bface", C.c_int),
                 ("nq", C.c_int), ("cartesian", C.c_int), ("n_material", C.c_int), ("n_levels", C.c_int),
-                ("n_self_types", C.c_int), ("n_nbr_types", C.c_int)]
+                ("n_self_types", C.c_int), ("n_nbr_types", C.c_int), ("general", C.c_int), ("n_bdr_attr", C.c_int)]
 
 
 class smm_solve_opts(C.Structure):
@@ -63,13 +76,14 @@ class smm_solve_opts(C.Structure):
                 ("inner_tol", C.c_double), ("max_inner", C.c_int), ("start", C.c_int),
                 ("delta_sweeps", C.c_int), ("use_graph", C.c_int), ("moment_path", C.c_int),
                 ("anderson", C.c_int), ("precond", C.c_int), ("inner_adapt", C.c_double),
-                ("discretization", C.c_int)]
+                ("discretization", C.c_int), ("kappa_scale", C.c_double)]
 
 
 class smm_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("residual", C.c_double), ("residual_abs", C.c_double),
                 ("cg_iterations_total", C.c_int), ("cg_iterations_max", C.c_int),
-                ("t_total_ms", C.c_double), ("t_setup_ms", C.c_double)]
+                ("t_total_ms", C.c_double), ("t_setup_ms", C.c_double), ("t_sweep_ms", C.c_double),
+                ("t_moments_ms", C.c_double), ("t_cg_ms", C.c_double), ("t_residual_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -95,6 +109,9 @@ def load_library(path: str = LIB_PATH):
         "smm_last_error": (C.c_char_p, [vp]),
         "smm_problem_create": (ip, [vp, C.POINTER(smm_mesh_desc), ip, ip, C.POINTER(vp)]),
         "smm_problem_destroy": (ip, [vp]),
+        "smm_problem_create_general": (ip, [vp, C.POINTER(smm_mesh_general_desc), ip, C.POINTER(smm_quad_desc),
+                                            C.POINTER(vp)]),
+        "smm_problem_create_q": (ip, [vp, C.POINTER(smm_mesh_desc), ip, C.POINTER(smm_quad_desc), C.POINTER(vp)]),
         "smm_get_dims": (ip, [vp, C.POINTER(smm_problem_dims)]),
         "smm_get_quadrature": (ip, [vp, vp, vp]),
         "smm_get_nodes": (ip, [vp, vp]),
@@ -104,6 +121,8 @@ def load_library(path: str = LIB_PATH):
         "smm_set_inflow": (ip, [vp, vp, ip]),
         "smm_default_opts": (None, [C.POINTER(smm_solve_opts)]),
         "smm_solve": (ip, [vp, C.POINTER(smm_solve_opts), vp, C.POINTER(smm_solve_info)]),
+        "smm_solve_history": (ip, [vp, ip, vp, vp, C.POINTER(ip)]),
+        "smm_set_warmstart": (ip, [vp, vp]),
         "smm_get_outputs": (ip, [vp, vp, vp, vp, vp, vp, ip]),
         "smm_apply_sweep": (ip, [vp, ip, vp, ip, vp, vp, ip]),
         "smm_apply_moments": (ip, [vp, ip, vp, vp]),
@@ -133,6 +152,7 @@ def load_library(path: str = LIB_PATH):
         "smm_debug_batch_precond": (ip, [vp, ip, C.POINTER(vp), C.POINTER(vp)]),
         "smm_debug_batch_spmv": (ip, [vp, C.POINTER(vp), C.POINTER(vp)]),
         "smm_debug_batch_grouped": (ip, [vp, ip]),
+        "smm_debug_batch_sweep_shape": (ip, [vp, ip]),
         "smm_cnn_create": (ip, [vp, ip, C.POINTER(ip), ip, ip, ip, C.POINTER(vp)]),
         "smm_cnn_destroy": (ip, [vp]),
         "smm_cnn_num_params": (ip, [vp, C.POINTER(C.c_size_t)]),
@@ -232,6 +252,47 @@ def smm_problem_create(ctx: Context, nx: int, ny: int, m: int, ctrl: np.ndarray,
     return Problem(ctx, h)
 
 
+def _quad_desc(sn: int = 0, quad=None):
+    """Quadrature descriptor and the arrays it points to (kept alive by the caller)."""
+    if quad is None:
+        return smm_quad_desc(SMM_QUAD_LEVEL_SYMMETRIC, int(sn), 0, None, None), ()
+    om, w = _f64(quad[0]).reshape(-1, 3), _f64(quad[1]).reshape(-1)
+    return smm_quad_desc(SMM_QUAD_EXPLICIT, 0, len(w), om.ctypes.data_as(C.POINTER(C.c_double)),
+                         w.ctypes.data_as(C.POINTER(C.c_double))), (om, w)
+
+
+def smm_problem_create_q(ctx: Context, nx: int, ny: int, m: int, ctrl: np.ndarray, p: int, sn: int = 0,
+                         quad=None) -> Problem:
+    """Structured mesh with the level-symmetric set of order sn, or the
+    explicit set quad = (omega [n_dir, 3], w [n_dir])."""
+    ctrl = _f64(ctrl)
+    assert ctrl.size == (ny * m + 1) * (nx * m + 1) * 2
+    desc = smm_mesh_desc(nx, ny, m, ctrl.ctypes.data_as(C.POINTER(C.c_double)))
+    qd, keep = _quad_desc(sn, quad)
+    h = C.c_void_p()
+    _check(load_library().smm_problem_create_q(ctx.handle, C.byref(desc), p, C.byref(qd), C.byref(h)), ctx)
+    return Problem(ctx, h)
+
+
+def smm_problem_create_general(ctx: Context, elem_ctrl: np.ndarray, nbr: np.ndarray, m: int, p: int,
+                               bdr_attr=None, sn: int = 0, quad=None) -> Problem:
+    """Mesh given element by element: elem_ctrl [ne, (m+1)^2, 2], nbr [ne, 4]
+    (-1: boundary), bdr_attr [ne, 4] or None; level-symmetric order sn or an
+    explicit set quad = (omega, w)."""
+    ctrl = _f64(elem_ctrl)
+    ne = len(ctrl)
+    assert ctrl.size == ne * (m + 1) ** 2 * 2
+    nb = np.ascontiguousarray(np.asarray(nbr, dtype=np.int32).reshape(ne, 4))
+    at = None if bdr_attr is None else np.ascontiguousarray(np.asarray(bdr_attr, dtype=np.int32).reshape(ne, 4))
+    desc = smm_mesh_general_desc(ne, m, ctrl.ctypes.data_as(C.POINTER(C.c_double)),
+                                 nb.ctypes.data_as(C.POINTER(C.c_int)),
+                                 None if at is None else at.ctypes.data_as(C.POINTER(C.c_int)))
+    qd, keep = _quad_desc(sn, quad)
+    h = C.c_void_p()
+    _check(load_library().smm_problem_create_general(ctx.handle, C.byref(desc), p, C.byref(qd), C.byref(h)), ctx)
+    return Problem(ctx, h)
+
+
 def smm_problem_destroy(prob: Problem):
     load_library().smm_problem_destroy(prob.handle)
 
@@ -302,6 +363,21 @@ def smm_solve(prob: Problem, opts: smm_solve_opts | None = None, varphi0=None, r
 def smm_get_outputs(prob: Problem, varphi=None, phi=None, J=None, T=None, beta=None, on_device=False):
     _check(load_library().smm_get_outputs(prob.handle, _ptr(varphi), _ptr(phi), _ptr(J), _ptr(T), _ptr(beta),
                                           1 if on_device else 0), prob.ctx)
+
+
+def smm_solve_history(prob: Problem):
+    """(outer residuals, CG iterations) of each outer iteration of the last smm_solve."""
+    n = C.c_int()
+    _check(load_library().smm_solve_history(prob.handle, 0, None, None, C.byref(n)), prob.ctx)
+    r = np.zeros(n.value)
+    c = np.zeros(n.value, dtype=np.int32)
+    _check(load_library().smm_solve_history(prob.handle, n.value, _ptr(r), _ptr(c), C.byref(n)), prob.ctx)
+    return r, c
+
+
+def smm_set_warmstart(prob: Problem, net):
+    """Attach (or detach with None) the warm-start network used by SMM_START_LEARNED in smm_solve."""
+    _check(load_library().smm_set_warmstart(prob.handle, None if net is None else net.handle), prob.ctx)
 
 
 def smm_get_outputs_host(prob: Problem) -> dict:
@@ -541,6 +617,11 @@ def smm_batch_apply_sweep(batch, precision: int, sources, k: int):
     psi = np.zeros((pk.n_dir, pk.n_elem, pk.n_node))
     _check(load_library().smm_batch_apply_sweep(batch.handle, precision, arr, int(k), _ptr(psi)), batch.ctx)
     return psi
+
+
+def smm_debug_batch_sweep_shape(batch, shape: int):
+    """Force the batched sweep's kernel shape: 0 column-wave, 1 element-lane, -1 autotuned."""
+    _check(load_library().smm_debug_batch_sweep_shape(batch.handle, shape), batch.ctx)
 
 
 def smm_debug_batch_grouped(batch, grouped: int):

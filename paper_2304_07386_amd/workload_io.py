@@ -12,7 +12,14 @@ from . import smm as S
 
 
 def problem_from_workload(ctx, wl, q=None, psibar=None):
-    prob = S.smm_problem_create(ctx, wl.nx, wl.ny, wl.m, wl.ctrl, wl.p, wl.sn)
+    quad = getattr(wl, "quad", None)
+    if getattr(wl, "elem_ctrl", None) is not None:
+        prob = S.smm_problem_create_general(ctx, wl.elem_ctrl, wl.nbr, wl.m, wl.p, bdr_attr=wl.bdr_attr,
+                                            sn=wl.sn, quad=quad)
+    elif quad is not None:
+        prob = S.smm_problem_create_q(ctx, wl.nx, wl.ny, wl.m, wl.ctrl, wl.p, quad=quad)
+    else:
+        prob = S.smm_problem_create(ctx, wl.nx, wl.ny, wl.m, wl.ctrl, wl.p, wl.sn)
     S.smm_set_materials(prob, wl.sigma_t, wl.sigma_s)
     n = prob.n_node
     if q is not None:
@@ -31,6 +38,8 @@ def problem_from_workload(ctx, wl, q=None, psibar=None):
         S.smm_set_inflow(prob, None, S.SMM_INFLOW_VACUUM)
     elif wl.inflow[0] == "iso":
         S.smm_set_inflow(prob, np.full(prob.dims.n_bface, float(wl.inflow[1])), S.SMM_INFLOW_ISO_FACE)
+    elif wl.inflow[0] == "attr":
+        S.smm_set_inflow(prob, np.asarray(wl.inflow[1], dtype=np.float64), S.SMM_INFLOW_ISO_ATTR)
     else:
         om, _ = S.smm_get_quadrature(prob)
         xy = S.smm_get_bface_points(prob)

@@ -99,12 +99,11 @@ def test_validation_errors(hctx):
     with pytest.raises(L.SmmError) as e:
         L.smm_problem_create(hctx, 2, 2, 1, bad, 1, 4)
     assert e.value.code == L.SMM_EINVAL
-    # slanted boundary is reported as unsupported
+    # a slanted boundary runs on the per-element paths (E_b0 per boundary point)
     sl = wl.ctrl.copy()
     sl[0, 1] = [0.5, -0.1]
-    with pytest.raises(L.SmmError) as e:
-        L.smm_problem_create(hctx, 2, 2, 1, sl, 1, 4)
-    assert e.value.code == L.SMM_EUNSUPPORTED
+    ps = L.smm_problem_create(hctx, 2, 2, 1, sl, 1, 4)
+    assert ps.dims.cartesian == 0
     p = L.smm_problem_create(hctx, 2, 2, 1, wl.ctrl, 1, 4)
     with pytest.raises(L.SmmError) as e:
         L.smm_set_materials(p, np.ones(4), np.full(4, 2.0))

@@ -1,0 +1,141 @@
+"""Boundary calls of the problem statement (no batch), on the GPU.
+
+* kappa_scale (Sec. 6: the penalty kappa = {(p+1)^2/(sigma_t h)} times a
+  factor): the converged flux with kappa_scale = 2 equals the oracle's with
+  the same factor (FP64, 1e-12) and differs from the factor-1 flux (the IP
+  discretisation depends on the penalty), on the per-element and on the
+  typed path; going back to 1 restores the factor-1 flux.
+* Forced from the host, normal early exits: kappa_scale = 0 makes the IP
+  operator indefinite (the oracle's matrix has negative eigenvalues), and the
+  moment solve meets p.Ap <= 0: SMM_EBREAKDOWN on both paths.  A start with
+  a NaN (SMM_START_GIVEN) makes the moment solve non-finite: SMM_ENAN.
+* The solve info splits the device time by phase and the per-iteration
+  history (outer residual and CG iterations) matches the iteration count.
+* SMM_START_LEARNED in smm_solve (one problem, the network set by
+  smm_set_warmstart) reaches the zero start's fixed point (FP32 bar).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import smm as osmm
+from workloads import config_blobs, config_channel, config_plain
+
+from .gpu_common import announce, make_pair, rel_l2
+
+torch = pytest.importorskip("torch")
+L = pytest.importorskip("paper_2304_07386_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return L.smm_ctx_create(0, torch.cuda.current_stream())
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_kappa_scale(ctx, path):
+    announce(f"kappa_scale 2 vs oracle, moment path {path}")
+    wl = config_channel(n=6, p=2, sn=4, side=1.3)
+    pr, p = make_pair(L, ctx, wl)
+    pr2 = osmm.make_problem(wl, kappa_scale=2.0)
+    ref1, _ = osmm.solve(pr, tol=1e-13, max_it=200)
+    ref2, _ = osmm.solve(pr2, tol=1e-13, max_it=200)
+    assert rel_l2(ref2, ref1) > 1e-6
+    out = {}
+    for ks in (2.0, 1.0):
+        rc, info = L.smm_solve(p, L.smm_default_opts(precision=L.SMM_FP64, outer_tol=1e-13, inner_tol=1e-15,
+                                                      max_inner=20000, max_outer=200, moment_path=path,
+                                                      kappa_scale=ks))
+        assert rc == L.SMM_OK
+        out[ks] = L.smm_get_outputs_host(p)["varphi"]
+    assert rel_l2(out[2.0], ref2) < 1e-12
+    assert rel_l2(out[1.0], ref1) < 1e-12
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_indefinite_penalty_breakdown(ctx, path):
+    announce(f"kappa_scale 0 -> SMM_EBREAKDOWN, moment path {path}")
+    wl = config_plain(4, 1, 4)
+    pr0 = osmm.make_problem(wl, kappa_scale=0.0)
+    A = osmm.ip_matrix(pr0).toarray()
+    assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() < 0
+    _, p = make_pair(L, ctx, wl)
+    with pytest.raises(L.SmmError) as e:
+        L.smm_solve(p, L.smm_default_opts(precision=L.SMM_FP64, outer_tol=1e-10, max_outer=5, max_inner=500,
+                                          moment_path=path, kappa_scale=0.0))
+    assert e.value.code == L.SMM_EBREAKDOWN
+    rc, _ = L.smm_solve(p, L.smm_default_opts(precision=L.SMM_FP64, outer_tol=1e-10, max_outer=100,
+                                               moment_path=path))
+    assert rc == L.SMM_OK
+
+
+def test_kappa_scale_validation(ctx):
+    _, p = make_pair(L, ctx, config_plain(4, 1, 4))
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(L.SmmError) as e:
+            L.smm_solve(p, L.smm_default_opts(kappa_scale=bad))
+        assert e.value.code == L.SMM_EINVAL
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_nan_start_gives_enan(ctx, path):
+    announce(f"NaN given start -> SMM_ENAN, moment path {path}")
+    _, p = make_pair(L, ctx, config_plain(4, 1, 4))
+    v0 = np.ones(p.n_elem * p.n_node)
+    v0[5] = np.nan
+    with pytest.raises(L.SmmError) as e:
+        L.smm_solve(p, L.smm_default_opts(precision=L.SMM_FP64, start=L.SMM_START_GIVEN, max_outer=5,
+                                          max_inner=200, moment_path=path), varphi0=v0)
+    assert e.value.code == L.SMM_ENAN
+
+
+@pytest.mark.parametrize("path", [0, 1])
+def test_info_time_split_and_history(ctx, path):
+    announce(f"solve info time split and history, moment path {path}")
+    _, p = make_pair(L, ctx, config_plain(8, 2, 6))
+    rc, info = L.smm_solve(p, L.smm_default_opts(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=1e-8,
+                                                  inner_tol=1e-12, moment_path=path))
+    assert rc == L.SMM_OK
+    for k in ("t_sweep_ms", "t_moments_ms", "t_cg_ms", "t_residual_ms"):
+        assert info[k] > 0, k
+    assert info["t_sweep_ms"] + info["t_moments_ms"] + info["t_cg_ms"] + info["t_residual_ms"] <= \
+        info["t_total_ms"] * 1.05 + 1.0
+    r, cg = L.smm_solve_history(p)
+    assert len(r) == info["iterations"] == len(cg)
+    assert r[-1] == info["residual"] and r[-1] < 1e-8 and r[0] == 1.0
+    assert cg.sum() == info["cg_iterations_total"] and cg.max() == info["cg_iterations_max"]
+
+
+def test_learned_start_single_problem(ctx):
+    from paper_2304_07386_amd import warmstart as W
+    if not os.path.exists(W.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights")
+    announce("SMM_START_LEARNED in smm_solve on one blob layout")
+    wl = config_blobs(20007)
+    _, p = make_pair(L, ctx, wl)
+    net, _ = W.load(ctx, max_batch=4)
+    rc, iz = L.smm_solve(p, W.solve_opts(1e-8, start=L.SMM_START_ZERO))
+    vz = L.smm_get_outputs_host(p)["varphi"]
+    with pytest.raises(L.SmmError) as e:
+        L.smm_solve(p, W.solve_opts(1e-8, start=L.SMM_START_LEARNED))
+    assert e.value.code == L.SMM_ESTATE
+    L.smm_set_warmstart(p, net)
+    rc, il = L.smm_solve(p, W.solve_opts(1e-8, start=L.SMM_START_LEARNED))
+    vl = L.smm_get_outputs_host(p)["varphi"]
+    assert rc == L.SMM_OK and rel_l2(vl, vz) < 1e-5
+    print(f"zero start {iz['iterations']} outer, learned start {il['iterations']}", flush=True)
+    assert il["iterations"] <= iz["iterations"]
+    L.smm_set_warmstart(p, None)
+    # not a uniform Cartesian problem: the learned start is refused
+    from workloads import config_curved_mms
+    _, pc = make_pair(L, ctx, config_curved_mms(4, 2, 4))
+    with pytest.raises(L.SmmError) as e:
+        L.smm_solve(pc, W.solve_opts(1e-8, precision=L.SMM_FP64, start=L.SMM_START_LEARNED, anderson=0,
+                                     precond=L.SMM_PRECOND_BJ))
+    assert e.value.code == L.SMM_EUNSUPPORTED
+    L.smm_cnn_destroy(net)

@@ -66,6 +66,9 @@ def test_full_batch_sampled_members(ctx):
 
 
 def _batched_sweep_vs_oracle(ctx, wls, members, dirs_per_member, seed):
+    """Both kernel shapes of the batched sweep (and the autotuned choice) in
+    the batch's launch configuration: equal to each other bit for bit, and
+    to the oracle's sweep."""
     probs = [L.problem_from_workload(ctx, wl) for wl in wls]
     batch = L.smm_batch_create(ctx, probs)
     rng = np.random.default_rng(seed)
@@ -79,13 +82,19 @@ def _batched_sweep_vs_oracle(ctx, wls, members, dirs_per_member, seed):
         dirs = sorted({(nd * j) // dirs_per_member for j in range(dirs_per_member)} | {nd - 1})
         ref = transport.sweep(pr.mesh, pr.omega[dirs], pr.sigma_t, srcs[k].reshape(pr.ne, pr.n), pr.psibar)
         for prec, bar in ((L.SMM_FP64, 1e-12), (L.SMM_FP32_SWEEP, 1e-5)):
-            announce(f"batched sweep member {k} ({wls[k].nx}^2 p={wls[k].p} S{wls[k].sn}) precision {prec}")
-            psi = L.smm_batch_apply_sweep(batch, prec, srcs, k)
-            assert np.all(np.isfinite(psi))
-            for j, d in enumerate(dirs):
-                e = rel_l2(psi[d], ref[j])
-                worst[(k, prec)] = max(worst.get((k, prec), 0.0), e)
-                assert e < bar, (k, prec, d, e)
+            got = {}
+            for shape in (0, 1, -1):
+                announce(f"batched sweep member {k} ({wls[k].nx}^2 p={wls[k].p} S{wls[k].sn}) precision {prec} "
+                         f"shape {shape}")
+                L.smm_debug_batch_sweep_shape(batch, shape)
+                psi = L.smm_batch_apply_sweep(batch, prec, srcs, k)
+                assert np.all(np.isfinite(psi))
+                got[shape] = psi
+                for j, d in enumerate(dirs):
+                    e = rel_l2(psi[d], ref[j])
+                    worst[(k, prec, shape)] = max(worst.get((k, prec, shape), 0.0), e)
+                    assert e < bar, (k, prec, shape, d, e)
+            assert np.array_equal(got[0], got[1]) and np.array_equal(got[0], got[-1])
     L.smm_batch_destroy(batch)
     return worst
 
