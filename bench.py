@@ -299,6 +299,29 @@ def time_to_solution(L, ctx, n: int, log):
         log(f"{name}: {t:.2f} s, outer its mean {res[name + '_outer_mean']:.2f}")
     res["learned_start_kept"] = int(L.smm_batch_warmstart_used(batch).sum())
     res["speedup_batched_warm_vs_plain"] = t_plain / res["batched_warm_s"]
+    res["speedup_batched_zero_vs_plain"] = t_plain / res["batched_zero_s"]
+    # what the learned start costs, part by part (the same calls the solve
+    # makes: the diffusion start's moment solve, the features, the network)
+    nf, nt, hh, ww = L.smm_batch_warmstart_dims(batch)
+    X = torch.zeros((n, hh, ww, nf), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((n, hh, ww, nt), dtype=torch.float32, device="cuda")
+    o = W.solve_opts(1e-8, start=L.SMM_START_LEARNED)
+    split = {}
+    for name, fn in (("diffusion_solve_s", lambda: L.smm_batch_diffusion(batch, max(o.inner_tol, o.inner_adapt),
+                                                                          o.max_inner)),
+                     ("features_s", lambda: L.smm_batch_warmstart_features(batch, 0, n, X)),
+                     ("network_forward_s", lambda: [L.smm_cnn_forward(net, X[k:k + 32], min(32, n - k), Y[k:k + 32])
+                                                    for k in range(0, n, 32)])):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        split[name] = time.perf_counter() - t0
+    per_it = res["batched_zero_s"] / max(res["batched_zero_outer_mean"], 1e-9)
+    split["outer_iteration_s"] = per_it
+    split["outer_iterations_saved"] = res["batched_zero_outer_mean"] - res["batched_warm_outer_mean"]
+    res["learned_start_cost"] = split
+    log("learned start cost: " + ", ".join(f"{k} {v:.4f}" for k, v in split.items()))
     L.smm_batch_set_warmstart(batch, None)
     L.smm_batch_destroy(batch)
     L.smm_cnn_destroy(net)

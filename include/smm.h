@@ -162,7 +162,15 @@ typedef struct {
     int delta_sweeps;    /* 1: sweep only the change of the scattering source and
                             accumulate the moments in FP64 (default for FP32_SWEEP) */
     int use_graph;       /* 1: replay the PCG iteration chunks of the typed (batched) path
-                            and of the CG moment solve from captured hipGraphs */
+                            and of the CG moment solve from captured hipGraphs; 2 (typed path):
+                            also replay each outer iteration -- scattering source, the forked
+                            persistent sweep launches, moments, closures, right-hand side, PCG
+                            start and a chunk of PCG iterations (what the last iteration's slowest
+                            solve needed, rounded down to an even number, 2..64), residual and
+                            Anderson's products --
+                            from one captured graph per iteration shape; moment solves that need
+                            more iterations continue in replayed chunks.  Results are bitwise
+                            those of the eager launches. */
     int moment_path;     /* 0: typed blocks on uniform Cartesian meshes with isotropic
                             sources (batched kernels), else per-element operators;
                             1: always per-element operators */
@@ -350,12 +358,14 @@ int smm_time_cg_spmv(smm_problem* prob, int reps, double* ms_avg);
 
 /* Sweep kernel selection: 0 = automatic (tabulated operators on uniform
  * Cartesian meshes, otherwise per-element assembly and elimination: one lane
- * per element for p <= 2, one wave per element for p >= 3); 1 = always the
- * per-element kernel (solve form as in 0); 2 = on Cartesian meshes, the
- * element-row kernel instead of the column-per-thread one; 3 = the
- * per-element kernel with one wave per element at every order.  2 and 3
- * are for cross-checking the kernels against each other.  Returns
- * SMM_EINVAL outside 0..3. */
+ * per row of the element's system with Gauss-Jordan elimination for p >= 3,
+ * and for p = 2 unless the levels are wide and spread over many workgroups;
+ * otherwise one lane per element); 1 = always the per-element kernel
+ * (solve form as in 0); 2 = on Cartesian meshes, the element-row kernel
+ * instead of the column-per-thread one; 3 = the per-element kernel with one
+ * wave per element at every order; 4 = the per-element kernel with one lane
+ * per row at every order p >= 2.  2, 3 and 4 are for cross-checking the
+ * kernels against each other.  Returns SMM_EINVAL outside 0..4. */
 int smm_set_sweep_path(smm_problem* prob, int path);
 
 /* Parallel block Jacobi sweep (Sec. 6.5, weak scaling): the element grid is
@@ -448,8 +458,12 @@ int smm_batch_units(const smm_batch* batch, double* units);
 /* Time of the outer-iteration phases of the last smm_batch_solve, in ms,
  * summed over its outer iterations (HIP events on the context's stream):
  * ms[0] scattering source and sweep, ms[1] moments, closures and right-hand
- * side, ms[2] PCG moment solve, ms[3] residual and shift.  cg_iterations
- * (nullable) receives the number of batched PCG iterations launched. */
+ * side, ms[2] PCG moment solve, ms[3] residual and shift.  With use_graph = 2
+ * the phases are instead: ms[0] the replayed iteration graph (source through
+ * the first PCG chunk and the residual), ms[1] further PCG chunks, ms[2] the
+ * residual taken again after them, ms[3] read-back, shift or mixing.
+ * cg_iterations (nullable) receives the number of batched PCG iterations
+ * launched. */
 int smm_batch_phase_times(const smm_batch* batch, double* ms, long* cg_iterations);
 /* Outer residual r_k (and PCG iterations, nullable) of each outer iteration of
  * problem k in the last smm_batch_solve: the first min(max_len, *len) entries

@@ -389,11 +389,13 @@ int smm_set_sweep_tiles(smm_problem* prob, int tile_nx, int tile_ny) {
 }
 
 // sweep paths 1 and 3 force the per-element kernel (3 also its wave-wide solve)
-static bool per_element_forced(const Dev& D) { return D.force_general == 1 || D.force_general == 3; }
+static bool per_element_forced(const Dev& D) {
+    return D.force_general == 1 || D.force_general == 3 || D.force_general == 4;
+}
 
 int smm_set_sweep_path(smm_problem* prob, int force_general) {
     if (!prob) return SMM_EINVAL;
-    if (force_general < 0 || force_general > 3) return SMM_EINVAL;
+    if (force_general < 0 || force_general > 4) return SMM_EINVAL;
     prob->D.force_general = force_general;
     return SMM_OK;
 }
@@ -651,7 +653,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
         a.ne = P.ne; a.nd = P.nd; a.nb = P.nb; a.nq = P.nq; a.nbf = P.nbf; a.nlev = P.nlev_max;
         a.ntiles = P.ntiles;
         a.maxw = P.lev_wmax;
-        a.wave_solve = D.force_general == 3 ? 1 : 0;
+        a.wave_solve = D.force_general == 3 ? 1 : (D.force_general == 4 ? 2 : 0);
         a.s_aniso = s_aniso;
         a.S = S;
         a.Mk = fp64 ? D.Mk64 : D.Mk32;

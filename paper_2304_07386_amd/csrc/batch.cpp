@@ -175,6 +175,9 @@ struct smm_batch {
     bool use_graph = false;
     hipStream_t cap = nullptr;
     std::map<std::tuple<int, bool, bool, int>, hipGraphExec_t> cg_graphs;  // (chunk, tolerances, two-level, orders)
+    // whole outer iterations (use_graph = 2), keyed by (PCG chunk, first sweep,
+    // Anderson slot, FP64, per-problem tolerances, two-level, grouped, orders x 8 + sweep streams)
+    std::map<std::tuple<int, int, int, int, int, int, int, int>, hipGraphExec_t> it_graphs;
     std::vector<uint8_t> cg_conv;  // per problem: the last PCG reached its tolerance
 };
 
@@ -252,6 +255,7 @@ void batch_free(smm_batch* B) {
     for (auto& e : B->pev)
         if (e) (void)hipEventDestroy(e);
     for (auto& g : B->cg_graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& g : B->it_graphs) (void)hipGraphExecDestroy(g.second);
     if (B->cap) (void)hipStreamDestroy(B->cap);
     delete B;
 }
@@ -815,7 +819,7 @@ hipError_t group_sweep(smm_batch* B, Group& G, bool fp64, int shape, int grid, c
 
 // Run the sweep of all active problems: one persistent launch per order, on
 // forked streams when there is more than one order.
-int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
+int batch_sweep(smm_batch* B, bool fp64, bool inflow, hipStream_t st) {
     smm_ctx* c = B->ctx;
     const int f = fp64 ? 1 : 0;
     const int ng = (int)B->groups.size();
@@ -823,14 +827,14 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
     // nstr side streams (chosen by the autotuner)
     const int nstr = std::min(B->sweep_streams[f] > 0 ? B->sweep_streams[f] : 1, 4);
     const bool fork = ng > 1 && nstr > 1;
-    HIPCHK(c, zero_ints(B->d_sweep_counters, ng, c->stream));
+    HIPCHK(c, zero_ints(B->d_sweep_counters, ng, st));
     if (fork) {
-        HIPCHK(c, hipEventRecord(B->ev_fork, c->stream));
+        HIPCHK(c, hipEventRecord(B->ev_fork, st));
         for (int k = 0; k < std::min(ng, nstr); ++k) HIPCHK(c, hipStreamWaitEvent(B->side[k], B->ev_fork, 0));
     }
     for (int k = 0; k < ng; ++k) {
         Group& G = B->groups[k];
-        hipStream_t s = fork ? B->side[k % nstr] : c->stream;
+        hipStream_t s = fork ? B->side[k % nstr] : st;
         int grid = G.grid[f] > 0 ? G.grid[f] : std::min<int>((int)G.tasks.size(), 2 * B->ncu);
         hipError_t e = group_sweep(B, G, fp64, G.shape[f] == 1 ? 1 : 0, grid, B->d_args[f][inflow ? 1 : 0], s);
         if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("batched sweep: ") + hipGetErrorString(e));
@@ -838,10 +842,11 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow) {
     if (fork)
         for (int k = 0; k < std::min(ng, nstr); ++k) {
             HIPCHK(c, hipEventRecord(B->ev_join[k], B->side[k]));
-            HIPCHK(c, hipStreamWaitEvent(c->stream, B->ev_join[k], 0));
+            HIPCHK(c, hipStreamWaitEvent(st, B->ev_join[k], 0));
         }
     return SMM_OK;
 }
+int batch_sweep(smm_batch* B, bool fp64, bool inflow) { return batch_sweep(B, fp64, inflow, B->ctx->stream); }
 
 // Autotuner: for every persistent sweep launch, time each candidate kernel
 // shape (column-wave: NB waves per 64-slot chunk, the node columns of an
@@ -938,10 +943,12 @@ int batch_autotune(smm_batch* B, bool fp64) {
     return SMM_OK;
 }
 
-int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
+// started: the PCG start and done0 iterations were already launched (by an
+// outer-iteration graph)
+int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its, bool started = false, int done0 = 0) {
     smm_ctx* c = B->ctx;
     const BatchLaunch L = launch_desc(B);
-    HIPCHK(c, b_cg_start(L, tol, c->stream, &B->mgl));
+    if (!started) HIPCHK(c, b_cg_start(L, tol, c->stream, &B->mgl));
     std::vector<double> sc(16 * (size_t)B->nprob);
     // per problem, r.r and the iteration count at the previous check: their
     // ratio gives the residual's reduction per iteration, from which the
@@ -949,7 +956,7 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
     // converges (a chunk that overshoots runs iterations with nothing left
     // to do; one that falls short costs one more host round trip)
     std::vector<double> rr_prev(B->nprob, -1.0), it_prev(B->nprob, 0.0);
-    int done_its = 0, chunk = 4;
+    int done_its = done0, chunk = 4;
     while (true) {
         HIPCHK(c, hipMemcpyAsync(sc.data(), B->d_scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -972,7 +979,9 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
                 const double* q = &sc[16 * (size_t)b];
                 if (!B->active[b] || q[4] != 0.0) continue;
                 const double rr = q[3], target = q[7], di = q[5] - it_prev[b];
-                int nb = 16;
+                // no rate known yet: 16 from a fresh start, 2 after the chunk of an
+                // iteration graph (which aims just below the iterations needed)
+                int nb = started && rr_prev[b] < 0.0 ? 2 : 16;
                 if (rr_prev[b] > 0.0 && rr > 0.0 && rr < rr_prev[b] && di > 0.0 && target > 0.0) {
                     const double per = std::log(rr / rr_prev[b]) / di;  // < 0
                     nb = (int)std::ceil(std::log(target / rr) / per);
@@ -1180,8 +1189,100 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     B->cg_batched_its = 0;
     B->hist.assign(np, {});
     B->cg_hist.assign(np, {});
+    const bool gmode = o.use_graph >= 2;   // the outer iteration from captured graphs
+    int kpred = 8;                          // PCG iterations inside the iteration graph
     for (it = 1; it <= o.max_outer && nactive > 0; ++it) {
         const bool first = (it == 1) || !delta;
+        const int slot = (it - 1) % 3;
+        if (gmode) {
+            // One graph per iteration shape: scattering source, sweep (forked
+            // per-order launches), moments, closures, right-hand side, PCG
+            // start and kpred PCG iterations, residual (and Anderson's store
+            // and Gram products), replayed on the context's stream.  The host
+            // then checks the moment solves once; any that has not converged
+            // gets more PCG chunks, after which the residual is taken again.
+            if (o.inner_adapt > 0) {
+                for (int b = 0; b < np; ++b) tol_k[b] = std::max(o.inner_tol, o.inner_adapt * r_prev[b]);
+                HIPCHK(c, hipMemcpyAsync(B->d_tol, tol_k.data(), sizeof(double) * np, hipMemcpyHostToDevice,
+                                         c->stream));
+                B->use_ptol = true;
+            }
+            const BatchLaunch Lg = launch_desc(B);
+            int mask = 0;
+            for (int b = 0; b < np; ++b)
+                if (B->active[b]) mask |= 1 << B->probs[b]->P.nb;
+            const int k = std::max(1, std::min(kpred, o.max_inner));
+            const int nstr = B->sweep_streams[fp64 ? 1 : 0];
+            const auto key = std::make_tuple(k, first ? 1 : 0, aa > 0 ? slot : -1, fp64 ? 1 : 0,
+                                             Lg.ptol ? 1 : 0, Lg.mg, Lg.grouped, mask * 8 + nstr);
+            auto gi = B->it_graphs.find(key);
+            if (gi == B->it_graphs.end()) {
+                if (!B->cap) HIPCHK(c, hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                hipGraphExec_t ge = nullptr;
+                hipStream_t cs = B->cap;
+                HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+                BatchLaunch Lk = Lg;
+                Lk.order_mask = mask;
+                hipError_t e = b_source(fp64, Lg, !first, cs);
+                int src = e == hipSuccess ? batch_sweep(B, fp64, first, cs) : SMM_EHIP;
+                if (src == SMM_OK) {
+                    hipError_t ek[8] = {b_moments(fp64, Lg, true, first, cs), b_closures_rhs(Lg, cs), b_copy_x(Lg, cs),
+                                        b_cg_start(Lg, o.inner_tol, cs, &B->mgl),
+                                        b_cg_iterations(Lk, k, cs, &B->mgl), b_residual(Lg, B->d_rout, cs),
+                                        aa > 0 ? b_aa_store(Lg, slot, cs) : hipSuccess,
+                                        aa > 0 ? b_aa_gram(Lg, B->d_aapart, B->d_aadot, cs) : hipSuccess};
+                    for (hipError_t x : ek)
+                        if (x != hipSuccess) e = x;
+                }
+                const hipError_t e2 = hipStreamEndCapture(cs, &g);
+                if (src != SMM_OK || e != hipSuccess || e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    B->use_ptol = false;
+                    return fail(c, SMM_EHIP, "outer-iteration graph capture failed");
+                }
+                const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e3 != hipSuccess) {
+                    B->use_ptol = false;
+                    return fail(c, SMM_EHIP, "outer-iteration graph instantiation failed");
+                }
+                gi = B->it_graphs.emplace(key, ge).first;
+            }
+            HIPCHK(c, hipEventRecord(B->pev[0], c->stream));
+            HIPCHK(c, hipGraphLaunch(gi->second, c->stream));
+            HIPCHK(c, hipEventRecord(B->pev[1], c->stream));
+            B->cg_batched_its += k;
+            const long before = B->cg_batched_its;
+            rc = batch_cg(B, o.inner_tol, o.max_inner, its, true, k);
+            B->use_ptol = false;
+            if (rc) return rc;
+            HIPCHK(c, hipEventRecord(B->pev[2], c->stream));
+            if (B->cg_batched_its != before) {   // more PCG chunks ran: the residual again
+                HIPCHK(c, b_residual(L, B->d_rout, c->stream));
+                if (aa > 0) {
+                    HIPCHK(c, b_aa_store(L, slot, c->stream));
+                    HIPCHK(c, b_aa_gram(L, B->d_aapart, B->d_aadot, c->stream));
+                }
+            }
+            HIPCHK(c, hipEventRecord(B->pev[3], c->stream));
+            HIPCHK(c, hipMemcpyAsync(ro.data(), B->d_rout, sizeof(double) * ro.size(), hipMemcpyDeviceToHost,
+                                     c->stream));
+            if (aa > 0)
+                HIPCHK(c, hipMemcpyAsync(gram.data(), B->d_aadot, sizeof(double) * gram.size(),
+                                         hipMemcpyDeviceToHost, c->stream));
+            else
+                HIPCHK(c, b_shift(L, c->stream));
+            // the next graph's PCG chunk, from the iterations the active moment
+            // solves took: iterations launched after every solve has converged
+            // cost whole launches, one host check and a short further chunk
+            // cost less, so the chunk aims at the slowest solve's count rounded
+            // down to an even number (2..64)
+            int need = 0;
+            for (int b = 0; b < np; ++b)
+                if (B->active[b]) need = std::max(need, its[b]);
+            kpred = std::max(2, std::min(64, need & ~1));
+        } else {
         HIPCHK(c, hipEventRecord(B->pev[0], c->stream));
         HIPCHK(c, b_source(fp64, L, !first, c->stream));
         if ((rc = batch_sweep(B, fp64, first))) return rc;
@@ -1201,7 +1302,6 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
         HIPCHK(c, hipEventRecord(B->pev[3], c->stream));
         HIPCHK(c, b_residual(L, B->d_rout, c->stream));
         HIPCHK(c, hipMemcpyAsync(ro.data(), B->d_rout, sizeof(double) * ro.size(), hipMemcpyDeviceToHost, c->stream));
-        const int slot = (it - 1) % 3;
         if (aa > 0) {
             HIPCHK(c, b_aa_store(L, slot, c->stream));
             HIPCHK(c, b_aa_gram(L, B->d_aapart, B->d_aadot, c->stream));
@@ -1209,6 +1309,7 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
                                      c->stream));
         } else {
             HIPCHK(c, b_shift(L, c->stream));
+        }
         }
         HIPCHK(c, hipEventRecord(B->pev[4], c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -574,7 +574,7 @@ __global__ __launch_bounds__(64 * GEN_WAVES) void sweep_general_kernel(GenSweepA
 // ceil(m / 256) waves instead of m wave-solves.  Same assembly (volume, then
 // faces in order), elimination without pivoting (one division per pivot) and
 // back substitution by rows.
-template <typename T, int NB>
+template <typename T, int NB, bool GENERAL>
 __global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a) {
     constexpr int N = NB * NB;
     const int d = blockIdx.x;
@@ -619,9 +619,11 @@ __global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a)
                 const int Nb = a.nbr[K * 4 + f];
                 const T* src = nullptr;
                 if (Nb >= 0) src = ((up >> f) & 1) ? psi : plag;
-                const int code = a.nbr_face ? (int)a.nbr_face[K * 4 + f] : ((f + 2) & 3);
+                // the neighbour's face and orientation (a structured grid: the
+                // opposite face, same way)
+                const int code = GENERAL ? (int)a.nbr_face[K * 4 + f] : ((f + 2) & 3);
                 const int fN = code & 3;
-                const bool rev = (code & 4) != 0;
+                const bool rev = GENERAL && (code & 4) != 0;
                 for (int q = 0; q < nq; ++q) {
                     const T* nn = nds + (((long)K * 4 + f) * nq + q) * 2;
                     const T on = ox * nn[0] + oy * nn[1];
@@ -675,9 +677,189 @@ __global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a)
     }
 }
 
+// The same per-element solve with one lane per row: a wave holds 64 / N
+// elements (N = (p+1)^2 lanes each; 7, 4, 2 elements at p = 2, 3, 4), lane i
+// assembles row i of its element's augmented system [A | b] in registers
+// (volume terms, then the faces through node i in order), and the system is
+// reduced by Gauss-Jordan elimination without pivoting: for each pivot k the
+// lane holding row k publishes it in LDS (double-buffered by the parity of k),
+// every other lane subtracts its multiple, so no back substitution is needed;
+// x_i = b_i / A_ii.  The pivot loop is unrolled (register indices are
+// compile-time).  Face data are staged first: the element's lanes compute
+// Omega.n ds and the upwind trace at all 4 nq face points together (one
+// round of independent loads) into LDS, where the face terms read them.  A
+// level of m elements takes ceil(m / (64 / N)) wave-solves spread over the
+// workgroup's waves.
+template <typename T, int NB, int WAVES, bool GENERAL>
+__global__ __launch_bounds__(64 * WAVES) void sweep_rows_general_kernel(GenSweepArgs a) {
+    constexpr int N = NB * NB;
+    constexpr int EPW = 64 / N;   // elements per wave
+    const int d = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int eslot = lane / N;           // element of this lane within the wave
+    const int i = lane - eslot * N;       // row of this lane
+    const bool lane_ok = eslot < EPW;
+    const int es = lane_ok ? eslot : 0;
+    const int nq = a.nq, ne = a.ne;
+    __shared__ T prow[WAVES][2][EPW][N + 1];
+    __shared__ T fon[WAVES][EPW][4 * GEN_MAXQ];    // Omega.n (weighted ds) at the face points
+    __shared__ T fval[WAVES][EPW][4 * GEN_MAXQ];   // upwind trace at the inflow points
+    __shared__ T lfs[NB * GEN_MAXQ];               // face basis at the face points
+    const T ox = (T)a.omega[d * 3], oy = (T)a.omega[d * 3 + 1];
+    const T* S = reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0);
+    const T* Mk = reinterpret_cast<const T*>(a.Mk);
+    const T* Gx = reinterpret_cast<const T*>(a.Gx);
+    const T* Gy = reinterpret_cast<const T*>(a.Gy);
+    const T* nds = reinterpret_cast<const T*>(a.nds);
+    const T* st = reinterpret_cast<const T*>(a.sigma_t);
+    const T* pbar = reinterpret_cast<const T*>(a.psibar);
+    const T* plag = reinterpret_cast<const T*>(a.psi_lag);
+    T* psi = reinterpret_cast<T*>(a.psi);
+    for (int t = threadIdx.x; t < NB * nq; t += blockDim.x) lfs[t] = reinterpret_cast<const T*>(a.Lf)[t];
+    __syncthreads();
+    const int* lp = a.lev_ptr + ((long)d * a.ntiles + blockIdx.y) * (a.nlev + 1);
+    const int* le = a.lev_elem + (long)d * ne;
+    for (int l = 0; l < a.nlev; ++l) {
+        const int beg = lp[l], end = lp[l + 1];
+        for (int base = beg; base < end; base += WAVES * EPW) {
+            const int e = base + wv * EPW + eslot;
+            const bool act = lane_ok && e < end;
+            const int K = act ? le[e] : le[beg];
+            // face data of the element, all points at once
+            if (lane_ok) {
+                const uint8_t up = a.upflag[(long)d * ne + K];
+                for (int t = i; t < 4 * nq; t += N) {
+                    const int f = t / nq, q = t - f * nq;
+                    const T* nn = nds + (((long)K * 4 + f) * nq + q) * 2;
+                    const T on = ox * nn[0] + oy * nn[1];
+                    T val = T(0);
+                    if (on < T(0)) {
+                        const int Nb = a.nbr[K * 4 + f];
+                        if (Nb < 0) {
+                            if (pbar) val = pbar[((long)d * a.nbf + a.bface_of[K * 4 + f]) * nq + q];
+                        } else {
+                            const T* src = ((up >> f) & 1) ? psi : plag;
+                            if (src) {
+                                const int code = GENERAL ? (int)a.nbr_face[K * 4 + f] : ((f + 2) & 3);
+                                const int fN = code & 3;
+                                const int qN = (GENERAL && (code & 4)) ? nq - 1 - q : q;
+                                const T* sN = src + ((long)d * ne + Nb) * N;
+#pragma unroll
+                                for (int c = 0; c < NB; ++c) val += lfs[c * nq + qN] * sN[face_node<NB>(fN, c)];
+                            }
+                        }
+                    }
+                    fon[wv][es][t] = on;
+                    fval[wv][es][t] = val;
+                }
+            }
+            // row i of [A | b]: volume terms
+            T A[N + 1];
+            {
+                const T sK = st[K];
+                const T* M = Mk + ((long)K * N + i) * N;
+                const T* gx = Gx + ((long)K * N + i) * N;
+                const T* gy = Gy + ((long)K * N + i) * N;
+                const T* sk = S + (long)K * N;
+                T b = T(0);
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    const T m = M[j];
+                    A[j] = sK * m - ox * gx[j] - oy * gy[j];
+                    b += m * sk[j];
+                }
+                A[N] = b;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // faces through node i: outflow points couple node i to the face's
+            // nodes, inflow points bring the upwind trace
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int c = face_pos<NB>(f, i);
+                if (c < 0) continue;
+                for (int q = 0; q < nq; ++q) {
+                    const T on = fon[wv][es][f * nq + q];
+                    const T lc = lfs[c * nq + q];
+                    if (on > T(0)) {
+#pragma unroll
+                        for (int c2 = 0; c2 < NB; ++c2) A[face_node<NB>(f, c2)] += on * lc * lfs[c2 * nq + q];
+                    } else if (on < T(0)) {
+                        A[N] -= on * lc * fval[wv][es][f * nq + q];
+                    }
+                }
+            }
+            // Gauss-Jordan elimination, one pivot at a time
+            T diag = T(1);
+            T (*pr)[EPW][N + 1] = prow[wv];
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                T* row = pr[k & 1][es];
+                if (i == k && lane_ok) {
+#pragma unroll
+                    for (int j = 0; j <= N; ++j) row[j] = A[j];
+                    diag = A[k];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (i != k) {
+                    const T m = A[k] / row[k];
+#pragma unroll
+                    for (int j = k; j <= N; ++j) A[j] -= m * row[j];
+                }
+            }
+            if (act) psi[((long)d * ne + K) * N + i] = A[N] / diag;
+            // the face data of the next element group overwrite fon / fval
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int NB, bool GENERAL>
+static hipError_t launch_rows_g(const GenSweepArgs& a, hipStream_t s) {
+    constexpr int N = NB * NB;
+    constexpr int EPW = 64 / N;
+    // as many waves as the widest level needs, at most 16 (8 in FP64, whose
+    // rows need more than the 128 VGPRs a 16-wave workgroup leaves a lane)
+    const int need = (a.maxw + EPW - 1) / EPW;
+    if constexpr (sizeof(T) == 4) {
+        if (need > 8) {
+            hipLaunchKernelGGL((sweep_rows_general_kernel<T, NB, 16, GENERAL>), dim3(a.nd, a.ntiles), dim3(1024), 0,
+                               s, a);
+            return hipGetLastError();
+        }
+    }
+    if (need > 4)
+        hipLaunchKernelGGL((sweep_rows_general_kernel<T, NB, 8, GENERAL>), dim3(a.nd, a.ntiles), dim3(512), 0, s, a);
+    else if (need > 2)
+        hipLaunchKernelGGL((sweep_rows_general_kernel<T, NB, 4, GENERAL>), dim3(a.nd, a.ntiles), dim3(256), 0, s, a);
+    else if (need > 1)
+        hipLaunchKernelGGL((sweep_rows_general_kernel<T, NB, 2, GENERAL>), dim3(a.nd, a.ntiles), dim3(128), 0, s, a);
+    else
+        hipLaunchKernelGGL((sweep_rows_general_kernel<T, NB, 1, GENERAL>), dim3(a.nd, a.ntiles), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NB>
+static hipError_t launch_rows_t(const GenSweepArgs& a, hipStream_t s) {
+    return a.nbr_face ? launch_rows_g<T, NB, true>(a, s) : launch_rows_g<T, NB, false>(a, s);
+}
+
 template <typename T, int NB>
 static hipError_t launch_gen_t(const GenSweepArgs& a, hipStream_t s) {
     if (a.nq > GEN_MAXQ || 4 * a.nq > 64) return hipErrorInvalidValue;
+    if constexpr (NB >= 3) {
+        // one lane per row: the default at p >= 3; at p = 2 where levels are
+        // narrow or workgroups few (the lane-per-element form wins only with
+        // wide levels spread over many tiles: measured 0.84 against 1.15 ms on
+        // 32^2 tiles of the 128^2 channel, 0.79 against 0.61 ms on the whole
+        // curved 32^2 mesh, 1.82 against 0.88 ms on 8^2 tiles); path 4 at p = 2
+        const bool rows_p2 = a.maxw <= 16 || (long)a.nd * a.ntiles < 1024;
+        if (a.wave_solve == 2 || (a.wave_solve == 0 && (NB >= 4 || rows_p2))) return launch_rows_t<T, NB>(a, s);
+    }
     // few workgroups (whole-mesh sweeps: one per direction) take the widest
     // workgroup their levels fill; many (tiles) take 4 waves, so that more
     // workgroups share each CU
@@ -689,7 +871,12 @@ static hipError_t launch_gen_t(const GenSweepArgs& a, hipStream_t s) {
     if constexpr (NB <= 3) {
         if (a.wave_solve != 1) {
             const int threads = std::min(256, std::max(64, (a.maxw + 63) / 64 * 64));
-            hipLaunchKernelGGL((sweep_lane_general_kernel<T, NB>), dim3(a.nd, a.ntiles), dim3(threads), 0, s, a);
+            if (a.nbr_face)
+                hipLaunchKernelGGL((sweep_lane_general_kernel<T, NB, true>), dim3(a.nd, a.ntiles), dim3(threads), 0,
+                                   s, a);
+            else
+                hipLaunchKernelGGL((sweep_lane_general_kernel<T, NB, false>), dim3(a.nd, a.ntiles), dim3(threads), 0,
+                                   s, a);
             return hipGetLastError();
         }
     }

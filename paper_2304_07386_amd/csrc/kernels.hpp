@@ -34,7 +34,8 @@ struct GenSweepArgs {
     int ne, nd, nb, nq, nbf, nlev;
     int ntiles;                  // independent element tiles (1: the full sweep)
     int maxw;                    // most elements in one level of one (direction, tile)
-    int wave_solve;              // 1: one wave per element also at p <= 2 (else one lane per element)
+    int wave_solve;              // 0 automatic (one lane per element at p <= 2, one lane per row at
+                                 //   p >= 3); 1 one wave per element; 2 one lane per row at p >= 2
     int s_aniso;
     const void* S;
     const void* Mk;              // [ne][n][n]

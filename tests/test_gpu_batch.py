@@ -129,16 +129,19 @@ def test_batch_given_start_is_resume(ctx):
 
 
 def test_graph_replay_is_bitwise_eager(ctx):
-    """PCG chunks replayed from captured hipGraphs give bitwise the eager
-    results, on repeated solves (several replays of each graph, with eager work
-    and synchronisations between them)."""
+    """PCG chunks replayed from captured hipGraphs (use_graph = 1), and whole
+    outer iterations replayed from captured graphs (use_graph = 2: source,
+    forked sweep launches, moments, closures, right-hand side, PCG start and a
+    chunk of PCG iterations, residual), give bitwise the eager results, on
+    repeated solves (several replays of each graph, with eager work and
+    synchronisations between them)."""
     announce("batch: PCG graph replay vs eager, fp64 and fp32")
     wls = _batch_members()
     probs = [make_pair(L, ctx, wl)[1] for wl in wls]
     batch = L.smm_batch_create(ctx, probs)
     for prec, tol in ((0, 1e-12), (1, 1e-8)):
         ref = None
-        for use_graph in (0, 1, 1, 0, 1):
+        for use_graph in (0, 1, 2, 2, 0, 1, 2):
             o = _opts(prec, tol, delta=prec)
             o.use_graph = use_graph
             rc, infos = L.smm_batch_solve(batch, o)
@@ -194,7 +197,7 @@ def test_two_level_preconditioner(ctx, prec):
     batch = L.smm_batch_create(ctx, [p for _, p in pairs])
     tol = 1e-13 if prec == 0 else 1e-8
     outs, cgs = {}, {}
-    for name, pc, graph in (("bj", 0, 0), ("mg", 1, 0), ("mg_graph", 1, 1)):
+    for name, pc, graph in (("bj", 0, 0), ("mg", 1, 0), ("mg_graph", 1, 1), ("mg_itgraph", 1, 2)):
         o = _opts(prec, tol, delta=prec)
         o.precond = pc
         o.use_graph = graph
@@ -210,6 +213,7 @@ def test_two_level_preconditioner(ctx, prec):
     assert cgs["mg"] < cgs["bj"]
     for k, (pr, p) in enumerate(pairs):
         assert np.array_equal(outs["mg"][k], outs["mg_graph"][k]), k
+        assert np.array_equal(outs["mg"][k], outs["mg_itgraph"][k]), k
         if prec == 0:
             assert rel_l2(outs["mg"][k], outs["bj"][k]) < 1e-11, k
         ref, _ = osmm.solve(pr, tol=1e-13, max_it=200)
@@ -245,4 +249,35 @@ def test_anderson_mixing(ctx, prec):
         ref, _ = osmm.solve(pr, tol=1e-13, max_it=200)
         for depth in (1, 2):
             assert rel_l2(outs[depth][k], ref) < (1e-10 if prec == 0 else 1e-5), (depth, k)
+    L.smm_batch_destroy(batch)
+
+
+def test_outer_iteration_graph_bench_options(ctx):
+    """The options of the benchmark (FP32 delta sweeps, two-level PCG with
+    per-problem adaptive tolerances, Anderson mixing of depth 2) on a mixed
+    batch: the outer iteration replayed from graphs equals the eager solve bit
+    for bit, in iteration counts and fluxes, on two solves in a row."""
+    announce("batch: whole-iteration graphs vs eager, bench options")
+    wls = _batch_members()
+    probs = [make_pair(L, ctx, wl)[1] for wl in wls]
+    batch = L.smm_batch_create(ctx, probs)
+    ref = None
+    for use_graph in (0, 2, 2, 1):
+        o = L.smm_default_opts(precision=1, delta_sweeps=1, outer_tol=1e-8, inner_tol=1e-10, inner_adapt=1e-2,
+                               max_inner=20000, max_outer=100, precond=L.SMM_PRECOND_TWOLEVEL, anderson=2,
+                               use_graph=use_graph)
+        rc, infos = L.smm_batch_solve(batch, o)
+        assert rc == L.SMM_OK
+        outs = []
+        for k, p in enumerate(probs):
+            v = np.zeros(p.n_elem * p.n_node)
+            L.smm_batch_get_outputs(batch, k, varphi=v)
+            outs.append(v)
+        its = [(i["iterations"], i["cg_iterations_total"]) for i in infos]
+        if ref is None:
+            ref = (outs, its)
+        else:
+            assert its == ref[1], (use_graph, its, ref[1])
+            for a, b in zip(outs, ref[0]):
+                assert np.array_equal(a, b)
     L.smm_batch_destroy(batch)

@@ -45,7 +45,8 @@ def _sweep_gpu(p, prec, S, lag=None, inflow=True):
 
 SWEEP_CASES = [
     # (name, workload factory, sweep path: 0 auto, 1 per-element kernel, 2 element-row
-    # kernel, 3 per-element kernel with one wave per element also at p <= 2)
+    # kernel, 3 per-element kernel with one wave per element also at p <= 2,
+    # 4 per-element kernel with one lane per row at every order p >= 2)
     ("plain8_p1_s4", lambda: config_plain(8, 1, 4), 0),
     ("plain8_p1_s4_general", lambda: config_plain(8, 1, 4), 1),
     ("plain8_p1_s4_rowkernel", lambda: config_plain(8, 1, 4), 2),
@@ -61,6 +62,13 @@ SWEEP_CASES = [
     ("plain8_p2_s4_general", lambda: config_plain(8, 2, 4), 1),
     ("plain8_p1_s4_wavesolve", lambda: config_plain(8, 1, 4), 3),
     ("curved3_p4_s4", lambda: config_curved_mms(3, 4, 4), 0),
+    # per-element kernel with one lane per row (Gauss-Jordan): the default at
+    # p >= 3, forced at p = 2; and the wave-per-element form at p = 3, 4
+    ("curved4_p2_s8_rowsolve", lambda: config_curved_mms(4, 2, 8, amplitude=0.09), 4),
+    ("curved5_p3_s6", lambda: config_curved_mms(5, 3, 6, amplitude=0.09), 0),
+    ("curved5_p3_s6_wavesolve", lambda: config_curved_mms(5, 3, 6, amplitude=0.09), 3),
+    ("curved3_p4_s4_wavesolve", lambda: config_curved_mms(3, 4, 4), 3),
+    ("ragged7x3_p4_s12_rowsolve", lambda: _rect(7, 3, 4, 12), 4),
 ]
 
 
