@@ -422,9 +422,14 @@ int smm_batch_apply_sweep(smm_batch* batch, int precision, const double* const* 
  * launches: 0 column-wave (the NB waves of a 64-slot chunk split each
  * element's node columns), 1 element-lane (one wave per chunk, each lane a
  * whole element; anti-diagonals of at most 256 slots, else
+ * SMM_EUNSUPPORTED), 2 and 3 matrix cores (each level a product of the
+ * element operator with the level's inputs, in tiles of 16 elements, 4 or 2
+ * tiles per wave; FP32 sweeps only, FP64 sweeps keep the autotuner's
+ * choice; anti-diagonals of at most 256 or 128 slots, else
  * SMM_EUNSUPPORTED), -1 the autotuner's choice per launch.  Grids are tuned
- * again at the next solve or sweep.  Both shapes apply each element's
- * operator rows in the same order. */
+ * again at the next solve or sweep.  Shapes 0 and 1 apply each element's
+ * operator rows in the same order, and so do shapes 2 and 3 (in another
+ * order: results agree to rounding). */
 int smm_debug_batch_sweep_shape(smm_batch* batch, int shape);
 /* Testing hook: choose the batch's PCG kernels: 1 the type-group kernels
  * (one wave per group of elements sharing their blocks), 0 the per-node

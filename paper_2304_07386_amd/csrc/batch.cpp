@@ -62,9 +62,14 @@ struct Group {
     size_t lds[2] = {0, 0};
     int grid[2] = {0, 0};
     // kernel shape per precision: 0 column-wave (b_sweep_kernel), 1 element-lane
-    // (b_sweep_elem_kernel, one wave of ethreads / 64 per chunk); -1 not tuned
+    // (b_sweep_elem_kernel, one wave of ethreads / 64 per chunk), 2 and 3 matrix
+    // cores (b_sweep_mfma_kernel, FP32 only: 4 and 2 tiles of 16 elements per
+    // wave); -1 not tuned
     int shape[2] = {-1, -1};
     int ethreads = 0;
+    int maxlen = 0;                        // longest anti-diagonal of the group
+    int maxnxy = 0;                        // largest nx + ny of the group
+    long maxwords = 0;                     // largest n_elem n_node (one direction's flux)
     std::vector<int2> tasks;
     int2* d_tasks = nullptr;
     int* d_counter = nullptr;
@@ -479,7 +484,11 @@ int batch_build(smm_batch* B) {
         const Problem& P = B->probs[b]->P;
         const int th = b_sweep_threads(P.nb, P.nx, P.ny);
         if (th > 1024) return fail(c, SMM_EUNSUPPORTED, "anti-diagonal too long for one workgroup");
-        const auto key = std::make_pair(P.nb, th);
+        // problems whose flux exceeds the matrix-core shapes' 32-bit byte
+        // offsets form groups of their own, so that a problem takes the same
+        // kernel family in any batch
+        const int big = (long)P.ne * P.n * (long)sizeof(float) >= (1L << 31) ? 1 : 0;
+        const auto key = std::make_pair(P.nb, th * 2 + big);
         if (!gi.count(key)) {
             gi[key] = (int)B->groups.size();
             B->groups.push_back(Group{});
@@ -488,6 +497,9 @@ int batch_build(smm_batch* B) {
         }
         Group& G = B->groups[gi[key]];
         G.ethreads = th / P.nb;          // one wave per chunk
+        G.maxlen = std::max(G.maxlen, std::min(P.nx, P.ny));
+        G.maxnxy = std::max(G.maxnxy, P.nx + P.ny);
+        G.maxwords = std::max(G.maxwords, (long)P.ne * P.n);
         if (P.nmat != 1) G.multi = true;
         for (int d = 0; d < P.nd; ++d) G.tasks.push_back(make_int2(b, d));
     }
@@ -808,8 +820,22 @@ int batch_build(smm_batch* B) {
 }
 
 // One persistent launch of group G in kernel shape `shape`.
+int mfma_threads(const Group& G, int shape) { return b_sweep_mfma_threads(shape == 2 ? 4 : 2, G.maxlen, G.maxlen); }
+
+// the matrix-core shapes address one direction's flux with 32-bit byte offsets
+// (buffer descriptors) and take at most four waves
+bool mfma_fits(const Group& G, int shape) {
+    return mfma_threads(G, shape) <= 256 && G.maxwords * (long)sizeof(float) < (1L << 31);
+}
+
 hipError_t group_sweep(smm_batch* B, Group& G, bool fp64, int shape, int grid, const CartSweepArgs* args,
                        hipStream_t s) {
+    if (shape >= 2) {
+        if (fp64 || !mfma_fits(G, shape)) return hipErrorNotSupported;
+        const int tpw = shape == 2 ? 4 : 2, threads = mfma_threads(G, shape);
+        return b_sweep_mfma(G.nb, G.multi, tpw, threads, b_sweep_mfma_lds(G.nb, tpw, threads, G.maxnxy), grid,
+                            args, G.d_tasks, (int)G.tasks.size(), G.d_counter, B->d_active, s);
+    }
     if (shape == 1)
         return b_sweep_elem(fp64, G.nb, G.multi, G.ethreads, grid, args, G.d_tasks, (int)G.tasks.size(), G.d_counter,
                             B->d_active, s);
@@ -836,7 +862,7 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow, hipStream_t st) {
         Group& G = B->groups[k];
         hipStream_t s = fork ? B->side[k % nstr] : st;
         int grid = G.grid[f] > 0 ? G.grid[f] : std::min<int>((int)G.tasks.size(), 2 * B->ncu);
-        hipError_t e = group_sweep(B, G, fp64, G.shape[f] == 1 ? 1 : 0, grid, B->d_args[f][inflow ? 1 : 0], s);
+        hipError_t e = group_sweep(B, G, fp64, G.shape[f] > 0 ? G.shape[f] : 0, grid, B->d_args[f][inflow ? 1 : 0], s);
         if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("batched sweep: ") + hipGetErrorString(e));
     }
     if (fork)
@@ -851,9 +877,12 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow) { return batch_sweep(B, fp
 // Autotuner: for every persistent sweep launch, time each candidate kernel
 // shape (column-wave: NB waves per 64-slot chunk, the node columns of an
 // element spread over waves; element-lane: one wave per chunk, each lane a
-// whole element) and each grid (workgroups per CU), and keep the fastest;
-// results are cached per launch shape.  Shape and grid only change
-// scheduling and the order of the FMAs within an element, within rounding.
+// whole element; matrix cores: tiles of 16 elements, 4 or 2 tiles per wave,
+// FP32 only) and each grid (workgroups per CU), and keep the fastest;
+// results are cached per launch shape.  FP32 sweeps choose among the
+// matrix-core shapes whenever these fit, so that a problem's result does not
+// depend on the batch it is in; within a family, shape and grid only change
+// scheduling, not the arithmetic of an element.
 int batch_autotune(smm_batch* B, bool fp64) {
     smm_ctx* c = B->ctx;
     const int f = fp64 ? 1 : 0;
@@ -862,7 +891,8 @@ int batch_autotune(smm_batch* B, bool fp64) {
     HIPCHK(c, hipEventCreate(&e1));
     for (Group& G : B->groups) {
         if (G.grid[f] > 0 && G.shape[f] >= 0) continue;
-        auto key = std::make_tuple(G.nb, (int)G.multi, G.threads, G.lds[f], G.tasks.size(), f);
+        auto key = std::make_tuple(G.nb, (int)G.multi + 2 * (G.maxlen + 1024 * (mfma_fits(G, 2) ? 1 : 0)), G.threads,
+                                   G.lds[f], G.tasks.size(), f);
         auto it = tune_cache().find(key);
         if (it != tune_cache().end() && G.shape[f] < 0) {
             G.grid[f] = it->second.first;
@@ -872,9 +902,15 @@ int batch_autotune(smm_batch* B, bool fp64) {
         int best = 0, best_shape = 0;
         float best_ms = 1e30f;
         const int forced = G.shape[f];   // a shape forced by the testing hook: tune its grid only
-        for (int shape = 0; shape < 2; ++shape) {
+        // FP32 sweeps take the matrix-core shapes whenever they fit (their two
+        // shapes agree bit for bit, so the choice between them, and the grid,
+        // never changes a result); otherwise, and in FP64, the VALU shapes
+        const bool mf = !fp64 && (mfma_fits(G, 2) || mfma_fits(G, 3));
+        for (int shape = 0; shape < 4; ++shape) {
             if (forced >= 0 && shape != forced) continue;
+            if (forced < 0 && mf && shape < 2) continue;
             if (shape == 1 && (G.ethreads < 64 || G.ethreads > 256)) continue;
+            if (shape >= 2 && (fp64 || !mfma_fits(G, shape))) continue;
             const std::vector<int> wpcs = shape == 0 ? std::vector<int>{1, 2, 3, 4, 6}
                                                      : std::vector<int>{2, 4, 8, 12, 16};
             for (int wpc : wpcs) {
@@ -1782,12 +1818,15 @@ int smm_debug_batch_spmv(smm_batch* batch, const double* const* x, double* const
 }
 
 int smm_debug_batch_sweep_shape(smm_batch* batch, int shape) {
-    if (!batch || shape < -1 || shape > 1) return SMM_EINVAL;
+    if (!batch || shape < -1 || shape > 3) return SMM_EINVAL;
     for (Group& G : batch->groups) {
         if (shape == 1 && (G.ethreads < 64 || G.ethreads > 256))
             return fail(batch->ctx, SMM_EUNSUPPORTED, "element-lane sweep: anti-diagonal longer than 256 slots");
+        if (shape >= 2 && !mfma_fits(G, shape))
+            return fail(batch->ctx, SMM_EUNSUPPORTED, "matrix-core sweep: anti-diagonal or mesh too large");
         for (int f = 0; f < 2; ++f) {
-            G.shape[f] = shape;
+            // the matrix-core shapes are FP32 only: FP64 sweeps keep the tuned choice
+            G.shape[f] = shape >= 2 && f == 1 ? -1 : shape;
             G.grid[f] = 0;
         }
     }

@@ -677,13 +677,17 @@ __global__ __launch_bounds__(256) void sweep_lane_general_kernel(GenSweepArgs a)
     }
 }
 
+// value of v in lane src (ds_bpermute), FP32 or FP64
+__device__ __forceinline__ float shfl_t(float v, int src) { return __shfl(v, src); }
+__device__ __forceinline__ double shfl_t(double v, int src) { return __shfl(v, src); }
+
 // The same per-element solve with one lane per row: a wave holds 64 / N
 // elements (N = (p+1)^2 lanes each; 7, 4, 2 elements at p = 2, 3, 4), lane i
 // assembles row i of its element's augmented system [A | b] in registers
 // (volume terms, then the faces through node i in order), and the system is
-// reduced by Gauss-Jordan elimination without pivoting: for each pivot k the
-// lane holding row k publishes it in LDS (double-buffered by the parity of k),
-// every other lane subtracts its multiple, so no back substitution is needed;
+// reduced by Gauss-Jordan elimination without pivoting: for each pivot k every
+// other lane of the element reads row k from the lane holding it (lane
+// shuffles) and subtracts its multiple, so no back substitution is needed;
 // x_i = b_i / A_ii.  The pivot loop is unrolled (register indices are
 // compile-time).  Face data are staged first: the element's lanes compute
 // Omega.n ds and the upwind trace at all 4 nq face points together (one
@@ -701,7 +705,6 @@ __global__ __launch_bounds__(64 * WAVES) void sweep_rows_general_kernel(GenSweep
     const bool lane_ok = eslot < EPW;
     const int es = lane_ok ? eslot : 0;
     const int nq = a.nq, ne = a.ne;
-    __shared__ T prow[WAVES][2][EPW][N + 1];
     __shared__ T fon[WAVES][EPW][4 * GEN_MAXQ];    // Omega.n (weighted ds) at the face points
     __shared__ T fval[WAVES][EPW][4 * GEN_MAXQ];   // upwind trace at the inflow points
     __shared__ T lfs[NB * GEN_MAXQ];               // face basis at the face points
@@ -790,25 +793,17 @@ __global__ __launch_bounds__(64 * WAVES) void sweep_rows_general_kernel(GenSweep
                     }
                 }
             }
-            // Gauss-Jordan elimination, one pivot at a time
+            // Gauss-Jordan elimination, one pivot at a time: the pivot row's
+            // entries come from the lane holding it by lane shuffles
             T diag = T(1);
-            T (*pr)[EPW][N + 1] = prow[wv];
+            const int r0 = es * N;   // lane of row 0 of this lane's element
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                T* row = pr[k & 1][es];
-                if (i == k && lane_ok) {
+                const T piv = shfl_t(A[k], r0 + k);
+                if (i == k) diag = piv;
+                const T m = i == k ? T(0) : A[k] / piv;
 #pragma unroll
-                    for (int j = 0; j <= N; ++j) row[j] = A[j];
-                    diag = A[k];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (i != k) {
-                    const T m = A[k] / row[k];
-#pragma unroll
-                    for (int j = k; j <= N; ++j) A[j] -= m * row[j];
-                }
+                for (int j = k + 1; j <= N; ++j) A[j] -= m * shfl_t(A[j], r0 + k);
             }
             if (act) psi[((long)d * ne + K) * N + i] = A[N] / diag;
             // the face data of the next element group overwrite fon / fval
@@ -2070,6 +2065,395 @@ hipError_t b_sweep(bool fp64, int nb, bool multi, int threads, size_t lds, int g
                             : b_sweep_nb<float, 4>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s);
         case 5: return fp64 ? b_sweep_nb<double, 5>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s)
                             : b_sweep_nb<float, 5>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---- persistent sweep on the matrix cores (FP32) ----------------------------
+// At one level of a (problem, direction) task every element applies the same
+// operator R = [Pm | Px | Py] (N rows; N + 2 NB inputs: its source values, the
+// x-face and the y-face inflow traces), so the level is the dense product
+// D = R X with one column of X per element.  Columns go in tiles of 16
+// elements through v_mfma_f32_16x16x4f32 (A[i][k] from lane i + 16 k, B[k][j]
+// from lane j + 16 k, D[i][j] in lane j + 16 (i / 4), element i % 4): R is the
+// A operand, rows 16 mt + i and inputs 4 t + k zero-padded, held in registers
+// for the whole task (reloaded only when a tile holds another material); lane
+// j + 16 k supplies inputs 4 t + k of element j -- source values loaded two
+// levels ahead, traces read from LDS.  A wave holds TPW tiles (16 TPW slots of
+// the anti-diagonal) and skips the tiles past the level's length, so short
+// anti-diagonals cost 16-column tiles, not 64-lane waves.  Rows 16 mt + 4 k + r
+// of element j (lane j + 16 k) are stored to HBM, and the outflow-face rows to
+// the trace arrays in LDS for the next level.
+// Raw buffer accesses: an offset at or past the descriptor's byte count reads
+// 0 and drops the store, with no memory access, so inactive lanes and tiles
+// need no branch around their loads and stores.  The level loop then issues
+// the same global operations on every path, and the wait counts the compiler
+// inserts stay exact: a level waits for the loads it consumes (issued levels
+// earlier), not for every store and prefetch in flight.
+constexpr unsigned BUF_OOB = 0x80000000u;
+constexpr int BUF_WORD3 = 0x00020000;   // gfx9-family raw buffer descriptor word 3
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, BUF_WORD3);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+// Input k-slots of the matrix-core sweep.  Slot (t, g) -- MFMA step t, lane
+// group g -- holds source value g QS + t of the element while that is below
+// N (so a lane's source values are QS consecutive words: one or two vector
+// loads), and the 2 NB face traces fill the remaining slots in order of t,
+// then g; -1 marks padding.
+template <int NB>
+struct MfmaSlots {
+    static constexpr int N = NB * NB, QS = (N + 3) / 4, NI = N + 2 * NB, KT = (NI + 3) / 4;
+    int q[KT][4];
+};
+template <int NB>
+constexpr MfmaSlots<NB> mfma_slots() {
+    using S = MfmaSlots<NB>;
+    MfmaSlots<NB> s{};
+    int e = 0;
+    for (int t = 0; t < S::KT; ++t)
+        for (int g = 0; g < 4; ++g) {
+            if (t < S::QS && g * S::QS + t < S::N) {
+                s.q[t][g] = g * S::QS + t;
+            } else {
+                s.q[t][g] = e < 2 * NB ? S::N + e : -1;
+                ++e;
+            }
+        }
+    return s;
+}
+
+// QS consecutive words at byte offset off (out of range: zeros), as vector
+// loads.  The vector results are converted whole (bit casts of single vector
+// elements of these loads were lowered to one repeated word by this compiler).
+typedef float v3f __attribute__((ext_vector_type(3)));
+template <int QS>
+__device__ __forceinline__ void buf_ld_run(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned off2, float (&v)[QS]) {
+    if constexpr (QS == 1) {
+        v[0] = buf_ld(r, off);
+    } else if constexpr (QS == 3) {
+        const v3f x = __builtin_bit_cast(v3f, __builtin_amdgcn_raw_buffer_load_b96(r, (int)off, 0, 0));
+        v[0] = x.x, v[1] = x.y, v[2] = x.z;
+    } else if constexpr (QS == 4) {
+        const v4f x = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+        v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+    } else {
+        static_assert(QS == 7, "source runs of 1, 3, 4 or 7 words");
+        // words 0-3 at off, 4-6 at off2 (each range wholly valid or wholly out of range)
+        const v4f x = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+        const v3f y = __builtin_bit_cast(v3f, __builtin_amdgcn_raw_buffer_load_b96(r, (int)off2, 0, 0));
+        v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+        v[4] = y.x, v[5] = y.y, v[6] = y.z;
+    }
+}
+
+// LDS row of one element's staged result: 16 MT words plus 4 (the vector
+// writes of neighbouring slots then start in different banks)
+__host__ __device__ constexpr int mfma_rs(int nb) { return 16 * ((nb * nb + 15) / 16) + 4; }
+
+template <int NB, int TPW, bool MULTI>
+__device__ __forceinline__ void sweep_mfma_task(const CartSweepArgs& a, const int d, float* smem) {
+    constexpr int N = NB * NB;
+    constexpr int NI = N + 2 * NB;      // inputs per element
+    constexpr int KT = (NI + 3) / 4;    // MFMA steps along the inputs
+    constexpr int MT = (N + 15) / 16;   // row tiles
+    constexpr int QS = (N + 3) / 4;     // source values per lane
+    constexpr int TS = lane_ts(NB);
+    constexpr int RW = lane_rw(NB);
+    constexpr int RS = mfma_rs(NB);
+    constexpr int D = TPW * QS * 3 <= 48 ? 3 : 2;   // levels between a source load and its use
+    constexpr MfmaSlots<NB> SL = mfma_slots<NB>();
+    const int nx = a.nx, ny = a.ny, nd = a.nd;
+    const long ne = (long)nx * ny;
+    const int nlev = nx + ny - 1;
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 15, g = lane >> 4;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int base = wv * 16 * TPW;     // first slot of this wave
+    const int nslot = (int)(blockDim.x >> 6) * 16 * TPW;
+    float* stg = smem;                  // [2][nslot][RS] results of a level, by parity and slot
+    float* bxl = stg + 2 * nslot * RS;  // [ny][TS] boundary inflow of the x faces, by grid row
+    float* byl = bxl + ny * TS;         // [nx][TS] boundary inflow of the y faces, by grid column
+    const auto om = as_global(a.omega);
+    const double ox = om[d * 3], oy = om[d * 3 + 1];
+    const bool sx = ox > 0.0, sy = oy > 0.0;
+    const unsigned bytes = (unsigned)(ne * N * sizeof(float));   // < 2^31 (checked by the host)
+    const auto Sr = buf_rsrc(reinterpret_cast<const float*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0), bytes);
+    const auto Pr = buf_rsrc(reinterpret_cast<float*>(a.psi) + (long)d * (a.psi_ld > 0 ? a.psi_ld : ne * N), bytes);
+    const auto Mr = buf_rsrc(a.mat, (unsigned)ne);
+    const auto tab = as_global(reinterpret_cast<const float*>(a.tab));
+    const auto bx = as_global(reinterpret_cast<const float*>(a.bx));
+    const auto by = as_global(reinterpret_cast<const float*>(a.by));
+    for (int t = threadIdx.x; t < ny * NB; t += blockDim.x) {
+        const int jj = t / NB, c = t - jj * NB;
+        bxl[jj * TS + c] = bx ? bx[(long)d * ny * NB + t] : 0.f;
+    }
+    for (int t = threadIdx.x; t < nx * NB; t += blockDim.x) {
+        const int ii = t / NB, c = t - ii * NB;
+        byl[ii * TS + c] = by ? by[(long)d * nx * NB + t] : 0.f;
+    }
+    // input held by this lane's slot of step t
+    auto slot_q = [&](int t) {
+        const int q0 = SL.q[t][0], q1 = SL.q[t][1], q2 = SL.q[t][2], q3 = SL.q[t][3];
+        return g == 0 ? q0 : g == 1 ? q1 : g == 2 ? q2 : q3;
+    };
+    // operator of material mat in A-operand layout; table row (ca, b) holds node ca + NB b
+    float af[MT][KT];
+    auto load_op = [&](int mat) {
+        const long blk = ((long)mat * nd + d) * N;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int row = 16 * mt + j;
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                const int q = slot_q(t);
+                af[mt][t] = (row < N && q >= 0) ? tab[(blk + (row % NB) * NB + row / NB) * RW + q] : 0.f;
+            }
+        }
+    };
+    int amat = 0;
+    load_op(0);
+    // the traces in this lane's slots: node of the upstream element's outflow
+    // face (x face: column aout, y face: row bout) and which face
+    const int aout = sx ? NB - 1 : 0;
+    const int bout = sy ? NB - 1 : 0;
+    // per slot: trow = that node's word in a staged row, tbnd = the trace's word
+    // in the boundary arrays, tisx = x face, tsrc = the slot holds a source value
+    int trow[KT], tbnd[KT];
+    bool tisx[KT], tsrc[KT];
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+        const int e = slot_q(t) - N;   // trace index (negative: source value or padding)
+        tsrc[t] = e < 0;
+        tisx[t] = e < NB;
+        trow[t] = e < 0 ? 0 : e < NB ? aout + NB * e : (e - NB) + NB * bout;
+        tbnd[t] = e < 0 ? 0 : e < NB ? e : e - NB;
+    }
+    auto lev_i0 = [&](int l) { return l - (ny - 1) > 0 ? l - (ny - 1) : 0; };
+    auto lev_len = [&](int l) {
+        const int i1 = l < nx - 1 ? l : nx - 1;
+        return l < nlev ? i1 - lev_i0(l) + 1 : 0;
+    };
+    // element of slot s at level l (quadrant-oriented coordinates ip, l - ip)
+    auto cell = [&](int l, int s, int& ci, int& cj) {
+        const int ip = lev_i0(l) + s, jp = l - ip;
+        ci = sx ? ip : nx - 1 - ip;
+        cj = sy ? jp : ny - 1 - jp;
+    };
+    // this lane's source words g QS .. g QS + QS - 1 of every tile's element at
+    // level l (and its material); lanes past the level or past N read zeros
+    const int c0 = g * QS;
+    const bool run1 = c0 + (QS > 4 ? 4 : QS) <= N;   // first vector of the run inside the element
+    const bool run2 = c0 + QS <= N;                   // second vector (QS = 7)
+    float pre[D][TPW][QS];
+    int pmat[D][TPW];
+    auto fetch = [&](int l, float(&dst)[TPW][QS], int(&dm)[TPW]) {
+        const int len = lev_len(l);
+#pragma unroll
+        for (int tt = 0; tt < TPW; ++tt) {
+            // (both arms of every choice computed first: selects, not branches)
+            const int s = base + 16 * tt + j;
+            const bool act = s < len;
+            int ci, cj;
+            cell(l, s, ci, cj);
+            const unsigned K = (unsigned)(cj * nx + ci);
+            const unsigned w0 = (K * N + c0) * 4u, w1 = w0 + 16u;
+            const unsigned o0 = (act & run1) ? w0 : BUF_OOB;   // & on bools: no short-circuit branch
+            const unsigned o1 = (act & run2) ? w1 : BUF_OOB;
+            buf_ld_run<QS>(Sr, o0, o1, dst[tt]);
+            if constexpr (MULTI) {
+                const int mv = (int)__builtin_amdgcn_raw_buffer_load_b8(Mr, (int)(act ? K : BUF_OOB), 0, 0);
+                dm[tt] = act ? mv : -1;
+            }
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < D; ++u) fetch(u, pre[u], pmat[u]);
+    lds_barrier();
+    for (int m0 = 0; m0 < nlev; m0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int m = m0 + u;
+            if (m >= nlev) break;
+            const float* prv = stg + ((m + 1) & 1) * nslot * RS;   // level m - 1
+            float* cur = stg + (m & 1) * nslot * RS;
+            const int len = lev_len(m);
+            const int i0 = lev_i0(m);
+            // slot of the left (x) neighbour at level m - 1 is s - 1 + dl, of the
+            // lower (y) neighbour s + dl, with dl = i0(m) - i0(m - 1)
+            const int dl = m > 0 ? i0 - lev_i0(m - 1) : 0;
+#pragma unroll
+            for (int tt = 0; tt < TPW; ++tt) {
+                const int s = base + 16 * tt + j;
+                const bool act = s < len;
+                const int ip = i0 + s, jp = m - ip;
+                const int cif = nx - 1 - ip, cjf = ny - 1 - jp;
+                const int ci0 = sx ? ip : cif, cj0 = sy ? jp : cjf;
+                const int ci = act ? ci0 : 0, cj = act ? cj0 : 0;
+                const unsigned K = (unsigned)(cj * nx + ci);
+                v4f acc[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+                if (base + 16 * tt < len) {   // wave-uniform: the tile holds elements of this level
+                    // inputs of element j in this lane's slots; traces from the
+                    // upstream neighbour's staged row or the boundary arrays
+                    // (every lane reads: inactive lanes and source slots read word 0)
+                    const bool xb = ip == 0, yb = jp == 0;
+                    const int pv = (int)(prv - stg) + (s + dl) * RS;   // lower neighbour's row
+                    const int xob = (int)(bxl - stg) + cj * TS, xos = pv - RS;
+                    const int yob = (int)(byl - stg) + ci * TS, yos = pv;
+                    float bv[KT];
+#pragma unroll
+                    for (int t = 0; t < KT; ++t) {
+                        if (SL.q[t][0] >= 0 && SL.q[t][0] < N && SL.q[t][3] >= 0 && SL.q[t][3] < N) {
+                            // every lane: a source value (lane groups 0 and 3 bound the run)
+                            bv[t] = pre[u][tt][t < QS ? t : 0];
+                        } else {
+                            const int oxb = xob + tbnd[t], oxs = xos + trow[t];
+                            const int oyb = yob + tbnd[t], oys = yos + trow[t];
+                            const int ox_ = xb ? oxb : oxs, oy_ = yb ? oyb : oys;
+                            const int o = tisx[t] ? ox_ : oy_;
+                            const int off = (act & !tsrc[t]) ? o : 0;
+                            const float tv = stg[off];
+                            const float sv = t < QS ? pre[u][tt][t < QS ? t : 0] : 0.f;
+                            bv[t] = tsrc[t] ? sv : tv;
+                        }
+                    }
+                    auto apply = [&](v4f(&o)[MT]) {
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) o[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int t = 0; t < KT; ++t)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt)
+                                o[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mt][t], bv[t], o[mt], 0, 0, 0);
+                    };
+                    if constexpr (!MULTI) {
+                        apply(acc);
+                    } else {
+                        // one pass per material present in the tile
+                        const int cm = act ? pmat[u][tt] : -1;
+                        unsigned long long todo = __ballot(act);
+                        while (todo) {
+                            const int lead = __builtin_ctzll(todo);
+                            const int mm = __builtin_amdgcn_readfirstlane(__shfl(cm, lead));
+                            if (mm != amat) {
+                                load_op(mm);
+                                amat = mm;
+                            }
+                            v4f tmp[MT];
+                            apply(tmp);
+                            const bool mine = cm == mm;
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) acc[mt] = mine ? tmp[mt] : acc[mt];
+                            todo &= ~__ballot(mine);
+                        }
+                    }
+                    // the level's results for the next level's traces
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        *reinterpret_cast<v4f*>(cur + s * RS + 16 * mt + 4 * g) = acc[mt];
+                }
+                // rows 16 mt + 4 g .. + 3 of element j: one vector store when
+                // all four are rows of the element, else word by word
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int r0 = 16 * mt + 4 * g;
+                    const unsigned w = (K * N + r0) * 4u;
+                    const unsigned o4 = (act & (r0 + 4 <= N)) ? w : BUF_OOB;
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, acc[mt]), Pr, (int)o4, 0, 0);
+                    const int part = (N - 16 * mt) > 0 && (N - 16 * mt) < 16 ? (N - 16 * mt) % 4 : 0;
+#pragma unroll
+                    for (int r = 0; r < part; ++r) {
+                        const unsigned wr = w + 4u * r;
+                        const unsigned o1 = (act & (r0 + r < N) & (r0 + 4 > N)) ? wr : BUF_OOB;
+                        buf_st(Pr, o1, acc[mt][r]);
+                    }
+                }
+            }
+            fetch(m + D, pre[u], pmat[u]);
+            lds_barrier();
+        }
+    }
+}
+
+template <int NB, int TPW, bool MULTI>
+__global__ __launch_bounds__(256) void b_sweep_mfma_kernel(const CartSweepArgs* __restrict__ args,
+                                                           const int2* __restrict__ tasks, int ntasks,
+                                                           int* __restrict__ counter,
+                                                           const int* __restrict__ active) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int tsk;
+    while (true) {
+        if (threadIdx.x == 0) tsk = atomicAdd(counter, 1);
+        __syncthreads();
+        const int t = tsk;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const int2 tk = tasks[t];
+        if (!active[tk.x]) continue;
+        sweep_mfma_task<NB, TPW, MULTI>(args[tk.x], tk.y, reinterpret_cast<float*>(smem));
+        __syncthreads();
+    }
+}
+
+template <int NB, int TPW, bool MULTI>
+static hipError_t b_sweep_mfma_tm(int threads, size_t lds, int grid, const CartSweepArgs* args, const int2* tasks,
+                                  int ntasks, int* counter, const int* active, hipStream_t s) {
+    auto kfn = b_sweep_mfma_kernel<NB, TPW, MULTI>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(threads), lds, s, args, tasks, ntasks, counter, active);
+    return hipGetLastError();
+}
+
+template <int NB, int TPW>
+static hipError_t b_sweep_mfma_t(bool multi, int threads, size_t lds, int grid, const CartSweepArgs* args,
+                                 const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s) {
+    return multi ? b_sweep_mfma_tm<NB, TPW, true>(threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                 : b_sweep_mfma_tm<NB, TPW, false>(threads, lds, grid, args, tasks, ntasks, counter, active, s);
+}
+
+template <int NB>
+static hipError_t b_sweep_mfma_nb(bool multi, int tpw, int threads, size_t lds, int grid, const CartSweepArgs* args,
+                                  const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s) {
+    return tpw == 4 ? b_sweep_mfma_t<NB, 4>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s)
+                    : b_sweep_mfma_t<NB, 2>(multi, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+}
+
+int b_sweep_mfma_threads(int tpw, int nx, int ny) {
+    const int maxlen = nx < ny ? nx : ny;
+    const int slots = 16 * tpw;
+    return 64 * ((maxlen + slots - 1) / slots);
+}
+
+size_t b_sweep_mfma_lds(int nb, int tpw, int threads, int nxy) {
+    // two levels of staged results (one row per slot of the workgroup), then
+    // the boundary traces of the nx + ny = nxy rows and columns
+    return sizeof(float) * (2 * (size_t)(threads / 64) * 16 * tpw * mfma_rs(nb) + (size_t)nxy * lane_ts(nb));
+}
+
+hipError_t b_sweep_mfma(int nb, bool multi, int tpw, int threads, size_t lds, int grid, const CartSweepArgs* args,
+                        const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s) {
+    // one wave per 16 tpw slots of the longest anti-diagonal, at most four waves
+    if ((tpw != 2 && tpw != 4) || threads < 64 || threads > 256 || threads % 64 != 0 || lds > 160 * 1024)
+        return hipErrorNotSupported;
+    switch (nb) {
+        case 2: return b_sweep_mfma_nb<2>(multi, tpw, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 3: return b_sweep_mfma_nb<3>(multi, tpw, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 4: return b_sweep_mfma_nb<4>(multi, tpw, threads, lds, grid, args, tasks, ntasks, counter, active, s);
+        case 5: return b_sweep_mfma_nb<5>(multi, tpw, threads, lds, grid, args, tasks, ntasks, counter, active, s);
         default: return hipErrorInvalidValue;
     }
 }

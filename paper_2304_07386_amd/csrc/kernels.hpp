@@ -219,6 +219,14 @@ hipError_t b_sweep_elem(bool fp64, int nb, bool multi, int threads, int grid, co
                         const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s);
 hipError_t b_sweep(bool fp64, int nb, bool multi, int threads, size_t lds, int grid, const CartSweepArgs* args,
                    const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s);
+// matrix-core shape of the batched sweep (FP32): tiles of 16 elements of an
+// anti-diagonal, tpw (2 or 4) tiles per wave; threads = b_sweep_mfma_threads of
+// the largest problem (at most 256), lds = b_sweep_mfma_lds with the largest
+// nx + ny of the task list
+hipError_t b_sweep_mfma(int nb, bool multi, int tpw, int threads, size_t lds, int grid, const CartSweepArgs* args,
+                        const int2* tasks, int ntasks, int* counter, const int* active, hipStream_t s);
+int b_sweep_mfma_threads(int tpw, int nx, int ny);
+size_t b_sweep_mfma_lds(int nb, int tpw, int threads, int nxy);
 int b_sweep_threads(int nb, int nx, int ny);
 size_t b_sweep_lds(bool fp64, int nb, bool multi, int nx, int ny);
 hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool first, hipStream_t s);
