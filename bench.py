@@ -478,24 +478,33 @@ def fp32_error(L, ctx, batch, probs, wls, log):
 
 def critical_path(L, ctx, log):
     """Wavefront critical path of single sweeps: levels x per-level time
-    (sweep time / levels), for the channel problem (C3), the curved 32^2
-    problem at p = 4 (C2) and the largest members of the batch (C4), each
-    swept alone."""
+    (sweep time / levels), for the channel problem (C3) and the curved 32^2
+    problem at p = 4 (C2) with their own kernels, and for the largest members
+    of the batch (C4) with the batch's kernel: each member alone in a batch,
+    all its directions at once (one workgroup each, so each level's latency
+    is measured without contention)."""
     from workloads import config_batched_problem, config_channel, config_curved_mms
 
     out = []
-    cases = [("channel 128^2 p=2 S12", config_channel()), ("curved 32^2 p=4 S8", config_curved_mms(32, 4, 8))]
-    for s in (23, 9, 0):
-        wl = config_batched_problem(s)
-        cases.append((f"batch member {s}: {wl.nx}^2 p={wl.p} S{wl.sn}", wl))
-    for name, wl in cases:
+    for name, wl in (("channel 128^2 p=2 S12", config_channel()), ("curved 32^2 p=4 S8", config_curved_mms(32, 4, 8))):
         p = L.problem_from_workload(ctx, wl)
-        lev = L.smm_get_dims(p)["n_levels"]
-        if not lev:
-            lev = wl.nx + wl.ny - 1
+        lev = L.smm_get_dims(p)["n_levels"] or wl.nx + wl.ny - 1
         ms = L.smm_time_sweep(p, L.SMM_FP32_SWEEP, 10)
-        out.append({"case": name, "levels": lev, "sweep_ms": ms, "us_per_level": 1e3 * ms / lev})
+        out.append({"case": name, "kernel": "single-problem sweep", "levels": lev, "sweep_ms": ms,
+                    "us_per_level": 1e3 * ms / lev})
         log(f"critical path {name}: {lev} levels, {ms:.3f} ms, {1e3 * ms / lev:.2f} us/level")
+        L.smm_problem_destroy(p)
+    for s in (23, 9, 0, 19):
+        wl = config_batched_problem(s)
+        name = f"batch member {s}: {wl.nx}^2 p={wl.p} S{wl.sn}"
+        p = L.problem_from_workload(ctx, wl)
+        b = L.smm_batch_create(ctx, [p])
+        lev = wl.nx + wl.ny - 1
+        ms = L.smm_batch_time_sweep(b, L.SMM_FP32_SWEEP, 10)
+        out.append({"case": name, "kernel": "b_sweep_mfma_kernel (batch of one)", "levels": lev, "sweep_ms": ms,
+                    "us_per_level": 1e3 * ms / lev})
+        log(f"critical path {name} (batched kernel): {lev} levels, {ms:.3f} ms, {1e3 * ms / lev:.2f} us/level")
+        L.smm_batch_destroy(b)
         L.smm_problem_destroy(p)
     return out
 
@@ -589,7 +598,8 @@ def main():
     sweep_ms = L.smm_batch_time_kernel(batch, L.SMM_KERNEL_SWEEP_FP32, 5)
     # the sweep against the method's unit roofline: 8 B per elem*angle*DOF in
     # FP32 (psi written by the sweep and read back by the moment contraction)
-    rl_sweep = roofline("b_sweep_kernel", "one batched sweep (the per-order launches b_sweep_kernel<T, NB, ...>) "
+    rl_sweep = roofline("b_sweep_mfma_kernel", "one batched FP32 sweep (the per-order launches "
+                        "b_sweep_mfma_kernel<NB, TPW, MULTI>, each level a product on the matrix cores) "
                         "at 8 B per elem*angle*DOF", 8.0 * units, sweep_ms)
     # the kernel's own bytes: psi written once in FP32 (4 B/unit) + the FP32
     # source read once per element and problem (4/N_dir B/unit)

@@ -96,8 +96,13 @@ def _per_dispatch(rows):
     return [tuple(acc[k]) for k in sorted(order)]
 
 
-FLOP_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32",
-                 "SQ_INSTS_VALU_MUL_F32")
+FLOP_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_FMA_F32",
+                 "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32")
+SWEEP = "b_sweep_mfma_kernel"   # table key of the batched FP32 sweep (any of its launches)
+
+
+def _is_sweep(name):
+    return "b_sweep_" in name
 
 
 def _per_dispatch_counters(rows):
@@ -120,14 +125,16 @@ def issued_flops(dir_flops):
     k1 = [(n, c) for n, c in disp if "b_cg_k1" in n]
     nvar = len({n for n, c in k1})
     spmv = [c for n, c in k1[-SPMV_REPS * nvar:]]
-    sw = [c for n, c in disp if "b_sweep_kernel" in n][-SWEEP_REPS * sweep_launches():]
+    sw = [c for n, c in disp if _is_sweep(n)][-SWEEP_REPS * sweep_launches():]
     mfma = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for c in spmv) * 512.0 / SPMV_REPS
-    f32 = sum(64.0 * (2.0 * c.get("SQ_INSTS_VALU_FMA_F32", 0.0) + c.get("SQ_INSTS_VALU_ADD_F32", 0.0)
-                      + c.get("SQ_INSTS_VALU_MUL_F32", 0.0)) for c in sw) / SWEEP_REPS
-    fma_insts = sum(c.get("SQ_INSTS_VALU_FMA_F32", 0.0) for c in sw) / SWEEP_REPS
+    f32m = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) for c in sw) * 512.0 / SWEEP_REPS
+    f32v = sum(64.0 * (2.0 * c.get("SQ_INSTS_VALU_FMA_F32", 0.0) + c.get("SQ_INSTS_VALU_ADD_F32", 0.0)
+                       + c.get("SQ_INSTS_VALU_MUL_F32", 0.0)) for c in sw) / SWEEP_REPS
     return {"b_cg_k1": {"issued_flops_per_launch": mfma, "kind": "FP64 MFMA (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512)"},
-            "b_sweep_kernel": {"issued_flops_per_launch": f32, "fma_wave_instructions": fma_insts,
-                               "kind": "FP32 VALU lane slots (64 x (2 FMA + ADD + MUL) instructions)"}}
+            SWEEP: {"issued_flops_per_launch": f32m + f32v, "issued_mfma_flops_per_launch": f32m,
+                    "issued_valu_flops_per_launch": f32v,
+                    "kind": "FP32 MFMA (SQ_INSTS_VALU_MFMA_MOPS_F32 x 512) + FP32 VALU lane slots "
+                            "(64 x (2 FMA + ADD + MUL) instructions)"}}
 
 
 def parse(dir_fetch, dir_write, out, dir_flops=None):
@@ -144,12 +151,12 @@ def parse(dir_fetch, dir_write, out, dir_flops=None):
         k1 = [(n, v) for n, v in disp if "b_cg_k1" in n]
         nvar = len({n for n, v in k1})
         spmv = [v for n, v in k1[-SPMV_REPS * nvar:]]
-        sweeps = [v for n, v in disp if "b_sweep_kernel" in n]
+        sweeps = [v for n, v in disp if _is_sweep(n)]
         # the timed sweeps: the last SWEEP_REPS * (launches per sweep) dispatches
         sw = sweeps[-SWEEP_REPS * sweep_launches():]
         res[which] = {"scale": scale, "copy_kib": big,
                       "b_cg_k1": 1024.0 * scale * sum(spmv) / SPMV_REPS,
-                      "b_sweep_kernel": 1024.0 * scale * sum(sw) / SWEEP_REPS}
+                      SWEEP: 1024.0 * scale * sum(sw) / SWEEP_REPS}
         # the other kernels of one PCG iteration, from the short solve (every
         # problem still iterating): the mean dispatch of each kernel, summed
         # over the per-order launches
@@ -163,7 +170,7 @@ def parse(dir_fetch, dir_write, out, dir_flops=None):
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     table = {}
-    for k in ("b_cg_k1", "b_sweep_kernel", "b_cg_k2", "b_cg_k3g", "cgl_kernel"):
+    for k in ("b_cg_k1", SWEEP, "b_cg_k2", "b_cg_k3g", "cgl_kernel"):
         table[k] = {"bytes_per_launch": res["fetch"][k] + res["write"][k],
                     "fetch_bytes": res["fetch"][k], "write_bytes": res["write"][k],
                     "source": "kernels.hip", "sha256": sha}

@@ -2155,9 +2155,14 @@ __device__ __forceinline__ void buf_ld_run(__amdgpu_buffer_rsrc_t r, unsigned of
     }
 }
 
-// LDS row of one element's staged result: 16 MT words plus 4 (the vector
-// writes of neighbouring slots then start in different banks)
+// LDS row of one element's staged result: 16 MT words plus 4 (a row stride
+// that is not a multiple of 32 words keeps the vector writes of neighbouring
+// slots in different banks; rows of only the faces, written word by word,
+// measured slower)
 __host__ __device__ constexpr int mfma_rs(int nb) { return 16 * ((nb * nb + 15) / 16) + 4; }
+// staged rows per level parity: one per slot of the workgroup, plus the x
+// boundary row in front and room for the y boundary row after the level
+__host__ __device__ constexpr int mfma_rows(int nslot) { return nslot + 3; }
 
 template <int NB, int TPW, bool MULTI>
 __device__ __forceinline__ void sweep_mfma_task(const CartSweepArgs& a, const int d, float* smem) {
@@ -2169,7 +2174,11 @@ __device__ __forceinline__ void sweep_mfma_task(const CartSweepArgs& a, const in
     constexpr int TS = lane_ts(NB);
     constexpr int RW = lane_rw(NB);
     constexpr int RS = mfma_rs(NB);
-    constexpr int D = TPW * QS * 3 <= 48 ? 3 : 2;   // levels between a source load and its use
+    // levels between a source load and its use: as many as about 48 registers
+    // of prefetched source allow (2 to 8); the loads of a level then arrive
+    // while the levels before it are swept
+    constexpr int DR = 48 / (TPW * QS);
+    constexpr int D = DR < 2 ? 2 : DR > 8 ? 8 : DR;
     constexpr MfmaSlots<NB> SL = mfma_slots<NB>();
     const int nx = a.nx, ny = a.ny, nd = a.nd;
     const long ne = (long)nx * ny;
@@ -2179,8 +2188,11 @@ __device__ __forceinline__ void sweep_mfma_task(const CartSweepArgs& a, const in
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int base = wv * 16 * TPW;     // first slot of this wave
     const int nslot = (int)(blockDim.x >> 6) * 16 * TPW;
-    float* stg = smem;                  // [2][nslot][RS] results of a level, by parity and slot
-    float* bxl = stg + 2 * nslot * RS;  // [ny][TS] boundary inflow of the x faces, by grid row
+    const int prow = mfma_rows(nslot) * RS;   // words per parity
+    // [2][rows][RS]: level results by parity, slot s in row s + 1; row 0 and
+    // the row after the level hold the next level's boundary inflow
+    float* stg = smem;
+    float* bxl = stg + 2 * prow;        // [ny][TS] boundary inflow of the x faces, by grid row
     float* byl = bxl + ny * TS;         // [nx][TS] boundary inflow of the y faces, by grid column
     const auto om = as_global(a.omega);
     const double ox = om[d * 3], oy = om[d * 3 + 1];
@@ -2221,60 +2233,96 @@ __device__ __forceinline__ void sweep_mfma_task(const CartSweepArgs& a, const in
     };
     int amat = 0;
     load_op(0);
-    // the traces in this lane's slots: node of the upstream element's outflow
-    // face (x face: column aout, y face: row bout) and which face
+    // the traces in this lane's slots: word of the upstream element's staged
+    // row (x face: node column aout of the left neighbour, row s + dl; y face:
+    // node row bout of the lower neighbour, row s + dl + 1); tsrc: the slot
+    // holds a source value
     const int aout = sx ? NB - 1 : 0;
     const int bout = sy ? NB - 1 : 0;
-    // per slot: trow = that node's word in a staged row, tbnd = the trace's word
-    // in the boundary arrays, tisx = x face, tsrc = the slot holds a source value
-    int trow[KT], tbnd[KT];
-    bool tisx[KT], tsrc[KT];
+    int tdel[KT];
+    bool tsrc[KT];
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
         const int e = slot_q(t) - N;   // trace index (negative: source value or padding)
         tsrc[t] = e < 0;
-        tisx[t] = e < NB;
-        trow[t] = e < 0 ? 0 : e < NB ? aout + NB * e : (e - NB) + NB * bout;
-        tbnd[t] = e < 0 ? 0 : e < NB ? e : e - NB;
+        tdel[t] = e < 0 ? 0 : e < NB ? aout + NB * e : RS + (e - NB) + NB * bout;
     }
+    // element of slot s at level l: K = Ku(l) + s dK, Ku(l) that of slot 0
+    const int dK = (sx ? 1 : -1) + (sy ? -nx : nx);
     auto lev_i0 = [&](int l) { return l - (ny - 1) > 0 ? l - (ny - 1) : 0; };
     auto lev_len = [&](int l) {
         const int i1 = l < nx - 1 ? l : nx - 1;
         return l < nlev ? i1 - lev_i0(l) + 1 : 0;
     };
-    // element of slot s at level l (quadrant-oriented coordinates ip, l - ip)
-    auto cell = [&](int l, int s, int& ci, int& cj) {
-        const int ip = lev_i0(l) + s, jp = l - ip;
-        ci = sx ? ip : nx - 1 - ip;
-        cj = sy ? jp : ny - 1 - jp;
+    auto lev_K = [&](int l) {
+        const int ip = lev_i0(l), jp = l - ip;
+        return (sy ? jp : ny - 1 - jp) * nx + (sx ? ip : nx - 1 - ip);
     };
-    // this lane's source words g QS .. g QS + QS - 1 of every tile's element at
-    // level l (and its material); lanes past the level or past N read zeros
+    // per tile of this lane: slot, K offset s dK in bytes of source run / result rows, staged row
+    int sl[TPW], lb[TPW], sb[TPW], sr[TPW];
     const int c0 = g * QS;
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt) {
+        sl[tt] = base + 16 * tt + j;
+        lb[tt] = (sl[tt] * dK * N + c0) * 4;
+        sb[tt] = (sl[tt] * dK * N + 4 * g) * 4;
+        sr[tt] = sl[tt] * RS;
+    }
+    // this lane's source words c0 .. c0 + QS - 1 of every tile's element at
+    // level l (and its material); lanes past the level or past N read zeros
     const bool run1 = c0 + (QS > 4 ? 4 : QS) <= N;   // first vector of the run inside the element
     const bool run2 = c0 + QS <= N;                   // second vector (QS = 7)
     float pre[D][TPW][QS];
     int pmat[D][TPW];
     auto fetch = [&](int l, float(&dst)[TPW][QS], int(&dm)[TPW]) {
         const int len = lev_len(l);
+        const int Ku = lev_K(l);
+        const unsigned kb = (unsigned)Ku * (unsigned)(N * 4);
 #pragma unroll
         for (int tt = 0; tt < TPW; ++tt) {
-            // (both arms of every choice computed first: selects, not branches)
-            const int s = base + 16 * tt + j;
-            const bool act = s < len;
-            int ci, cj;
-            cell(l, s, ci, cj);
-            const unsigned K = (unsigned)(cj * nx + ci);
-            const unsigned w0 = (K * N + c0) * 4u, w1 = w0 + 16u;
-            const unsigned o0 = (act & run1) ? w0 : BUF_OOB;   // & on bools: no short-circuit branch
+            // (both arms of every choice computed first, & on bools: selects, not branches)
+            const bool act = sl[tt] < len;
+            const unsigned w0 = kb + (unsigned)lb[tt], w1 = w0 + 16u;
+            const unsigned o0 = (act & run1) ? w0 : BUF_OOB;
             const unsigned o1 = (act & run2) ? w1 : BUF_OOB;
             buf_ld_run<QS>(Sr, o0, o1, dst[tt]);
             if constexpr (MULTI) {
-                const int mv = (int)__builtin_amdgcn_raw_buffer_load_b8(Mr, (int)(act ? K : BUF_OOB), 0, 0);
+                const unsigned kk = (unsigned)(Ku + sl[tt] * dK);
+                const int mv = (int)__builtin_amdgcn_raw_buffer_load_b8(Mr, (int)(act ? kk : BUF_OOB), 0, 0);
                 dm[tt] = act ? mv : -1;
             }
         }
     };
+    // boundary inflow of level l into the staged buffer level l - 1 leaves it:
+    // the x faces of the element at ip = 0 (l < ny) into row 0, the y faces of
+    // the element at jp = 0 (l < nx) into the row after level l - 1's last
+    // slot; lanes 0 .. 2 NB - 1 of wave 0 read their value early (get) and
+    // store it after the level's own work (put)
+    const int bt = threadIdx.x;
+    auto get_boundary = [&](int l) {
+        const int cj = sy ? l : ny - 1 - l, ci = sx ? l : nx - 1 - l;
+        const int ox_ = cj * TS + bt, oy_ = ny * TS + ci * TS + bt - NB;
+        const bool okx = (bt < NB) & (l < ny), oky = (bt >= NB) & (bt < 2 * NB) & (l < nx);
+        return (okx | oky) ? bxl[okx ? ox_ : oy_] : 0.f;
+    };
+    auto put_boundary = [&](int l, float v) {
+        float* q = stg + ((l + 1) & 1) * prow;
+        const int row = (l > 0 ? lev_len(l - 1) : 0) + 1;
+        if ((bt < NB) & (l < ny)) q[aout + NB * bt] = v;
+        else if ((bt >= NB) & (bt < 2 * NB) & (l < nx)) q[row * RS + (bt - NB) + NB * bout] = v;
+    };
+    const bool one_wave = blockDim.x == 64;   // LDS operations of one wave need no barrier
+    auto level_sync = [&]() {
+        if (one_wave) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            lds_barrier();
+        }
+    };
+    lds_barrier();   // boundary arrays complete
+    put_boundary(0, get_boundary(0));
 #pragma unroll
     for (int u = 0; u < D; ++u) fetch(u, pre[u], pmat[u]);
     lds_barrier();
@@ -2283,50 +2331,34 @@ __device__ __forceinline__ void sweep_mfma_task(const CartSweepArgs& a, const in
         for (int u = 0; u < D; ++u) {
             const int m = m0 + u;
             if (m >= nlev) break;
-            const float* prv = stg + ((m + 1) & 1) * nslot * RS;   // level m - 1
-            float* cur = stg + (m & 1) * nslot * RS;
             const int len = lev_len(m);
             const int i0 = lev_i0(m);
-            // slot of the left (x) neighbour at level m - 1 is s - 1 + dl, of the
-            // lower (y) neighbour s + dl, with dl = i0(m) - i0(m - 1)
+            // neighbours at level m - 1: left (x) in slot s - 1 + dl (row s + dl),
+            // lower (y) in slot s + dl (row s + dl + 1), dl = i0(m) - i0(m - 1)
             const int dl = m > 0 ? i0 - lev_i0(m - 1) : 0;
+            const int pvu = ((m + 1) & 1) * prow + dl * RS;
+            float* cur = stg + (m & 1) * prow;
+            const unsigned kb = (unsigned)lev_K(m) * (unsigned)(N * 4);
+            const float bnext = wv == 0 ? get_boundary(m + 1) : 0.f;
 #pragma unroll
             for (int tt = 0; tt < TPW; ++tt) {
-                const int s = base + 16 * tt + j;
+                const int s = sl[tt];
                 const bool act = s < len;
-                const int ip = i0 + s, jp = m - ip;
-                const int cif = nx - 1 - ip, cjf = ny - 1 - jp;
-                const int ci0 = sx ? ip : cif, cj0 = sy ? jp : cjf;
-                const int ci = act ? ci0 : 0, cj = act ? cj0 : 0;
-                const unsigned K = (unsigned)(cj * nx + ci);
                 v4f acc[MT];
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
                 if (base + 16 * tt < len) {   // wave-uniform: the tile holds elements of this level
-                    // inputs of element j in this lane's slots; traces from the
-                    // upstream neighbour's staged row or the boundary arrays
-                    // (every lane reads: inactive lanes and source slots read word 0)
-                    const bool xb = ip == 0, yb = jp == 0;
-                    const int pv = (int)(prv - stg) + (s + dl) * RS;   // lower neighbour's row
-                    const int xob = (int)(bxl - stg) + cj * TS, xos = pv - RS;
-                    const int yob = (int)(byl - stg) + ci * TS, yos = pv;
+                    const int pv = pvu + sr[tt];
                     float bv[KT];
 #pragma unroll
                     for (int t = 0; t < KT; ++t) {
                         if (SL.q[t][0] >= 0 && SL.q[t][0] < N && SL.q[t][3] >= 0 && SL.q[t][3] < N) {
-                            // every lane: a source value (lane groups 0 and 3 bound the run)
                             bv[t] = pre[u][tt][t < QS ? t : 0];
                         } else {
-                            const int oxb = xob + tbnd[t], oxs = xos + trow[t];
-                            const int oyb = yob + tbnd[t], oys = yos + trow[t];
-                            const int ox_ = xb ? oxb : oxs, oy_ = yb ? oyb : oys;
-                            const int o = tisx[t] ? ox_ : oy_;
-                            const int off = (act & !tsrc[t]) ? o : 0;
-                            const float tv = stg[off];
+                            const float tv = stg[pv + tdel[t]];
                             const float sv = t < QS ? pre[u][tt][t < QS ? t : 0] : 0.f;
                             bv[t] = tsrc[t] ? sv : tv;
                         }
                     }
+
                     auto apply = [&](v4f(&o)[MT]) {
 #pragma unroll
                         for (int mt = 0; mt < MT; ++mt) o[mt] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -2342,6 +2374,8 @@ __device__ __forceinline__ void sweep_mfma_task(const CartSweepArgs& a, const in
                         // one pass per material present in the tile
                         const int cm = act ? pmat[u][tt] : -1;
                         unsigned long long todo = __ballot(act);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
                         while (todo) {
                             const int lead = __builtin_ctzll(todo);
                             const int mm = __builtin_amdgcn_readfirstlane(__shfl(cm, lead));
@@ -2360,27 +2394,33 @@ __device__ __forceinline__ void sweep_mfma_task(const CartSweepArgs& a, const in
                     // the level's results for the next level's traces
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
-                        *reinterpret_cast<v4f*>(cur + s * RS + 16 * mt + 4 * g) = acc[mt];
+                        if (act & (16 * mt + 4 * g < N))
+                            *reinterpret_cast<v4f*>(cur + sr[tt] + RS + 16 * mt + 4 * g) = acc[mt];
+                } else {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) acc[mt] = __builtin_nondeterministic_value(acc[mt]);
                 }
                 // rows 16 mt + 4 g .. + 3 of element j: one vector store when
                 // all four are rows of the element, else word by word
+                const unsigned w = kb + (unsigned)sb[tt];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const int r0 = 16 * mt + 4 * g;
-                    const unsigned w = (K * N + r0) * 4u;
-                    const unsigned o4 = (act & (r0 + 4 <= N)) ? w : BUF_OOB;
+                    const unsigned wm = w + 64u * mt;
+                    const unsigned o4 = (act & (r0 + 4 <= N)) ? wm : BUF_OOB;
                     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, acc[mt]), Pr, (int)o4, 0, 0);
                     const int part = (N - 16 * mt) > 0 && (N - 16 * mt) < 16 ? (N - 16 * mt) % 4 : 0;
 #pragma unroll
                     for (int r = 0; r < part; ++r) {
-                        const unsigned wr = w + 4u * r;
+                        const unsigned wr = wm + 4u * r;
                         const unsigned o1 = (act & (r0 + r < N) & (r0 + 4 > N)) ? wr : BUF_OOB;
                         buf_st(Pr, o1, acc[mt][r]);
                     }
                 }
             }
+            if (wv == 0) put_boundary(m + 1, bnext);
             fetch(m + D, pre[u], pmat[u]);
-            lds_barrier();
+            level_sync();
         }
     }
 }
@@ -2439,9 +2479,10 @@ int b_sweep_mfma_threads(int tpw, int nx, int ny) {
 }
 
 size_t b_sweep_mfma_lds(int nb, int tpw, int threads, int nxy) {
-    // two levels of staged results (one row per slot of the workgroup), then
-    // the boundary traces of the nx + ny = nxy rows and columns
-    return sizeof(float) * (2 * (size_t)(threads / 64) * 16 * tpw * mfma_rs(nb) + (size_t)nxy * lane_ts(nb));
+    // two levels of staged results (rows of the workgroup's slots and the
+    // boundary rows), then the boundary traces of the nx + ny = nxy rows and columns
+    const int nslot = threads / 64 * 16 * tpw;
+    return sizeof(float) * (2 * (size_t)mfma_rows(nslot) * mfma_rs(nb) + (size_t)nxy * lane_ts(nb));
 }
 
 hipError_t b_sweep_mfma(int nb, bool multi, int tpw, int threads, size_t lds, int grid, const CartSweepArgs* args,
