@@ -62,17 +62,11 @@ def run():
 
 
 def sweep_launches(nprob=256):
-    """Persistent launches per batched sweep: one per (order, workgroup size),
-    the workgroup being NB waves per 64-slot chunk of the longest
-    anti-diagonal (as the library groups the tasks)."""
+    """Persistent launches per batched sweep: one per order present (as the
+    library groups the tasks)."""
     sys.path.insert(0, os.path.dirname(HERE))
     from workloads import config_batched_problem
-    groups = set()
-    for s in range(nprob):
-        wl = config_batched_problem(s)
-        nb = wl.p + 1
-        groups.add((nb, 64 * nb * ((min(wl.nx, wl.ny) + 63) // 64)))
-    return len(groups)
+    return len({config_batched_problem(s).p for s in range(nprob)})
 
 
 def _rows(d):

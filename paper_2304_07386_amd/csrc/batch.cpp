@@ -476,27 +476,29 @@ int batch_build(smm_batch* B) {
     pool.req(&B->d_tol, sizeof(double) * np);
     for (int f = 0; f < 2; ++f)
         for (int g = 0; g < 2; ++g) pool.req(&B->d_args[f][g], sizeof(CartSweepArgs) * np);
-    // sweep groups by order and anti-diagonal chunks (64 slots each): the
-    // workgroup of a group is NB waves per chunk of its longest anti-diagonal
+    // sweep groups by order: the workgroup of a group is NB waves per 64-slot
+    // chunk of its longest anti-diagonal (column-wave shape)
     std::map<std::pair<int, int>, int> gi;
     B->groups.clear();
     for (int b = 0; b < np; ++b) {
         const Problem& P = B->probs[b]->P;
         const int th = b_sweep_threads(P.nb, P.nx, P.ny);
         if (th > 1024) return fail(c, SMM_EUNSUPPORTED, "anti-diagonal too long for one workgroup");
-        // problems whose flux exceeds the matrix-core shapes' 32-bit byte
-        // offsets form groups of their own, so that a problem takes the same
-        // kernel family in any batch
+        // one group (one persistent launch) per order: its workgroup is sized
+        // for the group's longest anti-diagonal, shorter problems leave the
+        // extra waves idle.  Problems whose flux exceeds the matrix-core
+        // shapes' 32-bit byte offsets form groups of their own, so that a
+        // problem takes the same kernel family in any batch
         const int big = (long)P.ne * P.n * (long)sizeof(float) >= (1L << 31) ? 1 : 0;
-        const auto key = std::make_pair(P.nb, th * 2 + big);
+        const auto key = std::make_pair(P.nb, big);
         if (!gi.count(key)) {
             gi[key] = (int)B->groups.size();
             B->groups.push_back(Group{});
             B->groups.back().nb = P.nb;
-            B->groups.back().threads = th;
         }
         Group& G = B->groups[gi[key]];
-        G.ethreads = th / P.nb;          // one wave per chunk
+        G.threads = std::max(G.threads, th);
+        G.ethreads = G.threads / P.nb;   // one wave per chunk
         G.maxlen = std::max(G.maxlen, std::min(P.nx, P.ny));
         G.maxnxy = std::max(G.maxnxy, P.nx + P.ny);
         G.maxwords = std::max(G.maxwords, (long)P.ne * P.n);
