@@ -414,10 +414,12 @@ def block_jacobi_sweeps(L, ctx, log):
 def curved_sweeps(L, ctx, log):
     """The sweep on curved meshes (the manufactured problem: 32 x 32 elements
     with an order-p map, S8), where every element and direction is assembled
-    and eliminated by the per-element kernel (one lane per element at p = 2,
-    one wave per element at p = 3, 4): time per sweep, units/s, and
-    the rate against the FP32 vector peak at the assembly and elimination
-    work per DOF (165 / 344 / 664 flops for p = 2 / 3 / 4)."""
+    and eliminated by the per-element kernel (one lane per row of the
+    element's system, sweep_rows_general_kernel, at every order of the
+    whole-mesh sweep): time per sweep, units/s, and the rate against the FP32
+    vector peak at the assembly and elimination work per DOF of an LU solve
+    (165 / 344 / 664 flops for p = 2 / 3 / 4; the kernel's Gauss-Jordan
+    elimination issues more)."""
     from workloads import config_curved_mms
 
     flops = {2: 165.0, 3: 344.0, 4: 664.0}
@@ -433,8 +435,7 @@ def curved_sweeps(L, ctx, log):
             run[name + "_units_per_s"] = units / (ms * 1e-3)
         tf = flops[p] * units / (run["fp32_ms"] * 1e-3) / 1e12
         run["roofline_fp32"] = {"bound": "alu", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
-                                "traffic": None,
-                                "kernel": "sweep_lane_general_kernel" if p <= 2 else "sweep_general_kernel"}
+                                "traffic": None, "kernel": "sweep_rows_general_kernel"}
         log(f"curved 32^2 p={p} S8: FP32 sweep {run['fp32_ms']:.3f} ms, FP64 {run['fp64_ms']:.3f} ms")
         res["runs"].append(run)
         L.smm_problem_destroy(prob)
@@ -526,12 +527,15 @@ def main():
                     help="run only the block Jacobi sweep comparison and print its JSON")
     ap.add_argument("--curved-only", action="store_true",
                     help="run only the curved-mesh sweep timings and print their JSON")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run only the batched FP32 sweep of the 256-problem batch (tuned, then 10 timed "
+                         "sweeps) and print its roofline JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: there is no multi-GPU path (the problems of a batch are "
               "independent and would be split across GPUs by the caller)", file=sys.stderr)
         sys.exit(2)
-    only = args.disc_only or args.tiles_only or args.curved_only
+    only = args.disc_only or args.tiles_only or args.curved_only or args.sweep_only
 
     # the CPU baseline runs first: its worker processes start before this
     # process touches the GPU
@@ -562,6 +566,14 @@ def main():
     probs = [L.problem_from_workload(ctx, wl) for wl in wls]
     batch = L.smm_batch_create(ctx, probs)
     units = L.smm_batch_units(batch)
+    if args.sweep_only:
+        # the source of the sweeps is whatever the batch holds (their time does not depend on it)
+        L.smm_batch_time_kernel(batch, L.SMM_KERNEL_SWEEP_FP32, 2)        # tunes grids and streams
+        ms = L.smm_batch_time_kernel(batch, L.SMM_KERNEL_SWEEP_FP32, 10)
+        rl = roofline("b_sweep_mfma_kernel", "one batched FP32 sweep at 8 B per elem*angle*DOF", 8.0 * units, ms)
+        rl["units_per_s"] = units / (ms * 1e-3)
+        print(json.dumps({"sweep_ms": ms, "units_per_sweep": units, "roofline": rl}))
+        return
     unit_k = np.array([p.n_elem * p.n_node * p.n_dir for p in probs], dtype=float)
     dofs = float(sum(p.n_elem * p.n_node for p in probs))
     log(f"batch of {args.problems} problems: {units:.4g} units per sweep, {dofs:.4g} DOF, "
