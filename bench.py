@@ -330,8 +330,9 @@ def time_to_solution(L, ctx, n: int, log):
 
 def moment_discretisations(L, ctx, log):
     """IP versus CG moment system (Sec. 5.1) on the multi-material channel
-    problem (128 x 128, p = 2, S12, FP32 sweep): wall time to a 1e-8 outer
-    residual from the zero start, and the roofline of the CG product kernel
+    problem (128 x 128, p = 2, S12, FP32 sweep), each with its preconditioners:
+    wall time to a 1e-8 outer residual from the zero start, and the roofline
+    of the CG product kernel
     (FP64 CSR, HBM-bound: 12 B per stored entry, the row pointers, x read
     once and y written once)."""
     import torch
@@ -342,7 +343,9 @@ def moment_discretisations(L, ctx, log):
                   max_inner=20000, max_outer=60, use_graph=1)
     variants = (("ip_two_level", dict(precond=1), "IP, typed path, two-level PCG"),
                 ("ip_block_jacobi", dict(moment_path=1), "IP, per-element path, block-Jacobi PCG"),
-                ("cg_jacobi", dict(discretization=L.SMM_DISC_CG), "CG, per-element path, Jacobi PCG"))
+                ("cg_jacobi", dict(discretization=L.SMM_DISC_CG), "CG, per-element path, Jacobi PCG"),
+                ("cg_two_level", dict(discretization=L.SMM_DISC_CG, precond=1),
+                 "CG, per-element path, two-level PCG (Jacobi + bilinear vertex space, one V-cycle)"))
     res = {"workload": "channel 128x128 p=2 S12 (two materials), FP32 sweep, zero start, outer 1e-8"}
     for name, kw, what in variants:
         p = L.problem_from_workload(ctx, wl)

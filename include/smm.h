@@ -176,9 +176,11 @@ typedef struct {
                             1: always per-element operators */
     int anderson;        /* 0: plain fixed point X <- G(X); 1 or 2: Anderson mixing of the
                             last anderson + 1 iterates (typed path only) */
-    int precond;         /* SMM_PRECOND_BJ: block-Jacobi PCG; SMM_PRECOND_TWOLEVEL: block-Jacobi
-                            plus a continuous Q1 coarse correction on the element vertices,
-                            solved by one vertex multigrid V-cycle (typed path only) */
+    int precond;         /* SMM_PRECOND_BJ: block-Jacobi PCG (Jacobi on the CG system);
+                            SMM_PRECOND_TWOLEVEL: that plus a continuous Q1 coarse correction
+                            on the element vertices, solved by one vertex multigrid V-cycle
+                            (IP: typed path; CG: the continuous system of any structured
+                            mesh, the coarse operator the Galerkin product with it) */
     double inner_adapt;  /* > 0: the moment solve of outer iteration k stops at the
                             relative residual max(inner_tol, inner_adapt * r_{k-1})
                             (r_0 = 1; per problem in a batch), and the solves that
@@ -186,8 +188,9 @@ typedef struct {
                             max(inner_tol, inner_adapt); 0: always inner_tol */
     int discretization;  /* SMM_DISC_IP (default) or SMM_DISC_CG.  SMM_DISC_CG solves the
                             continuous moment system of Sec. 5.1 (one unknown per node of the
-                            (nx p + 1) x (ny p + 1) grid of V_p) by FP64 Jacobi-preconditioned
-                            CG on the per-element path of smm_solve; varphi is returned at the
+                            (nx p + 1) x (ny p + 1) grid of V_p) by FP64 preconditioned CG
+                            (Jacobi, or two-level with SMM_PRECOND_TWOLEVEL) on the per-element
+                            path of smm_solve; varphi is returned at the
                             DG nodes (continuous).  `precond` does not apply; Anderson mixing
                             and batches return SMM_EUNSUPPORTED */
     double kappa_scale;  /* factor on the IP penalty kappa = {(p+1)^2 / (sigma_t h)} (Sec. 6; the

@@ -13,6 +13,7 @@
 #include "../../include/smm_cnn.h"
 #include "api_internal.hpp"
 #include "cg_smm.hpp"
+#include "mg_internal.hpp"
 
 using namespace smm;
 
@@ -701,6 +702,30 @@ static int ensure_cg(smm_problem* pr) {
     if (!P.cg_ready) {
         assemble_cg(P);
         D.cg_dirty = true;
+        D.cg_mg_dirty = true;
+    }
+    if (D.cg_twolevel && D.cg_mg_dirty) {
+        MGHost M;
+        std::string err;
+        const int rc = build_mg_cg(P, M, err);
+        if (rc) return fail(c, rc, "two-level preconditioner of the CG system: " + err);
+        if ((int)M.lev.size() > CGS_MG_MAXLEV || P.p + 1 > 8)
+            return fail(c, SMM_EUNSUPPORTED, "two-level preconditioner of the CG system: too many levels");
+        D.cg_mg_nlev = (int)M.lev.size();
+        for (int l = 0; l < D.cg_mg_nlev; ++l) {
+            const size_t nv = (size_t)M.lev[l].nvx * M.lev[l].nvy;
+            D.cg_mg_nvx[l] = M.lev[l].nvx;
+            D.cg_mg_nvy[l] = M.lev[l].nvy;
+            UP(D.cg_mg_A[l], M.lev[l].A);
+            double** vecs[] = {&D.cg_mg_x[l], &D.cg_mg_t[l], &D.cg_mg_b[l]};
+            for (double** v : vecs) {
+                const int rc2 = alloc(c, D, v, sizeof(double) * nv);
+                if (rc2) return rc2;
+            }
+        }
+        UP(D.cg_mg_cinv, M.cinv);
+        for (size_t k = 0; k < M.gll.size() && k < 8; ++k) D.cg_mg_gll[k] = M.gll[k];
+        D.cg_mg_dirty = false;
     }
     if (D.cg_dirty) {
         UP(D.cg_rowptr, P.cg_rowptr);
@@ -734,7 +759,33 @@ static CgsArgs cgs_args(smm_problem* pr) {
     a.part = D.cg_part; a.scal = D.cg_scal;
     a.vblocks = (P.cg_nc + 255) / 256;
     a.sblocks = (P.cg_nc + CGS_SPMV_ROWS - 1) / CGS_SPMV_ROWS;
+    a.mg = D.cg_twolevel ? 1 : 0;
+    a.nx = P.nx;
+    a.ny = P.ny;
+    a.order = P.p;
+    for (int k = 0; k < 8; ++k) a.gll[k] = D.cg_mg_gll[k];
+    if (a.mg) {
+        a.rv = D.cg_mg_b[0];
+        a.xv = D.cg_mg_nlev > 1 ? D.cg_mg_t[0] : D.cg_mg_x[0];   // the V-cycle ends in t above the coarsest level
+    }
     return a;
+}
+
+static CgsMG cgs_mg(smm_problem* pr) {
+    Dev& D = pr->D;
+    CgsMG m{};
+    m.nlev = D.cg_mg_nlev;
+    for (int l = 0; l < m.nlev; ++l) {
+        m.nvx[l] = D.cg_mg_nvx[l];
+        m.nvy[l] = D.cg_mg_nvy[l];
+        m.A[l] = D.cg_mg_A[l];
+        m.x[l] = D.cg_mg_x[l];
+        m.t[l] = D.cg_mg_t[l];
+        m.b[l] = D.cg_mg_b[l];
+    }
+    m.cinv = D.cg_mg_cinv;
+    m.omega = 2.0 / 3.0;
+    return m;
 }
 
 // The CG moment solve: restrict the DG right-hand side D.b to V_p, start from
@@ -744,9 +795,10 @@ static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its,
     Dev& D = pr->D;
     smm_ctx* c = pr->P.ctx;
     const CgsArgs a = cgs_args(pr);
+    const CgsMG m = cgs_mg(pr);
     HIPCHK(c, cgs_gather(a, D.b, c->stream));
     HIPCHK(c, cgs_pick(a, D.x, c->stream));
-    HIPCHK(c, cgs_start(a, tol, c->stream));
+    HIPCHK(c, cgs_start(a, m, tol, c->stream));
     double sc[8];
     int chunk = 4, done = 0;
     while (true) {
@@ -761,13 +813,14 @@ static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its,
             // capture the chunk of k iterations once on a private stream
             // (kernel nodes only), then replay it on the context's stream
             hipGraphExec_t ge = nullptr;
+            const int key = 2 * k + a.mg;
             for (auto& e : D.cg_graphs)
-                if (e.first == k) ge = e.second;
+                if (e.first == key) ge = e.second;
             if (!ge) {
                 if (!D.cg_cap) HIPCHK(c, hipStreamCreateWithFlags(&D.cg_cap, hipStreamNonBlocking));
                 hipGraph_t g = nullptr;
                 HIPCHK(c, hipStreamBeginCapture(D.cg_cap, hipStreamCaptureModeRelaxed));
-                const hipError_t e1 = cgs_iterations(a, k, D.cg_cap);
+                const hipError_t e1 = cgs_iterations(a, m, k, D.cg_cap);
                 const hipError_t e2 = hipStreamEndCapture(D.cg_cap, &g);
                 if (e1 != hipSuccess || e2 != hipSuccess) {
                     if (g) (void)hipGraphDestroy(g);
@@ -776,11 +829,11 @@ static int cg_moment_solve(smm_problem* pr, double tol, int max_inner, int* its,
                 const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(g);
                 if (e3 != hipSuccess) return fail(c, SMM_EHIP, "CG graph instantiation failed");
-                D.cg_graphs.emplace_back(k, ge);
+                D.cg_graphs.emplace_back(key, ge);
             }
             HIPCHK(c, hipGraphLaunch(ge, c->stream));
         } else {
-            HIPCHK(c, cgs_iterations(a, k, c->stream));
+            HIPCHK(c, cgs_iterations(a, m, k, c->stream));
         }
         chunk = std::min(chunk * 2, 64);
     }
@@ -882,6 +935,9 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     if (o.discretization != SMM_DISC_IP && o.discretization != SMM_DISC_CG)
         return fail(c, SMM_EINVAL, "smm_solve: discretization must be SMM_DISC_IP or SMM_DISC_CG");
     const bool cgdisc = o.discretization == SMM_DISC_CG;
+    if (cgdisc && o.precond != SMM_PRECOND_BJ && o.precond != SMM_PRECOND_TWOLEVEL)
+        return fail(c, SMM_EINVAL, "smm_solve: unknown preconditioner");
+    if (cgdisc) D.cg_twolevel = o.precond == SMM_PRECOND_TWOLEVEL;
     if (cgdisc && P.general)
         return fail(c, SMM_EUNSUPPORTED, "smm_solve: the CG moment system needs a structured mesh");
     if (cgdisc && o.anderson != 0)

@@ -61,7 +61,15 @@ struct Dev {
            *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr, *cg_part = nullptr, *cg_scal = nullptr;
     bool cg_dirty = true;   // host CG system rebuilt since the last upload
     hipStream_t cg_cap = nullptr;                 // private stream for graph capture
-    std::vector<std::pair<int, hipGraphExec_t>> cg_graphs;  // captured chunks of k iterations
+    std::vector<std::pair<int, hipGraphExec_t>> cg_graphs;  // captured chunks: key 2 k + two-level
+    // two-level preconditioner of the CG system (the vertex multigrid levels)
+    bool cg_twolevel = false;   // chosen by the solve options
+    bool cg_mg_dirty = true;    // CG system rebuilt since the hierarchy was built
+    int cg_mg_nlev = 0;
+    int cg_mg_nvx[12] = {}, cg_mg_nvy[12] = {};
+    double *cg_mg_A[12] = {}, *cg_mg_x[12] = {}, *cg_mg_t[12] = {}, *cg_mg_b[12] = {};
+    double* cg_mg_cinv = nullptr;
+    double cg_mg_gll[8] = {};
     bool have_outputs = false;
     bool last_typed = false;       // last solve ran on the typed (batched) path
     bool gen_sweep_built = false;  // per-element sweep data uploaded

@@ -76,6 +76,10 @@ bool invert(std::vector<double> a, int n, std::vector<double>& inv) {
 
 int mg_coarse_count(int nf) { return coarse_count(nf); }
 
+// Level 0 from the 5 x 5 vertex windows W[v][25] of the Galerkin product, then
+// the coarser levels and the dense inverse of the coarsest one.
+static int finish_mg(MGHost& M, int vx, int vy, const std::vector<double>& W, std::string& err);
+
 int build_mg(const Problem& P, MGHost& M, std::string& err) {
     const int nb = P.nb, n = P.n, nx = P.nx, ny = P.ny;
     std::vector<double> x1;
@@ -130,6 +134,52 @@ int build_mg(const Problem& P, MGHost& M, std::string& err) {
                 for (int w = 0; w < 4; ++w) add(gvert(K, v), gvert(N, w), T[v * 4 + w]);
         }
     }
+    return finish_mg(M, vx, vy, W, err);
+}
+
+int build_mg_cg(const Problem& P, MGHost& M, std::string& err) {
+    // the continuous system has no face terms: each element couples only its
+    // own four vertices, through P_loc^T A_K P_loc of its volume and boundary
+    // block (the block the continuous assembly sums)
+    const int nb = P.nb, n = P.n, nx = P.nx, ny = P.ny;
+    std::vector<double> x1;
+    gauss_lobatto01(P.p, x1);
+    M.gll = x1;
+    std::vector<double> Ploc((size_t)n * 4);
+    for (int b = 0; b < nb; ++b)
+        for (int a = 0; a < nb; ++a)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx)
+                    Ploc[(size_t)(a + nb * b) * 4 + cx + 2 * cy] =
+                        (cx ? x1[a] : 1.0 - x1[a]) * (cy ? x1[b] : 1.0 - x1[b]);
+    const int vx = nx + 1, vy = ny + 1;
+    std::vector<double> W((size_t)vx * vy * 25, 0.0);
+    std::vector<double> blk((size_t)n * n);
+    for (int K = 0; K < P.ne; ++K) {
+        std::fill(blk.begin(), blk.end(), 0.0);
+        add_volume_block(P, K, blk.data());
+        for (int f = 0; f < 4; ++f)
+            if (P.nbr[K * 4 + f] < 0) add_boundary_block(P, K, f, blk.data());
+        const int ex = K % nx, ey = K / nx;
+        for (int v = 0; v < 4; ++v)
+            for (int w = 0; w < 4; ++w) {
+                double s = 0;
+                for (int i = 0; i < n; ++i) {
+                    const double pi = Ploc[(size_t)i * 4 + v];
+                    if (pi == 0) continue;
+                    double t = 0;
+                    for (int j = 0; j < n; ++j) t += blk[(size_t)i * n + j] * Ploc[(size_t)j * 4 + w];
+                    s += pi * t;
+                }
+                const int iv = (ey + (v >> 1)) * vx + ex + (v & 1);
+                const int dx = (w & 1) - (v & 1), dy = (w >> 1) - (v >> 1);
+                W[(size_t)iv * 25 + (dy + 2) * 5 + (dx + 2)] += s;
+            }
+    }
+    return finish_mg(M, vx, vy, W, err);
+}
+
+static int finish_mg(MGHost& M, int vx, int vy, const std::vector<double>& W, std::string& err) {
     MGLevelHost L0;
     L0.nvx = vx;
     L0.nvy = vy;

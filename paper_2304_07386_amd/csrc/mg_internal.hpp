@@ -25,6 +25,9 @@ struct MGHost {
 };
 
 int build_mg(const Problem& P, MGHost& M, std::string& err);
+// the same hierarchy for the continuous (CG) moment system: level 0 is the
+// Galerkin product of the bilinear vertex space with A_c
+int build_mg_cg(const Problem& P, MGHost& M, std::string& err);
 int mg_coarse_count(int nf);
 
 }  // namespace smm

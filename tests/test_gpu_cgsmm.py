@@ -154,3 +154,47 @@ def test_cg_graph_replay_is_bitwise_eager(ctx):
         assert np.array_equal(got, ref), rep
         L.smm_solve(p, o_eager)
         assert np.array_equal(L.smm_get_outputs_host(p)["varphi"], ref), rep
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_cg_twolevel_fixed_outer_iterations_fp64(ctx, case):
+    """The two-level preconditioner (Jacobi plus the bilinear vertex space,
+    one V-cycle) in the CG moment solve: with inner solves to 1e-15 the
+    outer iterates are the oracle's CG iterates to 1e-12.  A preconditioner
+    that were not symmetric positive definite would stall short of 1e-15."""
+    K = 4
+    announce(f"CG SMM two-level {K} outer iterations fp64 {case}")
+    pr, p = _pair(ctx, CASES[case]())
+    ref, _ = osmm.solve(pr, tol=0.0, max_it=K)
+    rc, info = L.smm_solve(p, _opts(precision=L.SMM_FP64, outer_tol=0.0, max_outer=K, inner_tol=1e-15,
+                                    max_inner=20000, precond=L.SMM_PRECOND_TWOLEVEL), raise_on_noconv=False)
+    assert rc == L.SMM_ENOCONV and info["iterations"] == K
+    got = L.smm_get_outputs_host(p)["varphi"]
+    assert rel_l2(got, ref) < 1e-12, rel_l2(got, ref)
+
+
+@pytest.mark.parametrize("wl_fn", [lambda: config_channel(n=32, p=2, sn=4, side=1.3),
+                                   lambda: config_curved_mms(16, 3, 4),
+                                   lambda: config_plain(16, 4, 4)])
+def test_cg_twolevel_fewer_iterations_same_answer(ctx, wl_fn):
+    """Converged CG solves with the Jacobi and the two-level preconditioner
+    reach the same flux (1e-10) and the oracle's converged CG flux (1e-10);
+    the two-level solve needs at most a quarter of the PCG iterations; its
+    graph-replayed chunks give bitwise the eager result."""
+    wl = wl_fn()
+    announce(f"CG SMM two-level vs Jacobi converged {wl.name} {wl.nx}^2 p={wl.p}")
+    pr, p = _pair(ctx, wl)
+    ref, _ = osmm.solve(pr, tol=1e-13, max_it=300)
+    out = {}
+    for name, pc, graph in (("jacobi", L.SMM_PRECOND_BJ, 1), ("twolevel", L.SMM_PRECOND_TWOLEVEL, 1),
+                            ("twolevel_eager", L.SMM_PRECOND_TWOLEVEL, 0)):
+        rc, info = L.smm_solve(p, _opts(precision=L.SMM_FP64, outer_tol=1e-12, inner_tol=1e-13, max_inner=50000,
+                                        max_outer=300, precond=pc, use_graph=graph))
+        assert rc == L.SMM_OK
+        out[name] = (L.smm_get_outputs_host(p)["varphi"], info["cg_iterations_total"], info["iterations"])
+    vj, itj, oj = out["jacobi"]
+    vt, itt, ot = out["twolevel"]
+    print(f"PCG iterations: Jacobi {itj} ({oj} outer), two-level {itt} ({ot} outer)", flush=True)
+    assert rel_l2(vt, vj) < 1e-10 and rel_l2(vt, ref) < 1e-10, (rel_l2(vt, vj), rel_l2(vt, ref))
+    assert itt * 4 <= itj, (itt, itj)
+    assert np.array_equal(out["twolevel_eager"][0], vt) and out["twolevel_eager"][1] == itt
