@@ -352,6 +352,13 @@ int smm_debug_sweep_graph(smm_problem* prob, int* level, unsigned char* upstream
  * values of a continuous vector c are c[map[t]]).  All arrays are host memory
  * owned by the caller. */
 int smm_debug_cg_system(smm_problem* prob, int* nc, int* nnz, int* rowptr, int* col, double* val, int* map);
+/* Host-only inspection of the two-level preconditioner of the CG moment
+ * system: the 9-point stencil [9][nvx*nvy] of multigrid level `level`, laid
+ * out as smm_debug_mg_level's (level 0: the Galerkin operator P1^T A_c P1 of
+ * the bilinear space on the element vertices, P1 its interpolation at the
+ * continuous nodes).  A9 may be NULL to query the grid size.  SMM_EINVAL for
+ * a level beyond the coarsest, SMM_EUNSUPPORTED on an unstructured mesh. */
+int smm_debug_cg_mg_level(smm_problem* prob, int level, double* A9, int* nvx, int* nvy);
 /* y = A_c x with the device product kernel of the CG moment solve; x and y are
  * host arrays of nc doubles (nc from smm_debug_cg_system). */
 int smm_debug_cg_spmv(smm_problem* prob, const double* x, double* y);

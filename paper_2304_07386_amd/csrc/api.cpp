@@ -1218,6 +1218,22 @@ int smm_debug_cg_system(smm_problem* prob, int* nc, int* nnz, int* rowptr, int* 
     return SMM_OK;
 }
 
+int smm_debug_cg_mg_level(smm_problem* prob, int level, double* A9, int* nvx, int* nvy) {
+    if (!prob || level < 0 || !nvx || !nvy) return SMM_EINVAL;
+    if (prob->P.general) return fail(prob->P.ctx, SMM_EUNSUPPORTED, "the CG moment system needs a structured mesh");
+    int rc = ensure_host(prob);
+    if (rc) return rc;
+    MGHost M;
+    std::string err;
+    if ((rc = build_mg_cg(prob->P, M, err))) return fail(prob->P.ctx, rc, err);
+    if (level >= (int)M.lev.size()) return fail(prob->P.ctx, SMM_EINVAL, "level beyond the coarsest");
+    const MGLevelHost& L = M.lev[level];
+    *nvx = L.nvx;
+    *nvy = L.nvy;
+    if (A9) std::copy(L.A.begin(), L.A.end(), A9);
+    return SMM_OK;
+}
+
 int smm_debug_cg_spmv(smm_problem* prob, const double* x, double* y) {
     if (!prob || !x || !y) return SMM_EINVAL;
     int rc = ensure_device(prob, true, per_element_forced(prob->D));

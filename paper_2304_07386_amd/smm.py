@@ -36,7 +36,7 @@ EXPORTED = [
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
     "smm_batch_history", "smm_debug_mg_level", "smm_debug_batch_precond", "smm_debug_batch_spmv",
     "smm_debug_batch_grouped", "smm_debug_sweep_graph", "smm_batch_apply_sweep", "smm_apply_G_noalloc", "smm_solve_history",
-    "smm_debug_batch_sweep_shape",
+    "smm_debug_batch_sweep_shape", "smm_debug_cg_mg_level",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
@@ -149,6 +149,7 @@ def load_library(path: str = LIB_PATH):
         "smm_batch_time_kernel": (ip, [vp, ip, ip, dp]),
         "smm_batch_history": (ip, [vp, ip, ip, vp, vp, C.POINTER(ip)]),
         "smm_debug_mg_level": (ip, [vp, ip, vp, C.POINTER(ip), C.POINTER(ip)]),
+        "smm_debug_cg_mg_level": (ip, [vp, ip, vp, C.POINTER(ip), C.POINTER(ip)]),
         "smm_debug_batch_precond": (ip, [vp, ip, C.POINTER(vp), C.POINTER(vp)]),
         "smm_debug_batch_spmv": (ip, [vp, C.POINTER(vp), C.POINTER(vp)]),
         "smm_debug_batch_grouped": (ip, [vp, ip]),
@@ -638,6 +639,16 @@ def smm_debug_mg_level(prob, level: int):
     _check(lib.smm_debug_mg_level(prob.handle, level, _ptr(A), C.byref(nx), C.byref(ny)), prob.ctx)
     return A, nx.value, ny.value
 
+
+def smm_debug_cg_mg_level(prob, level: int):
+    """9-point stencil [9][nvy*nvx] of a multigrid level of the CG system's
+    two-level preconditioner."""
+    nx, ny = C.c_int(), C.c_int()
+    lib = load_library()
+    _check(lib.smm_debug_cg_mg_level(prob.handle, level, None, C.byref(nx), C.byref(ny)), prob.ctx)
+    A = np.zeros((9, nx.value * ny.value))
+    _check(lib.smm_debug_cg_mg_level(prob.handle, level, _ptr(A), C.byref(nx), C.byref(ny)), prob.ctx)
+    return A, nx.value, ny.value
 
 class Cnn:
     def __init__(self, ctx, handle, channels, height, width, max_batch):

@@ -90,3 +90,39 @@ def test_galerkin_levels(hctx, wl):
         D1 = _stencil_dense(A9b, cx, cy)
         assert np.abs(D1 - A1ref).max() < 1e-12 * scale
         assert np.linalg.eigvalsh(D1).min() > 0
+
+
+@pytest.mark.parametrize("k", range(4))
+def test_cg_galerkin_levels(hctx, k):
+    """The CG system's coarse operator is P1^T A_c P1 with A_c the oracle's
+    continuous moment matrix (Sec. 5.1) and P1 the bilinear vertex
+    interpolation at its continuous nodes, obtained here from the DG-node
+    interpolation P0 = P_c P1 (an interpolated bilinear function is
+    continuous, so the least-squares solve is exact)."""
+    from oracle import smm as osmm
+    from workloads import config_channel, config_curved_mms
+    wl = [config_plain(5, 2, 4), config_blobs(20003, n=6, p=3, sn=4), config_curved_mms(n=4, p=2, sn=4),
+          config_channel(n=7, p=2, sn=4, side=1.3)][k]
+    pr = osmm.make_problem(wl, disc="cg")
+    Po = osmm.cg_space(pr.mesh)
+    Po = Po.toarray() if hasattr(Po, "toarray") else np.asarray(Po)
+    Ao = osmm.cg_matrix(pr)
+    Ao = Ao.toarray() if hasattr(Ao, "toarray") else np.asarray(Ao)
+    P0 = _p0(wl.nx, wl.ny, wl.p)
+    P1 = np.linalg.solve(Po.T @ Po, Po.T @ P0)
+    assert np.abs(Po @ P1 - P0).max() < 1e-13
+    Ac = P1.T @ Ao @ P1
+    p = L.problem_from_workload(hctx, wl, q=pr.q, psibar=pr.psibar)
+    A9, vx, vy = L.smm_debug_cg_mg_level(p, 0)
+    assert (vx, vy) == (wl.nx + 1, wl.ny + 1)
+    D0 = _stencil_dense(A9, vx, vy)
+    scale = np.abs(Ac).max()
+    assert np.abs(D0 - Ac).max() < 1e-12 * scale
+    assert np.linalg.eigvalsh(D0).min() > 0
+    if max(vx, vy) > 3:
+        P1c = np.kron(_p1d(vy), _p1d(vx))
+        A9b, cx, cy = L.smm_debug_cg_mg_level(p, 1)
+        D1 = _stencil_dense(A9b, cx, cy)
+        assert np.abs(D1 - P1c.T @ D0 @ P1c).max() < 1e-12 * scale
+    with pytest.raises(L.SmmError):
+        L.smm_debug_cg_mg_level(p, 99)
