@@ -327,7 +327,10 @@ int smm_apply_G(smm_problem* prob, int precision, const double* varphi_in, doubl
  * device shares that device's array, whose contents are whatever the last
  * call left (each buffer is written before it is read): calls that overlap
  * on one device, from any context or stream, race.  smm_get_outputs is not
- * changed by this call. */
+ * changed by this call.  On curved meshes the sweep uses the stored element
+ * operators of that precision when their memory exists (it is then refilled
+ * after a change of materials, which allocates nothing), else it assembles
+ * each element's system. */
 int smm_apply_G_noalloc(smm_problem* prob, int precision, const double* varphi_in, double* varphi_out,
                         double inner_tol, int max_inner);
 
@@ -367,15 +370,20 @@ int smm_debug_cg_spmv(smm_problem* prob, const double* x, double* y);
 int smm_time_cg_spmv(smm_problem* prob, int reps, double* ms_avg);
 
 /* Sweep kernel selection: 0 = automatic (tabulated operators on uniform
- * Cartesian meshes, otherwise per-element assembly and elimination: one lane
- * per row of the element's system with Gauss-Jordan elimination for p >= 3,
- * and for p = 2 unless the levels are wide and spread over many workgroups;
- * otherwise one lane per element); 1 = always the per-element kernel
- * (solve form as in 0); 2 = on Cartesian meshes, the element-row kernel
- * instead of the column-per-thread one; 3 = the per-element kernel with one
- * wave per element at every order; 4 = the per-element kernel with one lane
- * per row at every order p >= 2.  2, 3 and 4 are for cross-checking the
- * kernels against each other.  Returns SMM_EINVAL outside 0..4. */
+ * Cartesian meshes; otherwise the per-element sweep with stored element
+ * operators: the inverse of each (element, direction) left-hand side and its
+ * inflow-face operators, built in parallel on first use after a change of
+ * materials and kept in device memory, n_dir * n_elem * (n_node^2 +
+ * 4 (p+1) n_node) values of the sweep type; where those would take more than
+ * a quarter of the free device memory, the form of path 5); 1 = always the
+ * per-element sweep (form as in 0); 2 = on Cartesian meshes, the element-row
+ * kernel instead of the column-per-thread one; 3 = the per-element kernel
+ * assembling and eliminating with one wave per element at every order; 4 =
+ * the same with one lane per row at every order p >= 2; 5 = the same with one
+ * lane per row for p >= 3, and for p = 2 unless the levels are wide and spread
+ * over many workgroups, otherwise one lane per element.  2 to 5 are for
+ * cross-checking the kernels against each other.  Returns SMM_EINVAL outside
+ * 0..5. */
 int smm_set_sweep_path(smm_problem* prob, int path);
 
 /* Parallel block Jacobi sweep (Sec. 6.5, weak scaling): the element grid is

@@ -389,14 +389,15 @@ int smm_set_sweep_tiles(smm_problem* prob, int tile_nx, int tile_ny) {
     return SMM_OK;
 }
 
-// sweep paths 1 and 3 force the per-element kernel (3 also its wave-wide solve)
+// sweep paths 1, 3, 4 and 5 force the per-element kernel (3, 4 and 5 also
+// its assembling forms)
 static bool per_element_forced(const Dev& D) {
-    return D.force_general == 1 || D.force_general == 3 || D.force_general == 4;
+    return D.force_general == 1 || D.force_general >= 3;
 }
 
 int smm_set_sweep_path(smm_problem* prob, int force_general) {
     if (!prob) return SMM_EINVAL;
-    if (force_general < 0 || force_general > 4) return SMM_EINVAL;
+    if (force_general < 0 || force_general > 5) return SMM_EINVAL;
     prob->D.force_general = force_general;
     return SMM_OK;
 }
@@ -592,6 +593,7 @@ static int ensure_device(smm_problem* pr, bool gen_moment, bool gen_sweep) {
         }
         D.tables_dirty = false;
         D.gen_dirty = true;
+        D.inv_ready[0] = D.inv_ready[1] = false;   // the element operators hold sigma_t
     }
     if (D.src_dirty) {
         UP(D.q, P.q);
@@ -628,6 +630,65 @@ static int ensure_device(smm_problem* pr, bool gen_moment, bool gen_sweep) {
 // ---------------------------------------------------------------------------
 // kernels of one outer iteration
 // ---------------------------------------------------------------------------
+// arguments of the per-element sweep with the tables of one precision
+static GenSweepArgs gen_args(smm_problem* pr, bool fp64) {
+    Problem& P = pr->P;
+    Dev& D = pr->D;
+    GenSweepArgs a{};
+    a.ne = P.ne; a.nd = P.nd; a.nb = P.nb; a.nq = P.nq; a.nbf = P.nbf; a.nlev = P.nlev_max;
+    a.ntiles = P.ntiles;
+    a.maxw = P.lev_wmax;
+    a.Mk = fp64 ? D.Mk64 : D.Mk32;
+    a.Gx = fp64 ? D.Gx64 : D.Gx32;
+    a.Gy = fp64 ? D.Gy64 : D.Gy32;
+    a.nds = fp64 ? D.nds64 : D.nds32;
+    a.Lf = fp64 ? D.Lf64 : D.Lf32;
+    a.sigma_t = fp64 ? D.st64 : D.st32;
+    a.nbr = D.nbr;
+    a.nbr_face = P.general ? D.nbr_face : nullptr;
+    a.bface_of = D.bface_of;
+    a.upflag = D.upflag;
+    a.lev_ptr = D.lev_ptr;
+    a.lev_elem = D.lev_elem;
+    a.omega = D.omega;
+    return a;
+}
+
+// Stored element operators of the per-element sweep in one precision: built
+// from the FP64 tables on first use after a change of sigma_t.  *use stays
+// false (the sweep then assembles and eliminates per element) when they would
+// take more than a quarter of the free device memory, or inside the
+// no-allocation entry point before their memory exists.
+static int ensure_inv(smm_problem* pr, bool fp64, bool* use) {
+    Problem& P = pr->P;
+    Dev& D = pr->D;
+    smm_ctx* c = P.ctx;
+    const int k = fp64 ? 1 : 0;
+    *use = false;
+    if (D.inv_ready[k]) {
+        *use = true;
+        return SMM_OK;
+    }
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    const size_t pairs = (size_t)P.nd * P.ne;
+    const size_t bytes_A = es * pairs * P.n * P.n, bytes_G = es * pairs * 4 * P.nb * P.n;
+    if (!D.inv_A[k]) {
+        if (D.noalloc_active) return SMM_OK;
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess || bytes_A + bytes_G + pairs > fr / 4) return SMM_OK;
+        int rc = alloc(c, D, &D.inv_A[k], bytes_A);
+        if (!rc) rc = alloc(c, D, &D.inv_G[k], bytes_G);
+        if (!rc && !D.inv_mask) rc = alloc(c, D, &D.inv_mask, pairs);
+        if (rc) return rc;
+    }
+    const GenSweepArgs a = gen_args(pr, true);
+    const hipError_t e = launch_gen_inv_setup(fp64, a, D.inv_A[k], D.inv_G[k], D.inv_mask, c->stream);
+    if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("element operator set-up: ") + hipGetErrorString(e));
+    D.inv_ready[k] = true;
+    *use = true;
+    return SMM_OK;
+}
+
 static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, const void* psi_lag, void* psi_out,
                      bool with_inflow) {
     Problem& P = pr->P;
@@ -650,29 +711,24 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
         a.variant = D.force_general == 2 ? 1 : 0;
         e = launch_sweep_cart(fp64, a, c->stream);
     } else {
-        GenSweepArgs a{};
-        a.ne = P.ne; a.nd = P.nd; a.nb = P.nb; a.nq = P.nq; a.nbf = P.nbf; a.nlev = P.nlev_max;
-        a.ntiles = P.ntiles;
-        a.maxw = P.lev_wmax;
+        GenSweepArgs a = gen_args(pr, fp64);
         a.wave_solve = D.force_general == 3 ? 1 : (D.force_general == 4 ? 2 : 0);
         a.s_aniso = s_aniso;
         a.S = S;
-        a.Mk = fp64 ? D.Mk64 : D.Mk32;
-        a.Gx = fp64 ? D.Gx64 : D.Gx32;
-        a.Gy = fp64 ? D.Gy64 : D.Gy32;
-        a.nds = fp64 ? D.nds64 : D.nds32;
-        a.Lf = fp64 ? D.Lf64 : D.Lf32;
-        a.sigma_t = fp64 ? D.st64 : D.st32;
-        a.nbr = D.nbr;
-        a.nbr_face = P.general ? D.nbr_face : nullptr;
-        a.bface_of = D.bface_of;
-        a.upflag = D.upflag;
-        a.lev_ptr = D.lev_ptr;
-        a.lev_elem = D.lev_elem;
-        a.omega = D.omega;
         a.psibar = with_inflow && P.inflow_layout != SMM_INFLOW_VACUUM ? (fp64 ? D.pbar64 : D.pbar32) : nullptr;
         a.psi_lag = psi_lag;
         a.psi = psi_out;
+        if (D.force_general <= 1) {
+            bool use = false;
+            const int rc = ensure_inv(pr, fp64, &use);
+            if (rc) return rc;
+            if (use) {
+                const int k = fp64 ? 1 : 0;
+                a.invA = D.inv_A[k];
+                a.invG = D.inv_G[k];
+                a.inmask = D.inv_mask;
+            }
+        }
         e = launch_sweep_general(fp64, a, c->stream);
     }
     if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
@@ -1171,8 +1227,10 @@ int smm_apply_G_noalloc(smm_problem* prob, int precision, const double* varphi_i
             d.varphi = s.varphi; d.S = s.S; d.psi[0] = s.psi[0]; d.mom = s.mom; d.T = s.T; d.beta = s.beta;
             d.x = s.x; d.b = s.b; d.r = s.r; d.z = s.z; d.p = s.p; d.qv = s.qv; d.part = s.part; d.scal = s.scal;
             d.last_mom = s.last_mom; d.last_varphi = s.last_varphi;
+            d.noalloc_active = false;
         }
     } restore{D, saved};
+    D.noalloc_active = true;
     D.varphi = reinterpret_cast<double*>(take(sizeof(double) * L));
     D.S = take(sizeof(double) * nd_q * L);
     D.psi[0] = take(sizeof(double) * (size_t)P.nd * L);

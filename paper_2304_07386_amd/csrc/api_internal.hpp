@@ -75,6 +75,12 @@ struct Dev {
     bool gen_sweep_built = false;  // per-element sweep data uploaded
     bool gen_dirty = true;         // per-element moment system needs (re)upload
     int force_general = 0;
+    // stored element operators of the per-element sweep, [0] FP32, [1] FP64
+    void* inv_A[2] = {nullptr, nullptr};
+    void* inv_G[2] = {nullptr, nullptr};
+    uint8_t* inv_mask = nullptr;
+    bool inv_ready[2] = {false, false};
+    bool noalloc_active = false;   // inside smm_apply_G_noalloc: build nothing that needs memory
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // phase timing of smm_solve
     double phase_ms[4] = {0, 0, 0, 0};  // source + sweep, moments + closures + rhs, CG, residual
     std::vector<double> hist_r;         // outer residual of each outer iteration of the last smm_solve

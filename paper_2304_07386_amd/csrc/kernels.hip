@@ -844,8 +844,12 @@ static hipError_t launch_rows_t(const GenSweepArgs& a, hipStream_t s) {
 }
 
 template <typename T, int NB>
+static hipError_t launch_inv_t(const GenSweepArgs& a, hipStream_t s);
+
+template <typename T, int NB>
 static hipError_t launch_gen_t(const GenSweepArgs& a, hipStream_t s) {
     if (a.nq > GEN_MAXQ || 4 * a.nq > 64) return hipErrorInvalidValue;
+    if (a.invA) return launch_inv_t<T, NB>(a, s);
     if constexpr (NB >= 3) {
         // one lane per row: the default at p >= 3; at p = 2 where levels are
         // narrow or workgroups few (the lane-per-element form wins only with
@@ -890,6 +894,296 @@ hipError_t launch_sweep_general(bool fp64, const GenSweepArgs& a, hipStream_t s)
         case 5: return fp64 ? launch_gen_t<double, 5>(a, s) : launch_gen_t<float, 5>(a, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// ---------------------------------------------------------------------------
+// General sweep with stored element operators.  The left-hand side of an
+// element's system (the volume terms and the outflow face terms above)
+// depends on the element, the direction and sigma_t but not on the upwind
+// data, so it is inverted once, in parallel over every (element, direction)
+// pair, and kept in device memory:
+//   invA   [nd][ne][N][N]      A^-1 by column j, then row i (the lanes of an
+//                              element read a column together)
+//   invG   [nd][ne][4][NB][N]  for a face f with a neighbour and an inflow
+//                              point, G_f = A^-1 E_f F_f with
+//                              F_f[c][c'] = sum over the inflow points q of
+//                              |Omega.n_q| u_c(q) u_c'(q'), q' the same point
+//                              in the neighbour's face numbering, so that the
+//                              neighbour's face-node values v enter psi_K as
+//                              G_f v (E_f places face node c at its element
+//                              node)
+//   inmask [nd][ne]            bit f set when face f has a neighbour and an
+//                              inflow point
+// A sweep is then psi_K = A^-1 (M S_K + boundary inflow) for all elements at
+// once (gen_inv_particular_kernel), followed by the levels in order, each
+// adding sum_f G_f v_f from the finished upwind neighbours
+// (gen_inv_sweep_kernel): one load of the neighbour's face nodes and NB
+// multiply-adds per inflow face and lane.  Same lane layout as the row
+// kernel: lane i of an element's N lanes holds row i.
+// ---------------------------------------------------------------------------
+template <typename TO, int NB, bool GENERAL>
+__global__ __launch_bounds__(256) void gen_inv_setup_kernel(GenSweepArgs a, TO* invA, TO* invG, uint8_t* inmask) {
+    constexpr int N = NB * NB;
+    constexpr int EPW = 64 / N;
+    const int d = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int eslot = lane / N;
+    const int i = lane - eslot * N;
+    const bool lane_ok = eslot < EPW;
+    const int es = lane_ok ? eslot : 0;
+    const int nq = a.nq, ne = a.ne;
+    const int Kr = (blockIdx.x * 4 + wv) * EPW + es;
+    const bool act = lane_ok && Kr < ne;
+    const int K = act ? Kr : 0;
+    __shared__ double fon[4][EPW][4 * GEN_MAXQ];
+    __shared__ double lfs[NB * GEN_MAXQ];
+    const double* Lf = reinterpret_cast<const double*>(a.Lf);
+    const double* nds = reinterpret_cast<const double*>(a.nds);
+    for (int t = threadIdx.x; t < NB * nq; t += blockDim.x) lfs[t] = Lf[t];
+    const double ox = a.omega[d * 3], oy = a.omega[d * 3 + 1];
+    if (lane_ok)
+        for (int t = i; t < 4 * nq; t += N) {
+            const double* nn = nds + (((long)K * 4 + t / nq) * nq + t % nq) * 2;
+            fon[wv][es][t] = ox * nn[0] + oy * nn[1];
+        }
+    __syncthreads();
+    // row i of A: volume terms, then the outflow points of the faces through
+    // node i (all in FP64 whatever the stored type)
+    double A[N], E[N];
+    {
+        const double sK = reinterpret_cast<const double*>(a.sigma_t)[K];
+        const double* M = reinterpret_cast<const double*>(a.Mk) + ((long)K * N + i) * N;
+        const double* gx = reinterpret_cast<const double*>(a.Gx) + ((long)K * N + i) * N;
+        const double* gy = reinterpret_cast<const double*>(a.Gy) + ((long)K * N + i) * N;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            A[j] = sK * M[j] - ox * gx[j] - oy * gy[j];
+            E[j] = j == i ? 1.0 : 0.0;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int c = face_pos<NB>(f, i);
+        if (c < 0) continue;
+        for (int q = 0; q < nq; ++q) {
+            const double on = fon[wv][es][f * nq + q];
+            if (on > 0.0) {
+                const double lc = lfs[c * nq + q];
+#pragma unroll
+                for (int c2 = 0; c2 < NB; ++c2) A[face_node<NB>(f, c2)] += on * lc * lfs[c2 * nq + q];
+            }
+        }
+    }
+    // Gauss-Jordan on [A | I] without pivoting (as in the row kernel); before
+    // pivot k the identity columns past k are untouched, so only columns
+    // 0..k of the right block take the update
+    double diag = 1.0;
+    const int r0 = es * N;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double piv = shfl_t(A[k], r0 + k);
+        if (i == k) diag = piv;
+        const double m = i == k ? 0.0 : A[k] / piv;
+#pragma unroll
+        for (int j = k + 1; j < N; ++j) A[j] -= m * shfl_t(A[j], r0 + k);
+#pragma unroll
+        for (int j = 0; j <= k; ++j) E[j] -= m * shfl_t(E[j], r0 + k);
+    }
+    const double rd = 1.0 / diag;
+#pragma unroll
+    for (int j = 0; j < N; ++j) E[j] *= rd;   // row i of A^-1
+    const long dK = (long)d * ne + K;
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) invA[(dK * N + j) * N + i] = (TO)E[j];
+    }
+    unsigned mask = 0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const int Nb = a.nbr[K * 4 + f];
+        bool inflow = false;
+        for (int q = 0; q < nq; ++q) inflow |= fon[wv][es][f * nq + q] < 0.0;
+        const bool use = Nb >= 0 && inflow;
+        const int code = GENERAL ? (int)a.nbr_face[K * 4 + f] : ((f + 2) & 3);
+        const bool flip = GENERAL && (code & 4);
+#pragma unroll
+        for (int c2 = 0; c2 < NB; ++c2) {
+            double g = 0.0;
+            if (use) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    double F = 0.0;
+                    for (int q = 0; q < nq; ++q) {
+                        const double on = fon[wv][es][f * nq + q];
+                        const int qN = flip ? nq - 1 - q : q;
+                        if (on < 0.0) F -= on * lfs[c * nq + q] * lfs[c2 * nq + qN];
+                    }
+                    g += E[face_node<NB>(f, c)] * F;
+                }
+            }
+            if (act) invG[((dK * 4 + f) * NB + c2) * N + i] = (TO)g;
+        }
+        if (use) mask |= 1u << f;
+    }
+    if (act && i == 0) inmask[dK] = (uint8_t)mask;
+}
+
+// psi_K = A^-1 (M S_K + the boundary inflow of K) for every element and
+// direction: the part of the element solution that needs no upwind element
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void gen_inv_particular_kernel(GenSweepArgs a) {
+    constexpr int N = NB * NB;
+    constexpr int EPW = 64 / N;
+    const int d = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int eslot = lane / N;
+    const int i = lane - eslot * N;
+    const bool lane_ok = eslot < EPW;
+    const int es = lane_ok ? eslot : 0;
+    const int nq = a.nq, ne = a.ne;
+    const int Kr = (blockIdx.x * 4 + wv) * EPW + es;
+    const bool act = lane_ok && Kr < ne;
+    const int K = act ? Kr : 0;
+    __shared__ T bs[4][EPW][N];
+    __shared__ T lfs[NB * GEN_MAXQ];
+    for (int t = threadIdx.x; t < NB * nq; t += blockDim.x) lfs[t] = reinterpret_cast<const T*>(a.Lf)[t];
+    __syncthreads();
+    const T ox = (T)a.omega[d * 3], oy = (T)a.omega[d * 3 + 1];
+    const T* S = reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0) + (long)K * N;
+    const T* M = reinterpret_cast<const T*>(a.Mk) + ((long)K * N + i) * N;
+    const T* nds = reinterpret_cast<const T*>(a.nds);
+    const T* pbar = reinterpret_cast<const T*>(a.psibar);
+    T b = T(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) b += M[j] * S[j];
+    if (pbar) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int c = face_pos<NB>(f, i);
+            if (c < 0 || a.nbr[K * 4 + f] >= 0) continue;
+            const T* pb = pbar + ((long)d * a.nbf + a.bface_of[K * 4 + f]) * nq;
+            for (int q = 0; q < nq; ++q) {
+                const T* nn = nds + (((long)K * 4 + f) * nq + q) * 2;
+                const T on = ox * nn[0] + oy * nn[1];
+                if (on < T(0)) b -= on * lfs[c * nq + q] * pb[q];
+            }
+        }
+    }
+    if (lane_ok) bs[wv][es][i] = b;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const long dK = (long)d * ne + K;
+    const T* Ai = reinterpret_cast<const T*>(a.invA) + dK * N * N + i;
+    T x = T(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) x += Ai[(long)j * N] * bs[wv][es][j];
+    if (act) reinterpret_cast<T*>(a.psi)[dK * N + i] = x;
+}
+
+// The levels: psi_K += sum over the faces of inmask of G_f v_f, v_f the
+// neighbour's face nodes from this sweep (upstream in the graph) or the
+// lagged one.  One workgroup per (direction, tile) as in the row kernel.
+template <typename T, int NB, int WAVES, bool GENERAL>
+__global__ __launch_bounds__(64 * WAVES) void gen_inv_sweep_kernel(GenSweepArgs a) {
+    constexpr int N = NB * NB;
+    constexpr int EPW = 64 / N;
+    const int d = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int eslot = lane / N;
+    const int i = lane - eslot * N;
+    const bool lane_ok = eslot < EPW;
+    const int ne = a.ne;
+    const gcptr<T> G = as_global(reinterpret_cast<const T*>(a.invG));
+    const gcptr<T> plag = as_global(reinterpret_cast<const T*>(a.psi_lag));
+    const gptr<T> psi = as_global(reinterpret_cast<T*>(a.psi));
+    const uint8_t* inm = a.inmask + (long)d * ne;
+    const uint8_t* upf = a.upflag + (long)d * ne;
+    const int* lp = a.lev_ptr + ((long)d * a.ntiles + blockIdx.y) * (a.nlev + 1);
+    const int* le = a.lev_elem + (long)d * ne;
+    for (int l = 0; l < a.nlev; ++l) {
+        const int beg = lp[l], end = lp[l + 1];
+        for (int base = beg; base < end; base += WAVES * EPW) {
+            const int e = base + wv * EPW + eslot;
+            if (lane_ok && e < end) {
+                const int K = le[e];
+                const long dK = (long)d * ne + K;
+                const unsigned m = inm[K], up = upf[K];
+                T x = psi[dK * N + i];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    if (!((m >> f) & 1)) continue;
+                    const gcptr<T> src = ((up >> f) & 1) ? gcptr<T>(psi) : plag;
+                    if (!src) continue;
+                    const int Nb = a.nbr[K * 4 + f];
+                    const int fN = GENERAL ? (int)(a.nbr_face[K * 4 + f] & 3) : ((f + 2) & 3);
+                    const gcptr<T> v = src + ((long)d * ne + Nb) * N;
+                    const gcptr<T> g = G + (dK * 4 + f) * NB * N + i;
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) x += g[c * N] * v[face_node<NB>(fN, c)];
+                }
+                psi[dK * N + i] = x;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename TO, int NB>
+static hipError_t launch_inv_setup_t(const GenSweepArgs& a, void* invA, void* invG, uint8_t* inmask, hipStream_t s) {
+    constexpr int EPW = 64 / (NB * NB);
+    const dim3 grid((a.ne + 4 * EPW - 1) / (4 * EPW), a.nd);
+    if (a.nbr_face)
+        hipLaunchKernelGGL((gen_inv_setup_kernel<TO, NB, true>), grid, dim3(256), 0, s, a, (TO*)invA, (TO*)invG,
+                           inmask);
+    else
+        hipLaunchKernelGGL((gen_inv_setup_kernel<TO, NB, false>), grid, dim3(256), 0, s, a, (TO*)invA, (TO*)invG,
+                           inmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_inv_setup(bool out_fp64, const GenSweepArgs& a, void* invA, void* invG, uint8_t* inmask,
+                                hipStream_t s) {
+    if (a.nq > GEN_MAXQ || 4 * a.nq > 64) return hipErrorInvalidValue;
+    switch (a.nb) {
+        case 2: return out_fp64 ? launch_inv_setup_t<double, 2>(a, invA, invG, inmask, s)
+                                : launch_inv_setup_t<float, 2>(a, invA, invG, inmask, s);
+        case 3: return out_fp64 ? launch_inv_setup_t<double, 3>(a, invA, invG, inmask, s)
+                                : launch_inv_setup_t<float, 3>(a, invA, invG, inmask, s);
+        case 4: return out_fp64 ? launch_inv_setup_t<double, 4>(a, invA, invG, inmask, s)
+                                : launch_inv_setup_t<float, 4>(a, invA, invG, inmask, s);
+        case 5: return out_fp64 ? launch_inv_setup_t<double, 5>(a, invA, invG, inmask, s)
+                                : launch_inv_setup_t<float, 5>(a, invA, invG, inmask, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int NB, bool GENERAL>
+static hipError_t launch_inv_levels(const GenSweepArgs& a, hipStream_t s) {
+    constexpr int EPW = 64 / (NB * NB);
+    const int need = (a.maxw + EPW - 1) / EPW;
+    const dim3 grid(a.nd, a.ntiles);
+    if (need > 8)
+        hipLaunchKernelGGL((gen_inv_sweep_kernel<T, NB, 16, GENERAL>), grid, dim3(1024), 0, s, a);
+    else if (need > 4)
+        hipLaunchKernelGGL((gen_inv_sweep_kernel<T, NB, 8, GENERAL>), grid, dim3(512), 0, s, a);
+    else if (need > 2)
+        hipLaunchKernelGGL((gen_inv_sweep_kernel<T, NB, 4, GENERAL>), grid, dim3(256), 0, s, a);
+    else if (need > 1)
+        hipLaunchKernelGGL((gen_inv_sweep_kernel<T, NB, 2, GENERAL>), grid, dim3(128), 0, s, a);
+    else
+        hipLaunchKernelGGL((gen_inv_sweep_kernel<T, NB, 1, GENERAL>), grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NB>
+static hipError_t launch_inv_t(const GenSweepArgs& a, hipStream_t s) {
+    constexpr int EPW = 64 / (NB * NB);
+    hipLaunchKernelGGL((gen_inv_particular_kernel<T, NB>), dim3((a.ne + 4 * EPW - 1) / (4 * EPW), a.nd), dim3(256),
+                       0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return a.nbr_face ? launch_inv_levels<T, NB, true>(a, s) : launch_inv_levels<T, NB, false>(a, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -55,8 +55,18 @@ struct GenSweepArgs {
     const void* psibar;          // [nd][nbf][nq] or null
     const void* psi_lag;         // [nd][ne][n] or null
     void* psi;                   // [nd][ne][n]
+    // stored element operators (sweep type; null: assemble and eliminate
+    // per sweep): A^-1 [nd][ne][n][n] by column, face operators
+    // [nd][ne][4][nb][n] and the inflow-face mask [nd][ne]
+    const void* invA;
+    const void* invG;
+    const uint8_t* inmask;
 };
 hipError_t launch_sweep_general(bool fp64, const GenSweepArgs& a, hipStream_t s);
+// Build the stored element operators of the general sweep (FP64 tables in a,
+// output in FP64 or FP32); invA, invG, inmask sized as in GenSweepArgs.
+hipError_t launch_gen_inv_setup(bool out_fp64, const GenSweepArgs& a, void* invA, void* invG, uint8_t* inmask,
+                                hipStream_t s);
 
 // mom[16 rows used 8][L] = W[16][nd] psi[nd][L] on the matrix cores
 hipError_t launch_moments(bool fp64, const void* psi, int nd, long L, const void* W, int ldw,

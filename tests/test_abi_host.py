@@ -144,12 +144,13 @@ def test_tiles_and_cg_calls_on_the_host(hctx):
         assert e.value.code == L.SMM_EINVAL
     L.smm_set_sweep_tiles(p, 2, 2)
     L.smm_set_sweep_tiles(p, 0, 0)
-    # sweep kernel selection: 0..4 (3 = one wave per element, 4 = one lane per row)
-    for bad in (-1, 5):
+    # sweep kernel selection: 0..5 (3 = one wave per element, 4 = one lane per
+    # row, 5 = the assembling forms chosen as 0 chooses them)
+    for bad in (-1, 6):
         with pytest.raises(L.SmmError) as e:
             L.smm_set_sweep_path(p, bad)
         assert e.value.code == L.SMM_EINVAL
-    for path in (3, 4, 0):
+    for path in (3, 4, 5, 0):
         L.smm_set_sweep_path(p, path)
     rowptr, col, val, cmap = L.smm_debug_cg_system(p)
     assert len(rowptr) == (4 * 2 + 1) ** 2 + 1 and cmap.max() == (4 * 2 + 1) ** 2 - 1

@@ -46,7 +46,10 @@ def _sweep_gpu(p, prec, S, lag=None, inflow=True):
 SWEEP_CASES = [
     # (name, workload factory, sweep path: 0 auto, 1 per-element kernel, 2 element-row
     # kernel, 3 per-element kernel with one wave per element also at p <= 2,
-    # 4 per-element kernel with one lane per row at every order p >= 2)
+    # 4 per-element kernel with one lane per row at every order p >= 2,
+    # 5 per-element kernel assembling and eliminating in the form 0 picked
+    # before the stored element operators; 0 and 1 on curved or non-uniform
+    # meshes use the stored operators)
     ("plain8_p1_s4", lambda: config_plain(8, 1, 4), 0),
     ("plain8_p1_s4_general", lambda: config_plain(8, 1, 4), 1),
     ("plain8_p1_s4_rowkernel", lambda: config_plain(8, 1, 4), 2),
@@ -69,6 +72,10 @@ SWEEP_CASES = [
     ("curved5_p3_s6_wavesolve", lambda: config_curved_mms(5, 3, 6, amplitude=0.09), 3),
     ("curved3_p4_s4_wavesolve", lambda: config_curved_mms(3, 4, 4), 3),
     ("ragged7x3_p4_s12_rowsolve", lambda: _rect(7, 3, 4, 12), 4),
+    ("ragged7x3_p4_s12", lambda: _rect(7, 3, 4, 12), 0),
+    ("curved4_p2_s8_assembled", lambda: config_curved_mms(4, 2, 8, amplitude=0.09), 5),
+    ("curved5_p3_s6_assembled", lambda: config_curved_mms(5, 3, 6, amplitude=0.09), 5),
+    ("curved3_p4_s4_assembled", lambda: config_curved_mms(3, 4, 4), 5),
 ]
 
 
