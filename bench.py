@@ -35,8 +35,8 @@ Also reported:
     CG product kernel;
   * the parallel block Jacobi sweep on the same problem: sweep time and
     outer iterations per tile size;
-  * the sweep on curved meshes (per-element assembly and elimination) at
-    p = 2, 3, 4;
+  * the sweep on curved meshes (stored element operators, and the
+    assembling form for comparison) at p = 2, 3, 4;
   * the CPU oracle on bounded samples of the workloads, one thread and all
     host cores, minimum of three runs.
 """
@@ -416,30 +416,40 @@ def block_jacobi_sweeps(L, ctx, log):
 
 def curved_sweeps(L, ctx, log):
     """The sweep on curved meshes (the manufactured problem: 32 x 32 elements
-    with an order-p map, S8), where every element and direction is assembled
-    and eliminated by the per-element kernel (one lane per row of the
-    element's system, sweep_rows_general_kernel, at every order of the
-    whole-mesh sweep): time per sweep, units/s, and the rate against the FP32
-    vector peak at the assembly and elimination work per DOF of an LU solve
-    (165 / 344 / 664 flops for p = 2 / 3 / 4; the kernel's Gauss-Jordan
-    elimination issues more)."""
+    with an order-p map, S8) with stored element operators: per p the FP32
+    and FP64 time per sweep and units/s; its parts (the one-off build of the
+    operators, the parallel pass psi = A^-1 (M S + inflow), the levels); the
+    levels and the time per level; the parallel pass against HBM at its
+    algorithmic bytes ((n^2 + n) values per element and direction: A^-1 read,
+    psi written); and, for comparison, the sweep that assembles and
+    eliminates every element's system in each sweep (sweep path 5)."""
     from workloads import config_curved_mms
 
-    flops = {2: 165.0, 3: 344.0, 4: 664.0}
     res = {"workload": "curved manufactured problem, 32x32 elements, order-p map, S8 (40 directions)", "runs": []}
     for p in (2, 3, 4):
         wl = config_curved_mms(32, p, 8)
         prob = L.problem_from_workload(ctx, wl)
-        units = float(wl.n_elem * (p + 1) ** 2 * 40)
+        n = (p + 1) ** 2
+        pairs = wl.n_elem * 40
+        units = float(pairs * n)
         run = {"p": p, "units_per_sweep": units}
         for name, prec in (("fp32", L.SMM_FP32_SWEEP), ("fp64", L.SMM_FP64)):
-            ms = L.smm_time_sweep(prob, prec, 5)
+            ms = L.smm_time_sweep(prob, prec, 10)
             run[name + "_ms"] = ms
             run[name + "_units_per_s"] = units / (ms * 1e-3)
-        tf = flops[p] * units / (run["fp32_ms"] * 1e-3) / 1e12
-        run["roofline_fp32"] = {"bound": "alu", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
-                                "traffic": None, "kernel": "sweep_rows_general_kernel"}
-        log(f"curved 32^2 p={p} S8: FP32 sweep {run['fp32_ms']:.3f} ms, FP64 {run['fp64_ms']:.3f} ms")
+        setup, part, lev_ms = L.smm_time_sweep_parts(prob, L.SMM_FP32_SWEEP, 10)
+        nlev = int(L.smm_debug_sweep_graph(prob)[0].max()) + 1
+        run["fp32_parts_ms"] = {"operator_build": setup, "particular": part, "levels": lev_ms}
+        run["levels"] = nlev
+        run["us_per_level"] = 1e3 * lev_ms / nlev
+        gbs = 4.0 * pairs * (n * n + n) / (part * 1e-3) / 1e9
+        run["roofline_fp32"] = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                                "traffic": None, "kernel": "gen_inv_particular_kernel"}
+        L.smm_set_sweep_path(prob, 5)
+        run["assembled_fp32_ms"] = L.smm_time_sweep(prob, L.SMM_FP32_SWEEP, 5)
+        log(f"curved 32^2 p={p} S8: FP32 sweep {run['fp32_ms']:.3f} ms (particular {part:.3f}, levels {lev_ms:.3f} = "
+            f"{nlev} x {run['us_per_level']:.2f} us; build {setup:.3f}), FP64 {run['fp64_ms']:.3f} ms; assembling "
+            f"{run['assembled_fp32_ms']:.3f} ms")
         res["runs"].append(run)
         L.smm_problem_destroy(prob)
     return res
@@ -490,14 +500,23 @@ def critical_path(L, ctx, log):
     from workloads import config_batched_problem, config_channel, config_curved_mms
 
     out = []
-    for name, wl in (("channel 128^2 p=2 S12", config_channel()), ("curved 32^2 p=4 S8", config_curved_mms(32, 4, 8))):
-        p = L.problem_from_workload(ctx, wl)
-        lev = L.smm_get_dims(p)["n_levels"] or wl.nx + wl.ny - 1
-        ms = L.smm_time_sweep(p, L.SMM_FP32_SWEEP, 10)
-        out.append({"case": name, "kernel": "single-problem sweep", "levels": lev, "sweep_ms": ms,
-                    "us_per_level": 1e3 * ms / lev})
-        log(f"critical path {name}: {lev} levels, {ms:.3f} ms, {1e3 * ms / lev:.2f} us/level")
-        L.smm_problem_destroy(p)
+    p = L.problem_from_workload(ctx, config_channel())
+    lev = 128 + 128 - 1
+    ms = L.smm_time_sweep(p, L.SMM_FP32_SWEEP, 10)
+    out.append({"case": "channel 128^2 p=2 S12", "kernel": "single-problem Cartesian sweep", "levels": lev,
+                "sweep_ms": ms, "us_per_level": 1e3 * ms / lev})
+    log(f"critical path channel 128^2 p=2 S12: {lev} levels, {ms:.3f} ms, {1e3 * ms / lev:.2f} us/level")
+    L.smm_problem_destroy(p)
+    # curved: the level pass alone (the parallel pass before it has no levels)
+    p = L.problem_from_workload(ctx, config_curved_mms(32, 4, 8))
+    lev = int(L.smm_debug_sweep_graph(p)[0].max()) + 1
+    ms = L.smm_time_sweep(p, L.SMM_FP32_SWEEP, 10)
+    lev_ms = L.smm_time_sweep_parts(p, L.SMM_FP32_SWEEP, 10)[2]
+    out.append({"case": "curved 32^2 p=4 S8", "kernel": "gen_inv_sweep_kernel (levels of the stored-operator sweep)",
+                "levels": lev, "sweep_ms": ms, "levels_ms": lev_ms, "us_per_level": 1e3 * lev_ms / lev})
+    log(f"critical path curved 32^2 p=4 S8: {lev} levels, {lev_ms:.3f} ms of {ms:.3f} ms, "
+        f"{1e3 * lev_ms / lev:.2f} us/level")
+    L.smm_problem_destroy(p)
     for s in (23, 9, 0, 19):
         wl = config_batched_problem(s)
         name = f"batch member {s}: {wl.nx}^2 p={wl.p} S{wl.sn}"

@@ -402,6 +402,16 @@ int smm_set_sweep_tiles(smm_problem* prob, int tile_nx, int tile_ny);
 /* Time one sweep configuration on device (average ms over `reps` launches
  * measured with HIP events on the context stream); used by the benchmark. */
 int smm_time_sweep(smm_problem* prob, int precision, int reps, double* ms_avg);
+/* The parts of a per-element sweep with stored element operators, each the
+ * average over `reps` rounds (HIP events on the context stream, ms): the
+ * build of the operators (*ms_setup, run after every change of materials),
+ * the pass psi = A^-1 (M S + boundary inflow) over all elements and
+ * directions (*ms_particular) and the pass over the levels (*ms_levels); the
+ * last two make one sweep.  SMM_EUNSUPPORTED when the problem does not sweep
+ * with stored operators (tabulated Cartesian kernel, an assembling sweep
+ * path, or operators too large for the free device memory). */
+int smm_time_sweep_parts(smm_problem* prob, int precision, int reps, double* ms_setup, double* ms_particular,
+                         double* ms_levels);
 
 /* Host-only inspection of the typed Cartesian representation: the IP matrix
  * [N][N], the correction-source operator [N][3N] (columns: T_xx, T_xy, T_yy

@@ -614,6 +614,7 @@ static int ensure_device(smm_problem* pr, bool gen_moment, bool gen_sweep) {
         }
         D.src_dirty = false;
         D.gen_dirty = true;
+        D.inv_ready[0] = D.inv_ready[1] = false;   // the element operators hold the inflow
     }
     if (gen_moment && D.gen_dirty) {
         UP(D.bsr_col, P.bsr_col);
@@ -671,18 +672,20 @@ static int ensure_inv(smm_problem* pr, bool fp64, bool* use) {
     }
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
     const size_t pairs = (size_t)P.nd * P.ne;
-    const size_t bytes_A = es * pairs * P.n * P.n, bytes_G = es * pairs * 4 * P.nb * P.n;
+    const size_t bytes_A = es * pairs * P.n * P.n, bytes_C = es * pairs * P.n, bytes_G = es * pairs * 4 * P.nb * P.n;
     if (!D.inv_A[k]) {
         if (D.noalloc_active) return SMM_OK;
         size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) != hipSuccess || bytes_A + bytes_G + pairs > fr / 4) return SMM_OK;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess || bytes_A + bytes_C + bytes_G + pairs > fr / 4) return SMM_OK;
         int rc = alloc(c, D, &D.inv_A[k], bytes_A);
+        if (!rc) rc = alloc(c, D, &D.inv_C[k], bytes_C);
         if (!rc) rc = alloc(c, D, &D.inv_G[k], bytes_G);
         if (!rc && !D.inv_mask) rc = alloc(c, D, &D.inv_mask, pairs);
         if (rc) return rc;
     }
-    const GenSweepArgs a = gen_args(pr, true);
-    const hipError_t e = launch_gen_inv_setup(fp64, a, D.inv_A[k], D.inv_G[k], D.inv_mask, c->stream);
+    GenSweepArgs a = gen_args(pr, true);
+    a.psibar = P.inflow_layout != SMM_INFLOW_VACUUM ? D.pbar64 : nullptr;
+    const hipError_t e = launch_gen_inv_setup(fp64, a, D.inv_A[k], D.inv_C[k], D.inv_G[k], D.inv_mask, c->stream);
     if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("element operator set-up: ") + hipGetErrorString(e));
     D.inv_ready[k] = true;
     *use = true;
@@ -725,6 +728,7 @@ static int run_sweep(smm_problem* pr, bool fp64, const void* S, int s_aniso, con
             if (use) {
                 const int k = fp64 ? 1 : 0;
                 a.invA = D.inv_A[k];
+                a.invC = D.inv_C[k];
                 a.invG = D.inv_G[k];
                 a.inmask = D.inv_mask;
             }
@@ -1426,6 +1430,67 @@ int smm_debug_corr_dense(smm_problem* prob, double* C) {
                     for (int j = 0; j < n; ++j)
                         C[((long)K * n + i) * 3 * N + cc * N + (long)Kc * n + j] += cb[i * 3 * n + cc * n + j];
         }
+    return SMM_OK;
+}
+
+int smm_time_sweep_parts(smm_problem* prob, int precision, int reps, double* ms_setup, double* ms_particular,
+                         double* ms_levels) {
+    if (!prob || !ms_setup || !ms_particular || !ms_levels || reps < 1) return SMM_EINVAL;
+    int rc = ensure_device(prob, false, per_element_forced(prob->D));
+    if (rc) return rc;
+    Problem& P = prob->P;
+    Dev& D = prob->D;
+    smm_ctx* c = P.ctx;
+    if (P.cartesian && !per_element_forced(D) && P.tile_x == 0)
+        return fail(c, SMM_EUNSUPPORTED, "smm_time_sweep_parts: this problem sweeps with the tabulated kernel");
+    if (D.force_general > 1)
+        return fail(c, SMM_EUNSUPPORTED, "smm_time_sweep_parts: the sweep path assembles per element");
+    const bool fp64 = precision == SMM_FP64;
+    bool use = false;
+    if ((rc = ensure_inv(prob, fp64, &use))) return rc;
+    if (!use) return fail(c, SMM_EUNSUPPORTED, "smm_time_sweep_parts: the stored element operators do not fit");
+    const int k = fp64 ? 1 : 0;
+    HIPCHK(c, launch_source(fp64, P.ne, P.n, 1, D.sigma_s, D.varphi, nullptr, D.q, D.S, c->stream));
+    GenSweepArgs a = gen_args(prob, fp64);
+    a.S = D.S;
+    a.psibar = P.inflow_layout != SMM_INFLOW_VACUUM ? (fp64 ? D.pbar64 : D.pbar32) : nullptr;
+    a.psi = D.psi[0];
+    a.invA = D.inv_A[k];
+    a.invC = D.inv_C[k];
+    a.invG = D.inv_G[k];
+    a.inmask = D.inv_mask;
+    GenSweepArgs a64 = gen_args(prob, true);
+    a64.psibar = P.inflow_layout != SMM_INFLOW_VACUUM ? D.pbar64 : nullptr;
+    std::vector<hipEvent_t> ev(6 * reps, nullptr);
+    for (hipEvent_t& e : ev) HIPCHK(c, hipEventCreate(&e));
+    auto done = [&]() { for (hipEvent_t& e : ev) (void)hipEventDestroy(e); };
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        hipEvent_t* t = &ev[6 * r];
+        e = hipEventRecord(t[0], c->stream);
+        if (e == hipSuccess)
+            e = launch_gen_inv_setup(fp64, a64, D.inv_A[k], D.inv_C[k], D.inv_G[k], D.inv_mask, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(t[1], c->stream);
+        if (e == hipSuccess) e = hipEventRecord(t[2], c->stream);
+        if (e == hipSuccess) e = launch_gen_inv_part(fp64, a, 1, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(t[3], c->stream);
+        if (e == hipSuccess) e = hipEventRecord(t[4], c->stream);
+        if (e == hipSuccess) e = launch_gen_inv_part(fp64, a, 2, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(t[5], c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    double sum[3] = {0, 0, 0};
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+        for (int q = 0; q < 3 && e == hipSuccess; ++q) {
+            float ms = 0;
+            e = hipEventElapsedTime(&ms, ev[6 * r + 2 * q], ev[6 * r + 2 * q + 1]);
+            sum[q] += ms;
+        }
+    done();
+    if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("smm_time_sweep_parts: ") + hipGetErrorString(e));
+    *ms_setup = sum[0] / reps;
+    *ms_particular = sum[1] / reps;
+    *ms_levels = sum[2] / reps;
     return SMM_OK;
 }
 

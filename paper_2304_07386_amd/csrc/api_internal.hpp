@@ -77,6 +77,7 @@ struct Dev {
     int force_general = 0;
     // stored element operators of the per-element sweep, [0] FP32, [1] FP64
     void* inv_A[2] = {nullptr, nullptr};
+    void* inv_C[2] = {nullptr, nullptr};
     void* inv_G[2] = {nullptr, nullptr};
     uint8_t* inv_mask = nullptr;
     bool inv_ready[2] = {false, false};

@@ -19,6 +19,22 @@ namespace smm {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+
+// 16 bytes of T as one vector
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    typedef v4f type;
+    static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+    typedef v2d type;
+    static constexpr int n = 2;
+};
 
 // Global-address-space views of buffer pointers that reach a kernel through a
 // descriptor in memory.  Through a generic pointer the compiler emits flat
@@ -901,28 +917,31 @@ hipError_t launch_sweep_general(bool fp64, const GenSweepArgs& a, hipStream_t s)
 // element's system (the volume terms and the outflow face terms above)
 // depends on the element, the direction and sigma_t but not on the upwind
 // data, so it is inverted once, in parallel over every (element, direction)
-// pair, and kept in device memory:
-//   invA   [nd][ne][N][N]      A^-1 by column j, then row i (the lanes of an
-//                              element read a column together)
-//   invG   [nd][ne][4][NB][N]  for a face f with a neighbour and an inflow
-//                              point, G_f = A^-1 E_f F_f with
+// pair, and what a sweep needs of A^-1 is kept in device memory:
+//   invA   [nd][ne][N][N]      H = A^-1 M by column j, then row i (the lanes
+//                              of an element read a column together)
+//   invC   [nd][ne][N]         c = A^-1 r, r the boundary inflow terms
+//   invG   [nd][ne][N][4][NB]  row i of G_f for every face (a lane's values
+//                              contiguous), where for a face f with a
+//                              neighbour and an inflow point
+//                              G_f = A^-1 E_f F_f with
 //                              F_f[c][c'] = sum over the inflow points q of
 //                              |Omega.n_q| u_c(q) u_c'(q'), q' the same point
 //                              in the neighbour's face numbering, so that the
 //                              neighbour's face-node values v enter psi_K as
 //                              G_f v (E_f places face node c at its element
-//                              node)
+//                              node); zero for the other faces
 //   inmask [nd][ne]            bit f set when face f has a neighbour and an
 //                              inflow point
-// A sweep is then psi_K = A^-1 (M S_K + boundary inflow) for all elements at
-// once (gen_inv_particular_kernel), followed by the levels in order, each
-// adding sum_f G_f v_f from the finished upwind neighbours
-// (gen_inv_sweep_kernel): one load of the neighbour's face nodes and NB
-// multiply-adds per inflow face and lane.  Same lane layout as the row
-// kernel: lane i of an element's N lanes holds row i.
+// A sweep is then psi_K = H S_K + c for all elements at once
+// (gen_inv_particular_kernel), followed by the levels in order, each adding
+// sum_f G_f v_f from the finished upwind neighbours (gen_inv_sweep_kernel).
+// Same lane layout as the row kernel: lane i of an element's N lanes holds
+// row i.
 // ---------------------------------------------------------------------------
 template <typename TO, int NB, bool GENERAL>
-__global__ __launch_bounds__(256) void gen_inv_setup_kernel(GenSweepArgs a, TO* invA, TO* invG, uint8_t* inmask) {
+__global__ __launch_bounds__(256) void gen_inv_setup_kernel(GenSweepArgs a, TO* invA, TO* invC, TO* invG,
+                                                            uint8_t* inmask) {
     constexpr int N = NB * NB;
     constexpr int EPW = 64 / N;
     const int d = blockIdx.y;
@@ -939,6 +958,8 @@ __global__ __launch_bounds__(256) void gen_inv_setup_kernel(GenSweepArgs a, TO* 
     __shared__ double lfs[NB * GEN_MAXQ];
     const double* Lf = reinterpret_cast<const double*>(a.Lf);
     const double* nds = reinterpret_cast<const double*>(a.nds);
+    const double* Mk = reinterpret_cast<const double*>(a.Mk) + (long)K * N * N;
+    const double* pbar = reinterpret_cast<const double*>(a.psibar);
     for (int t = threadIdx.x; t < NB * nq; t += blockDim.x) lfs[t] = Lf[t];
     const double ox = a.omega[d * 3], oy = a.omega[d * 3 + 1];
     if (lane_ok)
@@ -948,29 +969,34 @@ __global__ __launch_bounds__(256) void gen_inv_setup_kernel(GenSweepArgs a, TO* 
         }
     __syncthreads();
     // row i of A: volume terms, then the outflow points of the faces through
-    // node i (all in FP64 whatever the stored type)
+    // node i; r_i: the inflow points of its boundary faces (all in FP64
+    // whatever the stored type)
     double A[N], E[N];
     {
         const double sK = reinterpret_cast<const double*>(a.sigma_t)[K];
-        const double* M = reinterpret_cast<const double*>(a.Mk) + ((long)K * N + i) * N;
         const double* gx = reinterpret_cast<const double*>(a.Gx) + ((long)K * N + i) * N;
         const double* gy = reinterpret_cast<const double*>(a.Gy) + ((long)K * N + i) * N;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            A[j] = sK * M[j] - ox * gx[j] - oy * gy[j];
+            A[j] = sK * Mk[i * N + j] - ox * gx[j] - oy * gy[j];
             E[j] = j == i ? 1.0 : 0.0;
         }
     }
+    double r = 0.0;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         const int c = face_pos<NB>(f, i);
         if (c < 0) continue;
+        const bool bdr = a.nbr[K * 4 + f] < 0 && pbar;
+        const double* pb = bdr ? pbar + ((long)d * a.nbf + a.bface_of[K * 4 + f]) * nq : nullptr;
         for (int q = 0; q < nq; ++q) {
             const double on = fon[wv][es][f * nq + q];
+            const double lc = lfs[c * nq + q];
             if (on > 0.0) {
-                const double lc = lfs[c * nq + q];
 #pragma unroll
                 for (int c2 = 0; c2 < NB; ++c2) A[face_node<NB>(f, c2)] += on * lc * lfs[c2 * nq + q];
+            } else if (on < 0.0 && bdr) {
+                r -= on * lc * pb[q];
             }
         }
     }
@@ -993,9 +1019,16 @@ __global__ __launch_bounds__(256) void gen_inv_setup_kernel(GenSweepArgs a, TO* 
 #pragma unroll
     for (int j = 0; j < N; ++j) E[j] *= rd;   // row i of A^-1
     const long dK = (long)d * ne + K;
-    if (act) {
+    // row i of H = A^-1 M and c = A^-1 r
+    double cval = 0.0;
 #pragma unroll
-        for (int j = 0; j < N; ++j) invA[(dK * N + j) * N + i] = (TO)E[j];
+    for (int k = 0; k < N; ++k) cval += E[k] * shfl_t(r, r0 + k);
+    if (act) invC[dK * N + i] = (TO)cval;
+    for (int j = 0; j < N; ++j) {
+        double h = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) h += E[k] * Mk[k * N + j];
+        if (act) invA[(dK * N + j) * N + i] = (TO)h;
     }
     unsigned mask = 0;
 #pragma unroll
@@ -1021,15 +1054,16 @@ __global__ __launch_bounds__(256) void gen_inv_setup_kernel(GenSweepArgs a, TO* 
                     g += E[face_node<NB>(f, c)] * F;
                 }
             }
-            if (act) invG[((dK * 4 + f) * NB + c2) * N + i] = (TO)g;
+            if (act) invG[(dK * N + i) * 4 * NB + f * NB + c2] = (TO)g;
         }
         if (use) mask |= 1u << f;
     }
     if (act && i == 0) inmask[dK] = (uint8_t)mask;
 }
 
-// psi_K = A^-1 (M S_K + the boundary inflow of K) for every element and
-// direction: the part of the element solution that needs no upwind element
+// psi_K = H S_K (+ c when the sweep takes the boundary inflow) for every
+// element and direction: the part of the element solution that needs no
+// upwind element.  Every load is independent of the others.
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void gen_inv_particular_kernel(GenSweepArgs a) {
     constexpr int N = NB * NB;
@@ -1040,120 +1074,199 @@ __global__ __launch_bounds__(256) void gen_inv_particular_kernel(GenSweepArgs a)
     const int i = lane - eslot * N;
     const bool lane_ok = eslot < EPW;
     const int es = lane_ok ? eslot : 0;
-    const int nq = a.nq, ne = a.ne;
+    const int ne = a.ne;
     const int Kr = (blockIdx.x * 4 + wv) * EPW + es;
     const bool act = lane_ok && Kr < ne;
     const int K = act ? Kr : 0;
-    __shared__ T bs[4][EPW][N];
-    __shared__ T lfs[NB * GEN_MAXQ];
-    for (int t = threadIdx.x; t < NB * nq; t += blockDim.x) lfs[t] = reinterpret_cast<const T*>(a.Lf)[t];
-    __syncthreads();
-    const T ox = (T)a.omega[d * 3], oy = (T)a.omega[d * 3 + 1];
-    const T* S = reinterpret_cast<const T*>(a.S) + (a.s_aniso ? (long)d * ne * N : 0) + (long)K * N;
-    const T* M = reinterpret_cast<const T*>(a.Mk) + ((long)K * N + i) * N;
-    const T* nds = reinterpret_cast<const T*>(a.nds);
-    const T* pbar = reinterpret_cast<const T*>(a.psibar);
-    T b = T(0);
-#pragma unroll
-    for (int j = 0; j < N; ++j) b += M[j] * S[j];
-    if (pbar) {
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            const int c = face_pos<NB>(f, i);
-            if (c < 0 || a.nbr[K * 4 + f] >= 0) continue;
-            const T* pb = pbar + ((long)d * a.nbf + a.bface_of[K * 4 + f]) * nq;
-            for (int q = 0; q < nq; ++q) {
-                const T* nn = nds + (((long)K * 4 + f) * nq + q) * 2;
-                const T on = ox * nn[0] + oy * nn[1];
-                if (on < T(0)) b -= on * lfs[c * nq + q] * pb[q];
-            }
-        }
-    }
-    if (lane_ok) bs[wv][es][i] = b;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const long dK = (long)d * ne + K;
-    const T* Ai = reinterpret_cast<const T*>(a.invA) + dK * N * N + i;
-    T x = T(0);
+    const gcptr<T> S = as_global(reinterpret_cast<const T*>(a.S)) + (a.s_aniso ? (long)d * ne * N : 0) + (long)K * N;
+    const gcptr<T> H = as_global(reinterpret_cast<const T*>(a.invA)) + dK * N * N + i;
+    T x = a.psibar ? as_global(reinterpret_cast<const T*>(a.invC))[dK * N + i] : T(0);
 #pragma unroll
-    for (int j = 0; j < N; ++j) x += Ai[(long)j * N] * bs[wv][es][j];
-    if (act) reinterpret_cast<T*>(a.psi)[dK * N + i] = x;
+    for (int j = 0; j < N; ++j) x += H[(long)j * N] * S[j];
+    if (act) as_global(reinterpret_cast<T*>(a.psi))[dK * N + i] = x;
 }
+
+// What a lane needs of its element for the level pass, loaded one work item
+// ahead: the element, its inflow mask and graph bits, its neighbours and
+// their face numbering, psi from the parallel pass and its row of G (4 NB
+// contiguous values, loaded as 16-byte vectors).
+template <typename T, int NB>
+struct InvItem {
+    static constexpr int NG = 4 * NB;
+    static constexpr int NV = NG / Vec16<T>::n;        // 16-byte vectors in a row of G
+    static constexpr int VPL = (NG + NB * NB - 1) / (NB * NB);   // face values a lane loads
+    int K;
+    unsigned m, up;
+    int nb[VPL];         // the neighbour across the face of each of the lane's face values
+    unsigned code[VPL];  // and its face number (bit 2: its points run the other way)
+    T x;
+    T g[NG];
+};
 
 // The levels: psi_K += sum over the faces of inmask of G_f v_f, v_f the
 // neighbour's face nodes from this sweep (upstream in the graph) or the
-// lagged one.  One workgroup per (direction, tile) as in the row kernel.
+// lagged one.  One workgroup per (direction, tile) as in the row kernel; the
+// work items (a level, or a workgroup-wide share of a wide level) are taken
+// in order, the next one's data loaded while the current one waits for its
+// neighbours.  Each of the 4 NB face values of an element is loaded once, by
+// one of its lanes (zero for faces without inflow from a neighbour), and
+// handed to the others through LDS.
 template <typename T, int NB, int WAVES, bool GENERAL>
 __global__ __launch_bounds__(64 * WAVES) void gen_inv_sweep_kernel(GenSweepArgs a) {
     constexpr int N = NB * NB;
     constexpr int EPW = 64 / N;
+    constexpr int PER = WAVES * EPW;
+    constexpr int NG = InvItem<T, NB>::NG;
+    constexpr int NV = InvItem<T, NB>::NV;
+    constexpr int VPL = InvItem<T, NB>::VPL;
+    typedef typename Vec16<T>::type VT;
+    static_assert(NG % Vec16<T>::n == 0, "rows of G come in 16-byte vectors");
     const int d = blockIdx.x;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int eslot = lane / N;
     const int i = lane - eslot * N;
     const bool lane_ok = eslot < EPW;
+    const int es = lane_ok ? eslot : 0;
+    const int slot = wv * EPW + eslot;
     const int ne = a.ne;
-    const gcptr<T> G = as_global(reinterpret_cast<const T*>(a.invG));
+    __shared__ __attribute__((aligned(16))) T vs[WAVES][EPW][NG];
+    const gcptr<VT> G = as_global(reinterpret_cast<const VT*>(a.invG));
     const gcptr<T> plag = as_global(reinterpret_cast<const T*>(a.psi_lag));
     const gptr<T> psi = as_global(reinterpret_cast<T*>(a.psi));
-    const uint8_t* inm = a.inmask + (long)d * ne;
-    const uint8_t* upf = a.upflag + (long)d * ne;
+    const gcptr<uint8_t> inm = as_global(a.inmask) + (long)d * ne;
+    const gcptr<uint8_t> upf = as_global(a.upflag) + (long)d * ne;
+    const gcptr<int> nbr = as_global(a.nbr);
+    const gcptr<uint8_t> nbfc = as_global(a.nbr_face);
     const int* lp = a.lev_ptr + ((long)d * a.ntiles + blockIdx.y) * (a.nlev + 1);
-    const int* le = a.lev_elem + (long)d * ne;
-    for (int l = 0; l < a.nlev; ++l) {
-        const int beg = lp[l], end = lp[l + 1];
-        for (int base = beg; base < end; base += WAVES * EPW) {
-            const int e = base + wv * EPW + eslot;
-            if (lane_ok && e < end) {
-                const int K = le[e];
-                const long dK = (long)d * ne + K;
-                const unsigned m = inm[K], up = upf[K];
-                T x = psi[dK * N + i];
+    const gcptr<int> le = as_global(a.lev_elem) + (long)d * ne;
+    // work items in order: (level l, first position base, end of the level);
+    // past the last level an item is empty
+    struct Pos {
+        int l, base, end;
+    };
+    auto advance = [&](const Pos& p) __attribute__((always_inline)) {
+        Pos q = p;
+        if (q.l >= a.nlev) return q;
+        q.base += PER;
+        if (q.base >= q.end) {
+            ++q.l;
+            q.base = q.end;
+            q.end = q.l < a.nlev ? lp[q.l + 1] : q.end;
+        }
+        return q;
+    };
+    auto loadK = [&](const Pos& p) __attribute__((always_inline)) {
+        const int e = p.base + slot;
+        return p.l < a.nlev && lane_ok && e < p.end ? le[e] : -1;
+    };
+    auto loadData = [&](int Kr, InvItem<T, NB>& it) __attribute__((always_inline)) {
+        it.K = Kr;
+        const int K = Kr < 0 ? 0 : Kr;
+        const long dK = (long)d * ne + K;
+        it.m = inm[K];
+        it.up = upf[K];
 #pragma unroll
-                for (int f = 0; f < 4; ++f) {
-                    if (!((m >> f) & 1)) continue;
-                    const gcptr<T> src = ((up >> f) & 1) ? gcptr<T>(psi) : plag;
-                    if (!src) continue;
-                    const int Nb = a.nbr[K * 4 + f];
-                    const int fN = GENERAL ? (int)(a.nbr_face[K * 4 + f] & 3) : ((f + 2) & 3);
-                    const gcptr<T> v = src + ((long)d * ne + Nb) * N;
-                    const gcptr<T> g = G + (dK * 4 + f) * NB * N + i;
+        for (int r = 0; r < VPL; ++r) {
+            const int t = r * N + i;
+            const int f = (t < NG ? t : 0) / NB;
+            it.nb[r] = nbr[K * 4 + f];
+            it.code[r] = GENERAL ? (unsigned)nbfc[K * 4 + f] : (unsigned)((f + 2) & 3);
+        }
+        it.x = psi[dK * N + i];
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) x += g[c * N] * v[face_node<NB>(fN, c)];
-                }
-                psi[dK * N + i] = x;
+        for (int q = 0; q < NV; ++q) {
+            const VT w = G[(dK * N + i) * NV + q];
+#pragma unroll
+            for (int k = 0; k < Vec16<T>::n; ++k) it.g[q * Vec16<T>::n + k] = w[k];
+        }
+    };
+    if (a.nlev < 1) return;
+    // P0: the item being solved (its data in X), P1: the next one (its element
+    // in kY), P2: the one after (its element loaded into kX while X is in use)
+    Pos P0{0, lp[0], lp[1]};
+    Pos P1 = advance(P0);
+    Pos P2 = advance(P1);
+    InvItem<T, NB> A, B;
+    int kA = 0, kB = loadK(P1);
+    loadData(loadK(P0), A);
+    // One item: the face values are loaded first, then the element two items
+    // ahead and the next item's data, so that waiting for the face values
+    // leaves those in flight (the load counter drains in issue order); the two
+    // item buffers swap roles from one call to the next, so no register copy
+    // waits for a load.
+    auto item = [&](InvItem<T, NB>& X, InvItem<T, NB>& Y, int& kX, int& kY) __attribute__((always_inline)) {
+        T fv[VPL];
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+            const int t = r * N + i;
+            fv[r] = T(0);
+            if (X.K >= 0 && t < NG) {
+                const int f = t / NB, c = t - f * NB;
+                const bool upstream = (X.up >> f) & 1;
+                const bool ok = ((X.m >> f) & 1) && (upstream || plag);
+                const gcptr<T> src = upstream ? gcptr<T>(psi) : plag;
+                const int fN = (int)(X.code[r] & 3);
+                const int node = fN == 0 ? c : (fN == 1 ? NB - 1 + NB * c : (fN == 2 ? c + NB * (NB - 1) : NB * c));
+                if (ok) fv[r] = src[((long)d * ne + X.nb[r]) * N + node];
             }
         }
-        __syncthreads();
+        kX = loadK(P2);
+        loadData(kY, Y);
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+            const int t = r * N + i;
+            if (lane_ok && t < NG) vs[wv][es][t] = fv[r];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (X.K >= 0) {
+            T x = X.x;
+#pragma unroll
+            for (int t = 0; t < NG; ++t) x += X.g[t] * vs[wv][es][t];
+            psi[((long)d * ne + X.K) * N + i] = x;
+        }
+        // the next item's face values overwrite vs
+        __builtin_amdgcn_wave_barrier();
+        if (P1.l != P0.l) __syncthreads();
+        P0 = P1;
+        P1 = P2;
+        P2 = advance(P2);
+    };
+    while (P0.l < a.nlev) {
+        item(A, B, kA, kB);
+        if (P0.l >= a.nlev) break;
+        item(B, A, kB, kA);
     }
 }
 
 template <typename TO, int NB>
-static hipError_t launch_inv_setup_t(const GenSweepArgs& a, void* invA, void* invG, uint8_t* inmask, hipStream_t s) {
+static hipError_t launch_inv_setup_t(const GenSweepArgs& a, void* invA, void* invC, void* invG, uint8_t* inmask,
+                                     hipStream_t s) {
     constexpr int EPW = 64 / (NB * NB);
     const dim3 grid((a.ne + 4 * EPW - 1) / (4 * EPW), a.nd);
     if (a.nbr_face)
-        hipLaunchKernelGGL((gen_inv_setup_kernel<TO, NB, true>), grid, dim3(256), 0, s, a, (TO*)invA, (TO*)invG,
-                           inmask);
+        hipLaunchKernelGGL((gen_inv_setup_kernel<TO, NB, true>), grid, dim3(256), 0, s, a, (TO*)invA, (TO*)invC,
+                           (TO*)invG, inmask);
     else
-        hipLaunchKernelGGL((gen_inv_setup_kernel<TO, NB, false>), grid, dim3(256), 0, s, a, (TO*)invA, (TO*)invG,
-                           inmask);
+        hipLaunchKernelGGL((gen_inv_setup_kernel<TO, NB, false>), grid, dim3(256), 0, s, a, (TO*)invA, (TO*)invC,
+                           (TO*)invG, inmask);
     return hipGetLastError();
 }
 
-hipError_t launch_gen_inv_setup(bool out_fp64, const GenSweepArgs& a, void* invA, void* invG, uint8_t* inmask,
-                                hipStream_t s) {
+hipError_t launch_gen_inv_setup(bool out_fp64, const GenSweepArgs& a, void* invA, void* invC, void* invG,
+                                uint8_t* inmask, hipStream_t s) {
     if (a.nq > GEN_MAXQ || 4 * a.nq > 64) return hipErrorInvalidValue;
     switch (a.nb) {
-        case 2: return out_fp64 ? launch_inv_setup_t<double, 2>(a, invA, invG, inmask, s)
-                                : launch_inv_setup_t<float, 2>(a, invA, invG, inmask, s);
-        case 3: return out_fp64 ? launch_inv_setup_t<double, 3>(a, invA, invG, inmask, s)
-                                : launch_inv_setup_t<float, 3>(a, invA, invG, inmask, s);
-        case 4: return out_fp64 ? launch_inv_setup_t<double, 4>(a, invA, invG, inmask, s)
-                                : launch_inv_setup_t<float, 4>(a, invA, invG, inmask, s);
-        case 5: return out_fp64 ? launch_inv_setup_t<double, 5>(a, invA, invG, inmask, s)
-                                : launch_inv_setup_t<float, 5>(a, invA, invG, inmask, s);
+        case 2: return out_fp64 ? launch_inv_setup_t<double, 2>(a, invA, invC, invG, inmask, s)
+                                : launch_inv_setup_t<float, 2>(a, invA, invC, invG, inmask, s);
+        case 3: return out_fp64 ? launch_inv_setup_t<double, 3>(a, invA, invC, invG, inmask, s)
+                                : launch_inv_setup_t<float, 3>(a, invA, invC, invG, inmask, s);
+        case 4: return out_fp64 ? launch_inv_setup_t<double, 4>(a, invA, invC, invG, inmask, s)
+                                : launch_inv_setup_t<float, 4>(a, invA, invC, invG, inmask, s);
+        case 5: return out_fp64 ? launch_inv_setup_t<double, 5>(a, invA, invC, invG, inmask, s)
+                                : launch_inv_setup_t<float, 5>(a, invA, invC, invG, inmask, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1163,9 +1276,15 @@ static hipError_t launch_inv_levels(const GenSweepArgs& a, hipStream_t s) {
     constexpr int EPW = 64 / (NB * NB);
     const int need = (a.maxw + EPW - 1) / EPW;
     const dim3 grid(a.nd, a.ntiles);
-    if (need > 8)
-        hipLaunchKernelGGL((gen_inv_sweep_kernel<T, NB, 16, GENERAL>), grid, dim3(1024), 0, s, a);
-    else if (need > 4)
+    // 16 waves leave 128 VGPRs a lane, too few for two FP64 work items at p = 4
+    constexpr bool wide_ok = !(sizeof(T) == 8 && NB >= 5);
+    if constexpr (wide_ok) {
+        if (need > 8) {
+            hipLaunchKernelGGL((gen_inv_sweep_kernel<T, NB, 16, GENERAL>), grid, dim3(1024), 0, s, a);
+            return hipGetLastError();
+        }
+    }
+    if (need > 4)
         hipLaunchKernelGGL((gen_inv_sweep_kernel<T, NB, 8, GENERAL>), grid, dim3(512), 0, s, a);
     else if (need > 2)
         hipLaunchKernelGGL((gen_inv_sweep_kernel<T, NB, 4, GENERAL>), grid, dim3(256), 0, s, a);
@@ -1176,14 +1295,34 @@ static hipError_t launch_inv_levels(const GenSweepArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// part 1: the particular pass, 2: the levels, 3: both
+template <typename T, int NB>
+static hipError_t launch_inv_part_t(const GenSweepArgs& a, int part, hipStream_t s) {
+    constexpr int EPW = 64 / (NB * NB);
+    if (part & 1) {
+        hipLaunchKernelGGL((gen_inv_particular_kernel<T, NB>), dim3((a.ne + 4 * EPW - 1) / (4 * EPW), a.nd),
+                           dim3(256), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (part & 2) return a.nbr_face ? launch_inv_levels<T, NB, true>(a, s) : launch_inv_levels<T, NB, false>(a, s);
+    return hipSuccess;
+}
+
 template <typename T, int NB>
 static hipError_t launch_inv_t(const GenSweepArgs& a, hipStream_t s) {
-    constexpr int EPW = 64 / (NB * NB);
-    hipLaunchKernelGGL((gen_inv_particular_kernel<T, NB>), dim3((a.ne + 4 * EPW - 1) / (4 * EPW), a.nd), dim3(256),
-                       0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return a.nbr_face ? launch_inv_levels<T, NB, true>(a, s) : launch_inv_levels<T, NB, false>(a, s);
+    return launch_inv_part_t<T, NB>(a, 3, s);
+}
+
+hipError_t launch_gen_inv_part(bool fp64, const GenSweepArgs& a, int part, hipStream_t s) {
+    if (!a.invA || a.nq > GEN_MAXQ || 4 * a.nq > 64 || part < 1 || part > 3) return hipErrorInvalidValue;
+    switch (a.nb) {
+        case 2: return fp64 ? launch_inv_part_t<double, 2>(a, part, s) : launch_inv_part_t<float, 2>(a, part, s);
+        case 3: return fp64 ? launch_inv_part_t<double, 3>(a, part, s) : launch_inv_part_t<float, 3>(a, part, s);
+        case 4: return fp64 ? launch_inv_part_t<double, 4>(a, part, s) : launch_inv_part_t<float, 4>(a, part, s);
+        case 5: return fp64 ? launch_inv_part_t<double, 5>(a, part, s) : launch_inv_part_t<float, 5>(a, part, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1272,7 +1411,6 @@ __global__ __launch_bounds__(256) void moments_f32_wide_kernel(const float* __re
     }
 }
 
-typedef double v2d __attribute__((ext_vector_type(2)));
 
 __global__ __launch_bounds__(256) void moments_f64_wide_kernel(const double* __restrict__ psi, int nd, long L,
                                                                const double* __restrict__ W, int ldw,
@@ -2396,7 +2534,6 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, f
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
 }
 
-typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
 // Input k-slots of the matrix-core sweep.  Slot (t, g) -- MFMA step t, lane
 // group g -- holds source value g QS + t of the element while that is below

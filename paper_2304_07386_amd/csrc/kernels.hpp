@@ -56,17 +56,23 @@ struct GenSweepArgs {
     const void* psi_lag;         // [nd][ne][n] or null
     void* psi;                   // [nd][ne][n]
     // stored element operators (sweep type; null: assemble and eliminate
-    // per sweep): A^-1 [nd][ne][n][n] by column, face operators
-    // [nd][ne][4][nb][n] and the inflow-face mask [nd][ne]
+    // per sweep): A^-1 M [nd][ne][n][n] by column, A^-1 r [nd][ne][n] (r the
+    // boundary inflow terms), face operators [nd][ne][4][nb][n] and the
+    // inflow-face mask [nd][ne]
     const void* invA;
+    const void* invC;
     const void* invG;
     const uint8_t* inmask;
 };
 hipError_t launch_sweep_general(bool fp64, const GenSweepArgs& a, hipStream_t s);
-// Build the stored element operators of the general sweep (FP64 tables in a,
-// output in FP64 or FP32); invA, invG, inmask sized as in GenSweepArgs.
-hipError_t launch_gen_inv_setup(bool out_fp64, const GenSweepArgs& a, void* invA, void* invG, uint8_t* inmask,
-                                hipStream_t s);
+// Build the stored element operators of the general sweep (FP64 tables and
+// inflow in a, output in FP64 or FP32); invA, invC, invG, inmask sized as in
+// GenSweepArgs.
+hipError_t launch_gen_inv_setup(bool out_fp64, const GenSweepArgs& a, void* invA, void* invC, void* invG,
+                                uint8_t* inmask, hipStream_t s);
+// One part of a sweep with the stored operators (a.invA set): 1 the
+// particular pass, 2 the levels, 3 both.
+hipError_t launch_gen_inv_part(bool fp64, const GenSweepArgs& a, int part, hipStream_t s);
 
 // mom[16 rows used 8][L] = W[16][nd] psi[nd][L] on the matrix cores
 hipError_t launch_moments(bool fp64, const void* psi, int nd, long L, const void* W, int ldw,

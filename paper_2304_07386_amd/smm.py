@@ -36,7 +36,7 @@ EXPORTED = [
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
     "smm_batch_history", "smm_debug_mg_level", "smm_debug_batch_precond", "smm_debug_batch_spmv",
     "smm_debug_batch_grouped", "smm_debug_sweep_graph", "smm_batch_apply_sweep", "smm_apply_G_noalloc", "smm_solve_history",
-    "smm_debug_batch_sweep_shape", "smm_debug_cg_mg_level",
+    "smm_debug_batch_sweep_shape", "smm_debug_cg_mg_level", "smm_time_sweep_parts",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
@@ -150,6 +150,8 @@ def load_library(path: str = LIB_PATH):
         "smm_batch_history": (ip, [vp, ip, ip, vp, vp, C.POINTER(ip)]),
         "smm_debug_mg_level": (ip, [vp, ip, vp, C.POINTER(ip), C.POINTER(ip)]),
         "smm_debug_cg_mg_level": (ip, [vp, ip, vp, C.POINTER(ip), C.POINTER(ip)]),
+        "smm_time_sweep_parts": (ip, [vp, ip, ip, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]),
         "smm_debug_batch_precond": (ip, [vp, ip, C.POINTER(vp), C.POINTER(vp)]),
         "smm_debug_batch_spmv": (ip, [vp, C.POINTER(vp), C.POINTER(vp)]),
         "smm_debug_batch_grouped": (ip, [vp, ip]),
@@ -639,6 +641,13 @@ def smm_debug_mg_level(prob, level: int):
     _check(lib.smm_debug_mg_level(prob.handle, level, _ptr(A), C.byref(nx), C.byref(ny)), prob.ctx)
     return A, nx.value, ny.value
 
+
+def smm_time_sweep_parts(prob, precision: int, reps: int):
+    """(setup, particular, levels) ms of a sweep with stored element operators."""
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(load_library().smm_time_sweep_parts(prob.handle, int(precision), int(reps), C.byref(a), C.byref(b),
+                                               C.byref(c)), prob.ctx)
+    return a.value, b.value, c.value
 
 def smm_debug_cg_mg_level(prob, level: int):
     """9-point stencil [9][nvy*nvx] of a multigrid level of the CG system's
