@@ -420,8 +420,8 @@ def curved_sweeps(L, ctx, log):
     and FP64 time per sweep and units/s; its parts (the one-off build of the
     operators, the parallel pass psi = A^-1 (M S + inflow), the levels); the
     levels and the time per level; the parallel pass against HBM at its
-    algorithmic bytes ((n^2 + n) values per element and direction: A^-1 read,
-    psi written); and, for comparison, the sweep that assembles and
+    algorithmic bytes ((n^2 + 2n) values per element and direction: H = A^-1 M
+    and c read, psi written); and, for comparison, the sweep that assembles and
     eliminates every element's system in each sweep (sweep path 5)."""
     from workloads import config_curved_mms
 
@@ -442,7 +442,7 @@ def curved_sweeps(L, ctx, log):
         run["fp32_parts_ms"] = {"operator_build": setup, "particular": part, "levels": lev_ms}
         run["levels"] = nlev
         run["us_per_level"] = 1e3 * lev_ms / nlev
-        gbs = 4.0 * pairs * (n * n + n) / (part * 1e-3) / 1e9
+        gbs = 4.0 * pairs * (n * n + 2 * n) / (part * 1e-3) / 1e9
         run["roofline_fp32"] = {"bound": "hbm", "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
                                 "traffic": None, "kernel": "gen_inv_particular_kernel"}
         L.smm_set_sweep_path(prob, 5)
