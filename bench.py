@@ -373,13 +373,13 @@ def moment_discretisations(L, ctx, log):
 
 def block_jacobi_sweeps(L, ctx, log):
     """Parallel block Jacobi sweep (Sec. 6.5) on the channel problem (128 x
-    128, p = 2, S12): time of one FP32 sweep of the per-element kernel (one
-    workgroup per direction and tile, one lane per element) for several tile sizes, outer
-    iterations and wall time to a 1e-8 outer residual (CG moment system,
-    FP32 delta sweeps), beside the tabulated Cartesian sweep, which has no
-    tiled form.  The per-element kernel assembles and eliminates every
-    element and direction: 165 flops per elem*angle*DOF at p = 2, on the FP32
-    vector units."""
+    128, p = 2, S12): time of one FP32 sweep of the per-element sweep with
+    stored element operators (one workgroup per direction and tile) for
+    several tile sizes, with its parts (the parallel pass, the levels),
+    outer iterations and wall time to a 1e-8 outer residual (CG moment
+    system, FP32 delta sweeps), beside the tabulated Cartesian sweep, which
+    has no tiled form, and the assembling per-element sweep (sweep path 5)
+    on 32 x 32 tiles."""
     import torch
     from workloads import config_channel
 
@@ -389,10 +389,11 @@ def block_jacobi_sweeps(L, ctx, log):
     units = float(wl.n_elem * (wl.p + 1) ** 2 * 84)
     res = {"workload": "channel 128x128 p=2 S12, FP32 delta sweeps, CG moment system, outer 1e-8",
            "units_per_sweep": units, "runs": []}
-    for tiles in ((0, 0), (128, 128), (32, 32), (16, 16), (8, 8)):
+    for tiles, path in (((0, 0), 0), ((128, 128), 0), ((32, 32), 0), ((16, 16), 0), ((8, 8), 0), ((32, 32), 5)):
         p = L.problem_from_workload(ctx, wl)
         if tiles != (0, 0):
             L.smm_set_sweep_tiles(p, *tiles)
+        L.smm_set_sweep_path(p, path)
         ms = L.smm_time_sweep(p, L.SMM_FP32_SWEEP, 5)
         L.smm_solve(p, L.smm_default_opts(**{**common, "max_outer": 1}), raise_on_noconv=False)  # set-up
         torch.cuda.synchronize()
@@ -400,14 +401,17 @@ def block_jacobi_sweeps(L, ctx, log):
         rc, info = L.smm_solve(p, L.smm_default_opts(**common), raise_on_noconv=False)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        kind = "tabulated Cartesian sweep (full)" if tiles == (0, 0) else \
-            f"per-element sweep, tiles {tiles[0]}x{tiles[1]}"
+        if tiles == (0, 0):
+            kind = "tabulated Cartesian sweep (full)"
+        elif path == 5:
+            kind = f"assembling per-element sweep, tiles {tiles[0]}x{tiles[1]}"
+        else:
+            kind = f"stored-operator sweep, tiles {tiles[0]}x{tiles[1]}"
         run = {"kernel": kind, "tiles": list(tiles), "sweep_ms": ms, "units_per_s": units / (ms * 1e-3),
                "solve_s": t, "converged": rc == L.SMM_OK, "outer": info["iterations"]}
-        if tiles != (0, 0):
-            tf = 165.0 * units / (ms * 1e-3) / 1e12
-            run["roofline"] = {"bound": "alu", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
-                               "traffic": None, "kernel": "sweep_lane_general_kernel"}
+        if tiles != (0, 0) and path == 0:
+            _, part, lev = L.smm_time_sweep_parts(p, L.SMM_FP32_SWEEP, 5)
+            run["parts_ms"] = {"particular": part, "levels": lev}
         res["runs"].append(run)
         log(f"{kind}: sweep {ms:.3f} ms, solve {t * 1e3:.1f} ms, {info['iterations']} outer")
         L.smm_problem_destroy(p)

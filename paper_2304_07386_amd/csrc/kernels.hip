@@ -8,6 +8,10 @@
 //                         by one wavefront; levels come from the sweep graph.
 //  * sweep_lane_general_kernel  The same at p <= 2 with one lane per element:
 //                         the augmented system stays in registers.
+//  * gen_inv_*            Curved meshes with stored element operators: the
+//                         inverses built once in parallel, a sweep being one
+//                         parallel pass and a pass over the levels that adds
+//                         the upwind faces' contributions.
 //  * moments_kernel       Angular moments mom = W psi on the matrix cores.
 //  * closure / rhs / cg   SMM correction tensor and boundary factor, the IP
 //                         right-hand side, FP64 block-Jacobi PCG.
