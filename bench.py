@@ -477,7 +477,7 @@ def fp32_error(L, ctx, batch, probs, wls, log):
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     v32 = outputs()
     o64 = L.smm_default_opts(precision=L.SMM_FP64, delta_sweeps=0, outer_tol=1e-10, inner_tol=1e-12,
-                             inner_adapt=1e-2, max_inner=20000, max_outer=150, precond=L.SMM_PRECOND_TWOLEVEL,
+                             inner_adapt=3e-3, max_inner=20000, max_outer=150, precond=L.SMM_PRECOND_TWOLEVEL,
                              use_graph=1, anderson=2)
     rc, _ = L.smm_batch_solve(batch, o64, raise_on_noconv=False)
     v64 = outputs()
@@ -553,6 +553,8 @@ def main():
                     help="run only the block Jacobi sweep comparison and print its JSON")
     ap.add_argument("--curved-only", action="store_true",
                     help="run only the curved-mesh sweep timings and print their JSON")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="run only the warm-up and timed batch solves and print their time and phases")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the batched FP32 sweep of the 256-problem batch (tuned, then 10 timed "
                          "sweeps) and print its roofline JSON")
@@ -561,7 +563,7 @@ def main():
         print("bench.py measures one GPU: there is no multi-GPU path (the problems of a batch are "
               "independent and would be split across GPUs by the caller)", file=sys.stderr)
         sys.exit(2)
-    only = args.disc_only or args.tiles_only or args.curved_only or args.sweep_only
+    only = args.disc_only or args.tiles_only or args.curved_only or args.sweep_only or args.solve_only
 
     # the CPU baseline runs first: its worker processes start before this
     # process touches the GPU
@@ -605,8 +607,12 @@ def main():
     log(f"batch of {args.problems} problems: {units:.4g} units per sweep, {dofs:.4g} DOF, "
         f"set-up {time.time() - t0:.1f} s")
 
+    # inner tolerance 3e-3 x the last outer residual: looser inner solves stall
+    # the outer iteration of the most scattering members (1e-2: 17 outer
+    # iterations at most, 1e-1: no convergence in 150), tighter ones cost more
+    # PCG iterations than the outer iterations they save
     opts = L.smm_default_opts(precision=L.SMM_FP32_SWEEP, delta_sweeps=1, outer_tol=1e-8,
-                              inner_tol=1e-10, inner_adapt=1e-2, max_inner=20000, max_outer=150,
+                              inner_tol=1e-10, inner_adapt=3e-3, max_inner=20000, max_outer=150,
                               precond=args.precond, use_graph=1, anderson=args.anderson)
     for _ in range(max(args.warmup, 1)):                         # also autotunes the sweep grids
         L.smm_batch_solve(batch, opts, raise_on_noconv=False)
@@ -632,6 +638,11 @@ def main():
     log(f"{args.steps} solves to 1e-8: {ms_per_step:.1f} ms each (min {1e3 * min(walls):.1f}); outer iterations "
         f"mean {its_last.mean():.2f} max {its_last.max()}; per solve " +
         ", ".join(f"{n} {v:.2f} ms" for n, v in phase.items()) + f"; batched PCG iterations {cg_its}")
+    if args.solve_only:
+        print(json.dumps({"ms_per_step": ms_per_step, "value": value, "phase_ms_per_step": phase,
+                          "batched_pcg_iterations_per_step": cg_its}))
+        L.smm_batch_destroy(batch)
+        return
 
     sweep_ms = L.smm_batch_time_kernel(batch, L.SMM_KERNEL_SWEEP_FP32, 5)
     # the sweep against the method's unit roofline: 8 B per elem*angle*DOF in
