@@ -462,8 +462,15 @@ int smm_debug_batch_sweep_shape(smm_batch* batch, int shape);
 /* Testing hook: choose the batch's PCG kernels: 1 the type-group kernels
  * (one wave per group of elements sharing their blocks), 0 the per-node
  * kernels, -1 the automatic choice (group fill).  Results agree up to the
- * summation order.  SMM_EUNSUPPORTED if the batch has no type groups. */
+ * summation order.  Drops the captured PCG and outer-iteration graphs.
+ * SMM_EUNSUPPORTED if the batch has no type groups. */
 int smm_debug_batch_grouped(smm_batch* batch, int grouped);
+/* Testing hook: 1 (the default) runs the per-order launches of each PCG
+ * phase concurrently on forked streams when the batch holds more than one
+ * order, 0 one after the other on the context stream.  The launches touch
+ * disjoint problems, so results are bitwise the same.  Drops the captured
+ * PCG and outer-iteration graphs.  SMM_EINVAL outside 0..1. */
+int smm_debug_batch_cg_fork(smm_batch* batch, int fork);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems (uniform Cartesian meshes, isotropic

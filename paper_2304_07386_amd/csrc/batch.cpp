@@ -136,6 +136,7 @@ struct smm_batch {
     double* d_gpart = nullptr;
     bool grouped = false;          // groups filled densely enough for the grouped PCG kernels
     bool grouped_auto = false;     // that choice before any testing override
+    bool cg_fork = true;           // the per-order PCG launches on forked side streams
     // two-level preconditioner (precond = 1): per-level flat vertex arrays
     bool use_mg = false;
     std::string mg_error;          // why the two-level preconditioner is unavailable (empty: available)
@@ -981,6 +982,18 @@ int batch_autotune(smm_batch* B, bool fp64) {
     return SMM_OK;
 }
 
+// the side streams and events of the PCG iterations' forked per-order
+// launches (the sweep's, which are idle while the PCG runs), or none
+static const CgFork* cg_fork(smm_batch* B, CgFork& F) {
+    if (!B->cg_fork || B->groups.size() < 2) return nullptr;
+    for (int k = 0; k < 3; ++k) {
+        F.side[k] = B->side[k];
+        F.join[k] = B->ev_join[k];
+    }
+    F.fork = B->ev_fork;
+    return &F;
+}
+
 // started: the PCG start and done0 iterations were already launched (by an
 // outer-iteration graph)
 int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its, bool started = false, int done0 = 0) {
@@ -1049,7 +1062,8 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its, boo
                 hipGraph_t g = nullptr;
                 hipGraphExec_t ge = nullptr;
                 HIPCHK(c, hipStreamBeginCapture(B->cap, hipStreamCaptureModeRelaxed));
-                const hipError_t e1 = b_cg_iterations(Lk, k, B->cap, &B->mgl);
+                CgFork F;
+                const hipError_t e1 = b_cg_iterations(Lk, k, B->cap, &B->mgl, cg_fork(B, F));
                 const hipError_t e2 = hipStreamEndCapture(B->cap, &g);
                 if (e1 != hipSuccess || e2 != hipSuccess) {
                     if (g) (void)hipGraphDestroy(g);
@@ -1062,7 +1076,8 @@ int batch_cg(smm_batch* B, double tol, int max_inner, std::vector<int>& its, boo
             }
             HIPCHK(c, hipGraphLaunch(it->second, c->stream));
         } else {
-            HIPCHK(c, b_cg_iterations(Lk, k, c->stream, &B->mgl));
+            CgFork F;
+            HIPCHK(c, b_cg_iterations(Lk, k, c->stream, &B->mgl, cg_fork(B, F)));
         }
         done_its += k;
         B->cg_batched_its += k;
@@ -1262,12 +1277,14 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
                 HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
                 BatchLaunch Lk = Lg;
                 Lk.order_mask = mask;
+                CgFork cgf;
                 hipError_t e = b_source(fp64, Lg, !first, cs);
                 int src = e == hipSuccess ? batch_sweep(B, fp64, first, cs) : SMM_EHIP;
                 if (src == SMM_OK) {
                     hipError_t ek[8] = {b_moments(fp64, Lg, true, first, cs), b_closures_rhs(Lg, cs), b_copy_x(Lg, cs),
                                         b_cg_start(Lg, o.inner_tol, cs, &B->mgl),
-                                        b_cg_iterations(Lk, k, cs, &B->mgl), b_residual(Lg, B->d_rout, cs),
+                                        b_cg_iterations(Lk, k, cs, &B->mgl, cg_fork(B, cgf)),
+                                        b_residual(Lg, B->d_rout, cs),
                                         aa > 0 ? b_aa_store(Lg, slot, cs) : hipSuccess,
                                         aa > 0 ? b_aa_gram(Lg, B->d_aapart, B->d_aadot, cs) : hipSuccess};
                     for (hipError_t x : ek)
@@ -1836,10 +1853,25 @@ int smm_debug_batch_sweep_shape(smm_batch* batch, int shape) {
     return SMM_OK;
 }
 
+int smm_debug_batch_cg_fork(smm_batch* batch, int fork) {
+    if (!batch || fork < 0 || fork > 1) return SMM_EINVAL;
+    batch->cg_fork = fork == 1;
+    for (auto& kv : batch->cg_graphs) (void)hipGraphExecDestroy(kv.second);
+    batch->cg_graphs.clear();
+    for (auto& kv : batch->it_graphs) (void)hipGraphExecDestroy(kv.second);
+    batch->it_graphs.clear();
+    return SMM_OK;
+}
+
 int smm_debug_batch_grouped(smm_batch* batch, int grouped) {
     if (!batch || grouped < -1 || grouped > 1) return SMM_EINVAL;
     if (grouped == 1 && batch->ngroups == 0) return fail(batch->ctx, SMM_EUNSUPPORTED, "batch has no type groups");
     batch->grouped = grouped < 0 ? batch->grouped_auto : grouped == 1;
+    // captured graphs hold the other kernels
+    for (auto& kv : batch->cg_graphs) (void)hipGraphExecDestroy(kv.second);
+    batch->cg_graphs.clear();
+    for (auto& kv : batch->it_graphs) (void)hipGraphExecDestroy(kv.second);
+    batch->it_graphs.clear();
     return SMM_OK;
 }
 

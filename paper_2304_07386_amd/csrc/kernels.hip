@@ -4114,16 +4114,6 @@ static void b_cg_k1_all(const BatchLaunch& B, hipStream_t s) {
     go(b_cg_k1<5>, 5);
 }
 
-static void b_cg_k2_all(const BatchLaunch& B, hipStream_t s) {
-    auto go = [&](auto kfn, int nb) {
-        const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
-        if (ng > 0 && (B.order_mask >> nb & 1)) hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B);
-    };
-    go(b_cg_k2<2>, 2);
-    go(b_cg_k2<3>, 3);
-    go(b_cg_k2<4>, 4);
-    go(b_cg_k2<5>, 5);
-}
 
 // coarse iterate of a problem on the vertex grid after b_mg_apply
 __device__ __forceinline__ const double* mg_x0(const MGLaunch& M, int prob) {
@@ -4287,17 +4277,59 @@ hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const MGLaunch* M) {
+// The grouped kernels of one phase, one launch per active order: on the
+// caller's stream, or (F set, more than one order) forked over side streams.
+template <typename Launch>
+static hipError_t per_order(const BatchLaunch& B, hipStream_t s, const CgFork* F, Launch go) {
+    int orders[4], no = 0;
+    for (int nb = 2; nb <= 5; ++nb)
+        if (B.g_nb0[nb + 1] > B.g_nb0[nb] && (B.order_mask >> nb & 1)) orders[no++] = nb;
+    if (!F || no < 2) {
+        for (int k = 0; k < no; ++k) go(orders[k], s);
+        return hipSuccess;
+    }
+    hipError_t e = hipEventRecord(F->fork, s);
+    for (int k = 1; k < no && e == hipSuccess; ++k) e = hipStreamWaitEvent(F->side[k - 1], F->fork, 0);
+    if (e != hipSuccess) return e;
+    go(orders[no - 1], s);   // the highest order on the caller's stream
+    for (int k = 1; k < no && e == hipSuccess; ++k) {
+        go(orders[k - 1], F->side[k - 1]);
+        e = hipEventRecord(F->join[k - 1], F->side[k - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, F->join[k - 1], 0);
+    }
+    return e;
+}
+
+hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const MGLaunch* M, const CgFork* F) {
+    const dim3 blk(256);
+    auto grid = [&](int nb) { return dim3((B.g_nb0[nb + 1] - B.g_nb0[nb] + 3) / 4); };
     for (int k = 0; k < iters; ++k) {
+        hipError_t e = hipSuccess;
         if (B.grouped)
-            b_cg_k1_all(B, s);
+            e = per_order(B, s, F, [&](int nb, hipStream_t st) {
+                switch (nb) {
+                    case 2: hipLaunchKernelGGL(b_cg_k1<2>, grid(2), blk, 0, st, B); break;
+                    case 3: hipLaunchKernelGGL(b_cg_k1<3>, grid(3), blk, 0, st, B); break;
+                    case 4: hipLaunchKernelGGL(b_cg_k1<4>, grid(4), blk, 0, st, B); break;
+                    default: hipLaunchKernelGGL(b_cg_k1<5>, grid(5), blk, 0, st, B); break;
+                }
+            });
         else
             hipLaunchKernelGGL(b_cg_k1n, dim3(B.nblocks), dim3(BT), 0, s, B);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(b_cg_red1, dim3(B.nprob), dim3(BT), 0, s, B);
         if (B.grouped)
-            b_cg_k2_all(B, s);
+            e = per_order(B, s, F, [&](int nb, hipStream_t st) {
+                switch (nb) {
+                    case 2: hipLaunchKernelGGL(b_cg_k2<2>, grid(2), blk, 0, st, B); break;
+                    case 3: hipLaunchKernelGGL(b_cg_k2<3>, grid(3), blk, 0, st, B); break;
+                    case 4: hipLaunchKernelGGL(b_cg_k2<4>, grid(4), blk, 0, st, B); break;
+                    default: hipLaunchKernelGGL(b_cg_k2<5>, grid(5), blk, 0, st, B); break;
+                }
+            });
         else
             hipLaunchKernelGGL(b_cg_k2n, dim3(B.nblocks), dim3(BT), 0, s, B);
+        if (e != hipSuccess) return e;
         if (B.mg) {
             hipError_t e = b_cgl_apply(B, *M, s);
             if (e != hipSuccess) return e;
@@ -4306,19 +4338,18 @@ hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const
         }
         const MGLaunch Mv = B.mg ? *M : MGLaunch{};
         hipLaunchKernelGGL(b_cg_red2, dim3(B.nprob), dim3(BT), 0, s, B, Mv);
-        if (B.grouped) {
-            auto go = [&](auto kfn, int nb) {
-                const int ng = B.g_nb0[nb + 1] - B.g_nb0[nb];
-                if (ng > 0 && (B.order_mask >> nb & 1))
-                    hipLaunchKernelGGL(kfn, dim3((ng + 3) / 4), dim3(256), 0, s, B, Mv);
-            };
-            go(b_cg_k3g<2>, 2);
-            go(b_cg_k3g<3>, 3);
-            go(b_cg_k3g<4>, 4);
-            go(b_cg_k3g<5>, 5);
-        } else {
+        if (B.grouped)
+            e = per_order(B, s, F, [&](int nb, hipStream_t st) {
+                switch (nb) {
+                    case 2: hipLaunchKernelGGL(b_cg_k3g<2>, grid(2), blk, 0, st, B, Mv); break;
+                    case 3: hipLaunchKernelGGL(b_cg_k3g<3>, grid(3), blk, 0, st, B, Mv); break;
+                    case 4: hipLaunchKernelGGL(b_cg_k3g<4>, grid(4), blk, 0, st, B, Mv); break;
+                    default: hipLaunchKernelGGL(b_cg_k3g<5>, grid(5), blk, 0, st, B, Mv); break;
+                }
+            });
+        else
             hipLaunchKernelGGL(b_cg_k3, dim3(B.nblocks), dim3(BT), 0, s, B, Mv);
-        }
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }

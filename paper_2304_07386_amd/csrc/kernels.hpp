@@ -250,7 +250,17 @@ hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s);
 hipError_t b_copy_x(const BatchLaunch& B, hipStream_t s);               // x = varphi
 hipError_t b_shift(const BatchLaunch& B, hipStream_t s);                // varphi_prev = varphi, varphi = x
 hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s, const MGLaunch* M);
-hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const MGLaunch* M);
+// Side streams for the per-order launches of a PCG iteration: with more than
+// one order active, each grouped phase forks from the caller's stream, runs
+// the orders concurrently and joins again (graph capture turns this into
+// parallel branches).
+struct CgFork {
+    hipStream_t side[3];
+    hipEvent_t fork;
+    hipEvent_t join[3];
+};
+hipError_t b_cg_iterations(const BatchLaunch& B, int iters, hipStream_t s, const MGLaunch* M,
+                           const CgFork* F = nullptr);
 hipError_t b_cg_spmv(const BatchLaunch& B, hipStream_t s);                // one q = A p launch
 hipError_t b_precond(const BatchLaunch& B, const MGLaunch* M, hipStream_t s); // z = M^-1 r (and p = z)
 hipError_t b_residual(const BatchLaunch& B, double* out, hipStream_t s);   // out[2*nprob]

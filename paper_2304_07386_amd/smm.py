@@ -36,7 +36,7 @@ EXPORTED = [
     "smm_batch_time_sweep", "smm_batch_units", "smm_batch_phase_times", "smm_batch_time_kernel",
     "smm_batch_history", "smm_debug_mg_level", "smm_debug_batch_precond", "smm_debug_batch_spmv",
     "smm_debug_batch_grouped", "smm_debug_sweep_graph", "smm_batch_apply_sweep", "smm_apply_G_noalloc", "smm_solve_history",
-    "smm_debug_batch_sweep_shape", "smm_debug_cg_mg_level", "smm_time_sweep_parts",
+    "smm_debug_batch_sweep_shape", "smm_debug_cg_mg_level", "smm_time_sweep_parts", "smm_debug_batch_cg_fork",
     # smm_cnn.h
     "smm_cnn_create", "smm_cnn_destroy", "smm_cnn_num_params", "smm_cnn_set_params", "smm_cnn_get_params",
     "smm_cnn_forward", "smm_cnn_loss_grad", "smm_cnn_adam_step", "smm_batch_warmstart_dims",
@@ -156,6 +156,7 @@ def load_library(path: str = LIB_PATH):
         "smm_debug_batch_spmv": (ip, [vp, C.POINTER(vp), C.POINTER(vp)]),
         "smm_debug_batch_grouped": (ip, [vp, ip]),
         "smm_debug_batch_sweep_shape": (ip, [vp, ip]),
+        "smm_debug_batch_cg_fork": (ip, [vp, ip]),
         "smm_cnn_create": (ip, [vp, ip, C.POINTER(ip), ip, ip, ip, C.POINTER(vp)]),
         "smm_cnn_destroy": (ip, [vp]),
         "smm_cnn_num_params": (ip, [vp, C.POINTER(C.c_size_t)]),
@@ -625,6 +626,10 @@ def smm_batch_apply_sweep(batch, precision: int, sources, k: int):
 def smm_debug_batch_sweep_shape(batch, shape: int):
     """Force the batched sweep's kernel shape: 0 column-wave, 1 element-lane, -1 autotuned."""
     _check(load_library().smm_debug_batch_sweep_shape(batch.handle, shape), batch.ctx)
+
+
+def smm_debug_batch_cg_fork(batch, fork: int):
+    _check(load_library().smm_debug_batch_cg_fork(batch.handle, int(fork)), batch.ctx)
 
 
 def smm_debug_batch_grouped(batch, grouped: int):

@@ -78,3 +78,38 @@ def test_grouped_solve_matches_per_node_and_oracle(ctx, precond):
         ref, _ = osmm.solve(pr, tol=1e-13, max_it=200)
         assert rel_l2(outs[1][k], ref) < 1e-11, k
     L.smm_batch_destroy(batch)
+
+
+@pytest.mark.parametrize("use_graph", [1, 0], ids=["graph", "eager"])
+def test_forked_pcg_launches_bitwise(ctx, use_graph):
+    """The per-order launches of each PCG phase run concurrently on forked
+    streams (the default) or one after the other; they touch disjoint
+    problems, so the solves agree bit for bit, replayed from graphs or not."""
+    announce(f"batched solves, forked vs serial per-order PCG launches, use_graph={use_graph}")
+    wls = [config_plain(12, p, 4) for p in (1, 2, 3, 4)] + [config_blobs(20007, n=10, p=3, sn=4),
+                                                            config_channel(n=9, side=1.3)]
+    probs = [L.problem_from_workload(ctx, wl) for wl in wls]
+    batch = L.smm_batch_create(ctx, probs)
+    L.smm_debug_batch_grouped(batch, 1)
+    outs, its = {}, {}
+    for fork in (1, 0, 1):
+        L.smm_debug_batch_cg_fork(batch, fork)
+        o = _opts(L.SMM_FP32_SWEEP, 1e-9)
+        o.precond = L.SMM_PRECOND_TWOLEVEL
+        o.delta_sweeps = 1
+        o.use_graph = use_graph
+        o.anderson = 2
+        rc, infos = L.smm_batch_solve(batch, o)
+        assert rc == L.SMM_OK, fork
+        vs = []
+        for k, p in enumerate(probs):
+            v = np.zeros(p.n_elem * p.n_node)
+            L.smm_batch_get_outputs(batch, k, varphi=v)
+            vs.append(v)
+        key = len(outs)
+        outs[key], its[key] = vs, [i["iterations"] for i in infos]
+    for k in range(len(probs)):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+        assert np.array_equal(outs[0][k], outs[2][k]), k
+    assert its[0] == its[1] == its[2]
+    L.smm_batch_destroy(batch)
