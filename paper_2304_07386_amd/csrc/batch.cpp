@@ -853,23 +853,29 @@ int batch_sweep(smm_batch* B, bool fp64, bool inflow, hipStream_t st) {
     const int f = fp64 ? 1 : 0;
     const int ng = (int)B->groups.size();
     // groups one after the other on the caller's stream, or forked over
-    // nstr side streams (chosen by the autotuner)
-    const int nstr = std::min(B->sweep_streams[f] > 0 ? B->sweep_streams[f] : 1, 4);
+    // nstr side streams, or (nstr = 5) the first group (the most work) on the
+    // caller's stream, where it is dispatched first, and the others over 3
+    // side streams, so that four streams suffice where the process has four
+    // hardware queues (chosen by the autotuner)
+    const int nstr = std::min(B->sweep_streams[f] > 0 ? B->sweep_streams[f] : 1, 5);
+    const bool with_main = nstr == 5;
+    const int nside = with_main ? 3 : nstr;
     const bool fork = ng > 1 && nstr > 1;
+    const int nfork = std::min(with_main ? ng - 1 : ng, nside);   // side streams in use
     HIPCHK(c, zero_ints(B->d_sweep_counters, ng, st));
     if (fork) {
         HIPCHK(c, hipEventRecord(B->ev_fork, st));
-        for (int k = 0; k < std::min(ng, nstr); ++k) HIPCHK(c, hipStreamWaitEvent(B->side[k], B->ev_fork, 0));
+        for (int k = 0; k < nfork; ++k) HIPCHK(c, hipStreamWaitEvent(B->side[k], B->ev_fork, 0));
     }
     for (int k = 0; k < ng; ++k) {
         Group& G = B->groups[k];
-        hipStream_t s = fork ? B->side[k % nstr] : st;
+        hipStream_t s = !fork ? st : (!with_main ? B->side[k % nside] : (k == 0 ? st : B->side[(k - 1) % nside]));
         int grid = G.grid[f] > 0 ? G.grid[f] : std::min<int>((int)G.tasks.size(), 2 * B->ncu);
         hipError_t e = group_sweep(B, G, fp64, G.shape[f] > 0 ? G.shape[f] : 0, grid, B->d_args[f][inflow ? 1 : 0], s);
         if (e != hipSuccess) return fail(c, SMM_EHIP, std::string("batched sweep: ") + hipGetErrorString(e));
     }
     if (fork)
-        for (int k = 0; k < std::min(ng, nstr); ++k) {
+        for (int k = 0; k < nfork; ++k) {
             HIPCHK(c, hipEventRecord(B->ev_join[k], B->side[k]));
             HIPCHK(c, hipStreamWaitEvent(st, B->ev_join[k], 0));
         }
@@ -956,7 +962,7 @@ int batch_autotune(smm_batch* B, bool fp64) {
         if (B->groups.size() > 1) {
             float best_ms = 1e30f;
             int best = 1;
-            for (int ns : {1, 2, 4}) {
+            for (int ns : {1, 2, 4, 5}) {
                 B->sweep_streams[f] = ns;
                 float ms_tot = 0;
                 for (int rep = 0; rep < 3; ++rep) {
