@@ -665,6 +665,12 @@ def main():
                            for wl in wls))
     rl_spmv = roofline_flops("b_cg_k1", "one q = A p over the batch (the per-order launches b_cg_k1<NB>)",
                              spmv_flops, 16.0 * dofs, spmv_ms)
+    # the angular moments of the last FP32 sweep (MFMA contraction over the
+    # directions): psi read once (4 B/unit), 8 FP64 moment rows written (64 B/DOF)
+    mom_ms = L.smm_batch_time_kernel(batch, L.SMM_KERNEL_MOMENTS_FP32, 20)
+    rl_mom = roofline("b_moments_kernel", "the angular moments of one FP32 sweep over the batch (8 rows, FP64 out)",
+                      4.0 * units + 64.0 * dofs, mom_ms)
+    log(f"moments {mom_ms:.3f} ms, {rl_mom['achieved']:.0f} GB/s ({rl_mom['frac']:.3f} of HBM)")
     log(f"sweep {sweep_ms:.3f} ms -> {units / sweep_ms / 1e-3:.3e} units/s, frac {rl_sweep['frac']:.3f} of the "
         f"8 B/unit roofline (own bytes {rl_sweep['kernel_own_gbs']:.0f} GB/s); PCG q=Ap {spmv_ms * 1e3:.1f} us, "
         f"{rl_spmv['achieved']:.2f} TFLOP/s")
@@ -705,6 +711,7 @@ def main():
         "sweep_only": {"ms": sweep_ms, "units_per_s": units / (sweep_ms * 1e-3)},
         "roofline": rl_sweep,
         "roofline_pcg_spmv": rl_spmv,
+        "roofline_moments": rl_mom,
         "fp32_error": err,
         "critical_path": crit,
         "paper_context": PAPER_CONTEXT,

@@ -513,10 +513,13 @@ int smm_batch_history(const smm_batch* batch, int k, int max_len, double* residu
  * back-to-back launches of one batched kernel: SMM_KERNEL_SWEEP_FP32 /
  * SMM_KERNEL_SWEEP_FP64 (one whole batched sweep), SMM_KERNEL_CG_SPMV (the
  * PCG kernel q = A p with its partial dot products, on the state left by the
- * last smm_batch_solve; SMM_ESTATE before any solve). */
+ * last smm_batch_solve), SMM_KERNEL_MOMENTS_FP32 (the angular moments of the
+ * last FP32 sweep into the work moments, which the solve's outputs do not
+ * read); SMM_ESTATE before any solve for the last two. */
 #define SMM_KERNEL_SWEEP_FP32 0
 #define SMM_KERNEL_SWEEP_FP64 1
 #define SMM_KERNEL_CG_SPMV 2
+#define SMM_KERNEL_MOMENTS_FP32 3
 int smm_batch_time_kernel(smm_batch* batch, int kernel, int reps, double* ms_avg);
 
 #ifdef __cplusplus

@@ -1732,12 +1732,32 @@ int smm_batch_time_kernel(smm_batch* batch, int kernel, int reps, double* ms_avg
     int rc;
     if (kernel == SMM_KERNEL_SWEEP_FP32 || kernel == SMM_KERNEL_SWEEP_FP64)
         return smm_batch_time_sweep(batch, kernel == SMM_KERNEL_SWEEP_FP64 ? SMM_FP64 : SMM_FP32_SWEEP, reps, ms_avg);
-    if (kernel != SMM_KERNEL_CG_SPMV) return fail(c, SMM_EINVAL, "smm_batch_time_kernel: unknown kernel");
+    if (kernel != SMM_KERNEL_CG_SPMV && kernel != SMM_KERNEL_MOMENTS_FP32)
+        return fail(c, SMM_EINVAL, "smm_batch_time_kernel: unknown kernel");
     if (!batch->have_outputs) return fail(c, SMM_ESTATE, "smm_batch_time_kernel: run smm_batch_solve first");
     HIPCHK(c, hipSetDevice(c->device));
     batch->active.assign(batch->nprob, 1);
     if ((rc = put(c, batch->d_active, batch->active.data(), sizeof(int) * batch->nprob))) return rc;
     const BatchLaunch L = launch_desc(batch);
+    if (kernel == SMM_KERNEL_MOMENTS_FP32) {
+        // non-accumulating: the work moments only (equal to the accumulated
+        // ones when the last solve did not use delta sweeps, and then the
+        // same values again)
+        hipEvent_t e0, e1;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        HIPCHK(c, b_moments(false, L, false, false, c->stream));
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int k = 0; k < reps; ++k) HIPCHK(c, b_moments(false, L, false, false, c->stream));
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *ms_avg = ms / reps;
+        return SMM_OK;
+    }
     // a CG state on the last right-hand side (x, b, p untouched by the timed launches
     // except q and the partial sums)
     HIPCHK(c, b_copy_x(L, c->stream));

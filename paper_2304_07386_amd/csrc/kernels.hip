@@ -2957,8 +2957,9 @@ __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accum
     double out[4][4];
     if constexpr (sizeof(T) == 4) {
         v4f a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
-        // U steps of 4 directions per round, all their loads issued first
-        constexpr int U = 4;
+        // U steps of 4 directions per round, all their loads issued first (2:
+        // more steps in flight touch more rows of psi at once and ran slower)
+        constexpr int U = 2;
         const auto pg = as_global(reinterpret_cast<const v4f*>(psi));
         for (int k0 = 0; k0 < nd; k0 += 4 * U) {
             v4f bv[U];

@@ -549,7 +549,7 @@ def smm_batch_time_sweep(batch: Batch, precision: int, reps: int) -> float:
     return ms.value
 
 
-SMM_KERNEL_SWEEP_FP32, SMM_KERNEL_SWEEP_FP64, SMM_KERNEL_CG_SPMV = 0, 1, 2
+SMM_KERNEL_SWEEP_FP32, SMM_KERNEL_SWEEP_FP64, SMM_KERNEL_CG_SPMV, SMM_KERNEL_MOMENTS_FP32 = 0, 1, 2, 3
 
 
 def smm_batch_phase_times(batch: Batch):
