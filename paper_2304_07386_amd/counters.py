@@ -16,7 +16,8 @@ hipMemcpy (calibration).  Then, anywhere:
 
 reads the per-dispatch counters (KiB), scales each counter by what it reads
 for the copy of known size, and writes the HBM bytes per launch of each
-kernel, with the SHA-256 of the kernel source they were taken on.  An
+kernel (q = A p, the sweep, the angular moments of one sweep), with the
+SHA-256 of the kernel source they were taken on.  An
 optional third pass (`--pmc` with FLOP_COUNTERS, parsed with `--flops`) adds
 the floating-point work the hardware issued for q = A p and the sweep.  Besides
 q = A p and the sweep it records the other kernels of one PCG iteration (the
@@ -36,6 +37,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 512 << 20
 SWEEP_REPS = 2
 SPMV_REPS = 5
+MOM_REPS = 3
 
 
 def run():
@@ -53,6 +55,7 @@ def run():
     L.smm_batch_solve(batch, o, raise_on_noconv=False)
     L.smm_batch_time_kernel(batch, L.SMM_KERNEL_SWEEP_FP32, SWEEP_REPS)
     L.smm_batch_time_kernel(batch, L.SMM_KERNEL_CG_SPMV, SPMV_REPS)
+    L.smm_batch_time_kernel(batch, L.SMM_KERNEL_MOMENTS_FP32, MOM_REPS)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(2):
@@ -148,9 +151,12 @@ def parse(dir_fetch, dir_write, out, dir_flops=None):
         sweeps = [v for n, v in disp if _is_sweep(n)]
         # the timed sweeps: the last SWEEP_REPS * (launches per sweep) dispatches
         sw = sweeps[-SWEEP_REPS * sweep_launches():]
+        # the moments of one whole sweep: the last MOM_REPS launches
+        mom = [v for n, v in disp if "b_moments_kernel" in n][-MOM_REPS:]
         res[which] = {"scale": scale, "copy_kib": big,
                       "b_cg_k1": 1024.0 * scale * sum(spmv) / SPMV_REPS,
-                      SWEEP: 1024.0 * scale * sum(sw) / SWEEP_REPS}
+                      SWEEP: 1024.0 * scale * sum(sw) / SWEEP_REPS,
+                      "b_moments_kernel": 1024.0 * scale * sum(mom) / max(len(mom), 1)}
         # the other kernels of one PCG iteration, from the short solve (every
         # problem still iterating): the mean dispatch of each kernel, summed
         # over the per-order launches
@@ -164,7 +170,7 @@ def parse(dir_fetch, dir_write, out, dir_flops=None):
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()
     table = {}
-    for k in ("b_cg_k1", SWEEP, "b_cg_k2", "b_cg_k3g", "cgl_kernel"):
+    for k in ("b_cg_k1", SWEEP, "b_cg_k2", "b_cg_k3g", "cgl_kernel", "b_moments_kernel"):
         table[k] = {"bytes_per_launch": res["fetch"][k] + res["write"][k],
                     "fetch_bytes": res["fetch"][k], "write_bytes": res["write"][k],
                     "source": "kernels.hip", "sha256": sha}
