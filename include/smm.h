@@ -206,8 +206,9 @@ typedef struct {
     double residual_abs;     /* last absolute max-norm change */
     int cg_iterations_total;
     int cg_iterations_max;
-    double t_total_ms;       /* wall time of the solve (host clock) */
-    double t_setup_ms;       /* one-time setup at the first solve (device tables) */
+    double t_total_ms;       /* wall time of the whole solve call, t_setup_ms included (host clock) */
+    double t_setup_ms;       /* before the first outer iteration: device tables on the first
+                              * solve, and building the start (diffusion solve, network) */
     /* device time of the outer-iteration phases, summed over the outer
      * iterations (HIP events on the context's stream; in a batch, the batch's
      * launches, which cover every problem): */
