@@ -185,7 +185,8 @@ typedef struct {
                             relative residual max(inner_tol, inner_adapt * r_{k-1})
                             (r_0 = 1; per problem in a batch), and the solves that
                             build a diffusion or learned start at
-                            max(inner_tol, inner_adapt); 0: always inner_tol */
+                            max(inner_tol, inner_adapt) unless start_tol is set; 0: always
+                            inner_tol */
     int discretization;  /* SMM_DISC_IP (default) or SMM_DISC_CG.  SMM_DISC_CG solves the
                             continuous moment system of Sec. 5.1 (one unknown per node of the
                             (nx p + 1) x (ny p + 1) grid of V_p) by FP64 preconditioned CG
@@ -198,6 +199,9 @@ typedef struct {
                             re-assembles the moment system; a batch keeps the value its problems had
                             when it was created (another value: SMM_EUNSUPPORTED).  A value that
                             makes the operator indefinite ends the solve with SMM_EBREAKDOWN. */
+    double start_tol;    /* > 0: the relative residual at which the moment solve that builds a
+                            diffusion or learned start stops; 0 (default): max(inner_tol,
+                            inner_adapt) when inner_adapt > 0, else inner_tol */
 } smm_solve_opts;
 
 typedef struct {

@@ -418,6 +418,7 @@ void smm_default_opts(smm_solve_opts* o) {
     o->anderson = 0;
     o->discretization = SMM_DISC_IP;
     o->kappa_scale = 1.0;
+    o->start_tol = 0.0;
 }
 
 }  // extern "C"
@@ -992,6 +993,7 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     smm_ctx* c = P.ctx;
     if (c->device < 0) return fail(c, SMM_ESTATE, "host-only context");
     if (!P.have_mat) return fail(c, SMM_ESTATE, "materials not set");
+    if (!(o.start_tol >= 0)) return fail(c, SMM_EINVAL, "start_tol must be >= 0");
     if (o.discretization != SMM_DISC_IP && o.discretization != SMM_DISC_CG)
         return fail(c, SMM_EINVAL, "smm_solve: discretization must be SMM_DISC_IP or SMM_DISC_CG");
     const bool cgdisc = o.discretization == SMM_DISC_CG;
@@ -1043,8 +1045,8 @@ int smm_solve(smm_problem* prob, const smm_solve_opts* opts, const double* varph
     } else if (o.start == SMM_START_DIFFUSION) {
         HIPCHK(c, hipMemcpyAsync(D.b, D.bfix, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemsetAsync(D.x, 0, sizeof(double) * L, c->stream));
-        rc = cgdisc ? cg_moment_solve(prob, o.inner_tol, o.max_inner, &its, o.use_graph != 0)
-                    : moment_solve(prob, o.inner_tol, o.max_inner, &its);
+        rc = cgdisc ? cg_moment_solve(prob, start_tol(o), o.max_inner, &its, o.use_graph != 0)
+                    : moment_solve(prob, start_tol(o), o.max_inner, &its);
         if (rc) return rc;
         HIPCHK(c, hipMemcpyAsync(D.varphi, D.x, sizeof(double) * L, hipMemcpyDeviceToDevice, c->stream));
     } else {

@@ -106,6 +106,8 @@ struct smm_problem {
 namespace smm {
 int fail(smm_ctx* c, int code, const std::string& msg);
 int batch_solve_single(smm_problem* pr, const smm_solve_opts& o, const double* varphi0, smm_solve_info* info);
+// tolerance of the moment solve that builds a diffusion or learned start
+double start_tol(const smm_solve_opts& o);
 int batch_outputs_single(smm_problem* pr, double* varphi, double* phi, double* J, double* T, double* beta,
                          int on_device);
 void batch_release_single(smm_problem* pr);

@@ -1113,24 +1113,12 @@ int ws_dims(smm_batch* B, int* nf, int* nt, int* ny, int* nx) {
 // varphi_D: the moment system with zero correction source, kept per problem.
 int batch_diffusion(smm_batch* B, double tol, int max_inner, std::vector<int>& its) {
     smm_ctx* c = B->ctx;
-    for (int b = 0; b < B->nprob; ++b) {
-        const PerProb& q = B->pp[b];
-        const size_t bytes = sizeof(double) * B->hP[b].L;
-        HIPCHK(c, hipMemcpyAsync(q.b, q.bfix, bytes, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemsetAsync(q.x, 0, bytes, c->stream));
-    }
+    HIPCHK(c, b_start_vectors(launch_desc(B), 4, c->stream));   // b = bfix, x = 0
     int rc;
     if ((rc = batch_cg(B, tol, max_inner, its))) return rc;
     HIPCHK(c, b_ws_store_diffusion(launch_desc(B), c->stream));
     B->have_diff = true;
     return SMM_OK;
-}
-
-// Tolerance of the moment solves that build a start (diffusion, learned): a
-// start only seeds the fixed point, so with inexact inner solves it is solved
-// to the first outer iteration's tolerance.
-double start_tol(const smm_solve_opts& o) {
-    return o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt) : o.inner_tol;
 }
 
 // Learned start: the network predicts, from the features of the diffusion
@@ -1192,6 +1180,7 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     B->ws_used.assign(np, 0);
     if (o.precond != SMM_PRECOND_BJ && o.precond != SMM_PRECOND_TWOLEVEL)
         return fail(c, SMM_EINVAL, "smm_batch_solve: unknown preconditioner");
+    if (!(o.start_tol >= 0)) return fail(c, SMM_EINVAL, "smm_batch_solve: start_tol must be >= 0");
     if (o.precond == SMM_PRECOND_TWOLEVEL && !B->mg_error.empty()) return fail(c, SMM_EUNSUPPORTED, B->mg_error);
     B->use_graph = o.use_graph != 0;
     B->use_mg = o.precond == SMM_PRECOND_TWOLEVEL;
@@ -1206,28 +1195,23 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
     const BatchLaunch L = launch_desc(B);
     std::vector<int> its;
     std::vector<smm_solve_info> inf(np, smm_solve_info{});
-    // initial guesses
-    for (int b = 0; b < np; ++b) {
-        const PerProb& q = B->pp[b];
-        const size_t bytes = sizeof(double) * B->hP[b].L;
-        HIPCHK(c, hipMemsetAsync(q.varphi_prev, 0, bytes, c->stream));
-        if (o.start == SMM_START_GIVEN && varphi0 && varphi0[b]) {
-            HIPCHK(c, hipMemcpyAsync(q.varphi, varphi0[b], bytes, hipMemcpyDefault, c->stream));
-        } else if (o.start == SMM_START_DIFFUSION) {
-            HIPCHK(c, hipMemcpyAsync(q.b, q.bfix, bytes, hipMemcpyDeviceToDevice, c->stream));
-            HIPCHK(c, hipMemsetAsync(q.x, 0, bytes, c->stream));
-        } else {
-            HIPCHK(c, hipMemsetAsync(q.varphi, 0, bytes, c->stream));
-        }
+    // initial guesses (one launch for the batch; given starts copied per problem)
+    if (o.start == SMM_START_GIVEN) {
+        HIPCHK(c, b_start_vectors(L, 1 | 2, c->stream));
+        for (int b = 0; b < np; ++b)
+            if (varphi0 && varphi0[b])
+                HIPCHK(c, hipMemcpyAsync(B->pp[b].varphi, varphi0[b], sizeof(double) * B->hP[b].L, hipMemcpyDefault,
+                                         c->stream));
+    } else if (o.start == SMM_START_DIFFUSION) {
+        HIPCHK(c, b_start_vectors(L, 1 | 4, c->stream));
+    } else {
+        HIPCHK(c, b_start_vectors(L, 1 | 2, c->stream));
     }
     std::vector<int> start_its(np, 0);
     if (o.start == SMM_START_DIFFUSION) {
         if ((rc = batch_cg(B, start_tol(o), o.max_inner, its))) return rc;
-        for (int b = 0; b < np; ++b) {
-            const PerProb& q = B->pp[b];
-            HIPCHK(c, hipMemcpyAsync(q.varphi, q.x, sizeof(double) * B->hP[b].L, hipMemcpyDeviceToDevice, c->stream));
-            start_its[b] = its[b];
-        }
+        HIPCHK(c, b_start_vectors(L, 8, c->stream));   // varphi = x
+        for (int b = 0; b < np; ++b) start_its[b] = its[b];
     } else if (o.start == SMM_START_LEARNED) {
         if ((rc = learned_start(B, o, start_its))) return rc;
     }
@@ -1513,6 +1497,14 @@ int batch_outputs(smm_batch* B, int b, double* varphi, double* phi, double* J, d
 }  // namespace
 
 namespace smm {
+// Tolerance of the moment solves that build a start (diffusion, learned): a
+// start only seeds the fixed point, so with inexact inner solves it is solved
+// to the first outer iteration's tolerance, unless the options set another.
+double start_tol(const smm_solve_opts& o) {
+    if (o.start_tol > 0) return o.start_tol;
+    return o.inner_adapt > 0 ? std::max(o.inner_tol, o.inner_adapt) : o.inner_tol;
+}
+
 
 int batch_solve_single(smm_problem* pr, const smm_solve_opts& o, const double* varphi0, smm_solve_info* info) {
     smm_ctx* c = pr->P.ctx;

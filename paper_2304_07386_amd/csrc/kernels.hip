@@ -3158,6 +3158,28 @@ __global__ __launch_bounds__(BT) void b_shift_kernel(BatchLaunch B) {
     P.varphi[t] = P.x[t];
 }
 
+// Vectors of a solve's start for every problem of the batch in one launch
+// (instead of a copy or fill per problem and vector): bit 1 varphi_prev = 0,
+// 2 varphi = 0, 4 b = bfix and x = 0, 8 varphi = x.
+__global__ __launch_bounds__(BT) void b_start_vectors_kernel(BatchLaunch B, int what) {
+    const EB m = eb_map(B);
+    if (m.K < 0) return;
+    const BProb& P = B.P[m.prob];
+    const long t = (long)m.K * P.n + m.i;
+    if (what & 1) P.varphi_prev[t] = 0.0;
+    if (what & 2) P.varphi[t] = 0.0;
+    if (what & 4) {
+        P.b[t] = P.bfix[t];
+        P.x[t] = 0.0;
+    }
+    if (what & 8) P.varphi[t] = P.x[t];
+}
+
+hipError_t b_start_vectors(const BatchLaunch& B, int what, hipStream_t s) {
+    hipLaunchKernelGGL(b_start_vectors_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, what);
+    return hipGetLastError();
+}
+
 hipError_t b_copy_x(const BatchLaunch& B, hipStream_t s) {
     hipLaunchKernelGGL(b_copy_x_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
     return hipGetLastError();

@@ -76,7 +76,7 @@ class smm_solve_opts(C.Structure):
                 ("inner_tol", C.c_double), ("max_inner", C.c_int), ("start", C.c_int),
                 ("delta_sweeps", C.c_int), ("use_graph", C.c_int), ("moment_path", C.c_int),
                 ("anderson", C.c_int), ("precond", C.c_int), ("inner_adapt", C.c_double),
-                ("discretization", C.c_int), ("kappa_scale", C.c_double)]
+                ("discretization", C.c_int), ("kappa_scale", C.c_double), ("start_tol", C.c_double)]
 
 
 class smm_solve_info(C.Structure):

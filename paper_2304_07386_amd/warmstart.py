@@ -43,14 +43,16 @@ def he_init(channels, seed: int) -> np.ndarray:
 
 
 def solve_opts(tol=1e-8, precision=L.SMM_FP32_SWEEP, start=L.SMM_START_DIFFUSION, inner_adapt=1e-2,
-               precond=L.SMM_PRECOND_TWOLEVEL, anderson=2):
+               precond=L.SMM_PRECOND_TWOLEVEL, anderson=2, start_tol=0.1):
     """Solve options used for data generation and the start comparisons:
     inexact moment solves tied to the outer residual, two-level PCG, Anderson
-    mixing of the outer iterates, PCG chunks from graphs."""
+    mixing of the outer iterates, PCG chunks from graphs; the moment solve
+    that builds a diffusion or learned start stops at relative residual
+    start_tol (the start only seeds the fixed point)."""
     o = L.smm_default_opts(precision=precision, outer_tol=tol, max_outer=200,
                            inner_tol=1e-10 if precision != L.SMM_FP64 else 1e-13, max_inner=20000,
                            delta_sweeps=1 if precision != L.SMM_FP64 else 0, use_graph=1,
-                           inner_adapt=inner_adapt, precond=precond, anderson=anderson)
+                           inner_adapt=inner_adapt, precond=precond, anderson=anderson, start_tol=start_tol)
     o.start = start
     return o
 

@@ -82,6 +82,28 @@ def test_kappa_scale_validation(ctx):
         assert e.value.code == L.SMM_EINVAL
 
 
+def test_start_tol_validation_and_use(ctx):
+    """start_tol: negative or NaN is refused (single solve and batch); a
+    diffusion start solved loosely reaches the same converged flux."""
+    _, p = make_pair(L, ctx, config_plain(4, 1, 4))
+    b = L.smm_batch_create(ctx, [p])
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(L.SmmError) as e:
+            L.smm_solve(p, L.smm_default_opts(start_tol=bad))
+        assert e.value.code == L.SMM_EINVAL
+        with pytest.raises(L.SmmError) as e:
+            L.smm_batch_solve(b, L.smm_default_opts(start_tol=bad))
+        assert e.value.code == L.SMM_EINVAL
+    L.smm_batch_destroy(b)
+    outs = []
+    for stol in (0.0, 0.3):
+        o = L.smm_default_opts(outer_tol=1e-11, inner_tol=1e-13, start=L.SMM_START_DIFFUSION, start_tol=stol)
+        rc, info = L.smm_solve(p, o)
+        assert rc == L.SMM_OK
+        outs.append(L.smm_get_outputs_host(p)["varphi"])
+    assert rel_l2(outs[1], outs[0]) < 1e-9
+
+
 @pytest.mark.parametrize("path", [0, 1])
 def test_nan_start_gives_enan(ctx, path):
     announce(f"NaN given start -> SMM_ENAN, moment path {path}")
