@@ -378,9 +378,10 @@ int smm_time_cg_spmv(smm_problem* prob, int reps, double* ms_avg);
  * Cartesian meshes; otherwise the per-element sweep with stored element
  * operators: the inverse of each (element, direction) left-hand side and its
  * inflow-face operators, built in parallel on first use after a change of
- * materials and kept in device memory, n_dir * n_elem * (n_node^2 +
- * 4 (p+1) n_node) values of the sweep type; where those would take more than
- * a quarter of the free device memory, the form of path 5); 1 = always the
+ * materials or inflow and kept in device memory, n_dir * n_elem *
+ * (n_node^2 + n_node + 4 (p+1) n_node) values of the sweep type; where
+ * those would take more than a quarter of the free device memory, the form
+ * of path 5); 1 = always the
  * per-element sweep (form as in 0); 2 = on Cartesian meshes, the element-row
  * kernel instead of the column-per-thread one; 3 = the per-element kernel
  * assembling and eliminating with one wave per element at every order; 4 =
