@@ -2935,13 +2935,19 @@ hipError_t b_sweep_mfma(int nb, bool multi, int tpw, int threads, size_t lds, in
 }
 
 // ---- moments (matrix cores), optional FP64 accumulation ----------------------
-// Wavefront w covers 64 columns of one problem (Lpad is a multiple of 4, so a
-// lane's 4 columns are 16-byte aligned; columns >= L read the zero padding).
+// A block of columns is 64 columns of one problem (Lpad is a multiple of 4, so
+// a lane's 4 columns are 16-byte aligned; columns >= L read the zero padding).
+// FP32: one workgroup of four waves per block; wave q contracts the rounds q,
+// q + 4, ... of 8 directions, the partial sums meet in LDS (added in the
+// order q = 0..3), and the 8 moment rows leave as whole rows, 64 consecutive
+// FP64 values per store (written column by column from the MFMA layout they
+// took 6 times the store requests and 40 % of the kernel's time).  FP64: one
+// wave per block, all directions.
 template <typename T>
 __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accumulate, int first) {
     const int lane = threadIdx.x & 63;
-    const long w = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (w >= B.nmw) return;
+    const long w = sizeof(T) == 4 ? (long)blockIdx.x : ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= B.nmw) return;   // FP32: uniform over the workgroup
     const int prob = bsearch_prob(B.mw0, B.nprob, w);
     if (!B.active[prob]) return;
     const BProb& P = B.P[prob];
@@ -2954,14 +2960,18 @@ __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accum
     if constexpr (sizeof(T) == 4) W = reinterpret_cast<const T*>(P.W32);
     else W = reinterpret_cast<const T*>(P.W64);
     const int nd = P.nd;
-    double out[4][4];
     if constexpr (sizeof(T) == 4) {
-        v4f a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
-        // U steps of 4 directions per round, all their loads issued first (2:
-        // more steps in flight touch more rows of psi at once and ran slower)
+        __shared__ v4f part[3][4][64];   // the accumulators of waves 1..3
+        __shared__ double tile[8][64];   // moment rows 0..7 of the block's columns
+        const int q = threadIdx.x >> 6;
+        v4f acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
+        // U steps of 4 directions per round, all their loads issued first (1
+        // or 4 ran slower)
         constexpr int U = 2;
         const auto pg = as_global(reinterpret_cast<const v4f*>(psi));
-        for (int k0 = 0; k0 < nd; k0 += 4 * U) {
+        for (int k0 = 4 * U * q; k0 < nd; k0 += 16 * U) {
             v4f bv[U];
             float av[U];
 #pragma unroll
@@ -2973,30 +2983,38 @@ __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accum
                 av[u] = dk < nd ? W[j * P.ldw + dk] : 0.f;
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][0], a0, 0, 0, 0);
-                a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][1], a1, 0, 0, 0);
-                a2 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][2], a2, 0, 0, 0);
-                a3 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][3], a3, 0, 0, 0);
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u][c], acc[c], 0, 0, 0);
+        }
+        if (q > 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) part[q - 1][c][lane] = acc[c];
+        }
+        __syncthreads();
+        if (q == 0) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] += part[p][c][lane];
+            // FP32 layout: row 4 kk + r, column 4 j + c
+            if (kk < 2) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) tile[4 * kk + r][4 * j + c] = (double)acc[c][r];
             }
         }
-        // FP32 layout: row 4 kk + r
-        for (int r = 0; r < 4; ++r) {
-            out[r][0] = a0[r];
-            out[r][1] = a1[r];
-            out[r][2] = a2[r];
-            out[r][3] = a3[r];
-        }
-        if (kk < 2 && colok) {
-            for (int r = 0; r < 4; ++r) {
-                const int row = 4 * kk + r;
-                for (int c = 0; c < 4; ++c) {
-                    const long col = c4 + c;
-                    if (col >= P.L) break;
-                    const long o = (long)row * P.L + col;
-                    if (accumulate) P.mom_acc[o] = (first ? 0.0 : P.mom_acc[o]) + out[r][c];
-                    else P.mom[o] = out[r][c];
-                }
+        __syncthreads();
+        const long col = col0 + lane;
+        if (col < P.L) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = 2 * q + i;
+                const long o = (long)row * P.L + col;
+                const double v = tile[row][lane];
+                if (accumulate) P.mom_acc[o] = (first ? 0.0 : P.mom_acc[o]) + v;
+                else P.mom[o] = v;
             }
         }
     } else {
@@ -3033,7 +3051,7 @@ __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accum
 }
 
 hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool first, hipStream_t s) {
-    const long blocks = (B.nmw + 3) / 4;
+    const long blocks = fp64 ? (B.nmw + 3) / 4 : B.nmw;
     if (fp64)
         hipLaunchKernelGGL(b_moments_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, B, accumulate ? 1 : 0,
                            first ? 1 : 0);
