@@ -3211,14 +3211,21 @@ hipError_t b_shift(const BatchLaunch& B, hipStream_t s) {
 // ---- typed block-Jacobi PCG --------------------------------------------------
 // Per-problem scalars (P.scal): 0 rz, 1 rz_old, 2 bb, 3 rr, 4 done, 5 iterations,
 // 6 breakdown, 7 tol^2 bb, 8 alpha, 9 beta.
+// fixed-order sum over the workgroup: wave 0 adds the BT / 64 values of its
+// lane's stride, then a butterfly over the wave (three barriers; a tree over
+// the workgroup took nine)
 __device__ __forceinline__ double b_block_sum(double v, double* red) {
     const int t = threadIdx.x;
     red[t] = v;
     __syncthreads();
-    for (int s = BT / 2; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
+    if (t < 64) {
+        double s = red[t];
+#pragma unroll
+        for (int i = 1; i < BT / 64; ++i) s += red[64 * i + t];
+        s = wave_sum(s);
+        if (t == 0) red[0] = s;
     }
+    __syncthreads();
     const double r = red[0];
     __syncthreads();
     return r;
@@ -4970,7 +4977,7 @@ __global__ __launch_bounds__(BT) void b_aa_store_kernel(BatchLaunch B, int slot)
 }
 
 __global__ __launch_bounds__(BT) void b_aa_gram_part(BatchLaunch B, double* part6) {
-    __shared__ double red[BT];
+    __shared__ double red[6][BT];
     const EB m = eb_map(B);
     double v[6] = {0, 0, 0, 0, 0, 0};
     if (B.active[m.prob] && m.K >= 0) {
@@ -4984,19 +4991,20 @@ __global__ __launch_bounds__(BT) void b_aa_gram_part(BatchLaunch B, double* part
         v[4] = f1 * f2;
         v[5] = f2 * f2;
     }
-    // the six sums in one pass: within each wave by shuffles, then the four
-    // wave sums in wave order
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the six sums in one pass: the products in LDS, then 32 lanes per sum
+    // add BT / 32 values each (strided, so the reads do not conflict) and a
+    // butterfly over the 32 (six butterflies over 64 lanes, one per sum,
+    // took twice as long)
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        v[k] = wave_sum(v[k]);
-        if (lane == 0) red[k * (BT / 64) + wv] = v[k];
-    }
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = v[k];
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < 6 * 32) {
+        const int k = threadIdx.x >> 5, c = threadIdx.x & 31;
         double s = 0.0;
-        for (int w = 0; w < BT / 64; ++w) s += red[threadIdx.x * (BT / 64) + w];
-        part6[(long)threadIdx.x * B.nblocks + blockIdx.x] = s;
+#pragma unroll
+        for (int i = 0; i < BT / 32; ++i) s += red[k][32 * i + c];
+        for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 32);
+        if (c == 0) part6[(long)k * B.nblocks + blockIdx.x] = s;
     }
 }
 
@@ -5043,7 +5051,7 @@ hipError_t b_aa_mix(const BatchLaunch& B, const double* coef, hipStream_t s) {
 
 // ---- outer residual per problem: out[2 prob] = max|x - varphi|, out[2 prob + 1] = max|x|
 __global__ __launch_bounds__(BT) void b_resid_part(BatchLaunch B) {
-    __shared__ double r0[BT], r1[BT];
+    __shared__ double r[2][BT];
     const EB m = eb_map(B);
     double a = 0, b = 0;
     if (B.active[m.prob] && m.K >= 0) {
@@ -5055,20 +5063,25 @@ __global__ __launch_bounds__(BT) void b_resid_part(BatchLaunch B) {
         b = fabs(v);
         if (v != v) b = v;
     }
-    r0[threadIdx.x] = a;
-    r1[threadIdx.x] = b;
+    // the two maxima (NaN propagates; the order does not matter): 32 lanes
+    // per maximum take BT / 32 values each, strided, then a butterfly over
+    // the 32 (a tree over the workgroup took eight barriers)
+    r[0][threadIdx.x] = a;
+    r[1][threadIdx.x] = b;
     __syncthreads();
-    for (int s = BT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            const double x0 = r0[threadIdx.x + s], x1 = r1[threadIdx.x + s];
-            r0[threadIdx.x] = (x0 > r0[threadIdx.x] || x0 != x0) ? x0 : r0[threadIdx.x];
-            r1[threadIdx.x] = (x1 > r1[threadIdx.x] || x1 != x1) ? x1 : r1[threadIdx.x];
+    if (threadIdx.x < 64) {
+        const int k = threadIdx.x >> 5, c = threadIdx.x & 31;
+        double mx = r[k][c];
+#pragma unroll
+        for (int i = 1; i < BT / 32; ++i) {
+            const double x = r[k][32 * i + c];
+            mx = (x > mx || x != x) ? x : mx;
         }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        B.part[blockIdx.x] = r0[0];
-        B.part[B.nblocks + blockIdx.x] = r1[0];
+        for (int off = 16; off > 0; off >>= 1) {
+            const double x = __shfl_xor(mx, off, 32);
+            mx = (x > mx || x != x) ? x : mx;
+        }
+        if (c == 0) B.part[(long)k * B.nblocks + blockIdx.x] = mx;
     }
 }
 
