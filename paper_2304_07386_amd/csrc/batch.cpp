@@ -266,6 +266,12 @@ void batch_free(smm_batch* B) {
     delete B;
 }
 
+// psi row stride of a problem: L rounded up to 32 values, so that every row
+// starts on a 128-byte line (the moment kernel's 256-byte chunks of a row
+// then never share a line with a neighbouring workgroup's chunk: with rows
+// aligned to 16 bytes only the line at each chunk boundary was fetched twice)
+static size_t psi_row(size_t L) { return (L + 31) / 32 * 32; }
+
 int batch_build(smm_batch* B) {
     smm_ctx* c = B->ctx;
     const int np = B->nprob;
@@ -285,7 +291,7 @@ int batch_build(smm_batch* B) {
     for (int b = 0; b < np; ++b) {
         const Problem& P = B->probs[b]->P;
         PerProb& q = B->pp[b];
-        const size_t L = (size_t)P.ne * P.n, Lpad = (L + 3) / 4 * 4, n = P.n, ne = P.ne;
+        const size_t L = (size_t)P.ne * P.n, Lpad = psi_row(L), n = P.n, ne = P.ne;
         const int ldw = (P.nd + 3) / 4 * 4;
         double** v8[] = {&q.varphi, &q.varphi_prev, &q.x, &q.b, &q.r, &q.z, &q.p, &q.q, &q.bfix, &q.qsrc};
         for (double** v : v8) pool.req(v, sizeof(double) * L);
@@ -553,7 +559,7 @@ int batch_build(smm_batch* B) {
     for (int b = 0; b < np; ++b) {
         const Problem& P = B->probs[b]->P;
         PerProb& q = B->pp[b];
-        const size_t L = (size_t)P.ne * P.n, Lpad = (L + 3) / 4 * 4;
+        const size_t L = (size_t)P.ne * P.n, Lpad = psi_row(L);
         const int ldw = (P.nd + 3) / 4 * 4;
         std::vector<double> W(16 * (size_t)ldw, 0.0);
         for (int d = 0; d < P.nd; ++d) {

@@ -2935,8 +2935,9 @@ hipError_t b_sweep_mfma(int nb, bool multi, int tpw, int threads, size_t lds, in
 }
 
 // ---- moments (matrix cores), optional FP64 accumulation ----------------------
-// A block of columns is 64 columns of one problem (Lpad is a multiple of 4, so
-// a lane's 4 columns are 16-byte aligned; columns >= L read the zero padding).
+// A block of columns is 64 columns of one problem (Lpad is a multiple of 32,
+// so a lane's 4 columns are 16-byte aligned and a direction's 64 columns one
+// 256-byte piece of two whole lines; columns >= L read the zero padding).
 // FP32: one workgroup of four waves per block; wave q contracts the rounds q,
 // q + 4, ... of 8 directions, the partial sums meet in LDS (added in the
 // order q = 0..3), and the 8 moment rows leave as whole rows, 64 consecutive

@@ -130,7 +130,7 @@ hipError_t launch_residual(long L, const double* xn, const double* xo, double* p
 struct BProb {
     int ne, n, nb, nq, nbf, nd, nx, ldw;
     long L;                        // ne * n
-    long Lpad;                     // psi row stride (L rounded up to a multiple of 4)
+    long Lpad;                     // psi row stride (L rounded up to a multiple of 32)
     double eb0x, eb0y;
     int blk0, nblk;                // element-block range
     long bq0;                      // first flat boundary-point index
