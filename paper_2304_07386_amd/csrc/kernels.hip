@@ -3288,17 +3288,8 @@ __global__ __launch_bounds__(BT) void b_cg_init2(BatchLaunch B) {
     if (act) {
         const int n = P.n;
         const double* D = P.dinv + (long)P.sid[m.K] * n * n + m.i;
-        // four partial sums: one chain of n dependent steps bounded the kernel
-        double z0 = 0.0, z1 = 0.0, z2 = 0.0, z3 = 0.0;
-        int j = 0;
-        for (; j + 3 < n; j += 4) {
-            z0 += D[j * n] * rl[m.e0 + j];
-            z1 += D[(j + 1) * n] * rl[m.e0 + j + 1];
-            z2 += D[(j + 2) * n] * rl[m.e0 + j + 2];
-            z3 += D[(j + 3) * n] * rl[m.e0 + j + 3];
-        }
-        for (; j < n; ++j) z0 += D[j * n] * rl[m.e0 + j];
-        const double z = (z0 + z1) + (z2 + z3);
+        double z = 0;
+        for (int j = 0; j < n; ++j) z += D[j * n] * rl[m.e0 + j];
         P.z[t] = z;
         P.p[t] = z;
         const double bv = P.b[t];
@@ -4599,18 +4590,9 @@ __global__ __launch_bounds__(BT) void mg_corner_kernel(BatchLaunch B, double* co
     __syncthreads();
     if (on && m.i < 4) {
         const BProb& P = B.P[m.prob];
-        // four partial sums (one chain of n dependent LDS reads bounded the kernel)
-        const double* wr = &w[m.i][m.e0];
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int j = 0;
-        for (; j + 3 < P.n; j += 4) {
-            s0 += wr[j];
-            s1 += wr[j + 1];
-            s2 += wr[j + 2];
-            s3 += wr[j + 3];
-        }
-        for (; j < P.n; ++j) s0 += wr[j];
-        corner[4L * (P.e_off + m.K) + m.i] = (s0 + s1) + (s2 + s3);
+        double s = 0.0;
+        for (int j = 0; j < P.n; ++j) s += w[m.i][m.e0 + j];
+        corner[4L * (P.e_off + m.K) + m.i] = s;
     }
 }
 
