@@ -805,6 +805,9 @@ int batch_build(smm_batch* B) {
         }
         if (B->mgl.ls < mg_nlev && mg_prepare(B->mgl.lds) != hipSuccess)
             return fail(c, SMM_EHIP, "multigrid workgroup LDS size");
+        B->mgl.coarse_any = 0;
+        for (int b = 0; b < np; ++b)
+            if (mg_lc[b] < B->mgl.ls) B->mgl.coarse_any = 1;
     }
     if ((rc = put(c, B->dP, B->hP.data(), sizeof(BProb) * np))) return rc;
     if ((rc = put(c, B->d_blk2p, B->blk2p.data(), sizeof(int) * B->nblocks))) return rc;

@@ -4596,7 +4596,10 @@ __global__ __launch_bounds__(BT) void mg_corner_kernel(BatchLaunch B, double* co
     }
 }
 
-__global__ __launch_bounds__(BT) void mg_restrict0_kernel(BatchLaunch B, MGLaunch M, const double* corner) {
+// smooth: also the first damped Jacobi step of level 0 from zero, x = omega
+// b / d (pointwise, so it needs no launch of its own)
+__global__ __launch_bounds__(BT) void mg_restrict0_kernel(BatchLaunch B, MGLaunch M, const double* corner,
+                                                          int smooth) {
     const MGLevelDev& L = M.lev[0];
     const int v = blockIdx.x * BT + threadIdx.x;
     if (v >= L.nv) return;
@@ -4615,6 +4618,7 @@ __global__ __launch_bounds__(BT) void mg_restrict0_kernel(BatchLaunch B, MGLaunc
             s += c[4L * (ey * nx + ex) + cx + 2 * cy];
         }
     L.b[v] = s;
+    if (smooth && M.lc[prob] > 0) L.x[v] = M.omega * s / L.A[4L * L.nv + v];
 }
 
 // damped Jacobi: xout = omega b / d (mode 1, the first step from zero) or
@@ -4931,7 +4935,8 @@ hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStr
     // per-level launches above level ls, one workgroup per problem below
     const int top = M.ls < M.nlev - 1 ? M.ls : M.nlev - 1;
     if (init) hipLaunchKernelGGL(mg_corner_kernel, dim3(B.nblocks), dim3(BT), 0, s, B, M.corner);
-    hipLaunchKernelGGL(mg_restrict0_kernel, grid(M.lev[0].nv), dim3(BT), 0, s, B, M, (const double*)M.corner);
+    hipLaunchKernelGGL(mg_restrict0_kernel, grid(M.lev[0].nv), dim3(BT), 0, s, B, M, (const double*)M.corner,
+                       top > 0 ? 1 : 0);
     // nu damped Jacobi steps before and after the coarse correction,
     // alternating between x and t; the pre-smoothed iterate ends in x (nu
     // odd) or t (nu even), the residual goes to the other one, and after the
@@ -4939,7 +4944,8 @@ hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStr
     const int nu = M.nu;
     for (int l = 0; l < top; ++l) {
         const MGLevelDev& L = M.lev[l];
-        hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 1, (const double*)L.x, L.x);
+        // (level 0's first step ran with the restriction)
+        if (l > 0) hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 1, (const double*)L.x, L.x);
         for (int k = 1; k < nu; ++k) {
             double* src = (k & 1) ? L.x : L.t;
             hipLaunchKernelGGL(mg_smooth_kernel, grid(L.nv), dim3(BT), 0, s, B, M, l, 0, (const double*)src,
@@ -4952,7 +4958,7 @@ hipError_t b_mg_apply(const BatchLaunch& B, const MGLaunch& M, bool init, hipStr
     }
     if (M.ls < M.nlev)
         hipLaunchKernelGGL(mg_vcycle_lds_kernel, dim3(B.nprob), dim3(1024), M.lds, s, B, M);
-    hipLaunchKernelGGL(mg_coarse_kernel, dim3(B.nprob), dim3(64), 0, s, B, M);
+    if (M.coarse_any) hipLaunchKernelGGL(mg_coarse_kernel, dim3(B.nprob), dim3(64), 0, s, B, M);
     for (int l = top - 1; l >= 0; --l) {
         const MGLevelDev& L = M.lev[l];
         double* it = (nu & 1) ? L.x : L.t;
