@@ -16,7 +16,7 @@ Bar: relative L2 1e-12 (FP64, only the summation order differs).
 import numpy as np
 import pytest
 
-from workloads import config_blobs, config_channel
+from workloads import config_blobs, config_channel, config_plain
 
 from .gpu_common import announce, rel_l2
 from .test_gpu_batch import _batch_members
@@ -106,5 +106,35 @@ def test_preconditioner_matches_emulation(ctx, precond):
     hctx = L.smm_ctx_create(-1)
     for k, (wl, r, z) in enumerate(zip(wls, rs, zs)):
         ref = _emulate(hctx, wl, r, precond == 1)
+        assert rel_l2(z, ref) < 1e-12, (k, rel_l2(z, ref))
+    L.smm_batch_destroy(batch)
+
+
+def test_preconditioner_single_level_member(ctx):
+    """A 2 x 2 mesh has a single vertex level (its 3 x 3 grid is the coarsest),
+    solved by the coarse-level launch, which runs only when some member of
+    the batch needs it; the other members take the workgroup V-cycle."""
+    announce("two-level preconditioner, batch with a single-level member vs CPU emulation")
+    wls = _batch_members()[:2] + [config_plain(2, 2, 4)]
+    probs = [L.problem_from_workload(ctx, wl) for wl in wls]
+    hctx = L.smm_ctx_create(-1)
+    levels = []
+    for wl in wls:
+        p = L.problem_from_workload(hctx, wl)
+        n = 0
+        while True:
+            try:
+                L.smm_debug_mg_level(p, n)
+            except L.SmmError:
+                break
+            n += 1
+        levels.append(n)
+    assert levels[-1] == 1 and min(levels[:-1]) > 1, levels
+    batch = L.smm_batch_create(ctx, probs)
+    rng = np.random.default_rng(11)
+    rs = [rng.normal(size=p.n_elem * p.n_node) for p in probs]
+    zs = L.smm_debug_batch_precond(batch, 1, rs)
+    for k, (wl, r, z) in enumerate(zip(wls, rs, zs)):
+        ref = _emulate(hctx, wl, r, True)
         assert rel_l2(z, ref) < 1e-12, (k, rel_l2(z, ref))
     L.smm_batch_destroy(batch)
