@@ -3211,7 +3211,12 @@ hipError_t b_shift(const BatchLaunch& B, hipStream_t s) {
 
 // ---- typed block-Jacobi PCG --------------------------------------------------
 // Per-problem scalars (P.scal): 0 rz, 1 rz_old, 2 bb, 3 rr, 4 done, 5 iterations,
-// 6 breakdown, 7 tol^2 bb, 8 alpha, 9 beta.
+// 6 breakdown, 7 tol^2 bb, 8 alpha, 9 beta, 12 the iteration that converged
+// while its x += alpha p is still owed (else -1).  With the type-group kernels
+// x += alpha p is applied by the direction update, which reads p anyway (the
+// update kernel then reads neither x nor p): in the iteration that converges
+// the direction update still runs for x, and the next iteration's first
+// reduction clears the mark.
 // fixed-order sum over the workgroup: wave 0 adds the BT / 64 values of its
 // lane's stride, then a butterfly over the wave (three barriers; a tree over
 // the workgroup took nine)
@@ -3932,7 +3937,10 @@ __device__ __forceinline__ double group_sum(const BatchLaunch& B, const BProb& P
 __global__ __launch_bounds__(BT) void b_cg_red1(BatchLaunch B) {
     __shared__ double red[BT];
     const int prob = blockIdx.x;
-    if (cg_skip(B, prob)) return;
+    if (cg_skip(B, prob)) {
+        if (B.active[prob] && threadIdx.x == 0) B.P[prob].scal[12] = -1.0;
+        return;
+    }
     const BProb& P = B.P[prob];
     const double pq = group_sum(B, P, 0, red);
     if (threadIdx.x == 0) {
@@ -3954,9 +3962,7 @@ __device__ __forceinline__ void k2_group(const BatchLaunch& B, const BProb& P, i
     const int tot = cnt * N;
     const double alpha = P.scal[8];
     double rr = 0.0, rz = 0.0;
-    const auto xg = as_global(P.x);
     const auto rg = as_global(P.r);
-    const auto pg = as_global((const double*)P.p);
     const auto qg = as_global((const double*)P.q);
 #pragma unroll
     for (int it = 0; it < N; ++it) {
@@ -3965,7 +3971,6 @@ __device__ __forceinline__ void k2_group(const BatchLaunch& B, const BProb& P, i
         const int K = __shfl(myK, e);
         if (u < tot) {
             const unsigned o = (unsigned)(K * N + (u - (u / N) * N));
-            st_at(xg, o, ld_at(xg, o) + alpha * ld_at(pg, o));
             const double r = ld_at(rg, o) - alpha * ld_at(qg, o);
             st_at(rg, o, r);
             rr += r * r;
@@ -4030,9 +4035,7 @@ __device__ __forceinline__ void k2_group_mfma(const BatchLaunch& B, const BProb&
     const int tot = cnt * N;
     const double alpha = P.scal[8];
     double rr = 0.0, rz = 0.0;
-    const auto xg = as_global(P.x);
     const auto rg = as_global(P.r);
-    const auto pg = as_global((const double*)P.p);
     const auto qg = as_global((const double*)P.q);
 #pragma unroll
     for (int it = 0; it < N; ++it) {
@@ -4041,7 +4044,6 @@ __device__ __forceinline__ void k2_group_mfma(const BatchLaunch& B, const BProb&
         const int K = __shfl(myK, e);
         if (u < tot) {
             const unsigned o = (unsigned)(K * N + (u - (u / N) * N));
-            st_at(xg, o, ld_at(xg, o) + alpha * ld_at(pg, o));
             const double r = ld_at(rg, o) - alpha * ld_at(qg, o);
             st_at(rg, o, r);
             rr += r * r;
@@ -4132,8 +4134,8 @@ __device__ __forceinline__ void k2_group_mfma(const BatchLaunch& B, const BProb&
     }
 }
 
-// x += alpha p, r -= alpha q, z = D^-1 r (block-Jacobi) and the group's partial
-// sums of r.z and r.r
+// r -= alpha q, z = D^-1 r (block-Jacobi) and the group's partial sums of r.z
+// and r.r (x += alpha p waits for the direction update)
 template <int NB>
 __global__ __launch_bounds__(256, NB == 5 ? 3 : 2) void b_cg_k2(BatchLaunch B) {
     constexpr int SL = 64 * (NB * NB | 1);
@@ -4209,7 +4211,10 @@ __global__ __launch_bounds__(BT) void b_cg_red2(BatchLaunch B, MGLaunch M) {
         s[0] = rzn;
         s[3] = rr;
         s[5] += 1.0;
-        if (rr <= s[7]) s[4] = 1.0;
+        if (rr <= s[7]) {
+            s[4] = 1.0;
+            s[12] = s[5];
+        }
     }
 }
 
@@ -4232,8 +4237,9 @@ __global__ __launch_bounds__(BT) void b_cg_k3(BatchLaunch B, MGLaunch M) {
     P.p[t] = z + P.scal[9] * P.p[t];
 }
 
-// p = z + beta p (z = D^-1 r + P0 x0 with the two-level preconditioner) over
-// one type group, flat element-major (coalesced) like the update kernel
+// x += alpha p, then p = z + beta p (z = D^-1 r + P0 x0 with the two-level
+// preconditioner) over one type group, flat element-major (coalesced) like the
+// update kernel; in the iteration that converged, x += alpha p only
 template <int NB>
 __global__ __launch_bounds__(256) void b_cg_k3g(BatchLaunch B, MGLaunch M) {
     constexpr int N = NB * NB;
@@ -4241,14 +4247,31 @@ __global__ __launch_bounds__(256) void b_cg_k3g(BatchLaunch B, MGLaunch M) {
     const int g = B.g_nb0[NB] + xcd_block() * 4 + w;
     if (g >= B.g_nb0[NB + 1]) return;
     const int prob = B.g_prob[g];
-    if (cg_skip(B, prob)) return;
+    if (!B.active[prob]) return;
     const BProb& P = B.P[prob];
+    // converged in this iteration: only x += alpha p is left
+    const bool last = P.scal[4] != 0.0;
+    if (last && P.scal[12] != P.scal[5]) return;
     const int lane = threadIdx.x & 63;
     const int cnt = B.g_count[g], tot = cnt * N;
     const int myK = B.g_elem[g * 64 + lane];
-    const double beta = P.scal[9];
+    const double alpha = P.scal[8], beta = P.scal[9];
     const auto zg = as_global((const double*)P.z);
     const auto pg = as_global(P.p);
+    const auto xg = as_global(P.x);
+    if (last) {
+#pragma unroll
+        for (int it = 0; it < N; ++it) {
+            const int u = lane + 64 * it;
+            const int e = u / N < 64 ? u / N : 63;
+            const int K = __shfl(myK, e);
+            if (u < tot) {
+                const unsigned o = (unsigned)(K * N + (u - (u / N) * N));
+                st_at(xg, o, ld_at(xg, o) + alpha * ld_at(pg, o));
+            }
+        }
+        return;
+    }
     // per lane (element): the vertex of its lower-left corner on the level-0
     // grid and its lower-left node on the continuous grid; a node (a, b) of
     // the element is then base + b gx + a (NB is a constant, so no division
@@ -4284,7 +4307,9 @@ __global__ __launch_bounds__(256) void b_cg_k3g(BatchLaunch B, MGLaunch M) {
                      xa * yb * xv[nvx + 1];
                 if (P.cgw) z += P.cgw[Cb + (j / NB) * gx + j % NB];
             }
-            st_at(pg, o, z + beta * ld_at(pg, o));
+            const double pv = ld_at(pg, o);
+            st_at(xg, o, ld_at(xg, o) + alpha * pv);
+            st_at(pg, o, z + beta * pv);
         }
     }
 }
@@ -4297,6 +4322,7 @@ __global__ void b_cg_clear_kernel(BatchLaunch B) {
     double* s = B.P[prob].scal;
     s[4] = 0.0;
     s[6] = 0.0;
+    s[12] = -1.0;
 }
 
 hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s, const MGLaunch* M) {
