@@ -208,7 +208,7 @@ struct MGLaunch {
     double* corner;             // [4][batch elements] corner sums of the residual
     int ls;                     // levels >= ls run in one workgroup per problem (nlev: none)
     size_t lds;                 // LDS bytes of that workgroup
-    int coarse_any;             // 1: some problem's coarsest level lies above ls (solved by its own launch)
+    int coarse_any;             // 1: some problem's coarsest level index is below ls (its dense solve has a launch of its own)
     // continuous-space term: blocks of 256 nodes of the Q_p grids, per problem
     const int* cg_blk2p;        // [cg_nblocks] problem of each block
     const int* cg_blk0;         // [nprob + 1] first block of each problem
