@@ -113,3 +113,36 @@ def test_forked_pcg_launches_bitwise(ctx, use_graph):
         assert np.array_equal(outs[0][k], outs[2][k]), k
     assert its[0] == its[1] == its[2]
     L.smm_batch_destroy(batch)
+
+
+@pytest.mark.parametrize("inner", [(1e-15, 1), (1e-15, 2), (1e-3, 4000)], ids=["one_step", "two_steps", "loose"])
+def test_grouped_matches_per_node_with_truncated_inner_solves(ctx, inner):
+    """The type-group kernels apply x += alpha p in the direction update (the
+    update kernel reads neither x nor p), the per-node kernels in the update:
+    after PCG solves stopped by max_inner (one or two iterations) or by a loose
+    tolerance (mid-chunk, where the direction update of the converging
+    iteration still owes x its last step) both give the same iterate up to
+    summation order.  A missing or repeated alpha p would differ at the size
+    of the step itself."""
+    inner_tol, max_inner = inner
+    announce(f"grouped vs per-node kernels, 3 outer iterations, inner_tol {inner_tol}, max_inner {max_inner}")
+    wls = _batch_members() + [config_plain(16, 4, 4), config_blobs(20006, n=14, p=2, sn=4)]
+    probs = [L.problem_from_workload(ctx, wl) for wl in wls]
+    batch = L.smm_batch_create(ctx, probs)
+    outs = {}
+    for grouped in (1, 0):
+        L.smm_debug_batch_grouped(batch, grouped)
+        o = L.smm_default_opts(precision=L.SMM_FP64, outer_tol=0.0, max_outer=3, inner_tol=inner_tol,
+                               max_inner=max_inner, precond=L.SMM_PRECOND_TWOLEVEL)
+        rc, infos = L.smm_batch_solve(batch, o, raise_on_noconv=False)
+        assert rc in (L.SMM_OK, L.SMM_ENOCONV), grouped
+        assert all(i["iterations"] == 3 for i in infos), grouped
+        outs[grouped] = []
+        for k, p in enumerate(probs):
+            v = np.zeros(p.n_elem * p.n_node)
+            L.smm_batch_get_outputs(batch, k, varphi=v)
+            outs[grouped].append(v)
+    for k in range(len(probs)):
+        assert np.all(np.isfinite(outs[1][k]))
+        assert rel_l2(outs[1][k], outs[0][k]) < 1e-10, (k, rel_l2(outs[1][k], outs[0][k]))
+    L.smm_batch_destroy(batch)
