@@ -1280,7 +1280,9 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
                 hipError_t e = b_source(fp64, Lg, !first, cs);
                 int src = e == hipSuccess ? batch_sweep(B, fp64, first, cs) : SMM_EHIP;
                 if (src == SMM_OK) {
-                    hipError_t ek[8] = {b_moments(fp64, Lg, true, first, cs), b_closures_rhs(Lg, cs), b_copy_x(Lg, cs),
+                    // (FP32: T formed with the moments)
+                    hipError_t ek[8] = {b_moments(fp64, Lg, true, first, cs, !fp64), b_closures_rhs(Lg, cs, !fp64),
+                                        b_copy_x(Lg, cs),
                                         b_cg_start(Lg, o.inner_tol, cs, &B->mgl),
                                         b_cg_iterations(Lk, k, cs, &B->mgl, cg_fork(B, cgf)),
                                         b_residual(Lg, B->d_rout, cs),
@@ -1341,8 +1343,8 @@ int batch_solve(smm_batch* B, const smm_solve_opts& o, const double* const* varp
         HIPCHK(c, b_source(fp64, L, !first, c->stream));
         if ((rc = batch_sweep(B, fp64, first))) return rc;
         HIPCHK(c, hipEventRecord(B->pev[1], c->stream));
-        HIPCHK(c, b_moments(fp64, L, true, first, c->stream));
-        HIPCHK(c, b_closures_rhs(L, c->stream));
+        HIPCHK(c, b_moments(fp64, L, true, first, c->stream, !fp64));   // FP32: T formed with the moments
+        HIPCHK(c, b_closures_rhs(L, c->stream, !fp64));
         HIPCHK(c, b_copy_x(L, c->stream));
         HIPCHK(c, hipEventRecord(B->pev[2], c->stream));
         if (o.inner_adapt > 0) {

@@ -2945,7 +2945,7 @@ hipError_t b_sweep_mfma(int nb, bool multi, int tpw, int threads, size_t lds, in
 // rows took 0.6 of the kernel's 1.5 ms).  FP64: one wave per block, all
 // directions.
 template <typename T>
-__global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accumulate, int first) {
+__global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accumulate, int first, int with_T) {
     const int lane = threadIdx.x & 63;
     const long w = sizeof(T) == 4 ? (long)blockIdx.x : ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (w >= B.nmw) return;   // FP32: uniform over the workgroup
@@ -3014,8 +3014,24 @@ __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accum
                 const int row = 2 * q + i;
                 const long o = (long)row * P.L + col;
                 const double v = tile[row][lane];
-                if (accumulate) P.mom_acc[o] = (first ? 0.0 : P.mom_acc[o]) + v;
-                else P.mom[o] = v;
+                if (accumulate) {
+                    const double a = (first ? 0.0 : P.mom_acc[o]) + v;
+                    P.mom_acc[o] = a;
+                    tile[row][lane] = a;   // (each thread rewrites only what it read)
+                } else {
+                    P.mom[o] = v;
+                }
+            }
+        }
+        // the closure T from the accumulated rows, as b_T_kernel forms it (the
+        // rows are in LDS already: that kernel's reads are saved)
+        if (with_T && accumulate) {
+            __syncthreads();
+            if (q == 0 && col < P.L) {
+                const double phi = tile[0][lane];
+                P.T[col] = tile[3][lane] - phi / 3.0;
+                P.T[P.L + col] = tile[4][lane];
+                P.T[2 * P.L + col] = tile[5][lane] - phi / 3.0;
             }
         }
     } else {
@@ -3051,14 +3067,14 @@ __global__ __launch_bounds__(256) void b_moments_kernel(BatchLaunch B, int accum
     }
 }
 
-hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool first, hipStream_t s) {
+hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool first, hipStream_t s, bool with_T) {
     const long blocks = fp64 ? (B.nmw + 3) / 4 : B.nmw;
     if (fp64)
         hipLaunchKernelGGL(b_moments_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, B, accumulate ? 1 : 0,
-                           first ? 1 : 0);
+                           first ? 1 : 0, 0);
     else
         hipLaunchKernelGGL(b_moments_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, B, accumulate ? 1 : 0,
-                           first ? 1 : 0);
+                           first ? 1 : 0, with_T && accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -3150,8 +3166,8 @@ __global__ __launch_bounds__(BT) void b_rhs_kernel(BatchLaunch B) {
     P.b[(long)K * n + i] = v;
 }
 
-hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s) {
-    hipLaunchKernelGGL(b_T_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
+hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s, bool t_done) {
+    if (!t_done) hipLaunchKernelGGL(b_T_kernel, dim3(B.nblocks), dim3(BT), 0, s, B);
     if (B.nbq > 0) hipLaunchKernelGGL(b_beta_kernel, dim3((unsigned)((B.nbq + 255) / 256)), dim3(256), 0, s, B);
     if (B.grouped)
         b_group_rows_all<1>(B, s);

@@ -246,11 +246,14 @@ int b_sweep_mfma_threads(int tpw, int nx, int ny);
 size_t b_sweep_mfma_lds(int nb, int tpw, int threads, int nxy);
 int b_sweep_threads(int nb, int nx, int ny);
 size_t b_sweep_lds(bool fp64, int nb, bool multi, int nx, int ny);
-hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool first, hipStream_t s);
+// with_T (FP32, accumulating): the launch also forms the closure T from the
+// accumulated moments, which b_closures_rhs then skips (t_done)
+hipError_t b_moments(bool fp64, const BatchLaunch& B, bool accumulate, bool first, hipStream_t s,
+                     bool with_T = false);
 // start vectors of every problem: bit 1 varphi_prev = 0, 2 varphi = 0,
 // 4 b = bfix and x = 0, 8 varphi = x
 hipError_t b_start_vectors(const BatchLaunch& B, int what, hipStream_t s);
-hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s);
+hipError_t b_closures_rhs(const BatchLaunch& B, hipStream_t s, bool t_done = false);
 hipError_t b_copy_x(const BatchLaunch& B, hipStream_t s);               // x = varphi
 hipError_t b_shift(const BatchLaunch& B, hipStream_t s);                // varphi_prev = varphi, varphi = x
 hipError_t b_cg_start(const BatchLaunch& B, double tol, hipStream_t s, const MGLaunch* M);
